@@ -1,0 +1,206 @@
+"""Nearest-neighbour melting temperature of a primer binding site
+(Section 2.1, "Melting temperature filtering").
+
+The paper computes, with a nearest-neighbour (NN) duplex-stability model that
+admits mismatches, the melting temperature of every oligonucleotide of the
+degenerate primer that is compatible with the site, keeps the site iff the
+*maximum* of these is above a user threshold, and reports that maximum.  The
+user supplies the primer and template concentrations (dnac1, dnac2), the ion
+concentrations (Na, K, Tris, Mg, dNTPs) and the salt-correction method.
+
+Model (float64 throughout):
+
+* Stacks: SantaLucia (1998) unified parameters (identical to Allawi &
+  SantaLucia 1997), Delta-H in kcal/mol and Delta-S in cal/(K mol) for the
+  stack read 5'->3' on either strand.
+* Initiation once per duplex end from that end's terminal pair:
+  G.C -> (+0.1, -2.8), A.T -> (+2.3, +4.1).
+* Symmetry correction Delta-S -1.4 and total strand concentration C = dnac1
+  only when the caller declares the duplex self-complementary (``selfcomp``).
+* Salt method 5 (SantaLucia 1998): Delta-S += 0.368 (N - 1) ln([Na+]) with
+  [Na+] in mol/L, N the primer length, and the sodium equivalent of von
+  Ahsen et al. (2001): Na + K + Tris/2 + 120 sqrt(Mg - dNTPs) mM (the Mg term
+  is zero when Mg <= dNTPs).  Method 0: no correction.
+* C = (max(dnac1, dnac2) - min(dnac1, dnac2) / 2) * 1e-9 M otherwise.
+* Tm = 1000 Delta-H / (Delta-S + R ln C) - 273.15 with R = 1.987.
+
+Readings:
+  R7  a compatible oligo is within k mismatches of the site and matches it on
+      every clamp position (the oligos whose own pattern would have matched).
+  R8  parameters as above; the configuration's conditions are 50 mM Na+,
+      1.5 mM Mg2+, 250 nM primer, template in trace (dnac2 = 0).
+  R9  mismatched duplexes ("MM0"): the published mismatch, terminal-mismatch
+      and dangling-end tables are not available here, so a stack that contains
+      a mismatched pair contributes zero, initiation is taken at the outermost
+      paired positions (both ends at the same pair if only one pair is
+      formed, none if no pair is formed), and the salt term keeps N - 1.  For a
+      perfect duplex this is exactly the closed form above.  Parity against the
+      paper's tool for mismatched duplexes: unpinned.
+  R20 only the maximum is part of the result.
+Template base opposite oligo position j: the complement of the top-strand base
+at pos + j for a + site, the top-strand base at pos + L - 1 - j for a - site.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from . import iupac
+from .scan import codes
+
+R_GAS = 1.987
+
+# SantaLucia (1998) unified / Allawi & SantaLucia (1997): (dH, dS)
+NN_UNIFIED = {
+    "AA": (-7.9, -22.2), "TT": (-7.9, -22.2),
+    "AT": (-7.2, -20.4),
+    "TA": (-7.2, -21.3),
+    "CA": (-8.5, -22.7), "TG": (-8.5, -22.7),
+    "GT": (-8.4, -22.4), "AC": (-8.4, -22.4),
+    "CT": (-7.8, -21.0), "AG": (-7.8, -21.0),
+    "GA": (-8.2, -22.2), "TC": (-8.2, -22.2),
+    "CG": (-10.6, -27.2),
+    "GC": (-9.8, -24.4),
+    "GG": (-8.0, -19.9), "CC": (-8.0, -19.9),
+}
+INIT_GC = (0.1, -2.8)
+INIT_AT = (2.3, 4.1)
+SYM_DS = -1.4
+
+_NH = np.zeros(16)
+_NS = np.zeros(16)
+for _k, (_h, _s) in NN_UNIFIED.items():
+    _i = "ACGT".index(_k[0]) * 4 + "ACGT".index(_k[1])
+    _NH[_i], _NS[_i] = _h, _s
+
+
+@dataclasses.dataclass(frozen=True)
+class TmParams:
+    dnac1: float = 250.0   # nM, primer
+    dnac2: float = 0.0     # nM, template
+    Na: float = 50.0       # mM
+    K: float = 0.0
+    Tris: float = 0.0
+    Mg: float = 1.5
+    dNTPs: float = 0.0
+    saltcorr: int = 5
+    selfcomp: bool = False
+
+
+def sodium_equivalent(p: TmParams) -> float:
+    mg = p.Mg - p.dNTPs
+    return p.Na + p.K + p.Tris / 2.0 + (120.0 * math.sqrt(mg) if mg > 0 else 0.0)
+
+
+def salt_entropy(p: TmParams, length: int) -> float:
+    if p.saltcorr == 0:
+        return 0.0
+    if p.saltcorr != 5:
+        raise ValueError("salt correction method must be 0 or 5")
+    na = sodium_equivalent(p)
+    if na <= 0:
+        raise ValueError("salt correction needs a positive sodium equivalent")
+    return 0.368 * (length - 1) * math.log(na / 1000.0)
+
+
+def concentration(p: TmParams) -> float:
+    if p.selfcomp:
+        return p.dnac1 * 1e-9
+    hi, lo = max(p.dnac1, p.dnac2), min(p.dnac1, p.dnac2)
+    return (hi - lo / 2.0) * 1e-9
+
+
+def duplex_terms(oligo: np.ndarray, paired: np.ndarray):
+    """Delta-H and Delta-S sums (stacks + initiation) for oligos (rows) with a
+    boolean pairing table of the same shape (MM0 for unpaired positions)."""
+    oligo = np.atleast_2d(oligo).astype(np.int64)
+    paired = np.atleast_2d(paired)
+    both = paired[:, :-1] & paired[:, 1:]
+    idx = oligo[:, :-1] * 4 + oligo[:, 1:]
+    dh = np.where(both, _NH[idx], 0.0).sum(axis=1)
+    ds = np.where(both, _NS[idx], 0.0).sum(axis=1)
+    any_p = paired.any(axis=1)
+    L = oligo.shape[1]
+    lo = np.argmax(paired, axis=1)
+    hi = L - 1 - np.argmax(paired[:, ::-1], axis=1)
+    for end in (lo, hi):
+        b = oligo[np.arange(oligo.shape[0]), end]
+        gc = (b == 1) | (b == 2)
+        dh += np.where(any_p, np.where(gc, INIT_GC[0], INIT_AT[0]), 0.0)
+        ds += np.where(any_p, np.where(gc, INIT_GC[1], INIT_AT[1]), 0.0)
+    return dh, ds
+
+
+def tm_from_terms(dh, ds, length: int, p: TmParams):
+    ds = np.asarray(ds, dtype=np.float64) + salt_entropy(p, length)
+    if p.selfcomp:
+        ds = ds + SYM_DS
+    return 1000.0 * np.asarray(dh, dtype=np.float64) / (ds + R_GAS * math.log(concentration(p))) - 273.15
+
+
+def tm_perfect(oligo: str, p: TmParams = TmParams()) -> float:
+    """Tm of an ACGT oligo with its exact complement."""
+    o = codes(oligo)
+    dh, ds = duplex_terms(o, np.ones((1, o.size), bool))
+    return float(tm_from_terms(dh, ds, o.size, p)[0])
+
+
+def tm_duplex(oligo: str, template_opposite: str, p: TmParams = TmParams()) -> float:
+    """Tm of oligo (5'->3') against the template bases written opposite each
+    oligo base (template read 3'->5'); a position pairs iff the template base
+    is the complement of the oligo base."""
+    o = codes(oligo)
+    t = codes(template_opposite)
+    paired = (t < 4) & (o == (3 - t))
+    dh, ds = duplex_terms(o, paired[None, :])
+    return float(tm_from_terms(dh, ds, o.size, p)[0])
+
+
+def _expansion_codes(primer: str) -> np.ndarray:
+    return np.array([codes(o) for o in iupac.expand(primer)], dtype=np.int64)
+
+
+_EXP_CACHE: dict = {}
+
+
+def site_tm(genome_codes: np.ndarray, pos: int, primer: str, strand: int, k: int,
+            clamp: int, p: TmParams = TmParams()) -> float:
+    """Maximum Tm over the oligos of ``primer`` compatible with the site."""
+    primer = iupac.normalise(primer)
+    L = len(primer)
+    if primer not in _EXP_CACHE:
+        _EXP_CACHE[primer] = _expansion_codes(primer)
+    olig = _EXP_CACHE[primer]
+    w = np.asarray(genome_codes[pos:pos + L], dtype=np.int64)
+    if strand == 0:
+        opp_ok = w  # oligo base j pairs iff it equals the top-strand base
+    else:
+        r = w[::-1]
+        opp_ok = np.where(r < 4, 3 - r, 9)
+    paired = olig == opp_ok[None, :]
+    mism = L - paired.sum(axis=1)
+    c = min(clamp, L)
+    ok = mism <= k
+    if c > 0:
+        ok &= paired[:, L - c:].all(axis=1)
+    if not ok.any():
+        return float("nan")
+    dh, ds = duplex_terms(olig[ok], paired[ok])
+    return float(tm_from_terms(dh, ds, L, p).max())
+
+
+def fill_tm(hits: np.ndarray, seqs, pairs, p: TmParams = TmParams()) -> np.ndarray:
+    """Copy of ``hits`` with the ``tm`` field set for every record."""
+    h = hits.copy()
+    cache = {}
+    for r in range(h.size):
+        g = int(h["genome"][r])
+        if g not in cache:
+            cache[g] = codes(seqs[g])
+        pr = pairs[int(h["pair"][r])]
+        primer = pr.fwd if h["primer"][r] == 0 else pr.rev
+        h["tm"][r] = site_tm(cache[g], int(h["pos"][r]), primer, int(h["strand"][r]),
+                             pr.k, pr.clamp, p)
+    return h
