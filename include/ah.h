@@ -1,0 +1,224 @@
+/*
+ * libah -- genome-wide scan for degenerate-primer binding sites, nearest-
+ * neighbour melting temperature and amplicon calling on AMD MI355X (gfx950).
+ *
+ * The operations follow AmpliconHunter (Howard-Stone & Mandoiu,
+ * arXiv 2509.13300), Section 2.1: primer matching with up to k mismatches and
+ * an optional 3'-clamp, melting-temperature scoring of every binding site as
+ * the maximum over the compatible oligonucleotides of the degenerate primer,
+ * and amplicon calling by pairing opposite-strand sites within a length
+ * window, labelled FR / RF / FF / RR.
+ *
+ * Conventions for every call:
+ *  - Device pointers (prefix d_) are owned by the caller and must stay valid
+ *    until the work enqueued on `stream` has finished.  Host pointers are
+ *    borrowed for the duration of the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously; the calls never synchronise the stream,
+ *    so a whole scan -> Tm -> pairing sequence can be captured in a hipGraph.
+ *  - Arguments and primers are validated synchronously; on any error nothing
+ *    is enqueued and the status is returned.  Errors discovered on the device
+ *    (output capacity exceeded) are written to a device-resident ah_result.
+ *  - The first call with a new primer set specialises and compiles the scan
+ *    kernel for it and uploads small per-set tables (cached per device and
+ *    per primer set until ah_release_caches); later calls with the same set
+ *    allocate nothing.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef AH_H
+#define AH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ah_status {
+  AH_OK = 0,
+  AH_ERR_INVALID_ARG = -1,    /* null pointer, bad size, bad parameter value */
+  AH_ERR_INVALID_PRIMER = -2, /* a character outside the IUPAC nucleotide codes */
+  AH_ERR_LIMIT = -3,          /* primer length, k, clamp or key-width limit exceeded */
+  AH_ERR_OVERFLOW = -4,       /* (device) more records than the output capacity */
+  AH_ERR_WORKSPACE = -5,      /* workspace smaller than the *_workspace_bytes query */
+  AH_ERR_HIP = -6,            /* a HIP runtime call failed */
+  AH_ERR_JIT = -7             /* specialising the scan kernel failed */
+} ah_status;
+
+enum {
+  AH_MIN_PRIMER_LEN = 5,   /* the paper's server limit: primers of at least 5 bp */
+  AH_MAX_PRIMER_LEN = 32,  /* one packed word of window positions */
+  AH_MAX_K = 15,
+  AH_HALO_WORDS = 31       /* packed words appended to each genome (AH_MAX_PRIMER_LEN - 1) */
+};
+
+/* Orientation codes of an amplicon (Section 2.1, "Amplicon analysis", item 1). */
+enum { AH_FR = 0, AH_RF = 1, AH_FF = 2, AH_RR = 3 };
+
+/* ---------------------------------------------------------------------------
+ * Packed genome collection (Section 1 / 2.1: genomes are the FASTA input).
+ *
+ * Layout of genome g with n bases: S = ceil(n / 32) segment words plus
+ * AH_HALO_WORDS halo words, starting at word word_off[g].  Word t is a pair of
+ * uint32 (h, l) stored consecutively in `words`; bit b of word t holds the
+ * base at position b*S + t as the 2-bit code A=00, C=01, G=10, T=11 (h the
+ * high bit, l the low bit; the complement of a base is the bitwise NOT of
+ * both planes).  Positions >= n read as A and are never reported.  `nmask`,
+ * when not NULL, holds one uint32 per word with bit b set iff that base was
+ * not A/C/G/T (such bases match no primer position).
+ * ------------------------------------------------------------------------- */
+typedef struct ah_genomes {
+  const uint32_t* words;    /* device, 2 uint32 per word                        */
+  const uint32_t* nmask;    /* device, 1 uint32 per word, or NULL              */
+  const uint64_t* word_off; /* device, [n + 1]                                  */
+  const uint32_t* len;      /* device, [n] bases per genome                    */
+  uint32_t n;               /* host: number of genomes                         */
+  uint32_t max_len;         /* host: an upper bound on every len[g] (>= 1)     */
+} ah_genomes;
+
+/* Host-side layout query.  Fills h_word_off[0..n] (may be NULL) for genomes of
+ * lengths h_len[0..n-1] and returns the total number of words.  The words
+ * buffer needs 8 bytes per word, the nmask buffer 4 bytes per word. */
+uint64_t ah_pack_layout(const uint64_t* h_len, uint32_t n, uint64_t* h_word_off);
+
+/* Pack ASCII genomes into the layout above.  Genome g is
+ * d_ascii[d_ascii_off[g] .. d_ascii_off[g+1]); upper or lower case A/C/G/T are
+ * bases, every other byte is a non-ACGT base.  d_word_off must hold the
+ * offsets from ah_pack_layout.  Writes d_words, d_len, and, when not NULL,
+ * d_nmask and d_non_acgt[g] (number of non-ACGT bytes of genome g).  If any
+ * genome has non-ACGT bytes the scan needs d_nmask.
+ * Errors: AH_ERR_INVALID_ARG (null required pointer, a genome longer than
+ * 2^32 - 1 bases), AH_ERR_HIP. */
+ah_status ah_pack_genomes(const uint8_t* d_ascii, const uint64_t* d_ascii_off, uint32_t n,
+                          const uint64_t* d_word_off, uint32_t* d_words, uint32_t* d_len,
+                          uint32_t* d_nmask, uint64_t* d_non_acgt, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Primer pairs and binding sites (Section 2.1, "Primer matching").
+ * ------------------------------------------------------------------------- */
+typedef struct ah_primer_pair {
+  const char* fwd;    /* IUPAC codes 5'->3' (case-insensitive), 5..32 nt    */
+  const char* rev;    /* IUPAC codes 5'->3'                                  */
+  uint32_t k;         /* maximum mismatches per site, <= AH_MAX_K            */
+  uint32_t clamp;     /* 3'-terminal primer bases that must match (0 = none) */
+} ah_primer_pair;
+
+/* One binding site.  pos is the 0-based leftmost top-strand coordinate of the
+ * window for both strands.  strand_primer: bit 1 = strand (0 = the primer
+ * sequence itself is on the top strand, 1 = its reverse complement is),
+ * bit 0 = primer (0 = fwd, 1 = rev).  mm = mismatching positions.  tm is
+ * filled by ah_tm (NaN before). */
+typedef struct ah_hit {
+  uint32_t genome;
+  uint32_t pos;
+  uint16_t pair;
+  uint8_t strand_primer;
+  uint8_t mm;
+  float tm;
+} ah_hit;
+
+/* Device-resident result of an asynchronous call.  required = records found;
+ * count = records written = min(required, capacity); status = AH_OK or
+ * AH_ERR_OVERFLOW (then the buffer contents are unspecified and the call can
+ * be repeated with capacity >= required, giving the same records). */
+typedef struct ah_result {
+  uint64_t count;
+  uint64_t required;
+  int32_t status;
+  uint32_t reserved;
+} ah_result;
+
+/* Find every window of every genome where a primer of a pair, or its reverse
+ * complement, has at most k mismatching positions (a genome base outside the
+ * position's IUPAC set is a mismatch; substitutions only) and no mismatch in
+ * the clamp (the primer's 3'-most `clamp` bases).  Output: d_hits sorted by
+ * (pair, genome, pos, strand, primer) -- a canonical order independent of
+ * scheduling -- and *d_res.  Needs a workspace of at least
+ * ah_scan_workspace_bytes(...) bytes (device, caller-owned, 256-byte aligned).
+ * Errors: AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT (primer
+ * length outside 5..32, k > AH_MAX_K, clamp > primer length, sort key wider
+ * than 64 bits), AH_ERR_WORKSPACE, AH_ERR_JIT, AH_ERR_HIP. */
+ah_status ah_scan_primers(const ah_genomes* genomes, const ah_primer_pair* pairs,
+                          uint32_t n_pairs, ah_hit* d_hits, uint64_t capacity,
+                          ah_result* d_res, void* d_work, size_t work_bytes, void* stream);
+size_t ah_scan_workspace_bytes(const ah_genomes* genomes, uint32_t n_pairs, uint64_t capacity);
+
+/* ---------------------------------------------------------------------------
+ * Melting temperature (Section 2.1, "Melting temperature filtering").
+ * Nearest-neighbour model: SantaLucia (1998) unified stacks, initiation per
+ * duplex end, salt method 5 (entropy term 0.368 (N-1) ln[Na+], sodium
+ * equivalent Na + K + Tris/2 + 120 sqrt(Mg - dNTPs) mM) or 0 (none), and
+ * C = max(dnac1,dnac2) - min(dnac1,dnac2)/2 (dnac1 if selfcomp).  A stack
+ * with a mismatched pair contributes nothing and initiation is taken at the
+ * outermost paired positions.  Sums are FP32 with compensation; the salt and
+ * logarithm terms are FP64.
+ * ------------------------------------------------------------------------- */
+typedef struct ah_tm_params {
+  double dnac1_nM, dnac2_nM, Na_mM, K_mM, Tris_mM, Mg_mM, dNTPs_mM;
+  int32_t saltcorr; /* 0 or 5 */
+  int32_t selfcomp; /* 1: symmetry correction -1.4 cal/(K mol) and C = dnac1 */
+} ah_tm_params;
+
+/* For each of the min(count, capacity) hits in d_hits (as written by
+ * ah_scan_primers with the same genomes and pairs), set tm to the maximum
+ * melting temperature over the oligos of the site's primer that have at most
+ * k mismatches against the site and none in the clamp.  `capacity` is the
+ * size of d_hits.  Errors: AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER,
+ * AH_ERR_LIMIT, AH_ERR_HIP. */
+ah_status ah_tm(const ah_genomes* genomes, const ah_primer_pair* pairs, uint32_t n_pairs,
+                const ah_tm_params* params, ah_hit* d_hits, const ah_result* d_nhits,
+                uint64_t capacity, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Amplicon calling (Section 2.1, "Amplicon calling" and "Amplicon analysis").
+ * ------------------------------------------------------------------------- */
+typedef struct ah_window {
+  uint32_t min_len;  /* inclusive bounds on end - start                   */
+  uint32_t max_len;
+  int32_t filter_tm; /* 1: drop sites with tm < min_tm before pairing     */
+  float min_tm;
+} ah_window;
+
+/* [start, end): start = pos of the + site, end = pos of the - site plus the
+ * length of that site's primer.  plus_hit / minus_hit index d_hits. */
+typedef struct ah_amplicon {
+  uint32_t genome;
+  uint32_t start;
+  uint32_t end;
+  uint32_t plus_hit;
+  uint32_t minus_hit;
+  uint16_t pair;
+  uint8_t orient; /* AH_FR, AH_RF, AH_FF, AH_RR */
+  uint8_t reserved;
+} ah_amplicon;
+
+/* Pair every kept + site with every kept - site of the same pair and genome
+ * whose amplicon length end - start lies in [min_len, max_len] of that pair's
+ * window; all such pairs are reported (FF and RR included).  d_hits must be
+ * in the canonical order written by ah_scan_primers.  Output sorted by
+ * (pair, genome, start, end, orient).  capacity 0 counts without writing.
+ * Errors: AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT,
+ * AH_ERR_WORKSPACE, AH_ERR_HIP. */
+ah_status ah_pair_amplicons(const ah_hit* d_hits, const ah_result* d_nhits, uint64_t hit_capacity,
+                            const ah_primer_pair* pairs, const ah_window* windows,
+                            uint32_t n_pairs, ah_amplicon* d_amp, uint64_t capacity,
+                            ah_result* d_res, void* d_work, size_t work_bytes, void* stream);
+size_t ah_pair_workspace_bytes(uint64_t hit_capacity, uint32_t n_pairs);
+
+/* ---------------------------------------------------------------------------
+ * Utilities.
+ * ------------------------------------------------------------------------- */
+const char* ah_status_str(int status);
+/* Message of the last error on the calling thread ("" if none). */
+const char* ah_last_error(void);
+/* Drop the cached specialised kernels and per-set device tables. */
+void ah_release_caches(void);
+/* Number of scan-kernel specialisations compiled so far and their total
+ * compile time in milliseconds. */
+void ah_jit_stats(uint64_t* n_compiled, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AH_H */

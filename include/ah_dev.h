@@ -1,0 +1,37 @@
+/*
+ * libah introspection helpers (host only; no GPU needed).  They expose the
+ * primer compiler and the per-primer-set scan specialisation described in
+ * ah.h (primer matching, Section 2.1 of AmpliconHunter, arXiv 2509.13300) so
+ * that both can be checked without running a kernel.
+ */
+#ifndef AH_DEV_H
+#define AH_DEV_H
+
+#include "ah.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Validate a primer set exactly as ah_scan_primers does (IUPAC codes, length
+ * 5..32, k <= AH_MAX_K, clamp <= primer length); no device work.  Returns
+ * AH_OK or the error ah_scan_primers would return (message in
+ * ah_last_error()). */
+ah_status ah_validate_pairs(const ah_primer_pair* pairs, uint32_t n_pairs);
+
+/* Source text of the specialised scan program for a primer set (has_nmask:
+ * whether the collection carries a non-ACGT mask).  Copies at most
+ * buf_bytes - 1 characters plus a terminating NUL into buf (buf may be NULL)
+ * and returns the full size including the NUL, or 0 if the set is invalid. */
+size_t ah_scan_program_source(const ah_primer_pair* pairs, uint32_t n_pairs, int has_nmask,
+                              char* buf, size_t buf_bytes);
+
+/* Compile (but do not load) the specialised scan program for gfx950 and
+ * report the code-object size.  Errors: as ah_validate_pairs, AH_ERR_JIT. */
+ah_status ah_scan_program_compile(const ah_primer_pair* pairs, uint32_t n_pairs, int has_nmask,
+                                  size_t* code_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AH_DEV_H */

@@ -45,15 +45,17 @@ def call_amplicons(hits: np.ndarray, pairs, filter_tm: bool = False,
             sel = sel_q & (h["genome"] == g)
             plus = np.flatnonzero(sel & (h["strand"] == 0))
             minus = np.flatnonzero(sel & (h["strand"] == 1))
+            bpos = h["pos"][minus].astype(np.int64)
+            bend = bpos + np.where(h["primer"][minus] == 0, plen[0], plen[1])
             for a in plus:
-                for b in minus:
-                    start = int(h["pos"][a])
-                    end = int(h["pos"][b]) + plen[int(h["primer"][b])]
-                    length = end - start
-                    if pr.min_len <= length <= pr.max_len:
-                        out.append((q, int(g), start, end,
-                                    _ORIENT[(int(h["primer"][a]), int(h["primer"][b]))],
-                                    int(idx[a]), int(idx[b])))
+                start = int(h["pos"][a])
+                length = bend - start
+                ok = np.flatnonzero((length >= pr.min_len) & (length <= pr.max_len))
+                ap = int(h["primer"][a])
+                for j in ok:
+                    b = minus[j]
+                    out.append((q, int(g), start, int(bend[j]),
+                                _ORIENT[(ap, int(h["primer"][b]))], int(idx[a]), int(idx[b])))
     amp = np.array(out, dtype=AMP_DTYPE) if out else np.zeros(0, AMP_DTYPE)
     order = np.lexsort((amp["orient"], amp["end"], amp["start"], amp["genome"], amp["pair"]))
     return amp[order]

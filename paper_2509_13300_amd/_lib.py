@@ -1,0 +1,243 @@
+"""ctypes binding of libah (include/ah.h): argument marshalling only.
+
+Every function here forwards to the C entry point of the same name; all the
+work runs in libah's HIP kernels.  Device buffers are torch tensors (their
+data pointers are passed through) and streams are torch streams.  There is
+no fallback: if libah.so is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libah.so")
+
+AH_OK, AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT = 0, -1, -2, -3
+AH_ERR_OVERFLOW, AH_ERR_WORKSPACE, AH_ERR_HIP, AH_ERR_JIT = -4, -5, -6, -7
+AH_FR, AH_RF, AH_FF, AH_RR = 0, 1, 2, 3
+HALO_WORDS = 31
+
+HIT_DTYPE = np.dtype([("genome", "<u4"), ("pos", "<u4"), ("pair", "<u2"),
+                      ("strand_primer", "u1"), ("mm", "u1"), ("tm", "<f4")])
+AMP_DTYPE = np.dtype([("genome", "<u4"), ("start", "<u4"), ("end", "<u4"), ("plus_hit", "<u4"),
+                      ("minus_hit", "<u4"), ("pair", "<u2"), ("orient", "u1"), ("reserved", "u1")])
+assert HIT_DTYPE.itemsize == 16 and AMP_DTYPE.itemsize == 24
+
+
+class AhError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status} ({message})")
+        self.status = status
+
+
+class ah_genomes(ctypes.Structure):
+    _fields_ = [("words", ctypes.c_void_p), ("nmask", ctypes.c_void_p),
+                ("word_off", ctypes.c_void_p), ("len", ctypes.c_void_p),
+                ("n", ctypes.c_uint32), ("max_len", ctypes.c_uint32)]
+
+
+class ah_primer_pair(ctypes.Structure):
+    _fields_ = [("fwd", ctypes.c_char_p), ("rev", ctypes.c_char_p),
+                ("k", ctypes.c_uint32), ("clamp", ctypes.c_uint32)]
+
+
+class ah_result(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("required", ctypes.c_uint64),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+
+
+class ah_tm_params(ctypes.Structure):
+    _fields_ = [("dnac1_nM", ctypes.c_double), ("dnac2_nM", ctypes.c_double),
+                ("Na_mM", ctypes.c_double), ("K_mM", ctypes.c_double),
+                ("Tris_mM", ctypes.c_double), ("Mg_mM", ctypes.c_double),
+                ("dNTPs_mM", ctypes.c_double), ("saltcorr", ctypes.c_int32),
+                ("selfcomp", ctypes.c_int32)]
+
+
+class ah_window(ctypes.Structure):
+    _fields_ = [("min_len", ctypes.c_uint32), ("max_len", ctypes.c_uint32),
+                ("filter_tm", ctypes.c_int32), ("min_tm", ctypes.c_float)]
+
+
+# Every symbol declared in include/ah.h and include/ah_dev.h.
+EXPORTS = (
+    "ah_pack_layout", "ah_pack_genomes", "ah_scan_primers", "ah_scan_workspace_bytes", "ah_tm",
+    "ah_pair_amplicons", "ah_pair_workspace_bytes", "ah_status_str", "ah_last_error",
+    "ah_release_caches", "ah_jit_stats", "ah_validate_pairs", "ah_scan_program_source",
+    "ah_scan_program_compile",
+)
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2509_13300_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    st = ctypes.c_int
+    P = ctypes.POINTER
+    L.ah_pack_layout.argtypes = [vp, u32, vp]
+    L.ah_pack_layout.restype = u64
+    L.ah_pack_genomes.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp]
+    L.ah_pack_genomes.restype = st
+    L.ah_scan_primers.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, vp, u64, vp, vp, sz, vp]
+    L.ah_scan_primers.restype = st
+    L.ah_scan_workspace_bytes.argtypes = [P(ah_genomes), u32, u64]
+    L.ah_scan_workspace_bytes.restype = sz
+    L.ah_tm.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, P(ah_tm_params), vp, vp, u64, vp]
+    L.ah_tm.restype = st
+    L.ah_pair_amplicons.argtypes = [vp, vp, u64, P(ah_primer_pair), P(ah_window), u32, vp, u64, vp,
+                                    vp, sz, vp]
+    L.ah_pair_amplicons.restype = st
+    L.ah_pair_workspace_bytes.argtypes = [u64, u32]
+    L.ah_pair_workspace_bytes.restype = sz
+    L.ah_status_str.argtypes = [ctypes.c_int]
+    L.ah_status_str.restype = ctypes.c_char_p
+    L.ah_last_error.argtypes = []
+    L.ah_last_error.restype = ctypes.c_char_p
+    L.ah_release_caches.argtypes = []
+    L.ah_release_caches.restype = None
+    L.ah_jit_stats.argtypes = [P(ctypes.c_uint64), P(ctypes.c_double)]
+    L.ah_jit_stats.restype = None
+    L.ah_validate_pairs.argtypes = [P(ah_primer_pair), u32]
+    L.ah_validate_pairs.restype = st
+    L.ah_scan_program_source.argtypes = [P(ah_primer_pair), u32, ctypes.c_int, ctypes.c_char_p, sz]
+    L.ah_scan_program_source.restype = sz
+    L.ah_scan_program_compile.argtypes = [P(ah_primer_pair), u32, ctypes.c_int, P(ctypes.c_size_t)]
+    L.ah_scan_program_compile.restype = st
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != AH_OK:
+        msg = lib().ah_last_error().decode(errors="replace")
+        raise AhError(status, where, msg or lib().ah_status_str(status).decode())
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+
+        return int(torch.cuda.current_stream().cuda_stream)
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def primer_pairs(pairs: Sequence) -> ctypes.Array:
+    """Marshal objects with fwd, rev, k, clamp attributes (or 4-tuples)."""
+    arr = (ah_primer_pair * len(pairs))()
+    keep = []
+    for i, p in enumerate(pairs):
+        fwd, rev, k, clamp = (p.fwd, p.rev, p.k, p.clamp) if hasattr(p, "fwd") else p
+        f, r = fwd.encode(), rev.encode()
+        keep += [f, r]
+        arr[i] = ah_primer_pair(f, r, int(k), int(clamp))
+    arr._keep = keep
+    return arr
+
+
+def windows(pairs: Sequence, filter_tm: bool = False, min_tm: float = 50.0) -> ctypes.Array:
+    arr = (ah_window * len(pairs))()
+    for i, p in enumerate(pairs):
+        arr[i] = ah_window(int(p.min_len), int(p.max_len), 1 if filter_tm else 0, float(min_tm))
+    return arr
+
+
+def tm_params(dnac1=250.0, dnac2=0.0, Na=50.0, K=0.0, Tris=0.0, Mg=1.5, dNTPs=0.0, saltcorr=5,
+              selfcomp=False) -> ah_tm_params:
+    return ah_tm_params(dnac1, dnac2, Na, K, Tris, Mg, dNTPs, int(saltcorr), 1 if selfcomp else 0)
+
+
+# ------------------------------------------------------------ entry points --
+def ah_pack_layout(lengths) -> np.ndarray:
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint64)
+    out = np.zeros(lengths.size + 1, dtype=np.uint64)
+    lib().ah_pack_layout(lengths.ctypes.data, lengths.size, out.ctypes.data)
+    return out
+
+
+def ah_pack_genomes(ascii, ascii_off, n, word_off, words, len_, nmask=None, non_acgt=None,
+                    stream=None):
+    _check(lib().ah_pack_genomes(_ptr(ascii), _ptr(ascii_off), int(n), _ptr(word_off), _ptr(words),
+                                 _ptr(len_), _ptr(nmask), _ptr(non_acgt), _stream(stream)),
+           "ah_pack_genomes")
+
+
+def ah_scan_workspace_bytes(genomes: ah_genomes, n_pairs: int, capacity: int) -> int:
+    return int(lib().ah_scan_workspace_bytes(ctypes.byref(genomes), n_pairs, capacity))
+
+
+def ah_scan_primers(genomes: ah_genomes, pairs, hits, capacity: int, res, work, stream=None):
+    pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
+    _check(lib().ah_scan_primers(ctypes.byref(genomes), pp, len(pp), _ptr(hits), int(capacity),
+                                 _ptr(res), _ptr(work), 0 if work is None else work.numel(),
+                                 _stream(stream)), "ah_scan_primers")
+
+
+def ah_tm(genomes: ah_genomes, pairs, params: ah_tm_params, hits, nhits, capacity: int,
+          stream=None):
+    pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
+    _check(lib().ah_tm(ctypes.byref(genomes), pp, len(pp), ctypes.byref(params), _ptr(hits),
+                       _ptr(nhits), int(capacity), _stream(stream)), "ah_tm")
+
+
+def ah_pair_workspace_bytes(hit_capacity: int, n_pairs: int) -> int:
+    return int(lib().ah_pair_workspace_bytes(int(hit_capacity), int(n_pairs)))
+
+
+def ah_pair_amplicons(hits, nhits, hit_capacity: int, pairs, wins, amp, capacity: int, res, work,
+                      stream=None):
+    pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
+    _check(lib().ah_pair_amplicons(_ptr(hits), _ptr(nhits), int(hit_capacity), pp, wins, len(pp),
+                                   _ptr(amp), int(capacity), _ptr(res), _ptr(work),
+                                   0 if work is None else work.numel(), _stream(stream)),
+           "ah_pair_amplicons")
+
+
+def ah_validate_pairs(pairs) -> int:
+    pp = primer_pairs(pairs)
+    return int(lib().ah_validate_pairs(pp, len(pp)))
+
+
+def ah_last_error() -> str:
+    return lib().ah_last_error().decode(errors="replace")
+
+
+def ah_scan_program_source(pairs, has_nmask: bool = False) -> str:
+    pp = primer_pairs(pairs)
+    n = lib().ah_scan_program_source(pp, len(pp), int(has_nmask), None, 0)
+    if n == 0:
+        raise AhError(AH_ERR_INVALID_ARG, "ah_scan_program_source", ah_last_error())
+    buf = ctypes.create_string_buffer(n)
+    lib().ah_scan_program_source(pp, len(pp), int(has_nmask), buf, n)
+    return buf.value.decode()
+
+
+def ah_scan_program_compile(pairs, has_nmask: bool = False) -> int:
+    pp = primer_pairs(pairs)
+    size = ctypes.c_size_t(0)
+    _check(lib().ah_scan_program_compile(pp, len(pp), int(has_nmask), ctypes.byref(size)),
+           "ah_scan_program_compile")
+    return int(size.value)
+
+
+def ah_jit_stats():
+    n, ms = ctypes.c_uint64(0), ctypes.c_double(0)
+    lib().ah_jit_stats(ctypes.byref(n), ctypes.byref(ms))
+    return int(n.value), float(ms.value)
+
+
+def ah_release_caches():
+    lib().ah_release_caches()

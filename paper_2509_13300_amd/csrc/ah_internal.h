@@ -1,0 +1,93 @@
+// Internal declarations shared by the host runtime (ah_host.cpp) and the
+// offline-compiled kernels (ah_kernels.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ah.h"
+
+namespace ah {
+
+constexpr int kBlock = 256;        // threads per workgroup for every kernel
+constexpr int kSortGrid = 256;     // workgroups of the radix-sort passes
+constexpr int kScanGrid = 256;     // workgroups of the generic prefix scan
+constexpr int kScanU = 8;          // packed words per lane in the scan kernel
+constexpr int kTileWords = kBlock * kScanU;
+
+// Per-primer table used by the Tm kernel (one per pair and primer).  Oligos
+// are 2-bit codes (A=0 C=1 G=2 T=3), position j of the primer (5'->3') at
+// bits 2j..2j+1; the masks below have bit 2j set for the positions they name.
+struct PrimerTab {
+  uint64_t fixed;     // codes of the non-degenerate positions (0 at degenerate ones)
+  uint64_t lanes;     // positions 0..L-1
+  uint64_t clampm;    // clamp positions L-c..L-1 (the primer's 3' end)
+  uint64_t stackm;    // positions 0..L-2 (left base of each stack)
+  uint64_t deg;       // oligos in the expansion
+  double KL;          // FP64: salt entropy + R ln C (+ symmetry), cal/(K mol)
+  uint32_t L, k, nd, pad;
+  uint8_t dpos[32];   // degenerate positions, 5'->3'
+  uint8_t nmem[32];   // number of members of each degenerate position
+  uint8_t mem[32];    // members, 2 bits each, in A<C<G<T order
+};
+
+// Per-pair table used by the pairing kernels.
+struct PairTab {
+  uint32_t lf, lr;        // primer lengths
+  uint32_t min_len, max_len;
+  int32_t filter_tm;
+  float min_tm;
+};
+
+// Sort-key field widths for hit records: key = pair | genome | pos | strand | primer.
+struct KeyBits {
+  int qb, gb, pb;
+  int total() const { return qb + gb + pb + 2; }
+};
+
+// ---- launch wrappers (ah_kernels.hip); all asynchronous on `st` ----------
+hipError_t launch_pack(const uint8_t* ascii, const uint64_t* ascii_off, uint32_t n,
+                       const uint64_t* word_off, uint32_t* words, uint32_t* len,
+                       uint32_t* nmask, uint64_t* non_acgt, int grid, hipStream_t st);
+hipError_t launch_result_init(ah_result* res, hipStream_t st);
+hipError_t launch_result_finalize(ah_result* res, uint64_t cap, uint64_t* n_out, hipStream_t st);
+hipError_t launch_tile_counts(const uint32_t* len, uint32_t n, uint64_t* counts, hipStream_t st);
+// Exclusive prefix sum of in[0..n) into out[0..n]; out[n] = total.  n is
+// n_host when n_dev is null, else *n_dev (device).  tmp: kScanGrid + 1 u64.
+hipError_t launch_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n_host,
+                                 const uint64_t* n_dev, uint64_t* tmp, hipStream_t st);
+hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, const uint64_t* n_dev,
+                                     uint64_t* tmp, hipStream_t st);
+// Radix sort of staged hit records into canonical order.
+struct SortBuffers {
+  uint64_t* keys[2];
+  uint32_t* idx[2];
+  uint64_t* hist;      // 256 * kSortGrid
+  uint64_t* hist_off;  // 256 * kSortGrid + 1
+  uint64_t* scan_tmp;  // kScanGrid + 1
+};
+hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev,
+                            KeyBits kb, const SortBuffers& sb, hipStream_t st);
+hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, ah_hit* hits,
+                     const ah_result* nhits, uint64_t cap, int grid, hipStream_t st);
+struct PairBuffers {
+  uint64_t* n;          // [1] number of hits to pair
+  uint32_t* flag_f;     // [cap] kept - site of the fwd primer
+  uint32_t* flag_r;     // [cap]
+  uint64_t* off_f;      // [cap + 1]
+  uint64_t* off_r;      // [cap + 1]
+  uint64_t* mkey_f;     // [cap] (pair << 32 | genome) of compacted - sites
+  uint32_t* mpos_f;     // [cap]
+  uint32_t* midx_f;     // [cap]
+  uint64_t* mkey_r;
+  uint32_t* mpos_r;
+  uint32_t* midx_r;
+  uint32_t* cnt;        // [cap] amplicons started by each leader + site
+  uint64_t* cnt_off;    // [cap + 1]
+  uint64_t* scan_tmp;   // kScanGrid + 1
+};
+hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
+                       const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
+                       const PairBuffers& pb, int grid, hipStream_t st);
+
+}  // namespace ah

@@ -1,0 +1,659 @@
+// Offline-compiled kernels of libah: packing, prefix scans, the canonical-order
+// radix sort of hit records, nearest-neighbour melting temperature and
+// amplicon calling.  The site scan itself is specialised per primer set at
+// run time (scan_core.hip).
+#include <math.h>
+
+#include "ah_internal.h"
+
+namespace ah {
+namespace {
+
+typedef unsigned long long u64;
+typedef uint32_t u32;
+
+__device__ __forceinline__ u64 grid_threads() { return (u64)gridDim.x * blockDim.x; }
+__device__ __forceinline__ u64 global_tid() { return (u64)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// Exclusive scan of one value per thread across a 256-thread workgroup.
+__device__ __forceinline__ u64 block_exclusive_scan(u64 v, u64* lds4, u64& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  u64 x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    u64 y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds4[w] = x;
+  __syncthreads();
+  u64 before = 0;
+  for (int i = 0; i < w; ++i) before += lds4[i];
+  total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+  __syncthreads();
+  return before + x - v;
+}
+
+__device__ __forceinline__ u64 block_sum(u64 v, u64* lds4) {
+  u64 t;
+  block_exclusive_scan(v, lds4, t);
+  return t;
+}
+
+// ---------------------------------------------------------------- packing --
+// One thread per packed word: bit b of word t of genome g is base b*S + t.
+__global__ __launch_bounds__(kBlock) void k_pack(const uint8_t* __restrict__ ascii,
+                                                 const u64* __restrict__ ascii_off, u32 n,
+                                                 const u64* __restrict__ word_off,
+                                                 uint2* __restrict__ words, u32* __restrict__ len,
+                                                 u32* __restrict__ nmask,
+                                                 u64* __restrict__ non_acgt) {
+  const u64 W = word_off[n];
+  for (u64 w = global_tid(); w < W; w += grid_threads()) {
+    u32 lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const u32 mid = (lo + hi) >> 1;
+      if (word_off[mid] <= w) lo = mid; else hi = mid;
+    }
+    const u32 g = lo;
+    const u64 a0 = ascii_off[g];
+    const u64 nb = ascii_off[g + 1] - a0;
+    const u64 S = (nb + 31) >> 5;
+    const u64 t = w - word_off[g];
+    u32 h = 0, l = 0, nm = 0;
+#pragma unroll 8
+    for (int b = 0; b < 32; ++b) {
+      const u64 p = (u64)b * S + t;
+      u32 code = 0, isn = 0;
+      if (p < nb) {
+        const u32 c = ascii[a0 + p] | 0x20u;  // fold case
+        if (c == 'a') code = 0;
+        else if (c == 'c') code = 1;
+        else if (c == 'g') code = 2;
+        else if (c == 't') code = 3;
+        else isn = 1;
+      }
+      h |= (code >> 1) << b;
+      l |= (code & 1u) << b;
+      nm |= isn << b;
+    }
+    words[w] = make_uint2(h, l);
+    if (nmask) nmask[w] = nm;
+    if (t == 0) len[g] = (u32)nb;
+    if (non_acgt && t < S && nm) atomicAdd(&non_acgt[g], (u64)__popc(nm));
+  }
+}
+
+__global__ void k_zero_u64(u64* p, u32 n) {
+  for (u64 i = global_tid(); i < n; i += grid_threads()) p[i] = 0;
+}
+
+// ----------------------------------------------------------- ah_result ----
+__global__ void k_result_init(ah_result* r) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    r->count = 0;
+    r->required = 0;
+    r->status = AH_OK;
+    r->reserved = 0;
+  }
+}
+
+__global__ void k_result_finalize(ah_result* r, u64 cap, u64* n_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const u64 req = r->required;
+    const u64 c = req < cap ? req : cap;
+    r->count = c;
+    r->status = req > cap ? AH_ERR_OVERFLOW : AH_OK;
+    if (n_out) *n_out = c;
+  }
+}
+
+__global__ void k_tile_counts(const u32* __restrict__ len, u32 n, u64* __restrict__ counts) {
+  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+    const u64 S = ((u64)len[i] + 31) >> 5;
+    counts[i] = (S + kTileWords - 1) / kTileWords;
+  }
+}
+
+// ------------------------------------------------------- prefix scans ----
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in, u64 n_host,
+                                                        const u64* __restrict__ n_dev,
+                                                        u64* __restrict__ partial) {
+  __shared__ u64 lds4[4];
+  const u64 n = n_dev ? *n_dev : n_host;
+  const u64 chunk = (n + gridDim.x - 1) / gridDim.x;
+  const u64 beg = (u64)blockIdx.x * chunk;
+  const u64 end = beg + chunk < n ? beg + chunk : n;
+  u64 s = 0;
+  for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x) s += (u64)in[i];
+  s = block_sum(s, lds4);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_partials(u64* partial) {
+  __shared__ u64 lds4[4];
+  u64 total;
+  const u64 v = partial[threadIdx.x];
+  const u64 e = block_exclusive_scan(v, lds4, total);
+  partial[threadIdx.x] = e;
+  if (threadIdx.x == 0) partial[kScanGrid] = total;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scan_down(const T* __restrict__ in, u64* __restrict__ out,
+                                                      u64 n_host, const u64* __restrict__ n_dev,
+                                                      const u64* __restrict__ partial) {
+  __shared__ u64 lds4[4];
+  const u64 n = n_dev ? *n_dev : n_host;
+  const u64 chunk = (n + gridDim.x - 1) / gridDim.x;
+  const u64 beg = (u64)blockIdx.x * chunk;
+  const u64 end = beg + chunk < n ? beg + chunk : n;
+  u64 run = partial[blockIdx.x];
+  for (u64 base = beg; base < end; base += blockDim.x) {
+    const u64 i = base + threadIdx.x;
+    const u64 v = i < end ? (u64)in[i] : 0;
+    u64 tot;
+    const u64 e = block_exclusive_scan(v, lds4, tot);
+    if (i < end) out[i] = run + e;
+    run += tot;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partial[kScanGrid];
+}
+
+// ------------------------------------------------------------ radix sort --
+__global__ __launch_bounds__(kBlock) void k_keygen(const ah_hit* __restrict__ st,
+                                                   const u64* __restrict__ n_dev, KeyBits kb,
+                                                   u64* __restrict__ keys, u32* __restrict__ idx) {
+  const u64 n = *n_dev;
+  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+    const ah_hit h = st[i];
+    keys[i] = ((u64)h.pair << (kb.gb + kb.pb + 2)) | ((u64)h.genome << (kb.pb + 2)) |
+              ((u64)h.pos << 2) | (u64)(h.strand_primer & 3u);
+    idx[i] = (u32)i;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_hist(const u64* __restrict__ keys,
+                                                      const u64* __restrict__ n_dev, int shift,
+                                                      u64* __restrict__ hist) {
+  __shared__ u32 h[256];
+  const u64 n = *n_dev;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const u64 chunk = (n + gridDim.x - 1) / gridDim.x;
+  const u64 beg = (u64)blockIdx.x * chunk;
+  const u64 end = beg + chunk < n ? beg + chunk : n;
+  for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x)
+    atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  __syncthreads();
+  hist[(u64)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: items keep their order within a digit (block, then tile,
+// then wave, then lane).
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(const u64* __restrict__ kin,
+                                                         const u32* __restrict__ iin,
+                                                         u64* __restrict__ kout, u32* __restrict__ iout,
+                                                         const u64* __restrict__ n_dev, int shift,
+                                                         const u64* __restrict__ hist_off) {
+  __shared__ u64 run[256];
+  __shared__ u32 wcnt[4][256];
+  const u64 n = *n_dev;
+  const u64 chunk = (n + gridDim.x - 1) / gridDim.x;
+  const u64 beg = (u64)blockIdx.x * chunk;
+  const u64 end = beg + chunk < n ? beg + chunk : n;
+  run[threadIdx.x] = hist_off[(u64)threadIdx.x * gridDim.x + blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (u64 base = beg; base < end; base += blockDim.x) {
+    for (int q = 0; q < 4; ++q) wcnt[q][threadIdx.x] = 0;
+    __syncthreads();
+    const u64 i = base + threadIdx.x;
+    const bool valid = i < end;
+    u64 key = 0;
+    u32 id = 0, d = 0;
+    if (valid) {
+      key = kin[i];
+      id = iin[i];
+      d = (u32)((key >> shift) & 255u);
+    }
+    u64 peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const u64 bal = __ballot(valid && on);
+      peers &= on ? bal : ~bal;
+    }
+    const u64 below = peers & ((1ull << lane) - 1ull);
+    const u32 rank = (u32)__popcll(below);
+    if (valid && rank == 0) wcnt[w][d] = (u32)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      u64 dst = run[d] + rank;
+      for (int q = 0; q < w; ++q) dst += wcnt[q][d];
+      kout[dst] = key;
+      iout[dst] = id;
+    }
+    __syncthreads();
+    run[threadIdx.x] += (u64)wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
+                        wcnt[3][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(const ah_hit* __restrict__ st,
+                                                   const u32* __restrict__ idx,
+                                                   const u64* __restrict__ n_dev,
+                                                   ah_hit* __restrict__ out) {
+  const u64 n = *n_dev;
+  for (u64 i = global_tid(); i < n; i += grid_threads()) out[i] = st[idx[i]];
+}
+
+// ------------------------------------------------ melting temperature ----
+// SantaLucia (1998) unified nearest-neighbour stacks, indexed by the
+// dinucleotide (5' base * 4 + 3' base) read on the oligo strand.
+__constant__ float c_nn_dh[16] = {
+    -7.9f, -8.4f, -7.8f, -7.2f,   // AA AC(=GT) AG(=CT) AT
+    -8.5f, -8.0f, -10.6f, -7.8f,  // CA CC(=GG) CG CT
+    -8.2f, -9.8f, -8.0f, -8.4f,   // GA GC GG GT
+    -7.2f, -8.2f, -8.5f, -7.9f};  // TA TC(=GA) TG(=CA) TT(=AA)
+__constant__ float c_nn_ds[16] = {
+    -22.2f, -22.4f, -21.0f, -20.4f,
+    -22.7f, -19.9f, -27.2f, -21.0f,
+    -22.2f, -24.4f, -19.9f, -22.4f,
+    -21.3f, -22.2f, -22.7f, -22.2f};
+constexpr float kInitGcH = 0.1f, kInitGcS = -2.8f, kInitAtH = 2.3f, kInitAtS = 4.1f;
+
+// Error-free transformation of s + x (Knuth's TwoSum); the rounding error is
+// accumulated in c.
+__device__ __forceinline__ void two_sum(float& s, float& c, float x) {
+  const float t = s + x;
+  const float bp = t - s;
+  const float err = (s - (t - bp)) + (x - bp);
+  s = t;
+  c += err;
+}
+
+__device__ __forceinline__ void init_term(u32 base, float& sh, float& ch, float& ss, float& cs) {
+  const bool gc = base == 1u || base == 2u;
+  two_sum(sh, ch, gc ? kInitGcH : kInitAtH);
+  two_sum(ss, cs, gc ? kInitGcS : kInitAtS);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
+                                               const u32* __restrict__ nmask,
+                                               const u64* __restrict__ word_off,
+                                               const u32* __restrict__ len,
+                                               const PrimerTab* __restrict__ tabs,
+                                               ah_hit* __restrict__ hits,
+                                               const ah_result* __restrict__ nhits, u64 cap) {
+  const u64 cnt = nhits->count;
+  const u64 n = cnt < cap ? cnt : cap;
+  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+    ah_hit h = hits[i];
+    const PrimerTab* T = &tabs[(u32)h.pair * 2u + (h.strand_primer & 1u)];
+    const u32 L = T->L;
+    const u32 strand = (h.strand_primer >> 1) & 1u;
+    const u64 S = ((u64)len[h.genome] + 31) >> 5;
+    const u32 b = (u32)(h.pos / S);
+    const u64 w0 = word_off[h.genome] + (h.pos - (u64)b * S);
+    // ow: the base an oligo must carry at each primer position to pair with
+    // the template (2 bits per position, primer 5'->3'); nb: positions
+    // opposite a non-ACGT template base, which pair with nothing.
+    u64 ow = 0, nb = 0;
+    for (u32 j = 0; j < L; ++j) {
+      const uint2 wv = words[w0 + j];
+      const u32 c = (((wv.x >> b) & 1u) << 1) | ((wv.y >> b) & 1u);
+      const u32 isn = nmask ? (nmask[w0 + j] >> b) & 1u : 0u;
+      const u32 jj = strand ? L - 1u - j : j;
+      ow |= (u64)(strand ? 3u - c : c) << (2u * jj);
+      nb |= (u64)isn << (2u * jj);
+    }
+    const u64 lanes = T->lanes & ~nb;
+    const u64 clampm = T->clampm;
+    const u64 stackm = T->stackm;
+    const u32 k = T->k;
+    const u32 nd = T->nd;
+    const double KL = T->KL;
+    // odometer over the degenerate positions, 3'-most fastest
+    u64 o = T->fixed;
+    u64 choice = 0;
+    for (u32 d = 0; d < nd; ++d) o |= (u64)(T->mem[d] & 3u) << (2u * T->dpos[d]);
+    float best = __int_as_float(0x7fc00000);  // NaN until a compatible oligo is seen
+    for (u64 it = 0; it < T->deg; ++it) {
+      const u64 x = o ^ ow;
+      const u64 eq = ~(x | (x >> 1)) & lanes;  // paired positions
+      const u32 mism = L - (u32)__popcll(eq);
+      if (mism <= k && (eq & clampm) == clampm) {
+        float sh = 0.f, ch = 0.f, ss = 0.f, cs = 0.f;
+        u64 st = eq & (eq >> 2) & stackm;
+        while (st) {
+          const u32 j2 = (u32)__ffsll((long long)st) - 1u;
+          st &= st - 1;
+          const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
+          two_sum(sh, ch, c_nn_dh[ix]);
+          two_sum(ss, cs, c_nn_ds[ix]);
+        }
+        if (eq) {
+          const u32 lo = (u32)__ffsll((long long)eq) - 1u;
+          const u32 hi = 63u - (u32)__clzll((long long)eq);
+          init_term((u32)(o >> lo) & 3u, sh, ch, ss, cs);
+          init_term((u32)(o >> hi) & 3u, sh, ch, ss, cs);
+        }
+        const float den = (float)((double)ss + (double)cs + KL);
+        const float tm = 1000.0f * (sh + ch) / den - 273.15f;
+        best = (best == best && best >= tm) ? best : tm;
+      }
+      // advance the odometer
+      for (int d = (int)nd - 1; d >= 0; --d) {
+        const u32 sh2 = 2u * (u32)d;
+        const u32 cur = (u32)(choice >> sh2) & 3u;
+        const u32 pos2 = 2u * T->dpos[d];
+        const u32 mcur = (T->mem[d] >> (2u * cur)) & 3u;
+        if (cur + 1u < T->nmem[d]) {
+          const u32 mnext = (T->mem[d] >> (2u * (cur + 1u))) & 3u;
+          choice += 1ull << sh2;
+          o ^= (u64)(mcur ^ mnext) << pos2;
+          break;
+        }
+        const u32 m0 = T->mem[d] & 3u;
+        choice &= ~(3ull << sh2);
+        o ^= (u64)(mcur ^ m0) << pos2;
+      }
+    }
+    h.tm = best;
+    hits[i] = h;
+  }
+}
+
+// ----------------------------------------------------------- pairing ----
+__global__ void k_pair_n(const ah_result* __restrict__ nhits, u64 cap, u64* __restrict__ n_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const u64 c = nhits->count;
+    *n_out = c < cap ? c : cap;
+  }
+}
+
+__device__ __forceinline__ bool kept(const ah_hit& h, const PairTab* tabs) {
+  const PairTab& p = tabs[h.pair];
+  return !p.filter_tm || h.tm >= p.min_tm;  // NaN fails the filter
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_mark(const ah_hit* __restrict__ hits,
+                                                      const u64* __restrict__ n_dev,
+                                                      const PairTab* __restrict__ tabs,
+                                                      u32* __restrict__ ff, u32* __restrict__ fr) {
+  const u64 n = *n_dev;
+  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+    const ah_hit h = hits[i];
+    const bool minus = (h.strand_primer >> 1) & 1u;
+    const bool k = kept(h, tabs) && minus;
+    ff[i] = k && !(h.strand_primer & 1u);
+    fr[i] = k && (h.strand_primer & 1u);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_compact(
+    const ah_hit* __restrict__ hits, const u64* __restrict__ n_dev, const u32* __restrict__ ff,
+    const u32* __restrict__ fr, const u64* __restrict__ off_f, const u64* __restrict__ off_r,
+    u64* __restrict__ kf, u32* __restrict__ pf, u32* __restrict__ xf, u64* __restrict__ kr,
+    u32* __restrict__ pr, u32* __restrict__ xr) {
+  const u64 n = *n_dev;
+  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+    if (!ff[i] && !fr[i]) continue;
+    const ah_hit h = hits[i];
+    const u64 key = ((u64)h.pair << 32) | h.genome;
+    if (ff[i]) {
+      const u64 j = off_f[i];
+      kf[j] = key; pf[j] = h.pos; xf[j] = (u32)i;
+    } else {
+      const u64 j = off_r[i];
+      kr[j] = key; pr[j] = h.pos; xr[j] = (u32)i;
+    }
+  }
+}
+
+// First index in [0, m) whose (key, pos) is >= (key0, pos0).
+__device__ __forceinline__ u64 lower(const u64* __restrict__ K, const u32* __restrict__ P, u64 m,
+                                     u64 key0, u64 pos0) {
+  u64 lo = 0, hi = m;
+  while (lo < hi) {
+    const u64 mid = (lo + hi) >> 1;
+    const bool less = K[mid] < key0 || (K[mid] == key0 && (u64)P[mid] < pos0);
+    if (less) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+struct Range {
+  u64 beg, end;
+};
+
+// Minus-site ranges for a + site at `pos` of (pair, genome) `key` whose
+// amplicon length b.pos + lb - pos lies in [min_len, max_len].
+__device__ __forceinline__ Range minus_range(const u64* K, const u32* P, u64 m, u64 key, u64 pos,
+                                             u32 lb, const PairTab& t) {
+  const long long lo = (long long)pos + (long long)t.min_len - (long long)lb;
+  const long long hi = (long long)pos + (long long)t.max_len - (long long)lb;
+  Range r{0, 0};
+  if (hi < 0) return r;
+  r.beg = lower(K, P, m, key, lo < 0 ? 0 : (u64)lo);
+  r.end = lower(K, P, m, key, (u64)hi + 1);
+  if (r.end < r.beg) r.end = r.beg;
+  return r;
+}
+
+__device__ __forceinline__ bool plus_kept(const ah_hit& h, const PairTab* tabs) {
+  return !((h.strand_primer >> 1) & 1u) && kept(h, tabs);
+}
+
+__device__ __forceinline__ bool same_site(const ah_hit& a, const ah_hit& b) {
+  return a.pair == b.pair && a.genome == b.genome && a.pos == b.pos;
+}
+
+// A leader is the first kept + site of its (pair, genome, pos) group; it owns
+// every amplicon that starts there (the fwd and rev + sites of that pos).
+__device__ __forceinline__ int group_of(const ah_hit* hits, u64 n, u64 i, const PairTab* tabs,
+                                        ah_hit& a0, ah_hit& a1) {
+  a0 = hits[i];
+  if (!plus_kept(a0, tabs)) return 0;
+  if (i > 0) {
+    const ah_hit p = hits[i - 1];
+    if (plus_kept(p, tabs) && same_site(p, a0)) return 0;
+  }
+  if (i + 1 < n) {
+    a1 = hits[i + 1];
+    if (plus_kept(a1, tabs) && same_site(a1, a0)) return 2;
+  }
+  return 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_count(
+    const ah_hit* __restrict__ hits, const u64* __restrict__ n_dev, const PairTab* __restrict__ tabs,
+    const u64* __restrict__ kf, const u32* __restrict__ pf, const u64* __restrict__ off_f,
+    const u64* __restrict__ kr, const u32* __restrict__ pr, const u64* __restrict__ off_r,
+    u32* __restrict__ cnt) {
+  const u64 n = *n_dev;
+  const u64 mf = off_f[n], mr = off_r[n];
+  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+    ah_hit a[2];
+    const int ng = group_of(hits, n, i, tabs, a[0], a[1]);
+    u64 c = 0;
+    for (int q = 0; q < ng; ++q) {
+      const PairTab t = tabs[a[q].pair];
+      const u64 key = ((u64)a[q].pair << 32) | a[q].genome;
+      const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t);
+      const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t);
+      c += (rf.end - rf.beg) + (rr.end - rr.beg);
+    }
+    cnt[i] = (u32)c;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_write(
+    const ah_hit* __restrict__ hits, const u64* __restrict__ n_dev, const PairTab* __restrict__ tabs,
+    const u64* __restrict__ kf, const u32* __restrict__ pf, const u32* __restrict__ xf,
+    const u64* __restrict__ off_f, const u64* __restrict__ kr, const u32* __restrict__ pr,
+    const u32* __restrict__ xr, const u64* __restrict__ off_r, const u64* __restrict__ cnt_off,
+    ah_amplicon* __restrict__ amp, u64 cap) {
+  const u64 n = *n_dev;
+  const u64 mf = off_f[n], mr = off_r[n];
+  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+    ah_hit a[2];
+    const int ng = group_of(hits, n, i, tabs, a[0], a[1]);
+    if (ng == 0) continue;
+    const u64 base = cnt_off[i];
+    if (base >= cap) continue;
+    // up to four lists, each ordered by end: (a primer, b primer)
+    Range r[4];
+    u32 orient[4], lb[4], plus_idx[4];
+    const u32* P[4];
+    const u32* X[4];
+    int nl = 0;
+    for (int q = 0; q < ng; ++q) {
+      const PairTab t = tabs[a[q].pair];
+      const u64 key = ((u64)a[q].pair << 32) | a[q].genome;
+      const u32 ap = a[q].strand_primer & 1u;
+      const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t);
+      const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t);
+      r[nl] = rf; lb[nl] = t.lf; P[nl] = pf; X[nl] = xf; plus_idx[nl] = (u32)(i + q);
+      orient[nl] = ap ? (u32)AH_RF : (u32)AH_FF; ++nl;
+      r[nl] = rr; lb[nl] = t.lr; P[nl] = pr; X[nl] = xr; plus_idx[nl] = (u32)(i + q);
+      orient[nl] = ap ? (u32)AH_RR : (u32)AH_FR; ++nl;
+    }
+    u64 w = base;
+    while (w < cap) {
+      int best = -1;
+      u64 bend = 0;
+      for (int q = 0; q < nl; ++q) {
+        if (r[q].beg >= r[q].end) continue;
+        const u64 e = (u64)P[q][r[q].beg] + lb[q];
+        if (best < 0 || e < bend || (e == bend && orient[q] < orient[best])) {
+          best = q;
+          bend = e;
+        }
+      }
+      if (best < 0) break;
+      ah_amplicon A;
+      A.genome = a[0].genome;
+      A.start = a[0].pos;
+      A.end = (u32)bend;
+      A.plus_hit = plus_idx[best];
+      A.minus_hit = X[best][r[best].beg];
+      A.pair = a[0].pair;
+      A.orient = (uint8_t)orient[best];
+      A.reserved = 0;
+      amp[w++] = A;
+      ++r[best].beg;
+    }
+  }
+}
+
+__global__ void k_pair_finalize(const u64* __restrict__ n_dev, const u64* __restrict__ cnt_off,
+                                u64 cap, ah_result* __restrict__ res) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const u64 req = cnt_off[*n_dev];
+    res->required = req;
+    res->count = req < cap ? req : cap;
+    res->status = req > cap ? AH_ERR_OVERFLOW : AH_OK;
+    res->reserved = 0;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------- launchers ----
+hipError_t launch_pack(const uint8_t* ascii, const uint64_t* ascii_off, uint32_t n,
+                       const uint64_t* word_off, uint32_t* words, uint32_t* len, uint32_t* nmask,
+                       uint64_t* non_acgt, int grid, hipStream_t st) {
+  if (non_acgt) {
+    k_zero_u64<<<(n + kBlock - 1) / kBlock > 0 ? (n + kBlock - 1) / kBlock : 1, kBlock, 0, st>>>(
+        (u64*)non_acgt, n);
+  }
+  k_pack<<<grid, kBlock, 0, st>>>(ascii, (const u64*)ascii_off, n, (const u64*)word_off,
+                                  (uint2*)words, len, nmask, (u64*)non_acgt);
+  return hipGetLastError();
+}
+
+hipError_t launch_result_init(ah_result* res, hipStream_t st) {
+  k_result_init<<<1, 64, 0, st>>>(res);
+  return hipGetLastError();
+}
+
+hipError_t launch_result_finalize(ah_result* res, uint64_t cap, uint64_t* n_out, hipStream_t st) {
+  k_result_finalize<<<1, 64, 0, st>>>(res, cap, (u64*)n_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_counts(const uint32_t* len, uint32_t n, uint64_t* counts, hipStream_t st) {
+  const int grid = (int)((n + kBlock - 1) / kBlock) > 0 ? (int)((n + kBlock - 1) / kBlock) : 1;
+  k_tile_counts<<<grid < 4096 ? grid : 4096, kBlock, 0, st>>>(len, n, (u64*)counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n_host,
+                                 const uint64_t* n_dev, uint64_t* tmp, hipStream_t st) {
+  k_scan_reduce<u64><<<kScanGrid, kBlock, 0, st>>>((const u64*)in, n_host, (const u64*)n_dev, (u64*)tmp);
+  k_scan_partials<<<1, kBlock, 0, st>>>((u64*)tmp);
+  k_scan_down<u64><<<kScanGrid, kBlock, 0, st>>>((const u64*)in, (u64*)out, n_host, (const u64*)n_dev,
+                                                 (const u64*)tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, const uint64_t* n_dev,
+                                     uint64_t* tmp, hipStream_t st) {
+  k_scan_reduce<u32><<<kScanGrid, kBlock, 0, st>>>(in, 0, (const u64*)n_dev, (u64*)tmp);
+  k_scan_partials<<<1, kBlock, 0, st>>>((u64*)tmp);
+  k_scan_down<u32><<<kScanGrid, kBlock, 0, st>>>(in, (u64*)out, 0, (const u64*)n_dev, (const u64*)tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev, KeyBits kb,
+                            const SortBuffers& sb, hipStream_t st) {
+  const int grid = 1024;
+  k_keygen<<<grid, kBlock, 0, st>>>(staged, (const u64*)n_dev, kb, (u64*)sb.keys[0], sb.idx[0]);
+  int cur = 0;
+  const int bits = kb.total();
+  for (int shift = 0; shift < bits; shift += 8) {
+    k_sort_hist<<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], (const u64*)n_dev, shift,
+                                             (u64*)sb.hist);
+    launch_exclusive_scan(sb.hist, sb.hist_off, (uint64_t)256 * kSortGrid, nullptr, sb.scan_tmp, st);
+    k_sort_scatter<<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], sb.idx[cur],
+                                                (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1],
+                                                (const u64*)n_dev, shift, (const u64*)sb.hist_off);
+    cur ^= 1;
+  }
+  k_gather<<<grid, kBlock, 0, st>>>(staged, sb.idx[cur], (const u64*)n_dev, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, ah_hit* hits, const ah_result* nhits,
+                     uint64_t cap, int grid, hipStream_t st) {
+  k_tm<<<grid, kBlock, 0, st>>>((const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, tabs,
+                                hits, nhits, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
+                       const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
+                       const PairBuffers& pb, int grid, hipStream_t st) {
+  const u64* n = (const u64*)pb.n;
+  k_pair_n<<<1, 64, 0, st>>>(nhits, hit_cap, (u64*)pb.n);
+  k_pair_mark<<<grid, kBlock, 0, st>>>(hits, n, tabs, pb.flag_f, pb.flag_r);
+  launch_exclusive_scan_u32(pb.flag_f, pb.off_f, pb.n, pb.scan_tmp, st);
+  launch_exclusive_scan_u32(pb.flag_r, pb.off_r, pb.n, pb.scan_tmp, st);
+  k_pair_compact<<<grid, kBlock, 0, st>>>(hits, n, pb.flag_f, pb.flag_r, (const u64*)pb.off_f,
+                                          (const u64*)pb.off_r, (u64*)pb.mkey_f, pb.mpos_f, pb.midx_f,
+                                          (u64*)pb.mkey_r, pb.mpos_r, pb.midx_r);
+  k_pair_count<<<grid, kBlock, 0, st>>>(hits, n, tabs, (const u64*)pb.mkey_f, pb.mpos_f,
+                                        (const u64*)pb.off_f, (const u64*)pb.mkey_r, pb.mpos_r,
+                                        (const u64*)pb.off_r, pb.cnt);
+  launch_exclusive_scan_u32(pb.cnt, pb.cnt_off, pb.n, pb.scan_tmp, st);
+  k_pair_write<<<grid, kBlock, 0, st>>>(hits, n, tabs, (const u64*)pb.mkey_f, pb.mpos_f, pb.midx_f,
+                                        (const u64*)pb.off_f, (const u64*)pb.mkey_r, pb.mpos_r,
+                                        pb.midx_r, (const u64*)pb.off_r, (const u64*)pb.cnt_off, amp,
+                                        cap);
+  k_pair_finalize<<<1, 64, 0, st>>>(n, (const u64*)pb.cnt_off, cap, res);
+  return hipGetLastError();
+}
+
+}  // namespace ah

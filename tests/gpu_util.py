@@ -1,0 +1,63 @@
+"""Helpers for the GPU parity tests: run the libah path on a plan and run the
+oracle on the same bytes."""
+import sys
+
+import numpy as np
+
+from oracle import pair as opair
+from oracle import scan as oscan
+from oracle import tm as otm
+from synth import fill, gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(p, pairs, dev, hit_cap=1 << 16, amp_cap=1 << 16, with_nmask=None, tm=None,
+            filter_tm=False, min_tm=50.0):
+    import torch
+
+    from paper_2509_13300_amd import path
+
+    if with_nmask is None:
+        with_nmask = p.nrun_genome.size > 0
+    ascii, off = gpu.fill_cuda(p, dev)
+    coll, _ = path.pack(ascii, off, p.lengths, with_nmask=with_nmask)
+    buf = path.alloc(coll, len(pairs), hit_cap, amp_cap, dev)
+    path.run(coll, pairs, buf, tm=tm, filter_tm=filter_tm, min_tm=min_tm)
+    torch.cuda.synchronize()
+    return coll, buf
+
+
+def run_oracle(p, pairs, tmp=None, filter_tm=False, min_tm=50.0):
+    seqs = [fill.genome_bytes(p, g) for g in range(p.n)]
+    h = oscan.scan_collection(seqs, pairs)
+    h = otm.fill_tm(h, seqs, pairs, tmp if tmp is not None else otm.TmParams())
+    a = []
+    for q, pr in enumerate(pairs):
+        sel = h[h["pair"] == q]
+        base = np.flatnonzero(h["pair"] == q)
+        aq = opair.call_amplicons(sel, [pr], filter_tm, min_tm)
+        aq["pair"] = q
+        aq["plus_hit"] = base[aq["plus_hit"]]
+        aq["minus_hit"] = base[aq["minus_hit"]]
+        a.append(aq)
+    amps = np.concatenate(a) if a else np.zeros(0, opair.AMP_DTYPE)
+    return h, amps
+
+
+def hit_tuples_gpu(h):
+    return [(int(x["pair"]), int(x["genome"]), int(x["pos"]), int(x["strand_primer"]) >> 1,
+             int(x["strand_primer"]) & 1, int(x["mm"])) for x in h]
+
+
+def hit_tuples_oracle(h):
+    return [(int(x["pair"]), int(x["genome"]), int(x["pos"]), int(x["strand"]), int(x["primer"]),
+             int(x["mm"])) for x in h]
+
+
+def amp_tuples(a):
+    return [(int(x["pair"]), int(x["genome"]), int(x["start"]), int(x["end"]), int(x["orient"]),
+             int(x["plus_hit"]), int(x["minus_hit"])) for x in a]

@@ -1,0 +1,217 @@
+"""GPU parity: the libah path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Hits and amplicons must match exactly; Tm within
+0.01 C."""
+import numpy as np
+import pytest
+
+from gpu_util import amp_tuples, hit_tuples_gpu, hit_tuples_oracle, run_gpu, run_oracle, say
+from oracle import tm as otm
+from synth import fill, gpu, plan
+
+pytestmark = pytest.mark.gpu
+
+TM_TOL = 0.01
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch.device("cuda:0")
+
+
+def check_case(p, pairs, dev, **kw):
+    coll, buf = run_gpu(p, pairs, dev, **kw)
+    from paper_2509_13300_amd import path
+
+    res = path.result(buf.hit_res)
+    assert res["status"] == 0, res
+    gh = path.hits_numpy(buf)
+    ga = path.amps_numpy(buf)
+    oh, oa = run_oracle(p, pairs, filter_tm=kw.get("filter_tm", False), min_tm=kw.get("min_tm", 50.0))
+    assert hit_tuples_gpu(gh) == hit_tuples_oracle(oh)
+    if gh.size:
+        err = np.abs(gh["tm"].astype(np.float64) - oh["tm"])
+        assert np.all(np.isfinite(gh["tm"])) and float(err.max()) <= TM_TOL, float(err.max())
+    assert amp_tuples(ga) == amp_tuples(oa)
+    return gh, ga
+
+
+def test_gpu_filler_matches_numpy_filler(dev):
+    for seed in (1, 2):
+        p = plan.tiny(seed, n_genomes=5, len_lo=1, len_hi=5000, nruns=4)
+        say("filler", p.name, p.lengths.tolist())
+        ascii, off = gpu.fill_cuda(p, dev)
+        want = fill.collection_bytes(p)
+        got = ascii.cpu().numpy()[: want.size]
+        assert np.array_equal(got, want)
+    p = plan.collection(6, seed=77).subset([4, 1])
+    ascii, _ = gpu.fill_cuda(p, dev)
+    assert np.array_equal(ascii.cpu().numpy()[: p.total_bp], fill.collection_bytes(p))
+
+
+def decode(coll, p):
+    """Host decode of the packed layout (bit b of word t = base b*S + t)."""
+    words = coll.words.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    nm = coll.nmask.cpu().numpy().view(np.uint32) if coll.nmask is not None else None
+    off = coll.word_off.cpu().numpy()
+    out = []
+    for g in range(p.n):
+        n = int(p.lengths[g])
+        S = (n + 31) // 32
+        w = words[off[g]:off[g + 1]]
+        assert w.shape[0] == S + 31
+        b = np.arange(32)
+        seq = np.zeros(n, dtype=np.uint8)
+        isn = np.zeros(n, dtype=bool)
+        for t in range(S + 31):
+            pos = b * S + t
+            code = ((w[t, 0] >> b) & 1) * 2 + ((w[t, 1] >> b) & 1)
+            ok = pos < n
+            if t >= S:  # halo words repeat the next segment's start
+                assert np.all(seq[pos[ok]] == np.frombuffer(b"ACGT", np.uint8)[code[ok]])
+                continue
+            seq[pos[ok]] = np.frombuffer(b"ACGT", np.uint8)[code[ok]]
+            if nm is not None:
+                isn[pos[ok]] = ((nm[off[g] + t] >> b) & 1)[ok].astype(bool)
+            assert np.all(code[~ok] == 0)
+        out.append((seq, isn))
+    return out
+
+
+def test_pack_layout_roundtrip(dev):
+    from paper_2509_13300_amd import path
+
+    p = plan.tiny(9, n_genomes=7, len_lo=1, len_hi=3000, nruns=6)
+    p.lengths[:4] = [1, 31, 32, 33]
+    ascii, off = gpu.fill_cuda(p, dev)
+    coll, nonacgt = path.pack(ascii, off, p.lengths, with_nmask=True)
+    dec = decode(coll, p)
+    for g in range(p.n):
+        want = fill.genome_bytes(p, g)
+        seq, isn = dec[g]
+        wn = ~np.isin(want, np.frombuffer(b"ACGT", np.uint8))
+        assert np.array_equal(isn, wn)
+        assert np.array_equal(seq[~wn], want[~wn])
+        assert int(nonacgt[g]) == int(wn.sum())
+
+
+EDGE_LENGTHS = [1, 4, 5, 19, 20, 21, 31, 32, 33, 63, 64, 65, 640, 641, 2047, 20000]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_scan_edge_lengths(dev, k):
+    pr = plan.PairSpec("ACGTRYACGTAC", "TTGCANNGCA", k=k, clamp=k % 3, min_len=20, max_len=400)
+    p = plan.tiny(300 + k, n_genomes=len(EDGE_LENGTHS), pair=pr, n_copies=(0, 2),
+                  gc_lo=0.45, gc_hi=0.55)
+    p.lengths[:] = EDGE_LENGTHS
+    for f in ("plant_genome", "plant_pos", "plant_strand", "plant_template"):
+        setattr(p, f, getattr(p, f)[:0])
+    say("edge lengths k", k)
+    check_case(p, [pr], dev)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_scan_tm_pair_random(dev, seed):
+    rs = np.random.RandomState(seed)
+    codes = "RYSWKMBDHVN"
+    lf, lr = rs.randint(5, 33), rs.randint(5, 33)
+    fwd = plan.random_primer(500 + seed, 0, lf, "".join(rs.choice(list(codes), size=rs.randint(0, 5))))
+    rev = plan.random_primer(500 + seed, 1, lr, "".join(rs.choice(list(codes), size=rs.randint(0, 5))))
+    k = int(rs.randint(0, 4))
+    clamp = int(rs.choice([0, 0, 1, 3, 5])) if min(lf, lr) >= 5 else 0
+    pr = plan.PairSpec(fwd, rev, k=k, clamp=clamp, min_len=lf + lr + 5, max_len=lf + lr + 900)
+    p = plan.tiny(600 + seed, n_genomes=int(rs.randint(1, 6)), len_lo=1, len_hi=60000, pair=pr,
+                  n_copies=(1, 4), nruns=int(rs.choice([0, 0, 5])),
+                  gc_lo=0.3, gc_hi=0.7)
+    say("random case", seed, fwd, rev, k, clamp, p.lengths.tolist())
+    check_case(p, [pr], dev)
+
+
+def test_low_complexity_dense_hits_and_all_orientations(dev):
+    """A tiny alphabet makes hits dense: many records per tile, all four
+    orientations, ties in amplicon ends."""
+    pr = plan.PairSpec("AAAAAAAC", "AAAAAAAG", k=2, clamp=0, min_len=8, max_len=60)
+    p = plan.tiny(77, n_genomes=3, len_lo=3000, len_hi=9000, pair=pr, n_copies=(0, 0),
+                  gc_lo=0.0, gc_hi=0.2)
+    say("dense", p.lengths.tolist())
+    gh, ga = check_case(p, [pr], dev, hit_cap=1 << 20, amp_cap=1 << 22)
+    assert gh.size > 1000 and {int(x) for x in ga["orient"]} == {0, 1, 2, 3}
+
+
+def test_several_pairs_in_one_call(dev):
+    pairs = plan.law_pairs(91, 5)
+    for i, q in enumerate(pairs):
+        q.min_len, q.max_len = 50, 3000
+        q.clamp = i % 3
+    p = plan.tiny(92, n_genomes=4, len_lo=2000, len_hi=30000, pair=pairs[0], n_copies=(1, 3),
+                  span=200)
+    say("several pairs", [(q.fwd, q.rev, q.k) for q in pairs])
+    check_case(p, pairs, dev)
+
+
+def test_overflow_reports_required_and_retry_is_identical(dev):
+    from paper_2509_13300_amd import path
+
+    pr = plan.PairSpec("AAAAAAAC", "AAAAAAAG", k=2, clamp=0, min_len=8, max_len=60)
+    p = plan.tiny(78, n_genomes=2, len_lo=4000, len_hi=6000, pair=pr, n_copies=(0, 0),
+                  gc_lo=0.0, gc_hi=0.2)
+    coll, buf = run_gpu(p, [pr], dev, hit_cap=1 << 20, amp_cap=1 << 22)
+    full = path.hits_numpy(buf)
+    famp = path.amps_numpy(buf)
+    assert full.size > 100
+    coll2, small = run_gpu(p, [pr], dev, hit_cap=37, amp_cap=5)
+    r = path.result(small.hit_res)
+    assert r["status"] == -4 and r["required"] == full.size and r["count"] == 37
+    coll3, again = run_gpu(p, [pr], dev, hit_cap=full.size, amp_cap=famp.size)
+    assert path.result(again.hit_res)["status"] == 0
+    assert path.result(again.amp_res)["status"] == 0
+    assert np.array_equal(path.hits_numpy(again), full)
+    assert np.array_equal(path.amps_numpy(again), famp)
+
+
+def test_tm_filter_on_matches_oracle(dev):
+    pr = plan.PairSpec("GCGTACRYTCCAGTAGC", "GATCGNATCGGCTAAC", k=3, clamp=2, min_len=40,
+                       max_len=2000)
+    p = plan.tiny(88, n_genomes=3, len_lo=5000, len_hi=20000, pair=pr, n_copies=(2, 4))
+    coll, buf = run_gpu(p, [pr], dev)
+    from paper_2509_13300_amd import path
+
+    gh = path.hits_numpy(buf)
+    thr = float(np.median(gh["tm"])) + 0.005  # away from any site's value
+    while np.any(np.abs(gh["tm"] - thr) < 0.011):
+        thr += 0.013
+    say("filter thr", thr)
+    check_case(p, [pr], dev, filter_tm=True, min_tm=thr)
+
+
+def test_tm_conditions_and_error_statistics(dev):
+    from paper_2509_13300_amd import _lib as L
+    from paper_2509_13300_amd import path
+
+    pr = plan.PairSpec("AGRRTTYGATYHTDGYTYAG", "YCNTTCCYTYDYRGTACT", k=3, clamp=0, min_len=100,
+                       max_len=3000)
+    p = plan.tiny(99, n_genomes=3, len_lo=20000, len_hi=60000, pair=pr, n_copies=(2, 4), span=2455)
+    for kw in (dict(), dict(Na=100.0, Mg=0.0, dnac1=500.0, dnac2=100.0),
+               dict(saltcorr=0), dict(K=20.0, Tris=10.0, dNTPs=0.8, selfcomp=True)):
+        tp = L.tm_params(**kw)
+        op = otm.TmParams(dnac1=tp.dnac1_nM, dnac2=tp.dnac2_nM, Na=tp.Na_mM, K=tp.K_mM,
+                          Tris=tp.Tris_mM, Mg=tp.Mg_mM, dNTPs=tp.dNTPs_mM, saltcorr=tp.saltcorr,
+                          selfcomp=bool(tp.selfcomp))
+        coll, buf = run_gpu(p, [pr], dev, tm=tp)
+        gh = path.hits_numpy(buf)
+        oh, _ = run_oracle(p, [pr], tmp=op)
+        assert hit_tuples_gpu(gh) == hit_tuples_oracle(oh)
+        err = np.abs(gh["tm"].astype(np.float64) - oh["tm"])
+        say("Tm", kw, "hits", gh.size, "max err", float(err.max()), "mean err", float(err.mean()))
+        assert float(err.max()) <= TM_TOL
+
+
+def test_plain_workload_full_parity(dev):
+    """The 5 Mbp plain workload, compared in full."""
+    p = plan.plain()
+    pr = p.pairs[0]
+    say("plain", pr)
+    gh, ga = check_case(p, [pr], dev)
+    assert ga.size >= 1 and gh.size >= 4

@@ -1,0 +1,83 @@
+"""CPU-side checks of libah: the library loads and exports every symbol its
+headers declare, host-side layout and validation behave as documented, and
+the per-primer-set scan programs compile for gfx950 (no GPU needed)."""
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2509_13300_amd import _lib as L
+from synth import plan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        for m in re.finditer(r"\b(ah_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert {"ah_pack_genomes", "ah_scan_primers", "ah_pair_amplicons", "ah_tm"} <= names
+    lib = L.lib()
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(L.EXPORTS) == names
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        L.lib()
+
+
+def test_pack_layout():
+    lens = np.array([0, 1, 31, 32, 33, 5_000_000], dtype=np.uint64)
+    off = L.ah_pack_layout(lens)
+    S = (lens + 31) // 32
+    want = np.concatenate([[0], np.cumsum(S + 31)])
+    assert off.tolist() == want.tolist()
+
+
+@pytest.mark.parametrize("fwd,rev,k,clamp,status", [
+    ("ACGTACGTAC", "GGGGCCCCAA", 2, 0, L.AH_OK),
+    ("acgtnnRYKM", "BDHVSWacgt", 15, 10, L.AH_OK),
+    ("ACGU", "ACGTACGT", 1, 0, L.AH_ERR_LIMIT),          # too short first
+    ("ACGUACGTAC", "ACGTACGT", 1, 0, L.AH_ERR_INVALID_PRIMER),
+    ("ACGTA-GTAC", "ACGTACGT", 1, 0, L.AH_ERR_INVALID_PRIMER),
+    ("A" * 33, "ACGTACGT", 1, 0, L.AH_ERR_LIMIT),
+    ("A" * 32, "ACGTACGT", 1, 0, L.AH_OK),
+    ("ACGTACGTAC", "ACGTACGT", 16, 0, L.AH_ERR_LIMIT),
+    ("ACGTACGTAC", "ACGTACGT", 2, 9, L.AH_ERR_LIMIT),
+    ("ACGTACGTAC", "ACGTACGT", 2, 8, L.AH_OK),
+])
+def test_primer_validation(fwd, rev, k, clamp, status):
+    assert L.ah_validate_pairs([(fwd, rev, k, clamp)]) == status
+    if status != L.AH_OK:
+        assert L.ah_last_error()
+
+
+def test_generated_program_tests_every_non_n_position():
+    src = L.ah_scan_program_source([("ACGTNRYSWKMBDHV", "NNNNNAAAAC", 1, 2)])
+    body = src.split("---- generated pattern program follows ----")[1]
+    pat0 = body.split("ah_pat_1")[0]
+    assert pat0.count("x = ") == 15 - 1  # the N position is never a mismatch
+    assert "cf |= x" in pat0 and "ah_valid(c, t, 15u)" in pat0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_generated_programs_compile_for_gfx950(seed):
+    rs = np.random.RandomState(seed)
+    pairs = plan.law_pairs(1000 + seed, 2)
+    for p in pairs:
+        p.clamp = int(rs.randint(0, 6))
+    size = L.ah_scan_program_compile(pairs, has_nmask=bool(seed % 2))
+    assert size > 1000
