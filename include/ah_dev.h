@@ -31,6 +31,16 @@ size_t ah_scan_program_source(const ah_primer_pair* pairs, uint32_t n_pairs, int
 ah_status ah_scan_program_compile(const ah_primer_pair* pairs, uint32_t n_pairs, int has_nmask,
                                   size_t* code_bytes);
 
+/* Kernel timing with HIP events recorded on the launching stream.  While
+ * enabled, every launch of the named kernels is bracketed by a pair of
+ * events: "scan" (the specialised site scan), "tm", "pair" (the amplicon
+ * writer), "sort" (all radix-sort passes of one call), "pack".  Queries wait
+ * for the recorded events and return the launch count and summed device time
+ * since the last reset.  Not for use inside hipGraph capture. */
+void ah_profile_enable(int on);
+void ah_profile_reset(void);
+ah_status ah_profile_query(const char* name, uint64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

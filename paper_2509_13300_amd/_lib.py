@@ -68,7 +68,7 @@ EXPORTS = (
     "ah_pack_layout", "ah_pack_genomes", "ah_scan_primers", "ah_scan_workspace_bytes", "ah_tm",
     "ah_pair_amplicons", "ah_pair_workspace_bytes", "ah_status_str", "ah_last_error",
     "ah_release_caches", "ah_jit_stats", "ah_validate_pairs", "ah_scan_program_source",
-    "ah_scan_program_compile",
+    "ah_scan_program_compile", "ah_profile_enable", "ah_profile_reset", "ah_profile_query",
 )
 
 _lib = None
@@ -113,6 +113,12 @@ def lib() -> ctypes.CDLL:
     L.ah_scan_program_source.restype = sz
     L.ah_scan_program_compile.argtypes = [P(ah_primer_pair), u32, ctypes.c_int, P(ctypes.c_size_t)]
     L.ah_scan_program_compile.restype = st
+    L.ah_profile_enable.argtypes = [ctypes.c_int]
+    L.ah_profile_enable.restype = None
+    L.ah_profile_reset.argtypes = []
+    L.ah_profile_reset.restype = None
+    L.ah_profile_query.argtypes = [ctypes.c_char_p, P(ctypes.c_uint64), P(ctypes.c_double)]
+    L.ah_profile_query.restype = st
     _lib = L
     return L
 
@@ -241,3 +247,19 @@ def ah_jit_stats():
 
 def ah_release_caches():
     lib().ah_release_caches()
+
+
+def ah_profile_enable(on: bool = True):
+    lib().ah_profile_enable(1 if on else 0)
+
+
+def ah_profile_reset():
+    lib().ah_profile_reset()
+
+
+def ah_profile_query(name: str):
+    """(launches, total device ms) of a library kernel since the last reset."""
+    n, ms = ctypes.c_uint64(0), ctypes.c_double(0)
+    _check(lib().ah_profile_query(name.encode(), ctypes.byref(n), ctypes.byref(ms)),
+           "ah_profile_query")
+    return int(n.value), float(ms.value)

@@ -330,6 +330,48 @@ int cu_count() {
   return n;
 }
 
+// ------------------------------------------------------------ profiling --
+struct ProfEntry {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  uint64_t launches = 0;
+  double ms = 0.0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, ProfEntry> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one or more launches on `st` with events when profiling is on.
+struct ProfScope {
+  const char* name;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    a = take_event();
+    b = take_event();
+    if (a && b) (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof[name].pending.emplace_back(a, b);
+  }
+};
+
 int bits_for(uint64_t max_value) {  // bits to hold 0..max_value
   int b = 0;
   while (b < 64 && (max_value >> b) != 0) ++b;
@@ -455,6 +497,7 @@ ah_status ah_pack_genomes(const uint8_t* d_ascii, const uint64_t* d_ascii_off, u
   if (!d_ascii || !d_ascii_off || !d_word_off || !d_words || !d_len)
     return fail(AH_ERR_INVALID_ARG, "ah_pack_genomes: null device pointer");
   const int grid = cu_count() * 8;
+  ProfScope prof_pack("pack", (hipStream_t)stream);
   AH_HIP(ah::launch_pack(d_ascii, d_ascii_off, n, d_word_off, d_words, d_len, d_nmask, d_non_acgt,
                          grid, (hipStream_t)stream));
   return AH_OK;
@@ -506,9 +549,11 @@ ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint
     uint64_t* counter = &d_res->required;
     void* args[] = {&words, &nmask, &word_off, &len, &tp, &n, &out, &cap, &counter};
     const unsigned grid = (unsigned)cu_count() * 8u;
+    ProfScope prof_scan("scan", st);
     AH_HIP(hipModuleLaunchKernel(fn, grid, 1, 1, ah::kBlock, 1, 1, 0, st, args, nullptr));
   }
   AH_HIP(ah::launch_result_finalize(d_res, capacity, w.n_sort, st));
+  ProfScope prof_sort("sort", st);
   AH_HIP(ah::launch_sort_hits(w.staging, d_hits, w.n_sort, kb, w.sb, st));
   return AH_OK;
 }
@@ -581,6 +626,7 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
   void* dt = nullptr;
   s = get_table(tabs.data(), tabs.size() * sizeof(ah::PrimerTab), &dt);
   if (s) return s;
+  ProfScope prof_tm("tm", (hipStream_t)stream);
   AH_HIP(ah::launch_tm(*g, (const ah::PrimerTab*)dt, d_hits, d_nhits, capacity, cu_count() * 4,
                        (hipStream_t)stream));
   return AH_OK;
@@ -624,6 +670,7 @@ ah_status ah_pair_amplicons(const ah_hit* d_hits, const ah_result* d_nhits, uint
   if (s) return s;
   Carver c(d_work, work_bytes);
   ah::PairBuffers pb = carve_pair(c, hit_capacity);
+  ProfScope prof_pair("pair", (hipStream_t)stream);
   AH_HIP(ah::launch_pair(d_hits, d_nhits, hit_capacity, (const ah::PairTab*)dt, d_amp, capacity,
                          d_res, pb, cu_count() * 4, (hipStream_t)stream));
   return AH_OK;
@@ -657,6 +704,43 @@ ah_status ah_scan_program_compile(const ah_primer_pair* pairs, uint32_t n_pairs,
   }
   if (s) return s;
   if (code_bytes) *code_bytes = code.size();
+  return AH_OK;
+}
+
+void ah_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+}
+
+void ah_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& kv : g_prof) {
+    for (auto& ev : kv.second.pending) {
+      (void)hipEventSynchronize(ev.second);
+      g_event_pool.push_back(ev.first);
+      g_event_pool.push_back(ev.second);
+    }
+  }
+  g_prof.clear();
+}
+
+ah_status ah_profile_query(const char* name, uint64_t* launches, double* total_ms) {
+  g_err.clear();
+  if (!name) return fail(AH_ERR_INVALID_ARG, "profile name is NULL");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  ProfEntry& e = g_prof[name];
+  for (auto& ev : e.pending) {
+    AH_HIP(hipEventSynchronize(ev.second));
+    float ms = 0.f;
+    AH_HIP(hipEventElapsedTime(&ms, ev.first, ev.second));
+    e.ms += ms;
+    e.launches += 1;
+    g_event_pool.push_back(ev.first);
+    g_event_pool.push_back(ev.second);
+  }
+  e.pending.clear();
+  if (launches) *launches = e.launches;
+  if (total_ms) *total_ms = e.ms;
   return AH_OK;
 }
 

@@ -46,6 +46,7 @@ def mutated_copy(plan: Plan, copy_index: int) -> np.ndarray:
 
 
 def genome_bytes(plan: Plan, g: int) -> np.ndarray:
+    plan.check()
     n = int(plan.lengths[g])
     key = rng.stream_key(plan.seed, rng.S_BASES | plan.source_id(g))
     u = (rng.draws(key, np.arange(n)) >> np.uint64(32)).astype(np.uint32)

@@ -43,6 +43,7 @@ def fill_cuda(plan: Plan, device="cuda:0", stream=None):
     """Return (ascii uint8 tensor, offsets int64 tensor) on ``device``."""
     import torch
 
+    plan.check()  # every write below stays inside its genome
     lib = _lib()
     dev = torch.device(device)
     st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream)

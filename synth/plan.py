@@ -127,6 +127,36 @@ class Plan:
                        else self._copy_ids[keep])
         return p
 
+    def with_lengths(self, lengths) -> "Plan":
+        """Same plan with new genome lengths; copies and N runs that no longer
+        fit inside their genome are dropped."""
+        lengths = np.asarray(lengths, dtype=np.int64).copy()
+        tl = np.array([len(t) for t in self.templates], dtype=np.int64)
+        keep = self.plant_pos + tl[self.plant_template] <= lengths[self.plant_genome]
+        keepn = self.nrun_pos + self.nrun_len <= lengths[self.nrun_genome]
+        p = dataclasses.replace(
+            self, lengths=lengths,
+            plant_genome=self.plant_genome[keep], plant_pos=self.plant_pos[keep],
+            plant_strand=self.plant_strand[keep], plant_template=self.plant_template[keep],
+            nrun_genome=self.nrun_genome[keepn], nrun_pos=self.nrun_pos[keepn],
+            nrun_len=self.nrun_len[keepn])
+        if hasattr(self, "_source_ids"):
+            p._source_ids = self._source_ids
+        p._copy_ids = self.copy_ids()[keep]
+        return p
+
+    def check(self) -> None:
+        """Raise if a planted copy or N run does not lie inside its genome."""
+        tl = np.array([len(t) for t in self.templates], dtype=np.int64)
+        if self.plant_genome.size:
+            end = self.plant_pos + tl[self.plant_template]
+            if np.any(self.plant_pos < 0) or np.any(end > self.lengths[self.plant_genome]):
+                raise ValueError("a planted copy lies outside its genome")
+        if self.nrun_genome.size:
+            end = self.nrun_pos + self.nrun_len
+            if np.any(self.nrun_pos < 0) or np.any(end > self.lengths[self.nrun_genome]):
+                raise ValueError("an N run lies outside its genome")
+
     # Identity of genome g / copy c for the per-base draw streams.
     def source_id(self, g: int) -> int:
         return int(self._source_ids[g]) if hasattr(self, "_source_ids") else int(g)

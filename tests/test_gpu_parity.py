@@ -84,7 +84,7 @@ def test_pack_layout_roundtrip(dev):
     from paper_2509_13300_amd import path
 
     p = plan.tiny(9, n_genomes=7, len_lo=1, len_hi=3000, nruns=6)
-    p.lengths[:4] = [1, 31, 32, 33]
+    p = p.with_lengths([1, 31, 32, 33] + p.lengths[4:].tolist())
     ascii, off = gpu.fill_cuda(p, dev)
     coll, nonacgt = path.pack(ascii, off, p.lengths, with_nmask=True)
     dec = decode(coll, p)
@@ -105,9 +105,7 @@ def test_scan_edge_lengths(dev, k):
     pr = plan.PairSpec("ACGTRYACGTAC", "TTGCANNGCA", k=k, clamp=k % 3, min_len=20, max_len=400)
     p = plan.tiny(300 + k, n_genomes=len(EDGE_LENGTHS), pair=pr, n_copies=(0, 2),
                   gc_lo=0.45, gc_hi=0.55)
-    p.lengths[:] = EDGE_LENGTHS
-    for f in ("plant_genome", "plant_pos", "plant_strand", "plant_template"):
-        setattr(p, f, getattr(p, f)[:0])
+    p = p.with_lengths(EDGE_LENGTHS)
     say("edge lengths k", k)
     check_case(p, [pr], dev)
 
