@@ -60,7 +60,8 @@ enum { AH_FR = 0, AH_RF = 1, AH_FF = 2, AH_RR = 3 };
  * Packed genome collection (Section 1 / 2.1: genomes are the FASTA input).
  *
  * Layout of genome g with n bases: S = ceil(n / 32) segment words plus
- * AH_HALO_WORDS halo words, starting at word word_off[g].  Word t is a pair of
+ * AH_HALO_WORDS halo words, rounded up to an even number of words so that
+ * every genome starts 16-byte aligned, starting at word word_off[g].  Word t is a pair of
  * uint32 (h, l) stored consecutively in `words`; bit b of word t holds the
  * base at position b*S + t as the 2-bit code A=00, C=01, G=10, T=11 (h the
  * high bit, l the low bit; the complement of a base is the bitwise NOT of

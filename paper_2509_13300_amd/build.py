@@ -31,16 +31,29 @@ SAMPLE_PROGRAM = r"""
 #define AH_HAS_N 1
 """
 SAMPLE_TAIL = r"""
-__device__ __forceinline__ void ah_pat_0(const u32* h, const u32* l, const u32* nm, const AhCtx& c, u32 t) {
+__device__ __forceinline__ void ah_pat_0(const u32* h, const u32* l, const AhCtx& c, u32 t) {
+  u32 cl = 0u;
+  cl |= (~h[19] | l[19]);
+  const u32 a0 = (h[0] | l[0]);
+  const u32 a1 = l[1];
+  u32 c1 = ~a0;
+  c1 |= ~a1;
+  u32 cand = c1 & ~cl;
+  if (!cand) return;
+  cand &= ah_valid(c, t, 20u);
+  if (!cand) return;
+  u32 nm[20];
+#pragma unroll
+  for (int j = 0; j < 20; ++j) nm[j] = c.gn[t + j];
   u32 x, cf = 0u; u32 s0 = 0u; u32 s1 = 0u; u32 s2 = 0u;
   x = ((h[0] | l[0]) | nm[0]); s2 |= s1 & x; s1 |= s0 & x; s0 |= x;
   x = (l[1] | nm[1]); s2 |= s1 & x; s1 |= s0 & x; s0 |= x;
   x = ((~h[19] | l[19]) | nm[19]); cf |= x;
-  const u32 hb = ~(s2 | cf) & ah_valid(c, t, 20u);
+  const u32 hb = cand & ~(s2 | cf);
   if (hb) { const u32 lv[2] = {s0, s1}; ah_emit<2>(c, t, hb, lv, 0u, 0u); }
 }
-__device__ void ah_patterns(const u32* h, const u32* l, const u32* nm, const AhCtx& c, u32 t) {
-  ah_pat_0(h, l, nm, c, t);
+__device__ void ah_patterns(const u32* h, const u32* l, const AhCtx& c, u32 t) {
+  ah_pat_0(h, l, c, t);
 }
 """
 

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -181,42 +183,229 @@ std::string mism_expr(uint8_t m, int j) {
   }
 }
 
-constexpr int kU = ah::kScanU;
+// Window words per lane and tile of the scan kernel (AH_SCAN_U = 2, 4, 8 or
+// 16; default 4): the tile of AH_BLOCK * U words plus the halo is staged in
+// LDS twice (double buffer), so larger tiles amortise the halo and the
+// per-tile set-up but leave room for fewer workgroups per CU.
+int scan_u() {
+  const char* e = getenv("AH_SCAN_U");
+  const int u = e ? atoi(e) : ah::kScanU;
+  return (u == 2 || u == 4 || u == 8 || u == 16) ? u : ah::kScanU;
+}
+
+// ---- v_bitop3_b32 truth tables.  The table of f over operands (S0, S1, S2)
+// is f evaluated bitwise on the 8-bit vectors S0 = 0xF0, S1 = 0xCC,
+// S2 = 0xAA (bit i of the table is f at S0 = i>>2 & 1, S1 = i>>1 & 1,
+// S2 = i & 1).
+constexpr uint8_t kS0 = 0xF0, kS1 = 0xCC, kS2 = 0xAA;
+
+// Mismatch indicator of IUPAC set m, bitwise over the code planes (h, l):
+// A = 00, C = 01, G = 10, T = 11.
+uint8_t tt_mism(uint8_t m, uint8_t H, uint8_t L) {
+  unsigned r = 0;
+  if (!(m & 1)) r |= ~H & ~L;
+  if (!(m & 2)) r |= ~H & L;
+  if (!(m & 4)) r |= H & ~L;
+  if (!(m & 8)) r |= H & L;
+  return (uint8_t)r;
+}
+
+std::string bitop3(const std::string& a, const std::string& b, const std::string& c, uint8_t tt) {
+  char t[16];
+  snprintf(t, sizeof t, "0x%02x", tt);
+  return "__builtin_amdgcn_bitop3_b32(" + a + ", " + b + ", " + c + ", " + t + ")";
+}
+
+std::string hj(int j) { return "h[" + std::to_string(j) + "]"; }
+std::string lj(int j) { return "l[" + std::to_string(j) + "]"; }
+
+// x = mismatch of position j (one op)
+std::string mism_op(uint8_t m, int j) { return bitop3(hj(j), lj(j), hj(j), tt_mism(m, kS0, kS1)); }
+// acc | mismatch of position j (one op)
+std::string acc_mism_op(const std::string& acc, uint8_t m, int j) {
+  return bitop3(acc, hj(j), lj(j), (uint8_t)(kS0 | tt_mism(m, kS1, kS2)));
+}
+
+// Prefilter of one pattern (pigeonhole): the non-clamp positions whose set is
+// not N are split into `blocks`; a window with at most k mismatches there
+// leaves at least `need` blocks without a mismatch (k + need blocks, each
+// holding at least one position).  need == 0: no prefilter.
+struct FilterPlan {
+  int need = 0;
+  std::vector<std::vector<int>> blocks;
+  double rate = 1.0;  // chance a random window passes (uniform bases)
+};
+
+int set_size(uint8_t m) { return __builtin_popcount(m); }
+
+// P(at least `need` of the independent events with probabilities p occur)
+double at_least(const std::vector<double>& p, int need) {
+  std::vector<double> d(p.size() + 1, 0.0);  // d[c] = P(exactly c so far)
+  d[0] = 1.0;
+  for (size_t i = 0; i < p.size(); ++i)
+    for (size_t c = i + 1; c-- > 0;) {
+      const double stay = d[c] * (1.0 - p[i]);
+      const double up = c ? d[c - 1] * p[i] : 0.0;
+      d[c] = stay + up;
+    }
+  double r = 0.0;
+  for (size_t c = (size_t)need; c < d.size(); ++c) r += d[c];
+  return r;
+}
+
+FilterPlan plan_filter(const Pattern& p, bool allow) {
+  std::vector<int> free_pos;
+  double clamp_p = 1.0;
+  int clamp_ops = 0, verify_ops = 0;
+  for (int j = 0; j < p.L; ++j) {
+    if (set_size(p.mask[j]) == 4) continue;
+    verify_ops += (p.clamp_bits >> j & 1u) ? 2 : (int)p.k + 2;
+    if (p.clamp_bits >> j & 1u) {
+      clamp_p *= set_size(p.mask[j]) / 4.0;
+      ++clamp_ops;
+    } else {
+      free_pos.push_back(j);
+    }
+  }
+  FilterPlan best;
+  best.rate = clamp_p;
+  // cost per window word of this pattern, in lane operations: prefilter ops
+  // plus the exact count whenever any lane of the wave has a candidate
+  auto slot = [](double r) { return 1.0 - std::pow(1.0 - std::min(r, 1.0), 32.0 * 64.0); };
+  double best_cost = clamp_ops + slot(clamp_p) * verify_ops;
+  if (!allow) return best;
+  for (int need = 1; need <= 3; ++need) {
+    const int B = (int)p.k + need;
+    if ((int)free_pos.size() < B) break;
+    // balance information content over the blocks (largest first)
+    std::vector<int> order = free_pos;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return set_size(p.mask[a]) < set_size(p.mask[b]);
+    });
+    std::vector<std::vector<int>> blocks(B);
+    std::vector<double> bits(B, 0.0);
+    for (int j : order) {
+      int at = 0;
+      for (int b = 1; b < B; ++b)
+        if (blocks[b].size() < blocks[at].size() ? bits[b] <= bits[at] : bits[b] < bits[at]) at = b;
+      // every block needs a position: fill empty ones first
+      for (int b = 0; b < B; ++b)
+        if (blocks[b].empty()) { at = b; break; }
+      blocks[at].push_back(j);
+      bits[at] += std::log2(4.0 / set_size(p.mask[j]));
+    }
+    std::vector<double> clean(B);
+    for (int b = 0; b < B; ++b) clean[b] = std::exp2(-bits[b]);
+    const double rate = clamp_p * at_least(clean, need);
+    const double cost = clamp_ops + (double)free_pos.size() + 2.0 * need * B + slot(rate) * verify_ops;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best.need = need;
+      best.blocks = blocks;
+      best.rate = rate;
+    }
+  }
+  return best;
+}
+
+bool filter_enabled() {
+  const char* e = getenv("AH_SCAN_PREFILTER");
+  return !(e && e[0] == '0');
+}
 
 std::string gen_program(const std::vector<Pattern>& pats, bool has_n) {
   int lmax = 0;
   for (const Pattern& p : pats) lmax = p.L > lmax ? p.L : lmax;
+  const bool allow = filter_enabled();
   std::string s;
-  char buf[512];
-  snprintf(buf, sizeof buf, "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n", kU,
-           lmax - 1, has_n ? 1 : 0);
+  char buf[640];
+  snprintf(buf, sizeof buf,
+           "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n", scan_u(), lmax - 1,
+           has_n ? 1 : 0);
   std::string head = buf;
   for (size_t i = 0; i < pats.size(); ++i) {
     const Pattern& p = pats[i];
     const int K = (int)p.k;
+    const FilterPlan fp = plan_filter(p, allow);
+    // ---- prefilter (hot): clamp positions must match, `need` blocks be clean
     snprintf(buf, sizeof buf,
-             "__device__ __forceinline__ void ah_pat_%zu(const u32* h, const u32* l, const u32* nm,"
-             " const AhCtx& c, u32 t) {\n  u32 x, cf = 0u;\n",
-             i);
+             "// pattern %zu: pair %u primer %u strand %u, L %d, k %d, prefilter: %d of %zu blocks "
+             "(random pass rate %.3g)\n"
+             "__device__ __forceinline__ void ah_pat_%zu(const u32* h, const u32* l, const AhCtx& c,"
+             " u32 t) {\n",
+             i, p.pair, p.primer, p.strand, p.L, K, fp.need, fp.blocks.size(), fp.rate, i);
     s += buf;
+    // clamp mismatches
+    std::string cl;
+    for (int j = 0; j < p.L; ++j) {
+      if (!(p.clamp_bits >> j & 1u) || set_size(p.mask[j]) == 4) continue;
+      if (cl.empty()) {
+        s += "  u32 cl = " + mism_op(p.mask[j], j) + ";\n";
+        cl = "cl";
+      } else {
+        s += "  cl = " + acc_mism_op("cl", p.mask[j], j) + ";\n";
+      }
+    }
+    std::string cand_expr;
+    if (fp.need > 0) {
+      // a_b: some position of block b mismatches ("dirty")
+      for (size_t b = 0; b < fp.blocks.size(); ++b) {
+        const std::string ab = "a" + std::to_string(b);
+        for (size_t q = 0; q < fp.blocks[b].size(); ++q) {
+          const int j = fp.blocks[b][q];
+          if (q == 0) s += "  u32 " + ab + " = " + mism_op(p.mask[j], j) + ";\n";
+          else s += "  " + ab + " = " + acc_mism_op(ab, p.mask[j], j) + ";\n";
+        }
+      }
+      // z_m: at most m blocks clean so far; a window is a candidate iff
+      // z_{need-1} is clear after the last block (and the clamp matches)
+      const int B = (int)fp.blocks.size();
+      const int need = fp.need;
+      s += "  u32 z0 = a0;\n";
+      for (int m = 1; m < need; ++m) s += "  u32 z" + std::to_string(m) + " = 0xffffffffu;\n";
+      for (int b = 1; b < B; ++b) {
+        const std::string ab = "a" + std::to_string(b);
+        for (int m = need - 1; m >= 1; --m) {
+          // z_m' = (z_m & a_b) | z_{m-1}
+          const std::string zm = "z" + std::to_string(m), zp = "z" + std::to_string(m - 1);
+          s += "  " + zm + " = " + bitop3(zm, ab, zp, (uint8_t)((kS0 & kS1) | kS2)) + ";\n";
+        }
+        if (b < B - 1 || need == 1) s += "  z0 &= " + ab + ";\n";
+      }
+      const std::string zl = "z" + std::to_string(need - 1);
+      cand_expr = cl.empty() ? "~" + zl : bitop3(zl, "cl", zl, (uint8_t)(~(kS0 | kS1)));
+    } else {
+      cand_expr = cl.empty() ? "0xffffffffu" : "~cl";
+    }
+    s += "  u32 cand = " + cand_expr + ";\n  if (!cand) return;\n";
+    // ---- exact count for candidate windows (rare), from the same registers
+    snprintf(buf, sizeof buf, "  cand &= ah_valid(c, t, %du);\n  if (!cand) return;\n", p.L);
+    s += buf;
+    if (has_n) {
+      snprintf(buf, sizeof buf,
+               "  u32 nm[%d];\n#pragma unroll\n  for (int j = 0; j < %d; ++j) nm[j] = c.gn[t + j];\n",
+               p.L, p.L);
+      s += buf;
+    }
+    s += "  u32 x, cf = 0u;\n";
     for (int m = 0; m <= K; ++m) s += "  u32 s" + std::to_string(m) + " = 0u;\n";
     for (int j = 0; j < p.L; ++j) {
-      std::string e = mism_expr(p.mask[j], j);
-      if (has_n) {
-        std::string nmj = "nm[" + std::to_string(j) + "]";
-        e = e.empty() ? nmj : "(" + e + " | " + nmj + ")";
-      }
-      if (e.empty()) continue;
+      const bool isN = set_size(p.mask[j]) == 4;
+      if (isN && !has_n) continue;
+      std::string e = isN ? std::string("0u") : mism_op(p.mask[j], j);
+      if (has_n) e = isN ? "nm[" + std::to_string(j) + "]" : "(" + e + " | nm[" + std::to_string(j) + "])";
       s += "  x = " + e + ";";
       if (p.clamp_bits >> j & 1u) {
         s += " cf |= x;\n";  // a clamp mismatch rejects the window outright
         continue;
       }
-      for (int m = K; m >= 1; --m)
-        s += " s" + std::to_string(m) + " |= s" + std::to_string(m - 1) + " & x;";
+      for (int m = K; m >= 1; --m) {
+        const std::string sm = "s" + std::to_string(m), sp = "s" + std::to_string(m - 1);
+        s += " " + sm + " = " + bitop3(sm, sp, "x", (uint8_t)(kS0 | (kS1 & kS2))) + ";";
+      }
       s += " s0 |= x;\n";
     }
-    snprintf(buf, sizeof buf, "  const u32 hb = ~(s%d | cf) & ah_valid(c, t, %du);\n", K, p.L);
+    snprintf(buf, sizeof buf, "  const u32 hb = cand & ~(s%d | cf);\n", K);
     s += buf;
     if (K == 0) {
       snprintf(buf, sizeof buf,
@@ -231,8 +420,8 @@ std::string gen_program(const std::vector<Pattern>& pats, bool has_n) {
     }
     s += buf;
   }
-  s += "__device__ void ah_patterns(const u32* h, const u32* l, const u32* nm, const AhCtx& c, u32 t) {\n";
-  for (size_t i = 0; i < pats.size(); ++i) s += "  ah_pat_" + std::to_string(i) + "(h, l, nm, c, t);\n";
+  s += "__device__ void ah_patterns(const u32* h, const u32* l, const AhCtx& c, u32 t) {\n";
+  for (size_t i = 0; i < pats.size(); ++i) s += "  ah_pat_" + std::to_string(i) + "(h, l, c, t);\n";
   s += "}\n";
   return head + std::string(kScanCore) + s;
 }
@@ -483,7 +672,7 @@ uint64_t ah_pack_layout(const uint64_t* h_len, uint32_t n, uint64_t* h_word_off)
   if (h_word_off) h_word_off[0] = 0;
   for (uint32_t g = 0; g < n; ++g) {
     const uint64_t S = h_len ? (h_len[g] + 31) / 32 : 0;
-    off += S + AH_HALO_WORDS;
+    off += (S + AH_HALO_WORDS + 1) & ~(uint64_t)1;  // even: every genome 16-byte aligned
     if (h_word_off) h_word_off[g + 1] = off;
   }
   return off;
@@ -536,7 +725,7 @@ ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint
   ScanWs w = carve_scan(c, g->n, capacity);
   AH_HIP(ah::launch_result_init(d_res, st));
   if (g->n > 0) {
-    AH_HIP(ah::launch_tile_counts(g->len, g->n, w.counts, st));
+    AH_HIP(ah::launch_tile_counts(g->len, g->n, (uint32_t)(ah::kBlock * scan_u()), w.counts, st));
     AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
     const void* words = g->words;
     const uint32_t* nmask = g->nmask;

@@ -12,8 +12,7 @@ namespace ah {
 constexpr int kBlock = 256;        // threads per workgroup for every kernel
 constexpr int kSortGrid = 256;     // workgroups of the radix-sort passes
 constexpr int kScanGrid = 256;     // workgroups of the generic prefix scan
-constexpr int kScanU = 8;          // packed words per lane in the scan kernel
-constexpr int kTileWords = kBlock * kScanU;
+constexpr int kScanU = 4;          // default window words per lane per tile in the scan kernel
 
 // Per-primer table used by the Tm kernel (one per pair and primer).  Oligos
 // are 2-bit codes (A=0 C=1 G=2 T=3), position j of the primer (5'->3') at
@@ -51,7 +50,8 @@ hipError_t launch_pack(const uint8_t* ascii, const uint64_t* ascii_off, uint32_t
                        uint32_t* nmask, uint64_t* non_acgt, int grid, hipStream_t st);
 hipError_t launch_result_init(ah_result* res, hipStream_t st);
 hipError_t launch_result_finalize(ah_result* res, uint64_t cap, uint64_t* n_out, hipStream_t st);
-hipError_t launch_tile_counts(const uint32_t* len, uint32_t n, uint64_t* counts, hipStream_t st);
+hipError_t launch_tile_counts(const uint32_t* len, uint32_t n, uint32_t tile_words, uint64_t* counts,
+                              hipStream_t st);
 // Exclusive prefix sum of in[0..n) into out[0..n]; out[n] = total.  n is
 // n_host when n_dev is null, else *n_dev (device).  tmp: kScanGrid + 1 u64.
 hipError_t launch_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n_host,

@@ -107,10 +107,11 @@ __global__ void k_result_finalize(ah_result* r, u64 cap, u64* n_out) {
   }
 }
 
-__global__ void k_tile_counts(const u32* __restrict__ len, u32 n, u64* __restrict__ counts) {
+__global__ void k_tile_counts(const u32* __restrict__ len, u32 n, u32 tile_words,
+                              u64* __restrict__ counts) {
   for (u64 i = global_tid(); i < n; i += grid_threads()) {
     const u64 S = ((u64)len[i] + 31) >> 5;
-    counts[i] = (S + kTileWords - 1) / kTileWords;
+    counts[i] = (S + tile_words - 1) / tile_words;
   }
 }
 
@@ -584,9 +585,10 @@ hipError_t launch_result_finalize(ah_result* res, uint64_t cap, uint64_t* n_out,
   return hipGetLastError();
 }
 
-hipError_t launch_tile_counts(const uint32_t* len, uint32_t n, uint64_t* counts, hipStream_t st) {
+hipError_t launch_tile_counts(const uint32_t* len, uint32_t n, uint32_t tile_words, uint64_t* counts,
+                              hipStream_t st) {
   const int grid = (int)((n + kBlock - 1) / kBlock) > 0 ? (int)((n + kBlock - 1) / kBlock) : 1;
-  k_tile_counts<<<grid < 4096 ? grid : 4096, kBlock, 0, st>>>(len, n, (u64*)counts);
+  k_tile_counts<<<grid < 4096 ? grid : 4096, kBlock, 0, st>>>(len, n, tile_words, (u64*)counts);
   return hipGetLastError();
 }
 

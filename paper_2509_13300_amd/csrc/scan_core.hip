@@ -11,8 +11,9 @@
 // Packed layout (see ah.h): bit b of word t of a genome holds the base at
 // b*S + t, so the window starting at b*S + t reads word t + j at bit b for
 // primer position j: 32 windows advance together with no shifts.  A lane
-// owns AH_U consecutive window words and keeps AH_U + AH_HALO words in
-// registers.
+// block stages a tile of AH_TILE window words plus the halo in LDS (double
+// buffered: the next tile's loads are in flight while this one is scanned);
+// each lane reads the AH_HALO + 1 words of one window word at a time.
 //
 // Macros supplied by the generated program: AH_U (window words per lane),
 // AH_HALO (longest primer - 1), AH_HAS_N (1 if the collection has non-ACGT
@@ -40,14 +41,19 @@ struct AhCtx {
   AhHitRec* out;
   u64 cap;
   u64* counter;
-  u32 g;  // genome
-  u32 n;  // bases
-  u32 S;  // segment words
+  const uint2* gw;  // this genome's first packed word
+  const u32* gn;    // this genome's first non-ACGT mask word (or null)
+  u32 g;            // genome
+  u32 n;            // bases
+  u32 S;            // segment words
+  int tail;         // n - 31*S: a window of length L at word t is valid in
+                    // every segment iff t + L <= tail
 };
 
 // Window starts b*S + t (b = 0..31) that lie inside the genome for a primer
 // of length L, as a bit mask over b.
 __device__ __forceinline__ u32 ah_valid(const AhCtx& c, u32 t, u32 L) {
+  if ((long long)t + (long long)L <= (long long)c.tail) return 0xffffffffu;
   const long long d = (long long)c.n - (long long)L - (long long)t;
   if (d < 0) return 0u;
   if (d >= 31ll * (long long)c.S) return 0xffffffffu;
@@ -81,45 +87,113 @@ __device__ __forceinline__ void ah_emit(const AhCtx& c, u32 t, u32 hb, const u32
   }
 }
 
-// Generated: evaluates every pattern of the primer set on one window word.
-__device__ void ah_patterns(const u32* h, const u32* l, const u32* nm, const AhCtx& c, u32 t);
+// Genome context of tile T (g from a binary search over the tile prefix,
+// starting from the previous tile's genome when it still applies).
+__device__ __forceinline__ AhCtx ah_tile_ctx(const u64* __restrict__ tile_prefix, u32 n_genomes,
+                                             const uint2* words, const u32* nmask,
+                                             const u64* __restrict__ word_off,
+                                             const u32* __restrict__ len, u64 T, u32& lo,
+                                             AhHitRec* out, u64 cap, u64* counter, u32& t0) {
+  u32 hi = n_genomes;
+  if (tile_prefix[lo] > T) lo = 0;
+  while (hi - lo > 1) {
+    const u32 mid = (lo + hi) >> 1;
+    if (tile_prefix[mid] <= T) lo = mid; else hi = mid;
+  }
+  AhCtx c;
+  c.out = out;
+  c.cap = cap;
+  c.counter = counter;
+  c.g = lo;
+  c.n = len[lo];
+  c.S = (c.n + 31u) >> 5;
+  c.tail = (int)((long long)c.n - 31ll * (long long)c.S);
+  const u64 wbase = word_off[lo];
+  c.gw = words + wbase;
+  c.gn = AH_HAS_N ? nmask + wbase : nullptr;
+  t0 = (u32)(T - tile_prefix[lo]) * (u32)AH_TILE;
+  return c;
+}
+
+// Generated: prefilters every pattern on one window word (words h[0..],
+// l[0..] in registers) and runs the exact count where a lane has a
+// candidate window.
+__device__ void ah_patterns(const u32* h, const u32* l, const AhCtx& c, u32 t);
+
+// Words staged per tile: the tile's window words plus the halo, in 16-byte
+// pairs (every genome starts 16-byte aligned).
+#define AH_STAGE_PAIRS ((AH_TILE + AH_HALO + 1) / 2)
+#define AH_STAGE_PER_THREAD ((AH_STAGE_PAIRS + AH_BLOCK - 1) / AH_BLOCK)
+
+typedef __attribute__((address_space(3))) void ah_lds_void;
+typedef __attribute__((address_space(1))) void ah_global_void;
+
+// Copy this wave's share of a tile straight from HBM into LDS (no registers):
+// each lane moves 16 bytes; the LDS base is uniform over the wave and the
+// hardware places lane i at base + 16 i.
+__device__ __forceinline__ void ah_stage(const AhCtx& c, u32 t0, uint4* tw) {
+  const u32 last_pair = ((c.S + 31u + 1u) >> 1) - 1u;
+  const uint4* gp = (const uint4*)c.gw;
+  const u32 wave_base = threadIdx.x & ~63u;
+#pragma unroll
+  for (int k = 0; k < AH_STAGE_PER_THREAD; ++k) {
+    const u32 i = threadIdx.x + (u32)k * AH_BLOCK;
+    if (i < AH_STAGE_PAIRS) {
+      // a clamped index only ever replaces words that no valid window reads
+      const uint4* src = gp + min((t0 >> 1) + i, last_pair);
+      __builtin_amdgcn_global_load_lds((ah_global_void*)src,
+                                       (ah_lds_void*)(tw + wave_base + (u32)k * AH_BLOCK), 16, 0, 0);
+    }
+  }
+}
 
 extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     const uint2* __restrict__ words, const u32* __restrict__ nmask,
     const u64* __restrict__ word_off, const u32* __restrict__ len,
     const u64* __restrict__ tile_prefix, u32 n_genomes, AhHitRec* __restrict__ out, u64 cap,
     u64* __restrict__ counter) {
+  __shared__ uint4 tiles[2][AH_STAGE_PAIRS];
   const u64 n_tiles = tile_prefix[n_genomes];
-  for (u64 T = blockIdx.x; T < n_tiles; T += gridDim.x) {
-    u32 lo = 0, hi = n_genomes;
-    while (hi - lo > 1) {
-      const u32 mid = (lo + hi) >> 1;
-      if (tile_prefix[mid] <= T) lo = mid; else hi = mid;
+  u64 T = blockIdx.x;
+  if (T >= n_tiles) return;
+  u32 lo = 0, t0;
+  AhCtx c = ah_tile_ctx(tile_prefix, n_genomes, words, nmask, word_off, len, T, lo, out, cap,
+                        counter, t0);
+  ah_stage(c, t0, tiles[0]);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int buf = 0;
+  for (;;) {
+    // the next tile streams into the other buffer while this one is scanned
+    const u64 Tn = T + gridDim.x;
+    u32 lon = lo, t0n = 0;
+    AhCtx cn = c;
+    if (Tn < n_tiles) {
+      cn = ah_tile_ctx(tile_prefix, n_genomes, words, nmask, word_off, len, Tn, lon, out, cap,
+                       counter, t0n);
+      ah_stage(cn, t0n, tiles[buf ^ 1]);
     }
-    AhCtx c;
-    c.out = out;
-    c.cap = cap;
-    c.counter = counter;
-    c.g = lo;
-    c.n = len[lo];
-    c.S = (c.n + 31u) >> 5;
-    const u64 wbase = word_off[lo];
-    const u32 nw = c.S + 31u;
-    const u32 t0 = (u32)(T - tile_prefix[lo]) * (u32)AH_TILE + threadIdx.x * (u32)AH_U;
-    if (t0 >= c.S) continue;
-    u32 h[AH_U + AH_HALO], l[AH_U + AH_HALO], nm[AH_U + AH_HALO];
+    const uint2* tw = (const uint2*)tiles[buf];
+    for (u32 i = threadIdx.x; i < (u32)AH_TILE; i += AH_BLOCK) {
+      const u32 t = t0 + i;
+      if (t >= c.S) break;
+      u32 h[AH_HALO + 1], l[AH_HALO + 1];
 #pragma unroll
-    for (int i = 0; i < AH_U + AH_HALO; ++i) {
-      const u32 wi = t0 + (u32)i;
-      uint2 v = make_uint2(0u, 0u);
-      if (wi < nw) v = words[wbase + wi];
-      h[i] = v.x;
-      l[i] = v.y;
-      nm[i] = (AH_HAS_N && wi < nw) ? nmask[wbase + wi] : 0u;
+      for (int j = 0; j <= AH_HALO; ++j) {
+        const uint2 v = tw[i + (u32)j];
+        h[j] = v.x;
+        l[j] = v.y;
+      }
+      ah_patterns(h, l, c, t);
     }
-#pragma unroll
-    for (int u = 0; u < AH_U; ++u)
-      if (t0 + (u32)u < c.S) ah_patterns(h + u, l + u, nm + u, c, t0 + (u32)u);
+    if (Tn >= n_tiles) break;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+    __syncthreads();                // and everyone's; nobody still reads `buf`
+    buf ^= 1;
+    T = Tn;
+    lo = lon;
+    t0 = t0n;
+    c = cn;
   }
 }
 

@@ -61,7 +61,7 @@ def decode(coll, p):
         n = int(p.lengths[g])
         S = (n + 31) // 32
         w = words[off[g]:off[g + 1]]
-        assert w.shape[0] == S + 31
+        assert w.shape[0] == (S + 32) // 2 * 2 and w.shape[0] >= S + 31
         b = np.arange(32)
         seq = np.zeros(n, dtype=np.uint8)
         isn = np.zeros(n, dtype=bool)
@@ -213,3 +213,74 @@ def test_plain_workload_full_parity(dev):
     say("plain", pr)
     gh, ga = check_case(p, [pr], dev)
     assert ga.size >= 1 and gh.size >= 4
+
+
+def _host_collection(seqs, dev):
+    import torch
+
+    from paper_2509_13300_amd import path
+
+    lens = np.array([len(s) for s in seqs], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    buf = np.frombuffer(b"".join(s.encode() for s in seqs), dtype=np.uint8)
+    ascii = torch.from_numpy(buf.copy()).to(dev)
+    coll, _ = path.pack(ascii, torch.from_numpy(off).to(dev), lens, with_nmask=True)
+    return coll
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+def test_windows_with_exactly_k_mismatches_are_all_found(dev, k):
+    """Plant many windows with exactly k (found) and k + 1 (not found)
+    mismatches at random positions, on both strands: a pigeonhole prefilter
+    that dropped a true site would show here."""
+    from oracle import iupac
+    from oracle import scan as oscan
+    from paper_2509_13300_amd import path
+
+    rs = np.random.RandomState(1000 + k)
+    fwd = plan.random_primer(2000 + k, 0, 22, "RYN")
+    rev = plan.random_primer(2000 + k, 1, 20, "SWK")
+    pr = plan.PairSpec(fwd, rev, k=k, clamp=0, min_len=40, max_len=400)
+    seqs, planted = [], []
+    for g in range(6):
+        n = 40000
+        s = list(rs.choice(list("ACGT"), size=n))
+        for q in range(300):
+            prim = fwd if q % 2 == 0 else rev
+            o = list(iupac.expand(prim)[rs.randint(iupac.degeneracy(prim))])
+            m = k + (q % 3 == 2)  # every third site has one mismatch too many
+            non_n = [j for j in range(len(o)) if prim[j] != "N"]
+            for j in rs.choice(non_n, size=m, replace=False):
+                o[j] = rs.choice([b for b in "ACGT" if iupac.mask(prim[j]) >> "ACGT".index(b) & 1 == 0])
+            o = "".join(o)
+            strand = int(rs.randint(2))
+            if strand:
+                o = iupac.revcomp_plain(o)
+            pos = q * (n // 300) + int(rs.randint(0, n // 300 - len(o)))
+            s[pos:pos + len(o)] = list(o)
+            planted.append((g, pos, strand, q % 2, m))
+        seqs.append("".join(s))
+    coll = _host_collection(seqs, dev)
+    buf = path.alloc(coll, 1, 1 << 18, 1 << 18, dev)
+    path.run(coll, [pr], buf)
+    import torch
+
+    torch.cuda.synchronize()
+    got = {(int(h["genome"]), int(h["pos"]), int(h["strand_primer"]) >> 1,
+            int(h["strand_primer"]) & 1): int(h["mm"]) for h in path.hits_numpy(buf)}
+    found = missed_ok = 0
+    for g, pos, strand, primer, m in planted:
+        key = (g, pos, strand, primer)
+        if m <= k:
+            assert got.get(key) == m, (key, m, got.get(key))
+            found += 1
+        else:
+            missed_ok += key not in got
+    assert found > 1000 and missed_ok > 400
+    want = []
+    for g, s in enumerate(seqs):
+        h = oscan.scan_sequence(s, fwd, rev, k, 0)
+        want += [(g, int(r["pos"]), int(r["strand"]), int(r["primer"]), int(r["mm"])) for r in h]
+    gotl = [(int(h["genome"]), int(h["pos"]), int(h["strand_primer"]) >> 1,
+             int(h["strand_primer"]) & 1, int(h["mm"])) for h in path.hits_numpy(buf)]
+    assert gotl == want

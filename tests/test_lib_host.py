@@ -43,7 +43,7 @@ def test_pack_layout():
     lens = np.array([0, 1, 31, 32, 33, 5_000_000], dtype=np.uint64)
     off = L.ah_pack_layout(lens)
     S = (lens + 31) // 32
-    want = np.concatenate([[0], np.cumsum(S + 31)])
+    want = np.concatenate([[0], np.cumsum((S + 32) // 2 * 2)])
     assert off.tolist() == want.tolist()
 
 
@@ -68,9 +68,36 @@ def test_primer_validation(fwd, rev, k, clamp, status):
 def test_generated_program_tests_every_non_n_position():
     src = L.ah_scan_program_source([("ACGTNRYSWKMBDHV", "NNNNNAAAAC", 1, 2)])
     body = src.split("---- generated pattern program follows ----")[1]
-    pat0 = body.split("ah_pat_1")[0]
-    assert pat0.count("x = ") == 15 - 1  # the N position is never a mismatch
-    assert "cf |= x" in pat0 and "ah_valid(c, t, 15u)" in pat0
+    pat0 = body.split("void ah_pat_0")[1].split("void ah_pat_1")[0]
+    pre, exact0 = pat0.split("ah_valid(c, t, ")
+    assert exact0.startswith("15u)")
+    assert exact0.count("x = ") == 15 - 1  # the N position is never a mismatch
+    assert exact0.count("cf |= x") == 2
+    # a degenerate, low-information primer gets no block prefilter: only the
+    # two clamp positions (13, 14) are tested before the exact count
+    assert set(int(m) for m in re.findall(r"h\[(\d+)\]", pre)) == {13, 14}
+    assert "u32 a0" not in pre
+    # a specific primer: every non-N, non-clamp position lands in some block
+    src = L.ah_scan_program_source([("ACGTACCGATNGCATTGGCAKT", "GGATCCAAGTTCGACGT", 2, 3)])
+    body = src.split("---- generated pattern program follows ----")[1]
+    pat0 = body.split("void ah_pat_0")[1].split("void ah_pat_1")[0]
+    pre = pat0.split("ah_valid(c, t, ")[0]
+    clamp = {int(m) for ln in pre.splitlines() if ln.strip().startswith(("u32 cl", "cl ="))
+             for m in re.findall(r"h\[(\d+)\]", ln)}
+    assert clamp == {19, 20, 21}
+    positions = {int(m) for ln in pre.splitlines() if ln.strip().startswith(("u32 a", "a"))
+                 for m in re.findall(r"h\[(\d+)\]", ln)}
+    assert positions == set(range(19)) - {10}
+    assert "if (!cand) return;" in pat0
+
+
+def test_prefilter_can_be_switched_off(monkeypatch):
+    monkeypatch.setenv("AH_SCAN_PREFILTER", "0")
+    src = L.ah_scan_program_source([("ACGTACGTACGTAC", "GGTTCCAAGGTTC", 2, 0)])
+    assert "prefilter: 0 of 0 blocks" in src
+    monkeypatch.setenv("AH_SCAN_PREFILTER", "1")
+    src = L.ah_scan_program_source([("ACGTACGTACGTAC", "GGTTCCAAGGTTC", 2, 0)])
+    assert "prefilter: 2 of 4 blocks" in src or "prefilter: 3 of 5 blocks" in src
 
 
 @pytest.mark.parametrize("seed", range(6))
