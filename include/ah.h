@@ -208,6 +208,47 @@ ah_status ah_pair_amplicons(const ah_hit* d_hits, const ah_result* d_nhits, uint
 size_t ah_pair_workspace_bytes(uint64_t hit_capacity, uint32_t n_pairs);
 
 /* ---------------------------------------------------------------------------
+ * Batched form: many primer pairs in one pass over the genomes (the paper's
+ * future work, Section 4: analysing several primer pairs simultaneously so that
+ * the genomes are not re-read for each pair).  ah_scan_primers, ah_tm and
+ * ah_pair_amplicons already take n_pairs pairs; the scan then reads each
+ * genome tile from HBM once and runs every pair's patterns on it, group by
+ * group.  The calls below choose the kernel shape for a primer set.
+ * ------------------------------------------------------------------------- */
+
+/* Scan kernel shape: window words per lane and tile (2, 4, 8 or 16; a tile of
+ * 256 x words_per_lane window words plus the primer halo is staged in LDS) and
+ * primer patterns per group (four per pair: each primer on each strand; a
+ * group's code runs over the whole staged tile before the next group's). */
+typedef struct ah_scan_tuning {
+  uint32_t words_per_lane;
+  uint32_t patterns_per_group;
+} ah_scan_tuning;
+
+/* Time candidate shapes of the scan kernel for this primer set on `genomes`
+ * (every candidate is compiled concurrently on host threads, run `repeats`
+ * times after a warm-up, timed with HIP events on `stream`), keep the fastest
+ * for later calls with the same set on this device, and return it.  The output
+ * buffers are used as scratch (results unspecified afterwards).  Synchronises
+ * `stream`.  Errors: as ah_scan_primers. */
+ah_status ah_autotune_scan(const ah_genomes* genomes, const ah_primer_pair* pairs, uint32_t n_pairs,
+                           ah_hit* d_hits, uint64_t capacity, ah_result* d_res, void* d_work,
+                           size_t work_bytes, void* stream, uint32_t repeats,
+                           ah_scan_tuning* chosen, double* best_ms);
+/* Specialise, compile and load the scan kernel for this primer set on the
+ * current device now (has_nmask: whether the genomes will carry a non-ACGT
+ * mask), so that a later ah_scan_primers call finds it cached.  Safe to call
+ * from several host threads at once (compilations run concurrently).
+ * Errors: AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT, AH_ERR_JIT, AH_ERR_HIP. */
+ah_status ah_scan_prepare(const ah_primer_pair* pairs, uint32_t n_pairs, int has_nmask);
+/* Set (tuning != NULL) or forget (NULL) the shape used for this primer set on
+ * the current device; AH_ERR_INVALID_ARG for an unsupported shape. */
+ah_status ah_set_scan_tuning(const ah_primer_pair* pairs, uint32_t n_pairs,
+                             const ah_scan_tuning* tuning);
+/* Shape that ah_scan_primers will use for this primer set. */
+ah_status ah_get_scan_tuning(const ah_primer_pair* pairs, uint32_t n_pairs, ah_scan_tuning* tuning);
+
+/* ---------------------------------------------------------------------------
  * Utilities.
  * ------------------------------------------------------------------------- */
 const char* ah_status_str(int status);

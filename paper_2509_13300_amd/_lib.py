@@ -58,6 +58,10 @@ class ah_tm_params(ctypes.Structure):
                 ("selfcomp", ctypes.c_int32)]
 
 
+class ah_scan_tuning(ctypes.Structure):
+    _fields_ = [("words_per_lane", ctypes.c_uint32), ("patterns_per_group", ctypes.c_uint32)]
+
+
 class ah_window(ctypes.Structure):
     _fields_ = [("min_len", ctypes.c_uint32), ("max_len", ctypes.c_uint32),
                 ("filter_tm", ctypes.c_int32), ("min_tm", ctypes.c_float)]
@@ -69,6 +73,7 @@ EXPORTS = (
     "ah_pair_amplicons", "ah_pair_workspace_bytes", "ah_status_str", "ah_last_error",
     "ah_release_caches", "ah_jit_stats", "ah_validate_pairs", "ah_scan_program_source",
     "ah_scan_program_compile", "ah_profile_enable", "ah_profile_reset", "ah_profile_query",
+    "ah_autotune_scan", "ah_set_scan_tuning", "ah_get_scan_tuning", "ah_scan_prepare",
 )
 
 _lib = None
@@ -119,6 +124,15 @@ def lib() -> ctypes.CDLL:
     L.ah_profile_reset.restype = None
     L.ah_profile_query.argtypes = [ctypes.c_char_p, P(ctypes.c_uint64), P(ctypes.c_double)]
     L.ah_profile_query.restype = st
+    L.ah_autotune_scan.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, vp, u64, vp, vp, sz, vp,
+                                   u32, P(ah_scan_tuning), P(ctypes.c_double)]
+    L.ah_autotune_scan.restype = st
+    L.ah_set_scan_tuning.argtypes = [P(ah_primer_pair), u32, P(ah_scan_tuning)]
+    L.ah_set_scan_tuning.restype = st
+    L.ah_get_scan_tuning.argtypes = [P(ah_primer_pair), u32, P(ah_scan_tuning)]
+    L.ah_get_scan_tuning.restype = st
+    L.ah_scan_prepare.argtypes = [P(ah_primer_pair), u32, ctypes.c_int]
+    L.ah_scan_prepare.restype = st
     _lib = L
     return L
 
@@ -263,3 +277,51 @@ def ah_profile_query(name: str):
     _check(lib().ah_profile_query(name.encode(), ctypes.byref(n), ctypes.byref(ms)),
            "ah_profile_query")
     return int(n.value), float(ms.value)
+
+
+def ah_autotune_scan(genomes: ah_genomes, pairs, hits, capacity: int, res, work, stream=None,
+                     repeats: int = 3):
+    """Time candidate scan shapes for the set; returns ((words_per_lane,
+    patterns_per_group), best ms)."""
+    pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
+    t = ah_scan_tuning()
+    ms = ctypes.c_double(0)
+    _check(lib().ah_autotune_scan(ctypes.byref(genomes), pp, len(pp), _ptr(hits), int(capacity),
+                                  _ptr(res), _ptr(work), 0 if work is None else work.numel(),
+                                  _stream(stream), int(repeats), ctypes.byref(t), ctypes.byref(ms)),
+           "ah_autotune_scan")
+    return (int(t.words_per_lane), int(t.patterns_per_group)), float(ms.value)
+
+
+def ah_set_scan_tuning(pairs, tuning=None):
+    pp = primer_pairs(pairs)
+    t = None if tuning is None else ctypes.byref(ah_scan_tuning(int(tuning[0]), int(tuning[1])))
+    _check(lib().ah_set_scan_tuning(pp, len(pp), t), "ah_set_scan_tuning")
+
+
+def ah_get_scan_tuning(pairs):
+    pp = primer_pairs(pairs)
+    t = ah_scan_tuning()
+    _check(lib().ah_get_scan_tuning(pp, len(pp), ctypes.byref(t)), "ah_get_scan_tuning")
+    return int(t.words_per_lane), int(t.patterns_per_group)
+
+
+def ah_scan_prepare(pairs, has_nmask: bool = False):
+    pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
+    _check(lib().ah_scan_prepare(pp, len(pp), int(has_nmask)), "ah_scan_prepare")
+
+
+def prepare_many(sets, has_nmask: bool = False, threads: int = 16):
+    """Compile the scan kernels of several primer sets concurrently."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    dev = torch.cuda.current_device()
+
+    def one(ps):
+        torch.cuda.set_device(dev)
+        ah_scan_prepare(ps, has_nmask)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, sets))

@@ -52,8 +52,18 @@ __device__ __forceinline__ void ah_pat_0(const u32* h, const u32* l, const AhCtx
   const u32 hb = cand & ~(s2 | cf);
   if (hb) { const u32 lv[2] = {s0, s1}; ah_emit<2>(c, t, hb, lv, 0u, 0u); }
 }
-__device__ void ah_patterns(const u32* h, const u32* l, const AhCtx& c, u32 t) {
-  ah_pat_0(h, l, c, t);
+__device__ __forceinline__ void ah_group_0(ah_lds_uint2* tw, u32 t0, AhCtx c) {
+  for (u32 i = threadIdx.x; i < (u32)AH_TILE; i += AH_BLOCK) {
+    const u32 t = t0 + i;
+    if (t >= c.S) break;
+    u32 h[20], l[20];
+#pragma unroll
+    for (int j = 0; j < 20; ++j) { const uint2 v = tw[i + (u32)j]; h[j] = v.x; l[j] = v.y; }
+    ah_pat_0(h, l, c, t);
+  }
+}
+__device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c) {
+  ah_group_0(tw, t0, c);
 }
 """
 

@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ah.h"
@@ -308,19 +309,36 @@ FilterPlan plan_filter(const Pattern& p, bool allow) {
   return best;
 }
 
+// Patterns per group (AH_SCAN_GROUP, default 16): each group's code runs
+// over the whole staged tile before the next group's.
+int scan_group() {
+  const char* e = getenv("AH_SCAN_GROUP");
+  const int g = e ? atoi(e) : 16;
+  return g >= 1 && g <= 1024 ? g : 16;
+}
+
+bool valid_u(int u) { return u == 2 || u == 4 || u == 8 || u == 16; }
+
+struct Tuning {
+  int u;      // window words per lane and tile
+  int group;  // patterns per group
+};
+
+Tuning default_tuning() { return Tuning{scan_u(), scan_group()}; }
+
 bool filter_enabled() {
   const char* e = getenv("AH_SCAN_PREFILTER");
   return !(e && e[0] == '0');
 }
 
-std::string gen_program(const std::vector<Pattern>& pats, bool has_n) {
+std::string gen_program(const std::vector<Pattern>& pats, bool has_n, Tuning tn) {
   int lmax = 0;
   for (const Pattern& p : pats) lmax = p.L > lmax ? p.L : lmax;
   const bool allow = filter_enabled();
   std::string s;
   char buf[640];
   snprintf(buf, sizeof buf,
-           "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n", scan_u(), lmax - 1,
+           "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n", tn.u, lmax - 1,
            has_n ? 1 : 0);
   std::string head = buf;
   for (size_t i = 0; i < pats.size(); ++i) {
@@ -420,8 +438,26 @@ std::string gen_program(const std::vector<Pattern>& pats, bool has_n) {
     }
     s += buf;
   }
-  s += "__device__ void ah_patterns(const u32* h, const u32* l, const AhCtx& c, u32 t) {\n";
-  for (size_t i = 0; i < pats.size(); ++i) s += "  ah_pat_" + std::to_string(i) + "(h, l, c, t);\n";
+  // groups of consecutive patterns; one function per group walks the tile
+  const size_t G = (size_t)tn.group;
+  const size_t ngroups = (pats.size() + G - 1) / G;
+  for (size_t gi = 0; gi < ngroups; ++gi) {
+    const size_t a = gi * G, b = std::min(pats.size(), a + G);
+    int lg = 0;
+    for (size_t i = a; i < b; ++i) lg = std::max(lg, pats[i].L);
+    snprintf(buf, sizeof buf,
+             "__device__ %s void ah_group_%zu(ah_lds_uint2* tw, u32 t0, AhCtx c) {\n"
+             "  for (u32 i = threadIdx.x; i < (u32)AH_TILE; i += AH_BLOCK) {\n"
+             "    const u32 t = t0 + i;\n    if (t >= c.S) break;\n"
+             "    u32 h[%d], l[%d];\n#pragma unroll\n"
+             "    for (int j = 0; j < %d; ++j) { const uint2 v = tw[i + (u32)j]; h[j] = v.x; l[j] = v.y; }\n",
+             ngroups > 1 ? "__noinline__" : "__forceinline__", gi, lg, lg, lg);
+    s += buf;
+    for (size_t i = a; i < b; ++i) s += "    ah_pat_" + std::to_string(i) + "(h, l, c, t);\n";
+    s += "  }\n}\n";
+  }
+  s += "__device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c) {\n";
+  for (size_t gi = 0; gi < ngroups; ++gi) s += "  ah_group_" + std::to_string(gi) + "(tw, t0, c);\n";
   s += "}\n";
   return head + std::string(kScanCore) + s;
 }
@@ -438,6 +474,8 @@ std::map<std::pair<int, std::string>, void*> g_tables;
 uint64_t g_jit_n = 0;
 double g_jit_ms = 0.0;
 std::map<int, int> g_cus;
+
+std::mutex g_stats_mu;
 
 ah_status rtc_compile(const std::string& src, std::vector<char>& code) {
   hiprtcProgram prog;
@@ -461,30 +499,71 @@ ah_status rtc_compile(const std::string& src, std::vector<char>& code) {
   code.resize(n);
   hiprtcGetCode(prog, code.data());
   hiprtcDestroyProgram(&prog);
+  std::lock_guard<std::mutex> lk(g_stats_mu);
   g_jit_n += 1;
   g_jit_ms += ms;
   return AH_OK;
 }
 
-ah_status get_scan_kernel(const std::string& src, hipFunction_t& fn) {
-  int dev = 0;
-  AH_HIP(hipGetDevice(&dev));
+// Loaded scan kernel for an already compiled program (cached per device).
+ah_status load_scan_kernel(int dev, const std::string& src, const std::vector<char>& code,
+                           hipFunction_t& fn) {
   std::lock_guard<std::mutex> lk(g_mu);
-  auto key = std::make_pair(dev, src);
-  auto it = g_jit.find(key);
+  const auto key = std::make_pair(dev, src);
+  auto it = g_jit.find(key);  // another thread may have loaded it meanwhile
   if (it != g_jit.end()) {
     fn = it->second.fn;
     return AH_OK;
   }
-  std::vector<char> code;
-  ah_status s = rtc_compile(src, code);
-  if (s) return s;
   JitEntry e;
   AH_HIP(hipModuleLoadData(&e.mod, code.data()));
   AH_HIP(hipModuleGetFunction(&e.fn, e.mod, "ah_scan_kernel"));
   g_jit[key] = e;
   fn = e.fn;
   return AH_OK;
+}
+
+// Compiled and loaded scan kernel for `src` on the current device (cached;
+// compiles outside the cache lock so that several programs can compile at
+// once).
+ah_status get_scan_kernel(const std::string& src, hipFunction_t& fn) {
+  int dev = 0;
+  AH_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_jit.find(std::make_pair(dev, src));
+    if (it != g_jit.end()) {
+      fn = it->second.fn;
+      return AH_OK;
+    }
+  }
+  std::vector<char> code;
+  ah_status s = rtc_compile(src, code);
+  if (s) return s;
+  return load_scan_kernel(dev, src, code, fn);
+}
+
+// Tile shape and grouping chosen for a primer set (by the autotuner or the
+// caller), per device.
+std::map<std::pair<int, std::string>, Tuning> g_tuning;
+
+std::string set_key(const ah_primer_pair* pairs, uint32_t n_pairs) {
+  std::string k;
+  for (uint32_t q = 0; q < n_pairs; ++q) {
+    k += pairs[q].fwd;
+    k += '|';
+    k += pairs[q].rev;
+    k += '|' + std::to_string(pairs[q].k) + '|' + std::to_string(pairs[q].clamp) + ';';
+  }
+  return k;
+}
+
+Tuning tuning_for(const ah_primer_pair* pairs, uint32_t n_pairs) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_tuning.find(std::make_pair(dev, set_key(pairs, n_pairs)));
+  return it != g_tuning.end() ? it->second : default_tuning();
 }
 
 // Device copy of a small immutable table, uploaded once per device.
@@ -632,6 +711,29 @@ ah_status check_genomes(const ah_genomes* g) {
   return AH_OK;
 }
 
+// Tile counts, tile prefix and the scan kernel itself (hits appended to the
+// staging area, counted in d_res->required).
+ah_status launch_scan_kernel(hipFunction_t fn, Tuning tn, const ah_genomes* g, const ScanWs& w,
+                             ah_result* d_res, uint64_t capacity, hipStream_t st) {
+  if (g->n == 0) return AH_OK;
+  AH_HIP(ah::launch_tile_counts(g->len, g->n, (uint32_t)(ah::kBlock * tn.u), w.counts, st));
+  AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
+  const void* words = g->words;
+  const uint32_t* nmask = g->nmask;
+  const uint64_t* word_off = g->word_off;
+  const uint32_t* len = g->len;
+  const uint64_t* tp = w.tile_prefix;
+  uint32_t n = g->n;
+  ah_hit* out = w.staging;
+  uint64_t cap = capacity;
+  uint64_t* counter = &d_res->required;
+  void* args[] = {&words, &nmask, &word_off, &len, &tp, &n, &out, &cap, &counter};
+  const unsigned grid = (unsigned)cu_count() * 8u;
+  ProfScope prof_scan("scan", st);
+  AH_HIP(hipModuleLaunchKernel(fn, grid, 1, 1, ah::kBlock, 1, 1, 0, st, args, nullptr));
+  return AH_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -716,31 +818,17 @@ ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint
   const size_t need = ah_scan_workspace_bytes(g, n_pairs, capacity);
   if (!d_work || work_bytes < need)
     return fail(AH_ERR_WORKSPACE, "scan workspace: %zu bytes given, %zu needed", work_bytes, need);
+  const Tuning tn = tuning_for(pairs, n_pairs);
   hipFunction_t fn;
-  s = get_scan_kernel(gen_program(patterns_of(ps), g->nmask != nullptr), fn);
+  s = get_scan_kernel(gen_program(patterns_of(ps), g->nmask != nullptr, tn), fn);
   if (s) return s;
 
   hipStream_t st = (hipStream_t)stream;
   Carver c(d_work, work_bytes);
   ScanWs w = carve_scan(c, g->n, capacity);
   AH_HIP(ah::launch_result_init(d_res, st));
-  if (g->n > 0) {
-    AH_HIP(ah::launch_tile_counts(g->len, g->n, (uint32_t)(ah::kBlock * scan_u()), w.counts, st));
-    AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
-    const void* words = g->words;
-    const uint32_t* nmask = g->nmask;
-    const uint64_t* word_off = g->word_off;
-    const uint32_t* len = g->len;
-    const uint64_t* tp = w.tile_prefix;
-    uint32_t n = g->n;
-    ah_hit* out = w.staging;
-    uint64_t cap = capacity;
-    uint64_t* counter = &d_res->required;
-    void* args[] = {&words, &nmask, &word_off, &len, &tp, &n, &out, &cap, &counter};
-    const unsigned grid = (unsigned)cu_count() * 8u;
-    ProfScope prof_scan("scan", st);
-    AH_HIP(hipModuleLaunchKernel(fn, grid, 1, 1, ah::kBlock, 1, 1, 0, st, args, nullptr));
-  }
+  s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st);
+  if (s) return s;
   AH_HIP(ah::launch_result_finalize(d_res, capacity, w.n_sort, st));
   ProfScope prof_sort("sort", st);
   AH_HIP(ah::launch_sort_hits(w.staging, d_hits, w.n_sort, kb, w.sb, st));
@@ -871,7 +959,7 @@ size_t ah_scan_program_source(const ah_primer_pair* pairs, uint32_t n_pairs, int
   g_err.clear();
   PairSet ps;
   if (compile_pairs(pairs, n_pairs, ps)) return 0;
-  const std::string src = gen_program(patterns_of(ps), has_nmask != 0);
+  const std::string src = gen_program(patterns_of(ps), has_nmask != 0, tuning_for(pairs, n_pairs));
   if (buf && buf_bytes) {
     const size_t n = src.size() < buf_bytes - 1 ? src.size() : buf_bytes - 1;
     memcpy(buf, src.data(), n);
@@ -887,12 +975,138 @@ ah_status ah_scan_program_compile(const ah_primer_pair* pairs, uint32_t n_pairs,
   ah_status s = compile_pairs(pairs, n_pairs, ps);
   if (s) return s;
   std::vector<char> code;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    s = rtc_compile(gen_program(patterns_of(ps), has_nmask != 0), code);
-  }
+  s = rtc_compile(gen_program(patterns_of(ps), has_nmask != 0, tuning_for(pairs, n_pairs)), code);
   if (s) return s;
   if (code_bytes) *code_bytes = code.size();
+  return AH_OK;
+}
+
+ah_status ah_scan_prepare(const ah_primer_pair* pairs, uint32_t n_pairs, int has_nmask) {
+  g_err.clear();
+  PairSet ps;
+  ah_status s = compile_pairs(pairs, n_pairs, ps);
+  if (s) return s;
+  hipFunction_t fn;
+  return get_scan_kernel(gen_program(patterns_of(ps), has_nmask != 0, tuning_for(pairs, n_pairs)),
+                         fn);
+}
+
+ah_status ah_set_scan_tuning(const ah_primer_pair* pairs, uint32_t n_pairs,
+                             const ah_scan_tuning* tuning) {
+  g_err.clear();
+  PairSet ps;
+  ah_status s = compile_pairs(pairs, n_pairs, ps);
+  if (s) return s;
+  int dev = 0;
+  AH_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  const auto key = std::make_pair(dev, set_key(pairs, n_pairs));
+  if (!tuning) {
+    g_tuning.erase(key);
+    return AH_OK;
+  }
+  if (!valid_u((int)tuning->words_per_lane) || tuning->patterns_per_group < 1 ||
+      tuning->patterns_per_group > 1024)
+    return fail(AH_ERR_INVALID_ARG, "tuning: words_per_lane in {2,4,8,16}, patterns_per_group in 1..1024");
+  g_tuning[key] = Tuning{(int)tuning->words_per_lane, (int)tuning->patterns_per_group};
+  return AH_OK;
+}
+
+ah_status ah_get_scan_tuning(const ah_primer_pair* pairs, uint32_t n_pairs, ah_scan_tuning* tuning) {
+  g_err.clear();
+  if (!tuning) return fail(AH_ERR_INVALID_ARG, "tuning is NULL");
+  PairSet ps;
+  ah_status s = compile_pairs(pairs, n_pairs, ps);
+  if (s) return s;
+  const Tuning t = tuning_for(pairs, n_pairs);
+  tuning->words_per_lane = (uint32_t)t.u;
+  tuning->patterns_per_group = (uint32_t)t.group;
+  return AH_OK;
+}
+
+ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pairs,
+                           ah_hit* d_hits, uint64_t capacity, ah_result* d_res, void* d_work,
+                           size_t work_bytes, void* stream, uint32_t repeats,
+                           ah_scan_tuning* chosen, double* best_ms) {
+  g_err.clear();
+  ah_status s = check_genomes(g);
+  if (s) return s;
+  if (!d_res || !chosen) return fail(AH_ERR_INVALID_ARG, "ah_autotune_scan: d_res and chosen are required");
+  if (capacity > 0 && !d_hits) return fail(AH_ERR_INVALID_ARG, "d_hits is NULL");
+  PairSet ps;
+  s = compile_pairs(pairs, n_pairs, ps);
+  if (s) return s;
+  const size_t need = ah_scan_workspace_bytes(g, n_pairs, capacity);
+  if (!d_work || work_bytes < need)
+    return fail(AH_ERR_WORKSPACE, "scan workspace: %zu bytes given, %zu needed", work_bytes, need);
+  const std::vector<Pattern> pats = patterns_of(ps);
+  // candidates: tile words per lane x patterns per group (a single group when
+  // the set is small)
+  std::vector<Tuning> cand;
+  for (int u : {2, 4, 8})
+    for (int grp : {8, 16, 32}) {
+      if (grp > (int)pats.size() && grp != 8) continue;
+      cand.push_back(Tuning{u, std::min(grp, (int)pats.size())});
+    }
+  // compile every candidate concurrently (host threads), then time each
+  std::vector<std::string> srcs(cand.size());
+  std::vector<std::vector<char>> codes(cand.size());
+  std::vector<ah_status> st(cand.size(), AH_OK);
+  std::vector<std::string> errs(cand.size());
+  for (size_t i = 0; i < cand.size(); ++i) srcs[i] = gen_program(pats, g->nmask != nullptr, cand[i]);
+  {
+    std::vector<std::thread> th;
+    for (size_t i = 0; i < cand.size(); ++i)
+      th.emplace_back([&, i] {
+        st[i] = rtc_compile(srcs[i], codes[i]);
+        if (st[i]) errs[i] = g_err;
+      });
+    for (auto& t : th) t.join();
+  }
+  int dev = 0;
+  AH_HIP(hipGetDevice(&dev));
+  hipStream_t strm = (hipStream_t)stream;
+  Carver c(d_work, work_bytes);
+  ScanWs w = carve_scan(c, g->n, capacity);
+  hipEvent_t e0, e1;
+  AH_HIP(hipEventCreate(&e0));
+  AH_HIP(hipEventCreate(&e1));
+  double best = 1e30;
+  size_t besti = 0;
+  const uint32_t reps = repeats ? repeats : 3;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    if (st[i]) return fail(st[i], "%s", errs[i].c_str());
+    hipFunction_t fn;
+    s = load_scan_kernel(dev, srcs[i], codes[i], fn);
+    if (s) return s;
+    double total = 0.0;
+    for (uint32_t r = 0; r <= reps; ++r) {  // the first run warms up
+      AH_HIP(ah::launch_result_init(d_res, strm));
+      AH_HIP(hipEventRecord(e0, strm));
+      s = launch_scan_kernel(fn, cand[i], g, w, d_res, capacity, strm);
+      if (s) return s;
+      AH_HIP(hipEventRecord(e1, strm));
+      AH_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      AH_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (r) total += ms;
+    }
+    const double avg = total / reps;
+    if (avg < best) {
+      best = avg;
+      besti = i;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  AH_HIP(ah::launch_result_init(d_res, strm));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuning[std::make_pair(dev, set_key(pairs, n_pairs))] = cand[besti];
+  }
+  chosen->words_per_lane = (uint32_t)cand[besti].u;
+  chosen->patterns_per_group = (uint32_t)cand[besti].group;
+  if (best_ms) *best_ms = best;
   return AH_OK;
 }
 

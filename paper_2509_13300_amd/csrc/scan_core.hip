@@ -115,10 +115,14 @@ __device__ __forceinline__ AhCtx ah_tile_ctx(const u64* __restrict__ tile_prefix
   return c;
 }
 
-// Generated: prefilters every pattern on one window word (words h[0..],
-// l[0..] in registers) and runs the exact count where a lane has a
-// candidate window.
-__device__ void ah_patterns(const u32* h, const u32* l, const AhCtx& c, u32 t);
+typedef __attribute__((address_space(3))) const uint2 ah_lds_uint2;
+
+// Generated: for every group of patterns in turn, every lane walks its window
+// words of the staged tile (reading the group's longest primer's worth of
+// words from LDS), prefilters each pattern of the group and runs the exact
+// count where a lane has a candidate window.  One group's code runs over the
+// whole tile before the next group's.
+__device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c);
 
 // Words staged per tile: the tile's window words plus the halo, in 16-byte
 // pairs (every genome starts 16-byte aligned).
@@ -173,19 +177,7 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
                        counter, t0n);
       ah_stage(cn, t0n, tiles[buf ^ 1]);
     }
-    const uint2* tw = (const uint2*)tiles[buf];
-    for (u32 i = threadIdx.x; i < (u32)AH_TILE; i += AH_BLOCK) {
-      const u32 t = t0 + i;
-      if (t >= c.S) break;
-      u32 h[AH_HALO + 1], l[AH_HALO + 1];
-#pragma unroll
-      for (int j = 0; j <= AH_HALO; ++j) {
-        const uint2 v = tw[i + (u32)j];
-        h[j] = v.x;
-        l[j] = v.y;
-      }
-      ah_patterns(h, l, c, t);
-    }
+    ah_groups((ah_lds_uint2*)tiles[buf], t0, c);
     if (Tn >= n_tiles) break;
     __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
     __syncthreads();                // and everyone's; nobody still reads `buf`

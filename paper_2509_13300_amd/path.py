@@ -114,3 +114,24 @@ def hits_numpy(buf: QueryBuffers) -> np.ndarray:
 def amps_numpy(buf: QueryBuffers) -> np.ndarray:
     n = result(buf.amp_res)["count"]
     return np.frombuffer(buf.amps[: n * 24].cpu().numpy().tobytes(), dtype=L.AMP_DTYPE).copy()
+
+
+def capture(coll: PackedCollection, pairs: Sequence, buf: QueryBuffers, tm=None, filter_tm=False,
+            min_tm: float = 50.0):
+    """Record one scan -> Tm -> pairing pass for ``pairs`` into a hipGraph
+    (through torch.cuda.CUDAGraph).  Call ``run`` once with the same pairs
+    first, so that the specialised kernel and per-set tables exist; the graph
+    then replays with no host-side work."""
+    import torch
+
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run(coll, pairs, buf, tm=tm, filter_tm=filter_tm, min_tm=min_tm)
+    return g
+
+
+def subset_view(coll: PackedCollection, n: int) -> L.ah_genomes:
+    """View of the first ``n`` genomes of a packed collection (no copy)."""
+    g = coll.view()
+    g.n = min(n, coll.n)
+    return g
