@@ -249,6 +249,70 @@ ah_status ah_set_scan_tuning(const ah_primer_pair* pairs, uint32_t n_pairs,
 ah_status ah_get_scan_tuning(const ah_primer_pair* pairs, uint32_t n_pairs, ah_scan_tuning* tuning);
 
 /* ---------------------------------------------------------------------------
+ * Streaming form: a packed collection held in host memory is copied to the GPU
+ * in chunks of whole genomes on the caller's copy streams while the previous
+ * chunks are scanned, scored and paired on the compute stream.  The paper
+ * reads genomes from disk and names that I/O as a large part of its run time
+ * (Section 4); here the host-to-HBM copy of the 2-bit packed form (0.25 B per
+ * base) is the only transfer, and it overlaps the device work.
+ * ------------------------------------------------------------------------- */
+
+/* A packed collection in host memory, laid out as ah_pack_layout and
+ * ah_pack_genomes lay it out on the device: words holds 2 x word_off[n]
+ * uint32 (h, l of each word), nmask word_off[n] uint32 or NULL.  words and
+ * nmask should be pinned (hipHostMalloc, or a torch tensor created with
+ * pin_memory=True): from pageable memory the copies do not overlap.
+ * word_off (n + 1) and len (n) are host arrays.  All borrowed for the call. */
+typedef struct ah_host_genomes {
+  const uint32_t* words;
+  const uint32_t* nmask;
+  const uint64_t* word_off;
+  const uint32_t* len;
+  uint32_t n;
+} ah_host_genomes;
+
+/* chunk_words: packed words per staging slot; consecutive genomes are grouped
+ * into chunks of at most this many words, and every genome must fit in one
+ * (word_off[g + 1] - word_off[g] <= chunk_words, else AH_ERR_LIMIT).
+ * n_slots (2..16): staging slots on the device; while one chunk is processed
+ * the copies of up to n_slots - 1 later chunks are in flight. */
+typedef struct ah_stream_config {
+  uint64_t chunk_words;
+  uint32_t n_slots;
+  uint32_t reserved; /* 0 */
+} ah_stream_config;
+
+/* Device workspace for ah_stream_query: the staging slots, the collection's
+ * offsets and lengths, and the scan and pairing workspaces of one chunk. */
+size_t ah_stream_workspace_bytes(const ah_host_genomes* genomes, const ah_stream_config* cfg,
+                                 uint32_t n_pairs, uint64_t hit_capacity);
+
+/* Scan, Tm and pairing of `pairs` over a host-resident packed collection,
+ * streamed chunk by chunk.  Chunk c's copy runs on copy_streams[c %
+ * n_copy_streams] (the compute stream when n_copy_streams is 0); everything
+ * else runs on `stream`.  The call blocks until every chunk is done (it reads
+ * each chunk's counts to place the next chunk's output); results are then
+ * complete in d_hits / d_amp and their ah_result records.
+ *
+ * Output: the chunks' outputs concatenated in chunk order, genome ids and the
+ * amplicons' hit indices rewritten to collection-wide ones.  Each chunk is in
+ * canonical order, so for one pair the output is byte-identical to a call of
+ * ah_scan_primers / ah_tm / ah_pair_amplicons on the resident collection; for
+ * several pairs it is that output ordered by (genome chunk, pair, ...).
+ * Overflow: when the hits exceed hit_capacity, both results report
+ * AH_ERR_OVERFLOW, d_hit_res->required is the exact total, and the amplicons
+ * are incomplete (retry with hit_capacity >= required); when only the
+ * amplicons exceed amp_capacity, d_amp_res->required is the exact total.
+ * Errors: those of the three calls, AH_ERR_LIMIT (a genome larger than a
+ * slot, or more than 2^32 - 1 hits), AH_ERR_WORKSPACE, AH_ERR_HIP. */
+ah_status ah_stream_query(const ah_host_genomes* genomes, const ah_stream_config* cfg,
+                          const ah_primer_pair* pairs, const ah_window* windows, uint32_t n_pairs,
+                          const ah_tm_params* tm, ah_hit* d_hits, uint64_t hit_capacity,
+                          ah_result* d_hit_res, ah_amplicon* d_amp, uint64_t amp_capacity,
+                          ah_result* d_amp_res, void* d_work, size_t work_bytes, void* stream,
+                          void* const* copy_streams, uint32_t n_copy_streams);
+
+/* ---------------------------------------------------------------------------
  * Utilities.
  * ------------------------------------------------------------------------- */
 const char* ah_status_str(int status);

@@ -67,6 +67,16 @@ class ah_window(ctypes.Structure):
                 ("filter_tm", ctypes.c_int32), ("min_tm", ctypes.c_float)]
 
 
+class ah_host_genomes(ctypes.Structure):
+    _fields_ = [("words", ctypes.c_void_p), ("nmask", ctypes.c_void_p),
+                ("word_off", ctypes.c_void_p), ("len", ctypes.c_void_p), ("n", ctypes.c_uint32)]
+
+
+class ah_stream_config(ctypes.Structure):
+    _fields_ = [("chunk_words", ctypes.c_uint64), ("n_slots", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
 # Every symbol declared in include/ah.h and include/ah_dev.h.
 EXPORTS = (
     "ah_pack_layout", "ah_pack_genomes", "ah_scan_primers", "ah_scan_workspace_bytes", "ah_tm",
@@ -74,6 +84,7 @@ EXPORTS = (
     "ah_release_caches", "ah_jit_stats", "ah_validate_pairs", "ah_scan_program_source",
     "ah_scan_program_compile", "ah_profile_enable", "ah_profile_reset", "ah_profile_query",
     "ah_autotune_scan", "ah_set_scan_tuning", "ah_get_scan_tuning", "ah_scan_prepare",
+    "ah_stream_workspace_bytes", "ah_stream_query",
 )
 
 _lib = None
@@ -133,6 +144,12 @@ def lib() -> ctypes.CDLL:
     L.ah_get_scan_tuning.restype = st
     L.ah_scan_prepare.argtypes = [P(ah_primer_pair), u32, ctypes.c_int]
     L.ah_scan_prepare.restype = st
+    L.ah_stream_workspace_bytes.argtypes = [P(ah_host_genomes), P(ah_stream_config), u32, u64]
+    L.ah_stream_workspace_bytes.restype = sz
+    L.ah_stream_query.argtypes = [P(ah_host_genomes), P(ah_stream_config), P(ah_primer_pair),
+                                  P(ah_window), u32, P(ah_tm_params), vp, u64, vp, vp, u64, vp, vp,
+                                  sz, vp, P(vp), u32]
+    L.ah_stream_query.restype = st
     _lib = L
     return L
 
@@ -325,3 +342,49 @@ def prepare_many(sets, has_nmask: bool = False, threads: int = 16):
 
     with ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(one, sets))
+
+
+class HostGenomes:
+    """Host view of a packed collection for the streaming calls.  ``words`` and
+    ``nmask`` are host tensors (pinned for overlapped copies); word_off and
+    len are kept here as numpy arrays so that they outlive the call."""
+
+    def __init__(self, words, word_off, lengths, nmask=None):
+        self.words, self.nmask = words, nmask
+        self.word_off = np.ascontiguousarray(word_off, dtype=np.uint64)
+        self.len = np.ascontiguousarray(lengths, dtype=np.uint32)
+        self.n = int(self.len.size)
+
+    def view(self) -> ah_host_genomes:
+        h = ah_host_genomes()
+        h.words = _ptr(self.words)
+        h.nmask = _ptr(self.nmask)
+        h.word_off = self.word_off.ctypes.data
+        h.len = self.len.ctypes.data if self.n else None
+        h.n = self.n
+        return h
+
+
+def stream_config(chunk_words: int, n_slots: int = 3) -> ah_stream_config:
+    c = ah_stream_config()
+    c.chunk_words = int(chunk_words)
+    c.n_slots = int(n_slots)
+    return c
+
+
+def ah_stream_workspace_bytes(hg: HostGenomes, cfg: ah_stream_config, n_pairs: int,
+                              hit_capacity: int) -> int:
+    return int(lib().ah_stream_workspace_bytes(ctypes.byref(hg.view()), ctypes.byref(cfg),
+                                               int(n_pairs), int(hit_capacity)))
+
+
+def ah_stream_query(hg: HostGenomes, cfg: ah_stream_config, pairs, wins, params: ah_tm_params,
+                    hits, hit_capacity: int, hit_res, amp, amp_capacity: int, amp_res, work,
+                    stream=None, copy_streams=()):
+    pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
+    cs = (ctypes.c_void_p * max(1, len(copy_streams)))(*[_stream(s) for s in copy_streams])
+    _check(lib().ah_stream_query(ctypes.byref(hg.view()), ctypes.byref(cfg), pp, wins, len(pp),
+                                 ctypes.byref(params), _ptr(hits), int(hit_capacity), _ptr(hit_res),
+                                 _ptr(amp), int(amp_capacity), _ptr(amp_res), _ptr(work),
+                                 0 if work is None else work.numel(), _stream(stream), cs,
+                                 len(copy_streams)), "ah_stream_query")

@@ -736,6 +736,20 @@ ah_status launch_scan_kernel(hipFunction_t fn, Tuning tn, const ah_genomes* g, c
 
 }  // namespace
 
+namespace ah {
+ah_status set_error(ah_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+void clear_error() { g_err.clear(); }
+int cu_count_current() { return cu_count(); }
+}  // namespace ah
+
 // =================================================================== C ABI
 extern "C" {
 

@@ -90,4 +90,16 @@ hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
                        const PairBuffers& pb, int grid, hipStream_t st);
 
+// Streaming: word offsets of genomes off[0..n] relative to off[0], and the
+// chunk-local -> collection id fix-up of a chunk's hits and amplicons.
+hipError_t launch_rebase(const uint64_t* off, uint32_t n, uint64_t* out, hipStream_t st);
+hipError_t launch_stream_fixup(ah_hit* hits, uint64_t nh, ah_amplicon* amp, uint64_t na,
+                               uint32_t gbase, uint32_t hbase, int grid, hipStream_t st);
+
+// Error reporting shared by the host sources: records the message returned by
+// ah_last_error() on this thread and returns s.
+ah_status set_error(ah_status s, const char* fmt, ...);
+void clear_error();
+int cu_count_current();
+
 }  // namespace ah

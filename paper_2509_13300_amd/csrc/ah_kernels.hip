@@ -560,6 +560,29 @@ __global__ void k_pair_finalize(const u64* __restrict__ n_dev, const u64* __rest
   }
 }
 
+// ---- streaming: per-chunk offsets and id fix-up ---------------------------
+// out[i] = off[i] - off[0] for i = 0..n: the word offsets of a run of genomes
+// relative to the first, for a chunk staged on its own.
+__global__ void k_rebase(const u64* __restrict__ off, u32 n, u64* __restrict__ out) {
+  const u64 base = off[0];
+  for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x)
+    out[i] = off[i] - base;
+}
+
+// Chunk-local ids to collection ids: genome += gbase on hits and amplicons,
+// hit indices of amplicons += hbase.
+__global__ __launch_bounds__(kBlock) void k_stream_fixup(ah_hit* __restrict__ hits, u64 nh,
+                                                         ah_amplicon* __restrict__ amp, u64 na,
+                                                         u32 gbase, u32 hbase) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += stride) hits[i].genome += gbase;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < na; i += stride) {
+    amp[i].genome += gbase;
+    amp[i].plus_hit += hbase;
+    amp[i].minus_hit += hbase;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------- launchers ----
@@ -618,7 +641,9 @@ hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n
   for (int shift = 0; shift < bits; shift += 8) {
     k_sort_hist<<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], (const u64*)n_dev, shift,
                                              (u64*)sb.hist);
-    launch_exclusive_scan(sb.hist, sb.hist_off, (uint64_t)256 * kSortGrid, nullptr, sb.scan_tmp, st);
+    hipError_t e = launch_exclusive_scan(sb.hist, sb.hist_off, (uint64_t)256 * kSortGrid, nullptr,
+                                         sb.scan_tmp, st);
+    if (e != hipSuccess) return e;
     k_sort_scatter<<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], sb.idx[cur],
                                                 (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1],
                                                 (const u64*)n_dev, shift, (const u64*)sb.hist_off);
@@ -641,20 +666,36 @@ hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_
   const u64* n = (const u64*)pb.n;
   k_pair_n<<<1, 64, 0, st>>>(nhits, hit_cap, (u64*)pb.n);
   k_pair_mark<<<grid, kBlock, 0, st>>>(hits, n, tabs, pb.flag_f, pb.flag_r);
-  launch_exclusive_scan_u32(pb.flag_f, pb.off_f, pb.n, pb.scan_tmp, st);
-  launch_exclusive_scan_u32(pb.flag_r, pb.off_r, pb.n, pb.scan_tmp, st);
+  hipError_t e = launch_exclusive_scan_u32(pb.flag_f, pb.off_f, pb.n, pb.scan_tmp, st);
+  if (e == hipSuccess) e = launch_exclusive_scan_u32(pb.flag_r, pb.off_r, pb.n, pb.scan_tmp, st);
+  if (e != hipSuccess) return e;
   k_pair_compact<<<grid, kBlock, 0, st>>>(hits, n, pb.flag_f, pb.flag_r, (const u64*)pb.off_f,
                                           (const u64*)pb.off_r, (u64*)pb.mkey_f, pb.mpos_f, pb.midx_f,
                                           (u64*)pb.mkey_r, pb.mpos_r, pb.midx_r);
   k_pair_count<<<grid, kBlock, 0, st>>>(hits, n, tabs, (const u64*)pb.mkey_f, pb.mpos_f,
                                         (const u64*)pb.off_f, (const u64*)pb.mkey_r, pb.mpos_r,
                                         (const u64*)pb.off_r, pb.cnt);
-  launch_exclusive_scan_u32(pb.cnt, pb.cnt_off, pb.n, pb.scan_tmp, st);
+  e = launch_exclusive_scan_u32(pb.cnt, pb.cnt_off, pb.n, pb.scan_tmp, st);
+  if (e != hipSuccess) return e;
   k_pair_write<<<grid, kBlock, 0, st>>>(hits, n, tabs, (const u64*)pb.mkey_f, pb.mpos_f, pb.midx_f,
                                         (const u64*)pb.off_f, (const u64*)pb.mkey_r, pb.mpos_r,
                                         pb.midx_r, (const u64*)pb.off_r, (const u64*)pb.cnt_off, amp,
                                         cap);
   k_pair_finalize<<<1, 64, 0, st>>>(n, (const u64*)pb.cnt_off, cap, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebase(const uint64_t* off, uint32_t n, uint64_t* out, hipStream_t st) {
+  const uint64_t blocks = ((uint64_t)n + kBlock) / kBlock;
+  const unsigned grid = blocks > 1024 ? 1024u : (unsigned)blocks;
+  k_rebase<<<grid, kBlock, 0, st>>>((const u64*)off, n, (u64*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_fixup(ah_hit* hits, uint64_t nh, ah_amplicon* amp, uint64_t na,
+                               uint32_t gbase, uint32_t hbase, int grid, hipStream_t st) {
+  if (nh == 0 && na == 0) return hipSuccess;
+  k_stream_fixup<<<grid, kBlock, 0, st>>>(hits, nh, amp, na, gbase, hbase);
   return hipGetLastError();
 }
 

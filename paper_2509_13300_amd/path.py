@@ -135,3 +135,96 @@ def subset_view(coll: PackedCollection, n: int) -> L.ah_genomes:
     g = coll.view()
     g.n = min(n, coll.n)
     return g
+
+
+def to_host(coll: PackedCollection, pin: bool = True) -> L.HostGenomes:
+    """Copy a packed collection from HBM into (pinned) host memory, in the
+    layout that the streaming calls read."""
+    import torch
+
+    words = torch.empty(coll.words.numel(), dtype=torch.int32, pin_memory=pin)
+    words.copy_(coll.words)
+    nmask = None
+    if coll.nmask is not None:
+        nmask = torch.empty(coll.nmask.numel(), dtype=torch.int32, pin_memory=pin)
+        nmask.copy_(coll.nmask)
+    return L.HostGenomes(words, coll.word_off.cpu().numpy().view(np.uint64), coll.lengths, nmask)
+
+
+@dataclasses.dataclass
+class StreamBuffers:
+    hits: "object"
+    hit_res: "object"
+    amps: "object"
+    amp_res: "object"
+    work: "object"
+    hit_cap: int
+    amp_cap: int
+    cfg: L.ah_stream_config
+
+
+def stream_alloc(hg: L.HostGenomes, n_pairs: int, hit_cap: int, amp_cap: int, device,
+                 chunk_words: int, n_slots: int = 3) -> StreamBuffers:
+    import torch
+
+    cfg = L.stream_config(chunk_words, n_slots)
+    wb = L.ah_stream_workspace_bytes(hg, cfg, n_pairs, hit_cap)
+    return StreamBuffers(
+        hits=torch.empty(max(hit_cap, 1) * 16, dtype=torch.uint8, device=device),
+        hit_res=torch.zeros(24, dtype=torch.uint8, device=device),
+        amps=torch.empty(max(amp_cap, 1) * 24, dtype=torch.uint8, device=device),
+        amp_res=torch.zeros(24, dtype=torch.uint8, device=device),
+        work=torch.empty(wb, dtype=torch.uint8, device=device),
+        hit_cap=hit_cap, amp_cap=amp_cap, cfg=cfg)
+
+
+def stream_run(hg: L.HostGenomes, pairs: Sequence, buf: StreamBuffers,
+               tm: Optional[L.ah_tm_params] = None, filter_tm: bool = False,
+               min_tm: float = 50.0, stream=None, copy_streams=()):
+    """Scan, Tm and pairing over a host-resident packed collection, copied to
+    the GPU chunk by chunk on ``copy_streams``.  Blocks until done."""
+    L.ah_stream_query(hg, buf.cfg, L.primer_pairs(pairs), L.windows(pairs, filter_tm, min_tm),
+                      tm if tm is not None else L.tm_params(), buf.hits, buf.hit_cap, buf.hit_res,
+                      buf.amps, buf.amp_cap, buf.amp_res, buf.work, stream=stream,
+                      copy_streams=copy_streams)
+
+
+def pack_to_host(fill_batch, lengths, device, batch_genomes: int = 500,
+                 with_nmask: bool = False, pin: bool = True) -> L.HostGenomes:
+    """Build a packed collection in (pinned) host memory without holding it
+    all on the GPU: ``fill_batch(ids)`` returns (ascii, ascii_off) device
+    tensors for genome ids ``ids``; each batch is packed on the GPU and its
+    words copied to their place in the host layout."""
+    import torch
+
+    lengths = np.asarray(lengths, dtype=np.int64)
+    word_off = L.ah_pack_layout(lengths)
+    W = int(word_off[-1])
+    words = torch.empty(2 * max(W, 1), dtype=torch.int32, pin_memory=pin)
+    nmask = torch.empty(max(W, 1), dtype=torch.int32, pin_memory=pin) if with_nmask else None
+    for a in range(0, lengths.size, batch_genomes):
+        ids = np.arange(a, min(a + batch_genomes, lengths.size))
+        ascii, off = fill_batch(ids)
+        c, _ = pack(ascii, off, lengths[ids], with_nmask=with_nmask)
+        w0, w1 = int(word_off[ids[0]]), int(word_off[ids[-1] + 1])
+        assert int(c.word_off[-1].item()) == w1 - w0  # same per-genome layout
+        words[2 * w0: 2 * w1].copy_(c.words[: 2 * (w1 - w0)])
+        if with_nmask:
+            nmask[w0:w1].copy_(c.nmask[: w1 - w0])
+        del ascii, off, c
+    torch.cuda.synchronize(device)
+    return L.HostGenomes(words, word_off, lengths, nmask)
+
+
+def to_device(hg: L.HostGenomes, device) -> PackedCollection:
+    """Copy a host-resident packed collection into HBM (the resident form)."""
+    import torch
+
+    words = hg.words.to(device)
+    nmask = hg.nmask.to(device) if hg.nmask is not None else None
+    d_off = torch.from_numpy(hg.word_off.view(np.int64)).to(device)
+    d_len = torch.from_numpy(np.maximum(hg.len, 0).astype(np.int32)).to(device) if hg.n else \
+        torch.zeros(1, dtype=torch.int32, device=device)
+    lens = hg.len.astype(np.int64)
+    return PackedCollection(words, nmask, d_off, d_len, hg.n, int(lens.max()) if hg.n else 1,
+                            int(lens.sum()), lens)
