@@ -43,7 +43,8 @@ typedef enum ah_status {
   AH_ERR_OVERFLOW = -4,       /* (device) more records than the output capacity */
   AH_ERR_WORKSPACE = -5,      /* workspace smaller than the *_workspace_bytes query */
   AH_ERR_HIP = -6,            /* a HIP runtime call failed */
-  AH_ERR_JIT = -7             /* specialising the scan kernel failed */
+  AH_ERR_JIT = -7,            /* specialising the scan kernel failed */
+  AH_ERR_AGAIN = -8           /* nothing to return yet (server wait timed out) */
 } ah_status;
 
 enum {
@@ -68,11 +69,16 @@ enum { AH_FR = 0, AH_RF = 1, AH_FF = 2, AH_RR = 3 };
  * both planes).  Positions >= n read as A and are never reported.  `nmask`,
  * when not NULL, holds one uint32 per word with bit b set iff that base was
  * not A/C/G/T (such bases match no primer position).
+ *
+ * ah_scan_primers and ah_tm read word_off[g] and len[g] for g < n only, so a
+ * view of any subset of a packed collection (words and nmask shared,
+ * word_off and len gathered for the chosen genomes, in any order) is valid
+ * for them; hits then name genomes by their index in the view.
  * ------------------------------------------------------------------------- */
 typedef struct ah_genomes {
   const uint32_t* words;    /* device, 2 uint32 per word                        */
   const uint32_t* nmask;    /* device, 1 uint32 per word, or NULL              */
-  const uint64_t* word_off; /* device, [n + 1]                                  */
+  const uint64_t* word_off; /* device, [n + 1]; word_off[g] = first word of g   */
   const uint32_t* len;      /* device, [n] bases per genome                    */
   uint32_t n;               /* host: number of genomes                         */
   uint32_t max_len;         /* host: an upper bound on every len[g] (>= 1)     */
@@ -311,6 +317,106 @@ ah_status ah_stream_query(const ah_host_genomes* genomes, const ah_stream_config
                           ah_result* d_hit_res, ah_amplicon* d_amp, uint64_t amp_capacity,
                           ah_result* d_amp_res, void* d_work, size_t work_bytes, void* stream,
                           void* const* copy_streams, uint32_t n_copy_streams);
+
+/* ---------------------------------------------------------------------------
+ * Serving form: a request loop over a collection resident in HBM, in the
+ * spirit of the paper's web server answering primer-pair queries against
+ * fixed reference databases (Section 2.2, Performance Optimization) and of the
+ * planned searches over subsets of those databases (Section 4).  Jobs (one
+ * primer pair over a subset of the resident genomes) are admitted as they
+ * arrive: each job is split into parts
+ * of whole genomes; lane threads, each driving its own device stream, take the
+ * next part of the active jobs in turn, so parts of different jobs run on the
+ * device at the same time and a job that arrives while others run starts as
+ * soon as a lane and memory are free.  Every part's device buffers are carved
+ * from a caller-given device pool (the HBM budget) while it runs: a part is
+ * started only when its buffers fit, and its records are copied to host
+ * memory when it ends, so the pool only ever holds running parts (admission
+ * cannot deadlock).  Capacities come from the pair's expected random-site
+ * rate; a part that overflows is run again with the exact counts, so results
+ * never depend on the estimate, on the mix of other jobs or on the lane that
+ * ran them.
+ * ------------------------------------------------------------------------- */
+typedef struct ah_server ah_server;
+
+typedef struct ah_server_config {
+  uint32_t n_lanes;       /* device streams, each driven by a host thread (1..16) */
+  uint32_t n_compilers;   /* host threads that specialise scan kernels for new pairs (1..32) */
+  uint64_t part_bases;    /* bases per part at most (whole genomes; >= 1) */
+  uint64_t max_part_hits; /* parts are also cut so that their expected sites stay below this */
+  double capacity_scale;  /* capacity = scale x expected records + a per-genome reserve */
+} ah_server_config;
+
+/* One request.  Strings and the genome list are copied at submission. */
+typedef struct ah_job {
+  ah_primer_pair pair;
+  ah_window window;
+  ah_tm_params tm;
+  const uint32_t* genomes; /* host, strictly ascending ids into the resident collection, or NULL = all */
+  uint32_t n_genomes;
+  uint32_t reserved;       /* 0 */
+} ah_job;
+
+/* A finished job.  Times are seconds on the server's clock (ah_server_now). */
+typedef struct ah_job_status {
+  uint64_t job;
+  int32_t status;          /* AH_OK or the error that ended the job */
+  uint32_t n_parts;
+  uint64_t hits;           /* sites, all parts */
+  uint64_t amplicons;      /* all parts */
+  uint64_t bases;          /* bases of the job's genomes */
+  double t_submit, t_ready, t_start, t_done; /* ready: kernel compiled; start: first part on a lane */
+  uint32_t retries;        /* parts run again after an overflow */
+  uint32_t reserved;
+} ah_job_status;
+
+/* Output of one part (host memory owned by the server, valid until the job is
+ * released).  Genome ids are ids of the resident collection; plus_hit and
+ * minus_hit index this part's hits.  The parts of a job cover its genomes in
+ * ascending order, so their concatenation is the job's canonical output. */
+typedef struct ah_job_part {
+  const ah_hit* hits;
+  uint64_t n_hits;
+  const ah_amplicon* amplicons;
+  uint64_t n_amplicons;
+  uint32_t first_genome;   /* index into the job's genome list */
+  uint32_t n_genomes;
+} ah_job_part;
+
+typedef struct ah_server_stats {
+  uint64_t jobs_submitted, jobs_finished, parts_run, retries;
+  uint64_t pool_bytes, pool_in_use, pool_high_water;
+  uint64_t admission_waits; /* times a lane found the next part's buffers not fitting yet */
+                            /* pool_in_use / pool_high_water: device bytes of running parts */
+  double lane_busy_s;       /* summed over lanes: time from a part's launch to its completion */
+} ah_server_stats;
+
+/* Start a server on the current device over `resident` (device views stay
+ * borrowed until ah_server_destroy; h_len: host copy of the genome lengths,
+ * copied; resident->word_off must hold the n + 1 offsets of ah_pack_layout).
+ * d_pool / pool_bytes: device memory that the server carves all per-part
+ * buffers from (caller-owned; no other device memory is allocated per job
+ * apart from small per-pair tables cached by ah_tm / ah_pair_amplicons).  A
+ * part that needs more than the whole pool ends its job with AH_ERR_LIMIT.
+ * Errors: AH_ERR_INVALID_ARG, AH_ERR_HIP. */
+ah_status ah_server_create(const ah_genomes* resident, const uint32_t* h_len,
+                           const ah_server_config* cfg, void* d_pool, size_t pool_bytes,
+                           ah_server** server);
+/* Queue a job; returns at once with its id.  Errors: AH_ERR_INVALID_ARG (bad
+ * genome list or window), AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT. */
+ah_status ah_server_submit(ah_server* server, const ah_job* job, uint64_t* job_id);
+/* Wait up to timeout_s for the next finished job (in order of completion);
+ * AH_ERR_AGAIN if none finished in time. */
+ah_status ah_server_wait(ah_server* server, double timeout_s, ah_job_status* status);
+/* Output of part `part` of a finished job. */
+ah_status ah_server_part(ah_server* server, uint64_t job_id, uint32_t part, ah_job_part* out);
+/* Drop a finished job and its records; its part pointers become invalid. */
+ah_status ah_server_release(ah_server* server, uint64_t job_id);
+void ah_server_stats_get(ah_server* server, ah_server_stats* stats);
+double ah_server_now(ah_server* server);
+/* Stop accepting parts, let the lanes finish the parts they run, join every
+ * thread and free the server (jobs not finished are dropped). */
+void ah_server_destroy(ah_server* server);
 
 /* ---------------------------------------------------------------------------
  * Utilities.

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libah.so")
 
 AH_OK, AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT = 0, -1, -2, -3
-AH_ERR_OVERFLOW, AH_ERR_WORKSPACE, AH_ERR_HIP, AH_ERR_JIT = -4, -5, -6, -7
+AH_ERR_OVERFLOW, AH_ERR_WORKSPACE, AH_ERR_HIP, AH_ERR_JIT, AH_ERR_AGAIN = -4, -5, -6, -7, -8
 AH_FR, AH_RF, AH_FF, AH_RR = 0, 1, 2, 3
 HALO_WORDS = 31
 
@@ -77,6 +77,39 @@ class ah_stream_config(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class ah_server_config(ctypes.Structure):
+    _fields_ = [("n_lanes", ctypes.c_uint32), ("n_compilers", ctypes.c_uint32),
+                ("part_bases", ctypes.c_uint64), ("max_part_hits", ctypes.c_uint64),
+                ("capacity_scale", ctypes.c_double)]
+
+
+class ah_job(ctypes.Structure):
+    _fields_ = [("pair", ah_primer_pair), ("window", ah_window), ("tm", ah_tm_params),
+                ("genomes", ctypes.c_void_p), ("n_genomes", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ah_job_status(ctypes.Structure):
+    _fields_ = [("job", ctypes.c_uint64), ("status", ctypes.c_int32), ("n_parts", ctypes.c_uint32),
+                ("hits", ctypes.c_uint64), ("amplicons", ctypes.c_uint64),
+                ("bases", ctypes.c_uint64), ("t_submit", ctypes.c_double),
+                ("t_ready", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("retries", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ah_job_part(ctypes.Structure):
+    _fields_ = [("hits", ctypes.c_void_p), ("n_hits", ctypes.c_uint64),
+                ("amplicons", ctypes.c_void_p), ("n_amplicons", ctypes.c_uint64),
+                ("first_genome", ctypes.c_uint32), ("n_genomes", ctypes.c_uint32)]
+
+
+class ah_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "jobs_submitted", "jobs_finished", "parts_run", "retries", "pool_bytes", "pool_in_use",
+        "pool_high_water", "admission_waits")] + [("lane_busy_s", ctypes.c_double)]
+
+
 # Every symbol declared in include/ah.h and include/ah_dev.h.
 EXPORTS = (
     "ah_pack_layout", "ah_pack_genomes", "ah_scan_primers", "ah_scan_workspace_bytes", "ah_tm",
@@ -84,7 +117,9 @@ EXPORTS = (
     "ah_release_caches", "ah_jit_stats", "ah_validate_pairs", "ah_scan_program_source",
     "ah_scan_program_compile", "ah_profile_enable", "ah_profile_reset", "ah_profile_query",
     "ah_autotune_scan", "ah_set_scan_tuning", "ah_get_scan_tuning", "ah_scan_prepare",
-    "ah_stream_workspace_bytes", "ah_stream_query",
+    "ah_stream_workspace_bytes", "ah_stream_query", "ah_server_create", "ah_server_submit",
+    "ah_server_wait", "ah_server_part", "ah_server_release", "ah_server_stats_get",
+    "ah_server_now", "ah_server_destroy",
 )
 
 _lib = None
@@ -150,6 +185,22 @@ def lib() -> ctypes.CDLL:
                                   P(ah_window), u32, P(ah_tm_params), vp, u64, vp, vp, u64, vp, vp,
                                   sz, vp, P(vp), u32]
     L.ah_stream_query.restype = st
+    L.ah_server_create.argtypes = [P(ah_genomes), vp, P(ah_server_config), vp, sz, P(vp)]
+    L.ah_server_create.restype = st
+    L.ah_server_submit.argtypes = [vp, P(ah_job), P(ctypes.c_uint64)]
+    L.ah_server_submit.restype = st
+    L.ah_server_wait.argtypes = [vp, ctypes.c_double, P(ah_job_status)]
+    L.ah_server_wait.restype = st
+    L.ah_server_part.argtypes = [vp, u64, u32, P(ah_job_part)]
+    L.ah_server_part.restype = st
+    L.ah_server_release.argtypes = [vp, u64]
+    L.ah_server_release.restype = st
+    L.ah_server_stats_get.argtypes = [vp, P(ah_server_stats)]
+    L.ah_server_stats_get.restype = None
+    L.ah_server_now.argtypes = [vp]
+    L.ah_server_now.restype = ctypes.c_double
+    L.ah_server_destroy.argtypes = [vp]
+    L.ah_server_destroy.restype = None
     _lib = L
     return L
 
@@ -388,3 +439,71 @@ def ah_stream_query(hg: HostGenomes, cfg: ah_stream_config, pairs, wins, params:
                                  _ptr(amp), int(amp_capacity), _ptr(amp_res), _ptr(work),
                                  0 if work is None else work.numel(), _stream(stream), cs,
                                  len(copy_streams)), "ah_stream_query")
+
+
+def server_config(n_lanes: int = 4, n_compilers: int = 8, part_bases: int = 1 << 32,
+                  max_part_hits: int = 1 << 25, capacity_scale: float = 2.0) -> ah_server_config:
+    return ah_server_config(int(n_lanes), int(n_compilers), int(part_bases), int(max_part_hits),
+                            float(capacity_scale))
+
+
+def ah_server_create(genomes: ah_genomes, lengths, cfg: ah_server_config, pool) -> int:
+    lens = np.ascontiguousarray(lengths, dtype=np.uint32)
+    out = ctypes.c_void_p()
+    _check(lib().ah_server_create(ctypes.byref(genomes), lens.ctypes.data if lens.size else None,
+                                  ctypes.byref(cfg), _ptr(pool), pool.numel(), ctypes.byref(out)),
+           "ah_server_create")
+    return int(out.value)
+
+
+def ah_server_submit(server: int, pair, genomes=None, tm: Optional[ah_tm_params] = None,
+                     filter_tm: bool = False, min_tm: float = 50.0) -> int:
+    job = ah_job()
+    f, r = pair.fwd.encode(), pair.rev.encode()
+    job.pair = ah_primer_pair(f, r, int(pair.k), int(pair.clamp))
+    job.window = ah_window(int(pair.min_len), int(pair.max_len), 1 if filter_tm else 0,
+                           float(min_tm))
+    job.tm = tm if tm is not None else tm_params()
+    ids = None
+    if genomes is not None:
+        ids = np.ascontiguousarray(genomes, dtype=np.uint32)
+        job.genomes = ids.ctypes.data if ids.size else None
+        job.n_genomes = ids.size
+        if not ids.size:  # an empty list, not "all genomes"
+            job.genomes = ctypes.cast(ctypes.pointer(ctypes.c_uint32(0)), ctypes.c_void_p).value
+    jid = ctypes.c_uint64()
+    _check(lib().ah_server_submit(server, ctypes.byref(job), ctypes.byref(jid)), "ah_server_submit")
+    return int(jid.value)
+
+
+def ah_server_wait(server: int, timeout_s: float) -> Optional[dict]:
+    st = ah_job_status()
+    rc = lib().ah_server_wait(server, float(timeout_s), ctypes.byref(st))
+    if rc == AH_ERR_AGAIN:
+        return None
+    _check(rc, "ah_server_wait")
+    return {name: getattr(st, name) for name, _ in ah_job_status._fields_ if name != "reserved"}
+
+
+def ah_server_part(server: int, job: int, part: int) -> ah_job_part:
+    out = ah_job_part()
+    _check(lib().ah_server_part(server, int(job), int(part), ctypes.byref(out)), "ah_server_part")
+    return out
+
+
+def ah_server_release(server: int, job: int):
+    _check(lib().ah_server_release(server, int(job)), "ah_server_release")
+
+
+def ah_server_stats_get(server: int) -> dict:
+    st = ah_server_stats()
+    lib().ah_server_stats_get(server, ctypes.byref(st))
+    return {name: getattr(st, name) for name, _ in ah_server_stats._fields_}
+
+
+def ah_server_now(server: int) -> float:
+    return float(lib().ah_server_now(server))
+
+
+def ah_server_destroy(server: int):
+    lib().ah_server_destroy(server)

@@ -96,7 +96,7 @@ def build(verbose: bool = False) -> str:
           "-c", sample, "-o",
           os.path.join(BUILD, "scan_core_check.o")])
     objs = []
-    for name in ("ah_kernels.hip", "ah_host.cpp", "ah_stream.cpp"):
+    for name in ("ah_kernels.hip", "ah_host.cpp", "ah_stream.cpp", "ah_serve.cpp"):
         src = os.path.join(CSRC, name)
         obj = os.path.join(BUILD, name + ".o")
         lang = ["-x", "hip"] if name.endswith(".hip") else []

@@ -763,6 +763,7 @@ const char* ah_status_str(int s) {
     case AH_ERR_WORKSPACE: return "workspace too small";
     case AH_ERR_HIP: return "HIP error";
     case AH_ERR_JIT: return "scan specialisation failed";
+    case AH_ERR_AGAIN: return "not ready";
     default: return "unknown status";
   }
 }

@@ -96,6 +96,14 @@ hipError_t launch_rebase(const uint64_t* off, uint32_t n, uint64_t* out, hipStre
 hipError_t launch_stream_fixup(ah_hit* hits, uint64_t nh, ah_amplicon* amp, uint64_t na,
                                uint32_t gbase, uint32_t hbase, int grid, hipStream_t st);
 
+// Serving: a gathered view of genomes ids[0..n) of a packed collection
+// (out_off [n + 1], out_len [n]), and view index -> collection id on a part's
+// records (counts read from the device results).
+hipError_t launch_gather_view(const uint32_t* ids, uint32_t n, const uint64_t* off, const uint32_t* len,
+                              uint64_t* out_off, uint32_t* out_len, hipStream_t st);
+hipError_t launch_remap(ah_hit* hits, const ah_result* hres, ah_amplicon* amp, const ah_result* ares,
+                        const uint32_t* ids, int grid, hipStream_t st);
+
 // Error reporting shared by the host sources: records the message returned by
 // ah_last_error() on this thread and returns s.
 ah_status set_error(ah_status s, const char* fmt, ...);

@@ -583,6 +583,36 @@ __global__ __launch_bounds__(kBlock) void k_stream_fixup(ah_hit* __restrict__ hi
   }
 }
 
+// ---- serving: subset views and id remapping ------------------------------
+// View of genomes ids[0..n) of a packed collection: their word offsets and
+// lengths gathered (out_off[n] = end of the last genome's words, for tidiness;
+// the scan and Tm read only the first n).
+__global__ void k_gather_view(const u32* __restrict__ ids, u32 n, const u64* __restrict__ off,
+                              const u32* __restrict__ len, u64* __restrict__ out_off,
+                              u32* __restrict__ out_len) {
+  for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const u32 g = ids[i];
+    out_off[i] = off[g];
+    out_len[i] = len[g];
+    if (i + 1 == n) out_off[n] = off[g + 1];
+  }
+}
+
+// View indices to collection ids on a part's hits and amplicons; the record
+// counts are read from the device results (count = records written).
+__global__ __launch_bounds__(kBlock) void k_remap(ah_hit* __restrict__ hits,
+                                                  const ah_result* __restrict__ hres,
+                                                  ah_amplicon* __restrict__ amp,
+                                                  const ah_result* __restrict__ ares,
+                                                  const u32* __restrict__ ids) {
+  const u64 nh = hres->count, na = ares->count;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += stride)
+    hits[i].genome = ids[hits[i].genome];
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < na; i += stride)
+    amp[i].genome = ids[amp[i].genome];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------- launchers ----
@@ -696,6 +726,21 @@ hipError_t launch_stream_fixup(ah_hit* hits, uint64_t nh, ah_amplicon* amp, uint
                                uint32_t gbase, uint32_t hbase, int grid, hipStream_t st) {
   if (nh == 0 && na == 0) return hipSuccess;
   k_stream_fixup<<<grid, kBlock, 0, st>>>(hits, nh, amp, na, gbase, hbase);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_view(const uint32_t* ids, uint32_t n, const uint64_t* off, const uint32_t* len,
+                              uint64_t* out_off, uint32_t* out_len, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint64_t blocks = ((uint64_t)n + kBlock - 1) / kBlock;
+  const unsigned grid = blocks > 1024 ? 1024u : (unsigned)blocks;
+  k_gather_view<<<grid, kBlock, 0, st>>>(ids, n, (const u64*)off, len, (u64*)out_off, out_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_remap(ah_hit* hits, const ah_result* hres, ah_amplicon* amp, const ah_result* ares,
+                        const uint32_t* ids, int grid, hipStream_t st) {
+  k_remap<<<grid, kBlock, 0, st>>>(hits, hres, amp, ares, ids);
   return hipGetLastError();
 }
 

@@ -1,0 +1,601 @@
+// Serving runtime of libah: a request loop over a packed collection resident
+// in HBM.  Jobs (one primer pair over a subset of the genomes) are split into
+// parts of whole genomes; compile threads specialise each new pair's scan
+// kernel off the request path; lane threads, each driving its own device
+// stream, take the next part of the active jobs in round-robin order, carve
+// the part's buffers from the caller's pool (the HBM budget), run gather ->
+// scan -> Tm -> pairing -> remap on their stream, wait for it and copy the
+// part's records to host memory (through a pinned staging buffer per lane).
+// Pool memory is held only while a part is in flight, so every admitted part
+// completes and frees it: admission by memory cannot deadlock.  Parts of
+// several jobs are in flight on the device together, and a new job starts as
+// soon as a lane and pool memory are free.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ah.h"
+#include "ah_dev.h"
+#include "ah_internal.h"
+
+namespace {
+
+#define AH_HIP(call)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return ah::set_error(AH_ERR_HIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                           __LINE__);                                                        \
+  } while (0)
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Members of an IUPAC code (0 for anything else; primers are validated first).
+int code_size(char c) {
+  switch (c | 0x20) {
+    case 'a': case 'c': case 'g': case 't': return 1;
+    case 'r': case 'y': case 's': case 'w': case 'k': case 'm': return 2;
+    case 'b': case 'd': case 'h': case 'v': return 3;
+    case 'n': return 4;
+    default: return 0;
+  }
+}
+
+// Chance that a window of independent uniform bases is a site of `primer` on
+// one strand: the clamp positions match and at most k others mismatch.  Used
+// only to size buffers; a part that overflows is run again with exact counts.
+double site_probability(const std::string& primer, uint32_t k, uint32_t clamp) {
+  const int L = (int)primer.size();
+  const int free_len = L - (int)std::min<uint32_t>(clamp, (uint32_t)L);
+  std::vector<double> d(L + 2, 0.0);
+  d[0] = 1.0;
+  for (int j = 0; j < free_len; ++j) {
+    const double p = code_size(primer[j]) / 4.0;
+    for (int m = j + 1; m >= 1; --m) d[m] = d[m] * p + d[m - 1] * (1.0 - p);
+    d[0] *= p;
+  }
+  double pk = 0.0;
+  for (int m = 0; m <= (int)k && m <= L; ++m) pk += d[m];
+  for (int j = free_len; j < L; ++j) pk *= code_size(primer[j]) / 4.0;
+  return pk;
+}
+
+// First-fit allocator over the caller's pool (offsets; 256-byte granules).
+class Pool {
+ public:
+  explicit Pool(uint64_t bytes) : bytes_(bytes) {
+    if (bytes) free_[0] = bytes;
+  }
+  bool alloc(uint64_t size, uint64_t* off) {
+    size = align256(std::max<uint64_t>(size, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < size) continue;
+      *off = it->first;
+      const uint64_t rest = it->second - size, next = it->first + size;
+      free_.erase(it);
+      if (rest) free_[next] = rest;
+      in_use_ += size;
+      high_ = std::max(high_, in_use_);
+      return true;
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t size) {
+    size = align256(std::max<uint64_t>(size, 1));
+    in_use_ -= size;
+    auto it = free_.emplace(off, size).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  uint64_t bytes() const { return bytes_; }
+  uint64_t in_use() const { return in_use_; }
+  uint64_t high() const { return high_; }
+
+ private:
+  uint64_t bytes_, in_use_ = 0, high_ = 0;
+  std::map<uint64_t, uint64_t> free_;
+};
+
+struct Part {
+  uint32_t g0 = 0, g1 = 0;  // indices into the job's genome list
+  uint64_t bases = 0;
+  uint32_t max_len = 1;
+  uint64_t hcap = 0, acap = 0;
+  std::vector<ah_hit> hits;            // host copies of the part's records
+  std::vector<ah_amplicon> amps;
+  bool done = false;
+};
+
+struct Job {
+  uint64_t id = 0;
+  std::string fwd, rev;
+  ah_primer_pair pair{};
+  ah_window win{};
+  ah_tm_params tm{};
+  std::vector<uint32_t> ids;
+  std::vector<Part> parts;
+  size_t next = 0;                 // next part never dispatched
+  std::deque<uint32_t> redo;       // parts to run again with exact capacities
+  uint32_t done_parts = 0, in_flight = 0, retries = 0;
+  int32_t status = AH_OK;
+  bool queued = false, finished = false;
+  double t_submit = 0, t_ready = -1, t_start = -1, t_done = -1;
+  uint64_t bases = 0, hits = 0, amps = 0;
+  bool has_work() const { return status == AH_OK && (next < parts.size() || !redo.empty()); }
+};
+
+// Byte sizes of a part's device buffers (one pool block while it runs).
+struct PartSizes {
+  uint64_t total, res, hits, amps, ids, off, len, scan_ws, pair_ws;
+};
+
+PartSizes part_sizes(const Part& p) {
+  PartSizes s{};
+  const uint32_t n = p.g1 - p.g0;
+  s.res = align256(2 * sizeof(ah_result));
+  s.hits = align256(p.hcap * sizeof(ah_hit));
+  s.amps = align256(p.acap * sizeof(ah_amplicon));
+  s.ids = align256((uint64_t)n * 4);
+  s.off = align256(((uint64_t)n + 1) * 8);
+  s.len = align256((uint64_t)n * 4);
+  ah_genomes probe{};
+  probe.n = n;
+  s.scan_ws = align256(ah_scan_workspace_bytes(&probe, 1, p.hcap));
+  s.pair_ws = align256(ah_pair_workspace_bytes(p.hcap, 1));
+  s.total = s.res + s.hits + s.amps + s.ids + s.off + s.len + s.scan_ws + s.pair_ws;
+  return s;
+}
+
+}  // namespace
+
+struct ah_server {
+  ah_genomes res{};
+  std::vector<uint32_t> len;
+  ah_server_config cfg{};
+  uintptr_t base = 0;
+  int dev = 0;
+  Pool pool{0};
+  std::chrono::steady_clock::time_point t0;
+
+  std::mutex mu;
+  std::condition_variable cv_lane, cv_done, cv_compile;
+  bool stop = false;
+  uint64_t next_id = 1;
+  std::unordered_map<uint64_t, std::unique_ptr<Job>> jobs;
+  std::deque<uint64_t> active;     // jobs with parts to dispatch, round robin
+  std::deque<uint64_t> compile_q;  // jobs whose kernel is not ready yet
+  std::deque<uint64_t> finished_q; // finished, not yet returned by wait
+  ah_server_stats stats{};
+  std::vector<std::thread> threads;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  // Called with mu held.
+  void finish(Job& j) {
+    if (j.finished) return;
+    j.finished = true;
+    if (j.queued) {  // a failed job may still sit in the round robin
+      active.erase(std::remove(active.begin(), active.end(), j.id), active.end());
+      j.queued = false;
+    }
+    j.t_done = now();
+    finished_q.push_back(j.id);
+    stats.jobs_finished++;
+    cv_done.notify_all();
+  }
+
+  void compile_loop() {
+    (void)hipSetDevice(dev);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv_compile.wait(lk, [&] { return stop || !compile_q.empty(); });
+      if (stop) return;
+      const uint64_t id = compile_q.front();
+      compile_q.pop_front();
+      Job* j = jobs.at(id).get();
+      lk.unlock();
+      const ah_status s = ah_scan_prepare(&j->pair, 1, res.nmask != nullptr);
+      lk.lock();
+      j->t_ready = now();
+      if (s != AH_OK) {
+        j->status = s;
+        finish(*j);
+        continue;
+      }
+      if (j->has_work()) {
+        j->queued = true;
+        active.push_back(id);
+        cv_lane.notify_all();
+      } else {
+        finish(*j);
+      }
+    }
+  }
+
+  // Runs part p of job j on `st` in the pool block at `blk`; hr[0..1] get the
+  // part's results; when both fit, the records are copied to p.hits / p.amps
+  // through the lane's pinned staging buffer.
+  ah_status run_part(Job& j, Part& p, const PartSizes& z, uint64_t blk, hipStream_t st,
+                     ah_result* hr, void*& stage, size_t& stage_bytes) {
+    const uint32_t n = p.g1 - p.g0;
+    uintptr_t q = base + blk;
+    ah_result* d_res = (ah_result*)q;
+    ah_hit* hits = (ah_hit*)(q += z.res);
+    ah_amplicon* amps = (ah_amplicon*)(q += z.hits);
+    uint32_t* ids = (uint32_t*)(q += z.amps);
+    uint64_t* off = (uint64_t*)(q += z.ids);
+    uint32_t* len_v = (uint32_t*)(q += z.off);
+    void* scan_ws = (void*)(q += z.len);
+    void* pair_ws = (void*)(q += z.scan_ws);
+    AH_HIP(hipMemcpyAsync(ids, j.ids.data() + p.g0, (size_t)n * 4, hipMemcpyHostToDevice, st));
+    AH_HIP(ah::launch_gather_view(ids, n, res.word_off, res.len, off, len_v, st));
+    ah_genomes view = res;
+    view.word_off = off;
+    view.len = len_v;
+    view.n = n;
+    view.max_len = std::max<uint32_t>(p.max_len, 1);
+    ah_status s = ah_scan_primers(&view, &j.pair, 1, hits, p.hcap, &d_res[0], scan_ws, z.scan_ws, st);
+    if (s) return s;
+    s = ah_tm(&view, &j.pair, 1, &j.tm, hits, &d_res[0], p.hcap, st);
+    if (s) return s;
+    s = ah_pair_amplicons(hits, &d_res[0], p.hcap, &j.pair, &j.win, 1, amps, p.acap, &d_res[1],
+                          pair_ws, z.pair_ws, st);
+    if (s) return s;
+    AH_HIP(ah::launch_remap(hits, &d_res[0], amps, &d_res[1], ids, ah::cu_count_current() * 4, st));
+    AH_HIP(hipMemcpyAsync(hr, d_res, 2 * sizeof(ah_result), hipMemcpyDeviceToHost, st));
+    AH_HIP(hipStreamSynchronize(st));
+    if (hr[0].status != AH_OK || hr[1].status != AH_OK) return AH_OK;  // run again
+    const size_t hb = hr[0].count * sizeof(ah_hit), ab = hr[1].count * sizeof(ah_amplicon);
+    if (hb + ab > stage_bytes) {
+      const size_t want = std::max<size_t>(hb + ab, 2 * stage_bytes + (1u << 20));
+      if (stage) AH_HIP(hipHostFree(stage));
+      stage = nullptr;
+      stage_bytes = 0;
+      AH_HIP(hipHostMalloc(&stage, want, hipHostMallocDefault));
+      stage_bytes = want;
+    }
+    if (hb) AH_HIP(hipMemcpyAsync(stage, hits, hb, hipMemcpyDeviceToHost, st));
+    if (ab) AH_HIP(hipMemcpyAsync((char*)stage + hb, amps, ab, hipMemcpyDeviceToHost, st));
+    AH_HIP(hipStreamSynchronize(st));
+    p.hits.assign((const ah_hit*)stage, (const ah_hit*)stage + hr[0].count);
+    p.amps.assign((const ah_amplicon*)((char*)stage + hb),
+                  (const ah_amplicon*)((char*)stage + hb) + hr[1].count);
+    return AH_OK;
+  }
+
+  void lane_loop() {
+    (void)hipSetDevice(dev);
+    hipStream_t st = nullptr;
+    void* stage = nullptr;  // pinned staging for the device -> host record copies
+    size_t stage_bytes = 0;
+    const hipError_t ce = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    std::unique_lock<std::mutex> lk(mu);
+    if (ce != hipSuccess) return;
+    for (;;) {
+      // the next part: the job at the front of the round robin, once its
+      // buffers fit in the pool
+      Job* j = nullptr;
+      uint32_t pi = 0;
+      uint64_t blk = 0;
+      PartSizes z{};
+      while (!stop) {
+        if (active.empty()) {
+          cv_lane.wait(lk);
+          continue;
+        }
+        Job* cand = jobs.at(active.front()).get();
+        if (!cand->has_work()) {  // failed meanwhile, or nothing left to start
+          cand->queued = false;
+          active.pop_front();
+          if (cand->in_flight == 0 &&
+              (cand->status != AH_OK || cand->done_parts == cand->parts.size()))
+            finish(*cand);
+          continue;
+        }
+        const uint32_t cpi = cand->redo.empty() ? (uint32_t)cand->next : cand->redo.front();
+        z = part_sizes(cand->parts[cpi]);
+        if (z.total > pool.bytes()) {
+          cand->status = ah::set_error(AH_ERR_LIMIT, "a part needs %llu bytes > pool %llu",
+                                       (unsigned long long)z.total,
+                                       (unsigned long long)pool.bytes());
+          continue;  // dropped on the next pass
+        }
+        if (pool.alloc(z.total, &blk)) {
+          j = cand;
+          pi = cpi;
+          break;
+        }
+        stats.admission_waits++;
+        cv_lane.wait(lk);  // a finished part frees pool memory
+      }
+      if (stop) break;
+      active.pop_front();
+      if (!j->redo.empty() && j->redo.front() == pi) j->redo.pop_front();
+      else j->next++;
+      j->in_flight++;
+      if (j->t_start < 0) j->t_start = now();
+      if (j->has_work()) active.push_back(j->id);
+      else j->queued = false;
+      Part& p = j->parts[pi];
+      stats.parts_run++;
+      lk.unlock();
+
+      const double t_run = now();
+      ah_result hr[2] = {};
+      const ah_status s = run_part(*j, p, z, blk, st, hr, stage, stage_bytes);
+
+      lk.lock();
+      stats.lane_busy_s += now() - t_run;
+      pool.release(blk, z.total);
+      j->in_flight--;
+      if (s != AH_OK) {
+        if (j->status == AH_OK) j->status = s;
+      } else if (hr[0].status != AH_OK || hr[1].status != AH_OK) {
+        // the exact counts are known now: run the part again with them
+        if (hr[0].required >= 0xffffffffull) {
+          if (j->status == AH_OK)
+            j->status = ah::set_error(AH_ERR_LIMIT, "a part of job %llu has %llu sites",
+                                      (unsigned long long)j->id,
+                                      (unsigned long long)hr[0].required);
+        } else {
+          p.hcap = std::max<uint64_t>(p.hcap, hr[0].required);
+          p.acap = std::max<uint64_t>(p.acap, hr[1].required);
+          j->redo.push_back(pi);
+          j->retries++;
+          stats.retries++;
+          if (!j->queued) {
+            j->queued = true;
+            active.push_back(j->id);
+          }
+        }
+      } else {
+        p.done = true;
+        j->done_parts++;
+        j->hits += p.hits.size();
+        j->amps += p.amps.size();
+      }
+      if (j->in_flight == 0 && (j->status != AH_OK || j->done_parts == j->parts.size())) {
+        if (j->status != AH_OK)
+          for (Part& q : j->parts) {  // a failed job returns no records
+            std::vector<ah_hit>().swap(q.hits);
+            std::vector<ah_amplicon>().swap(q.amps);
+            q.done = false;
+          }
+        finish(*j);
+      }
+      cv_lane.notify_all();
+    }
+    lk.unlock();
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (stage) (void)hipHostFree(stage);
+  }
+};
+
+extern "C" {
+
+ah_status ah_server_create(const ah_genomes* resident, const uint32_t* h_len,
+                           const ah_server_config* cfg, void* d_pool, size_t pool_bytes,
+                           ah_server** out) {
+  ah::clear_error();
+  if (!resident || !cfg || !out || (resident->n > 0 && !h_len))
+    return ah::set_error(AH_ERR_INVALID_ARG, "resident, h_len, cfg and out are required");
+  if (resident->n > 0 && (!resident->words || !resident->word_off || !resident->len))
+    return ah::set_error(AH_ERR_INVALID_ARG, "resident: words, word_off and len are required");
+  if (cfg->n_lanes < 1 || cfg->n_lanes > 16 || cfg->n_compilers < 1 || cfg->n_compilers > 32)
+    return ah::set_error(AH_ERR_INVALID_ARG, "n_lanes must be 1..16 and n_compilers 1..32");
+  if (cfg->part_bases == 0 || cfg->max_part_hits == 0 || !(cfg->capacity_scale >= 0.0))
+    return ah::set_error(AH_ERR_INVALID_ARG, "part_bases and max_part_hits must be >= 1, "
+                         "capacity_scale >= 0");
+  if (!d_pool || pool_bytes < 4096)
+    return ah::set_error(AH_ERR_INVALID_ARG, "a device pool of at least 4 KiB is required");
+  auto s = std::make_unique<ah_server>();
+  AH_HIP(hipGetDevice(&s->dev));
+  s->res = *resident;
+  s->len.assign(h_len, h_len + resident->n);
+  s->cfg = *cfg;
+  s->base = ((uintptr_t)d_pool + 255) & ~(uintptr_t)255;
+  const uint64_t lost = s->base - (uintptr_t)d_pool;
+  s->pool = Pool((pool_bytes - lost) & ~255ull);
+  s->t0 = std::chrono::steady_clock::now();
+  s->stats.pool_bytes = s->pool.bytes();
+  ah_server* srv = s.get();
+  for (uint32_t i = 0; i < cfg->n_compilers; ++i)
+    s->threads.emplace_back([srv] { srv->compile_loop(); });
+  for (uint32_t i = 0; i < cfg->n_lanes; ++i) s->threads.emplace_back([srv] { srv->lane_loop(); });
+  *out = s.release();
+  return AH_OK;
+}
+
+ah_status ah_server_submit(ah_server* srv, const ah_job* job, uint64_t* job_id) {
+  ah::clear_error();
+  if (!srv || !job) return ah::set_error(AH_ERR_INVALID_ARG, "server and job are required");
+  ah_status st = ah_validate_pairs(&job->pair, 1);
+  if (st) return st;
+  if (job->window.min_len > job->window.max_len)
+    return ah::set_error(AH_ERR_INVALID_ARG, "window: min_len > max_len");
+  auto j = std::make_unique<Job>();
+  j->fwd = job->pair.fwd;
+  j->rev = job->pair.rev;
+  j->pair = job->pair;
+  j->pair.fwd = j->fwd.c_str();
+  j->pair.rev = j->rev.c_str();
+  j->win = job->window;
+  j->tm = job->tm;
+  const uint32_t N = srv->res.n;
+  if (job->genomes) {
+    j->ids.assign(job->genomes, job->genomes + job->n_genomes);
+    for (size_t i = 0; i < j->ids.size(); ++i)
+      if (j->ids[i] >= N || (i > 0 && j->ids[i] <= j->ids[i - 1]))
+        return ah::set_error(AH_ERR_INVALID_ARG, "genome list must be strictly ascending ids < %u",
+                             N);
+  } else {
+    j->ids.resize(N);
+    for (uint32_t g = 0; g < N; ++g) j->ids[g] = g;
+  }
+  // parts: whole genomes, at most part_bases bases and about max_part_hits
+  // expected sites each
+  const auto& cfg = srv->cfg;
+  const double rate = 2.0 * (site_probability(j->fwd, j->pair.k, j->pair.clamp) +
+                             site_probability(j->rev, j->pair.k, j->pair.clamp));
+  const double scale = cfg.capacity_scale;
+  double cut = (double)cfg.part_bases;
+  if (rate * scale > 0) cut = std::min(cut, (double)cfg.max_part_hits / (rate * scale));
+  const uint64_t part_bases = std::max<uint64_t>((uint64_t)cut, 1);
+  const double win = (double)j->win.max_len - (double)j->win.min_len + 1.0;
+  auto close = [&](Part& p) {
+    const uint32_t n = p.g1 - p.g0;
+    const double eh = scale * rate * (double)p.bases;
+    const double ea = scale * (rate / 2) * (rate / 2) * win * (double)p.bases;
+    p.hcap = std::min<uint64_t>((uint64_t)std::ceil(eh) + 16ull * n + 1024, 0xfffffffeull);
+    p.acap = (uint64_t)std::min(std::ceil(ea), 1e12) + 4ull * n + 256;
+    j->parts.push_back(p);
+  };
+  Part cur;
+  for (uint32_t i = 0; i < (uint32_t)j->ids.size(); ++i) {
+    const uint32_t L = srv->len[j->ids[i]];
+    if (cur.g1 > cur.g0 && cur.bases + L > part_bases) {
+      close(cur);
+      cur = Part();
+      cur.g0 = cur.g1 = i;
+    }
+    cur.g1 = i + 1;
+    cur.bases += L;
+    cur.max_len = std::max(cur.max_len, L);
+    j->bases += L;
+  }
+  if (cur.g1 > cur.g0) close(cur);
+
+  std::lock_guard<std::mutex> lk(srv->mu);
+  j->id = srv->next_id++;
+  j->t_submit = srv->now();
+  const uint64_t id = j->id;
+  Job* jp = j.get();
+  srv->jobs[id] = std::move(j);
+  srv->stats.jobs_submitted++;
+  if (jp->parts.empty()) {
+    jp->t_ready = jp->t_start = jp->t_submit;
+    srv->finish(*jp);
+  } else {
+    srv->compile_q.push_back(id);
+    srv->cv_compile.notify_one();
+  }
+  if (job_id) *job_id = id;
+  return AH_OK;
+}
+
+ah_status ah_server_wait(ah_server* srv, double timeout_s, ah_job_status* out) {
+  ah::clear_error();
+  if (!srv || !out) return ah::set_error(AH_ERR_INVALID_ARG, "server and status are required");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  const auto until = std::chrono::steady_clock::now() +
+                     std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                         std::chrono::duration<double>(std::max(timeout_s, 0.0)));
+  if (!srv->cv_done.wait_until(lk, until, [&] { return !srv->finished_q.empty(); }))
+    return AH_ERR_AGAIN;
+  const uint64_t id = srv->finished_q.front();
+  srv->finished_q.pop_front();
+  const Job& j = *srv->jobs.at(id);
+  *out = ah_job_status{};
+  out->job = id;
+  out->status = j.status;
+  out->n_parts = (uint32_t)j.parts.size();
+  out->hits = j.hits;
+  out->amplicons = j.amps;
+  out->bases = j.bases;
+  out->t_submit = j.t_submit;
+  out->t_ready = j.t_ready;
+  out->t_start = j.t_start;
+  out->t_done = j.t_done;
+  out->retries = j.retries;
+  return AH_OK;
+}
+
+ah_status ah_server_part(ah_server* srv, uint64_t job_id, uint32_t part, ah_job_part* out) {
+  ah::clear_error();
+  if (!srv || !out) return ah::set_error(AH_ERR_INVALID_ARG, "server and out are required");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->jobs.find(job_id);
+  if (it == srv->jobs.end() || !it->second->finished)
+    return ah::set_error(AH_ERR_INVALID_ARG, "job %llu is not a finished, unreleased job",
+                         (unsigned long long)job_id);
+  const Job& j = *it->second;
+  if (j.status != AH_OK)
+    return ah::set_error((ah_status)j.status, "job %llu failed", (unsigned long long)job_id);
+  if (part >= j.parts.size()) return ah::set_error(AH_ERR_INVALID_ARG, "job has %zu parts", j.parts.size());
+  const Part& p = j.parts[part];
+  out->hits = p.hits.data();
+  out->n_hits = p.hits.size();
+  out->amplicons = p.amps.data();
+  out->n_amplicons = p.amps.size();
+  out->first_genome = p.g0;
+  out->n_genomes = p.g1 - p.g0;
+  return AH_OK;
+}
+
+ah_status ah_server_release(ah_server* srv, uint64_t job_id) {
+  ah::clear_error();
+  if (!srv) return ah::set_error(AH_ERR_INVALID_ARG, "server is required");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->jobs.find(job_id);
+  if (it == srv->jobs.end() || !it->second->finished)
+    return ah::set_error(AH_ERR_INVALID_ARG, "job %llu is not a finished, unreleased job",
+                         (unsigned long long)job_id);
+  for (auto q = srv->finished_q.begin(); q != srv->finished_q.end(); ++q)
+    if (*q == job_id) {
+      srv->finished_q.erase(q);
+      break;
+    }
+  srv->jobs.erase(it);
+  srv->cv_lane.notify_all();
+  return AH_OK;
+}
+
+void ah_server_stats_get(ah_server* srv, ah_server_stats* out) {
+  if (!srv || !out) return;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  *out = srv->stats;
+  out->pool_bytes = srv->pool.bytes();
+  out->pool_in_use = srv->pool.in_use();
+  out->pool_high_water = srv->pool.high();
+}
+
+double ah_server_now(ah_server* srv) { return srv ? srv->now() : 0.0; }
+
+void ah_server_destroy(ah_server* srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+  }
+  srv->cv_lane.notify_all();
+  srv->cv_compile.notify_all();
+  srv->cv_done.notify_all();
+  for (std::thread& t : srv->threads) t.join();
+  delete srv;
+}
+
+}  // extern "C"

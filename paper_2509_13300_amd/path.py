@@ -228,3 +228,92 @@ def to_device(hg: L.HostGenomes, device) -> PackedCollection:
     lens = hg.len.astype(np.int64)
     return PackedCollection(words, nmask, d_off, d_len, hg.n, int(lens.max()) if hg.n else 1,
                             int(lens.sum()), lens)
+
+
+def pack_resident(fill_batch, lengths, device, batch_genomes: int = 500,
+                  with_nmask: bool = False) -> PackedCollection:
+    """Build a packed collection in HBM batch by batch (only one batch of ASCII
+    on the GPU at a time): ``fill_batch(ids)`` returns (ascii, ascii_off)
+    device tensors for genome ids ``ids``."""
+    import torch
+
+    lengths = np.asarray(lengths, dtype=np.int64)
+    word_off = L.ah_pack_layout(lengths)
+    W = int(word_off[-1])
+    words = torch.empty(2 * max(W, 1), dtype=torch.int32, device=device)
+    nmask = torch.empty(max(W, 1), dtype=torch.int32, device=device) if with_nmask else None
+    d_len = torch.empty(max(lengths.size, 1), dtype=torch.int32, device=device)
+    for a in range(0, lengths.size, batch_genomes):
+        ids = np.arange(a, min(a + batch_genomes, lengths.size))
+        ascii, off = fill_batch(ids)
+        c, _ = pack(ascii, off, lengths[ids], with_nmask=with_nmask)
+        w0, w1 = int(word_off[ids[0]]), int(word_off[ids[-1] + 1])
+        words[2 * w0: 2 * w1].copy_(c.words[: 2 * (w1 - w0)])
+        if with_nmask:
+            nmask[w0:w1].copy_(c.nmask[: w1 - w0])
+        d_len[ids[0]: ids[-1] + 1].copy_(c.len[: ids.size])
+        del ascii, off, c
+    d_off = torch.from_numpy(word_off.view(np.int64)).to(device)
+    torch.cuda.synchronize(device)
+    return PackedCollection(words, nmask, d_off, d_len, int(lengths.size),
+                            int(lengths.max()) if lengths.size else 1, int(lengths.sum()), lengths)
+
+
+class Server:
+    """Request loop over a collection resident in HBM (libah's serving
+    runtime): jobs are admitted as they arrive, split into parts, and run on
+    several device streams at once inside a fixed device pool."""
+
+    def __init__(self, coll: PackedCollection, pool_bytes: int, device, **cfg):
+        import torch
+
+        self.coll = coll  # the server borrows its device views
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
+        self.handle = L.ah_server_create(coll.view(), coll.lengths, L.server_config(**cfg),
+                                         self.pool)
+
+    def submit(self, pair, genomes=None, tm=None, filter_tm=False, min_tm=50.0) -> int:
+        return L.ah_server_submit(self.handle, pair, genomes, tm, filter_tm, min_tm)
+
+    def wait(self, timeout_s: float = 1.0) -> Optional[dict]:
+        return L.ah_server_wait(self.handle, timeout_s)
+
+    def now(self) -> float:
+        return L.ah_server_now(self.handle)
+
+    def result(self, status: dict):
+        """(hits, amplicons) of a finished job as numpy records: the parts
+        concatenated; amplicon hit indices refer to the concatenated hits."""
+        import ctypes
+
+        hs, as_, base = [], [], 0
+        for i in range(status["n_parts"]):
+            pt = L.ah_server_part(self.handle, status["job"], i)
+            h = np.frombuffer(ctypes.string_at(pt.hits, pt.n_hits * 16), dtype=L.HIT_DTYPE) \
+                if pt.n_hits else np.zeros(0, L.HIT_DTYPE)
+            a = np.frombuffer(ctypes.string_at(pt.amplicons, pt.n_amplicons * 24),
+                              dtype=L.AMP_DTYPE).copy() if pt.n_amplicons else np.zeros(0, L.AMP_DTYPE)
+            a["plus_hit"] += np.uint32(base)
+            a["minus_hit"] += np.uint32(base)
+            hs.append(h)
+            as_.append(a)
+            base += h.size
+        cat = lambda xs, dt: np.concatenate(xs) if xs else np.zeros(0, dt)  # noqa: E731
+        return cat(hs, L.HIT_DTYPE), cat(as_, L.AMP_DTYPE)
+
+    def release(self, job: int):
+        L.ah_server_release(self.handle, job)
+
+    def stats(self) -> dict:
+        return L.ah_server_stats_get(self.handle)
+
+    def close(self):
+        if self.handle:
+            L.ah_server_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -4,6 +4,7 @@ import sys
 
 import numpy as np
 
+from oracle import iupac
 from oracle import pair as opair
 from oracle import scan as oscan
 from oracle import tm as otm
@@ -61,3 +62,17 @@ def hit_tuples_oracle(h):
 def amp_tuples(a):
     return [(int(x["pair"]), int(x["genome"]), int(x["start"]), int(x["end"]), int(x["orient"]),
              int(x["plus_hit"]), int(x["minus_hit"])) for x in a]
+
+
+def random_rate(pr):
+    """Expected random sites per base (uniform bases), to pick hit-rich pairs."""
+    tot = 0.0
+    for prim in (pr.fwd, pr.rev):
+        d = np.zeros(len(prim) + 1)
+        d[0] = 1.0
+        for c in prim:
+            m = len(iupac.SETS[c]) / 4
+            d[1:] = d[1:] * m + d[:-1] * (1 - m)
+            d[0] *= m
+        tot += 2 * d[: pr.k + 1].sum()
+    return tot

@@ -4,7 +4,7 @@ nothing; a hipGraph replay equals the eager pass."""
 import numpy as np
 import pytest
 
-from gpu_util import amp_tuples, hit_tuples_gpu, hit_tuples_oracle, run_oracle, say
+from gpu_util import amp_tuples, hit_tuples_gpu, hit_tuples_oracle, random_rate, run_oracle, say
 from synth import gpu, plan
 
 pytestmark = pytest.mark.gpu
@@ -18,27 +18,11 @@ def dev():
     return torch.device("cuda:0")
 
 
-def _random_rate(pr):
-    """Expected random sites per base (uniform bases), to pick hit-rich pairs."""
-    from oracle import iupac
-
-    tot = 0.0
-    for prim in (pr.fwd, pr.rev):
-        d = np.zeros(len(prim) + 1)
-        d[0] = 1.0
-        for c in prim:
-            m = len(iupac.SETS[c]) / 4
-            d[1:] = d[1:] * m + d[:-1] * (1 - m)
-            d[0] *= m
-        tot += 2 * d[: pr.k + 1].sum()
-    return tot
-
-
 @pytest.fixture(scope="module")
 def batch(dev):
     from paper_2509_13300_amd import path
 
-    pairs = sorted(plan.law_pairs(4401, 64), key=_random_rate, reverse=True)[:8]
+    pairs = sorted(plan.law_pairs(4401, 64), key=random_rate, reverse=True)[:8]
     for q in pairs:  # windows that fit the small genomes
         q.min_len, q.max_len = 40, 1500
     pairs[3].clamp = 2
