@@ -422,7 +422,7 @@ def _lat_summary(sts):
             "queue_p99_ms": float(np.percentile(wait, 99))}
 
 
-def gpu_serve(n_jobs: int = 200, rate: float = 20.0, n_genomes: int = 100000,
+def gpu_serve(n_jobs: int = 120, rate: float = 4.0, n_genomes: int = 100000,
               pool_gb: float = 64.0, n_lanes: int = 4):
     """Serving form: the 100,000-genome collection resident in HBM, Poisson
     job arrivals (one law pair over a log-uniform genome subset each)."""
@@ -449,8 +449,10 @@ def gpu_serve(n_jobs: int = 200, rate: float = 20.0, n_genomes: int = 100000,
     print(f"serve: {len(used)} pair kernels compiled in {compile_s:.1f} s", file=sys.stderr,
           flush=True)
     cfg = dict(n_lanes=n_lanes, n_compilers=8, part_bases=1 << 32, max_part_hits=1 << 25,
-               capacity_scale=2.0)
+               capacity_scale=2.0, host_pool_bytes=64 << 30)
+    t0 = time.perf_counter()
     srv = path.Server(coll, int(pool_gb * (1 << 30)), dev, **cfg)
+    create_s = time.perf_counter() - t0
     try:
         _serve_pass(srv, p, jobs[:8], "burst")  # warm-up: tables, staging buffers
         sts, span = _serve_pass(srv, p, jobs, "poisson")
@@ -483,8 +485,11 @@ def gpu_serve(n_jobs: int = 200, rate: float = 20.0, n_genomes: int = 100000,
         "amplicons": int(sum(st["amplicons"] for st in sts)),
         "retries": int(sum(st["retries"] for st in sts)),
         "server": {k: stats[k] for k in ("parts_run", "retries", "pool_bytes", "pool_high_water",
-                                          "admission_waits", "lane_busy_s")},
+                                          "admission_waits", "lane_busy_s", "host_pool_bytes",
+                                          "host_pool_high_water", "host_fallbacks", "gpu_s",
+                                          "copy_s")},
         "config": cfg, "pool_gb": pool_gb, "build_s": build_s, "compile_s": compile_s,
+        "server_create_s": create_s,
         "distinct_pairs": len(used),
     }
 
@@ -500,8 +505,8 @@ def main():
                          "pass vs one by one; stream: 10,000 genomes copied host -> HBM in "
                          "packed chunks during the query; serve: Poisson jobs over a resident "
                          "100,000-genome collection")
-    ap.add_argument("--jobs", type=int, default=200, help="serve: number of jobs")
-    ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
+    ap.add_argument("--jobs", type=int, default=120, help="serve: number of jobs")
+    ap.add_argument("--rate", type=float, default=4.0, help="serve: arrivals per second")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-mbp", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -551,6 +556,7 @@ def main():
                            "genomes", "total_bp", "jobs", "rate_per_s", "jobs_per_s", "bases",
                            "latency", "burst", "serial_one_lane", "hits", "amplicons", "retries",
                            "server", "config", "pool_gb", "build_s", "compile_s",
+                           "server_create_s",
                            "distinct_pairs")}},
             "roofline": None, "cpu_baseline": None}))
         return

@@ -345,6 +345,8 @@ typedef struct ah_server_config {
   uint64_t part_bases;    /* bases per part at most (whole genomes; >= 1) */
   uint64_t max_part_hits; /* parts are also cut so that their expected sites stay below this */
   double capacity_scale;  /* capacity = scale x expected records + a per-genome reserve */
+  uint64_t host_pool_bytes; /* pinned host arena for part records (0: none); parts whose
+                               records do not fit go through a staging buffer instead */
 } ah_server_config;
 
 /* One request.  Strings and the genome list are copied at submission. */
@@ -370,8 +372,8 @@ typedef struct ah_job_status {
   uint32_t reserved;
 } ah_job_status;
 
-/* Output of one part (host memory owned by the server, valid until the job is
- * released).  Genome ids are ids of the resident collection; plus_hit and
+/* Output of one part (host memory owned by the server: the pinned arena or
+ * ordinary memory, valid until the job is released).  Genome ids are ids of the resident collection; plus_hit and
  * minus_hit index this part's hits.  The parts of a job cover its genomes in
  * ascending order, so their concatenation is the job's canonical output. */
 typedef struct ah_job_part {
@@ -389,6 +391,10 @@ typedef struct ah_server_stats {
   uint64_t admission_waits; /* times a lane found the next part's buffers not fitting yet */
                             /* pool_in_use / pool_high_water: device bytes of running parts */
   double lane_busy_s;       /* summed over lanes: time from a part's launch to its completion */
+  uint64_t host_pool_bytes, host_pool_high_water;
+  uint64_t host_fallbacks;  /* parts whose records did not fit in the host arena */
+  double gpu_s;             /* summed over parts: launch to results on the host (last run) */
+  double copy_s;            /* summed over parts: copying records to host memory */
 } ah_server_stats;
 
 /* Start a server on the current device over `resident` (device views stay

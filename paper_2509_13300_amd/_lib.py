@@ -80,7 +80,7 @@ class ah_stream_config(ctypes.Structure):
 class ah_server_config(ctypes.Structure):
     _fields_ = [("n_lanes", ctypes.c_uint32), ("n_compilers", ctypes.c_uint32),
                 ("part_bases", ctypes.c_uint64), ("max_part_hits", ctypes.c_uint64),
-                ("capacity_scale", ctypes.c_double)]
+                ("capacity_scale", ctypes.c_double), ("host_pool_bytes", ctypes.c_uint64)]
 
 
 class ah_job(ctypes.Structure):
@@ -107,7 +107,9 @@ class ah_job_part(ctypes.Structure):
 class ah_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "jobs_submitted", "jobs_finished", "parts_run", "retries", "pool_bytes", "pool_in_use",
-        "pool_high_water", "admission_waits")] + [("lane_busy_s", ctypes.c_double)]
+        "pool_high_water", "admission_waits")] + [("lane_busy_s", ctypes.c_double)] + [
+        (n, ctypes.c_uint64) for n in ("host_pool_bytes", "host_pool_high_water", "host_fallbacks")] + [
+        ("gpu_s", ctypes.c_double), ("copy_s", ctypes.c_double)]
 
 
 # Every symbol declared in include/ah.h and include/ah_dev.h.
@@ -442,9 +444,10 @@ def ah_stream_query(hg: HostGenomes, cfg: ah_stream_config, pairs, wins, params:
 
 
 def server_config(n_lanes: int = 4, n_compilers: int = 8, part_bases: int = 1 << 32,
-                  max_part_hits: int = 1 << 25, capacity_scale: float = 2.0) -> ah_server_config:
+                  max_part_hits: int = 1 << 25, capacity_scale: float = 2.0,
+                  host_pool_bytes: int = 0) -> ah_server_config:
     return ah_server_config(int(n_lanes), int(n_compilers), int(part_bases), int(max_part_hits),
-                            float(capacity_scale))
+                            float(capacity_scale), int(host_pool_bytes))
 
 
 def ah_server_create(genomes: ah_genomes, lengths, cfg: ah_server_config, pool) -> int:

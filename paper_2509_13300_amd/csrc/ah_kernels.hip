@@ -313,52 +313,70 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
     const u64 clampm = T->clampm;
     const u64 stackm = T->stackm;
     const u32 k = T->k;
-    const u32 nd = T->nd;
     const double KL = T->KL;
-    // odometer over the degenerate positions, 3'-most fastest
-    u64 o = T->fixed;
-    u64 choice = 0;
-    for (u32 d = 0; d < nd; ++d) o |= (u64)(T->mem[d] & 3u) << (2u * T->dpos[d]);
-    float best = __int_as_float(0x7fc00000);  // NaN until a compatible oligo is seen
-    for (u64 it = 0; it < T->deg; ++it) {
-      const u64 x = o ^ ow;
-      const u64 eq = ~(x | (x >> 1)) & lanes;  // paired positions
-      const u32 mism = L - (u32)__popcll(eq);
-      if (mism <= k && (eq & clampm) == clampm) {
-        float sh = 0.f, ch = 0.f, ss = 0.f, cs = 0.f;
-        u64 st = eq & (eq >> 2) & stackm;
-        while (st) {
-          const u32 j2 = (u32)__ffsll((long long)st) - 1u;
-          st &= st - 1;
-          const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
-          two_sum(sh, ch, c_nn_dh[ix]);
-          two_sum(ss, cs, c_nn_ds[ix]);
-        }
-        if (eq) {
-          const u32 lo = (u32)__ffsll((long long)eq) - 1u;
-          const u32 hi = 63u - (u32)__clzll((long long)eq);
-          init_term((u32)(o >> lo) & 3u, sh, ch, ss, cs);
-          init_term((u32)(o >> hi) & 3u, sh, ch, ss, cs);
-        }
-        const float den = (float)((double)ss + (double)cs + KL);
-        const float tm = 1000.0f * (sh + ch) / den - 273.15f;
-        best = (best == best && best >= tm) ? best : tm;
+    // Under the model only paired positions enter Delta-H, Delta-S and the
+    // initiation terms, so every oligo with the same set of paired positions
+    // has the same Tm.  Representative oligo: the template's base at each
+    // degenerate position whose set holds it ("in-set"), any member
+    // elsewhere (those positions mismatch for every oligo).  Other compatible
+    // pairings come from turning at most k - mm in-set, non-clamp positions
+    // into mismatches, which any other member of their set does.
+    u64 o = T->fixed, afree = 0;
+    for (u32 d = 0; d < T->nd; ++d) {
+      const u32 pos2 = 2u * T->dpos[d];
+      const u32 t = (u32)(ow >> pos2) & 3u;
+      const u32 mem = T->mem[d];
+      bool in_set = false;
+      for (u32 r = 0; r < T->nmem[d]; ++r) in_set |= ((mem >> (2u * r)) & 3u) == t;
+      in_set &= ((nb >> pos2) & 1u) == 0u;
+      o |= (u64)(in_set ? t : (mem & 3u)) << pos2;
+      if (in_set && ((clampm >> pos2) & 1u) == 0u) afree |= 1ull << pos2;
+    }
+    const u64 x = o ^ ow;
+    const u64 eq0 = ~(x | (x >> 1)) & lanes;  // paired positions of the representative
+    const u32 mism0 = L - (u32)__popcll(eq0);
+    float best = __int_as_float(0x7fc00000);  // NaN: no compatible oligo
+    auto consider = [&](u64 eq) {
+      float sh = 0.f, ch = 0.f, ss = 0.f, cs = 0.f;
+      u64 st = eq & (eq >> 2) & stackm;
+      while (st) {
+        const u32 j2 = (u32)__ffsll((long long)st) - 1u;
+        st &= st - 1;
+        const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
+        two_sum(sh, ch, c_nn_dh[ix]);
+        two_sum(ss, cs, c_nn_ds[ix]);
       }
-      // advance the odometer
-      for (int d = (int)nd - 1; d >= 0; --d) {
-        const u32 sh2 = 2u * (u32)d;
-        const u32 cur = (u32)(choice >> sh2) & 3u;
-        const u32 pos2 = 2u * T->dpos[d];
-        const u32 mcur = (T->mem[d] >> (2u * cur)) & 3u;
-        if (cur + 1u < T->nmem[d]) {
-          const u32 mnext = (T->mem[d] >> (2u * (cur + 1u))) & 3u;
-          choice += 1ull << sh2;
-          o ^= (u64)(mcur ^ mnext) << pos2;
-          break;
+      if (eq) {
+        const u32 lo = (u32)__ffsll((long long)eq) - 1u;
+        const u32 hi = 63u - (u32)__clzll((long long)eq);
+        init_term((u32)(o >> lo) & 3u, sh, ch, ss, cs);
+        init_term((u32)(o >> hi) & 3u, sh, ch, ss, cs);
+      }
+      const float den = (float)((double)ss + (double)cs + KL);
+      const float tm = 1000.0f * (sh + ch) / den - 273.15f;
+      best = (best == best && best >= tm) ? best : tm;
+    };
+    if (mism0 <= k && (eq0 & clampm) == clampm) {
+      consider(eq0);
+      const u32 nfree = (u32)__popcll(afree);
+      const u32 budget = min(k - mism0, nfree);
+      for (u32 e = 1; e <= budget; ++e) {
+        // every e-subset of the free positions (Gosper's next combination
+        // over nfree bits, deposited onto the position mask)
+        u64 comb = (1ull << e) - 1ull;
+        while (comb < (1ull << nfree)) {  // nfree <= 32
+          u64 sub = 0, m = afree, c = comb;
+          while (c) {
+            if (c & 1ull) sub |= m & (0ull - m);
+            m &= m - 1ull;
+            c >>= 1;
+          }
+          consider(eq0 & ~sub);
+          const u64 low = comb & (0ull - comb);
+          const u64 r = comb + low;
+          if (r == 0) break;
+          comb = (((r ^ comb) >> 2) / low) | r;
         }
-        const u32 m0 = T->mem[d] & 3u;
-        choice &= ~(3ull << sh2);
-        o ^= (u64)(mcur ^ m0) << pos2;
       }
     }
     h.tm = best;

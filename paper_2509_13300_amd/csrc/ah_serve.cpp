@@ -5,7 +5,9 @@
 // stream, take the next part of the active jobs in round-robin order, carve
 // the part's buffers from the caller's pool (the HBM budget), run gather ->
 // scan -> Tm -> pairing -> remap on their stream, wait for it and copy the
-// part's records to host memory (through a pinned staging buffer per lane).
+// part's records to host memory: straight into a pinned result arena
+// allocated once at start, or, when the arena is full, through a pinned
+// staging buffer per lane into ordinary host memory.
 // Pool memory is held only while a part is in flight, so every admitted part
 // completes and frees it: admission by memory cannot deadlock.  Parts of
 // several jobs are in flight on the device together, and a new job starts as
@@ -122,9 +124,12 @@ struct Part {
   uint64_t bases = 0;
   uint32_t max_len = 1;
   uint64_t hcap = 0, acap = 0;
-  std::vector<ah_hit> hits;            // host copies of the part's records
+  uint64_t n_hits = 0, n_amps = 0;       // records of a done part
+  uint64_t arena_off = ~0ull, arena_bytes = 0;  // their place in the host arena, or
+  std::vector<ah_hit> hits;              // host copies when the arena was full
   std::vector<ah_amplicon> amps;
   bool done = false;
+  bool in_arena() const { return arena_off != ~0ull; }
 };
 
 struct Job {
@@ -176,6 +181,8 @@ struct ah_server {
   uintptr_t base = 0;
   int dev = 0;
   Pool pool{0};
+  char* arena = nullptr;  // pinned host memory for part records
+  Pool arena_pool{0};
   std::chrono::steady_clock::time_point t0;
 
   std::mutex mu;
@@ -191,6 +198,15 @@ struct ah_server {
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  // Frees a part's records (mu held).
+  void drop_records(Part& q) {
+    if (q.in_arena()) arena_pool.release(q.arena_off, q.arena_bytes);
+    q.arena_off = ~0ull;
+    std::vector<ah_hit>().swap(q.hits);
+    std::vector<ah_amplicon>().swap(q.amps);
+    q.done = false;
   }
 
   // Called with mu held.
@@ -235,11 +251,25 @@ struct ah_server {
     }
   }
 
-  // Runs part p of job j on `st` in the pool block at `blk`; hr[0..1] get the
-  // part's results; when both fit, the records are copied to p.hits / p.amps
-  // through the lane's pinned staging buffer.
+  // Amplicon capacity from the sites a part actually has: random + and -
+  // sites at the measured density, paired within the window.
+  uint64_t amp_capacity(uint64_t nh, const Part& p, double win) const {
+    const double b = std::max<double>((double)p.bases, 1.0);
+    const double e = (double)nh * (double)nh * win / (4.0 * b);
+    return (uint64_t)std::min(std::ceil(cfg.capacity_scale * e), 1e12) +
+           4ull * (p.g1 - p.g0) + 256;
+  }
+
+  // Runs part p of job j on `st` in the pool block at `blk`.  hr[0..1] get the
+  // part's results; when both fit, the records are copied to host memory.  The
+  // amplicon buffer is resized from the sites found before pairing (an extra
+  // pool block when the planned one is too small), and pairing alone is run
+  // again when it overflows, so only an overflow of sites (or no pool memory
+  // for the extra block) sends the whole part back for another run.
   ah_status run_part(Job& j, Part& p, const PartSizes& z, uint64_t blk, hipStream_t st,
-                     ah_result* hr, void*& stage, size_t& stage_bytes) {
+                     ah_result* hr, void*& stage, size_t& stage_bytes, double* t_gpu,
+                     double* t_copy) {
+    const double t0 = now();
     const uint32_t n = p.g1 - p.g0;
     uintptr_t q = base + blk;
     ah_result* d_res = (ah_result*)q;
@@ -250,6 +280,30 @@ struct ah_server {
     uint32_t* len_v = (uint32_t*)(q += z.off);
     void* scan_ws = (void*)(q += z.len);
     void* pair_ws = (void*)(q += z.scan_ws);
+    struct Extra {  // an extra amplicon block, returned to the pool on exit
+      ah_server* srv;
+      uint64_t off = ~0ull, bytes = 0;
+      ~Extra() {
+        if (off == ~0ull) return;
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->pool.release(off, bytes);
+        srv->cv_lane.notify_all();
+      }
+    } extra{this};
+    uint64_t acap = p.acap;
+    auto take_extra = [&](uint64_t cap) -> bool {
+      std::lock_guard<std::mutex> lk(mu);
+      if (extra.off != ~0ull) pool.release(extra.off, extra.bytes);
+      extra.off = ~0ull;
+      const uint64_t bytes = align256(cap * sizeof(ah_amplicon));
+      uint64_t o;
+      if (!pool.alloc(bytes, &o)) return false;
+      extra.off = o;
+      extra.bytes = bytes;
+      amps = (ah_amplicon*)(base + o);
+      acap = cap;
+      return true;
+    };
     AH_HIP(hipMemcpyAsync(ids, j.ids.data() + p.g0, (size_t)n * 4, hipMemcpyHostToDevice, st));
     AH_HIP(ah::launch_gather_view(ids, n, res.word_off, res.len, off, len_v, st));
     ah_genomes view = res;
@@ -261,14 +315,61 @@ struct ah_server {
     if (s) return s;
     s = ah_tm(&view, &j.pair, 1, &j.tm, hits, &d_res[0], p.hcap, st);
     if (s) return s;
-    s = ah_pair_amplicons(hits, &d_res[0], p.hcap, &j.pair, &j.win, 1, amps, p.acap, &d_res[1],
-                          pair_ws, z.pair_ws, st);
-    if (s) return s;
-    AH_HIP(ah::launch_remap(hits, &d_res[0], amps, &d_res[1], ids, ah::cu_count_current() * 4, st));
-    AH_HIP(hipMemcpyAsync(hr, d_res, 2 * sizeof(ah_result), hipMemcpyDeviceToHost, st));
+    AH_HIP(hipMemcpyAsync(&hr[0], &d_res[0], sizeof(ah_result), hipMemcpyDeviceToHost, st));
     AH_HIP(hipStreamSynchronize(st));
-    if (hr[0].status != AH_OK || hr[1].status != AH_OK) return AH_OK;  // run again
+    hr[1] = ah_result{0, 0, AH_OK, 0};
+    if (hr[0].status != AH_OK) return AH_OK;  // run again with the exact site count
+    const uint64_t want = amp_capacity(hr[0].count, p, (double)j.win.max_len - j.win.min_len + 1.0);
+    if (want > acap && !take_extra(want)) {
+      hr[1].status = AH_ERR_OVERFLOW;  // run again, planning the larger buffer
+      hr[1].required = want;
+      return AH_OK;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      s = ah_pair_amplicons(hits, &d_res[0], p.hcap, &j.pair, &j.win, 1, amps, acap, &d_res[1],
+                            pair_ws, z.pair_ws, st);
+      if (s) return s;
+      AH_HIP(hipMemcpyAsync(&hr[1], &d_res[1], sizeof(ah_result), hipMemcpyDeviceToHost, st));
+      AH_HIP(hipStreamSynchronize(st));
+      if (hr[1].status == AH_OK || pass == 1 || !take_extra(hr[1].required)) break;
+    }
+    if (hr[1].status != AH_OK) return AH_OK;  // run again with the exact amplicon count
+    AH_HIP(ah::launch_remap(hits, &d_res[0], amps, &d_res[1], ids, ah::cu_count_current() * 4, st));
+    AH_HIP(hipStreamSynchronize(st));
+    const double t1 = now();
+    *t_gpu = t1 - t0;
+    struct CopyClock {
+      ah_server* srv;
+      double t1;
+      double* out;
+      ~CopyClock() { *out = srv->now() - t1; }
+    } copy_clock{this, t1, t_copy};
     const size_t hb = hr[0].count * sizeof(ah_hit), ab = hr[1].count * sizeof(ah_amplicon);
+    p.n_hits = hr[0].count;
+    p.n_amps = hr[1].count;
+    uint64_t aoff = 0;
+    bool in_arena = false;
+    if (hb + ab > 0 && arena) {
+      std::lock_guard<std::mutex> lk(mu);
+      in_arena = arena_pool.alloc(hb + ab, &aoff);
+      if (!in_arena) stats.host_fallbacks++;
+    }
+    if (in_arena) {  // straight into the arena
+      p.arena_off = aoff;
+      p.arena_bytes = hb + ab;
+      hipError_t e = hb ? hipMemcpyAsync(arena + aoff, hits, hb, hipMemcpyDeviceToHost, st)
+                        : hipSuccess;
+      if (e == hipSuccess && ab)
+        e = hipMemcpyAsync(arena + aoff + hb, amps, ab, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        std::lock_guard<std::mutex> lk(mu);
+        arena_pool.release(aoff, hb + ab);
+        p.arena_off = ~0ull;
+        return ah::set_error(AH_ERR_HIP, "record copy: %s", hipGetErrorString(e));
+      }
+      return AH_OK;
+    }
     if (hb + ab > stage_bytes) {
       const size_t want = std::max<size_t>(hb + ab, 2 * stage_bytes + (1u << 20));
       if (stage) AH_HIP(hipHostFree(stage));
@@ -345,10 +446,14 @@ struct ah_server {
 
       const double t_run = now();
       ah_result hr[2] = {};
-      const ah_status s = run_part(*j, p, z, blk, st, hr, stage, stage_bytes);
+      double t_gpu = 0, t_copy = 0;
+      const ah_status s =
+          run_part(*j, p, z, blk, st, hr, stage, stage_bytes, &t_gpu, &t_copy);
 
       lk.lock();
       stats.lane_busy_s += now() - t_run;
+      stats.gpu_s += t_gpu;
+      stats.copy_s += t_copy;
       pool.release(blk, z.total);
       j->in_flight--;
       if (s != AH_OK) {
@@ -374,16 +479,12 @@ struct ah_server {
       } else {
         p.done = true;
         j->done_parts++;
-        j->hits += p.hits.size();
-        j->amps += p.amps.size();
+        j->hits += p.n_hits;
+        j->amps += p.n_amps;
       }
       if (j->in_flight == 0 && (j->status != AH_OK || j->done_parts == j->parts.size())) {
         if (j->status != AH_OK)
-          for (Part& q : j->parts) {  // a failed job returns no records
-            std::vector<ah_hit>().swap(q.hits);
-            std::vector<ah_amplicon>().swap(q.amps);
-            q.done = false;
-          }
+          for (Part& q : j->parts) drop_records(q);  // a failed job returns no records
         finish(*j);
       }
       cv_lane.notify_all();
@@ -422,6 +523,12 @@ ah_status ah_server_create(const ah_genomes* resident, const uint32_t* h_len,
   s->pool = Pool((pool_bytes - lost) & ~255ull);
   s->t0 = std::chrono::steady_clock::now();
   s->stats.pool_bytes = s->pool.bytes();
+  if (cfg->host_pool_bytes) {
+    void* a = nullptr;
+    AH_HIP(hipHostMalloc(&a, cfg->host_pool_bytes, hipHostMallocDefault));
+    s->arena = (char*)a;
+    s->arena_pool = Pool(cfg->host_pool_bytes & ~255ull);
+  }
   ah_server* srv = s.get();
   for (uint32_t i = 0; i < cfg->n_compilers; ++i)
     s->threads.emplace_back([srv] { srv->compile_loop(); });
@@ -547,10 +654,15 @@ ah_status ah_server_part(ah_server* srv, uint64_t job_id, uint32_t part, ah_job_
     return ah::set_error((ah_status)j.status, "job %llu failed", (unsigned long long)job_id);
   if (part >= j.parts.size()) return ah::set_error(AH_ERR_INVALID_ARG, "job has %zu parts", j.parts.size());
   const Part& p = j.parts[part];
-  out->hits = p.hits.data();
-  out->n_hits = p.hits.size();
-  out->amplicons = p.amps.data();
-  out->n_amplicons = p.amps.size();
+  if (p.in_arena()) {
+    out->hits = (const ah_hit*)(srv->arena + p.arena_off);
+    out->amplicons = (const ah_amplicon*)(srv->arena + p.arena_off + p.n_hits * sizeof(ah_hit));
+  } else {
+    out->hits = p.hits.data();
+    out->amplicons = p.amps.data();
+  }
+  out->n_hits = p.n_hits;
+  out->n_amplicons = p.n_amps;
   out->first_genome = p.g0;
   out->n_genomes = p.g1 - p.g0;
   return AH_OK;
@@ -564,6 +676,7 @@ ah_status ah_server_release(ah_server* srv, uint64_t job_id) {
   if (it == srv->jobs.end() || !it->second->finished)
     return ah::set_error(AH_ERR_INVALID_ARG, "job %llu is not a finished, unreleased job",
                          (unsigned long long)job_id);
+  for (Part& p : it->second->parts) srv->drop_records(p);
   for (auto q = srv->finished_q.begin(); q != srv->finished_q.end(); ++q)
     if (*q == job_id) {
       srv->finished_q.erase(q);
@@ -581,6 +694,8 @@ void ah_server_stats_get(ah_server* srv, ah_server_stats* out) {
   out->pool_bytes = srv->pool.bytes();
   out->pool_in_use = srv->pool.in_use();
   out->pool_high_water = srv->pool.high();
+  out->host_pool_bytes = srv->arena_pool.bytes();
+  out->host_pool_high_water = srv->arena_pool.high();
 }
 
 double ah_server_now(ah_server* srv) { return srv ? srv->now() : 0.0; }
@@ -595,6 +710,7 @@ void ah_server_destroy(ah_server* srv) {
   srv->cv_compile.notify_all();
   srv->cv_done.notify_all();
   for (std::thread& t : srv->threads) t.join();
+  if (srv->arena) (void)hipHostFree(srv->arena);
   delete srv;
 }
 

@@ -386,12 +386,14 @@ def jobs(seed: int, n_jobs: int, rate: float, n_genomes: int, pool: int,
     """Poisson arrivals; each job is one pool pair over a random genome subset
     of log-uniform size in [lo, min(hi, n_genomes)].  Returns a list of
     (arrival_s, pair_id, sorted genome ids)."""
-    key = rng.stream_key(seed, rng.S_MISC | (2 << 20))
-    u = 1.0 - rng.uniform01(key, np.arange(n_jobs))
+    # one draw stream per quantity, so the first n jobs are the same for any
+    # n_jobs >= n
+    idx = np.arange(n_jobs)
+    u = 1.0 - rng.uniform01(rng.stream_key(seed, rng.S_MISC | (2 << 20)), idx)
     arrivals = np.cumsum(-np.log(u) / rate)
-    pids = rng.uniform_int(key, np.arange(n_jobs, 2 * n_jobs), 0, pool - 1)
+    pids = rng.uniform_int(rng.stream_key(seed, rng.S_MISC | (4 << 20)), idx, 0, pool - 1)
     hi = min(hi, n_genomes)
-    su = rng.uniform01(key, np.arange(2 * n_jobs, 3 * n_jobs))
+    su = rng.uniform01(rng.stream_key(seed, rng.S_MISC | (5 << 20)), idx)
     sizes = np.round(np.exp(math.log(lo) + su * (math.log(hi) - math.log(lo)))).astype(np.int64)
     out = []
     for j in range(n_jobs):

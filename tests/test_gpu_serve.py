@@ -129,7 +129,8 @@ def test_each_result_is_the_same_alone_and_in_the_mix(world, dev):
 
     p, c, pool = world
     jobs = job_mix(p, pool, 6603, 22)
-    cfg = dict(n_lanes=4, part_bases=400_000)
+    # a 32 KiB host arena: small parts land in it, larger ones fall back
+    cfg = dict(n_lanes=4, part_bases=400_000, host_pool_bytes=32 << 10)
     srv = path.Server(c, 512 << 20, dev, **cfg)
     try:
         alone = {i: serve_all(srv, [job])[0] for i, job in enumerate(jobs)}
@@ -149,6 +150,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix(world, dev):
         h0, a0 = direct(c, np.arange(p.n) if ids is None else ids, pr, dev)
         assert np.array_equal(alone[i][0], h0) and np.array_equal(alone[i][1], a0)
     assert st["pool_in_use"] == 0 and st["parts_run"] > 3 * len(jobs)
+    assert st["host_fallbacks"] > 0 and st["host_pool_high_water"] > 0
 
 
 def test_tight_pool_admission_changes_nothing(world, dev):
@@ -189,7 +191,8 @@ def test_capacity_retries_change_nothing(world, dev):
         assert srv.stats()["retries"] == 0
     finally:
         srv.close()
-    srv = path.Server(c, 512 << 20, dev, n_lanes=4, part_bases=400_000, capacity_scale=0.0)
+    srv = path.Server(c, 512 << 20, dev, n_lanes=4, part_bases=400_000, capacity_scale=0.0,
+                      host_pool_bytes=256 << 20)
     try:
         got = serve_all(srv, jobs)
         st = srv.stats()
