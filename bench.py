@@ -124,7 +124,7 @@ def gpu_run(name: str, steps: int, warmup: int):
     del ascii
     torch.cuda.empty_cache()
 
-    buf = path.alloc(coll, 1, 1 << 22, 1 << 22, dev)
+    buf = path.alloc(coll, [pr], 1 << 22, 1 << 22, dev)
     jit0 = L.ah_jit_stats()
     for _ in range(max(1, warmup)):
         path.run(coll, [pr], buf)
@@ -144,7 +144,7 @@ def gpu_run(name: str, steps: int, warmup: int):
     dt = time.perf_counter() - t0
     L.ah_profile_enable(False)
     kern = {}
-    for k in ("scan", "sort", "tm", "pair"):
+    for k in ("scan", "verify", "sort", "tm", "pair"):
         n, ms = L.ah_profile_query(k)
         kern[k] = ms / max(n, 1)
     traffic = None
@@ -157,6 +157,7 @@ def gpu_run(name: str, steps: int, warmup: int):
         if d.get("program_sha256") == sha:  # counters were taken on this exact kernel
             traffic = d["traffic_bytes_per_dispatch"]
     hits = path.hits_numpy(buf)
+    cands = L.ah_scan_candidate_stats(buf.scan_work, coll.n, buf.hit_cap)
     tm_ok = bool(np.all(np.isfinite(hits["tm"]))) if hits.size else True
     ms_step = dt * 1e3 / steps
     bp = coll.total_bp
@@ -165,6 +166,7 @@ def gpu_run(name: str, steps: int, warmup: int):
     return {
         "bp": bp, "desc": desc, "ms_per_step": ms_step, "value": bp / (ms_step * 1e-3) / 1e9,
         "kernel_ms": kern, "hits": res_h["count"], "amplicons": res_a["count"], "tm_finite": tm_ok,
+        "scan_candidates": cands,
         "pack": {"ms": pack_ms, "wall_ms": pack_s * 1e3, "gbps": bp / (pack_ms * 1e-3) / 1e9},
         "jit": {"compiles": jit1[0] - jit0[0], "ms": jit1[1] - jit0[1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -215,7 +217,7 @@ def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 6
     del ascii
     torch.cuda.empty_cache()
     bp = coll.total_bp
-    buf = path.alloc(coll, len(pairs), 1 << 25, 1 << 24, dev)
+    buf = path.alloc(coll, pairs, 1 << 25, 1 << 24, dev)
     t0 = time.perf_counter()
     L.ah_scan_prepare(pairs)
     prep_s = time.perf_counter() - t0
@@ -249,7 +251,8 @@ def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 6
     t0 = time.perf_counter()
     L.prepare_many([[q] for q in pairs])
     prep_seq_s = time.perf_counter() - t0
-    one = path.alloc(coll, 1, 1 << 25, 1 << 24, dev)
+    widest = max(pairs, key=lambda q: L.ah_scan_workspace_bytes(coll.view(), [q], 1 << 25))
+    one = path.alloc(coll, [widest], 1 << 25, 1 << 24, dev)
     for q in pairs:
         path.run(coll, [q], one)
     torch.cuda.synchronize()
@@ -302,7 +305,7 @@ def gpu_stream(steps: int, warmup: int, n_genomes: int = 10000, chunk_words: int
     print(f"stream: host collection {bp / 1e9:.2f} Gbp, {packed_bytes / 1e9:.2f} GB packed, "
           f"built in {build_s:.1f} s", file=sys.stderr, flush=True)
     hit_cap, amp_cap = 1 << 24, 1 << 22
-    buf = path.stream_alloc(hg, 1, hit_cap, amp_cap, dev, chunk_words, n_slots)
+    buf = path.stream_alloc(hg, [pr], hit_cap, amp_cap, dev, chunk_words, n_slots)
     copies = [torch.cuda.Stream(dev) for _ in range(n_copy)]
     for _ in range(max(1, warmup)):
         path.stream_run(hg, [pr], buf, copy_streams=copies)
@@ -334,7 +337,7 @@ def gpu_stream(steps: int, warmup: int, n_genomes: int = 10000, chunk_words: int
     del staging
     # the same query on the collection resident in HBM, and full-size parity
     coll = path.to_device(hg, dev)
-    rbuf = path.alloc(coll, 1, hit_cap, amp_cap, dev)
+    rbuf = path.alloc(coll, [pr], hit_cap, amp_cap, dev)
     path.run(coll, [pr], rbuf)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -604,7 +607,8 @@ def main():
         "config": {
             "workload": r["desc"], "genomes": r["genomes"], "total_bp": r["bp"],
             "pair": r["pair"], "form": "plain", "hits": r["hits"], "amplicons": r["amplicons"],
-            "kernel_ms": r["kernel_ms"], "ingest_pack": r["pack"], "jit": r["jit"],
+            "kernel_ms": r["kernel_ms"], "scan_candidates": r["scan_candidates"],
+            "ingest_pack": r["pack"], "jit": r["jit"],
             "tm_dtype": "f32 (compensated sums, f64 salt/log terms)",
         },
         "roofline": r["roofline"],

@@ -141,15 +141,26 @@ typedef struct ah_result {
  * position's IUPAC set is a mismatch; substitutions only) and no mismatch in
  * the clamp (the primer's 3'-most `clamp` bases).  Output: d_hits sorted by
  * (pair, genome, pos, strand, primer) -- a canonical order independent of
- * scheduling -- and *d_res.  Needs a workspace of at least
- * ah_scan_workspace_bytes(...) bytes (device, caller-owned, 256-byte aligned).
+ * scheduling -- and *d_res.  Needs a device workspace (caller-owned,
+ * 256-byte aligned); ah_scan_workspace_bytes gives the recommended size.
+ * Part of it holds the list of candidate windows that pass the scan's filter
+ * (at least max(capacity, 2^16) records; all extra workspace lengthens it).
+ * The list is split evenly over the filter's workgroups; if one finds more
+ * candidates than its share holds, the sites are incomplete: the result is
+ * AH_ERR_OVERFLOW and `required` is an upper bound on the sites, large
+ * enough that a call with capacity >= required succeeds.
  * Errors: AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT (primer
  * length outside 5..32, k > AH_MAX_K, clamp > primer length, sort key wider
  * than 64 bits), AH_ERR_WORKSPACE, AH_ERR_JIT, AH_ERR_HIP. */
 ah_status ah_scan_primers(const ah_genomes* genomes, const ah_primer_pair* pairs,
                           uint32_t n_pairs, ah_hit* d_hits, uint64_t capacity,
                           ah_result* d_res, void* d_work, size_t work_bytes, void* stream);
-size_t ah_scan_workspace_bytes(const ah_genomes* genomes, uint32_t n_pairs, uint64_t capacity);
+/* Recommended workspace: the fixed parts for `capacity` sites plus a
+ * candidate list of twice the records that the filters of `pairs` are
+ * expected to pass on random bases, over at most n x ceil(max_len / 32)
+ * window words, plus 2^16 records.  pairs may be NULL (the minimum). */
+size_t ah_scan_workspace_bytes(const ah_genomes* genomes, const ah_primer_pair* pairs,
+                               uint32_t n_pairs, uint64_t capacity);
 
 /* ---------------------------------------------------------------------------
  * Melting temperature (Section 2.1, "Melting temperature filtering").
@@ -222,8 +233,9 @@ size_t ah_pair_workspace_bytes(uint64_t hit_capacity, uint32_t n_pairs);
  * group.  The calls below choose the kernel shape for a primer set.
  * ------------------------------------------------------------------------- */
 
-/* Scan kernel shape: window words per lane and tile (2, 4, 8 or 16; a tile of
- * 256 x words_per_lane window words plus the primer halo is staged in LDS) and
+/* Scan kernel shape: window words per lane (odd, 3..31; a tile of 256 x
+ * words_per_lane window words plus the primer halo is staged in LDS, and each
+ * lane filters words_per_lane consecutive window words from registers) and
  * primer patterns per group (four per pair: each primer on each strand; a
  * group's code runs over the whole staged tile before the next group's). */
 typedef struct ah_scan_tuning {
@@ -289,9 +301,14 @@ typedef struct ah_stream_config {
 } ah_stream_config;
 
 /* Device workspace for ah_stream_query: the staging slots, the collection's
- * offsets and lengths, and the scan and pairing workspaces of one chunk. */
+ * offsets and lengths, and the pairing and scan workspaces of one chunk.
+ * Returns the recommended size (the scan's candidate list sized for the
+ * filters of `pairs` over a chunk, as ah_scan_workspace_bytes does); with
+ * pairs NULL, the minimum.  Any size from the minimum up is accepted; extra
+ * bytes lengthen the candidate list. */
 size_t ah_stream_workspace_bytes(const ah_host_genomes* genomes, const ah_stream_config* cfg,
-                                 uint32_t n_pairs, uint64_t hit_capacity);
+                                 const ah_primer_pair* pairs, uint32_t n_pairs,
+                                 uint64_t hit_capacity);
 
 /* Scan, Tm and pairing of `pairs` over a host-resident packed collection,
  * streamed chunk by chunk.  Chunk c's copy runs on copy_streams[c %

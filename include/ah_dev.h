@@ -33,13 +33,21 @@ ah_status ah_scan_program_compile(const ah_primer_pair* pairs, uint32_t n_pairs,
 
 /* Kernel timing with HIP events recorded on the launching stream.  While
  * enabled, every launch of the named kernels is bracketed by a pair of
- * events: "scan" (the specialised site scan), "tm", "pair" (the amplicon
+ * events: "scan" (the filter of the specialised site scan), "verify" (its
+ * exact count of the candidates), "tm", "pair" (the amplicon
  * writer), "sort" (all radix-sort passes of one call), "pack".  Queries wait
  * for the recorded events and return the launch count and summed device time
  * since the last reset.  Not for use inside hipGraph capture. */
 void ah_profile_enable(int on);
 void ah_profile_reset(void);
 ah_status ah_profile_query(const char* name, uint64_t* launches, double* total_ms);
+
+/* Statistics of the filter stage of the last ah_scan_primers call that used
+ * this workspace (the same n genomes and capacity): out[0] candidate records,
+ * out[1] windows in them, out[2] workgroups whose share of the candidate list
+ * was full, out[3] most candidates of one workgroup.  Synchronises the device. */
+ah_status ah_scan_candidate_stats(const void* d_work, size_t work_bytes, uint32_t n_genomes,
+                                  uint64_t capacity, uint64_t out[4]);
 
 #ifdef __cplusplus
 }

@@ -121,7 +121,7 @@ EXPORTS = (
     "ah_autotune_scan", "ah_set_scan_tuning", "ah_get_scan_tuning", "ah_scan_prepare",
     "ah_stream_workspace_bytes", "ah_stream_query", "ah_server_create", "ah_server_submit",
     "ah_server_wait", "ah_server_part", "ah_server_release", "ah_server_stats_get",
-    "ah_server_now", "ah_server_destroy",
+    "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats",
 )
 
 _lib = None
@@ -143,7 +143,7 @@ def lib() -> ctypes.CDLL:
     L.ah_pack_genomes.restype = st
     L.ah_scan_primers.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, vp, u64, vp, vp, sz, vp]
     L.ah_scan_primers.restype = st
-    L.ah_scan_workspace_bytes.argtypes = [P(ah_genomes), u32, u64]
+    L.ah_scan_workspace_bytes.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, u64]
     L.ah_scan_workspace_bytes.restype = sz
     L.ah_tm.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, P(ah_tm_params), vp, vp, u64, vp]
     L.ah_tm.restype = st
@@ -181,7 +181,8 @@ def lib() -> ctypes.CDLL:
     L.ah_get_scan_tuning.restype = st
     L.ah_scan_prepare.argtypes = [P(ah_primer_pair), u32, ctypes.c_int]
     L.ah_scan_prepare.restype = st
-    L.ah_stream_workspace_bytes.argtypes = [P(ah_host_genomes), P(ah_stream_config), u32, u64]
+    L.ah_stream_workspace_bytes.argtypes = [P(ah_host_genomes), P(ah_stream_config),
+                                            P(ah_primer_pair), u32, u64]
     L.ah_stream_workspace_bytes.restype = sz
     L.ah_stream_query.argtypes = [P(ah_host_genomes), P(ah_stream_config), P(ah_primer_pair),
                                   P(ah_window), u32, P(ah_tm_params), vp, u64, vp, vp, u64, vp, vp,
@@ -203,6 +204,8 @@ def lib() -> ctypes.CDLL:
     L.ah_server_now.restype = ctypes.c_double
     L.ah_server_destroy.argtypes = [vp]
     L.ah_server_destroy.restype = None
+    L.ah_scan_candidate_stats.argtypes = [vp, sz, u32, u64, P(ctypes.c_uint64)]
+    L.ah_scan_candidate_stats.restype = st
     _lib = L
     return L
 
@@ -265,8 +268,18 @@ def ah_pack_genomes(ascii, ascii_off, n, word_off, words, len_, nmask=None, non_
            "ah_pack_genomes")
 
 
-def ah_scan_workspace_bytes(genomes: ah_genomes, n_pairs: int, capacity: int) -> int:
-    return int(lib().ah_scan_workspace_bytes(ctypes.byref(genomes), n_pairs, capacity))
+def _pairs_arg(pairs):
+    """(array or None, count): a pair list, or an int for a count alone."""
+    if isinstance(pairs, int):
+        return None, pairs
+    pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
+    return pp, len(pp)
+
+
+def ah_scan_workspace_bytes(genomes: ah_genomes, pairs, capacity: int) -> int:
+    """Recommended scan workspace; `pairs` may be an int (the minimum)."""
+    pp, n = _pairs_arg(pairs)
+    return int(lib().ah_scan_workspace_bytes(ctypes.byref(genomes), pp, n, capacity))
 
 
 def ah_scan_primers(genomes: ah_genomes, pairs, hits, capacity: int, res, work, stream=None):
@@ -425,10 +438,11 @@ def stream_config(chunk_words: int, n_slots: int = 3) -> ah_stream_config:
     return c
 
 
-def ah_stream_workspace_bytes(hg: HostGenomes, cfg: ah_stream_config, n_pairs: int,
+def ah_stream_workspace_bytes(hg: HostGenomes, cfg: ah_stream_config, pairs,
                               hit_capacity: int) -> int:
-    return int(lib().ah_stream_workspace_bytes(ctypes.byref(hg.view()), ctypes.byref(cfg),
-                                               int(n_pairs), int(hit_capacity)))
+    pp, n = _pairs_arg(pairs)
+    return int(lib().ah_stream_workspace_bytes(ctypes.byref(hg.view()), ctypes.byref(cfg), pp,
+                                               int(n), int(hit_capacity)))
 
 
 def ah_stream_query(hg: HostGenomes, cfg: ah_stream_config, pairs, wins, params: ah_tm_params,
@@ -510,3 +524,11 @@ def ah_server_now(server: int) -> float:
 
 def ah_server_destroy(server: int):
     lib().ah_server_destroy(server)
+
+
+def ah_scan_candidate_stats(work, n_genomes: int, capacity: int) -> dict:
+    out = (ctypes.c_uint64 * 4)()
+    _check(lib().ah_scan_candidate_stats(_ptr(work), work.numel(), int(n_genomes), int(capacity),
+                                         out), "ah_scan_candidate_stats")
+    return {"records": int(out[0]), "windows": int(out[1]), "full_slices": int(out[2]),
+            "max_per_workgroup": int(out[3])}

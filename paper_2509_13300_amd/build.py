@@ -4,8 +4,9 @@
 
 Compiles every HIP source with hipcc --offload-arch=gfx950, embeds the scan
 core (csrc/scan_core.hip) into the host runtime as a string for run-time
-specialisation, and compiles that core offline once with a sample pattern
-program so that a mistake in it fails the build rather than the first call.
+specialisation, and compiles a few specialisations through the new library
+so that a mistake in the core or its generator fails the build rather than
+the first call.
 """
 from __future__ import annotations
 
@@ -25,46 +26,21 @@ DEVFLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{INCLUDE}", f"-I{CSRC}",
           f"-I{BUILD}"]
 
-SAMPLE_PROGRAM = r"""
-#define AH_U 8
-#define AH_HALO 19
-#define AH_HAS_N 1
-"""
-SAMPLE_TAIL = r"""
-__device__ __forceinline__ void ah_pat_0(const u32* h, const u32* l, const AhCtx& c, u32 t) {
-  u32 cl = 0u;
-  cl |= (~h[19] | l[19]);
-  const u32 a0 = (h[0] | l[0]);
-  const u32 a1 = l[1];
-  u32 c1 = ~a0;
-  c1 |= ~a1;
-  u32 cand = c1 & ~cl;
-  if (!cand) return;
-  cand &= ah_valid(c, t, 20u);
-  if (!cand) return;
-  u32 nm[20];
-#pragma unroll
-  for (int j = 0; j < 20; ++j) nm[j] = c.gn[t + j];
-  u32 x, cf = 0u; u32 s0 = 0u; u32 s1 = 0u; u32 s2 = 0u;
-  x = ((h[0] | l[0]) | nm[0]); s2 |= s1 & x; s1 |= s0 & x; s0 |= x;
-  x = (l[1] | nm[1]); s2 |= s1 & x; s1 |= s0 & x; s0 |= x;
-  x = ((~h[19] | l[19]) | nm[19]); cf |= x;
-  const u32 hb = cand & ~(s2 | cf);
-  if (hb) { const u32 lv[2] = {s0, s1}; ah_emit<2>(c, t, hb, lv, 0u, 0u); }
-}
-__device__ __forceinline__ void ah_group_0(ah_lds_uint2* tw, u32 t0, AhCtx c) {
-  for (u32 i = threadIdx.x; i < (u32)AH_TILE; i += AH_BLOCK) {
-    const u32 t = t0 + i;
-    if (t >= c.S) break;
-    u32 h[20], l[20];
-#pragma unroll
-    for (int j = 0; j < 20; ++j) { const uint2 v = tw[i + (u32)j]; h[j] = v.x; l[j] = v.y; }
-    ah_pat_0(h, l, c, t);
-  }
-}
-__device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c) {
-  ah_group_0(tw, t0, c);
-}
+# Run-time specialisations compiled once at build time (through the built
+# library's own generator and hipRTC) so that a mistake in the scan core or
+# the generator fails the build rather than the first call: degenerate sets,
+# N, a clamp and a non-ACGT mask; then several pairs in several groups.
+CHECK = r"""
+import os, sys
+sys.path.insert(0, sys.argv[1])
+from paper_2509_13300_amd import _lib as L
+L.LIB_PATH = sys.argv[2]
+assert L.ah_scan_program_compile([("ACGTNRYSWKMBDHVACG", "NNNNNAAAACGTGCATG", 2, 3)], True) > 1000
+os.environ["AH_SCAN_GROUP"] = "3"
+assert L.ah_scan_program_compile([("ACGTACGTACGTACG", "GGCCAATTGGCCAAT", 0, 0),
+                                  ("ACRTACGTNNGTACGAAT", "GGCYAATTGGSCAATCC", 1, 1),
+                                  ("ACGTACGWACGTACGTACGTAC", "GGCCAATTGGCCAATTAAGG", 3, 0)],
+                                 False) > 1000
 """
 
 
@@ -88,13 +64,6 @@ def _embed(src_path, dst_path):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     _embed(os.path.join(CSRC, "scan_core.hip"), os.path.join(BUILD, "scan_core_src.inc"))
-    # offline check of the run-time-compiled core with a sample program
-    sample = os.path.join(BUILD, "scan_core_check.hip")
-    with open(sample, "w") as f:
-        f.write(SAMPLE_PROGRAM + open(os.path.join(CSRC, "scan_core.hip")).read() + SAMPLE_TAIL)
-    _run([HIPCC, *COMMON, *DEVFLAGS, "--cuda-device-only", "-include", "hip/hip_runtime.h",
-          "-c", sample, "-o",
-          os.path.join(BUILD, "scan_core_check.o")])
     objs = []
     for name in ("ah_kernels.hip", "ah_host.cpp", "ah_stream.cpp", "ah_serve.cpp"):
         src = os.path.join(CSRC, name)
@@ -106,6 +75,8 @@ def build(verbose: bool = False) -> str:
     tmp = lib + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs,
           "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
+    # specialisation check with the new library, in a process of its own
+    _run([sys.executable, "-c", CHECK, ROOT, tmp])
     os.replace(tmp, lib)
     if verbose:
         print("built", lib)

@@ -184,14 +184,15 @@ std::string mism_expr(uint8_t m, int j) {
   }
 }
 
-// Window words per lane and tile of the scan kernel (AH_SCAN_U = 2, 4, 8 or
-// 16; default 4): the tile of AH_BLOCK * U words plus the halo is staged in
-// LDS twice (double buffer), so larger tiles amortise the halo and the
-// per-tile set-up but leave room for fewer workgroups per CU.
+// Window words per lane of the scan kernel (AH_SCAN_U, odd, 3..31; default
+// 19, the fastest measured for the collection workload): each lane converts the U + L - 1 words of its U window words once, so
+// larger U amortises the conversion and the halo, but the tile of
+// AH_BLOCK * U words plus the halo staged in LDS leaves room for fewer
+// workgroups per CU.  Odd U puts the lanes' 8-byte LDS reads in distinct banks.
 int scan_u() {
   const char* e = getenv("AH_SCAN_U");
   const int u = e ? atoi(e) : ah::kScanU;
-  return (u == 2 || u == 4 || u == 8 || u == 16) ? u : ah::kScanU;
+  return (u >= 3 && u <= 31 && (u & 1)) ? u : ah::kScanU;
 }
 
 // ---- v_bitop3_b32 truth tables.  The table of f over operands (S0, S1, S2)
@@ -227,17 +228,196 @@ std::string acc_mism_op(const std::string& acc, uint8_t m, int j) {
   return bitop3(acc, hj(j), lj(j), (uint8_t)(kS0 | tt_mism(m, kS1, kS2)));
 }
 
-// Prefilter of one pattern (pigeonhole): the non-clamp positions whose set is
-// not N are split into `blocks`; a window with at most k mismatches there
-// leaves at least `need` blocks without a mismatch (k + need blocks, each
-// holding at least one position).  need == 0: no prefilter.
-struct FilterPlan {
-  int need = 0;
-  std::vector<std::vector<int>> blocks;
-  double rate = 1.0;  // chance a random window passes (uniform bases)
+// ---- filter codegen over one-hot planes.  In the scan kernel each lane holds,
+// for the words of its windows, the planes pa/pc/pg/pt (bit b set iff that
+// base is A/C/G/T).  The match indicator of a primer position is then one
+// plane (a single base), the complement of one plane (three bases), or the OR
+// of two planes (two bases); N always matches.
+const char* const kPlane[4] = {"pa", "pc", "pg", "pt"};
+
+struct Lit {
+  std::string v;
+  bool neg;
+};
+// A factor of an AND: one literal, or the OR of two.
+struct Factor {
+  Lit a, b;
+  int n;
 };
 
 int set_size(uint8_t m) { return __builtin_popcount(m); }
+
+Factor match_factor(uint8_t m, int j) {
+  const std::string sj = "[" + std::to_string(j) + "]";
+  int bases[4], nb = 0;
+  for (int b = 0; b < 4; ++b)
+    if (m >> b & 1) bases[nb++] = b;
+  Factor f;
+  if (nb == 1) {
+    f.a = {kPlane[bases[0]] + sj, false};
+    f.n = 1;
+  } else if (nb == 3) {
+    int miss = 0;
+    while (m >> miss & 1) ++miss;
+    f.a = {kPlane[miss] + sj, true};
+    f.n = 1;
+  } else {  // nb == 2
+    f.a = {kPlane[bases[0]] + sj, false};
+    f.b = {kPlane[bases[1]] + sj, false};
+    f.n = 2;
+  }
+  return f;
+}
+
+// One v_bitop3_b32 computing acc? & factors (at most 3 literals in total).
+std::string and_op(const std::string& acc, const std::vector<Factor>& fs) {
+  std::vector<Lit> in;
+  if (!acc.empty()) in.push_back({acc, false});
+  for (const Factor& f : fs) {
+    in.push_back(f.a);
+    if (f.n == 2) in.push_back(f.b);
+  }
+  const uint8_t sv[3] = {kS0, kS1, kS2};
+  auto lit = [&](size_t i, bool neg) -> unsigned { return neg ? (uint8_t)~sv[i] : sv[i]; };
+  unsigned tt = 0xff;
+  size_t i = 0;
+  if (!acc.empty()) tt &= lit(i++, false);
+  for (const Factor& f : fs) {
+    if (f.n == 1) {
+      tt &= lit(i++, f.a.neg);
+    } else {
+      tt &= lit(i, f.a.neg) | lit(i + 1, f.b.neg);
+      i += 2;
+    }
+  }
+  std::vector<std::string> v;
+  for (const Lit& l : in) v.push_back(l.v);
+  while (v.size() < 3) v.push_back(v[0]);  // unused operand slots
+  return bitop3(v[0], v[1], v[2], (uint8_t)tt);
+}
+
+// AND of a list of factors as a chain of 3-input operations; returns the
+// statements and the number of operations (0 for an empty list).
+int and_chain(const std::vector<Factor>& fs, const std::string& dst, std::string* out) {
+  std::vector<Factor> one, two;
+  for (const Factor& f : fs) (f.n == 1 ? one : two).push_back(f);
+  size_t i1 = 0, i2 = 0;
+  int ops = 0;
+  std::string acc;
+  while (i1 < one.size() || i2 < two.size()) {
+    std::vector<Factor> take;
+    int slots = acc.empty() ? 3 : 2;
+    if (i2 < two.size()) {
+      take.push_back(two[i2++]);
+      slots -= 2;
+    }
+    while (slots > 0 && i1 < one.size()) {
+      take.push_back(one[i1++]);
+      --slots;
+    }
+    if (out) *out += "  " + std::string(acc.empty() ? "u32 " : "") + dst + " = " + and_op(acc, take) + ";\n";
+    acc = dst;
+    ++ops;
+  }
+  return ops;
+}
+
+// "At least `need` of the B clean indicators k0..k{B-1}" into `dst`; returns
+// the number of operations.  Small cases use full adders (sum = xor3, carry
+// = maj3, one operation each); larger ones a running count of clean blocks.
+int threshold(int B, int need, const std::string& dst, std::string* out) {
+  auto k = [](int i) { return "k" + std::to_string(i); };
+  int ops = 0;
+  auto op = [&](const std::string& d, const std::string& a, const std::string& b,
+                const std::string& c, uint8_t tt) {
+    if (out) *out += "  u32 " + d + " = " + bitop3(a, b, c, tt) + ";\n";
+    ++ops;
+  };
+  const uint8_t kXor3 = kS0 ^ kS1 ^ kS2;
+  const uint8_t kMaj = (kS0 & kS1) | (kS0 & kS2) | (kS1 & kS2);
+  const uint8_t kOr3 = kS0 | kS1 | kS2, kAnd3 = kS0 & kS1 & kS2;
+  if (need == 1 || need == B) {  // OR / AND of all, three at a time
+    const uint8_t tt3 = need == 1 ? kOr3 : kAnd3;
+    std::string acc = k(0);
+    int i = 1;
+    if (B == 1) {
+      op(dst, acc, acc, acc, kS0);
+      return ops;
+    }
+    int step = 0;
+    while (i < B) {
+      const std::string a = k(i), b = i + 1 < B ? k(i + 1) : k(i);
+      const std::string d = (i + 2 >= B) ? dst : dst + "_" + std::to_string(step++);
+      op(d, acc, a, b, tt3);
+      acc = d;
+      i += 2;
+    }
+    return ops;
+  }
+  if (B == 3 && need == 2) {
+    op(dst, k(0), k(1), k(2), kMaj);
+  } else if (B == 4) {
+    op(dst + "_s", k(0), k(1), k(2), kXor3);
+    op(dst + "_y", k(0), k(1), k(2), kMaj);
+    // need 2: y | (s & k3); need 3: y & (s | k3)
+    op(dst, dst + "_y", dst + "_s", k(3),
+       need == 2 ? (uint8_t)(kS0 | (kS1 & kS2)) : (uint8_t)(kS0 & (kS1 | kS2)));
+  } else if (B == 5 && need == 2) {
+    op(dst + "_y", k(0), k(1), k(2), kMaj);
+    op(dst + "_o", k(0), k(1), k(2), kOr3);
+    op(dst + "_t", dst + "_o", k(3), k(4), kMaj);
+    op(dst, dst + "_y", dst + "_t", dst + "_t", kS0 | kS1);
+  } else if (B == 5 && need == 3) {
+    op(dst + "_s1", k(0), k(1), k(2), kXor3);
+    op(dst + "_y1", k(0), k(1), k(2), kMaj);
+    op(dst + "_s2", dst + "_s1", k(3), k(4), kXor3);
+    op(dst + "_y2", dst + "_s1", k(3), k(4), kMaj);
+    op(dst, dst + "_y1", dst + "_y2", dst + "_s2", kMaj);
+  } else if (B == 6 && (need == 2 || need == 3)) {
+    op(dst + "_s1", k(0), k(1), k(2), kXor3);
+    op(dst + "_y1", k(0), k(1), k(2), kMaj);
+    op(dst + "_s2", k(3), k(4), k(5), kXor3);
+    op(dst + "_y2", k(3), k(4), k(5), kMaj);
+    if (need == 2) {  // y1 | y2 | (s1 & s2)
+      op(dst + "_t", dst + "_s1", dst + "_s2", dst + "_s2", kS0 & kS1);
+      op(dst, dst + "_y1", dst + "_y2", dst + "_t", kOr3);
+    } else {  // maj(y1, y2, s1 | s2)
+      op(dst + "_t", dst + "_s1", dst + "_s2", dst + "_s2", kS0 | kS1);
+      op(dst, dst + "_y1", dst + "_y2", dst + "_t", kMaj);
+    }
+  } else {
+    // y_j: at least j clean among the blocks so far
+    std::vector<std::string> y(need + 1);
+    for (int j = 1; j <= need; ++j) y[j] = dst + "_y" + std::to_string(j);
+    op(y[1], k(0), k(0), k(0), kS0);
+    for (int j = 2; j <= need; ++j) {
+      if (out) *out += "  u32 " + y[j] + " = 0u;\n";
+    }
+    for (int b = 1; b < B; ++b) {
+      for (int j = need; j >= 2; --j) {
+        if (out) *out += "  " + y[j] + " = " + bitop3(y[j], y[j - 1], k(b), kS0 | (kS1 & kS2)) + ";\n";
+        ++ops;
+      }
+      if (out) *out += "  " + y[1] + " |= " + k(b) + ";\n";
+      ++ops;
+    }
+    if (out) *out += "  u32 " + dst + " = " + y[need] + ";\n";
+  }
+  return ops;
+}
+
+// Filter of one pattern.  mode 1 (pigeonhole): the non-clamp, non-N positions
+// are split into k + need blocks; a window with at most k mismatches there
+// leaves at least `need` of them clean.  mode 0 (exact): the bit-sliced
+// mismatch count itself, for patterns whose blocks would pass too many
+// windows.  In both modes the clamp positions must match.
+struct FilterPlan {
+  int mode = 0;
+  int need = 0;
+  std::vector<std::vector<int>> blocks;
+  double rate = 1.0;  // chance a random window passes (uniform bases)
+  double cost = 0.0;  // estimated lane operations per window word
+};
 
 // P(at least `need` of the independent events with probabilities p occur)
 double at_least(const std::vector<double>& p, int need) {
@@ -254,26 +434,51 @@ double at_least(const std::vector<double>& p, int need) {
   return r;
 }
 
+// Cost of candidates: the append branch runs when any lane of the wave has
+// one (64 lanes x 32 windows), and each candidate costs its exact count in
+// the verify kernel (about 8 operations per position, lane-parallel).
+// Weight of candidates against filter operations (AH_SCAN_CAND_WEIGHT,
+// default 10, measured: a candidate's exact count, in its own kernel, costs
+// about ten times the estimate below in filter-equivalent time): larger
+// values choose stronger filters.
+double cand_weight() {
+  const char* e = getenv("AH_SCAN_CAND_WEIGHT");
+  const double w = e ? atof(e) : 10.0;
+  return w > 0 ? w : 10.0;
+}
+
+double cand_cost(double rate, int L) {
+  const double wave = 1.0 - std::pow(1.0 - std::min(rate, 1.0), 32.0 * 64.0);
+  const double per_word = 1.0 - std::pow(1.0 - std::min(rate, 1.0), 32.0);
+  return cand_weight() * (14.0 * wave + per_word * 8.0 * L);
+}
+
 FilterPlan plan_filter(const Pattern& p, bool allow) {
   std::vector<int> free_pos;
+  std::vector<Factor> clampf;
   double clamp_p = 1.0;
-  int clamp_ops = 0, verify_ops = 0;
+  std::vector<double> miss;  // mismatch probabilities of the free positions
+  int exact_ops = 0;
   for (int j = 0; j < p.L; ++j) {
-    if (set_size(p.mask[j]) == 4) continue;
-    verify_ops += (p.clamp_bits >> j & 1u) ? 2 : (int)p.k + 2;
+    const int sz = set_size(p.mask[j]);
+    if (sz == 4) continue;
     if (p.clamp_bits >> j & 1u) {
-      clamp_p *= set_size(p.mask[j]) / 4.0;
-      ++clamp_ops;
+      clamp_p *= sz / 4.0;
+      clampf.push_back(match_factor(p.mask[j], j));
     } else {
       free_pos.push_back(j);
+      miss.push_back(1.0 - sz / 4.0);
+      exact_ops += (int)p.k + 1 + (sz == 2 ? 1 : 0);
     }
   }
+  const int clamp_ops = clampf.empty() ? 0 : and_chain(clampf, "cl", nullptr) + 1;
+  // exact: P(at most k of the free positions mismatch)
+  std::vector<double> mm(miss);
+  const double exact_rate = clamp_p * (1.0 - at_least(mm, (int)p.k + 1));
   FilterPlan best;
-  best.rate = clamp_p;
-  // cost per window word of this pattern, in lane operations: prefilter ops
-  // plus the exact count whenever any lane of the wave has a candidate
-  auto slot = [](double r) { return 1.0 - std::pow(1.0 - std::min(r, 1.0), 32.0 * 64.0); };
-  double best_cost = clamp_ops + slot(clamp_p) * verify_ops;
+  best.mode = 0;
+  best.rate = exact_rate;
+  best.cost = exact_ops + clamp_ops + 2 + cand_cost(exact_rate, p.L);
   if (!allow) return best;
   for (int need = 1; need <= 3; ++need) {
     const int B = (int)p.k + need;
@@ -296,14 +501,22 @@ FilterPlan plan_filter(const Pattern& p, bool allow) {
       bits[at] += std::log2(4.0 / set_size(p.mask[j]));
     }
     std::vector<double> clean(B);
-    for (int b = 0; b < B; ++b) clean[b] = std::exp2(-bits[b]);
+    int ops = 0;
+    for (int b = 0; b < B; ++b) {
+      clean[b] = std::exp2(-bits[b]);
+      std::vector<Factor> fs;
+      for (int j : blocks[b]) fs.push_back(match_factor(p.mask[j], j));
+      ops += and_chain(fs, "k", nullptr);
+    }
+    ops += threshold(B, need, "r", nullptr);
     const double rate = clamp_p * at_least(clean, need);
-    const double cost = clamp_ops + (double)free_pos.size() + 2.0 * need * B + slot(rate) * verify_ops;
-    if (cost < best_cost) {
-      best_cost = cost;
+    const double cost = ops + clamp_ops + 1 + cand_cost(rate, p.L);
+    if (cost < best.cost) {
+      best.mode = 1;
       best.need = need;
       best.blocks = blocks;
       best.rate = rate;
+      best.cost = cost;
     }
   }
   return best;
@@ -317,10 +530,10 @@ int scan_group() {
   return g >= 1 && g <= 1024 ? g : 16;
 }
 
-bool valid_u(int u) { return u == 2 || u == 4 || u == 8 || u == 16; }
+bool valid_u(int u) { return u >= 3 && u <= 31 && (u & 1); }
 
 struct Tuning {
-  int u;      // window words per lane and tile
+  int u;      // window words per lane (odd) and tile
   int group;  // patterns per group
 };
 
@@ -331,114 +544,135 @@ bool filter_enabled() {
   return !(e && e[0] == '0');
 }
 
+// Filter of pattern i over one-hot planes: returns the candidate windows.
+std::string gen_filter(size_t i, const Pattern& p, const FilterPlan& fp) {
+  char buf[512];
+  snprintf(buf, sizeof buf,
+           "// pattern %zu: pair %u primer %u strand %u, L %d, k %u, %s (random pass rate %.3g, "
+           "~%.1f ops per window word)\n"
+           "__device__ __forceinline__ u32 ah_pf_%zu(const u32* pa, const u32* pc, const u32* pg,"
+           " const u32* pt) {\n",
+           i, p.pair, p.primer, p.strand, p.L, p.k,
+           fp.mode ? ("prefilter: " + std::to_string(fp.need) + " of " +
+                      std::to_string(fp.blocks.size()) + " blocks").c_str()
+                   : "exact count",
+           fp.rate, fp.cost, i);
+  std::string s = buf;
+  std::vector<Factor> clampf;
+  for (int j = 0; j < p.L; ++j)
+    if ((p.clamp_bits >> j & 1u) && set_size(p.mask[j]) < 4) clampf.push_back(match_factor(p.mask[j], j));
+  if (!clampf.empty()) and_chain(clampf, "cl", &s);
+  std::string r;
+  if (fp.mode == 1) {
+    const int B = (int)fp.blocks.size();
+    for (int b = 0; b < B; ++b) {
+      std::vector<Factor> fs;
+      for (int j : fp.blocks[b]) fs.push_back(match_factor(p.mask[j], j));
+      and_chain(fs, "k" + std::to_string(b), &s);
+    }
+    threshold(B, fp.need, "r", &s);
+    r = "r";
+  } else {
+    // bit-sliced count: s_m set iff more than m mismatches so far; a
+    // position's mismatch is the complement of its match factor
+    const int K = (int)p.k;
+    for (int m = 0; m <= K; ++m) s += "  u32 s" + std::to_string(m) + " = 0u;\n";
+    for (int j = 0; j < p.L; ++j) {
+      if ((p.clamp_bits >> j & 1u) || set_size(p.mask[j]) == 4) continue;
+      Factor f = match_factor(p.mask[j], j);
+      Lit x;  // mismatch literal
+      if (f.n == 1) {
+        x = {f.a.v, !f.a.neg};
+      } else {
+        s += "  const u32 x" + std::to_string(j) + " = " +
+             bitop3(f.a.v, f.b.v, f.a.v, (uint8_t)~(kS0 | kS1)) + ";\n";
+        x = {"x" + std::to_string(j), false};
+      }
+      const uint8_t xv = x.neg ? (uint8_t)~kS2 : kS2;
+      for (int m = K; m >= 1; --m) {
+        const std::string sm = "s" + std::to_string(m), sp = "s" + std::to_string(m - 1);
+        s += "  " + sm + " = " + bitop3(sm, sp, x.v, (uint8_t)(kS0 | (kS1 & xv))) + ";\n";
+      }
+      s += "  s0 = " + bitop3("s0", x.v, x.v, (uint8_t)(kS0 | (x.neg ? (uint8_t)~kS1 : kS1))) + ";\n";
+    }
+    s += "  u32 r = ~s" + std::to_string(K) + ";\n";
+    r = "r";
+  }
+  if (!clampf.empty()) s += "  return " + r + " & cl;\n}\n";
+  else s += "  return " + r + ";\n}\n";
+  return s;
+}
+
+// Exact count of pattern i for the candidate windows `cand` at window word t
+// (h, l: the L words from t on), and append of the binding sites.
+std::string gen_exact(size_t i, const Pattern& p, bool has_n) {
+  const int K = (int)p.k;
+  char buf[512];
+  snprintf(buf, sizeof buf,
+           "__device__ __forceinline__ u32 ah_ex_%zu(const u32* h, const u32* l, const AhCtx& c,"
+           " u32 t, u32 cand, AhHitRec* out, u64 cap, u64 slot, bool emit) {\n"
+           "  cand &= ah_valid(c, t, %du);\n  if (!cand) return 0u;\n",
+           i, p.L);
+  std::string s = buf;
+  if (has_n) {
+    snprintf(buf, sizeof buf,
+             "  u32 nm[%d];\n#pragma unroll\n  for (int j = 0; j < %d; ++j) nm[j] = c.gn[t + j];\n",
+             p.L, p.L);
+    s += buf;
+  }
+  s += "  u32 x, cf = 0u;\n";
+  for (int m = 0; m <= K; ++m) s += "  u32 s" + std::to_string(m) + " = 0u;\n";
+  for (int j = 0; j < p.L; ++j) {
+    const bool isN = set_size(p.mask[j]) == 4;
+    if (isN && !has_n) continue;
+    std::string e = isN ? std::string("0u") : mism_op(p.mask[j], j);
+    if (has_n) e = isN ? "nm[" + std::to_string(j) + "]" : "(" + e + " | nm[" + std::to_string(j) + "])";
+    s += "  x = " + e + ";";
+    if (p.clamp_bits >> j & 1u) {
+      s += " cf |= x;\n";  // a clamp mismatch rejects the window outright
+      continue;
+    }
+    for (int m = K; m >= 1; --m) {
+      const std::string sm = "s" + std::to_string(m), sp = "s" + std::to_string(m - 1);
+      s += " " + sm + " = " + bitop3(sm, sp, "x", (uint8_t)(kS0 | (kS1 & kS2))) + ";";
+    }
+    s += " s0 |= x;\n";
+  }
+  snprintf(buf, sizeof buf, "  const u32 hb = cand & ~(s%d | cf);\n", K);
+  s += buf;
+  if (K == 0) {
+    snprintf(buf, sizeof buf,
+             "  if (hb && emit) { const u32 lv[1] = {0u}; ah_emit<0>(c, out, cap, slot, t, hb, lv, %uu, "
+             "%uu); }\n  return (u32)__popc(hb);\n}\n",
+             p.pair, (p.strand << 1) | p.primer);
+  } else {
+    std::string lv = "s0";
+    for (int m = 1; m < K; ++m) lv += ", s" + std::to_string(m);
+    snprintf(buf, sizeof buf,
+             "  if (hb && emit) { const u32 lv[%d] = {%s}; ah_emit<%d>(c, out, cap, slot, t, hb, lv, "
+             "%uu, %uu); }\n  return (u32)__popc(hb);\n}\n",
+             K, lv.c_str(), K, p.pair, (p.strand << 1) | p.primer);
+  }
+  s += buf;
+  return s;
+}
+
 std::string gen_program(const std::vector<Pattern>& pats, bool has_n, Tuning tn) {
   int lmax = 0;
   for (const Pattern& p : pats) lmax = p.L > lmax ? p.L : lmax;
   const bool allow = filter_enabled();
   std::string s;
-  char buf[640];
-  snprintf(buf, sizeof buf,
-           "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n", tn.u, lmax - 1,
-           has_n ? 1 : 0);
+  char buf[768];
+  snprintf(buf, sizeof buf, "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n", tn.u,
+           lmax - 1, has_n ? 1 : 0);
   std::string head = buf;
   for (size_t i = 0; i < pats.size(); ++i) {
-    const Pattern& p = pats[i];
-    const int K = (int)p.k;
-    const FilterPlan fp = plan_filter(p, allow);
-    // ---- prefilter (hot): clamp positions must match, `need` blocks be clean
-    snprintf(buf, sizeof buf,
-             "// pattern %zu: pair %u primer %u strand %u, L %d, k %d, prefilter: %d of %zu blocks "
-             "(random pass rate %.3g)\n"
-             "__device__ __forceinline__ void ah_pat_%zu(const u32* h, const u32* l, const AhCtx& c,"
-             " u32 t) {\n",
-             i, p.pair, p.primer, p.strand, p.L, K, fp.need, fp.blocks.size(), fp.rate, i);
-    s += buf;
-    // clamp mismatches
-    std::string cl;
-    for (int j = 0; j < p.L; ++j) {
-      if (!(p.clamp_bits >> j & 1u) || set_size(p.mask[j]) == 4) continue;
-      if (cl.empty()) {
-        s += "  u32 cl = " + mism_op(p.mask[j], j) + ";\n";
-        cl = "cl";
-      } else {
-        s += "  cl = " + acc_mism_op("cl", p.mask[j], j) + ";\n";
-      }
-    }
-    std::string cand_expr;
-    if (fp.need > 0) {
-      // a_b: some position of block b mismatches ("dirty")
-      for (size_t b = 0; b < fp.blocks.size(); ++b) {
-        const std::string ab = "a" + std::to_string(b);
-        for (size_t q = 0; q < fp.blocks[b].size(); ++q) {
-          const int j = fp.blocks[b][q];
-          if (q == 0) s += "  u32 " + ab + " = " + mism_op(p.mask[j], j) + ";\n";
-          else s += "  " + ab + " = " + acc_mism_op(ab, p.mask[j], j) + ";\n";
-        }
-      }
-      // z_m: at most m blocks clean so far; a window is a candidate iff
-      // z_{need-1} is clear after the last block (and the clamp matches)
-      const int B = (int)fp.blocks.size();
-      const int need = fp.need;
-      s += "  u32 z0 = a0;\n";
-      for (int m = 1; m < need; ++m) s += "  u32 z" + std::to_string(m) + " = 0xffffffffu;\n";
-      for (int b = 1; b < B; ++b) {
-        const std::string ab = "a" + std::to_string(b);
-        for (int m = need - 1; m >= 1; --m) {
-          // z_m' = (z_m & a_b) | z_{m-1}
-          const std::string zm = "z" + std::to_string(m), zp = "z" + std::to_string(m - 1);
-          s += "  " + zm + " = " + bitop3(zm, ab, zp, (uint8_t)((kS0 & kS1) | kS2)) + ";\n";
-        }
-        if (b < B - 1 || need == 1) s += "  z0 &= " + ab + ";\n";
-      }
-      const std::string zl = "z" + std::to_string(need - 1);
-      cand_expr = cl.empty() ? "~" + zl : bitop3(zl, "cl", zl, (uint8_t)(~(kS0 | kS1)));
-    } else {
-      cand_expr = cl.empty() ? "0xffffffffu" : "~cl";
-    }
-    s += "  u32 cand = " + cand_expr + ";\n  if (!cand) return;\n";
-    // ---- exact count for candidate windows (rare), from the same registers
-    snprintf(buf, sizeof buf, "  cand &= ah_valid(c, t, %du);\n  if (!cand) return;\n", p.L);
-    s += buf;
-    if (has_n) {
-      snprintf(buf, sizeof buf,
-               "  u32 nm[%d];\n#pragma unroll\n  for (int j = 0; j < %d; ++j) nm[j] = c.gn[t + j];\n",
-               p.L, p.L);
-      s += buf;
-    }
-    s += "  u32 x, cf = 0u;\n";
-    for (int m = 0; m <= K; ++m) s += "  u32 s" + std::to_string(m) + " = 0u;\n";
-    for (int j = 0; j < p.L; ++j) {
-      const bool isN = set_size(p.mask[j]) == 4;
-      if (isN && !has_n) continue;
-      std::string e = isN ? std::string("0u") : mism_op(p.mask[j], j);
-      if (has_n) e = isN ? "nm[" + std::to_string(j) + "]" : "(" + e + " | nm[" + std::to_string(j) + "])";
-      s += "  x = " + e + ";";
-      if (p.clamp_bits >> j & 1u) {
-        s += " cf |= x;\n";  // a clamp mismatch rejects the window outright
-        continue;
-      }
-      for (int m = K; m >= 1; --m) {
-        const std::string sm = "s" + std::to_string(m), sp = "s" + std::to_string(m - 1);
-        s += " " + sm + " = " + bitop3(sm, sp, "x", (uint8_t)(kS0 | (kS1 & kS2))) + ";";
-      }
-      s += " s0 |= x;\n";
-    }
-    snprintf(buf, sizeof buf, "  const u32 hb = cand & ~(s%d | cf);\n", K);
-    s += buf;
-    if (K == 0) {
-      snprintf(buf, sizeof buf,
-               "  if (hb) { const u32 lv[1] = {0u}; ah_emit<0>(c, t, hb, lv, %uu, %uu); }\n}\n",
-               p.pair, (p.strand << 1) | p.primer);
-    } else {
-      std::string lv = "s0";
-      for (int m = 1; m < K; ++m) lv += ", s" + std::to_string(m);
-      snprintf(buf, sizeof buf,
-               "  if (hb) { const u32 lv[%d] = {%s}; ah_emit<%d>(c, t, hb, lv, %uu, %uu); }\n}\n", K,
-               lv.c_str(), K, p.pair, (p.strand << 1) | p.primer);
-    }
-    s += buf;
+    s += gen_filter(i, pats[i], plan_filter(pats[i], allow));
+    s += gen_exact(i, pats[i], has_n);
   }
-  // groups of consecutive patterns; one function per group walks the tile
+  // groups of consecutive patterns; one function per group walks the tile:
+  // each lane converts the words of its AH_U window words once and runs
+  // every filter of the group on each window word
   const size_t G = (size_t)tn.group;
   const size_t ngroups = (pats.size() + G - 1) / G;
   for (size_t gi = 0; gi < ngroups; ++gi) {
@@ -446,26 +680,63 @@ std::string gen_program(const std::vector<Pattern>& pats, bool has_n, Tuning tn)
     int lg = 0;
     for (size_t i = a; i < b; ++i) lg = std::max(lg, pats[i].L);
     snprintf(buf, sizeof buf,
-             "__device__ %s void ah_group_%zu(ah_lds_uint2* tw, u32 t0, AhCtx c) {\n"
-             "  for (u32 i = threadIdx.x; i < (u32)AH_TILE; i += AH_BLOCK) {\n"
-             "    const u32 t = t0 + i;\n    if (t >= c.S) break;\n"
-             "    u32 h[%d], l[%d];\n#pragma unroll\n"
-             "    for (int j = 0; j < %d; ++j) { const uint2 v = tw[i + (u32)j]; h[j] = v.x; l[j] = v.y; }\n",
-             ngroups > 1 ? "__noinline__" : "__forceinline__", gi, lg, lg, lg);
+             "__device__ %s void ah_group_%zu(ah_lds_uint2* tw, u32 t0, const AhCtx& c, "
+             "const AhCands& k) {\n"
+             "  const u32 base = threadIdx.x * (u32)AH_U;\n"
+             "  if (t0 + base >= c.S) return;\n"
+             "  u32 pa[AH_U + %d], pc[AH_U + %d], pg[AH_U + %d], pt[AH_U + %d];\n"
+             "#pragma unroll\n"
+             "  for (int w = 0; w < %d; ++w) ah_onehot(tw[base + (u32)w], pa[w], pc[w], pg[w], pt[w]);\n"
+             "  uint2 nxt = tw[base + %du];  // read one step ahead\n"
+             "#pragma unroll\n"
+             "  for (int u = 0; u < AH_U; ++u) {\n"
+             "    ah_onehot(nxt, pa[u + %d], pc[u + %d], pg[u + %d], pt[u + %d]);\n"
+             "    if (u + 1 < AH_U) nxt = tw[base + (u32)u + %du];\n"
+             "    const u32 t = t0 + base + (u32)u;\n    u32 cand;\n",
+             ngroups > 1 ? "__noinline__" : "__forceinline__", gi, lg - 1, lg - 1, lg - 1, lg - 1,
+             lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg);
     s += buf;
-    for (size_t i = a; i < b; ++i) s += "    ah_pat_" + std::to_string(i) + "(h, l, c, t);\n";
+    for (size_t i = a; i < b; ++i) {
+      snprintf(buf, sizeof buf,
+               "    cand = ah_pf_%zu(pa + u, pc + u, pg + u, pt + u);\n"
+               "    if (cand) ah_cand(c, k, t, %zuu, cand);\n",
+               i, i);
+      s += buf;
+    }
     s += "  }\n}\n";
   }
-  s += "__device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c) {\n";
-  for (size_t gi = 0; gi < ngroups; ++gi) s += "  ah_group_" + std::to_string(gi) + "(tw, t0, c);\n";
+  s += "__device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c, const AhCands& k) {\n";
+  for (size_t gi = 0; gi < ngroups; ++gi) s += "  ah_group_" + std::to_string(gi) + "(tw, t0, c, k);\n";
   s += "}\n";
+  // verification: the candidate's words from HBM, then the pattern's count
+  snprintf(buf, sizeof buf,
+           "template <class W>\n"
+           "__device__ u32 ah_verify_one(const AhCtx& c, W w, u32 t, u32 p, u32 cand, AhHitRec* out,"
+           " u64 cap, u64 slot, bool emit) {\n"
+           "  u32 h[%d], l[%d];\n#pragma unroll\n"
+           "  for (int j = 0; j < %d; ++j) { const uint2 v = w[j]; h[j] = v.x; l[j] = v.y; }\n"
+           "  switch (p) {\n",
+           lmax, lmax, lmax);
+  s += buf;
+  for (size_t i = 0; i < pats.size(); ++i) {
+    snprintf(buf, sizeof buf, "    case %zuu: return ah_ex_%zu(h, l, c, t, cand, out, cap, slot, emit);\n",
+             i, i);
+    s += buf;
+  }
+  s += "    default: return 0u;\n  }\n}\n";
   return head + std::string(kScanCore) + s;
 }
 
 // --------------------------------------------------------------- caches --
+// The two kernels of a specialised scan program.
+struct ScanFns {
+  hipFunction_t scan = nullptr;    // filter: appends candidates
+  hipFunction_t verify = nullptr;  // exact count of the candidates: appends sites
+};
+
 struct JitEntry {
   hipModule_t mod = nullptr;
-  hipFunction_t fn = nullptr;
+  ScanFns fn;
 };
 
 std::mutex g_mu;
@@ -507,7 +778,7 @@ ah_status rtc_compile(const std::string& src, std::vector<char>& code) {
 
 // Loaded scan kernel for an already compiled program (cached per device).
 ah_status load_scan_kernel(int dev, const std::string& src, const std::vector<char>& code,
-                           hipFunction_t& fn) {
+                           ScanFns& fn) {
   std::lock_guard<std::mutex> lk(g_mu);
   const auto key = std::make_pair(dev, src);
   auto it = g_jit.find(key);  // another thread may have loaded it meanwhile
@@ -517,7 +788,8 @@ ah_status load_scan_kernel(int dev, const std::string& src, const std::vector<ch
   }
   JitEntry e;
   AH_HIP(hipModuleLoadData(&e.mod, code.data()));
-  AH_HIP(hipModuleGetFunction(&e.fn, e.mod, "ah_scan_kernel"));
+  AH_HIP(hipModuleGetFunction(&e.fn.scan, e.mod, "ah_scan_kernel"));
+  AH_HIP(hipModuleGetFunction(&e.fn.verify, e.mod, "ah_verify_kernel"));
   g_jit[key] = e;
   fn = e.fn;
   return AH_OK;
@@ -526,7 +798,7 @@ ah_status load_scan_kernel(int dev, const std::string& src, const std::vector<ch
 // Compiled and loaded scan kernel for `src` on the current device (cached;
 // compiles outside the cache lock so that several programs can compile at
 // once).
-ah_status get_scan_kernel(const std::string& src, hipFunction_t& fn) {
+ah_status get_scan_kernel(const std::string& src, ScanFns& fn) {
   int dev = 0;
   AH_HIP(hipGetDevice(&dev));
   {
@@ -663,10 +935,44 @@ struct Carver {
 struct ScanWs {
   uint64_t *counts, *tile_prefix, *scan_tmp, *n_sort;
   ah_hit* staging;
+  uint4* cands;         // filter output: {genome, window word, pattern, window mask}
+  uint32_t* slice_cnt;  // [kMaxScanGrid] candidates kept per workgroup
+  uint64_t* cstat;      // [0] candidates, [1] windows in them, [2] full slices, [3] most per workgroup
+  uint64_t ccap;
   ah::SortBuffers sb;
 };
 
-ScanWs carve_scan(Carver& c, uint32_t n, uint64_t cap) {
+// Workgroups of the scan's filter at most (each owns a slice of the list).
+constexpr uint32_t kMaxScanGrid = 4096;
+
+// Candidate records the workspace must hold at least: the hit capacity (a
+// candidate holds one or more windows; every window of a site is in one), and
+// at least 2^16.  Extra workspace lengthens the list.
+uint64_t min_cands(uint64_t cap) { return std::max<uint64_t>(cap, 1ull << 16); }
+
+// Candidate records per window word expected from the filters of a primer set
+// (uniform bases).
+double cand_per_word(const std::vector<Pattern>& pats) {
+  const bool allow = filter_enabled();
+  double r = 0.0;
+  for (const Pattern& p : pats) {
+    const double rate = std::min(plan_filter(p, allow).rate, 1.0);
+    r += 1.0 - std::pow(1.0 - rate, 32.0);
+  }
+  return r;
+}
+
+// Recommended list length: twice the expected records over `window_words`
+// window words plus 2^16 (at most 2^28 records unless the hit capacity is
+// larger).
+uint64_t recommended_cands(uint64_t window_words, double per_word, uint64_t cap) {
+  const double e = std::min(2.0 * (double)window_words * per_word + 65536.0, (double)(1ull << 28));
+  return std::max(min_cands(cap), (uint64_t)e);
+}
+
+// Fixed parts first, then the candidate list, which takes `ccap` records or,
+// when ccap is 0, everything up to the end of the workspace.
+ScanWs carve_scan(Carver& c, uint32_t n, uint64_t cap, uint64_t ccap) {
   ScanWs w;
   w.counts = c.take<uint64_t>(n ? n : 1);
   w.tile_prefix = c.take<uint64_t>((uint64_t)n + 1);
@@ -680,7 +986,21 @@ ScanWs carve_scan(Carver& c, uint32_t n, uint64_t cap) {
   w.sb.hist = c.take<uint64_t>((uint64_t)256 * ah::kSortGrid);
   w.sb.hist_off = c.take<uint64_t>((uint64_t)256 * ah::kSortGrid + 1);
   w.sb.scan_tmp = w.scan_tmp;
+  w.cstat = c.take<uint64_t>(4);
+  w.slice_cnt = c.take<uint32_t>(kMaxScanGrid);
+  if (ccap == 0) {
+    const uintptr_t at = (c.cur + 255) & ~(uintptr_t)255;
+    ccap = c.end > at ? (uint64_t)(c.end - at) / sizeof(uint4) : 0;
+  }
+  w.ccap = ccap;
+  w.cands = c.take<uint4>(ccap);
   return w;
+}
+
+size_t scan_ws_bytes(uint32_t n, uint64_t cap, uint64_t ccap) {
+  Carver c(nullptr, 0);
+  carve_scan(c, n, cap, ccap);
+  return c.used();
 }
 
 ah::PairBuffers carve_pair(Carver& c, uint64_t cap) {
@@ -713,30 +1033,64 @@ ah_status check_genomes(const ah_genomes* g) {
 
 // Tile counts, tile prefix and the scan kernel itself (hits appended to the
 // staging area, counted in d_res->required).
-ah_status launch_scan_kernel(hipFunction_t fn, Tuning tn, const ah_genomes* g, const ScanWs& w,
+ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, const ScanWs& w,
                              ah_result* d_res, uint64_t capacity, hipStream_t st) {
   if (g->n == 0) return AH_OK;
-  AH_HIP(ah::launch_tile_counts(g->len, g->n, (uint32_t)(ah::kBlock * tn.u), w.counts, st));
+  const uint32_t tile = (uint32_t)(ah::kBlock * tn.u);
+  AH_HIP(ah::launch_tile_counts(g->len, g->n, tile, w.counts, st));
   AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
+  AH_HIP(ah::launch_zero_u64(w.cstat, 4, st));
+  // persistent grid, no larger than an upper bound on the tiles (so that small
+  // inputs get long slices); each workgroup owns ccap / grid records
+  const uint64_t words_ub = ((uint64_t)g->max_len + 31) / 32;
+  const uint64_t tiles_ub = (uint64_t)g->n * ((words_ub + tile - 1) / tile);
+  const unsigned grid = (unsigned)std::max<uint64_t>(
+      1, std::min<uint64_t>({(uint64_t)cu_count() * 8u, tiles_ub, kMaxScanGrid}));
   const void* words = g->words;
   const uint32_t* nmask = g->nmask;
   const uint64_t* word_off = g->word_off;
   const uint32_t* len = g->len;
   const uint64_t* tp = w.tile_prefix;
   uint32_t n = g->n;
+  uint4* cands = w.cands;
+  uint32_t slice = (uint32_t)std::min<uint64_t>(w.ccap / grid, 0xffffffffu);
+  uint32_t* slice_cnt = w.slice_cnt;
+  uint64_t* cstat = w.cstat;
+  void* args[] = {&words, &nmask, &word_off, &len, &tp, &n, &cands, &slice, &slice_cnt, &cstat};
+  {
+    ProfScope prof_scan("scan", st);
+    AH_HIP(hipModuleLaunchKernel(fn.scan, grid, 1, 1, ah::kBlock, 1, 1, 0, st, args, nullptr));
+  }
   ah_hit* out = w.staging;
   uint64_t cap = capacity;
   uint64_t* counter = &d_res->required;
-  void* args[] = {&words, &nmask, &word_off, &len, &tp, &n, &out, &cap, &counter};
-  const unsigned grid = (unsigned)cu_count() * 8u;
-  ProfScope prof_scan("scan", st);
-  AH_HIP(hipModuleLaunchKernel(fn, grid, 1, 1, ah::kBlock, 1, 1, 0, st, args, nullptr));
+  const uint4* ccands = w.cands;
+  const uint32_t* cslice_cnt = w.slice_cnt;
+  void* vargs[] = {&words, &nmask, &word_off, &len, &ccands, &slice, &cslice_cnt, &out, &cap, &counter};
+  {
+    ProfScope prof_verify("verify", st);
+    AH_HIP(hipModuleLaunchKernel(fn.verify, grid, 1, 1, ah::kBlock, 1, 1, 0, st, vargs, nullptr));
+  }
+  AH_HIP(ah::launch_cand_overflow(w.cstat, grid, d_res, st));
   return AH_OK;
 }
 
 }  // namespace
 
 namespace ah {
+size_t scan_workspace_for(uint32_t n, uint64_t window_words, const ah_primer_pair* pairs,
+                          uint32_t n_pairs, uint64_t capacity) {
+  uint64_t ccap = min_cands(capacity);
+  PairSet ps;
+  if (pairs && n_pairs) {
+    const std::string saved = g_err;  // a sizing query reports no error
+    if (compile_pairs(pairs, n_pairs, ps) == AH_OK)
+      ccap = recommended_cands(window_words, cand_per_word(patterns_of(ps)), capacity);
+    g_err = saved;
+  }
+  return scan_ws_bytes(n, capacity, ccap);
+}
+
 ah_status set_error(ah_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -809,11 +1163,11 @@ ah_status ah_pack_genomes(const uint8_t* d_ascii, const uint64_t* d_ascii_off, u
   return AH_OK;
 }
 
-size_t ah_scan_workspace_bytes(const ah_genomes* g, uint32_t n_pairs, uint64_t capacity) {
-  (void)n_pairs;
-  Carver c(nullptr, 0);
-  carve_scan(c, g ? g->n : 0, capacity);
-  return c.used();
+size_t ah_scan_workspace_bytes(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pairs,
+                               uint64_t capacity) {
+  const uint32_t n = g ? g->n : 0;
+  const uint64_t words = g ? (uint64_t)n * (((uint64_t)g->max_len + 31) / 32) : 0;
+  return ah::scan_workspace_for(n, words, pairs, n_pairs, capacity);
 }
 
 ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pairs,
@@ -830,17 +1184,17 @@ ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint
   if (s) return s;
   ah::KeyBits kb{bits_for(n_pairs - 1), bits_for(g->n ? g->n - 1 : 0), bits_for(g->max_len)};
   if (kb.total() > 64) return fail(AH_ERR_LIMIT, "sort key needs %d > 64 bits", kb.total());
-  const size_t need = ah_scan_workspace_bytes(g, n_pairs, capacity);
+  const size_t need = scan_ws_bytes(g->n, capacity, min_cands(capacity));
   if (!d_work || work_bytes < need)
     return fail(AH_ERR_WORKSPACE, "scan workspace: %zu bytes given, %zu needed", work_bytes, need);
   const Tuning tn = tuning_for(pairs, n_pairs);
-  hipFunction_t fn;
+  ScanFns fn;
   s = get_scan_kernel(gen_program(patterns_of(ps), g->nmask != nullptr, tn), fn);
   if (s) return s;
 
   hipStream_t st = (hipStream_t)stream;
   Carver c(d_work, work_bytes);
-  ScanWs w = carve_scan(c, g->n, capacity);
+  ScanWs w = carve_scan(c, g->n, capacity, 0);
   AH_HIP(ah::launch_result_init(d_res, st));
   s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st);
   if (s) return s;
@@ -1001,7 +1355,7 @@ ah_status ah_scan_prepare(const ah_primer_pair* pairs, uint32_t n_pairs, int has
   PairSet ps;
   ah_status s = compile_pairs(pairs, n_pairs, ps);
   if (s) return s;
-  hipFunction_t fn;
+  ScanFns fn;
   return get_scan_kernel(gen_program(patterns_of(ps), has_nmask != 0, tuning_for(pairs, n_pairs)),
                          fn);
 }
@@ -1022,7 +1376,8 @@ ah_status ah_set_scan_tuning(const ah_primer_pair* pairs, uint32_t n_pairs,
   }
   if (!valid_u((int)tuning->words_per_lane) || tuning->patterns_per_group < 1 ||
       tuning->patterns_per_group > 1024)
-    return fail(AH_ERR_INVALID_ARG, "tuning: words_per_lane in {2,4,8,16}, patterns_per_group in 1..1024");
+    return fail(AH_ERR_INVALID_ARG,
+                "tuning: words_per_lane odd in 3..31, patterns_per_group in 1..1024");
   g_tuning[key] = Tuning{(int)tuning->words_per_lane, (int)tuning->patterns_per_group};
   return AH_OK;
 }
@@ -1051,16 +1406,16 @@ ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uin
   PairSet ps;
   s = compile_pairs(pairs, n_pairs, ps);
   if (s) return s;
-  const size_t need = ah_scan_workspace_bytes(g, n_pairs, capacity);
+  const size_t need = scan_ws_bytes(g->n, capacity, min_cands(capacity));
   if (!d_work || work_bytes < need)
     return fail(AH_ERR_WORKSPACE, "scan workspace: %zu bytes given, %zu needed", work_bytes, need);
   const std::vector<Pattern> pats = patterns_of(ps);
   // candidates: tile words per lane x patterns per group (a single group when
   // the set is small)
   std::vector<Tuning> cand;
-  for (int u : {2, 4, 8})
-    for (int grp : {8, 16, 32}) {
-      if (grp > (int)pats.size() && grp != 8) continue;
+  for (int u : {9, 15})
+    for (int grp : {4, 8, 16}) {
+      if (grp > (int)pats.size() && grp != 4) continue;
       cand.push_back(Tuning{u, std::min(grp, (int)pats.size())});
     }
   // compile every candidate concurrently (host threads), then time each
@@ -1082,7 +1437,7 @@ ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uin
   AH_HIP(hipGetDevice(&dev));
   hipStream_t strm = (hipStream_t)stream;
   Carver c(d_work, work_bytes);
-  ScanWs w = carve_scan(c, g->n, capacity);
+  ScanWs w = carve_scan(c, g->n, capacity, 0);
   hipEvent_t e0, e1;
   AH_HIP(hipEventCreate(&e0));
   AH_HIP(hipEventCreate(&e1));
@@ -1091,7 +1446,7 @@ ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uin
   const uint32_t reps = repeats ? repeats : 3;
   for (size_t i = 0; i < cand.size(); ++i) {
     if (st[i]) return fail(st[i], "%s", errs[i].c_str());
-    hipFunction_t fn;
+    ScanFns fn;
     s = load_scan_kernel(dev, srcs[i], codes[i], fn);
     if (s) return s;
     double total = 0.0;
@@ -1159,6 +1514,17 @@ ah_status ah_profile_query(const char* name, uint64_t* launches, double* total_m
   e.pending.clear();
   if (launches) *launches = e.launches;
   if (total_ms) *total_ms = e.ms;
+  return AH_OK;
+}
+
+ah_status ah_scan_candidate_stats(const void* d_work, size_t work_bytes, uint32_t n_genomes,
+                                  uint64_t capacity, uint64_t out[4]) {
+  g_err.clear();
+  if (!d_work || !out) return fail(AH_ERR_INVALID_ARG, "d_work and out are required");
+  Carver c((void*)d_work, work_bytes);
+  const ScanWs w = carve_scan(c, n_genomes, capacity, 0);
+  AH_HIP(hipDeviceSynchronize());
+  AH_HIP(hipMemcpy(out, w.cstat, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost));
   return AH_OK;
 }
 

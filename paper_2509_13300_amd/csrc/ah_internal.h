@@ -12,7 +12,7 @@ namespace ah {
 constexpr int kBlock = 256;        // threads per workgroup for every kernel
 constexpr int kSortGrid = 256;     // workgroups of the radix-sort passes
 constexpr int kScanGrid = 256;     // workgroups of the generic prefix scan
-constexpr int kScanU = 4;          // default window words per lane per tile in the scan kernel
+constexpr int kScanU = 19;         // default window words per lane (odd) in the scan kernel
 
 // Per-primer table used by the Tm kernel (one per pair and primer).  Oligos
 // are 2-bit codes (A=0 C=1 G=2 T=3), position j of the primer (5'->3') at
@@ -103,6 +103,16 @@ hipError_t launch_gather_view(const uint32_t* ids, uint32_t n, const uint64_t* o
                               uint64_t* out_off, uint32_t* out_len, hipStream_t st);
 hipError_t launch_remap(ah_hit* hits, const ah_result* hres, ah_amplicon* amp, const ah_result* ares,
                         const uint32_t* ids, int grid, hipStream_t st);
+
+// Scan: zero n u64 (graph-capturable, no memset node), and the candidate-list
+// overflow adjustment of a scan result.
+hipError_t launch_zero_u64(uint64_t* p, uint32_t n, hipStream_t st);
+hipError_t launch_cand_overflow(const uint64_t* stat, uint32_t grid, ah_result* res, hipStream_t st);
+
+// Recommended scan workspace for n genomes holding at most `window_words`
+// window words in total (pairs may be null: the minimum).
+size_t scan_workspace_for(uint32_t n, uint64_t window_words, const ah_primer_pair* pairs,
+                          uint32_t n_pairs, uint64_t capacity);
 
 // Error reporting shared by the host sources: records the message returned by
 // ah_last_error() on this thread and returns s.

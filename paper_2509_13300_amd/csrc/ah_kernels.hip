@@ -631,6 +631,22 @@ __global__ __launch_bounds__(kBlock) void k_remap(ah_hit* __restrict__ hits,
     amp[i].genome = ids[amp[i].genome];
 }
 
+// ---- scan: candidate-list overflow -------------------------------------
+// stat: [0] candidates, [1] windows in them, [2] workgroups whose slice of the
+// list was full, [3] most candidates of one workgroup.  A full slice means
+// lost candidates: raise `required` to at least the windows in all
+// candidates (an upper bound on the sites) and grid x the fullest workgroup's
+// candidates (which exceeds the capacity, since the slice was ccap / grid >=
+// capacity / grid).  A call with that capacity gets slices long enough for
+// every workgroup (the tiles map to workgroups the same way) and finds all
+// sites.
+__global__ void k_cand_overflow(const u64* __restrict__ stat, u32 grid, ah_result* r) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && stat[2] > 0) {
+    u64 bound = stat[1] > (u64)grid * stat[3] ? stat[1] : (u64)grid * stat[3];
+    if (bound > r->required) r->required = bound;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------- launchers ----
@@ -759,6 +775,16 @@ hipError_t launch_gather_view(const uint32_t* ids, uint32_t n, const uint64_t* o
 hipError_t launch_remap(ah_hit* hits, const ah_result* hres, ah_amplicon* amp, const ah_result* ares,
                         const uint32_t* ids, int grid, hipStream_t st) {
   k_remap<<<grid, kBlock, 0, st>>>(hits, hres, amp, ares, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(uint64_t* p, uint32_t n, hipStream_t st) {
+  k_zero_u64<<<1, 64, 0, st>>>((u64*)p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_overflow(const uint64_t* stat, uint32_t grid, ah_result* res, hipStream_t st) {
+  k_cand_overflow<<<1, 64, 0, st>>>((const u64*)stat, grid, res);
   return hipGetLastError();
 }
 

@@ -122,6 +122,7 @@ class Pool {
 struct Part {
   uint32_t g0 = 0, g1 = 0;  // indices into the job's genome list
   uint64_t bases = 0;
+  uint64_t words = 0;       // window words of its genomes
   uint32_t max_len = 1;
   uint64_t hcap = 0, acap = 0;
   uint64_t n_hits = 0, n_amps = 0;       // records of a done part
@@ -155,7 +156,7 @@ struct PartSizes {
   uint64_t total, res, hits, amps, ids, off, len, scan_ws, pair_ws;
 };
 
-PartSizes part_sizes(const Part& p) {
+PartSizes part_sizes(const Part& p, const ah_primer_pair* pair) {
   PartSizes s{};
   const uint32_t n = p.g1 - p.g0;
   s.res = align256(2 * sizeof(ah_result));
@@ -164,9 +165,7 @@ PartSizes part_sizes(const Part& p) {
   s.ids = align256((uint64_t)n * 4);
   s.off = align256(((uint64_t)n + 1) * 8);
   s.len = align256((uint64_t)n * 4);
-  ah_genomes probe{};
-  probe.n = n;
-  s.scan_ws = align256(ah_scan_workspace_bytes(&probe, 1, p.hcap));
+  s.scan_ws = align256(ah::scan_workspace_for(n, p.words, pair, 1, p.hcap));
   s.pair_ws = align256(ah_pair_workspace_bytes(p.hcap, 1));
   s.total = s.res + s.hits + s.amps + s.ids + s.off + s.len + s.scan_ws + s.pair_ws;
   return s;
@@ -417,7 +416,7 @@ struct ah_server {
           continue;
         }
         const uint32_t cpi = cand->redo.empty() ? (uint32_t)cand->next : cand->redo.front();
-        z = part_sizes(cand->parts[cpi]);
+        z = part_sizes(cand->parts[cpi], &cand->pair);
         if (z.total > pool.bytes()) {
           cand->status = ah::set_error(AH_ERR_LIMIT, "a part needs %llu bytes > pool %llu",
                                        (unsigned long long)z.total,
@@ -591,6 +590,7 @@ ah_status ah_server_submit(ah_server* srv, const ah_job* job, uint64_t* job_id) 
     }
     cur.g1 = i + 1;
     cur.bases += L;
+    cur.words += ((uint64_t)L + 31) / 32;
     cur.max_len = std::max(cur.max_len, L);
     j->bases += L;
   }

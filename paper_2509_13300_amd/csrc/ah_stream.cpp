@@ -50,8 +50,8 @@ struct Layout {
   uint32_t max_g;
 };
 
-Layout layout(const ah_host_genomes* hg, const ah_stream_config* cfg, uint32_t n_pairs,
-              uint64_t hit_capacity) {
+Layout layout(const ah_host_genomes* hg, const ah_stream_config* cfg, const ah_primer_pair* pairs,
+              uint32_t n_pairs, uint64_t hit_capacity) {
   Layout L{};
   L.max_g = max_genomes_per_slot(cfg->chunk_words);
   L.slot_words = align256(cfg->chunk_words * 8);
@@ -61,9 +61,8 @@ Layout layout(const ah_host_genomes* hg, const ah_stream_config* cfg, uint32_t n
   L.g_len = align256((uint64_t)std::max<uint32_t>(hg->n, 1) * 4);
   L.g_off = align256(((uint64_t)hg->n + 1) * 8);
   L.res = align256(2 * sizeof(ah_result));
-  ah_genomes probe{};
-  probe.n = L.max_g;
-  L.scan_ws = align256(ah_scan_workspace_bytes(&probe, n_pairs, hit_capacity));
+  L.scan_ws =
+      align256(ah::scan_workspace_for(L.max_g, cfg->chunk_words, pairs, n_pairs, hit_capacity));
   L.pair_ws = align256(ah_pair_workspace_bytes(hit_capacity, n_pairs));
   L.total = L.slots + L.g_len + L.g_off + L.res + L.scan_ws + L.pair_ws + 256;
   return L;
@@ -129,9 +128,10 @@ struct Drain {
 extern "C" {
 
 size_t ah_stream_workspace_bytes(const ah_host_genomes* hg, const ah_stream_config* cfg,
-                                 uint32_t n_pairs, uint64_t hit_capacity) {
+                                 const ah_primer_pair* pairs, uint32_t n_pairs,
+                                 uint64_t hit_capacity) {
   if (!hg || !cfg || cfg->n_slots < 2 || cfg->n_slots > kMaxSlots) return 0;
-  return (size_t)layout(hg, cfg, n_pairs, hit_capacity).total;
+  return (size_t)layout(hg, cfg, pairs, n_pairs, hit_capacity).total;
 }
 
 ah_status ah_stream_query(const ah_host_genomes* hg, const ah_stream_config* cfg,
@@ -152,7 +152,9 @@ ah_status ah_stream_query(const ah_host_genomes* hg, const ah_stream_config* cfg
     return ah::set_error(AH_ERR_INVALID_ARG, "copy_streams is NULL");
   s = ah_validate_pairs(pairs, n_pairs);
   if (s) return s;
-  const Layout L = layout(hg, cfg, n_pairs, hit_capacity);
+  // the minimum layout; the scan workspace comes last and takes whatever the
+  // caller gave beyond it (a longer candidate list)
+  const Layout L = layout(hg, cfg, nullptr, n_pairs, hit_capacity);
   if (!d_work || work_bytes < L.total)
     return ah::set_error(AH_ERR_WORKSPACE, "stream workspace: %zu bytes given, %llu needed",
                          work_bytes, (unsigned long long)L.total);
@@ -185,9 +187,10 @@ ah_status ah_stream_query(const ah_host_genomes* hg, const ah_stream_config* cfg
   p += L.g_off;
   ah_result* d_cres = (ah_result*)p;  // [0] hits, [1] amplicons of the current chunk
   p += L.res;
-  void* scan_ws = (void*)p;
-  p += L.scan_ws;
   void* pair_ws = (void*)p;
+  p += L.pair_ws;
+  void* scan_ws = (void*)p;
+  const size_t scan_bytes = (size_t)((uintptr_t)d_work + work_bytes - p);
 
   Drain drain{compute, copies, slots};
   for (Slot& sl : slots) AH_HIP(hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming));
@@ -237,7 +240,7 @@ ah_status ah_stream_query(const ah_host_genomes* hg, const ah_stream_config* cfg
     const uint64_t hcap = hit_capacity - hoff, acap = amp_capacity - aoff;
     ah_hit* hits = hcap ? d_hits + hoff : nullptr;
     ah_amplicon* amps = acap ? d_amp + aoff : nullptr;
-    s = ah_scan_primers(&view, pairs, n_pairs, hits, hcap, &d_cres[0], scan_ws, L.scan_ws, compute);
+    s = ah_scan_primers(&view, pairs, n_pairs, hits, hcap, &d_cres[0], scan_ws, scan_bytes, compute);
     if (s) return s;
     s = ah_tm(&view, pairs, n_pairs, tm, hits, &d_cres[0], hcap, compute);
     if (s) return s;

@@ -69,11 +69,14 @@ class QueryBuffers:
     amp_cap: int
 
 
-def alloc(coll: PackedCollection, n_pairs: int, hit_cap: int, amp_cap: int, device) -> QueryBuffers:
+def alloc(coll: PackedCollection, pairs, hit_cap: int, amp_cap: int, device) -> QueryBuffers:
+    """Buffers for queries of `pairs` (a pair list, sizing the scan's candidate
+    list for their filters; or a pair count, for the minimum)."""
     import torch
 
     g = coll.view()
-    sw = L.ah_scan_workspace_bytes(g, n_pairs, hit_cap)
+    n_pairs = pairs if isinstance(pairs, int) else len(pairs)
+    sw = L.ah_scan_workspace_bytes(g, pairs, hit_cap)
     pw = L.ah_pair_workspace_bytes(hit_cap, n_pairs)
     return QueryBuffers(
         hits=torch.empty(max(hit_cap, 1) * 16, dtype=torch.uint8, device=device),
@@ -163,12 +166,12 @@ class StreamBuffers:
     cfg: L.ah_stream_config
 
 
-def stream_alloc(hg: L.HostGenomes, n_pairs: int, hit_cap: int, amp_cap: int, device,
+def stream_alloc(hg: L.HostGenomes, pairs, hit_cap: int, amp_cap: int, device,
                  chunk_words: int, n_slots: int = 3) -> StreamBuffers:
     import torch
 
     cfg = L.stream_config(chunk_words, n_slots)
-    wb = L.ah_stream_workspace_bytes(hg, cfg, n_pairs, hit_cap)
+    wb = L.ah_stream_workspace_bytes(hg, cfg, pairs, hit_cap)
     return StreamBuffers(
         hits=torch.empty(max(hit_cap, 1) * 16, dtype=torch.uint8, device=device),
         hit_res=torch.zeros(24, dtype=torch.uint8, device=device),

@@ -26,7 +26,7 @@ def run_gpu(p, pairs, dev, hit_cap=1 << 16, amp_cap=1 << 16, with_nmask=None, tm
         with_nmask = p.nrun_genome.size > 0
     ascii, off = gpu.fill_cuda(p, dev)
     coll, _ = path.pack(ascii, off, p.lengths, with_nmask=with_nmask)
-    buf = path.alloc(coll, len(pairs), hit_cap, amp_cap, dev)
+    buf = path.alloc(coll, pairs, hit_cap, amp_cap, dev)
     path.run(coll, pairs, buf, tm=tm, filter_tm=filter_tm, min_tm=min_tm)
     torch.cuda.synchronize()
     return coll, buf

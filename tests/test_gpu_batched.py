@@ -38,7 +38,7 @@ def run_all(coll, pairs, dev):
 
     from paper_2509_13300_amd import path
 
-    buf = path.alloc(coll, len(pairs), 1 << 20, 1 << 20, dev)
+    buf = path.alloc(coll, pairs, 1 << 20, 1 << 20, dev)
     path.run(coll, pairs, buf)
     torch.cuda.synchronize()
     assert path.result(buf.hit_res)["status"] == 0
@@ -73,7 +73,7 @@ def test_batched_matches_oracle_on_two_pairs(batch, dev):
     assert amp_tuples(ab) == amp_tuples(oa)
 
 
-@pytest.mark.parametrize("shape", [(2, 1), (4, 3), (8, 16), (16, 32), (4, 5)])
+@pytest.mark.parametrize("shape", [(3, 1), (7, 3), (9, 16), (15, 32), (5, 5), (31, 4)])
 def test_every_kernel_shape_gives_the_same_result(batch, dev, shape):
     from paper_2509_13300_amd import _lib as L
 
@@ -96,12 +96,12 @@ def test_autotuner_choice_changes_nothing(batch, dev):
 
     p, pairs, coll = batch
     ref = run_all(coll, pairs, dev)
-    buf = path.alloc(coll, len(pairs), 1 << 20, 1 << 20, dev)
+    buf = path.alloc(coll, pairs, 1 << 20, 1 << 20, dev)
     shape, ms = L.ah_autotune_scan(path.subset_view(coll, 3), L.primer_pairs(pairs), buf.hits,
                                    buf.hit_cap, buf.hit_res, buf.scan_work, repeats=2)
     torch.cuda.synchronize()
     say("autotuned", shape, ms)
-    assert shape[0] in (2, 4, 8) and 1 <= shape[1] <= 32 and ms > 0
+    assert shape[0] in (9, 15) and 1 <= shape[1] <= 16 and ms > 0
     assert L.ah_get_scan_tuning(pairs) == shape
     got = run_all(coll, pairs, dev)
     L.ah_set_scan_tuning(pairs, None)
@@ -114,7 +114,7 @@ def test_graph_replay_equals_eager(batch, dev):
     from paper_2509_13300_amd import path
 
     p, pairs, coll = batch
-    buf = path.alloc(coll, len(pairs), 1 << 20, 1 << 20, dev)
+    buf = path.alloc(coll, pairs, 1 << 20, 1 << 20, dev)
     path.run(coll, pairs, buf)
     torch.cuda.synchronize()
     eager_h, eager_a = path.hits_numpy(buf), path.amps_numpy(buf)

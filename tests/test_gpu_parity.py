@@ -169,6 +169,39 @@ def test_overflow_reports_required_and_retry_is_identical(dev):
     assert np.array_equal(path.amps_numpy(again), famp)
 
 
+def test_candidate_list_overflow_reports_bound_and_retry_is_identical(dev):
+    """The filter's candidate list split over its workgroups: with the minimum
+    workspace, a dense pair fills some workgroup's share; the call reports
+    overflow with a bound, and a call with that capacity gives the full
+    result."""
+    import torch
+
+    from paper_2509_13300_amd import path
+
+    pr = plan.PairSpec("AAAAAAAC", "AAAAAAAG", k=2, clamp=0, min_len=8, max_len=20)
+    p = plan.tiny(79, n_genomes=1, len_lo=2_000_000, len_hi=2_000_001, pair=pr, n_copies=(0, 0),
+                  gc_lo=0.0, gc_hi=0.1)
+    ascii, off = gpu.fill_cuda(p, dev)
+    coll, _ = path.pack(ascii, off, p.lengths)
+    ref = path.alloc(coll, [pr], 1 << 22, 1 << 22, dev)  # recommended workspace
+    path.run(coll, [pr], ref)
+    small = path.alloc(coll, 1, 1 << 16, 1 << 22, dev)   # minimum workspace
+    path.run(coll, [pr], small)
+    torch.cuda.synchronize()
+    full, famp = path.hits_numpy(ref), path.amps_numpy(ref)
+    r = path.result(small.hit_res)
+    say("dense pair sites", full.size, "minimum-workspace result", r)
+    assert path.result(ref.hit_res)["status"] == 0 and path.result(ref.amp_res)["status"] == 0
+    assert full.size > 100_000
+    assert r["status"] == -4 and r["required"] >= full.size
+    again = path.alloc(coll, 1, r["required"], 1 << 22, dev)
+    path.run(coll, [pr], again)
+    torch.cuda.synchronize()
+    assert path.result(again.hit_res)["status"] == 0
+    assert np.array_equal(path.hits_numpy(again), full)
+    assert np.array_equal(path.amps_numpy(again), famp)
+
+
 def test_tm_filter_on_matches_oracle(dev):
     pr = plan.PairSpec("GCGTACRYTCCAGTAGC", "GATCGNATCGGCTAAC", k=3, clamp=2, min_len=40,
                        max_len=2000)
@@ -261,7 +294,7 @@ def test_windows_with_exactly_k_mismatches_are_all_found(dev, k):
             planted.append((g, pos, strand, q % 2, m))
         seqs.append("".join(s))
     coll = _host_collection(seqs, dev)
-    buf = path.alloc(coll, 1, 1 << 18, 1 << 18, dev)
+    buf = path.alloc(coll, [pr], 1 << 18, 1 << 18, dev)
     path.run(coll, [pr], buf)
     import torch
 

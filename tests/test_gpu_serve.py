@@ -54,7 +54,7 @@ def direct(c, ids, pair, dev):
     from paper_2509_13300_amd import path
 
     sub = subset_collection(c, ids)
-    buf = path.alloc(sub, 1, 1 << 22, 1 << 22, dev)
+    buf = path.alloc(sub, [pair], 1 << 22, 1 << 22, dev)
     path.run(sub, [pair], buf)
     torch.cuda.synchronize()
     h, a = path.hits_numpy(buf), path.amps_numpy(buf)

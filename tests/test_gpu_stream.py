@@ -39,7 +39,7 @@ def resident(c, pairs, dev, hit_cap=1 << 18, amp_cap=1 << 18):
 
     from paper_2509_13300_amd import path
 
-    buf = path.alloc(c, len(pairs), hit_cap, amp_cap, dev)
+    buf = path.alloc(c, pairs, hit_cap, amp_cap, dev)
     path.run(c, pairs, buf)
     torch.cuda.synchronize()
     return path.hits_numpy(buf), path.amps_numpy(buf), path.result(buf.hit_res), \
@@ -51,7 +51,7 @@ def streamed(hg, pairs, dev, chunk_words, n_slots, n_copy, hit_cap=1 << 18, amp_
 
     from paper_2509_13300_amd import path
 
-    buf = path.stream_alloc(hg, len(pairs), hit_cap, amp_cap, dev, chunk_words, n_slots)
+    buf = path.stream_alloc(hg, pairs, hit_cap, amp_cap, dev, chunk_words, n_slots)
     copies = [torch.cuda.Stream(dev) for _ in range(n_copy)]
     path.stream_run(hg, pairs, buf, copy_streams=copies)
     torch.cuda.synchronize()
@@ -131,7 +131,7 @@ def test_empty_collection(dev):
 
     hg = L.HostGenomes(torch.zeros(2, dtype=torch.int32, pin_memory=True), np.zeros(1, np.uint64),
                        np.zeros(0, np.uint32))
-    buf = path.stream_alloc(hg, 1, 16, 16, dev, 4096, 2)
+    buf = path.stream_alloc(hg, [PAIR], 16, 16, dev, 4096, 2)
     buf.hit_res.fill_(0xFF)
     path.stream_run(hg, [PAIR], buf)
     torch.cuda.synchronize()

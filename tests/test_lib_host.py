@@ -65,39 +65,50 @@ def test_primer_validation(fwd, rev, k, clamp, status):
         assert L.ah_last_error()
 
 
+def _functions(src, i):
+    body = src.split("---- generated pattern program follows ----")[1]
+    pf = body.split(f"u32 ah_pf_{i}(")[1].split("\n}\n")[0]
+    ex = body.split(f"u32 ah_ex_{i}(")[1].split("\n}\n")[0]
+    return pf, ex
+
+
+def _positions(text):
+    return {int(m) for m in re.findall(r"\bp[acgt]\[(\d+)\]", text)}
+
+
 def test_generated_program_tests_every_non_n_position():
     src = L.ah_scan_program_source([("ACGTNRYSWKMBDHV", "NNNNNAAAAC", 1, 2)])
-    body = src.split("---- generated pattern program follows ----")[1]
-    pat0 = body.split("void ah_pat_0")[1].split("void ah_pat_1")[0]
-    pre, exact0 = pat0.split("ah_valid(c, t, ")
-    assert exact0.startswith("15u)")
-    assert exact0.count("x = ") == 15 - 1  # the N position is never a mismatch
-    assert exact0.count("cf |= x") == 2
-    # a degenerate, low-information primer gets no block prefilter: only the
-    # two clamp positions (13, 14) are tested before the exact count
-    assert set(int(m) for m in re.findall(r"h\[(\d+)\]", pre)) == {13, 14}
-    assert "u32 a0" not in pre
-    # a specific primer: every non-N, non-clamp position lands in some block
+    pf, ex = _functions(src, 0)
+    # the exact count tests every position but the N, the clamp ones into cf
+    assert ex.count("ah_valid(c, t, 15u)") == 1
+    assert ex.count("x = ") == 15 - 1
+    assert ex.count("cf |= x") == 2
+    # the filter reads every non-N position, the two clamp ones (13, 14) into
+    # the clamp chain
+    assert _positions(pf) == set(range(15)) - {4}
+    clamp = {int(m) for ln in pf.splitlines() if ln.strip().startswith(("u32 cl", "cl ="))
+             for m in re.findall(r"\[(\d+)\]", ln)}
+    assert clamp == {13, 14}
+    # a specific primer gets pigeonhole blocks over exactly its free positions
     src = L.ah_scan_program_source([("ACGTACCGATNGCATTGGCAKT", "GGATCCAAGTTCGACGT", 2, 3)])
     body = src.split("---- generated pattern program follows ----")[1]
-    pat0 = body.split("void ah_pat_0")[1].split("void ah_pat_1")[0]
-    pre = pat0.split("ah_valid(c, t, ")[0]
-    clamp = {int(m) for ln in pre.splitlines() if ln.strip().startswith(("u32 cl", "cl ="))
-             for m in re.findall(r"h\[(\d+)\]", ln)}
+    assert re.search(r"pattern 0: .*prefilter: [123] of [345] blocks", body)
+    pf, _ = _functions(src, 0)
+    blocks = {int(m) for ln in pf.splitlines() if re.match(r"\s+(u32 )?k\d+ =", ln)
+              for m in re.findall(r"\[(\d+)\]", ln)}
+    assert blocks == set(range(19)) - {10}
+    clamp = {int(m) for ln in pf.splitlines() if ln.strip().startswith(("u32 cl", "cl ="))
+             for m in re.findall(r"\[(\d+)\]", ln)}
     assert clamp == {19, 20, 21}
-    positions = {int(m) for ln in pre.splitlines() if ln.strip().startswith(("u32 a", "a"))
-                 for m in re.findall(r"h\[(\d+)\]", ln)}
-    assert positions == set(range(19)) - {10}
-    assert "if (!cand) return;" in pat0
 
 
 def test_prefilter_can_be_switched_off(monkeypatch):
     monkeypatch.setenv("AH_SCAN_PREFILTER", "0")
     src = L.ah_scan_program_source([("ACGTACGTACGTAC", "GGTTCCAAGGTTC", 2, 0)])
-    assert "prefilter: 0 of 0 blocks" in src
+    assert "pattern 0: pair 0 primer 0 strand 0, L 14, k 2, exact count" in src
     monkeypatch.setenv("AH_SCAN_PREFILTER", "1")
     src = L.ah_scan_program_source([("ACGTACGTACGTAC", "GGTTCCAAGGTTC", 2, 0)])
-    assert "prefilter: 2 of 4 blocks" in src or "prefilter: 3 of 5 blocks" in src
+    assert re.search(r"pattern 0: .*prefilter: [23] of [45] blocks", src)
 
 
 @pytest.mark.parametrize("seed", range(6))
