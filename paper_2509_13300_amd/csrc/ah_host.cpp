@@ -424,10 +424,11 @@ double at_least(const std::vector<double>& p, int need) {
   std::vector<double> d(p.size() + 1, 0.0);  // d[c] = P(exactly c so far)
   d[0] = 1.0;
   for (size_t i = 0; i < p.size(); ++i)
-    for (size_t c = i + 1; c-- > 0;) {
+    for (size_t c = i + 1;; --c) {  // c = i + 1 down to 0
       const double stay = d[c] * (1.0 - p[i]);
       const double up = c ? d[c - 1] * p[i] : 0.0;
       d[c] = stay + up;
+      if (c == 0) break;
     }
   double r = 0.0;
   for (size_t c = (size_t)need; c < d.size(); ++c) r += d[c];
@@ -437,10 +438,10 @@ double at_least(const std::vector<double>& p, int need) {
 // Cost of candidates: the append branch runs when any lane of the wave has
 // one (64 lanes x 32 windows), and each candidate costs its exact count in
 // the verify kernel (about 8 operations per position, lane-parallel).
-// Weight of candidates against filter operations (AH_SCAN_CAND_WEIGHT,
-// default 10, measured: a candidate's exact count, in its own kernel, costs
-// about ten times the estimate below in filter-equivalent time): larger
-// values choose stronger filters.
+// Weight of a candidate's exact count against filter operations
+// (AH_SCAN_CAND_WEIGHT, default 10, measured: the exact count, in its own
+// kernel, costs about ten times the estimate below in filter-equivalent
+// time): larger values choose stronger filters.
 double cand_weight() {
   const char* e = getenv("AH_SCAN_CAND_WEIGHT");
   const double w = e ? atof(e) : 10.0;
@@ -450,7 +451,16 @@ double cand_weight() {
 double cand_cost(double rate, int L) {
   const double wave = 1.0 - std::pow(1.0 - std::min(rate, 1.0), 32.0 * 64.0);
   const double per_word = 1.0 - std::pow(1.0 - std::min(rate, 1.0), 32.0);
-  return cand_weight() * (14.0 * wave + per_word * 8.0 * L);
+  return 14.0 * wave + cand_weight() * per_word * 8.0 * L;
+}
+
+// Development knob (AH_SCAN_FORCE_NEED = 1, 2 or 3): plan only pigeonhole
+// filters with that many clean blocks required (tests use it to make weak
+// filters on purpose).
+int forced_need() {
+  const char* e = getenv("AH_SCAN_FORCE_NEED");
+  const int n = e ? atoi(e) : 0;
+  return n >= 1 && n <= 3 ? n : 0;
 }
 
 FilterPlan plan_filter(const Pattern& p, bool allow) {
@@ -480,7 +490,10 @@ FilterPlan plan_filter(const Pattern& p, bool allow) {
   best.rate = exact_rate;
   best.cost = exact_ops + clamp_ops + 2 + cand_cost(exact_rate, p.L);
   if (!allow) return best;
+  const int force = forced_need();
+  if (force) best.cost = 1e300;  // any pigeonhole plan with that need wins
   for (int need = 1; need <= 3; ++need) {
+    if (force && need != force) continue;
     const int B = (int)p.k + need;
     if ((int)free_pos.size() < B) break;
     // balance information content over the blocks (largest first)
@@ -500,17 +513,56 @@ FilterPlan plan_filter(const Pattern& p, bool allow) {
       blocks[at].push_back(j);
       bits[at] += std::log2(4.0 / set_size(p.mask[j]));
     }
-    std::vector<double> clean(B);
-    int ops = 0;
-    for (int b = 0; b < B; ++b) {
-      clean[b] = std::exp2(-bits[b]);
-      std::vector<Factor> fs;
-      for (int j : blocks[b]) fs.push_back(match_factor(p.mask[j], j));
-      ops += and_chain(fs, "k", nullptr);
+    // cost of a partition: chain operations (a 3-input chain over I inputs
+    // takes ceil((I - 1) / 2), so odd input counts waste no slot), the
+    // threshold, the clamp, and the candidates it lets through
+    auto evaluate = [&](const std::vector<std::vector<int>>& bl, double* rate_out) {
+      std::vector<double> clean(B);
+      int ops = 0;
+      for (int b = 0; b < B; ++b) {
+        double bb = 0.0;
+        std::vector<Factor> fs;
+        for (int j : bl[b]) {
+          fs.push_back(match_factor(p.mask[j], j));
+          bb += std::log2(4.0 / set_size(p.mask[j]));
+        }
+        clean[b] = std::exp2(-bb);
+        ops += and_chain(fs, "k", nullptr);
+      }
+      ops += threshold(B, need, "r", nullptr);
+      const double rate = clamp_p * at_least(clean, need);
+      if (rate_out) *rate_out = rate;
+      return ops + clamp_ops + 1 + cand_cost(rate, p.L);
+    };
+    double rate = 1.0;
+    double cost = evaluate(blocks, &rate);
+    // local search: move one position to another block while that lowers
+    // the cost (typically evening out input counts to odd ones)
+    for (int iter = 0; iter < 64; ++iter) {
+      double best_move = cost;
+      int ba = -1, bb = -1, ja = -1;
+      for (int a = 0; a < B; ++a) {
+        if (blocks[a].size() < 2) continue;
+        for (size_t q = 0; q < blocks[a].size(); ++q)
+          for (int b = 0; b < B; ++b) {
+            if (b == a) continue;
+            auto trial = blocks;
+            trial[b].push_back(trial[a][q]);
+            trial[a].erase(trial[a].begin() + (long)q);
+            const double c2 = evaluate(trial, nullptr);
+            if (c2 < best_move - 1e-9) {
+              best_move = c2;
+              ba = a;
+              bb = b;
+              ja = (int)q;
+            }
+          }
+      }
+      if (ba < 0) break;
+      blocks[bb].push_back(blocks[ba][ja]);
+      blocks[ba].erase(blocks[ba].begin() + ja);
+      cost = evaluate(blocks, &rate);
     }
-    ops += threshold(B, need, "r", nullptr);
-    const double rate = clamp_p * at_least(clean, need);
-    const double cost = ops + clamp_ops + 1 + cand_cost(rate, p.L);
     if (cost < best.cost) {
       best.mode = 1;
       best.need = need;
@@ -657,7 +709,7 @@ std::string gen_exact(size_t i, const Pattern& p, bool has_n) {
   return s;
 }
 
-std::string gen_program(const std::vector<Pattern>& pats, bool has_n, Tuning tn) {
+std::string gen_program_uncached(const std::vector<Pattern>& pats, bool has_n, Tuning tn) {
   int lmax = 0;
   for (const Pattern& p : pats) lmax = p.L > lmax ? p.L : lmax;
   const bool allow = filter_enabled();
@@ -725,6 +777,37 @@ std::string gen_program(const std::vector<Pattern>& pats, bool has_n, Tuning tn)
   }
   s += "    default: return 0u;\n  }\n}\n";
   return head + std::string(kScanCore) + s;
+}
+
+// The generated source of a pattern set, memoised: planning the filters
+// (a local search per pattern) costs far more than a scan launch.  The key
+// holds every input of the generator, the planner's knobs included.
+std::string gen_program(const std::vector<Pattern>& pats, bool has_n, Tuning tn) {
+  static std::mutex mu;
+  static std::map<std::string, std::string> cache;
+  std::string key;
+  key.reserve(pats.size() * sizeof(Pattern) + 64);
+  for (const Pattern& p : pats) {
+    Pattern q{};  // a zeroed copy: the key holds no padding bytes
+    q.pair = p.pair; q.primer = p.primer; q.strand = p.strand; q.k = p.k; q.L = p.L;
+    memcpy(q.mask, p.mask, sizeof q.mask);
+    q.clamp_bits = p.clamp_bits;
+    key.append((const char*)&q, sizeof q);
+  }
+  char buf[160];
+  snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%.17g|%d", has_n ? 1 : 0, tn.u, tn.group,
+           filter_enabled() ? 1 : 0, cand_weight(), forced_need());
+  key += buf;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  std::string src = gen_program_uncached(pats, has_n, tn);
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache.size() >= 512) cache.clear();  // bounded: pattern sets are few in practice
+  cache.emplace(key, src);
+  return src;
 }
 
 // --------------------------------------------------------------- caches --
@@ -1033,8 +1116,12 @@ ah_status check_genomes(const ah_genomes* g) {
 
 // Tile counts, tile prefix and the scan kernel itself (hits appended to the
 // staging area, counted in d_res->required).
+// Filter and exact count; the sites found are counted in d_res->required.
+// *grid_out: the filter's workgroups (for the candidate-overflow bound).
 ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, const ScanWs& w,
-                             ah_result* d_res, uint64_t capacity, hipStream_t st) {
+                             ah_result* d_res, uint64_t capacity, hipStream_t st,
+                             uint32_t* grid_out = nullptr) {
+  if (grid_out) *grid_out = 1;
   if (g->n == 0) return AH_OK;
   const uint32_t tile = (uint32_t)(ah::kBlock * tn.u);
   AH_HIP(ah::launch_tile_counts(g->len, g->n, tile, w.counts, st));
@@ -1071,7 +1158,7 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
     ProfScope prof_verify("verify", st);
     AH_HIP(hipModuleLaunchKernel(fn.verify, grid, 1, 1, ah::kBlock, 1, 1, 0, st, vargs, nullptr));
   }
-  AH_HIP(ah::launch_cand_overflow(w.cstat, grid, d_res, st));
+  if (grid_out) *grid_out = grid;
   return AH_OK;
 }
 
@@ -1196,9 +1283,14 @@ ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint
   Carver c(d_work, work_bytes);
   ScanWs w = carve_scan(c, g->n, capacity, 0);
   AH_HIP(ah::launch_result_init(d_res, st));
-  s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st);
+  AH_HIP(ah::launch_zero_u64(w.cstat, 4, st));  // also for an empty collection
+  uint32_t grid = 1;
+  s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st, &grid);
   if (s) return s;
+  // count = records written (the sites found, up to the capacity); only then
+  // may a full candidate slice raise `required` to its bound
   AH_HIP(ah::launch_result_finalize(d_res, capacity, w.n_sort, st));
+  AH_HIP(ah::launch_cand_overflow(w.cstat, grid, d_res, st));
   ProfScope prof_sort("sort", st);
   AH_HIP(ah::launch_sort_hits(w.staging, d_hits, w.n_sort, kb, w.sb, st));
   return AH_OK;
@@ -1273,8 +1365,8 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
   s = get_table(tabs.data(), tabs.size() * sizeof(ah::PrimerTab), &dt);
   if (s) return s;
   ProfScope prof_tm("tm", (hipStream_t)stream);
-  AH_HIP(ah::launch_tm(*g, (const ah::PrimerTab*)dt, d_hits, d_nhits, capacity, cu_count() * 4,
-                       (hipStream_t)stream));
+  AH_HIP(ah::launch_tm(*g, (const ah::PrimerTab*)dt, n_pairs, d_hits, d_nhits, capacity,
+                       cu_count() * 4, (hipStream_t)stream));
   return AH_OK;
 }
 
@@ -1452,6 +1544,7 @@ ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uin
     double total = 0.0;
     for (uint32_t r = 0; r <= reps; ++r) {  // the first run warms up
       AH_HIP(ah::launch_result_init(d_res, strm));
+      AH_HIP(ah::launch_zero_u64(w.cstat, 4, strm));
       AH_HIP(hipEventRecord(e0, strm));
       s = launch_scan_kernel(fn, cand[i], g, w, d_res, capacity, strm);
       if (s) return s;

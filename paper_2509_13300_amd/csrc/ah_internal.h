@@ -68,7 +68,7 @@ struct SortBuffers {
 };
 hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev,
                             KeyBits kb, const SortBuffers& sb, hipStream_t st);
-hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, ah_hit* hits,
+hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pairs, ah_hit* hits,
                      const ah_result* nhits, uint64_t cap, int grid, hipStream_t st);
 struct PairBuffers {
   uint64_t* n;          // [1] number of hits to pair

@@ -286,11 +286,15 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
                                                const u32* __restrict__ len,
                                                const PrimerTab* __restrict__ tabs,
                                                ah_hit* __restrict__ hits,
-                                               const ah_result* __restrict__ nhits, u64 cap) {
+                                               const ah_result* __restrict__ nhits, u64 cap,
+                                               u32 n_genomes, u32 n_pairs) {
   const u64 cnt = nhits->count;
   const u64 n = cnt < cap ? cnt : cap;
   for (u64 i = global_tid(); i < n; i += grid_threads()) {
     ah_hit h = hits[i];
+    // a record that does not name a genome and pair of this call (never
+    // written by a scan of it) is left alone rather than followed
+    if (h.genome >= n_genomes || h.pair >= n_pairs) continue;
     const PrimerTab* T = &tabs[(u32)h.pair * 2u + (h.strand_primer & 1u)];
     const u32 L = T->L;
     const u32 strand = (h.strand_primer >> 1) & 1u;
@@ -634,16 +638,20 @@ __global__ __launch_bounds__(kBlock) void k_remap(ah_hit* __restrict__ hits,
 // ---- scan: candidate-list overflow -------------------------------------
 // stat: [0] candidates, [1] windows in them, [2] workgroups whose slice of the
 // list was full, [3] most candidates of one workgroup.  A full slice means
-// lost candidates: raise `required` to at least the windows in all
+// lost candidates: the result is an overflow, and `required` is raised to at
+// least the windows in all
 // candidates (an upper bound on the sites) and grid x the fullest workgroup's
 // candidates (which exceeds the capacity, since the slice was ccap / grid >=
 // capacity / grid).  A call with that capacity gets slices long enough for
 // every workgroup (the tiles map to workgroups the same way) and finds all
 // sites.
+// Runs after the result is finalised, so `count` stays the number of records
+// written; only `required` and `status` change.
 __global__ void k_cand_overflow(const u64* __restrict__ stat, u32 grid, ah_result* r) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && stat[2] > 0) {
     u64 bound = stat[1] > (u64)grid * stat[3] ? stat[1] : (u64)grid * stat[3];
     if (bound > r->required) r->required = bound;
+    r->status = AH_ERR_OVERFLOW;
   }
 }
 
@@ -717,10 +725,10 @@ hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n
   return hipGetLastError();
 }
 
-hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, ah_hit* hits, const ah_result* nhits,
-                     uint64_t cap, int grid, hipStream_t st) {
+hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pairs, ah_hit* hits,
+                     const ah_result* nhits, uint64_t cap, int grid, hipStream_t st) {
   k_tm<<<grid, kBlock, 0, st>>>((const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, tabs,
-                                hits, nhits, cap);
+                                hits, nhits, cap, g.n, n_pairs);
   return hipGetLastError();
 }
 

@@ -202,6 +202,50 @@ def test_candidate_list_overflow_reports_bound_and_retry_is_identical(dev):
     assert np.array_equal(path.amps_numpy(again), famp)
 
 
+def test_full_candidate_slices_with_few_sites(dev, monkeypatch):
+    """A weak filter (forced: one clean block of four) on a specific primer:
+    many candidates fill the workgroups' shares of a minimum list while the
+    real sites stay far below the capacity.  The result reports overflow
+    with a bound, `count` is exactly the sites written (every counted record
+    is a real site with its Tm), and a call with the bound as capacity gives
+    the full result."""
+    import torch
+
+    from paper_2509_13300_amd import _lib as L
+    from paper_2509_13300_amd import path
+
+    monkeypatch.setenv("AH_SCAN_FORCE_NEED", "1")
+    pr = plan.PairSpec("ACGTTGCAAGCTTCGAAC", "GGATCCTTGAGCAATGCC", k=3, clamp=0, min_len=20,
+                       max_len=4000)
+    src = L.ah_scan_program_source([pr])
+    assert "prefilter: 1 of 4 blocks" in src
+    p = plan.tiny(80, n_genomes=1, len_lo=10_000_000, len_hi=10_000_001, pair=pr,
+                  n_copies=(3, 3), span=1000)
+    ascii, off = gpu.fill_cuda(p, dev)
+    coll, _ = path.pack(ascii, off, p.lengths)
+    ref = path.alloc(coll, [pr], 1 << 16, 1 << 16, dev)  # recommended workspace
+    path.run(coll, [pr], ref)
+    small = path.alloc(coll, 1, 1 << 16, 1 << 16, dev)   # minimum workspace
+    path.run(coll, [pr], small)
+    torch.cuda.synchronize()
+    full = path.hits_numpy(ref)
+    r = path.result(small.hit_res)
+    stats = L.ah_scan_candidate_stats(small.scan_work, coll.n, small.hit_cap)
+    say("weak filter: sites", full.size, "minimum-workspace result", r, stats)
+    assert path.result(ref.hit_res)["status"] == 0 and 0 < full.size < 1000
+    assert stats["full_slices"] > 0
+    assert r["status"] == -4 and r["required"] > small.hit_cap
+    got = path.hits_numpy(small)  # the sites the filled slices still held
+    assert got.size == r["count"] <= full.size
+    assert np.all(np.isfinite(got["tm"])) and np.all(got["genome"] == 0)
+    again = path.alloc(coll, 1, r["required"], 1 << 16, dev)
+    path.run(coll, [pr], again)
+    torch.cuda.synchronize()
+    assert path.result(again.hit_res)["status"] == 0
+    assert np.array_equal(path.hits_numpy(again), full)
+    assert np.array_equal(path.amps_numpy(again), path.amps_numpy(ref))
+
+
 def test_tm_filter_on_matches_oracle(dev):
     pr = plan.PairSpec("GCGTACRYTCCAGTAGC", "GATCGNATCGGCTAAC", k=3, clamp=2, min_len=40,
                        max_len=2000)

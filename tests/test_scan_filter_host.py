@@ -68,11 +68,32 @@ def window_sets(primer, strand):
     return ["".join(sorted(COMP[b] for b in s)) for s in reversed(sets)]
 
 
+def planned_rate(body, i):
+    return float(re.search(rf"// pattern {i}: .*random pass rate ([0-9.e+-]+)", body).group(1))
+
+
+def random_pass_rate(fn, length, rs, n_words):
+    win = rs.choice(list("ACGT"), size=(n_words * 32, length))
+    weights = (np.uint64(1) << np.arange(32, dtype=np.uint64))
+    planes = {}
+    for p, base in (("pa", "A"), ("pc", "C"), ("pg", "G"), ("pt", "T")):
+        bits = (win == base).reshape(n_words, 32, length)
+        planes[p] = [((bits[:, :, j].astype(np.uint64) * weights).sum(1)).astype(np.uint32)
+                     for j in range(length)]
+    got = run_filter(fn, planes)
+    return sum(bin(int(x)).count("1") for x in got) / (n_words * 32)
+
+
 def check_pair(fwd, rev, k, clamp, rs, n_words=64):
     src = L.ah_scan_program_source([(fwd, rev, k, clamp)])
     body = src.split("---- generated pattern program follows ----")[1]
     for i, (primer, strand) in enumerate([(fwd, 0), (fwd, 1), (rev, 0), (rev, 1)]):
         fn = body.split(f"u32 ah_pf_{i}(")[1].split("\n}\n")[0].split("{", 1)[1]
+        # the planner's pass rate matches the filter's on uniform random bases
+        # (within sampling error: 20,480 windows)
+        planned = planned_rate(body, i)
+        measured = random_pass_rate(fn, len(primer), rs, 640)
+        assert measured <= 2.0 * planned + 6.0 / 20480, (fwd, rev, i, planned, measured)
         sets = window_sets(primer, strand)
         Lp = len(sets)
         clamp_pos = set(range(Lp - clamp, Lp)) if strand == 0 else set(range(clamp))
