@@ -378,7 +378,7 @@ def _serve_pass(srv, p, jobs, mode: str, rate_start_delay: float = 0.05):
         t0 = srv.now()
         for _, pid, ids in jobs:
             j = srv.submit(p.pairs[pid], ids)
-            st = srv.wait(600.0)
+            st = srv.wait(120.0)
             assert st is not None and st["job"] == j and st["status"] == 0, st
             out.append(st)
             srv.release(j)
@@ -399,13 +399,17 @@ def _serve_pass(srv, p, jobs, mode: str, rate_start_delay: float = 0.05):
 
     th = threading.Thread(target=submit_all)
     th.start()
+    last = time.perf_counter()
     while len(out) < len(jobs):
-        st = srv.wait(600.0)
+        st = srv.wait(120.0)  # no job finishing for two minutes: stuck
         if st is None or err:
             break
         assert st["status"] == 0, st
         out.append(st)
         srv.release(st["job"])
+        if time.perf_counter() - last > 10.0:
+            print(f"serve: {mode} {len(out)}/{len(jobs)} jobs done", file=sys.stderr, flush=True)
+            last = time.perf_counter()
     th.join()
     if err:
         raise err[0]
@@ -458,6 +462,7 @@ def gpu_serve(n_jobs: int = 120, rate: float = 4.0, n_genomes: int = 100000,
     create_s = time.perf_counter() - t0
     try:
         _serve_pass(srv, p, jobs[:8], "burst")  # warm-up: tables, staging buffers
+        print("serve: warm-up done", file=sys.stderr, flush=True)
         sts, span = _serve_pass(srv, p, jobs, "poisson")
         stats = srv.stats()
         print(f"serve: poisson {n_jobs} jobs in {span:.2f} s", file=sys.stderr, flush=True)

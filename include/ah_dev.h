@@ -49,6 +49,12 @@ ah_status ah_profile_query(const char* name, uint64_t* launches, double* total_m
 ah_status ah_scan_candidate_stats(const void* d_work, size_t work_bytes, uint32_t n_genomes,
                                   uint64_t capacity, uint64_t out[4]);
 
+/* Candidate records that the list of a scan workspace of work_bytes holds
+ * for n genomes and a hit capacity, with the workspace starting base_offset
+ * (mod 256) bytes past a 256-byte boundary.  Host arithmetic only. */
+uint64_t ah_scan_candidate_capacity(size_t base_offset, size_t work_bytes, uint32_t n_genomes,
+                                    uint64_t capacity);
+
 #ifdef __cplusplus
 }
 #endif

@@ -121,7 +121,7 @@ EXPORTS = (
     "ah_autotune_scan", "ah_set_scan_tuning", "ah_get_scan_tuning", "ah_scan_prepare",
     "ah_stream_workspace_bytes", "ah_stream_query", "ah_server_create", "ah_server_submit",
     "ah_server_wait", "ah_server_part", "ah_server_release", "ah_server_stats_get",
-    "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats",
+    "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats", "ah_scan_candidate_capacity",
 )
 
 _lib = None
@@ -206,6 +206,8 @@ def lib() -> ctypes.CDLL:
     L.ah_server_destroy.restype = None
     L.ah_scan_candidate_stats.argtypes = [vp, sz, u32, u64, P(ctypes.c_uint64)]
     L.ah_scan_candidate_stats.restype = st
+    L.ah_scan_candidate_capacity.argtypes = [sz, sz, u32, u64]
+    L.ah_scan_candidate_capacity.restype = u64
     _lib = L
     return L
 
@@ -532,3 +534,10 @@ def ah_scan_candidate_stats(work, n_genomes: int, capacity: int) -> dict:
                                          out), "ah_scan_candidate_stats")
     return {"records": int(out[0]), "windows": int(out[1]), "full_slices": int(out[2]),
             "max_per_workgroup": int(out[3])}
+
+
+def ah_scan_candidate_capacity(work_bytes: int, n_genomes: int, capacity: int,
+                               base_offset: int = 0) -> int:
+    """Candidate records a scan workspace of work_bytes holds (host arithmetic)."""
+    return int(lib().ah_scan_candidate_capacity(int(base_offset), int(work_bytes),
+                                                int(n_genomes), int(capacity)))

@@ -228,11 +228,14 @@ std::string acc_mism_op(const std::string& acc, uint8_t m, int j) {
   return bitop3(acc, hj(j), lj(j), (uint8_t)(kS0 | tt_mism(m, kS1, kS2)));
 }
 
-// ---- filter codegen over one-hot planes.  In the scan kernel each lane holds,
-// for the words of its windows, the planes pa/pc/pg/pt (bit b set iff that
-// base is A/C/G/T).  The match indicator of a primer position is then one
-// plane (a single base), the complement of one plane (three bases), or the OR
-// of two planes (two bases); N always matches.
+// ---- filter codegen over bit planes.  In the scan kernel each lane holds,
+// for the words of its windows, the one-hot planes pa/pc/pg/pt (bit b set
+// iff that base is A/C/G/T) and the planes ph = h, pl = l, px = h ^ l of the
+// 2-bit code (A=00, C=01, G=10, T=11).  Every IUPAC code but N is then one
+// literal: a single base is a one-hot plane, three bases the complement of
+// the missing base's plane, and each of the six two-base codes one bit
+// plane or its complement (M = AC: ~h, K = GT: h, R = AG: ~l, Y = CT: l,
+// S = CG: h ^ l, W = AT: ~(h ^ l)).  N always matches.
 const char* const kPlane[4] = {"pa", "pc", "pg", "pt"};
 
 struct Lit {
@@ -247,24 +250,40 @@ struct Factor {
 
 int set_size(uint8_t m) { return __builtin_popcount(m); }
 
+// Whether two-base codes read the code planes (one literal, but up to three
+// more live registers per ring word) or OR two one-hot planes
+// (AH_SCAN_CODE_PLANES, default 0).
+bool code_planes() {
+  const char* e = getenv("AH_SCAN_CODE_PLANES");
+  return e && e[0] == '1';
+}
+
 Factor match_factor(uint8_t m, int j) {
   const std::string sj = "[" + std::to_string(j) + "]";
   int bases[4], nb = 0;
   for (int b = 0; b < 4; ++b)
     if (m >> b & 1) bases[nb++] = b;
   Factor f;
+  f.n = 1;
   if (nb == 1) {
     f.a = {kPlane[bases[0]] + sj, false};
-    f.n = 1;
   } else if (nb == 3) {
     int miss = 0;
     while (m >> miss & 1) ++miss;
     f.a = {kPlane[miss] + sj, true};
-    f.n = 1;
-  } else {  // nb == 2
+  } else if (!code_planes()) {  // nb == 2, as the OR of two one-hot planes
     f.a = {kPlane[bases[0]] + sj, false};
     f.b = {kPlane[bases[1]] + sj, false};
     f.n = 2;
+  } else {  // nb == 2: bit masks over A=1, C=2, G=4, T=8
+    switch (m) {
+      case 0x3: f.a = {"ph" + sj, true}; break;    // M
+      case 0xc: f.a = {"ph" + sj, false}; break;   // K
+      case 0x5: f.a = {"pl" + sj, true}; break;    // R
+      case 0xa: f.a = {"pl" + sj, false}; break;   // Y
+      case 0x6: f.a = {"px" + sj, false}; break;   // S
+      default: f.a = {"px" + sj, true}; break;     // W (0x9)
+    }
   }
   return f;
 }
@@ -603,7 +622,7 @@ std::string gen_filter(size_t i, const Pattern& p, const FilterPlan& fp) {
            "// pattern %zu: pair %u primer %u strand %u, L %d, k %u, %s (random pass rate %.3g, "
            "~%.1f ops per window word)\n"
            "__device__ __forceinline__ u32 ah_pf_%zu(const u32* pa, const u32* pc, const u32* pg,"
-           " const u32* pt) {\n",
+           " const u32* pt, const u32* ph, const u32* pl, const u32* px) {\n",
            i, p.pair, p.primer, p.strand, p.L, p.k,
            fp.mode ? ("prefilter: " + std::to_string(fp.need) + " of " +
                       std::to_string(fp.blocks.size()) + " blocks").c_str()
@@ -714,7 +733,7 @@ std::string gen_program_uncached(const std::vector<Pattern>& pats, bool has_n, T
   for (const Pattern& p : pats) lmax = p.L > lmax ? p.L : lmax;
   const bool allow = filter_enabled();
   std::string s;
-  char buf[768];
+  char buf[2048];
   snprintf(buf, sizeof buf, "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n", tn.u,
            lmax - 1, has_n ? 1 : 0);
   std::string head = buf;
@@ -737,25 +756,36 @@ std::string gen_program_uncached(const std::vector<Pattern>& pats, bool has_n, T
              "  const u32 base = threadIdx.x * (u32)AH_U;\n"
              "  if (t0 + base >= c.S) return;\n"
              "  u32 pa[AH_U + %d], pc[AH_U + %d], pg[AH_U + %d], pt[AH_U + %d];\n"
+             "  u32 ph[AH_U + %d], pl[AH_U + %d], px[AH_U + %d];\n"
              "#pragma unroll\n"
-             "  for (int w = 0; w < %d; ++w) ah_onehot(tw[base + (u32)w], pa[w], pc[w], pg[w], pt[w]);\n"
+             "  for (int w = 0; w < %d; ++w)\n"
+             "    ah_planes(tw[base + (u32)w], pa[w], pc[w], pg[w], pt[w], ph[w], pl[w], px[w]);\n"
              "  uint2 nxt = tw[base + %du];  // read one step ahead\n"
              "#pragma unroll\n"
              "  for (int u = 0; u < AH_U; ++u) {\n"
-             "    ah_onehot(nxt, pa[u + %d], pc[u + %d], pg[u + %d], pt[u + %d]);\n"
+             "    ah_planes(nxt, pa[u + %d], pc[u + %d], pg[u + %d], pt[u + %d], ph[u + %d], pl[u + %d],"
+             " px[u + %d]);\n"
              "    if (u + 1 < AH_U) nxt = tw[base + (u32)u + %du];\n"
-             "    const u32 t = t0 + base + (u32)u;\n    u32 cand;\n",
+             "    const u32 t = t0 + base + (u32)u;\n",
              ngroups > 1 ? "__noinline__" : "__forceinline__", gi, lg - 1, lg - 1, lg - 1, lg - 1,
-             lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg);
+             lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg - 1, lg - 1,
+             lg - 1, lg);
     s += buf;
+    // one branch per window word for the whole group: candidates are rare
+    std::string any;
     for (size_t i = a; i < b; ++i) {
       snprintf(buf, sizeof buf,
-               "    cand = ah_pf_%zu(pa + u, pc + u, pg + u, pt + u);\n"
-               "    if (cand) ah_cand(c, k, t, %zuu, cand);\n",
-               i, i);
+               "    const u32 c%zu = ah_pf_%zu(pa + u, pc + u, pg + u, pt + u, ph + u, pl + u, px + u);\n",
+               i - a, i);
+      s += buf;
+      any += (i > a ? " | c" : "c") + std::to_string(i - a);
+    }
+    s += "    if (" + any + ") {\n";
+    for (size_t i = a; i < b; ++i) {
+      snprintf(buf, sizeof buf, "      if (c%zu) ah_cand(c, k, t, %zuu, c%zu);\n", i - a, i, i - a);
       s += buf;
     }
-    s += "  }\n}\n";
+    s += "    }\n  }\n}\n";
   }
   s += "__device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c, const AhCands& k) {\n";
   for (size_t gi = 0; gi < ngroups; ++gi) s += "  ah_group_" + std::to_string(gi) + "(tw, t0, c, k);\n";
@@ -795,8 +825,8 @@ std::string gen_program(const std::vector<Pattern>& pats, bool has_n, Tuning tn)
     key.append((const char*)&q, sizeof q);
   }
   char buf[160];
-  snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%.17g|%d", has_n ? 1 : 0, tn.u, tn.group,
-           filter_enabled() ? 1 : 0, cand_weight(), forced_need());
+  snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%.17g|%d|%d", has_n ? 1 : 0, tn.u, tn.group,
+           filter_enabled() ? 1 : 0, cand_weight(), forced_need(), code_planes() ? 1 : 0);
   key += buf;
   {
     std::lock_guard<std::mutex> lk(mu);
@@ -814,7 +844,8 @@ std::string gen_program(const std::vector<Pattern>& pats, bool has_n, Tuning tn)
 // The two kernels of a specialised scan program.
 struct ScanFns {
   hipFunction_t scan = nullptr;    // filter: appends candidates
-  hipFunction_t verify = nullptr;  // exact count of the candidates: appends sites
+  hipFunction_t verify = nullptr;  // exact count of the candidates: sites per candidate
+  hipFunction_t emit = nullptr;    // the site records, the result and the statistics
 };
 
 struct JitEntry {
@@ -873,6 +904,7 @@ ah_status load_scan_kernel(int dev, const std::string& src, const std::vector<ch
   AH_HIP(hipModuleLoadData(&e.mod, code.data()));
   AH_HIP(hipModuleGetFunction(&e.fn.scan, e.mod, "ah_scan_kernel"));
   AH_HIP(hipModuleGetFunction(&e.fn.verify, e.mod, "ah_verify_kernel"));
+  AH_HIP(hipModuleGetFunction(&e.fn.emit, e.mod, "ah_emit_kernel"));
   g_jit[key] = e;
   fn = e.fn;
   return AH_OK;
@@ -1018,9 +1050,13 @@ struct Carver {
 struct ScanWs {
   uint64_t *counts, *tile_prefix, *scan_tmp, *n_sort;
   ah_hit* staging;
-  uint4* cands;         // filter output: {genome, window word, pattern, window mask}
-  uint32_t* slice_cnt;  // [kMaxScanGrid] candidates kept per workgroup
-  uint64_t* cstat;      // [0] candidates, [1] windows in them, [2] full slices, [3] most per workgroup
+  uint4* cands;           // filter output: {genome, window word, pattern, window mask}
+  uint32_t* slice_cnt;    // [kMaxScanGrid] candidates kept per workgroup
+  uint32_t* slice_tot;    // [kMaxScanGrid] candidates found per workgroup
+  uint64_t* slice_win;    // [kMaxScanGrid] windows in them
+  uint64_t* slice_sites;  // [kMaxScanGrid] sites in the kept ones
+  uint32_t* cand_sites;   // [ccap] sites of each kept candidate
+  uint64_t* cstat;        // [0] candidates, [1] windows in them, [2] full slices, [3] most per workgroup
   uint64_t ccap;
   ah::SortBuffers sb;
 };
@@ -1066,17 +1102,27 @@ ScanWs carve_scan(Carver& c, uint32_t n, uint64_t cap, uint64_t ccap) {
   w.sb.keys[1] = c.take<uint64_t>(cap ? cap : 1);
   w.sb.idx[0] = c.take<uint32_t>(cap ? cap : 1);
   w.sb.idx[1] = c.take<uint32_t>(cap ? cap : 1);
-  w.sb.hist = c.take<uint64_t>((uint64_t)256 * ah::kSortGrid);
-  w.sb.hist_off = c.take<uint64_t>((uint64_t)256 * ah::kSortGrid + 1);
-  w.sb.scan_tmp = w.scan_tmp;
+  w.sb.hist = c.take<uint32_t>((uint64_t)256 * ah::kSortGrid);
   w.cstat = c.take<uint64_t>(4);
   w.slice_cnt = c.take<uint32_t>(kMaxScanGrid);
-  if (ccap == 0) {
+  w.slice_tot = c.take<uint32_t>(kMaxScanGrid);
+  w.slice_win = c.take<uint64_t>(kMaxScanGrid);
+  w.slice_sites = c.take<uint64_t>(kMaxScanGrid);
+  // The candidate records and their site counts: `ccap` of them, or (ccap =
+  // 0) as many as the rest holds.  A size computed for some ccap carries 512
+  // spare bytes, so that the rest of a workspace of that size holds at least
+  // ccap records, whatever the alignment of the workspace (one 256-byte
+  // alignment pad between the two arrays, one for the base).
+  constexpr uint64_t kPerCand = sizeof(uint4) + sizeof(uint32_t);
+  const bool rest = ccap == 0;
+  if (rest) {
     const uintptr_t at = (c.cur + 255) & ~(uintptr_t)255;
-    ccap = c.end > at ? (uint64_t)(c.end - at) / sizeof(uint4) : 0;
+    ccap = c.end > at + 256 ? (uint64_t)(c.end - at - 256) / kPerCand : 0;
   }
   w.ccap = ccap;
   w.cands = c.take<uint4>(ccap);
+  w.cand_sites = c.take<uint32_t>(ccap);
+  if (!rest) c.cur += 512;
   return w;
 }
 
@@ -1089,11 +1135,10 @@ size_t scan_ws_bytes(uint32_t n, uint64_t cap, uint64_t ccap) {
 ah::PairBuffers carve_pair(Carver& c, uint64_t cap) {
   const uint64_t m = cap ? cap : 1;
   ah::PairBuffers b;
-  b.n = c.take<uint64_t>(1);
-  b.flag_f = c.take<uint32_t>(m);
-  b.flag_r = c.take<uint32_t>(m);
-  b.off_f = c.take<uint64_t>(m + 1);
-  b.off_r = c.take<uint64_t>(m + 1);
+  b.cf = c.take<uint64_t>(ah::kPairGrid);
+  b.cr = c.take<uint64_t>(ah::kPairGrid);
+  b.cc = c.take<uint64_t>(ah::kPairGrid);
+  b.mtot = c.take<uint64_t>(2);
   b.mkey_f = c.take<uint64_t>(m);
   b.mpos_f = c.take<uint32_t>(m);
   b.midx_f = c.take<uint32_t>(m);
@@ -1101,8 +1146,6 @@ ah::PairBuffers carve_pair(Carver& c, uint64_t cap) {
   b.mpos_r = c.take<uint32_t>(m);
   b.midx_r = c.take<uint32_t>(m);
   b.cnt = c.take<uint32_t>(m);
-  b.cnt_off = c.take<uint64_t>(m + 1);
-  b.scan_tmp = c.take<uint64_t>(ah::kScanGrid + 1);
   return b;
 }
 
@@ -1114,19 +1157,26 @@ ah_status check_genomes(const ah_genomes* g) {
   return AH_OK;
 }
 
-// Tile counts, tile prefix and the scan kernel itself (hits appended to the
-// staging area, counted in d_res->required).
-// Filter and exact count; the sites found are counted in d_res->required.
-// *grid_out: the filter's workgroups (for the candidate-overflow bound).
+// Reset of d_res, tile counts and prefix, then the filter, the exact count
+// and the emit pass, which writes the sites to the staging area in slice
+// order, the final d_res (required, count, status), n_sort and the
+// candidate-list statistics.
 ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, const ScanWs& w,
-                             ah_result* d_res, uint64_t capacity, hipStream_t st,
-                             uint32_t* grid_out = nullptr) {
-  if (grid_out) *grid_out = 1;
-  if (g->n == 0) return AH_OK;
+                             ah_result* d_res, uint64_t capacity, hipStream_t st) {
+  if (g->n == 0) {
+    AH_HIP(ah::launch_result_init(d_res, st));
+    AH_HIP(ah::launch_zero_u64(w.cstat, 4, st));
+    AH_HIP(ah::launch_zero_u64(w.n_sort, 1, st));
+    return AH_OK;
+  }
   const uint32_t tile = (uint32_t)(ah::kBlock * tn.u);
-  AH_HIP(ah::launch_tile_counts(g->len, g->n, tile, w.counts, st));
-  AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
-  AH_HIP(ah::launch_zero_u64(w.cstat, 4, st));
+  if (g->n <= ah::kSmallPrefix) {  // one launch, result reset included
+    AH_HIP(ah::launch_tile_prefix_small(g->len, g->n, tile, w.tile_prefix, d_res, st));
+  } else {
+    AH_HIP(ah::launch_result_init(d_res, st));
+    AH_HIP(ah::launch_tile_counts(g->len, g->n, tile, w.counts, st));
+    AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
+  }
   // persistent grid, no larger than an upper bound on the tiles (so that small
   // inputs get long slices); each workgroup owns ccap / grid records
   const uint64_t words_ub = ((uint64_t)g->max_len + 31) / 32;
@@ -1142,23 +1192,36 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   uint4* cands = w.cands;
   uint32_t slice = (uint32_t)std::min<uint64_t>(w.ccap / grid, 0xffffffffu);
   uint32_t* slice_cnt = w.slice_cnt;
-  uint64_t* cstat = w.cstat;
-  void* args[] = {&words, &nmask, &word_off, &len, &tp, &n, &cands, &slice, &slice_cnt, &cstat};
+  uint32_t* slice_tot = w.slice_tot;
+  uint64_t* slice_win = w.slice_win;
+  void* args[] = {&words, &nmask,     &word_off,  &len,      &tp,       &n,
+                  &cands, &slice,     &slice_cnt, &slice_tot, &slice_win};
   {
     ProfScope prof_scan("scan", st);
     AH_HIP(hipModuleLaunchKernel(fn.scan, grid, 1, 1, ah::kBlock, 1, 1, 0, st, args, nullptr));
   }
-  ah_hit* out = w.staging;
-  uint64_t cap = capacity;
-  uint64_t* counter = &d_res->required;
+  uint32_t* cand_sites = w.cand_sites;
+  uint64_t* slice_sites = w.slice_sites;
   const uint4* ccands = w.cands;
   const uint32_t* cslice_cnt = w.slice_cnt;
-  void* vargs[] = {&words, &nmask, &word_off, &len, &ccands, &slice, &cslice_cnt, &out, &cap, &counter};
+  void* vargs[] = {&words, &nmask,      &word_off,    &len,       &ccands,
+                   &slice, &cslice_cnt, &cand_sites,  &slice_sites, &slice_win};
   {
     ProfScope prof_verify("verify", st);
     AH_HIP(hipModuleLaunchKernel(fn.verify, grid, 1, 1, ah::kBlock, 1, 1, 0, st, vargs, nullptr));
+    ah_hit* out = w.staging;
+    uint64_t cap = capacity;
+    const uint32_t* cslice_tot = w.slice_tot;
+    const uint64_t* cslice_win = w.slice_win;
+    const uint32_t* ccand_sites = w.cand_sites;
+    const uint64_t* cslice_sites = w.slice_sites;
+    uint64_t* n_out = w.n_sort;
+    uint64_t* cstat = w.cstat;
+    void* eargs[] = {&words,      &nmask,       &word_off,     &len, &ccands, &slice,
+                     &cslice_cnt, &cslice_tot,  &cslice_win,   &ccand_sites, &cslice_sites,
+                     &out,        &cap,         &d_res,        &n_out, &cstat};
+    AH_HIP(hipModuleLaunchKernel(fn.emit, grid, 1, 1, ah::kBlock, 1, 1, 0, st, eargs, nullptr));
   }
-  if (grid_out) *grid_out = grid;
   return AH_OK;
 }
 
@@ -1282,15 +1345,9 @@ ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint
   hipStream_t st = (hipStream_t)stream;
   Carver c(d_work, work_bytes);
   ScanWs w = carve_scan(c, g->n, capacity, 0);
-  AH_HIP(ah::launch_result_init(d_res, st));
-  AH_HIP(ah::launch_zero_u64(w.cstat, 4, st));  // also for an empty collection
-  uint32_t grid = 1;
-  s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st, &grid);
+  // the result, the records to sort (n_sort) and the candidate statistics
+  s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st);
   if (s) return s;
-  // count = records written (the sites found, up to the capacity); only then
-  // may a full candidate slice raise `required` to its bound
-  AH_HIP(ah::launch_result_finalize(d_res, capacity, w.n_sort, st));
-  AH_HIP(ah::launch_cand_overflow(w.cstat, grid, d_res, st));
   ProfScope prof_sort("sort", st);
   AH_HIP(ah::launch_sort_hits(w.staging, d_hits, w.n_sort, kb, w.sb, st));
   return AH_OK;
@@ -1410,7 +1467,7 @@ ah_status ah_pair_amplicons(const ah_hit* d_hits, const ah_result* d_nhits, uint
   ah::PairBuffers pb = carve_pair(c, hit_capacity);
   ProfScope prof_pair("pair", (hipStream_t)stream);
   AH_HIP(ah::launch_pair(d_hits, d_nhits, hit_capacity, (const ah::PairTab*)dt, d_amp, capacity,
-                         d_res, pb, cu_count() * 4, (hipStream_t)stream));
+                         d_res, pb, (hipStream_t)stream));
   return AH_OK;
 }
 
@@ -1544,7 +1601,6 @@ ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uin
     double total = 0.0;
     for (uint32_t r = 0; r <= reps; ++r) {  // the first run warms up
       AH_HIP(ah::launch_result_init(d_res, strm));
-      AH_HIP(ah::launch_zero_u64(w.cstat, 4, strm));
       AH_HIP(hipEventRecord(e0, strm));
       s = launch_scan_kernel(fn, cand[i], g, w, d_res, capacity, strm);
       if (s) return s;
@@ -1619,6 +1675,12 @@ ah_status ah_scan_candidate_stats(const void* d_work, size_t work_bytes, uint32_
   AH_HIP(hipDeviceSynchronize());
   AH_HIP(hipMemcpy(out, w.cstat, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost));
   return AH_OK;
+}
+
+uint64_t ah_scan_candidate_capacity(size_t base_offset, size_t work_bytes, uint32_t n_genomes,
+                                    uint64_t capacity) {
+  Carver c((void*)(uintptr_t)(base_offset & 255u), work_bytes);
+  return carve_scan(c, n_genomes, capacity, 0).ccap;
 }
 
 ah_status ah_validate_pairs(const ah_primer_pair* pairs, uint32_t n_pairs) {

@@ -10,7 +10,8 @@
 namespace ah {
 
 constexpr int kBlock = 256;        // threads per workgroup for every kernel
-constexpr int kSortGrid = 256;     // workgroups of the radix-sort passes
+constexpr int kSortGrid = 256;     // workgroups (chunks) of the radix-sort passes
+constexpr int kPairGrid = 1024;    // workgroups (chunks) of the pairing kernels
 constexpr int kScanGrid = 256;     // workgroups of the generic prefix scan
 constexpr int kScanU = 19;         // default window words per lane (odd) in the scan kernel
 
@@ -49,7 +50,6 @@ hipError_t launch_pack(const uint8_t* ascii, const uint64_t* ascii_off, uint32_t
                        const uint64_t* word_off, uint32_t* words, uint32_t* len,
                        uint32_t* nmask, uint64_t* non_acgt, int grid, hipStream_t st);
 hipError_t launch_result_init(ah_result* res, hipStream_t st);
-hipError_t launch_result_finalize(ah_result* res, uint64_t cap, uint64_t* n_out, hipStream_t st);
 hipError_t launch_tile_counts(const uint32_t* len, uint32_t n, uint32_t tile_words, uint64_t* counts,
                               hipStream_t st);
 // Exclusive prefix sum of in[0..n) into out[0..n]; out[n] = total.  n is
@@ -62,20 +62,17 @@ hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, const ui
 struct SortBuffers {
   uint64_t* keys[2];
   uint32_t* idx[2];
-  uint64_t* hist;      // 256 * kSortGrid
-  uint64_t* hist_off;  // 256 * kSortGrid + 1
-  uint64_t* scan_tmp;  // kScanGrid + 1
+  uint32_t* hist;      // 256 x kSortGrid digit counts (one row per digit)
 };
 hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev,
                             KeyBits kb, const SortBuffers& sb, hipStream_t st);
 hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pairs, ah_hit* hits,
                      const ah_result* nhits, uint64_t cap, int grid, hipStream_t st);
 struct PairBuffers {
-  uint64_t* n;          // [1] number of hits to pair
-  uint32_t* flag_f;     // [cap] kept - site of the fwd primer
-  uint32_t* flag_r;     // [cap]
-  uint64_t* off_f;      // [cap + 1]
-  uint64_t* off_r;      // [cap + 1]
+  uint64_t* cf;         // [kPairGrid] kept fwd-primer minus sites per chunk
+  uint64_t* cr;         // [kPairGrid] rev-primer
+  uint64_t* cc;         // [kPairGrid] amplicons per chunk
+  uint64_t* mtot;       // [2] lengths of the two minus-site lists
   uint64_t* mkey_f;     // [cap] (pair << 32 | genome) of compacted - sites
   uint32_t* mpos_f;     // [cap]
   uint32_t* midx_f;     // [cap]
@@ -83,12 +80,10 @@ struct PairBuffers {
   uint32_t* mpos_r;
   uint32_t* midx_r;
   uint32_t* cnt;        // [cap] amplicons started by each leader + site
-  uint64_t* cnt_off;    // [cap + 1]
-  uint64_t* scan_tmp;   // kScanGrid + 1
 };
 hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
-                       const PairBuffers& pb, int grid, hipStream_t st);
+                       const PairBuffers& pb, hipStream_t st);
 
 // Streaming: word offsets of genomes off[0..n] relative to off[0], and the
 // chunk-local -> collection id fix-up of a chunk's hits and amplicons.
@@ -104,10 +99,13 @@ hipError_t launch_gather_view(const uint32_t* ids, uint32_t n, const uint64_t* o
 hipError_t launch_remap(ah_hit* hits, const ah_result* hres, ah_amplicon* amp, const ah_result* ares,
                         const uint32_t* ids, int grid, hipStream_t st);
 
-// Scan: zero n u64 (graph-capturable, no memset node), and the candidate-list
-// overflow adjustment of a scan result.
+// Scan: zero n u64 (graph-capturable, no memset node).
 hipError_t launch_zero_u64(uint64_t* p, uint32_t n, hipStream_t st);
-hipError_t launch_cand_overflow(const uint64_t* stat, uint32_t grid, ah_result* res, hipStream_t st);
+// Tile counts of n <= kSmallPrefix genomes, their exclusive prefix
+// (prefix[n] = total) and the reset of `res`, in one launch.
+constexpr uint32_t kSmallPrefix = 4096;
+hipError_t launch_tile_prefix_small(const uint32_t* len, uint32_t n, uint32_t tile_words,
+                                    uint64_t* prefix, ah_result* res, hipStream_t st);
 
 // Recommended scan workspace for n genomes holding at most `window_words`
 // window words in total (pairs may be null: the minimum).

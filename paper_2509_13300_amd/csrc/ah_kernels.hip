@@ -97,22 +97,57 @@ __global__ void k_result_init(ah_result* r) {
   }
 }
 
-__global__ void k_result_finalize(ah_result* r, u64 cap, u64* n_out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const u64 req = r->required;
-    const u64 c = req < cap ? req : cap;
-    r->count = c;
-    r->status = req > cap ? AH_ERR_OVERFLOW : AH_OK;
-    if (n_out) *n_out = c;
-  }
-}
-
 __global__ void k_tile_counts(const u32* __restrict__ len, u32 n, u32 tile_words,
                               u64* __restrict__ counts) {
   for (u64 i = global_tid(); i < n; i += grid_threads()) {
     const u64 S = ((u64)len[i] + 31) >> 5;
     counts[i] = (S + tile_words - 1) / tile_words;
   }
+}
+
+// Small collections (n <= kSmallPrefix): tile counts and their exclusive
+// prefix (n + 1 entries) in one workgroup of 1024 threads, and the result
+// reset, in one launch.
+constexpr int kSmallBlock = 1024;
+
+__global__ __launch_bounds__(kSmallBlock) void k_tile_prefix_small(const u32* __restrict__ len, u32 n,
+                                                                   u32 tile_words,
+                                                                   u64* __restrict__ prefix,
+                                                                   ah_result* r) {
+  __shared__ u64 wsum[kSmallBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) {
+    r->count = 0;
+    r->required = 0;
+    r->status = AH_OK;
+    r->reserved = 0;
+  }
+  u64 run = 0;
+  for (u32 base = 0; base < n; base += kSmallBlock) {
+    const u32 i = base + threadIdx.x;
+    u64 v = 0;
+    if (i < n) {
+      const u64 S = ((u64)len[i] + 31) >> 5;
+      v = (S + tile_words - 1) / tile_words;
+    }
+    u64 x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const u64 y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    u64 before = 0, total = 0;
+    for (int q = 0; q < kSmallBlock / 64; ++q) {
+      before += q < w ? wsum[q] : 0u;
+      total += wsum[q];
+    }
+    if (i < n) prefix[i] = run + before + x - v;
+    run += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) prefix[n] = run;
 }
 
 // ------------------------------------------------------- prefix scans ----
@@ -162,48 +197,98 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const T* __restrict__ in, 
 }
 
 // ------------------------------------------------------------ radix sort --
+// LSD radix sort of the hit records by their canonical key, 8 bits a pass.
+// Every pass splits the n records into the same G <= kSortGrid contiguous
+// chunks, one per workgroup: a histogram kernel writes each chunk's digit
+// counts, and the scatter kernel derives its chunk's output offsets from all
+// G histograms itself (no separate prefix-scan launches).  The first
+// histogram comes with the keys; the last scatter writes the records.  The
+// counts are stored digit-major (hist[digit * kSortGrid + chunk]), so that the
+// thread of a digit reads its G counts with 16-byte loads, all in flight at
+// once: the counts were written by another kernel and miss the caches.
+constexpr u64 kSortChunkMin = 4 * kBlock;
+
+__device__ __forceinline__ u32 sort_chunks(u64 n, u64& chunk) {
+  u64 c = (n + kSortGrid - 1) / kSortGrid;
+  c = (c + kBlock - 1) / kBlock * kBlock;
+  chunk = c < kSortChunkMin ? kSortChunkMin : c;
+  return (u32)((n + chunk - 1) / chunk);
+}
+
 __global__ __launch_bounds__(kBlock) void k_keygen(const ah_hit* __restrict__ st,
                                                    const u64* __restrict__ n_dev, KeyBits kb,
-                                                   u64* __restrict__ keys, u32* __restrict__ idx) {
+                                                   u64* __restrict__ keys, u32* __restrict__ idx,
+                                                   u32* __restrict__ hist) {
+  __shared__ u32 h[256];
   const u64 n = *n_dev;
-  for (u64 i = global_tid(); i < n; i += grid_threads()) {
-    const ah_hit h = st[i];
-    keys[i] = ((u64)h.pair << (kb.gb + kb.pb + 2)) | ((u64)h.genome << (kb.pb + 2)) |
-              ((u64)h.pos << 2) | (u64)(h.strand_primer & 3u);
+  u64 chunk;
+  if (blockIdx.x >= sort_chunks(n, chunk)) return;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const ah_hit x = st[i];
+    const u64 key = ((u64)x.pair << (kb.gb + kb.pb + 2)) | ((u64)x.genome << (kb.pb + 2)) |
+                    ((u64)x.pos << 2) | (u64)(x.strand_primer & 3u);
+    keys[i] = key;
     idx[i] = (u32)i;
+    atomicAdd(&h[key & 255u], 1u);
   }
+  __syncthreads();
+  hist[(u64)threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
 }
 
 __global__ __launch_bounds__(kBlock) void k_sort_hist(const u64* __restrict__ keys,
                                                       const u64* __restrict__ n_dev, int shift,
-                                                      u64* __restrict__ hist) {
+                                                      u32* __restrict__ hist) {
   __shared__ u32 h[256];
   const u64 n = *n_dev;
+  u64 chunk;
+  if (blockIdx.x >= sort_chunks(n, chunk)) return;
   h[threadIdx.x] = 0;
   __syncthreads();
-  const u64 chunk = (n + gridDim.x - 1) / gridDim.x;
-  const u64 beg = (u64)blockIdx.x * chunk;
-  const u64 end = beg + chunk < n ? beg + chunk : n;
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x)
     atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
   __syncthreads();
-  hist[(u64)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+  hist[(u64)threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter: items keep their order within a digit (block, then tile,
-// then wave, then lane).
-__global__ __launch_bounds__(kBlock) void k_sort_scatter(const u64* __restrict__ kin,
-                                                         const u32* __restrict__ iin,
-                                                         u64* __restrict__ kout, u32* __restrict__ iout,
-                                                         const u64* __restrict__ n_dev, int shift,
-                                                         const u64* __restrict__ hist_off) {
+// Stable scatter: items keep their order within a digit (chunk, then round,
+// then wave, then lane).  With `out` set (last pass) the records themselves
+// are written in sorted order instead of keys and indices.
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(
+    const u64* __restrict__ kin, const u32* __restrict__ iin, u64* __restrict__ kout,
+    u32* __restrict__ iout, const u64* __restrict__ n_dev, int shift, const u32* __restrict__ hist,
+    const ah_hit* __restrict__ staged, ah_hit* __restrict__ out) {
   __shared__ u64 run[256];
   __shared__ u32 wcnt[4][256];
+  __shared__ u64 lds4[4];
   const u64 n = *n_dev;
-  const u64 chunk = (n + gridDim.x - 1) / gridDim.x;
-  const u64 beg = (u64)blockIdx.x * chunk;
-  const u64 end = beg + chunk < n ? beg + chunk : n;
-  run[threadIdx.x] = hist_off[(u64)threadIdx.x * gridDim.x + blockIdx.x];
+  u64 chunk;
+  const u32 G = sort_chunks(n, chunk);
+  if (blockIdx.x >= G) return;
+  // this chunk's first slot per digit: records of smaller digits, then those
+  // of the same digit in earlier chunks (thread = digit)
+  {
+    const uint4* row = (const uint4*)(hist + (u64)threadIdx.x * kSortGrid);
+    u64 tot = 0, before = 0;
+#pragma unroll 16
+    for (u32 q = 0; q < kSortGrid / 4; ++q) {
+      if (4 * q >= G) break;
+      const uint4 v = row[q];
+      const u32 c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (u32 e = 0; e < 4; ++e) {
+        const u32 w = 4 * q + e;
+        tot += w < G ? c[e] : 0u;
+        before += w < blockIdx.x ? c[e] : 0u;
+      }
+    }
+    u64 all;
+    run[threadIdx.x] = block_exclusive_scan(tot, lds4, all) + before;
+  }
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (u64 base = beg; base < end; base += blockDim.x) {
     for (int q = 0; q < 4; ++q) wcnt[q][threadIdx.x] = 0;
@@ -231,22 +316,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const u64* __restrict__
     if (valid) {
       u64 dst = run[d] + rank;
       for (int q = 0; q < w; ++q) dst += wcnt[q][d];
-      kout[dst] = key;
-      iout[dst] = id;
+      if (out) {
+        out[dst] = staged[id];
+      } else {
+        kout[dst] = key;
+        iout[dst] = id;
+      }
     }
     __syncthreads();
     run[threadIdx.x] += (u64)wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
                         wcnt[3][threadIdx.x];
     __syncthreads();
   }
-}
-
-__global__ __launch_bounds__(kBlock) void k_gather(const ah_hit* __restrict__ st,
-                                                   const u32* __restrict__ idx,
-                                                   const u64* __restrict__ n_dev,
-                                                   ah_hit* __restrict__ out) {
-  const u64 n = *n_dev;
-  for (u64 i = global_tid(); i < n; i += grid_threads()) out[i] = st[idx[i]];
 }
 
 // ------------------------------------------------ melting temperature ----
@@ -389,11 +470,38 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
 }
 
 // ----------------------------------------------------------- pairing ----
-__global__ void k_pair_n(const ah_result* __restrict__ nhits, u64 cap, u64* __restrict__ n_out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const u64 c = nhits->count;
-    *n_out = c < cap ? c : cap;
+// Four kernels over the same partition of the sorted hits into G <= kPairGrid
+// contiguous chunks, one per workgroup; each kernel derives its chunk's
+// offsets from the previous kernel's per-chunk totals itself.
+//   mark:    kept minus sites of the fwd and rev primer per chunk;
+//   compact: the minus sites into two lists ordered like the hits;
+//   count:   amplicons started by each leader + site, and per chunk;
+//   write:   the amplicons at their offsets, and the result.
+constexpr u64 kPairChunkMin = kBlock;
+
+__device__ __forceinline__ u32 pair_chunks(u64 n, u64& chunk) {
+  u64 c = (n + kPairGrid - 1) / kPairGrid;
+  c = (c + kBlock - 1) / kBlock * kBlock;
+  chunk = c < kPairChunkMin ? kPairChunkMin : c;
+  return (u32)((n + chunk - 1) / chunk);
+}
+
+__device__ __forceinline__ u64 pair_n(const ah_result* nhits, u64 cap) {
+  const u64 c = nhits->count;
+  return c < cap ? c : cap;
+}
+
+// Sum of part[w] over w < upto (and over all w < G into *total), G <= kPairGrid.
+__device__ __forceinline__ u64 chunk_prefix(const u64* __restrict__ part, u32 G, u32 upto,
+                                            u64* lds4, u64* total) {
+  u64 b = 0, t = 0;
+  for (u32 w = threadIdx.x; w < G; w += blockDim.x) {
+    const u64 v = part[w];
+    t += v;
+    b += w < upto ? v : 0u;
   }
+  if (total) *total = block_sum(t, lds4);
+  return block_sum(b, lds4);
 }
 
 __device__ __forceinline__ bool kept(const ah_hit& h, const PairTab* tabs) {
@@ -401,37 +509,75 @@ __device__ __forceinline__ bool kept(const ah_hit& h, const PairTab* tabs) {
   return !p.filter_tm || h.tm >= p.min_tm;  // NaN fails the filter
 }
 
+// 1: fwd-primer (bit 0) and rev-primer (bit 1) kept minus site
+__device__ __forceinline__ u32 minus_kind(const ah_hit& h, const PairTab* tabs) {
+  if (!((h.strand_primer >> 1) & 1u) || !kept(h, tabs)) return 0u;
+  return (h.strand_primer & 1u) ? 2u : 1u;
+}
+
 __global__ __launch_bounds__(kBlock) void k_pair_mark(const ah_hit* __restrict__ hits,
-                                                      const u64* __restrict__ n_dev,
+                                                      const ah_result* __restrict__ nhits, u64 hcap,
                                                       const PairTab* __restrict__ tabs,
-                                                      u32* __restrict__ ff, u32* __restrict__ fr) {
-  const u64 n = *n_dev;
-  for (u64 i = global_tid(); i < n; i += grid_threads()) {
-    const ah_hit h = hits[i];
-    const bool minus = (h.strand_primer >> 1) & 1u;
-    const bool k = kept(h, tabs) && minus;
-    ff[i] = k && !(h.strand_primer & 1u);
-    fr[i] = k && (h.strand_primer & 1u);
+                                                      u64* __restrict__ cf, u64* __restrict__ cr) {
+  __shared__ u64 lds4[4];
+  const u64 n = pair_n(nhits, hcap);
+  u64 chunk;
+  if (blockIdx.x >= pair_chunks(n, chunk)) return;
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  u64 f = 0, r = 0;
+  for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const u32 k = minus_kind(hits[i], tabs);
+    f += k & 1u;
+    r += k >> 1;
+  }
+  f = block_sum(f, lds4);
+  r = block_sum(r, lds4);
+  if (threadIdx.x == 0) {
+    cf[blockIdx.x] = f;
+    cr[blockIdx.x] = r;
   }
 }
 
+// mtot = {fwd list length, rev list length}, written by workgroup 0.
 __global__ __launch_bounds__(kBlock) void k_pair_compact(
-    const ah_hit* __restrict__ hits, const u64* __restrict__ n_dev, const u32* __restrict__ ff,
-    const u32* __restrict__ fr, const u64* __restrict__ off_f, const u64* __restrict__ off_r,
+    const ah_hit* __restrict__ hits, const ah_result* __restrict__ nhits, u64 hcap,
+    const PairTab* __restrict__ tabs, const u64* __restrict__ cf, const u64* __restrict__ cr,
     u64* __restrict__ kf, u32* __restrict__ pf, u32* __restrict__ xf, u64* __restrict__ kr,
-    u32* __restrict__ pr, u32* __restrict__ xr) {
-  const u64 n = *n_dev;
-  for (u64 i = global_tid(); i < n; i += grid_threads()) {
-    if (!ff[i] && !fr[i]) continue;
-    const ah_hit h = hits[i];
+    u32* __restrict__ pr, u32* __restrict__ xr, u64* __restrict__ mtot) {
+  __shared__ u64 lds4[4];
+  const u64 n = pair_n(nhits, hcap);
+  u64 chunk;
+  const u32 G = pair_chunks(n, chunk);
+  if (blockIdx.x >= (G ? G : 1u)) return;  // workgroup 0 runs even for no hits
+  u64 tf, tr;
+  u64 bf = chunk_prefix(cf, G, blockIdx.x, lds4, &tf);
+  u64 br = chunk_prefix(cr, G, blockIdx.x, lds4, &tr);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    mtot[0] = tf;
+    mtot[1] = tr;
+  }
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  for (u64 base = beg; base < end; base += blockDim.x) {
+    const u64 i = base + threadIdx.x;
+    ah_hit h{};
+    u32 k = 0;
+    if (i < end) {
+      h = hits[i];
+      k = minus_kind(h, tabs);
+    }
+    u64 sf, sr;
+    const u64 ef = block_exclusive_scan(k & 1u, lds4, sf);
+    const u64 er = block_exclusive_scan(k >> 1, lds4, sr);
     const u64 key = ((u64)h.pair << 32) | h.genome;
-    if (ff[i]) {
-      const u64 j = off_f[i];
+    if (k == 1u) {
+      const u64 j = bf + ef;
       kf[j] = key; pf[j] = h.pos; xf[j] = (u32)i;
-    } else {
-      const u64 j = off_r[i];
+    } else if (k == 2u) {
+      const u64 j = br + er;
       kr[j] = key; pr[j] = h.pos; xr[j] = (u32)i;
     }
+    bf += sf;
+    br += sr;
   }
 }
 
@@ -491,13 +637,18 @@ __device__ __forceinline__ int group_of(const ah_hit* hits, u64 n, u64 i, const 
 }
 
 __global__ __launch_bounds__(kBlock) void k_pair_count(
-    const ah_hit* __restrict__ hits, const u64* __restrict__ n_dev, const PairTab* __restrict__ tabs,
-    const u64* __restrict__ kf, const u32* __restrict__ pf, const u64* __restrict__ off_f,
-    const u64* __restrict__ kr, const u32* __restrict__ pr, const u64* __restrict__ off_r,
-    u32* __restrict__ cnt) {
-  const u64 n = *n_dev;
-  const u64 mf = off_f[n], mr = off_r[n];
-  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+    const ah_hit* __restrict__ hits, const ah_result* __restrict__ nhits, u64 hcap,
+    const PairTab* __restrict__ tabs, const u64* __restrict__ kf, const u32* __restrict__ pf,
+    const u64* __restrict__ kr, const u32* __restrict__ pr, const u64* __restrict__ mtot,
+    u32* __restrict__ cnt, u64* __restrict__ cc) {
+  __shared__ u64 lds4[4];
+  const u64 n = pair_n(nhits, hcap);
+  u64 chunk;
+  if (blockIdx.x >= pair_chunks(n, chunk)) return;
+  const u64 mf = mtot[0], mr = mtot[1];
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  u64 sum = 0;
+  for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x) {
     ah_hit a[2];
     const int ng = group_of(hits, n, i, tabs, a[0], a[1]);
     u64 c = 0;
@@ -509,22 +660,43 @@ __global__ __launch_bounds__(kBlock) void k_pair_count(
       c += (rf.end - rf.beg) + (rr.end - rr.beg);
     }
     cnt[i] = (u32)c;
+    sum += c;
   }
+  sum = block_sum(sum, lds4);
+  if (threadIdx.x == 0) cc[blockIdx.x] = sum;
 }
 
 __global__ __launch_bounds__(kBlock) void k_pair_write(
-    const ah_hit* __restrict__ hits, const u64* __restrict__ n_dev, const PairTab* __restrict__ tabs,
-    const u64* __restrict__ kf, const u32* __restrict__ pf, const u32* __restrict__ xf,
-    const u64* __restrict__ off_f, const u64* __restrict__ kr, const u32* __restrict__ pr,
-    const u32* __restrict__ xr, const u64* __restrict__ off_r, const u64* __restrict__ cnt_off,
-    ah_amplicon* __restrict__ amp, u64 cap) {
-  const u64 n = *n_dev;
-  const u64 mf = off_f[n], mr = off_r[n];
-  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+    const ah_hit* __restrict__ hits, const ah_result* __restrict__ nhits, u64 hcap,
+    const PairTab* __restrict__ tabs, const u64* __restrict__ kf, const u32* __restrict__ pf,
+    const u32* __restrict__ xf, const u64* __restrict__ kr, const u32* __restrict__ pr,
+    const u32* __restrict__ xr, const u64* __restrict__ mtot, const u32* __restrict__ cnt,
+    const u64* __restrict__ cc, ah_amplicon* __restrict__ amp, u64 cap, ah_result* __restrict__ res) {
+  __shared__ u64 lds4[4];
+  const u64 n = pair_n(nhits, hcap);
+  u64 chunk;
+  const u32 G = pair_chunks(n, chunk);
+  if (blockIdx.x >= (G ? G : 1u)) return;  // workgroup 0 writes the result even for no hits
+  u64 total;
+  u64 run = chunk_prefix(cc, G, blockIdx.x, lds4, &total);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    res->required = total;
+    res->count = total < cap ? total : cap;
+    res->status = total > cap ? AH_ERR_OVERFLOW : AH_OK;
+    res->reserved = 0;
+  }
+  const u64 mf = mtot[0], mr = mtot[1];
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  for (u64 rb = beg; rb < end; rb += blockDim.x) {
+    const u64 i = rb + threadIdx.x;
+    const u32 ci = i < end ? cnt[i] : 0u;
+    u64 rt;
+    const u64 base = run + block_exclusive_scan(ci, lds4, rt);
+    run += rt;
+    if (ci == 0) continue;
     ah_hit a[2];
     const int ng = group_of(hits, n, i, tabs, a[0], a[1]);
     if (ng == 0) continue;
-    const u64 base = cnt_off[i];
     if (base >= cap) continue;
     // up to four lists, each ordered by end: (a primer, b primer)
     Range r[4];
@@ -568,17 +740,6 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
       amp[w++] = A;
       ++r[best].beg;
     }
-  }
-}
-
-__global__ void k_pair_finalize(const u64* __restrict__ n_dev, const u64* __restrict__ cnt_off,
-                                u64 cap, ah_result* __restrict__ res) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const u64 req = cnt_off[*n_dev];
-    res->required = req;
-    res->count = req < cap ? req : cap;
-    res->status = req > cap ? AH_ERR_OVERFLOW : AH_OK;
-    res->reserved = 0;
   }
 }
 
@@ -647,14 +808,6 @@ __global__ __launch_bounds__(kBlock) void k_remap(ah_hit* __restrict__ hits,
 // sites.
 // Runs after the result is finalised, so `count` stays the number of records
 // written; only `required` and `status` change.
-__global__ void k_cand_overflow(const u64* __restrict__ stat, u32 grid, ah_result* r) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && stat[2] > 0) {
-    u64 bound = stat[1] > (u64)grid * stat[3] ? stat[1] : (u64)grid * stat[3];
-    if (bound > r->required) r->required = bound;
-    r->status = AH_ERR_OVERFLOW;
-  }
-}
-
 }  // namespace
 
 // ---------------------------------------------------------- launchers ----
@@ -675,8 +828,9 @@ hipError_t launch_result_init(ah_result* res, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_result_finalize(ah_result* res, uint64_t cap, uint64_t* n_out, hipStream_t st) {
-  k_result_finalize<<<1, 64, 0, st>>>(res, cap, (u64*)n_out);
+hipError_t launch_tile_prefix_small(const uint32_t* len, uint32_t n, uint32_t tile_words,
+                                    uint64_t* prefix, ah_result* res, hipStream_t st) {
+  k_tile_prefix_small<<<1, kSmallBlock, 0, st>>>(len, n, tile_words, (u64*)prefix, res);
   return hipGetLastError();
 }
 
@@ -706,22 +860,20 @@ hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, const ui
 
 hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev, KeyBits kb,
                             const SortBuffers& sb, hipStream_t st) {
-  const int grid = 1024;
-  k_keygen<<<grid, kBlock, 0, st>>>(staged, (const u64*)n_dev, kb, (u64*)sb.keys[0], sb.idx[0]);
-  int cur = 0;
   const int bits = kb.total();
+  k_keygen<<<kSortGrid, kBlock, 0, st>>>(staged, (const u64*)n_dev, kb, (u64*)sb.keys[0], sb.idx[0],
+                                         sb.hist);
+  int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
-    k_sort_hist<<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], (const u64*)n_dev, shift,
-                                             (u64*)sb.hist);
-    hipError_t e = launch_exclusive_scan(sb.hist, sb.hist_off, (uint64_t)256 * kSortGrid, nullptr,
-                                         sb.scan_tmp, st);
-    if (e != hipSuccess) return e;
-    k_sort_scatter<<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], sb.idx[cur],
-                                                (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1],
-                                                (const u64*)n_dev, shift, (const u64*)sb.hist_off);
+    if (shift > 0)
+      k_sort_hist<<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], (const u64*)n_dev, shift,
+                                               sb.hist);
+    const bool last = shift + 8 >= bits;
+    k_sort_scatter<<<kSortGrid, kBlock, 0, st>>>(
+        (const u64*)sb.keys[cur], sb.idx[cur], (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1],
+        (const u64*)n_dev, shift, sb.hist, staged, last ? out : nullptr);
     cur ^= 1;
   }
-  k_gather<<<grid, kBlock, 0, st>>>(staged, sb.idx[cur], (const u64*)n_dev, out);
   return hipGetLastError();
 }
 
@@ -734,26 +886,19 @@ hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pair
 
 hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
-                       const PairBuffers& pb, int grid, hipStream_t st) {
-  const u64* n = (const u64*)pb.n;
-  k_pair_n<<<1, 64, 0, st>>>(nhits, hit_cap, (u64*)pb.n);
-  k_pair_mark<<<grid, kBlock, 0, st>>>(hits, n, tabs, pb.flag_f, pb.flag_r);
-  hipError_t e = launch_exclusive_scan_u32(pb.flag_f, pb.off_f, pb.n, pb.scan_tmp, st);
-  if (e == hipSuccess) e = launch_exclusive_scan_u32(pb.flag_r, pb.off_r, pb.n, pb.scan_tmp, st);
-  if (e != hipSuccess) return e;
-  k_pair_compact<<<grid, kBlock, 0, st>>>(hits, n, pb.flag_f, pb.flag_r, (const u64*)pb.off_f,
-                                          (const u64*)pb.off_r, (u64*)pb.mkey_f, pb.mpos_f, pb.midx_f,
-                                          (u64*)pb.mkey_r, pb.mpos_r, pb.midx_r);
-  k_pair_count<<<grid, kBlock, 0, st>>>(hits, n, tabs, (const u64*)pb.mkey_f, pb.mpos_f,
-                                        (const u64*)pb.off_f, (const u64*)pb.mkey_r, pb.mpos_r,
-                                        (const u64*)pb.off_r, pb.cnt);
-  e = launch_exclusive_scan_u32(pb.cnt, pb.cnt_off, pb.n, pb.scan_tmp, st);
-  if (e != hipSuccess) return e;
-  k_pair_write<<<grid, kBlock, 0, st>>>(hits, n, tabs, (const u64*)pb.mkey_f, pb.mpos_f, pb.midx_f,
-                                        (const u64*)pb.off_f, (const u64*)pb.mkey_r, pb.mpos_r,
-                                        pb.midx_r, (const u64*)pb.off_r, (const u64*)pb.cnt_off, amp,
-                                        cap);
-  k_pair_finalize<<<1, 64, 0, st>>>(n, (const u64*)pb.cnt_off, cap, res);
+                       const PairBuffers& pb, hipStream_t st) {
+  k_pair_mark<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (u64*)pb.cf, (u64*)pb.cr);
+  k_pair_compact<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.cf,
+                                              (const u64*)pb.cr, (u64*)pb.mkey_f, pb.mpos_f,
+                                              pb.midx_f, (u64*)pb.mkey_r, pb.mpos_r, pb.midx_r,
+                                              (u64*)pb.mtot);
+  k_pair_count<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.mkey_f,
+                                            pb.mpos_f, (const u64*)pb.mkey_r, pb.mpos_r,
+                                            (const u64*)pb.mtot, pb.cnt, (u64*)pb.cc);
+  k_pair_write<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.mkey_f,
+                                            pb.mpos_f, pb.midx_f, (const u64*)pb.mkey_r, pb.mpos_r,
+                                            pb.midx_r, (const u64*)pb.mtot, pb.cnt,
+                                            (const u64*)pb.cc, amp, cap, res);
   return hipGetLastError();
 }
 
@@ -788,11 +933,6 @@ hipError_t launch_remap(ah_hit* hits, const ah_result* hres, ah_amplicon* amp, c
 
 hipError_t launch_zero_u64(uint64_t* p, uint32_t n, hipStream_t st) {
   k_zero_u64<<<1, 64, 0, st>>>((u64*)p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_cand_overflow(const uint64_t* stat, uint32_t grid, ah_result* res, hipStream_t st) {
-  k_cand_overflow<<<1, 64, 0, st>>>((const u64*)stat, grid, res);
   return hipGetLastError();
 }
 

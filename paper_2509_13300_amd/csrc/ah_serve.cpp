@@ -464,6 +464,15 @@ struct ah_server {
             j->status = ah::set_error(AH_ERR_LIMIT, "a part of job %llu has %llu sites",
                                       (unsigned long long)j->id,
                                       (unsigned long long)hr[0].required);
+        } else if (hr[0].required <= p.hcap && hr[1].required <= p.acap) {
+          // a rerun with the same buffers would overflow again
+          if (j->status == AH_OK)
+            j->status = ah::set_error(AH_ERR_LIMIT,
+                                      "a part of job %llu overflows buffers sized for its "
+                                      "counts (%llu sites, %llu amplicons)",
+                                      (unsigned long long)j->id,
+                                      (unsigned long long)hr[0].required,
+                                      (unsigned long long)hr[1].required);
         } else {
           p.hcap = std::max<uint64_t>(p.hcap, hr[0].required);
           p.acap = std::max<uint64_t>(p.acap, hr[1].required);

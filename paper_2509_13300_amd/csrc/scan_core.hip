@@ -21,8 +21,15 @@
 //   path, where same-address device atomics would serialise).
 // * ah_verify_kernel: one workgroup per slice; the exact count (every
 //   position, the non-ACGT mask, the clamp, window starts inside the genome)
-//   of every candidate, which appends the binding sites.  Kept apart from the
-//   filter so that its registers do not lower the filter's occupancy.
+//   of every candidate, stored per candidate and summed per slice.  Kept
+//   apart from the filter so that its registers do not lower the filter's
+//   occupancy.
+// * ah_emit_kernel: one workgroup per slice; the slice's output offset is the
+//   sum of the earlier slices' sites (no device atomics), and the candidates
+//   with sites are counted again, now writing the site records.  Workgroup 0
+//   also writes the result (required = sites found, count = records written)
+//   and the candidate-list statistics; a full slice makes the result an
+//   overflow whose bound covers both lists.
 //
 // Macros supplied by the generated program: AH_U (window words per lane, odd
 // so that the lanes' LDS reads fall in distinct banks), AH_HALO (longest
@@ -36,6 +43,15 @@ typedef unsigned long long u64;
 #define AH_BLOCK 256
 #endif
 #define AH_TILE (AH_BLOCK * AH_U)
+
+// Must match ah_result in ah.h.
+struct AhResult {
+  u64 count;
+  u64 required;
+  int status;
+  u32 reserved;
+};
+#define AH_RES_OVERFLOW (-4)
 
 // Must match ah_hit in ah.h (16 bytes).
 struct AhHitRec {
@@ -67,7 +83,7 @@ struct AhCands {
 
 // This workgroup's candidate count and the windows in them.
 __shared__ u32 ah_n_cand;
-__shared__ u32 ah_n_win;
+__shared__ unsigned long long ah_n_lost;  // windows of the candidates a full slice dropped
 
 // Window starts b*S + t (b = 0..31) that lie inside the genome for a primer
 // of length L, as a bit mask over b.
@@ -137,17 +153,25 @@ __device__ __forceinline__ void ah_cand(const AhCtx& c, const AhCands& k, u32 t,
                                         u32 cand) {
   if (t >= c.S) return;  // lanes past the genome's last window word
   const u32 slot = atomicAdd(&ah_n_cand, 1u);
-  atomicAdd(&ah_n_win, (u32)__popc(cand));
-  if (slot < k.slice) k.out[(u64)blockIdx.x * k.slice + slot] = make_uint4(c.g, t, pattern, cand);
+  if (slot < k.slice)
+    k.out[(u64)blockIdx.x * k.slice + slot] = make_uint4(c.g, t, pattern, cand);
+  else
+    atomicAdd(&ah_n_lost, (unsigned long long)__popc(cand));
 }
 
-// One-hot planes of a packed word: bit b of each is set iff base b*S + t is
-// that base (A=00, C=01, G=10, T=11 in (h, l)).
-__device__ __forceinline__ void ah_onehot(uint2 v, u32& a, u32& c, u32& g, u32& t) {
+// Bit planes of a packed word: bit b of the one-hot planes a/c/g/t is set iff
+// base b*S + t is that base (A=00, C=01, G=10, T=11 in (h, l)); h, l and
+// x = h ^ l hold the two-base classes.  Planes a filter never reads cost
+// nothing (the compiler drops them).
+__device__ __forceinline__ void ah_planes(uint2 v, u32& a, u32& c, u32& g, u32& t, u32& h, u32& l,
+                                          u32& x) {
   a = ~(v.x | v.y);
   c = ~v.x & v.y;
   g = v.x & ~v.y;
   t = v.x & v.y;
+  h = v.x;
+  l = v.y;
+  x = v.x ^ v.y;
 }
 
 typedef __attribute__((address_space(3))) const uint2 ah_lds_uint2;
@@ -193,13 +217,14 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     const uint2* __restrict__ words, const u32* __restrict__ nmask,
     const u64* __restrict__ word_off, const u32* __restrict__ len,
     const u64* __restrict__ tile_prefix, u32 n_genomes, uint4* __restrict__ cand_out,
-    u32 slice, u32* __restrict__ slice_count, u64* __restrict__ cand_stat) {
+    u32 slice, u32* __restrict__ slice_count, u32* __restrict__ slice_total,
+    u64* __restrict__ slice_win) {
   __shared__ uint4 tile[AH_STAGE_PAIRS];
   const u64 n_tiles = tile_prefix[n_genomes];
   const AhCands k{cand_out, slice};
   if (threadIdx.x == 0) {
     ah_n_cand = 0;
-    ah_n_win = 0;
+    ah_n_lost = 0;
   }
   __syncthreads();
   u32 lo = 0;
@@ -215,12 +240,8 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
   }
   if (threadIdx.x == 0) {  // every workgroup reports, with or without tiles
     slice_count[blockIdx.x] = min(ah_n_cand, slice);
-    if (ah_n_cand) {
-      atomicAdd(&cand_stat[0], (u64)ah_n_cand);
-      atomicAdd(&cand_stat[1], (u64)ah_n_win);
-      if (ah_n_cand > slice) atomicAdd(&cand_stat[2], 1ull);
-      atomicMax(&cand_stat[3], (u64)ah_n_cand);
-    }
+    slice_total[blockIdx.x] = ah_n_cand;
+    slice_win[blockIdx.x] = ah_n_lost;  // the verify kernel adds the kept ones
   }
 }
 
@@ -228,32 +249,137 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
     const uint2* __restrict__ words, const u32* __restrict__ nmask,
     const u64* __restrict__ word_off, const u32* __restrict__ len,
     const uint4* __restrict__ cands, u32 slice, const u32* __restrict__ slice_count,
-    AhHitRec* __restrict__ out, u64 cap, u64* __restrict__ counter) {
-  // One workgroup per slice, in rounds of one candidate per thread: count the
-  // round's sites, reserve their records with one atomic for the workgroup
-  // (same-address device atomics serialise), then count again and write.
-  __shared__ u32 round_sites;
-  __shared__ u64 round_base;
+    u32* __restrict__ cand_sites, u64* __restrict__ slice_sites, u64* __restrict__ slice_win) {
+  // Sites of each candidate of this workgroup's slice, their sum, and the
+  // candidates' windows (added to those of the candidates a full slice
+  // dropped).
+  __shared__ u64 s_sites, s_win;
+  if (threadIdx.x == 0) {
+    s_sites = 0;
+    s_win = 0;
+  }
+  __syncthreads();
   const u32 n = slice_count[blockIdx.x];
   const uint4* mine = cands + (u64)blockIdx.x * slice;
-  for (u32 r = 0; r < n; r += AH_BLOCK) {
-    if (threadIdx.x == 0) round_sites = 0;
-    __syncthreads();
-    const u32 i = r + threadIdx.x;
-    uint4 e = make_uint4(0, 0, 0, 0);
-    AhCtx c{};
-    u32 found = 0, off = 0;
-    if (i < n) {
-      e = mine[i];
-      c = ah_ctx(words, nmask, word_off, len, e.x);
-      found = ah_verify_one(c, c.gw + e.y, e.y, e.z, e.w, out, cap, 0, false);
-      if (found) off = atomicAdd(&round_sites, found);
+  u32* sites = cand_sites + (u64)blockIdx.x * slice;
+  u64 my_sites = 0, my_win = 0;
+  for (u32 i = threadIdx.x; i < n; i += AH_BLOCK) {
+    const uint4 e = mine[i];
+    const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
+    const u32 found = ah_verify_one(c, c.gw + e.y, e.y, e.z, e.w, nullptr, 0, 0, false);
+    sites[i] = found;
+    my_sites += found;
+    my_win += (u64)__popc(e.w);
+  }
+  if (my_sites) atomicAdd(&s_sites, my_sites);
+  atomicAdd(&s_win, my_win);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    slice_sites[blockIdx.x] = s_sites;
+    slice_win[blockIdx.x] += s_win;
+  }
+}
+
+// Exclusive prefix of one value per thread over the workgroup; *total gets
+// the sum.  Two barriers; `tmp` holds AH_BLOCK / 64 entries.
+__device__ __forceinline__ u64 ah_block_scan(u64 v, u64* tmp, u64* total) {
+  const u32 lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  u64 x = v;
+#pragma unroll
+  for (u32 o = 1; o < 64; o <<= 1) {
+    const u64 y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63u) tmp[w] = x;
+  __syncthreads();
+  u64 before = 0, all = 0;
+#pragma unroll
+  for (u32 q = 0; q < AH_BLOCK / 64; ++q) {
+    before += q < w ? tmp[q] : 0ull;
+    all += tmp[q];
+  }
+  *total = all;
+  __syncthreads();
+  return before + x - v;
+}
+
+extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
+    const uint2* __restrict__ words, const u32* __restrict__ nmask,
+    const u64* __restrict__ word_off, const u32* __restrict__ len,
+    const uint4* __restrict__ cands, u32 slice, const u32* __restrict__ slice_count,
+    const u32* __restrict__ slice_total, const u64* __restrict__ slice_win,
+    const u32* __restrict__ cand_sites, const u64* __restrict__ slice_sites, AhHitRec* __restrict__ out,
+    u64 cap, AhResult* __restrict__ res, u64* __restrict__ n_out, u64* __restrict__ cand_stat) {
+  __shared__ u64 tmp[AH_BLOCK / 64];
+  const u32 G = gridDim.x;
+  // this slice's first record: the sites of the earlier slices
+  u64 mine_before = 0, mine_all = 0;
+#pragma unroll 4
+  for (u32 w = threadIdx.x; w < G; w += AH_BLOCK) {
+    const u64 v = slice_sites[w];
+    mine_all += v;
+    mine_before += w < blockIdx.x ? v : 0ull;
+  }
+  u64 slot, found;
+  ah_block_scan(mine_before, tmp, &slot);
+  ah_block_scan(mine_all, tmp, &found);
+  if (blockIdx.x == 0) {
+    // candidate-list statistics: candidates, their windows, full slices, most
+    // of one workgroup
+    u64 c = 0, wn = 0, full = 0, mx = 0;
+    for (u32 w = threadIdx.x; w < G; w += AH_BLOCK) {
+      const u64 t = slice_total[w];
+      c += t;
+      wn += slice_win[w];
+      full += t > slice_count[w] ? 1ull : 0ull;
+      mx = t > mx ? t : mx;
     }
+    u64 sc, sw, sf;
+    ah_block_scan(c, tmp, &sc);
+    ah_block_scan(wn, tmp, &sw);
+    ah_block_scan(full, tmp, &sf);
+    // maximum: through the shuffle tree of each wave, then the waves
+    for (u32 o = 32; o > 0; o >>= 1) {
+      const u64 y = __shfl_xor(mx, o, 64);
+      mx = y > mx ? y : mx;
+    }
+    if ((threadIdx.x & 63u) == 0) tmp[threadIdx.x >> 6] = mx;
     __syncthreads();
-    if (threadIdx.x == 0 && round_sites) round_base = atomicAdd(counter, (u64)round_sites);
-    __syncthreads();
-    if (found) ah_verify_one(c, c.gw + e.y, e.y, e.z, e.w, out, cap, round_base + off, true);
-    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (u32 q = 0; q < AH_BLOCK / 64; ++q) mx = tmp[q] > mx ? tmp[q] : mx;
+      const u64 cnt = found < cap ? found : cap;
+      res->count = cnt;
+      res->required = found;
+      res->status = found > cap ? AH_RES_OVERFLOW : 0;
+      if (n_out) *n_out = cnt;
+      cand_stat[0] = sc;
+      cand_stat[1] = sw;
+      cand_stat[2] = sf;
+      cand_stat[3] = mx;
+      if (sf > 0) {  // dropped candidates: sites <= windows, list >= G x most
+        const u64 list = (u64)G * mx;
+        const u64 bound = sw > list ? sw : list;
+        if (bound > res->required) res->required = bound;
+        res->status = AH_RES_OVERFLOW;
+      }
+    }
+    __syncthreads();  // thread 0 has read tmp before the loop below reuses it
+  }
+  // the slice's candidates with sites, in order, written from `slot` on
+  const u32 n = slice_count[blockIdx.x];
+  const uint4* mine = cands + (u64)blockIdx.x * slice;
+  const u32* sites = cand_sites + (u64)blockIdx.x * slice;
+  for (u32 r = 0; r < n; r += AH_BLOCK) {
+    const u32 i = r + threadIdx.x;
+    const u32 f = i < n ? sites[i] : 0u;
+    u64 rt;
+    const u64 off = ah_block_scan(f, tmp, &rt);
+    if (f) {
+      const uint4 e = mine[i];
+      const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
+      ah_verify_one(c, c.gw + e.y, e.y, e.z, e.w, out, cap, slot + off, true);
+    }
+    slot += rt;
   }
 }
 

@@ -73,7 +73,7 @@ def _functions(src, i):
 
 
 def _positions(text):
-    return {int(m) for m in re.findall(r"\bp[acgt]\[(\d+)\]", text)}
+    return {int(m) for m in re.findall(r"\bp[acgthlx]\[(\d+)\]", text)}
 
 
 def test_generated_program_tests_every_non_n_position():
@@ -119,3 +119,26 @@ def test_generated_programs_compile_for_gfx950(seed):
         p.clamp = int(rs.randint(0, 6))
     size = L.ah_scan_program_compile(pairs, has_nmask=bool(seed % 2))
     assert size > 1000
+
+
+@pytest.mark.parametrize("n_genomes", [1, 1000, 100_000])
+@pytest.mark.parametrize("capacity", [0, 1, 5000, 1 << 20, 10_000_000])
+def test_workspace_of_a_size_holds_the_list_it_was_sized_for(n_genomes, capacity):
+    """A scan run with `capacity` needs at least max(capacity, 2^16) candidate
+    records (an overflow's `required` is sized so that a rerun with it as the
+    capacity keeps every workgroup's candidates); the minimum workspace for
+    that capacity must hold them, whatever its alignment, and the
+    recommended one at least as many."""
+    g = L.ah_genomes()
+    g.n = n_genomes
+    g.max_len = 4_000_000
+    need = max(capacity, 1 << 16)
+    minimum = L.ah_scan_workspace_bytes(g, 1, capacity)
+    recommended = L.ah_scan_workspace_bytes(
+        g, [("GCMCCTGGYAAACTGTTGG", "AAAGACGTATGACGATCWNA", 2, 0)], capacity)
+    assert recommended >= minimum
+    for off in (0, 8, 128, 255):
+        assert L.ah_scan_candidate_capacity(minimum, n_genomes, capacity, off) >= need
+        assert L.ah_scan_candidate_capacity(recommended, n_genomes, capacity, off) >= need
+    # and a little less than the minimum holds fewer (the size is tight)
+    assert L.ah_scan_candidate_capacity(minimum - 600, n_genomes, capacity) < need

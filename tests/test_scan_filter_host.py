@@ -32,7 +32,7 @@ def run_filter(body, planes):
 
     def val(tok):
         tok = tok.strip()
-        m = re.fullmatch(r"(p[acgt])\[(\d+)\]", tok)
+        m = re.fullmatch(r"(p[acgthlx])\[(\d+)\]", tok)
         if m:
             return planes[m.group(1)][int(m.group(2))]
         if tok.endswith("u") and tok[:-1].isdigit():
@@ -72,15 +72,26 @@ def planned_rate(body, i):
     return float(re.search(rf"// pattern {i}: .*random pass rate ([0-9.e+-]+)", body).group(1))
 
 
-def random_pass_rate(fn, length, rs, n_words):
-    win = rs.choice(list("ACGT"), size=(n_words * 32, length))
+# bit planes over the windows: the one-hot planes and those of the 2-bit code
+# (A=00, C=01, G=10, T=11 in (h, l)), as in the scan kernel
+PLANE_SETS = (("pa", "A"), ("pc", "C"), ("pg", "G"), ("pt", "T"), ("ph", "GT"), ("pl", "CT"),
+              ("px", "CG"))
+
+
+def planes_of(win, n_words):
+    length = win.shape[1]
     weights = (np.uint64(1) << np.arange(32, dtype=np.uint64))
     planes = {}
-    for p, base in (("pa", "A"), ("pc", "C"), ("pg", "G"), ("pt", "T")):
-        bits = (win == base).reshape(n_words, 32, length)
+    for p, bases in PLANE_SETS:
+        bits = np.isin(win, list(bases)).reshape(n_words, 32, length)
         planes[p] = [((bits[:, :, j].astype(np.uint64) * weights).sum(1)).astype(np.uint32)
                      for j in range(length)]
-    got = run_filter(fn, planes)
+    return planes
+
+
+def random_pass_rate(fn, length, rs, n_words):
+    win = rs.choice(list("ACGT"), size=(n_words * 32, length))
+    got = run_filter(fn, planes_of(win, n_words))
     return sum(bin(int(x)).count("1") for x in got) / (n_words * 32)
 
 
@@ -110,13 +121,7 @@ def check_pair(fwd, rev, k, clamp, rs, n_words=64):
         mism = np.array([[win[w, j] not in sets[j] for j in range(Lp)] for w in range(W)])
         ok = (mism.sum(1) <= k) & ~mism[:, sorted(clamp_pos)].any(1) if clamp_pos else \
             (mism.sum(1) <= k)
-        planes = {}
-        weights = (np.uint64(1) << np.arange(32, dtype=np.uint64))
-        for p, base in (("pa", "A"), ("pc", "C"), ("pg", "G"), ("pt", "T")):
-            bits = (win == base).reshape(n_words, 32, Lp)
-            planes[p] = [((bits[:, :, j].astype(np.uint64) * weights).sum(1)).astype(np.uint32)
-                         for j in range(Lp)]
-        got = run_filter(fn, planes)
+        got = run_filter(fn, planes_of(win, n_words))
         passed = ((got[:, None] >> np.arange(32, dtype=np.uint32)) & 1).astype(bool).reshape(W)
         missed = np.flatnonzero(ok & ~passed)
         assert missed.size == 0, (fwd, rev, k, clamp, i, missed[:5])
@@ -152,3 +157,14 @@ def test_random_pairs():
         fwd = "".join(rs.choice(list(codes), size=rs.randint(10, 31)))
         rev = "".join(rs.choice(list(codes), size=rs.randint(10, 31)))
         check_pair(fwd, rev, int(rs.randint(0, 4)), int(rs.randint(0, 4)), rs, n_words=16)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_code_plane_literals_pass_every_site(case, monkeypatch):
+    """Two-base codes read as one bit plane of the 2-bit code (h, l or h ^ l,
+    maybe complemented) instead of the OR of two one-hot planes."""
+    monkeypatch.setenv("AH_SCAN_CODE_PLANES", "1")
+    src = L.ah_scan_program_source([case[:4]])
+    if any(ch in "RYSWKM" for ch in (case[0] + case[1]).upper()):
+        assert re.search(r"\bp[hlx]\[\d+\]", src.split("---- generated pattern program follows")[1])
+    check_pair(*case, rs=np.random.RandomState(19))
