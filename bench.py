@@ -221,11 +221,14 @@ def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 6
     t0 = time.perf_counter()
     L.ah_scan_prepare(pairs)
     prep_s = time.perf_counter() - t0
+    print(f"batched: {len(pairs)} pairs compiled in {prep_s:.1f} s; autotuning", file=sys.stderr,
+          flush=True)
     sample = min(200, coll.n)
     t0 = time.perf_counter()
     shape, tune_ms = L.ah_autotune_scan(path.subset_view(coll, sample), L.primer_pairs(pairs),
                                         buf.hits, buf.hit_cap, buf.hit_res, buf.scan_work, repeats=2)
     tune_s = time.perf_counter() - t0
+    print(f"batched: autotuned in {tune_s:.1f} s: {shape}", file=sys.stderr, flush=True)
     for _ in range(max(1, warmup)):
         path.run(coll, pairs, buf)
     torch.cuda.synchronize()
@@ -246,11 +249,15 @@ def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 6
     torch.cuda.synchronize()
     ms_batched = (time.perf_counter() - t0) * 1e3 / steps
     assert path.result(buf.hit_res)["count"] == rh["count"]
+    print(f"batched: {ms_batched:.2f} ms per step; the pairs one by one next", file=sys.stderr,
+          flush=True)
     # the same pairs one by one (each its own specialised kernel, prepared
     # concurrently beforehand)
     t0 = time.perf_counter()
     L.prepare_many([[q] for q in pairs])
     prep_seq_s = time.perf_counter() - t0
+    print(f"batched: {len(pairs)} single-pair kernels compiled in {prep_seq_s:.1f} s",
+          file=sys.stderr, flush=True)
     widest = max(pairs, key=lambda q: L.ah_scan_workspace_bytes(coll.view(), [q], 1 << 25))
     one = path.alloc(coll, [widest], 1 << 25, 1 << 24, dev)
     for q in pairs:

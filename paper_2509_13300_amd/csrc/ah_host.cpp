@@ -458,13 +458,14 @@ double at_least(const std::vector<double>& p, int need) {
 // one (64 lanes x 32 windows), and each candidate costs its exact count in
 // the verify kernel (about 8 operations per position, lane-parallel).
 // Weight of a candidate's exact count against filter operations
-// (AH_SCAN_CAND_WEIGHT, default 10, measured: the exact count, in its own
-// kernel, costs about ten times the estimate below in filter-equivalent
-// time): larger values choose stronger filters.
+// (AH_SCAN_CAND_WEIGHT, default 20, measured: the exact count, in its own
+// kernels and reading the candidate's words from HBM at random, costs about
+// twenty times the estimate below in filter-equivalent time): larger values
+// choose stronger filters.
 double cand_weight() {
   const char* e = getenv("AH_SCAN_CAND_WEIGHT");
-  const double w = e ? atof(e) : 10.0;
-  return w > 0 ? w : 10.0;
+  const double w = e ? atof(e) : 20.0;
+  return w > 0 ? w : 20.0;
 }
 
 double cand_cost(double rate, int L) {
@@ -1055,6 +1056,7 @@ struct ScanWs {
   uint32_t* slice_tot;    // [kMaxScanGrid] candidates found per workgroup
   uint64_t* slice_win;    // [kMaxScanGrid] windows in them
   uint64_t* slice_sites;  // [kMaxScanGrid] sites in the kept ones
+  uint64_t* group_sites;  // [kMaxScanGrid / 64, stride 32] sites of each group of 64 slices
   uint32_t* cand_sites;   // [ccap] sites of each kept candidate
   uint64_t* cstat;        // [0] candidates, [1] windows in them, [2] full slices, [3] most per workgroup
   uint64_t ccap;
@@ -1102,12 +1104,13 @@ ScanWs carve_scan(Carver& c, uint32_t n, uint64_t cap, uint64_t ccap) {
   w.sb.keys[1] = c.take<uint64_t>(cap ? cap : 1);
   w.sb.idx[0] = c.take<uint32_t>(cap ? cap : 1);
   w.sb.idx[1] = c.take<uint32_t>(cap ? cap : 1);
-  w.sb.hist = c.take<uint32_t>((uint64_t)256 * ah::kSortGrid);
+  w.sb.hist = c.take<uint32_t>((uint64_t)ah::kSortDigits * ah::kSortGrid);
   w.cstat = c.take<uint64_t>(4);
   w.slice_cnt = c.take<uint32_t>(kMaxScanGrid);
   w.slice_tot = c.take<uint32_t>(kMaxScanGrid);
   w.slice_win = c.take<uint64_t>(kMaxScanGrid);
   w.slice_sites = c.take<uint64_t>(kMaxScanGrid);
+  w.group_sites = c.take<uint64_t>(kMaxScanGrid / 64 * 32);
   // The candidate records and their site counts: `ccap` of them, or (ccap =
   // 0) as many as the rest holds.  A size computed for some ccap carries 512
   // spare bytes, so that the rest of a workspace of that size holds at least
@@ -1146,6 +1149,8 @@ ah::PairBuffers carve_pair(Carver& c, uint64_t cap) {
   b.mpos_r = c.take<uint32_t>(m);
   b.midx_r = c.take<uint32_t>(m);
   b.cnt = c.take<uint32_t>(m);
+  b.pre_f = c.take<uint32_t>(m);
+  b.pre_r = c.take<uint32_t>(m);
   return b;
 }
 
@@ -1194,8 +1199,9 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   uint32_t* slice_cnt = w.slice_cnt;
   uint32_t* slice_tot = w.slice_tot;
   uint64_t* slice_win = w.slice_win;
-  void* args[] = {&words, &nmask,     &word_off,  &len,      &tp,       &n,
-                  &cands, &slice,     &slice_cnt, &slice_tot, &slice_win};
+  uint64_t* group_sites = w.group_sites;
+  void* args[] = {&words, &nmask,     &word_off,  &len,       &tp,        &n,
+                  &cands, &slice,     &slice_cnt, &slice_tot, &slice_win, &group_sites};
   {
     ProfScope prof_scan("scan", st);
     AH_HIP(hipModuleLaunchKernel(fn.scan, grid, 1, 1, ah::kBlock, 1, 1, 0, st, args, nullptr));
@@ -1204,8 +1210,8 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   uint64_t* slice_sites = w.slice_sites;
   const uint4* ccands = w.cands;
   const uint32_t* cslice_cnt = w.slice_cnt;
-  void* vargs[] = {&words, &nmask,      &word_off,    &len,       &ccands,
-                   &slice, &cslice_cnt, &cand_sites,  &slice_sites, &slice_win};
+  void* vargs[] = {&words,      &nmask,      &word_off,    &len,         &ccands,   &slice,
+                   &cslice_cnt, &cand_sites, &slice_sites, &group_sites, &slice_win};
   {
     ProfScope prof_verify("verify", st);
     AH_HIP(hipModuleLaunchKernel(fn.verify, grid, 1, 1, ah::kBlock, 1, 1, 0, st, vargs, nullptr));
@@ -1215,11 +1221,12 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
     const uint64_t* cslice_win = w.slice_win;
     const uint32_t* ccand_sites = w.cand_sites;
     const uint64_t* cslice_sites = w.slice_sites;
+    const uint64_t* cgroup_sites = w.group_sites;
     uint64_t* n_out = w.n_sort;
     uint64_t* cstat = w.cstat;
-    void* eargs[] = {&words,      &nmask,       &word_off,     &len, &ccands, &slice,
-                     &cslice_cnt, &cslice_tot,  &cslice_win,   &ccand_sites, &cslice_sites,
-                     &out,        &cap,         &d_res,        &n_out, &cstat};
+    void* eargs[] = {&words,       &nmask,        &word_off,     &len,  &ccands,     &slice,
+                     &cslice_cnt,  &cslice_tot,   &cslice_win,   &ccand_sites, &cslice_sites,
+                     &cgroup_sites, &out,         &cap,          &d_res, &n_out,     &cstat};
     AH_HIP(hipModuleLaunchKernel(fn.emit, grid, 1, 1, ah::kBlock, 1, 1, 0, st, eargs, nullptr));
   }
   return AH_OK;

@@ -11,6 +11,7 @@ namespace ah {
 
 constexpr int kBlock = 256;        // threads per workgroup for every kernel
 constexpr int kSortGrid = 256;     // workgroups (chunks) of the radix-sort passes
+constexpr int kSortDigits = 512;   // most digit values of a radix-sort pass (9 bits)
 constexpr int kPairGrid = 1024;    // workgroups (chunks) of the pairing kernels
 constexpr int kScanGrid = 256;     // workgroups of the generic prefix scan
 constexpr int kScanU = 19;         // default window words per lane (odd) in the scan kernel
@@ -62,7 +63,7 @@ hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, const ui
 struct SortBuffers {
   uint64_t* keys[2];
   uint32_t* idx[2];
-  uint32_t* hist;      // 256 x kSortGrid digit counts (one row per digit)
+  uint32_t* hist;      // kSortDigits x kSortGrid digit counts (one row per digit)
 };
 hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev,
                             KeyBits kb, const SortBuffers& sb, hipStream_t st);
@@ -80,6 +81,8 @@ struct PairBuffers {
   uint32_t* mpos_r;
   uint32_t* midx_r;
   uint32_t* cnt;        // [cap] amplicons started by each leader + site
+  uint32_t* pre_f;      // [cap] fwd-list minus sites before each hit (search hint)
+  uint32_t* pre_r;      // [cap] rev-list
 };
 hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,

@@ -197,16 +197,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const T* __restrict__ in, 
 }
 
 // ------------------------------------------------------------ radix sort --
-// LSD radix sort of the hit records by their canonical key, 8 bits a pass.
-// Every pass splits the n records into the same G <= kSortGrid contiguous
-// chunks, one per workgroup: a histogram kernel writes each chunk's digit
-// counts, and the scatter kernel derives its chunk's output offsets from all
-// G histograms itself (no separate prefix-scan launches).  The first
-// histogram comes with the keys; the last scatter writes the records.  The
-// counts are stored digit-major (hist[digit * kSortGrid + chunk]), so that the
-// thread of a digit reads its G counts with 16-byte loads, all in flight at
-// once: the counts were written by another kernel and miss the caches.
-constexpr u64 kSortChunkMin = 4 * kBlock;
+// LSD radix sort of the hit records by their canonical key, D = 8 or 9 bits
+// a pass (9 when that saves a pass).  Every pass splits the n records into
+// the same G <= kSortGrid contiguous chunks, one per workgroup: a histogram
+// kernel writes each chunk's digit counts, and the scatter kernel derives
+// its chunk's output offsets from all G histograms itself (no separate
+// prefix-scan launches).  The first histogram comes with the keys; the last
+// scatter writes the records.  The counts are stored digit-major
+// (hist[digit * kSortGrid + chunk]), so that the thread of a digit reads its
+// G counts with 16-byte loads, all in flight at once: the counts were written
+// by another kernel and miss the caches.
+constexpr u64 kSortChunkMin = kBlock;
 
 __device__ __forceinline__ u32 sort_chunks(u64 n, u64& chunk) {
   u64 c = (n + kSortGrid - 1) / kSortGrid;
@@ -215,96 +216,163 @@ __device__ __forceinline__ u32 sort_chunks(u64 n, u64& chunk) {
   return (u32)((n + chunk - 1) / chunk);
 }
 
+// Digit counts of this chunk (h: 2^D LDS counters) into the digit-major table.
+template <int D>
+__device__ __forceinline__ void store_hist(const u32* h, u32* __restrict__ hist) {
+  for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x)
+    hist[(u64)d * kSortGrid + blockIdx.x] = h[d];
+}
+
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_keygen(const ah_hit* __restrict__ st,
                                                    const u64* __restrict__ n_dev, KeyBits kb,
                                                    u64* __restrict__ keys, u32* __restrict__ idx,
                                                    u32* __restrict__ hist) {
-  __shared__ u32 h[256];
+  __shared__ u32 h[1u << D];
   const u64 n = *n_dev;
   u64 chunk;
   if (blockIdx.x >= sort_chunks(n, chunk)) return;
-  h[threadIdx.x] = 0;
+  for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x) h[d] = 0;
   __syncthreads();
   const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
-  for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    const ah_hit x = st[i];
-    const u64 key = ((u64)x.pair << (kb.gb + kb.pb + 2)) | ((u64)x.genome << (kb.pb + 2)) |
-                    ((u64)x.pos << 2) | (u64)(x.strand_primer & 3u);
-    keys[i] = key;
-    idx[i] = (u32)i;
-    atomicAdd(&h[key & 255u], 1u);
+  for (u64 i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
+    ah_hit x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u64 i = i0 + (u64)q * blockDim.x;
+      if (i < end) x[q] = st[i];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u64 i = i0 + (u64)q * blockDim.x;
+      if (i >= end) continue;
+      const u64 key = ((u64)x[q].pair << (kb.gb + kb.pb + 2)) | ((u64)x[q].genome << (kb.pb + 2)) |
+                      ((u64)x[q].pos << 2) | (u64)(x[q].strand_primer & 3u);
+      keys[i] = key;
+      idx[i] = (u32)i;
+      atomicAdd(&h[key & ((1u << D) - 1u)], 1u);
+    }
   }
   __syncthreads();
-  hist[(u64)threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
+  store_hist<D>(h, hist);
 }
 
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_sort_hist(const u64* __restrict__ keys,
                                                       const u64* __restrict__ n_dev, int shift,
                                                       u32* __restrict__ hist) {
-  __shared__ u32 h[256];
+  __shared__ u32 h[1u << D];
   const u64 n = *n_dev;
   u64 chunk;
   if (blockIdx.x >= sort_chunks(n, chunk)) return;
-  h[threadIdx.x] = 0;
+  for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x) h[d] = 0;
   __syncthreads();
   const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
-  for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x)
-    atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  // four keys per thread in flight at once
+  for (u64 i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
+    u64 k[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u64 i = i0 + (u64)q * blockDim.x;
+      k[q] = i < end ? keys[i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (i0 + (u64)q * blockDim.x < end) atomicAdd(&h[(k[q] >> shift) & ((1u << D) - 1u)], 1u);
+  }
   __syncthreads();
-  hist[(u64)threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
+  store_hist<D>(h, hist);
 }
 
 // Stable scatter: items keep their order within a digit (chunk, then round,
 // then wave, then lane).  With `out` set (last pass) the records themselves
 // are written in sorted order instead of keys and indices.
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(
     const u64* __restrict__ kin, const u32* __restrict__ iin, u64* __restrict__ kout,
     u32* __restrict__ iout, const u64* __restrict__ n_dev, int shift, const u32* __restrict__ hist,
     const ah_hit* __restrict__ staged, ah_hit* __restrict__ out) {
-  __shared__ u64 run[256];
-  __shared__ u32 wcnt[4][256];
+  constexpr u32 NB = 1u << D, R = NB / kBlock;  // digits, digits per thread
+  __shared__ u64 run[NB];
+  __shared__ u32 wcnt[4][NB];
   __shared__ u64 lds4[4];
   const u64 n = *n_dev;
   u64 chunk;
   const u32 G = sort_chunks(n, chunk);
   if (blockIdx.x >= G) return;
   // this chunk's first slot per digit: records of smaller digits, then those
-  // of the same digit in earlier chunks (thread = digit)
+  // of the same digit in earlier chunks (thread t owns digits R t .. R t + R - 1)
   {
-    const uint4* row = (const uint4*)(hist + (u64)threadIdx.x * kSortGrid);
-    u64 tot = 0, before = 0;
-#pragma unroll 16
-    for (u32 q = 0; q < kSortGrid / 4; ++q) {
-      if (4 * q >= G) break;
-      const uint4 v = row[q];
-      const u32 c[4] = {v.x, v.y, v.z, v.w};
+    u64 tot[R], before[R];
 #pragma unroll
-      for (u32 e = 0; e < 4; ++e) {
-        const u32 w = 4 * q + e;
-        tot += w < G ? c[e] : 0u;
-        before += w < blockIdx.x ? c[e] : 0u;
+    for (u32 e = 0; e < R; ++e) {
+      const uint4* row = (const uint4*)(hist + (u64)(R * threadIdx.x + e) * kSortGrid);
+      tot[e] = 0;
+      before[e] = 0;
+#pragma unroll 16
+      for (u32 q = 0; q < kSortGrid / 4; ++q) {
+        if (4 * q >= G) break;
+        const uint4 v = row[q];
+        const u32 c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (u32 f = 0; f < 4; ++f) {
+          const u32 w = 4 * q + f;
+          tot[e] += w < G ? c[f] : 0u;
+          before[e] += w < blockIdx.x ? c[f] : 0u;
+        }
       }
     }
+    u64 mine = 0;
+#pragma unroll
+    for (u32 e = 0; e < R; ++e) mine += tot[e];
     u64 all;
-    run[threadIdx.x] = block_exclusive_scan(tot, lds4, all) + before;
+    u64 at = block_exclusive_scan(mine, lds4, all);
+#pragma unroll
+    for (u32 e = 0; e < R; ++e) {
+      run[R * threadIdx.x + e] = at + before[e];
+      at += tot[e];
+    }
   }
   const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  u64 pk[4];
+  u32 pi[4];
+  ah_hit ph[4];
   for (u64 base = beg; base < end; base += blockDim.x) {
-    for (int q = 0; q < 4; ++q) wcnt[q][threadIdx.x] = 0;
+    // the keys (and, in the last pass, the records) of four rounds are
+    // loaded together: one round's latency
+    const int r = (int)(((base - beg) / blockDim.x) & 3u);
+    if (r == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const u64 j = base + (u64)q * blockDim.x + threadIdx.x;
+        pk[q] = j < end ? kin[j] : 0;
+        pi[q] = j < end ? iin[j] : 0u;
+      }
+      if (out) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const u64 j = base + (u64)q * blockDim.x + threadIdx.x;
+          if (j < end) ph[q] = staged[pi[q]];
+        }
+      }
+    }
+    for (int q = 0; q < 4; ++q)
+      for (u32 d = threadIdx.x; d < NB; d += blockDim.x) wcnt[q][d] = 0;
     __syncthreads();
     const u64 i = base + threadIdx.x;
     const bool valid = i < end;
     u64 key = 0;
     u32 id = 0, d = 0;
     if (valid) {
-      key = kin[i];
-      id = iin[i];
-      d = (u32)((key >> shift) & 255u);
+      key = r == 0 ? pk[0] : r == 1 ? pk[1] : r == 2 ? pk[2] : pk[3];
+      id = r == 0 ? pi[0] : r == 1 ? pi[1] : r == 2 ? pi[2] : pi[3];
+      d = (u32)((key >> shift) & (NB - 1u));
     }
+    // lanes of this wave with the same digit, and this lane's rank among them
     u64 peers = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < D; ++bit) {
       const bool on = (d >> bit) & 1u;
       const u64 bal = __ballot(valid && on);
       peers &= on ? bal : ~bal;
@@ -317,15 +385,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
       u64 dst = run[d] + rank;
       for (int q = 0; q < w; ++q) dst += wcnt[q][d];
       if (out) {
-        out[dst] = staged[id];
+        out[dst] = r == 0 ? ph[0] : r == 1 ? ph[1] : r == 2 ? ph[2] : ph[3];
       } else {
         kout[dst] = key;
         iout[dst] = id;
       }
     }
     __syncthreads();
-    run[threadIdx.x] += (u64)wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
-                        wcnt[3][threadIdx.x];
+    for (u32 e = threadIdx.x; e < NB; e += blockDim.x)
+      run[e] += (u64)wcnt[0][e] + wcnt[1][e] + wcnt[2][e] + wcnt[3][e];
     __syncthreads();
   }
 }
@@ -369,6 +437,13 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
                                                ah_hit* __restrict__ hits,
                                                const ah_result* __restrict__ nhits, u64 cap,
                                                u32 n_genomes, u32 n_pairs) {
+  // the stack tables in LDS: lanes index them divergently, once per stack
+  __shared__ float s_dh[16], s_ds[16];
+  if (threadIdx.x < 16) {
+    s_dh[threadIdx.x] = c_nn_dh[threadIdx.x];
+    s_ds[threadIdx.x] = c_nn_ds[threadIdx.x];
+  }
+  __syncthreads();
   const u64 cnt = nhits->count;
   const u64 n = cnt < cap ? cnt : cap;
   for (u64 i = global_tid(); i < n; i += grid_threads()) {
@@ -428,8 +503,8 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
         const u32 j2 = (u32)__ffsll((long long)st) - 1u;
         st &= st - 1;
         const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
-        two_sum(sh, ch, c_nn_dh[ix]);
-        two_sum(ss, cs, c_nn_ds[ix]);
+        two_sum(sh, ch, s_dh[ix]);
+        two_sum(ss, cs, s_ds[ix]);
       }
       if (eq) {
         const u32 lo = (u32)__ffsll((long long)eq) - 1u;
@@ -543,7 +618,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_compact(
     const ah_hit* __restrict__ hits, const ah_result* __restrict__ nhits, u64 hcap,
     const PairTab* __restrict__ tabs, const u64* __restrict__ cf, const u64* __restrict__ cr,
     u64* __restrict__ kf, u32* __restrict__ pf, u32* __restrict__ xf, u64* __restrict__ kr,
-    u32* __restrict__ pr, u32* __restrict__ xr, u64* __restrict__ mtot) {
+    u32* __restrict__ pr, u32* __restrict__ xr, u32* __restrict__ pre_f, u32* __restrict__ pre_r,
+    u64* __restrict__ mtot) {
   __shared__ u64 lds4[4];
   const u64 n = pair_n(nhits, hcap);
   u64 chunk;
@@ -568,6 +644,10 @@ __global__ __launch_bounds__(kBlock) void k_pair_compact(
     u64 sf, sr;
     const u64 ef = block_exclusive_scan(k & 1u, lds4, sf);
     const u64 er = block_exclusive_scan(k >> 1, lds4, sr);
+    if (i < end) {  // minus sites of each list before hit i: a search hint
+      pre_f[i] = (u32)(bf + ef);
+      pre_r[i] = (u32)(br + er);
+    }
     const u64 key = ((u64)h.pair << 32) | h.genome;
     if (k == 1u) {
       const u64 j = bf + ef;
@@ -581,14 +661,41 @@ __global__ __launch_bounds__(kBlock) void k_pair_compact(
   }
 }
 
-// First index in [0, m) whose (key, pos) is >= (key0, pos0).
-__device__ __forceinline__ u64 lower(const u64* __restrict__ K, const u32* __restrict__ P, u64 m,
-                                     u64 key0, u64 pos0) {
-  u64 lo = 0, hi = m;
+// First index in [0, m) whose (key, pos) is >= (key0, pos0), found by
+// exponential search from a hint h (few probes when the answer is near h, as
+// it is for a hit's own minus sites).
+__device__ __forceinline__ u64 lower_from(const u64* __restrict__ K, const u32* __restrict__ P,
+                                          u64 m, u64 key0, u64 pos0, u64 h) {
+  auto less = [&](u64 x) { return K[x] < key0 || (K[x] == key0 && (u64)P[x] < pos0); };
+  if (h > m) h = m;
+  u64 lo, hi;
+  if (h < m && less(h)) {  // the answer lies in (h, m]
+    lo = h + 1;
+    hi = lo;
+    u64 step = 1;
+    while (hi < m && less(hi)) {
+      lo = hi + 1;
+      hi = lo + step;
+      step <<= 1;
+    }
+    if (hi > m) hi = m;
+  } else {  // the answer lies in [0, h]
+    hi = h;
+    lo = 0;
+    u64 step = 1;
+    while (hi > 0) {
+      const u64 p = hi >= step ? hi - step : 0;
+      if (less(p)) {
+        lo = p + 1;
+        break;
+      }
+      hi = p;
+      step <<= 1;
+    }
+  }
   while (lo < hi) {
     const u64 mid = (lo + hi) >> 1;
-    const bool less = K[mid] < key0 || (K[mid] == key0 && (u64)P[mid] < pos0);
-    if (less) lo = mid + 1; else hi = mid;
+    if (less(mid)) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
@@ -598,15 +705,16 @@ struct Range {
 };
 
 // Minus-site ranges for a + site at `pos` of (pair, genome) `key` whose
-// amplicon length b.pos + lb - pos lies in [min_len, max_len].
+// amplicon length b.pos + lb - pos lies in [min_len, max_len]; `hint`: the
+// list's sites before the + site.
 __device__ __forceinline__ Range minus_range(const u64* K, const u32* P, u64 m, u64 key, u64 pos,
-                                             u32 lb, const PairTab& t) {
+                                             u32 lb, const PairTab& t, u64 hint) {
   const long long lo = (long long)pos + (long long)t.min_len - (long long)lb;
   const long long hi = (long long)pos + (long long)t.max_len - (long long)lb;
   Range r{0, 0};
   if (hi < 0) return r;
-  r.beg = lower(K, P, m, key, lo < 0 ? 0 : (u64)lo);
-  r.end = lower(K, P, m, key, (u64)hi + 1);
+  r.beg = lower_from(K, P, m, key, lo < 0 ? 0 : (u64)lo, hint);
+  r.end = lower_from(K, P, m, key, (u64)hi + 1, r.beg);
   if (r.end < r.beg) r.end = r.beg;
   return r;
 }
@@ -639,8 +747,9 @@ __device__ __forceinline__ int group_of(const ah_hit* hits, u64 n, u64 i, const 
 __global__ __launch_bounds__(kBlock) void k_pair_count(
     const ah_hit* __restrict__ hits, const ah_result* __restrict__ nhits, u64 hcap,
     const PairTab* __restrict__ tabs, const u64* __restrict__ kf, const u32* __restrict__ pf,
-    const u64* __restrict__ kr, const u32* __restrict__ pr, const u64* __restrict__ mtot,
-    u32* __restrict__ cnt, u64* __restrict__ cc) {
+    const u64* __restrict__ kr, const u32* __restrict__ pr, const u32* __restrict__ pre_f,
+    const u32* __restrict__ pre_r, const u64* __restrict__ mtot, u32* __restrict__ cnt,
+    u64* __restrict__ cc) {
   __shared__ u64 lds4[4];
   const u64 n = pair_n(nhits, hcap);
   u64 chunk;
@@ -655,8 +764,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_count(
     for (int q = 0; q < ng; ++q) {
       const PairTab t = tabs[a[q].pair];
       const u64 key = ((u64)a[q].pair << 32) | a[q].genome;
-      const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t);
-      const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t);
+      const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t, pre_f[i]);
+      const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t, pre_r[i]);
       c += (rf.end - rf.beg) + (rr.end - rr.beg);
     }
     cnt[i] = (u32)c;
@@ -670,8 +779,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
     const ah_hit* __restrict__ hits, const ah_result* __restrict__ nhits, u64 hcap,
     const PairTab* __restrict__ tabs, const u64* __restrict__ kf, const u32* __restrict__ pf,
     const u32* __restrict__ xf, const u64* __restrict__ kr, const u32* __restrict__ pr,
-    const u32* __restrict__ xr, const u64* __restrict__ mtot, const u32* __restrict__ cnt,
-    const u64* __restrict__ cc, ah_amplicon* __restrict__ amp, u64 cap, ah_result* __restrict__ res) {
+    const u32* __restrict__ xr, const u32* __restrict__ pre_f, const u32* __restrict__ pre_r,
+    const u64* __restrict__ mtot, const u32* __restrict__ cnt, const u64* __restrict__ cc,
+    ah_amplicon* __restrict__ amp, u64 cap, ah_result* __restrict__ res) {
   __shared__ u64 lds4[4];
   const u64 n = pair_n(nhits, hcap);
   u64 chunk;
@@ -708,8 +818,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
       const PairTab t = tabs[a[q].pair];
       const u64 key = ((u64)a[q].pair << 32) | a[q].genome;
       const u32 ap = a[q].strand_primer & 1u;
-      const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t);
-      const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t);
+      const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t, pre_f[i]);
+      const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t, pre_r[i]);
       r[nl] = rf; lb[nl] = t.lf; P[nl] = pf; X[nl] = xf; plus_idx[nl] = (u32)(i + q);
       orient[nl] = ap ? (u32)AH_RF : (u32)AH_FF; ++nl;
       r[nl] = rr; lb[nl] = t.lr; P[nl] = pr; X[nl] = xr; plus_idx[nl] = (u32)(i + q);
@@ -858,22 +968,30 @@ hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, const ui
   return hipGetLastError();
 }
 
+template <int D>
+void sort_passes(const ah_hit* staged, ah_hit* out, const u64* n_dev, KeyBits kb,
+                 const SortBuffers& sb, hipStream_t st) {
+  const int bits = kb.total();
+  k_keygen<D><<<kSortGrid, kBlock, 0, st>>>(staged, n_dev, kb, (u64*)sb.keys[0], sb.idx[0], sb.hist);
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += D) {
+    if (shift > 0)
+      k_sort_hist<D><<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], n_dev, shift, sb.hist);
+    const bool last = shift + D >= bits;
+    k_sort_scatter<D><<<kSortGrid, kBlock, 0, st>>>(
+        (const u64*)sb.keys[cur], sb.idx[cur], (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1], n_dev, shift,
+        sb.hist, staged, last ? out : nullptr);
+    cur ^= 1;
+  }
+}
+
 hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev, KeyBits kb,
                             const SortBuffers& sb, hipStream_t st) {
   const int bits = kb.total();
-  k_keygen<<<kSortGrid, kBlock, 0, st>>>(staged, (const u64*)n_dev, kb, (u64*)sb.keys[0], sb.idx[0],
-                                         sb.hist);
-  int cur = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
-    if (shift > 0)
-      k_sort_hist<<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], (const u64*)n_dev, shift,
-                                               sb.hist);
-    const bool last = shift + 8 >= bits;
-    k_sort_scatter<<<kSortGrid, kBlock, 0, st>>>(
-        (const u64*)sb.keys[cur], sb.idx[cur], (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1],
-        (const u64*)n_dev, shift, sb.hist, staged, last ? out : nullptr);
-    cur ^= 1;
-  }
+  if ((bits + 8) / 9 < (bits + 7) / 8)  // 9-bit digits save a pass
+    sort_passes<9>(staged, out, (const u64*)n_dev, kb, sb, st);
+  else
+    sort_passes<8>(staged, out, (const u64*)n_dev, kb, sb, st);
   return hipGetLastError();
 }
 
@@ -891,14 +1009,15 @@ hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_
   k_pair_compact<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.cf,
                                               (const u64*)pb.cr, (u64*)pb.mkey_f, pb.mpos_f,
                                               pb.midx_f, (u64*)pb.mkey_r, pb.mpos_r, pb.midx_r,
-                                              (u64*)pb.mtot);
+                                              pb.pre_f, pb.pre_r, (u64*)pb.mtot);
   k_pair_count<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.mkey_f,
                                             pb.mpos_f, (const u64*)pb.mkey_r, pb.mpos_r,
-                                            (const u64*)pb.mtot, pb.cnt, (u64*)pb.cc);
+                                            pb.pre_f, pb.pre_r, (const u64*)pb.mtot, pb.cnt,
+                                            (u64*)pb.cc);
   k_pair_write<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.mkey_f,
                                             pb.mpos_f, pb.midx_f, (const u64*)pb.mkey_r, pb.mpos_r,
-                                            pb.midx_r, (const u64*)pb.mtot, pb.cnt,
-                                            (const u64*)pb.cc, amp, cap, res);
+                                            pb.midx_r, pb.pre_f, pb.pre_r, (const u64*)pb.mtot,
+                                            pb.cnt, (const u64*)pb.cc, amp, cap, res);
   return hipGetLastError();
 }
 

@@ -43,6 +43,11 @@ typedef unsigned long long u64;
 #define AH_BLOCK 256
 #endif
 #define AH_TILE (AH_BLOCK * AH_U)
+// Slices per group of the emit pass's offsets (group sums kept by the verify
+// pass; the filter zeroes them).  Each group's sum has a 256-byte line of its
+// own: atomics to one line serialise.
+#define AH_SLICE_GROUP 64
+#define AH_GROUP_STRIDE 32
 
 // Must match ah_result in ah.h.
 struct AhResult {
@@ -218,7 +223,7 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     const u64* __restrict__ word_off, const u32* __restrict__ len,
     const u64* __restrict__ tile_prefix, u32 n_genomes, uint4* __restrict__ cand_out,
     u32 slice, u32* __restrict__ slice_count, u32* __restrict__ slice_total,
-    u64* __restrict__ slice_win) {
+    u64* __restrict__ slice_win, u64* __restrict__ group_sites) {
   __shared__ uint4 tile[AH_STAGE_PAIRS];
   const u64 n_tiles = tile_prefix[n_genomes];
   const AhCands k{cand_out, slice};
@@ -226,6 +231,8 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     ah_n_cand = 0;
     ah_n_lost = 0;
   }
+  if (blockIdx.x % AH_SLICE_GROUP == 0 && threadIdx.x == 0)
+    group_sites[(blockIdx.x / AH_SLICE_GROUP) * AH_GROUP_STRIDE] = 0;  // summed by the verify pass
   __syncthreads();
   u32 lo = 0;
   for (u64 T = blockIdx.x; T < n_tiles; T += gridDim.x) {
@@ -249,7 +256,8 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
     const uint2* __restrict__ words, const u32* __restrict__ nmask,
     const u64* __restrict__ word_off, const u32* __restrict__ len,
     const uint4* __restrict__ cands, u32 slice, const u32* __restrict__ slice_count,
-    u32* __restrict__ cand_sites, u64* __restrict__ slice_sites, u64* __restrict__ slice_win) {
+    u32* __restrict__ cand_sites, u64* __restrict__ slice_sites, u64* __restrict__ group_sites,
+    u64* __restrict__ slice_win) {
   // Sites of each candidate of this workgroup's slice, their sum, and the
   // candidates' windows (added to those of the candidates a full slice
   // dropped).
@@ -276,6 +284,7 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
   __syncthreads();
   if (threadIdx.x == 0) {
     slice_sites[blockIdx.x] = s_sites;
+    if (s_sites) atomicAdd(&group_sites[(blockIdx.x / AH_SLICE_GROUP) * AH_GROUP_STRIDE], s_sites);
     slice_win[blockIdx.x] += s_win;
   }
 }
@@ -308,18 +317,22 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
     const u64* __restrict__ word_off, const u32* __restrict__ len,
     const uint4* __restrict__ cands, u32 slice, const u32* __restrict__ slice_count,
     const u32* __restrict__ slice_total, const u64* __restrict__ slice_win,
-    const u32* __restrict__ cand_sites, const u64* __restrict__ slice_sites, AhHitRec* __restrict__ out,
-    u64 cap, AhResult* __restrict__ res, u64* __restrict__ n_out, u64* __restrict__ cand_stat) {
+    const u32* __restrict__ cand_sites, const u64* __restrict__ slice_sites,
+    const u64* __restrict__ group_sites, AhHitRec* __restrict__ out, u64 cap,
+    AhResult* __restrict__ res, u64* __restrict__ n_out, u64* __restrict__ cand_stat) {
   __shared__ u64 tmp[AH_BLOCK / 64];
   const u32 G = gridDim.x;
-  // this slice's first record: the sites of the earlier slices
+  // this slice's first record: the sites of the earlier groups of slices,
+  // then of the earlier slices of its own group
+  const u32 ng = (G + AH_SLICE_GROUP - 1) / AH_SLICE_GROUP, my = blockIdx.x / AH_SLICE_GROUP;
   u64 mine_before = 0, mine_all = 0;
-#pragma unroll 4
-  for (u32 w = threadIdx.x; w < G; w += AH_BLOCK) {
-    const u64 v = slice_sites[w];
+  for (u32 q = threadIdx.x; q < ng; q += AH_BLOCK) {
+    const u64 v = group_sites[q * AH_GROUP_STRIDE];
     mine_all += v;
-    mine_before += w < blockIdx.x ? v : 0ull;
+    mine_before += q < my ? v : 0ull;
   }
+  for (u32 w = my * AH_SLICE_GROUP + threadIdx.x; w < blockIdx.x; w += AH_BLOCK)
+    mine_before += slice_sites[w];
   u64 slot, found;
   ah_block_scan(mine_before, tmp, &slot);
   ah_block_scan(mine_all, tmp, &found);
