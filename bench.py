@@ -148,6 +148,7 @@ def gpu_run(name: str, steps: int, warmup: int):
         n, ms = L.ah_profile_query(k)
         kern[k] = ms / max(n, 1)
     traffic = None
+    valu = None
     rec = os.path.join(ROOT, "profiles", f"ah_scan_kernel__{name}-{coll.n}.json")
     if os.path.exists(rec):
         import hashlib
@@ -156,6 +157,7 @@ def gpu_run(name: str, steps: int, warmup: int):
         sha = hashlib.sha256(L.ah_scan_program_source([pr], False).encode()).hexdigest()
         if d.get("program_sha256") == sha:  # counters were taken on this exact kernel
             traffic = d["traffic_bytes_per_dispatch"]
+            valu = d.get("sq_insts_valu_per_dispatch")
     hits = path.hits_numpy(buf)
     cands = L.ah_scan_candidate_stats(buf.scan_work, coll.n, buf.hit_cap)
     tm_ok = bool(np.all(np.isfinite(hits["tm"]))) if hits.size else True
@@ -172,9 +174,13 @@ def gpu_run(name: str, steps: int, warmup: int):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "ah_scan_kernel", "algorithmic_bytes": scan_bytes,
-                     "alu_view": {k: v for k, v in alu_roofline([pr], bp, kern["scan"],
-                                                                scan_bytes).items()
-                                  if k in ("achieved", "peak", "unit", "frac")}},
+                     # the filter's VALU issue rate: the profiled instruction count of
+                     # this exact program (64 lanes each) over the live kernel time
+                     "valu_issue": None if valu is None else {
+                         "achieved": valu * 64 / (kern["scan"] * 1e-3) / 1e12,
+                         "peak": ALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                         "frac": valu * 64 / (kern["scan"] * 1e-3) / 1e12 / ALU_PEAK_TOPS,
+                         "valu_insts_per_dispatch": valu}},
         "pair": {"fwd": pr.fwd, "rev": pr.rev, "k": pr.k, "clamp": pr.clamp,
                  "window": [pr.min_len, pr.max_len]},
         "genomes": coll.n,
