@@ -460,14 +460,29 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
     // ow: the base an oligo must carry at each primer position to pair with
     // the template (2 bits per position, primer 5'->3'); nb: positions
     // opposite a non-ACGT template base, which pair with nothing.
-    u64 ow = 0, nb = 0;
-    for (u32 j = 0; j < L; ++j) {
-      const uint2 wv = words[w0 + j];
-      const u32 c = (((wv.x >> b) & 1u) << 1) | ((wv.y >> b) & 1u);
-      const u32 isn = nmask ? (nmask[w0 + j] >> b) & 1u : 0u;
+    // All 32 words a primer can span are loaded at once, unconditionally:
+    // the window word is t < S and every genome carries 31 halo words, so
+    // words t .. t + 31 lie inside its allocation (and its mask's).
+    uint2 wv[32];
+#pragma unroll
+    for (u32 j = 0; j < 32; ++j) wv[j] = words[w0 + j];
+    u64 ow = 0;
+#pragma unroll
+    for (u32 j = 0; j < 32; ++j) {
+      const u32 c = (((wv[j].x >> b) & 1u) << 1) | ((wv[j].y >> b) & 1u);
       const u32 jj = strand ? L - 1u - j : j;
-      ow |= (u64)(strand ? 3u - c : c) << (2u * jj);
-      nb |= (u64)isn << (2u * jj);
+      if (j < L) ow |= (u64)(strand ? 3u - c : c) << (2u * jj);
+    }
+    u64 nb = 0;
+    if (nmask) {
+      u32 nmv[32];
+#pragma unroll
+      for (u32 j = 0; j < 32; ++j) nmv[j] = nmask[w0 + j];
+#pragma unroll
+      for (u32 j = 0; j < 32; ++j) {
+        const u32 jj = strand ? L - 1u - j : j;
+        if (j < L) nb |= (u64)((nmv[j] >> b) & 1u) << (2u * jj);
+      }
     }
     const u64 lanes = T->lanes & ~nb;
     const u64 clampm = T->clampm;
