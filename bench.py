@@ -292,6 +292,72 @@ def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 6
     }
 
 
+def gpu_decoy(steps: int, warmup: int):
+    """Decoy estimate (the analysis on the genomes reversed) in the same pass
+    as the real pair: [pair, decoy of pair] in one call, against the pair
+    alone and against two separate passes."""
+    import dataclasses
+
+    import torch
+
+    from paper_2509_13300_amd import _lib as L
+    from paper_2509_13300_amd import path
+    from synth import gpu
+
+    p, desc = workload("collection")
+    dev = torch.device("cuda:0")
+    ascii, off = gpu.fill_cuda(p, dev)
+    coll, _ = path.pack(ascii, off, p.lengths)
+    torch.cuda.synchronize()
+    del ascii
+    torch.cuda.empty_cache()
+    pr = p.pairs[0]
+    dec = dataclasses.replace(pr, decoy=True)
+    bp = coll.total_bp
+
+    def timed(pairs):
+        buf = path.alloc(coll, pairs, 1 << 22, 1 << 22, dev)
+        for _ in range(max(1, warmup)):
+            path.run(coll, pairs, buf)
+        torch.cuda.synchronize()
+        L.ah_profile_reset()
+        L.ah_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            path.run(coll, pairs, buf)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        L.ah_profile_enable(False)
+        kern = {k: L.ah_profile_query(k)[1] / max(L.ah_profile_query(k)[0], 1)
+                for k in ("scan", "verify", "sort", "tm", "pair")}
+        rh, ra = path.result(buf.hit_res), path.result(buf.amp_res)
+        assert rh["status"] == 0 and ra["status"] == 0, (rh, ra)
+        return ms, kern, path.hits_numpy(buf), path.amps_numpy(buf)
+
+    ms_real, k_real, h_real, a_real = timed([pr])
+    ms_dec, k_dec, h_dec, a_dec = timed([dec])
+    ms_both, k_both, h_both, a_both = timed([pr, dec])
+    n_real = int((a_both["pair"] == 0).sum())
+    n_dec = int((a_both["pair"] == 1).sum())
+    assert n_real == a_real.size and n_dec == a_dec.size
+    return {
+        "desc": desc.replace("collection:", "decoy: collection") +
+        "; the pair and its decoy (every genome reversed) in one pass",
+        "bp": bp, "genomes": coll.n, "value": bp / (ms_both * 1e-3) / 1e9, "ms_per_step": ms_both,
+        "real_only": {"ms_per_step": ms_real, "kernel_ms": k_real},
+        "two_passes_ms": ms_real + ms_dec,
+        "one_pass": {"ms_per_step": ms_both, "kernel_ms": k_both},
+        "time_vs_real_only": ms_both / ms_real,
+        "amplicons": {"real": n_real, "decoy": n_dec},
+        "sites": {"real": int((h_both["pair"] == 0).sum()), "decoy": int((h_both["pair"] == 1).sum())},
+        "decoy_ratio": n_dec / max(n_real, 1),
+        "roofline_scan": {"bound": "hbm", "achieved": SCAN_BYTES_PER_BP * bp /
+                          (k_both["scan"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": SCAN_BYTES_PER_BP * bp / (k_both["scan"] * 1e-3) / 1e9 /
+                          HBM_PEAK_GBS, "traffic": None, "kernel": "ah_scan_kernel"},
+    }
+
+
 PCIE_PEAK_GBS = 64.0  # PCIe 5.0 x16, one direction, nominal
 
 
@@ -521,11 +587,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="collection", choices=["collection", "plain"])
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "stream", "serve"],
+    ap.add_argument("--form", default="plain",
+                    choices=["plain", "batched", "stream", "serve", "decoy"],
                     help="plain: one pair per query (the headline); batched: 64 pairs in one "
                          "pass vs one by one; stream: 10,000 genomes copied host -> HBM in "
                          "packed chunks during the query; serve: Poisson jobs over a resident "
-                         "100,000-genome collection")
+                         "100,000-genome collection; decoy: the pair and its decoy estimate "
+                         "(genomes reversed) in one pass")
     ap.add_argument("--jobs", type=int, default=120, help="serve: number of jobs")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: arrivals per second")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -557,6 +625,23 @@ def main():
                        "amplicons": r["amplicons"], "kernel_ms": r["kernel_ms"],
                        "tuning": r["tuning"]},
             "roofline": r["roofline"], "cpu_baseline": None}))
+        return
+    if args.form == "decoy":
+        r = gpu_decoy(args.steps, args.warmup)
+        print(f"decoy: {r['ms_per_step']:.3f} ms per pass with the decoy vs "
+              f"{r['real_only']['ms_per_step']:.3f} alone ({r['time_vs_real_only']:.2f}x; two "
+              f"passes {r['two_passes_ms']:.3f} ms); amplicons {r['amplicons']}, ratio "
+              f"{r['decoy_ratio']:.4f}", file=sys.stderr, flush=True)
+        print(json.dumps({
+            "metric": METRIC, "value": r["value"], "unit": "Gbp/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+            "data": "synthetic",
+            "config": {"workload": r["desc"], "form": "decoy", "genomes": r["genomes"],
+                       "total_bp": r["bp"], **{k: r[k] for k in (
+                           "real_only", "one_pass", "two_passes_ms", "time_vs_real_only",
+                           "amplicons", "sites", "decoy_ratio")}},
+            "roofline": r["roofline_scan"], "cpu_baseline": None}))
         return
     if args.form == "serve":
         r = gpu_serve(args.jobs, args.rate)

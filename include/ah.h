@@ -109,7 +109,23 @@ typedef struct ah_primer_pair {
   const char* rev;    /* IUPAC codes 5'->3'                                  */
   uint32_t k;         /* maximum mismatches per site, <= AH_MAX_K            */
   uint32_t clamp;     /* 3'-terminal primer bases that must match (0 = none) */
+  uint32_t flags;     /* 0 or AH_PAIR_DECOY                                   */
 } ah_primer_pair;
+
+/* Decoy pair (Section 2.1, "Amplicon analysis": off-target amplification
+ * estimated from decoys made by reversing the genome sequences).  A pair with
+ * this flag stands for the same primers run on every genome reversed (not
+ * reverse-complemented), scanned in the same pass as the other pairs, over
+ * the genomes as given.  Scanning reverse(G) for a primer P is scanning G
+ * for the position-wise complement of P as an ordinary primer (its 3' clamp
+ * stays at the window end the clamp rule expects), so a decoy pair's sites
+ * and amplicons are reported in G's coordinates: a decoy-frame site at pos
+ * p on strand s of a genome of n bases is reported at pos n - p - L on
+ * strand 1 - s; a decoy-frame amplicon [a, b) is reported as [n - b, n - a)
+ * with FR and RF exchanged (FF and RR stay).  Its melting temperatures are
+ * those of the given primers against the reversed genome.  Counts, lengths,
+ * mismatches and Tm are the decoy run's. */
+#define AH_PAIR_DECOY 1u
 
 /* One binding site.  pos is the 0-based leftmost top-strand coordinate of the
  * window for both strands.  strand_primer: bit 1 = strand (0 = the primer

@@ -40,9 +40,12 @@ class ah_genomes(ctypes.Structure):
                 ("n", ctypes.c_uint32), ("max_len", ctypes.c_uint32)]
 
 
+AH_PAIR_DECOY = 1
+
+
 class ah_primer_pair(ctypes.Structure):
     _fields_ = [("fwd", ctypes.c_char_p), ("rev", ctypes.c_char_p),
-                ("k", ctypes.c_uint32), ("clamp", ctypes.c_uint32)]
+                ("k", ctypes.c_uint32), ("clamp", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class ah_result(ctypes.Structure):
@@ -230,15 +233,24 @@ def _stream(stream) -> Optional[int]:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def _pair_flags(p) -> int:
+    return AH_PAIR_DECOY if getattr(p, "decoy", False) else 0
+
+
 def primer_pairs(pairs: Sequence) -> ctypes.Array:
-    """Marshal objects with fwd, rev, k, clamp attributes (or 4-tuples)."""
+    """Marshal objects with fwd, rev, k, clamp (and optionally decoy)
+    attributes, or (fwd, rev, k, clamp[, flags]) tuples."""
     arr = (ah_primer_pair * len(pairs))()
     keep = []
     for i, p in enumerate(pairs):
-        fwd, rev, k, clamp = (p.fwd, p.rev, p.k, p.clamp) if hasattr(p, "fwd") else p
+        if hasattr(p, "fwd"):
+            fwd, rev, k, clamp, flags = p.fwd, p.rev, p.k, p.clamp, _pair_flags(p)
+        else:
+            fwd, rev, k, clamp = p[:4]
+            flags = p[4] if len(p) > 4 else 0
         f, r = fwd.encode(), rev.encode()
         keep += [f, r]
-        arr[i] = ah_primer_pair(f, r, int(k), int(clamp))
+        arr[i] = ah_primer_pair(f, r, int(k), int(clamp), int(flags))
     arr._keep = keep
     return arr
 
@@ -479,7 +491,7 @@ def ah_server_submit(server: int, pair, genomes=None, tm: Optional[ah_tm_params]
                      filter_tm: bool = False, min_tm: float = 50.0) -> int:
     job = ah_job()
     f, r = pair.fwd.encode(), pair.rev.encode()
-    job.pair = ah_primer_pair(f, r, int(pair.k), int(pair.clamp))
+    job.pair = ah_primer_pair(f, r, int(pair.k), int(pair.clamp), _pair_flags(pair))
     job.window = ah_window(int(pair.min_len), int(pair.max_len), 1 if filter_tm else 0,
                            float(min_tm))
     job.tm = tm if tm is not None else tm_params()

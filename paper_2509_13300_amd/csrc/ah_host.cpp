@@ -109,7 +109,7 @@ struct Pattern {
 
 struct PairSet {
   std::vector<Primer> fwd, rev;
-  std::vector<uint32_t> k, clamp;
+  std::vector<uint32_t> k, clamp, flags;
 };
 
 ah_status compile_pairs(const ah_primer_pair* pairs, uint32_t n_pairs, PairSet& ps) {
@@ -119,6 +119,7 @@ ah_status compile_pairs(const ah_primer_pair* pairs, uint32_t n_pairs, PairSet& 
   ps.rev.resize(n_pairs);
   ps.k.resize(n_pairs);
   ps.clamp.resize(n_pairs);
+  ps.flags.resize(n_pairs);
   for (uint32_t q = 0; q < n_pairs; ++q) {
     ah_status s = parse_primer(pairs[q].fwd, "fwd", q, ps.fwd[q]);
     if (s) return s;
@@ -128,8 +129,11 @@ ah_status compile_pairs(const ah_primer_pair* pairs, uint32_t n_pairs, PairSet& 
     const int lmin = ps.fwd[q].L < ps.rev[q].L ? ps.fwd[q].L : ps.rev[q].L;
     if ((int)pairs[q].clamp > lmin)
       return fail(AH_ERR_LIMIT, "pair %u: clamp %u longer than a primer", q, pairs[q].clamp);
+    if (pairs[q].flags & ~AH_PAIR_DECOY)
+      return fail(AH_ERR_INVALID_ARG, "pair %u: unknown flags 0x%x", q, pairs[q].flags);
     ps.k[q] = pairs[q].k;
     ps.clamp[q] = pairs[q].clamp;
+    ps.flags[q] = pairs[q].flags;
   }
   return AH_OK;
 }
@@ -138,7 +142,11 @@ std::vector<Pattern> patterns_of(const PairSet& ps) {
   std::vector<Pattern> out;
   for (uint32_t q = 0; q < ps.fwd.size(); ++q) {
     for (uint32_t primer = 0; primer < 2; ++primer) {
-      const Primer& p = primer ? ps.rev[q] : ps.fwd[q];
+      // a decoy pair scans the position-wise complement of each primer
+      // (reverse(G) read for P is G read for that primer; see ah.h)
+      Primer p = primer ? ps.rev[q] : ps.fwd[q];
+      if (ps.flags[q] & AH_PAIR_DECOY)
+        for (int j = 0; j < p.L; ++j) p.mask[j] = comp_mask(p.mask[j]);
       const int c = (int)ps.clamp[q];
       for (uint32_t strand = 0; strand < 2; ++strand) {
         Pattern t{};
@@ -941,7 +949,8 @@ std::string set_key(const ah_primer_pair* pairs, uint32_t n_pairs) {
     k += pairs[q].fwd;
     k += '|';
     k += pairs[q].rev;
-    k += '|' + std::to_string(pairs[q].k) + '|' + std::to_string(pairs[q].clamp) + ';';
+    k += '|' + std::to_string(pairs[q].k) + '|' + std::to_string(pairs[q].clamp) + '|' +
+         std::to_string(pairs[q].flags) + ';';
   }
   return k;
 }
@@ -1420,6 +1429,7 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
         return fail(AH_ERR_LIMIT, "pair %u: primer degeneracy %llu exceeds 2^20 for Tm", q,
                     (unsigned long long)deg);
       t.deg = deg;
+      t.decoy = (ps.flags[q] & AH_PAIR_DECOY) ? 1u : 0u;
       const double salt = p->saltcorr == 5 ? 0.368 * (pr.L - 1) * std::log(na_eq / 1000.0) : 0.0;
       t.KL = salt + R * std::log(C) + (p->selfcomp ? -1.4 : 0.0);
       tabs[2 * q + primer] = t;

@@ -26,7 +26,8 @@ struct PrimerTab {
   uint64_t stackm;    // positions 0..L-2 (left base of each stack)
   uint64_t deg;       // oligos in the expansion
   double KL;          // FP64: salt entropy + R ln C (+ symmetry), cal/(K mol)
-  uint32_t L, k, nd, pad;
+  uint32_t L, k, nd;
+  uint32_t decoy;     // 1: the site is the primer against the reversed genome
   uint8_t dpos[32];   // degenerate positions, 5'->3'
   uint8_t nmem[32];   // number of members of each degenerate position
   uint8_t mem[32];    // members, 2 bits each, in A<C<G<T order

@@ -459,7 +459,12 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
     const u64 w0 = word_off[h.genome] + (h.pos - (u64)b * S);
     // ow: the base an oligo must carry at each primer position to pair with
     // the template (2 bits per position, primer 5'->3'); nb: positions
-    // opposite a non-ACGT template base, which pair with nothing.
+    // opposite a non-ACGT template base, which pair with nothing.  The
+    // oligo's position runs against the window on the - strand; it carries
+    // the complement of the window's base on the - strand of a site, and on
+    // the + strand of a decoy site (the decoy's + pattern is the primer's
+    // complement: the primer against the reversed genome's - strand).
+    const u32 cflip = strand ^ T->decoy;
     // All 32 words a primer can span are loaded at once, unconditionally:
     // the window word is t < S and every genome carries 31 halo words, so
     // words t .. t + 31 lie inside its allocation (and its mask's).
@@ -471,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
     for (u32 j = 0; j < 32; ++j) {
       const u32 c = (((wv[j].x >> b) & 1u) << 1) | ((wv[j].y >> b) & 1u);
       const u32 jj = strand ? L - 1u - j : j;
-      if (j < L) ow |= (u64)(strand ? 3u - c : c) << (2u * jj);
+      if (j < L) ow |= (u64)(cflip ? 3u - c : c) << (2u * jj);
     }
     u64 nb = 0;
     if (nmask) {

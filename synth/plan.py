@@ -63,6 +63,7 @@ class PairSpec:
     clamp: int = 0
     min_len: int = 200
     max_len: int = 2000
+    decoy: bool = False  # run on the genomes reversed (the decoy estimate)
 
 
 @dataclasses.dataclass

@@ -4,6 +4,7 @@ import sys
 
 import numpy as np
 
+from oracle import decoy as odecoy
 from oracle import iupac
 from oracle import pair as opair
 from oracle import scan as oscan
@@ -33,20 +34,31 @@ def run_gpu(p, pairs, dev, hit_cap=1 << 16, amp_cap=1 << 16, with_nmask=None, tm
 
 
 def run_oracle(p, pairs, tmp=None, filter_tm=False, min_tm=50.0):
+    """Hits (with Tm) and amplicons of every pair, in canonical order; a decoy
+    pair's records are the oracle's run on the reversed genomes, stated in
+    the genomes' own coordinates."""
     seqs = [fill.genome_bytes(p, g) for g in range(p.n)]
-    h = oscan.scan_collection(seqs, pairs)
-    h = otm.fill_tm(h, seqs, pairs, tmp if tmp is not None else otm.TmParams())
-    a = []
+    tmp = tmp if tmp is not None else otm.TmParams()
+    hs, amps = [], []
+    at = 0
     for q, pr in enumerate(pairs):
-        sel = h[h["pair"] == q]
-        base = np.flatnonzero(h["pair"] == q)
-        aq = opair.call_amplicons(sel, [pr], filter_tm, min_tm)
-        aq["pair"] = q
-        aq["plus_hit"] = base[aq["plus_hit"]]
-        aq["minus_hit"] = base[aq["minus_hit"]]
-        a.append(aq)
-    amps = np.concatenate(a) if a else np.zeros(0, opair.AMP_DTYPE)
-    return h, amps
+        if getattr(pr, "decoy", False):
+            h, a = odecoy.run(seqs, [pr], tmp, filter_tm, min_tm)
+            h, a = odecoy.to_forward_frame(h, a, p.lengths, [pr])
+        else:
+            h = oscan.scan_collection(seqs, [pr])
+            h = otm.fill_tm(h, seqs, [pr], tmp)
+            a = opair.call_amplicons(h, [pr], filter_tm, min_tm)
+        h["pair"] = q
+        a["pair"] = q
+        a["plus_hit"] += at
+        a["minus_hit"] += at
+        at += h.size
+        hs.append(h)
+        amps.append(a)
+    h = np.concatenate(hs) if hs else np.zeros(0, oscan.HIT_DTYPE)
+    a = np.concatenate(amps) if amps else np.zeros(0, opair.AMP_DTYPE)
+    return h, a
 
 
 def hit_tuples_gpu(h):

@@ -142,3 +142,20 @@ def test_workspace_of_a_size_holds_the_list_it_was_sized_for(n_genomes, capacity
         assert L.ah_scan_candidate_capacity(recommended, n_genomes, capacity, off) >= need
     # and a little less than the minimum holds fewer (the size is tight)
     assert L.ah_scan_candidate_capacity(minimum - 600, n_genomes, capacity) < need
+
+
+def test_decoy_pair_scans_the_complement_primers():
+    """A decoy pair's scan program is that of the position-wise complement
+    primers as an ordinary pair (reverse(G) read for P is G read for the
+    complement of P); unknown flags are rejected."""
+    from oracle import iupac
+
+    fwd, rev = "GCMCCTGGYAAACTGTTGG", "AAAGACGTATGACGATCWNA"
+    comp = lambda s: "".join(iupac.complement_code(c) for c in s)  # noqa: E731
+    for k, clamp in ((2, 0), (3, 4)):
+        dec = L.ah_scan_program_source([(fwd, rev, k, clamp, L.AH_PAIR_DECOY)])
+        plain = L.ah_scan_program_source([(comp(fwd), comp(rev), k, clamp)])
+        assert dec == plain
+        assert dec != L.ah_scan_program_source([(fwd, rev, k, clamp)])
+    assert L.ah_validate_pairs([(fwd, rev, 2, 0, 2)]) == L.AH_ERR_INVALID_ARG
+    assert L.ah_validate_pairs([(fwd, rev, 2, 0, L.AH_PAIR_DECOY)]) == L.AH_OK
