@@ -340,6 +340,21 @@ def gpu_decoy(steps: int, warmup: int):
     n_real = int((a_both["pair"] == 0).sum())
     n_dec = int((a_both["pair"] == 1).sum())
     assert n_real == a_real.size and n_dec == a_dec.size
+    # the long-amplicon pair of the streaming workload (192 + 768 oligos, k 3)
+    # on the same genomes: random binding is common enough for decoy amplicons
+    from synth import plan as splan
+
+    lp = splan.stream(10).pairs[0]
+    ms_l, _, _, a_l = timed([lp])
+    ms_lb, _, h_lb, a_lb = timed([lp, dataclasses.replace(lp, decoy=True)])
+    long_pair = {"fwd": lp.fwd, "rev": lp.rev, "k": lp.k, "window": [lp.min_len, lp.max_len],
+                 "real_only_ms": ms_l, "one_pass_ms": ms_lb, "time_vs_real_only": ms_lb / ms_l,
+                 "amplicons": {"real": int((a_lb["pair"] == 0).sum()),
+                               "decoy": int((a_lb["pair"] == 1).sum())},
+                 "sites": {"real": int((h_lb["pair"] == 0).sum()),
+                           "decoy": int((h_lb["pair"] == 1).sum())}}
+    long_pair["decoy_ratio"] = long_pair["amplicons"]["decoy"] / max(long_pair["amplicons"]["real"], 1)
+    assert long_pair["amplicons"]["real"] == a_l.size
     return {
         "desc": desc.replace("collection:", "decoy: collection") +
         "; the pair and its decoy (every genome reversed) in one pass",
@@ -351,11 +366,72 @@ def gpu_decoy(steps: int, warmup: int):
         "amplicons": {"real": n_real, "decoy": n_dec},
         "sites": {"real": int((h_both["pair"] == 0).sum()), "decoy": int((h_both["pair"] == 1).sum())},
         "decoy_ratio": n_dec / max(n_real, 1),
+        "long_amplicon_pair": long_pair,
         "roofline_scan": {"bound": "hbm", "achieved": SCAN_BYTES_PER_BP * bp /
                           (k_both["scan"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": SCAN_BYTES_PER_BP * bp / (k_both["scan"] * 1e-3) / 1e9 /
                           HBM_PEAK_GBS, "traffic": None, "kernel": "ah_scan_kernel"},
     }
+
+
+def gpu_fasta(steps: int, warmup: int):
+    """FASTA records, sequence hashes and amplitypes of the amplicons of one
+    query (after scan, Tm and pairing), for the V4-like pair and the
+    long-amplicon pair on the 1000-genome collection."""
+    import numpy as np
+    import torch
+
+    from paper_2509_13300_amd import _lib as L
+    from paper_2509_13300_amd import path
+    from synth import gpu
+    from synth import plan as splan
+
+    p, desc = workload("collection")
+    dev = torch.device("cuda:0")
+    ascii, off = gpu.fill_cuda(p, dev)
+    coll, _ = path.pack(ascii, off, p.lengths)
+    torch.cuda.synchronize()
+    del ascii
+    torch.cuda.empty_cache()
+    out = {}
+    for name, pr in (("v4_like", p.pairs[0]), ("long_amplicon", splan.stream(10).pairs[0])):
+        buf = path.alloc(coll, [pr], 1 << 22, 1 << 22, dev)
+        path.run(coll, [pr], buf)
+        torch.cuda.synchronize()
+        n_amp = path.result(buf.amp_res)["count"]
+        fb = path.fasta_alloc(coll, 1, buf.amp_cap, 16, dev)
+        path.fasta(coll, 1, buf, fb)  # sizes the text
+        torch.cuda.synchronize()
+        need = path.result(fb.text_res)["required"]
+        fb = path.fasta_alloc(coll, 1, buf.amp_cap, need, dev)
+        for _ in range(max(1, warmup)):
+            path.fasta(coll, 1, buf, fb)
+        torch.cuda.synchronize()
+        L.ah_profile_reset()
+        L.ah_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            path.fasta(coll, 1, buf, fb)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        L.ah_profile_enable(False)
+        nk, kms = L.ah_profile_query("fasta")
+        assert path.result(fb.text_res)["status"] == 0
+        amps = path.amps_numpy(buf)
+        bases = int((amps["end"].astype(np.int64) - amps["start"]).sum()) if amps.size else 0
+        kernel_ms = kms / max(nk, 1)
+        # bytes: the text written, the amplicon records read (24 B each) and
+        # the packed words of the bases decoded (0.25 B per base)
+        algo = need + 24 * n_amp + bases / 4
+        out[name] = {"amplicons": n_amp, "text_bytes": need, "bases": bases, "ms": ms,
+                     "kernel_ms": kernel_ms, "text_gbps": need / (kernel_ms * 1e-3) / 1e9,
+                     "hbm_frac": algo / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "distinct_amplitypes": int(np.unique(
+                         fb.amplitype.cpu().numpy().view(np.uint64)[
+                             fb.amplitype_n.cpu().numpy() > 0]).size)}
+        del buf, fb
+        torch.cuda.empty_cache()
+    return {"desc": desc, "bp": coll.total_bp, "genomes": coll.n, **out}
 
 
 PCIE_PEAK_GBS = 64.0  # PCIe 5.0 x16, one direction, nominal
@@ -588,12 +664,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="collection", choices=["collection", "plain"])
     ap.add_argument("--form", default="plain",
-                    choices=["plain", "batched", "stream", "serve", "decoy"],
+                    choices=["plain", "batched", "stream", "serve", "decoy", "fasta"],
                     help="plain: one pair per query (the headline); batched: 64 pairs in one "
                          "pass vs one by one; stream: 10,000 genomes copied host -> HBM in "
                          "packed chunks during the query; serve: Poisson jobs over a resident "
                          "100,000-genome collection; decoy: the pair and its decoy estimate "
-                         "(genomes reversed) in one pass")
+                         "(genomes reversed) in one pass; fasta: amplicon FASTA records, "
+                         "sequence hashes and amplitypes")
     ap.add_argument("--jobs", type=int, default=120, help="serve: number of jobs")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: arrivals per second")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -626,12 +703,30 @@ def main():
                        "tuning": r["tuning"]},
             "roofline": r["roofline"], "cpu_baseline": None}))
         return
+    if args.form == "fasta":
+        r = gpu_fasta(args.steps, args.warmup)
+        print(f"fasta: v4 {r['v4_like']}; long {r['long_amplicon']}", file=sys.stderr, flush=True)
+        lng = r["long_amplicon"]
+        print(json.dumps({
+            "metric": "amplicon FASTA GB/s written (records, hashes, amplitypes)",
+            "value": lng["text_gbps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": lng["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": r["desc"] + "; FASTA of the amplicons of one query",
+                       "form": "fasta", "genomes": r["genomes"], "total_bp": r["bp"],
+                       "v4_like": r["v4_like"], "long_amplicon": lng},
+            "roofline": {"bound": "hbm", "achieved": lng["hbm_frac"] * HBM_PEAK_GBS,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": lng["hbm_frac"],
+                         "traffic": None, "kernel": "k_fasta_write"},
+            "cpu_baseline": None}))
+        return
     if args.form == "decoy":
         r = gpu_decoy(args.steps, args.warmup)
         print(f"decoy: {r['ms_per_step']:.3f} ms per pass with the decoy vs "
               f"{r['real_only']['ms_per_step']:.3f} alone ({r['time_vs_real_only']:.2f}x; two "
               f"passes {r['two_passes_ms']:.3f} ms); amplicons {r['amplicons']}, ratio "
-              f"{r['decoy_ratio']:.4f}", file=sys.stderr, flush=True)
+              f"{r['decoy_ratio']:.4f}; long-amplicon pair {r['long_amplicon_pair']}",
+              file=sys.stderr, flush=True)
         print(json.dumps({
             "metric": METRIC, "value": r["value"], "unit": "Gbp/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
@@ -640,7 +735,7 @@ def main():
             "config": {"workload": r["desc"], "form": "decoy", "genomes": r["genomes"],
                        "total_bp": r["bp"], **{k: r[k] for k in (
                            "real_only", "one_pass", "two_passes_ms", "time_vs_real_only",
-                           "amplicons", "sites", "decoy_ratio")}},
+                           "amplicons", "sites", "decoy_ratio", "long_amplicon_pair")}},
             "roofline": r["roofline_scan"], "cpu_baseline": None}))
         return
     if args.form == "serve":

@@ -283,6 +283,44 @@ ah_status ah_set_scan_tuning(const ah_primer_pair* pairs, uint32_t n_pairs,
 ah_status ah_get_scan_tuning(const ah_primer_pair* pairs, uint32_t n_pairs, ah_scan_tuning* tuning);
 
 /* ---------------------------------------------------------------------------
+ * Amplicon sequences (Section 2.1, "Visualization": the main output is a
+ * FASTA file of the predicted amplicon sequences with their coordinates,
+ * orientation and maximum Tm) and amplitypes (Section 3.3, "Amplicon Pattern
+ * Visualization": per genome, the combination of copy numbers and sequence
+ * variants).
+ * ------------------------------------------------------------------------- */
+
+/* FASTA text of the amplicons d_amp[0 .. min(d_namp->count, amp_capacity))
+ * (as written by ah_pair_amplicons over d_hits of the same genomes), one
+ * record per amplicon in their order:
+ *   >g<genome>:<start>-<end> pair=<pair> orient=<FR|RF|FF|RR> tm=<tm+>,<tm->
+ *   <sequence>
+ * tm+ / tm-: the Tm of the amplicon's + and - sites, two decimals (round half
+ * to even), "nan" without a compatible oligo.  The sequence is the top strand
+ * [start, end) for FR, FF and RR and its reverse complement for RF (copies of
+ * one target read alike on either strand); a masked non-ACGT base is N.
+ * d_text (device, text_capacity bytes) receives the records back to back;
+ * *d_text_res: required = total bytes, count = min(required, capacity),
+ * AH_ERR_OVERFLOW when they do not fit (contents then unspecified).
+ * d_seq_hash [amp_capacity] (optional): each amplicon's sequence hash
+ * mix(n ^ sum_k (c_k + 1) P^k mod 2^64) over its n bases c_k (A0 C1 G2 T3
+ * N4), P = 0x100000001B3, mix = the SplitMix64 finaliser (Steele, Lea & Flood
+ * 2014).  d_amplitype / d_amplitype_n [n_pairs x n_genomes] (optional, index
+ * pair * n_genomes + genome): the amplitype of each (pair, genome), the sum
+ * mod 2^64 of mix(h + 0x9E3779B97F4A7C15) over the hashes h of its FR and RF
+ * amplicons, and their number; equal for two genomes with the same sequences
+ * in the same copy numbers, 0 / 0 for none.  Workspace:
+ * ah_fasta_workspace_bytes.  Errors: AH_ERR_INVALID_ARG, AH_ERR_WORKSPACE,
+ * AH_ERR_HIP. */
+size_t ah_fasta_workspace_bytes(uint64_t amp_capacity);
+ah_status ah_amplicon_fasta(const ah_genomes* genomes, const ah_hit* d_hits,
+                            const ah_amplicon* d_amp, const ah_result* d_namp,
+                            uint64_t amp_capacity, uint32_t n_pairs, char* d_text,
+                            uint64_t text_capacity, ah_result* d_text_res, uint64_t* d_seq_hash,
+                            uint64_t* d_amplitype, uint32_t* d_amplitype_n, void* d_work,
+                            size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Streaming form: a packed collection held in host memory is copied to the GPU
  * in chunks of whole genomes on the caller's copy streams while the previous
  * chunks are scanned, scored and paired on the compute stream.  The paper

@@ -125,6 +125,7 @@ EXPORTS = (
     "ah_stream_workspace_bytes", "ah_stream_query", "ah_server_create", "ah_server_submit",
     "ah_server_wait", "ah_server_part", "ah_server_release", "ah_server_stats_get",
     "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats", "ah_scan_candidate_capacity",
+    "ah_fasta_workspace_bytes", "ah_amplicon_fasta",
 )
 
 _lib = None
@@ -153,6 +154,11 @@ def lib() -> ctypes.CDLL:
     L.ah_pair_amplicons.argtypes = [vp, vp, u64, P(ah_primer_pair), P(ah_window), u32, vp, u64, vp,
                                     vp, sz, vp]
     L.ah_pair_amplicons.restype = st
+    L.ah_fasta_workspace_bytes.argtypes = [u64]
+    L.ah_fasta_workspace_bytes.restype = sz
+    L.ah_amplicon_fasta.argtypes = [P(ah_genomes), vp, vp, vp, u64, u32, vp, u64, vp, vp, vp, vp,
+                                    vp, sz, vp]
+    L.ah_amplicon_fasta.restype = st
     L.ah_pair_workspace_bytes.argtypes = [u64, u32]
     L.ah_pair_workspace_bytes.restype = sz
     L.ah_status_str.argtypes = [ctypes.c_int]
@@ -321,6 +327,20 @@ def ah_pair_amplicons(hits, nhits, hit_capacity: int, pairs, wins, amp, capacity
                                    _ptr(amp), int(capacity), _ptr(res), _ptr(work),
                                    0 if work is None else work.numel(), _stream(stream)),
            "ah_pair_amplicons")
+
+
+def ah_fasta_workspace_bytes(amp_capacity: int) -> int:
+    return int(lib().ah_fasta_workspace_bytes(int(amp_capacity)))
+
+
+def ah_amplicon_fasta(genomes: ah_genomes, hits, amps, namp, amp_capacity: int, n_pairs: int,
+                      text, text_res, seq_hash, amplitype, amplitype_n, work, stream=None):
+    _check(lib().ah_amplicon_fasta(ctypes.byref(genomes), _ptr(hits), _ptr(amps), _ptr(namp),
+                                   int(amp_capacity), int(n_pairs), _ptr(text),
+                                   0 if text is None else text.numel(), _ptr(text_res),
+                                   _ptr(seq_hash), _ptr(amplitype), _ptr(amplitype_n), _ptr(work),
+                                   0 if work is None else work.numel(), _stream(stream)),
+           "ah_amplicon_fasta")
 
 
 def ah_validate_pairs(pairs) -> int:

@@ -1488,6 +1488,45 @@ ah_status ah_pair_amplicons(const ah_hit* d_hits, const ah_result* d_nhits, uint
   return AH_OK;
 }
 
+size_t ah_fasta_workspace_bytes(uint64_t amp_capacity) {
+  Carver c(nullptr, 0);
+  c.take<uint32_t>(amp_capacity ? amp_capacity : 1);
+  c.take<uint64_t>(amp_capacity ? amp_capacity : 1);
+  c.take<uint64_t>(ah::kPairGrid);
+  return c.used();
+}
+
+ah_status ah_amplicon_fasta(const ah_genomes* g, const ah_hit* d_hits, const ah_amplicon* d_amp,
+                            const ah_result* d_namp, uint64_t amp_capacity, uint32_t n_pairs,
+                            char* d_text, uint64_t text_capacity, ah_result* d_text_res,
+                            uint64_t* d_seq_hash, uint64_t* d_amplitype, uint32_t* d_amplitype_n,
+                            void* d_work, size_t work_bytes, void* stream) {
+  g_err.clear();
+  ah_status s = check_genomes(g);
+  if (s) return s;
+  if (!d_namp || !d_text_res) return fail(AH_ERR_INVALID_ARG, "ah_amplicon_fasta: null result");
+  if (amp_capacity > 0 && (!d_amp || !d_hits))
+    return fail(AH_ERR_INVALID_ARG, "ah_amplicon_fasta: amplicons and hits are required");
+  if (text_capacity > 0 && !d_text) return fail(AH_ERR_INVALID_ARG, "d_text is NULL");
+  if ((d_amplitype || d_amplitype_n) && n_pairs == 0)
+    return fail(AH_ERR_INVALID_ARG, "amplitypes need n_pairs >= 1");
+  const size_t need = ah_fasta_workspace_bytes(amp_capacity);
+  if (!d_work || work_bytes < need)
+    return fail(AH_ERR_WORKSPACE, "fasta workspace: %zu bytes given, %zu needed", work_bytes, need);
+  Carver c(d_work, work_bytes);
+  uint32_t* rec_len = c.take<uint32_t>(amp_capacity ? amp_capacity : 1);
+  uint64_t* rec_at = c.take<uint64_t>(amp_capacity ? amp_capacity : 1);
+  uint64_t* cc = c.take<uint64_t>(ah::kPairGrid);
+  // writers: up to 32 waves per CU, no more than the amplicons can use
+  const uint64_t waves = std::min<uint64_t>(std::max<uint64_t>(amp_capacity, 1),
+                                            (uint64_t)cu_count() * 32u);
+  ProfScope prof("fasta", (hipStream_t)stream);
+  AH_HIP(ah::launch_fasta(*g, d_hits, d_amp, d_namp, amp_capacity, n_pairs, d_text, text_capacity,
+                          d_text_res, d_seq_hash, d_amplitype, d_amplitype_n, rec_len, rec_at, cc,
+                          (int)waves, (hipStream_t)stream));
+  return AH_OK;
+}
+
 // ------------------------------------------------------------ dev helpers
 size_t ah_scan_program_source(const ah_primer_pair* pairs, uint32_t n_pairs, int has_nmask,
                               char* buf, size_t buf_bytes) {

@@ -89,6 +89,14 @@ hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
                        const PairBuffers& pb, hipStream_t st);
 
+// Amplicon FASTA records, sequence hashes and amplitypes (see ah.h); rec_len
+// [acap], rec_at [acap] and cc [kPairGrid] are workspace; `waves` writers.
+hipError_t launch_fasta(const ah_genomes& g, const ah_hit* hits, const ah_amplicon* amp,
+                        const ah_result* namp, uint64_t acap, uint32_t n_pairs, char* text,
+                        uint64_t tcap, ah_result* res, uint64_t* seq_hash, uint64_t* atype,
+                        uint32_t* atype_n, uint32_t* rec_len, uint64_t* rec_at, uint64_t* cc,
+                        int waves, hipStream_t st);
+
 // Streaming: word offsets of genomes off[0..n] relative to off[0], and the
 // chunk-local -> collection id fix-up of a chunk's hits and amplicons.
 hipError_t launch_rebase(const uint64_t* off, uint32_t n, uint64_t* out, hipStream_t st);

@@ -873,6 +873,238 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
   }
 }
 
+// ----------------------------------------------------- amplicon FASTA ----
+// The main output of the tool is a FASTA file of the predicted amplicons with
+// their coordinates, orientation and maximum Tm (Section 2.1,
+// "Visualization"); amplitypes are the per-genome patterns of copy numbers
+// and sequence variants (Section 3.3, "Amplicon Pattern Visualization").
+// Record of amplicon i:
+//   >g<genome>:<start>-<end> pair=<pair> orient=<FR|RF|FF|RR> tm=<tm+>,<tm->
+//   <sequence>
+// tm+ / tm- are the Tm of its + and - sites with two decimals (nan when no
+// compatible oligo).  The sequence is the top strand [start, end) for FR, FF
+// and RR and its reverse complement for RF, so that the copies of one target
+// read alike on either strand; a non-ACGT genome base is N.
+// Sequence hash: mix(n ^ sum_k (c_k + 1) P^k mod 2^64) over its n bases
+// (A0 C1 G2 T3 N4), P = 0x100000001B3, mix = the SplitMix64 finaliser.
+// Amplitype of (pair, genome): the sum mod 2^64 of mix(h + 0x9E3779B97F4A7C15)
+// over the sequence hashes h of its FR and RF amplicons, and their count: an
+// order-free multiset hash, equal for two genomes with the same sequences in
+// the same copy numbers.
+constexpr u64 kSeqP = 0x100000001B3ull;
+constexpr u64 kGolden = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ u64 mix64(u64 z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ u32 dec_digits(u32 v) {
+  u32 d = 1;
+  while (v >= 10u) {
+    v /= 10u;
+    ++d;
+  }
+  return d;
+}
+
+__device__ __forceinline__ char* put_dec(char* o, u32 v) {
+  const u32 d = dec_digits(v);
+  for (u32 i = d; i > 0; --i) {
+    o[i - 1] = (char)('0' + v % 10u);
+    v /= 10u;
+  }
+  return o + d;
+}
+
+__device__ __forceinline__ char* put_str(char* o, const char* s) {
+  while (*s) *o++ = *s++;
+  return o;
+}
+
+// Tm x 100 rounded half to even, as a magnitude and a sign; false for NaN.
+// |Tm| < 2^31 / 100 for every finite value this library computes.
+__device__ __forceinline__ bool tm_centi(float v, u32& a, bool& neg) {
+  if (!(v == v)) return false;
+  const double r = rint((double)v * 100.0);
+  neg = r < 0;
+  a = (u32)(neg ? -r : r);
+  return true;
+}
+
+__device__ __forceinline__ u32 tm_len(float v) {
+  u32 a;
+  bool neg;
+  if (!tm_centi(v, a, neg)) return 3;  // "nan"
+  return (neg ? 1u : 0u) + dec_digits(a / 100u) + 3u;
+}
+
+__device__ __forceinline__ char* put_tm(char* o, float v) {
+  u32 a;
+  bool neg;
+  if (!tm_centi(v, a, neg)) return put_str(o, "nan");
+  if (neg) *o++ = '-';
+  o = put_dec(o, a / 100u);
+  *o++ = '.';
+  *o++ = (char)('0' + (a % 100u) / 10u);
+  *o++ = (char)('0' + a % 10u);
+  return o;
+}
+
+__device__ __forceinline__ u32 fasta_header_len(const ah_amplicon& A, const ah_hit* hits) {
+  // ">g" ":" "-" " pair=" " orient=XX" " tm=" "," "\n"
+  return 2u + dec_digits(A.genome) + 1u + dec_digits(A.start) + 1u + dec_digits(A.end) + 6u +
+         dec_digits(A.pair) + 10u + 4u + tm_len(hits[A.plus_hit].tm) + 1u +
+         tm_len(hits[A.minus_hit].tm) + 1u;
+}
+
+// 1: record lengths (header + sequence + newline) and per-chunk sums; the
+// amplitype tables are zeroed for the writer.
+__global__ __launch_bounds__(kBlock) void k_fasta_len(
+    const ah_amplicon* __restrict__ amp, const ah_result* __restrict__ namp, u64 acap,
+    const ah_hit* __restrict__ hits, u32* __restrict__ rec_len, u64* __restrict__ cc,
+    u64* __restrict__ atype, u32* __restrict__ atype_n, u64 n_groups) {
+  __shared__ u64 lds4[4];
+  for (u64 q = global_tid(); q < n_groups; q += grid_threads()) {
+    if (atype) atype[q] = 0;
+    if (atype_n) atype_n[q] = 0;
+  }
+  const u64 n = pair_n(namp, acap);
+  u64 chunk;
+  if (blockIdx.x >= pair_chunks(n, chunk)) return;
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  u64 sum = 0;
+  for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const ah_amplicon A = amp[i];
+    const u32 l = fasta_header_len(A, hits) + (A.end - A.start) + 1u;
+    rec_len[i] = l;
+    sum += l;
+  }
+  sum = block_sum(sum, lds4);
+  if (threadIdx.x == 0) cc[blockIdx.x] = sum;
+}
+
+// 2: each record's first byte, and the result.
+__global__ __launch_bounds__(kBlock) void k_fasta_offsets(
+    const ah_result* __restrict__ namp, u64 acap, const u32* __restrict__ rec_len,
+    const u64* __restrict__ cc, u64* __restrict__ rec_at, u64 tcap, ah_result* __restrict__ res) {
+  __shared__ u64 lds4[4];
+  const u64 n = pair_n(namp, acap);
+  u64 chunk;
+  const u32 G = pair_chunks(n, chunk);
+  if (blockIdx.x >= (G ? G : 1u)) return;  // workgroup 0 writes the result even for none
+  u64 total;
+  u64 run = chunk_prefix(cc, G, blockIdx.x, lds4, &total);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    res->required = total;
+    res->count = total < tcap ? total : tcap;
+    res->status = total > tcap ? AH_ERR_OVERFLOW : AH_OK;
+    res->reserved = 0;
+  }
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  for (u64 rb = beg; rb < end; rb += blockDim.x) {
+    const u64 i = rb + threadIdx.x;
+    const u32 li = i < end ? rec_len[i] : 0u;
+    u64 rt;
+    const u64 at = run + block_exclusive_scan(li, lds4, rt);
+    if (i < end) rec_at[i] = at;
+    run += rt;
+  }
+}
+
+// 3: one wave per amplicon (grid-stride): lane 0 writes the header, the
+// lanes the bases (lane j takes bases j, j + 64, ...: its word index steps by
+// 64 words, wrapping into the next segment, with no division per base), and
+// the wave sums the lanes' shares of the sequence hash.
+__global__ __launch_bounds__(kBlock) void k_fasta_write(
+    const uint2* __restrict__ words, const u32* __restrict__ nmask, const u64* __restrict__ word_off,
+    const u32* __restrict__ glen, u32 n_genomes, const ah_amplicon* __restrict__ amp,
+    const ah_result* __restrict__ namp, u64 acap, const ah_hit* __restrict__ hits,
+    const u32* __restrict__ rec_len, const u64* __restrict__ rec_at, char* __restrict__ text,
+    u64 tcap, u64* __restrict__ seq_hash, u64* __restrict__ atype, u32* __restrict__ atype_n,
+    u32 n_pairs) {
+  const u64 n = pair_n(namp, acap);
+  const u32 lane = threadIdx.x & 63u;
+  const u64 wid = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const u64 nw = ((u64)gridDim.x * blockDim.x) >> 6;
+  // P^lane and Q = P^64 for the lane-parallel sequence hash
+  u64 p_lane = 1;
+  for (u32 e = 0; e < lane; ++e) p_lane *= kSeqP;
+  u64 Q = kSeqP;
+  for (int e = 0; e < 6; ++e) Q *= Q;
+  for (u64 ai = wid; ai < n; ai += nw) {
+    const ah_amplicon A = amp[ai];
+    if (A.genome >= n_genomes) continue;  // not written by a pairing of these genomes
+    const u64 at = rec_at[ai];
+    const u32 len = A.end - A.start;
+    const u32 rl = rec_len[ai];
+    const u32 hl = rl - len - 1u;
+    const bool fits = at + rl <= tcap;
+    if (fits && lane == 0) {
+      char* o = text + at;
+      o = put_str(o, ">g");
+      o = put_dec(o, A.genome);
+      *o++ = ':';
+      o = put_dec(o, A.start);
+      *o++ = '-';
+      o = put_dec(o, A.end);
+      o = put_str(o, " pair=");
+      o = put_dec(o, A.pair);
+      o = put_str(o, A.orient == AH_FR ? " orient=FR" : A.orient == AH_RF ? " orient=RF"
+                     : A.orient == AH_FF ? " orient=FF" : " orient=RR");
+      o = put_str(o, " tm=");
+      o = put_tm(o, hits[A.plus_hit].tm);
+      *o++ = ',';
+      o = put_tm(o, hits[A.minus_hit].tm);
+      *o++ = '\n';
+      text[at + rl - 1u] = '\n';
+    }
+    const int S = (int)((glen[A.genome] + 31u) >> 5);
+    const uint2* w = words + word_off[A.genome];
+    const u32* nm = nmask ? nmask + word_off[A.genome] : nullptr;
+    const bool rc = A.orient == AH_RF;
+    // base x = b * S + t of this lane's first position; then x moves by 64
+    const int x0 = rc ? (int)A.end - 1 - (int)lane : (int)A.start + (int)lane;
+    int b = x0 / S, t = x0 - b * S;
+    char* out = text + at + hl;
+    u64 acc = 0, qp = 1;
+    for (u32 k = lane; k < len; k += 64u) {
+      const uint2 v = w[t];
+      u32 c = (((v.x >> b) & 1u) << 1) | ((v.y >> b) & 1u);
+      if (nm && ((nm[t] >> b) & 1u)) c = 4u;
+      else if (rc) c = 3u - c;
+      if (fits) out[k] = "ACGTN"[c];
+      acc += (u64)(c + 1u) * qp;
+      qp *= Q;
+      if (rc) {
+        t -= 64;
+        while (t < 0) {
+          t += S;
+          --b;
+        }
+      } else {
+        t += 64;
+        while (t >= S) {
+          t -= S;
+          ++b;
+        }
+      }
+    }
+    acc *= p_lane;
+    for (u32 o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) {
+      const u64 h = mix64(acc ^ (u64)len);
+      if (seq_hash) seq_hash[ai] = h;
+      if ((A.orient == AH_FR || A.orient == AH_RF) && atype && A.pair < n_pairs) {
+        const u64 gq = (u64)A.pair * n_genomes + A.genome;
+        atomicAdd(&atype[gq], mix64(h + kGolden));
+        if (atype_n) atomicAdd(&atype_n[gq], 1u);
+      }
+    }
+  }
+}
+
 // ---- streaming: per-chunk offsets and id fix-up ---------------------------
 // out[i] = off[i] - off[0] for i = 0..n: the word offsets of a run of genomes
 // relative to the first, for a chunk staged on its own.
@@ -1038,6 +1270,23 @@ hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_
                                             pb.mpos_f, pb.midx_f, (const u64*)pb.mkey_r, pb.mpos_r,
                                             pb.midx_r, pb.pre_f, pb.pre_r, (const u64*)pb.mtot,
                                             pb.cnt, (const u64*)pb.cc, amp, cap, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_fasta(const ah_genomes& g, const ah_hit* hits, const ah_amplicon* amp,
+                        const ah_result* namp, uint64_t acap, uint32_t n_pairs, char* text,
+                        uint64_t tcap, ah_result* res, uint64_t* seq_hash, uint64_t* atype,
+                        uint32_t* atype_n, uint32_t* rec_len, uint64_t* rec_at, uint64_t* cc,
+                        int waves, hipStream_t st) {
+  const u64 n_groups = (u64)n_pairs * g.n;
+  k_fasta_len<<<kPairGrid, kBlock, 0, st>>>(amp, namp, acap, hits, rec_len, (u64*)cc, (u64*)atype,
+                                           atype_n, n_groups);
+  k_fasta_offsets<<<kPairGrid, kBlock, 0, st>>>(namp, acap, rec_len, (const u64*)cc, (u64*)rec_at,
+                                               tcap, res);
+  const int blocks = (waves + kBlock / 64 - 1) / (kBlock / 64);
+  k_fasta_write<<<blocks > 0 ? blocks : 1, kBlock, 0, st>>>(
+      (const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, g.n, amp, namp, acap, hits,
+      rec_len, (const u64*)rec_at, text, tcap, (u64*)seq_hash, (u64*)atype, atype_n, n_pairs);
   return hipGetLastError();
 }
 

@@ -103,6 +103,42 @@ def run(coll: PackedCollection, pairs: Sequence, buf: QueryBuffers, tm: Optional
                             buf.amps, buf.amp_cap, buf.amp_res, buf.pair_work, stream)
 
 
+@dataclasses.dataclass
+class FastaBuffers:
+    text: "object"         # uint8 [text_cap]
+    text_res: "object"     # ah_result
+    seq_hash: "object"     # int64 [amp_cap] (uint64 values)
+    amplitype: "object"    # int64 [n_pairs * n_genomes] (uint64 values)
+    amplitype_n: "object"  # int32 [n_pairs * n_genomes] (uint32 values)
+    work: "object"
+
+
+def fasta_alloc(coll: PackedCollection, n_pairs: int, amp_cap: int, text_cap: int, device) -> FastaBuffers:
+    import torch
+
+    groups = max(1, n_pairs * coll.n)
+    return FastaBuffers(
+        torch.empty(max(1, text_cap), dtype=torch.uint8, device=device),
+        torch.zeros(24, dtype=torch.uint8, device=device),
+        torch.empty(max(1, amp_cap), dtype=torch.int64, device=device),
+        torch.empty(groups, dtype=torch.int64, device=device),
+        torch.empty(groups, dtype=torch.int32, device=device),
+        torch.empty(L.ah_fasta_workspace_bytes(amp_cap), dtype=torch.uint8, device=device))
+
+
+def fasta(coll: PackedCollection, n_pairs: int, buf: QueryBuffers, fb: FastaBuffers, stream=None):
+    """Enqueue the FASTA records, sequence hashes and amplitypes of the
+    amplicons in ``buf`` (after ``run``)."""
+    L.ah_amplicon_fasta(coll.view(), buf.hits, buf.amps, buf.amp_res, buf.amp_cap, n_pairs,
+                        fb.text, fb.text_res, fb.seq_hash, fb.amplitype, fb.amplitype_n, fb.work,
+                        stream)
+
+
+def fasta_text(fb: FastaBuffers) -> bytes:
+    n = result(fb.text_res)["count"]
+    return fb.text[:n].cpu().numpy().tobytes()
+
+
 def result(res_tensor) -> dict:
     r = np.frombuffer(res_tensor.cpu().numpy().tobytes(), dtype=np.dtype(
         [("count", "<u8"), ("required", "<u8"), ("status", "<i4"), ("reserved", "<u4")]))[0]
