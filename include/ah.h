@@ -89,6 +89,25 @@ typedef struct ah_genomes {
  * buffer needs 8 bytes per word, the nmask buffer 4 bytes per word. */
 uint64_t ah_pack_layout(const uint64_t* h_len, uint32_t n, uint64_t* h_word_off);
 
+/* FASTA text in host memory -> the records' sequence bytes (Section 2.1: the
+ * input is genomes in FASTA).  A record starts at a line whose first byte is
+ * '>'; its name is the rest of that line (trailing blanks and '\r'
+ * removed).  Its sequence is every byte of the lines up to the next record,
+ * line breaks, '\r', blanks and tabs removed: case and IUPAC codes are kept
+ * (ah_pack_genomes folds case and masks the non-ACGT bytes).  Each record is
+ * its own linear sequence; a genome of several contigs is several records.
+ * ah_fasta_count gives the number of records and of sequence bytes;
+ * ah_fasta_read writes the bytes to seq (host, seq_capacity bytes), record r
+ * at [seq_off[r], seq_off[r + 1]) (seq_off: n_records + 1 entries), and its
+ * name's byte span in the text to name_span[2r], name_span[2r + 1].  The text
+ * is read by up to 16 threads.  Errors: AH_ERR_INVALID_ARG (null argument,
+ * sequence bytes before the first '>' line), AH_ERR_LIMIT (more records or
+ * bytes than given room for). */
+ah_status ah_fasta_count(const char* text, uint64_t bytes, uint64_t* n_records,
+                         uint64_t* seq_bytes);
+ah_status ah_fasta_read(const char* text, uint64_t bytes, uint8_t* seq, uint64_t seq_capacity,
+                        uint64_t* seq_off, uint64_t* name_span, uint64_t max_records);
+
 /* Pack ASCII genomes into the layout above.  Genome g is
  * d_ascii[d_ascii_off[g] .. d_ascii_off[g+1]); upper or lower case A/C/G/T are
  * bases, every other byte is a non-ACGT base.  d_word_off must hold the

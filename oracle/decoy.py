@@ -44,16 +44,7 @@ def run(seqs: Sequence, pairs, p: otm.TmParams = otm.TmParams(), filter_tm: bool
     rs = reversed_genomes(seqs)
     h = oscan.scan_collection(rs, pairs)
     h = otm.fill_tm(h, rs, pairs, p)
-    a = []
-    for q, pr in enumerate(pairs):
-        base = np.flatnonzero(h["pair"] == q)
-        aq = opair.call_amplicons(h[base], [pr], filter_tm, min_tm)
-        aq["pair"] = q
-        aq["plus_hit"] = base[aq["plus_hit"]]
-        aq["minus_hit"] = base[aq["minus_hit"]]
-        a.append(aq)
-    amps = np.concatenate(a) if a else np.zeros(0, opair.AMP_DTYPE)
-    return h, amps
+    return h, opair.call_amplicons(h, pairs, filter_tm, min_tm)
 
 
 _SWAP = np.array([opair.RF, opair.FR, opair.FF, opair.RR], dtype=np.int8)

@@ -125,7 +125,7 @@ EXPORTS = (
     "ah_stream_workspace_bytes", "ah_stream_query", "ah_server_create", "ah_server_submit",
     "ah_server_wait", "ah_server_part", "ah_server_release", "ah_server_stats_get",
     "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats", "ah_scan_candidate_capacity",
-    "ah_fasta_workspace_bytes", "ah_amplicon_fasta",
+    "ah_fasta_workspace_bytes", "ah_amplicon_fasta", "ah_fasta_count", "ah_fasta_read",
 )
 
 _lib = None
@@ -154,6 +154,10 @@ def lib() -> ctypes.CDLL:
     L.ah_pair_amplicons.argtypes = [vp, vp, u64, P(ah_primer_pair), P(ah_window), u32, vp, u64, vp,
                                     vp, sz, vp]
     L.ah_pair_amplicons.restype = st
+    L.ah_fasta_count.argtypes = [ctypes.c_char_p, u64, P(ctypes.c_uint64), P(ctypes.c_uint64)]
+    L.ah_fasta_count.restype = st
+    L.ah_fasta_read.argtypes = [ctypes.c_char_p, u64, vp, u64, vp, vp, u64]
+    L.ah_fasta_read.restype = st
     L.ah_fasta_workspace_bytes.argtypes = [u64]
     L.ah_fasta_workspace_bytes.restype = sz
     L.ah_amplicon_fasta.argtypes = [P(ah_genomes), vp, vp, vp, u64, u32, vp, u64, vp, vp, vp, vp,
@@ -327,6 +331,30 @@ def ah_pair_amplicons(hits, nhits, hit_capacity: int, pairs, wins, amp, capacity
                                    _ptr(amp), int(capacity), _ptr(res), _ptr(work),
                                    0 if work is None else work.numel(), _stream(stream)),
            "ah_pair_amplicons")
+
+
+def fasta_read(text: bytes, pinned: bool = False):
+    """Records of FASTA text: (sequence bytes, offsets [n + 1] int64, names
+    [n] str).  The bytes are a numpy uint8 array, or with ``pinned`` a torch
+    uint8 tensor in pinned host memory, written there directly."""
+    n = ctypes.c_uint64()
+    q = ctypes.c_uint64()
+    _check(lib().ah_fasta_count(text, len(text), ctypes.byref(n), ctypes.byref(q)), "ah_fasta_count")
+    if pinned:
+        import torch
+
+        seq = torch.empty(max(1, q.value), dtype=torch.uint8, pin_memory=True)
+        dst = seq.data_ptr()
+    else:
+        seq = np.empty(max(1, q.value), dtype=np.uint8)
+        dst = seq.ctypes.data
+    off = np.empty(n.value + 1, dtype=np.uint64)
+    span = np.empty(max(1, 2 * n.value), dtype=np.uint64)
+    _check(lib().ah_fasta_read(text, len(text), dst, q.value, off.ctypes.data, span.ctypes.data,
+                               n.value), "ah_fasta_read")
+    names = [text[int(span[2 * r]):int(span[2 * r + 1])].decode(errors="replace")
+             for r in range(n.value)]
+    return seq[: q.value], off.astype(np.int64), names
 
 
 def ah_fasta_workspace_bytes(amp_capacity: int) -> int:

@@ -65,7 +65,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     _embed(os.path.join(CSRC, "scan_core.hip"), os.path.join(BUILD, "scan_core_src.inc"))
     objs = []
-    for name in ("ah_kernels.hip", "ah_host.cpp", "ah_stream.cpp", "ah_serve.cpp"):
+    for name in ("ah_kernels.hip", "ah_host.cpp", "ah_stream.cpp", "ah_serve.cpp",
+                 "ah_fasta_io.cpp"):
         src = os.path.join(CSRC, name)
         obj = os.path.join(BUILD, name + ".o")
         lang = ["-x", "hip"] if name.endswith(".hip") else []

@@ -57,6 +57,22 @@ def pack(ascii, ascii_off, lengths, with_nmask: bool = False, stream=None):
     return coll, non_acgt
 
 
+def read_fasta(text: bytes, device, with_nmask: bool = True, stream=None):
+    """FASTA text -> a packed collection on the device (one sequence per
+    record: a genome of several contigs is several records).  The host reads
+    the records (``ah_fasta_read``) straight into pinned memory, the bytes
+    cross to the device, the device packs them.  Returns (collection, names,
+    non-ACGT count per record or None)."""
+    import torch
+
+    seq, off, names = L.fasta_read(text, pinned=True)
+    lengths = np.diff(off)
+    ascii = seq.to(device, non_blocking=True)
+    d_off = torch.from_numpy(off).to(device)
+    coll, non_acgt = pack(ascii, d_off, lengths, with_nmask=with_nmask, stream=stream)
+    return coll, names, non_acgt
+
+
 @dataclasses.dataclass
 class QueryBuffers:
     hits: "object"

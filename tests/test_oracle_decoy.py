@@ -15,15 +15,7 @@ from synth import fill, plan
 def _real(seqs, pairs):
     h = scan.scan_collection(seqs, pairs)
     h = tm.fill_tm(h, seqs, pairs)
-    a = []
-    for q, pr in enumerate(pairs):
-        base = np.flatnonzero(h["pair"] == q)
-        aq = pair.call_amplicons(h[base], [pr])
-        aq["pair"] = q
-        aq["plus_hit"] = base[aq["plus_hit"]]
-        aq["minus_hit"] = base[aq["minus_hit"]]
-        a.append(aq)
-    return h, np.concatenate(a)
+    return h, pair.call_amplicons(h, pairs)
 
 
 def _collection(seed):
@@ -66,15 +58,9 @@ def test_forward_frame_is_the_scan_of_the_complement_primers():
             for pr in pairs]
     hc = scan.scan_collection(rseqs, comp)
     _same(f, hc, ("pair", "genome", "pos", "strand", "primer", "mm"))
-    ac = []
-    for q, pr in enumerate(comp):
-        base = np.flatnonzero(hc["pair"] == q)
-        aq = pair.call_amplicons(hc[base], [pr])
-        aq["pair"] = q
-        aq["plus_hit"] = base[aq["plus_hit"]]
-        aq["minus_hit"] = base[aq["minus_hit"]]
-        ac.append(aq)
-    ac = np.concatenate(ac)
+    ac = pair.call_amplicons(hc, comp)
+    # both pairs form amplicons (the second with a clamp and k 3)
+    assert set(np.unique(ac["pair"]).tolist()) == {0, 1}
     _same(g, ac, ("pair", "genome", "start", "end", "orient", "plus_hit", "minus_hit"))
     # FR and RF exchange labels, lengths are kept
     assert sorted((a["end"] - a["start"]).tolist()) == sorted((g["end"] - g["start"]).tolist())
