@@ -158,6 +158,16 @@ def gpu_run(name: str, steps: int, warmup: int):
         if d.get("program_sha256") == sha:  # counters were taken on this exact kernel
             traffic = d["traffic_bytes_per_dispatch"]
             valu = d.get("sq_insts_valu_per_dispatch")
+    # the same pass captured once into a hipGraph and replayed
+    graph = path.capture(coll, [pr], buf)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+    assert path.result(buf.hit_res)["count"] == res_h["count"]
     hits = path.hits_numpy(buf)
     cands = L.ah_scan_candidate_stats(buf.scan_work, coll.n, buf.hit_cap)
     tm_ok = bool(np.all(np.isfinite(hits["tm"]))) if hits.size else True
@@ -168,6 +178,7 @@ def gpu_run(name: str, steps: int, warmup: int):
     return {
         "bp": bp, "desc": desc, "ms_per_step": ms_step, "value": bp / (ms_step * 1e-3) / 1e9,
         "kernel_ms": kern, "hits": res_h["count"], "amplicons": res_a["count"], "tm_finite": tm_ok,
+        "graph_replay": {"ms_per_step": ms_graph, "gbps": bp / (ms_graph * 1e-3) / 1e9},
         "scan_candidates": cands,
         "pack": {"ms": pack_ms, "wall_ms": pack_s * 1e3, "gbps": bp / (pack_ms * 1e-3) / 1e9},
         "jit": {"compiles": jit1[0] - jit0[0], "ms": jit1[1] - jit0[1]},
@@ -883,6 +894,7 @@ def main():
             "workload": r["desc"], "genomes": r["genomes"], "total_bp": r["bp"],
             "pair": r["pair"], "form": "plain", "hits": r["hits"], "amplicons": r["amplicons"],
             "kernel_ms": r["kernel_ms"], "scan_candidates": r["scan_candidates"],
+            "graph_replay": r["graph_replay"],
             "ingest_pack": r["pack"], "jit": r["jit"],
             "tm_dtype": "f32 (compensated sums, f64 salt/log terms)",
         },

@@ -922,6 +922,42 @@ ah_status load_scan_kernel(int dev, const std::string& src, const std::vector<ch
 // Compiled and loaded scan kernel for `src` on the current device (cached;
 // compiles outside the cache lock so that several programs can compile at
 // once).
+// The kernels of a primer set, looked up by the set itself (the pairs'
+// strings and parameters, the mask flag, the tuning, the planner's knobs)
+// before the generated source is built: the per-call path then does no code
+// generation and no comparison of sources.
+std::map<std::pair<int, std::string>, ScanFns> g_fns;
+
+std::string fns_key(const std::string& set, bool has_n, Tuning tn) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "#%d|%d|%d|%d|%.17g|%d|%d", has_n ? 1 : 0, tn.u, tn.group,
+           filter_enabled() ? 1 : 0, cand_weight(), forced_need(), code_planes() ? 1 : 0);
+  return set + buf;
+}
+
+ah_status get_scan_kernel(const std::string& src, ScanFns& fn);
+std::string set_key(const ah_primer_pair* pairs, uint32_t n_pairs);
+
+ah_status scan_kernels_for(const ah_primer_pair* pairs, uint32_t n_pairs, const PairSet& ps,
+                           bool has_n, Tuning tn, ScanFns& fn) {
+  int dev = 0;
+  AH_HIP(hipGetDevice(&dev));
+  const auto key = std::make_pair(dev, fns_key(set_key(pairs, n_pairs), has_n, tn));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_fns.find(key);
+    if (it != g_fns.end()) {
+      fn = it->second;
+      return AH_OK;
+    }
+  }
+  ah_status s = get_scan_kernel(gen_program(patterns_of(ps), has_n, tn), fn);
+  if (s) return s;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_fns[key] = fn;
+  return AH_OK;
+}
+
 ah_status get_scan_kernel(const std::string& src, ScanFns& fn) {
   int dev = 0;
   AH_HIP(hipGetDevice(&dev));
@@ -1300,6 +1336,7 @@ void ah_release_caches(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& kv : g_jit) (void)hipModuleUnload(kv.second.mod);
   g_jit.clear();
+  g_fns.clear();
   for (auto& kv : g_tables) (void)hipFree(kv.second);
   g_tables.clear();
 }
@@ -1355,7 +1392,7 @@ ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint
     return fail(AH_ERR_WORKSPACE, "scan workspace: %zu bytes given, %zu needed", work_bytes, need);
   const Tuning tn = tuning_for(pairs, n_pairs);
   ScanFns fn;
-  s = get_scan_kernel(gen_program(patterns_of(ps), g->nmask != nullptr, tn), fn);
+  s = scan_kernels_for(pairs, n_pairs, ps, g->nmask != nullptr, tn, fn);
   if (s) return s;
 
   hipStream_t st = (hipStream_t)stream;
