@@ -361,3 +361,53 @@ def test_windows_with_exactly_k_mismatches_are_all_found(dev, k):
     gotl = [(int(h["genome"]), int(h["pos"]), int(h["strand_primer"]) >> 1,
              int(h["strand_primer"]) & 1, int(h["mm"])) for h in path.hits_numpy(buf)]
     assert gotl == want
+
+
+def test_collection_full_size_sampled_against_oracle(dev):
+    """The benchmark's collection workload (1,000 genomes, 4.2 Gbp) in the
+    launch configuration bench.py times (same capacities, so the same grid
+    and slices): five genomes compared record by record with the oracle, and
+    the invariants every record of the full output must meet."""
+    import torch
+
+    from paper_2509_13300_amd import path
+    from synth import gpu
+
+    p = plan.collection(1000, seed=13302)
+    pr = p.pairs[0]
+    ascii, off = gpu.fill_cuda(p, dev)
+    coll, _ = path.pack(ascii, off, p.lengths)
+    del ascii
+    buf = path.alloc(coll, [pr], 1 << 22, 1 << 22, dev)
+    path.run(coll, [pr], buf)
+    torch.cuda.synchronize()
+    assert path.result(buf.hit_res)["status"] == 0 and path.result(buf.amp_res)["status"] == 0
+    gh, ga = path.hits_numpy(buf), path.amps_numpy(buf)
+    say("collection full size: hits", gh.size, "amplicons", ga.size)
+    # invariants over everything
+    key = (gh["genome"].astype(np.int64) << 34) | (gh["pos"].astype(np.int64) << 2) | \
+        gh["strand_primer"].astype(np.int64)
+    assert np.all(np.diff(key) > 0)  # canonical order, no duplicates
+    assert np.all(gh["mm"] <= pr.k) and np.all(np.isfinite(gh["tm"]))
+    lens = ga["end"].astype(np.int64) - ga["start"]
+    assert np.all((lens >= pr.min_len) & (lens <= pr.max_len))
+    assert np.all(gh["pos"].astype(np.int64) + np.where(gh["strand_primer"] & 1, len(pr.rev),
+                                                         len(pr.fwd)) <= p.lengths[gh["genome"]])
+    # sampled genomes against the oracle
+    sample = [0, 249, 500, 761, 999]
+    sub = p.subset(sample)
+    oh, oa = run_oracle(sub, [pr])
+    for j, g in enumerate(sample):
+        hg = gh[gh["genome"] == g].copy()
+        hg["genome"] = j
+        og = oh[oh["genome"] == j]
+        assert hit_tuples_gpu(hg) == hit_tuples_oracle(og), g
+        assert float(np.abs(hg["tm"].astype(np.float64) - og["tm"]).max(initial=0)) <= TM_TOL
+        ag = ga[ga["genome"] == g]
+        ao = oa[oa["genome"] == j]
+        first_g = np.flatnonzero(gh["genome"] == g)
+        first_o = np.flatnonzero(oh["genome"] == j)
+        assert [(int(a["start"]), int(a["end"]), int(a["orient"]), int(a["plus_hit"]) - first_g[0],
+                 int(a["minus_hit"]) - first_g[0]) for a in ag] == \
+            [(int(a["start"]), int(a["end"]), int(a["orient"]), int(a["plus_hit"]) - first_o[0],
+              int(a["minus_hit"]) - first_o[0]) for a in ao], g
