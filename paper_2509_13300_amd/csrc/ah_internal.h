@@ -58,8 +58,6 @@ hipError_t launch_tile_counts(const uint32_t* len, uint32_t n, uint32_t tile_wor
 // n_host when n_dev is null, else *n_dev (device).  tmp: kScanGrid + 1 u64.
 hipError_t launch_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n_host,
                                  const uint64_t* n_dev, uint64_t* tmp, hipStream_t st);
-hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, const uint64_t* n_dev,
-                                     uint64_t* tmp, hipStream_t st);
 // Radix sort of staged hit records into canonical order.
 struct SortBuffers {
   uint64_t* keys[2];

@@ -1212,14 +1212,6 @@ hipError_t launch_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n_h
   return hipGetLastError();
 }
 
-hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint64_t* out, const uint64_t* n_dev,
-                                     uint64_t* tmp, hipStream_t st) {
-  k_scan_reduce<u32><<<kScanGrid, kBlock, 0, st>>>(in, 0, (const u64*)n_dev, (u64*)tmp);
-  k_scan_partials<<<1, kBlock, 0, st>>>((u64*)tmp);
-  k_scan_down<u32><<<kScanGrid, kBlock, 0, st>>>(in, (u64*)out, 0, (const u64*)n_dev, (const u64*)tmp);
-  return hipGetLastError();
-}
-
 template <int D>
 void sort_passes(const ah_hit* staged, ah_hit* out, const u64* n_dev, KeyBits kb,
                  const SortBuffers& sb, hipStream_t st) {

@@ -3,7 +3,7 @@
 // This file is compiled at run time (hipRTC) once per primer set, with a
 // generated pattern program appended after it; the build compiles a few such
 // specialisations to check that it builds.  A pattern is one primer of a pair
-// on one strand.  Two kernels:
+// on one strand.  Three kernels:
 //
 // * ah_scan_kernel, the filter.  Packed layout (see ah.h): bit b of word t of a
 //   genome holds the base at b*S + t, so the window starting at b*S + t reads
@@ -25,8 +25,10 @@
 //   apart from the filter so that its registers do not lower the filter's
 //   occupancy.
 // * ah_emit_kernel: one workgroup per slice; the slice's output offset is the
-//   sum of the earlier slices' sites (no device atomics), and the candidates
-//   with sites are counted again, now writing the site records.  Workgroup 0
+//   sum of the earlier slices' sites (the sums of the earlier groups of 64
+//   slices, then of the earlier slices of its own group; no device atomics),
+//   and the candidates with sites are counted again, now writing the site
+//   records.  Workgroup 0
 //   also writes the result (required = sites found, count = records written)
 //   and the candidate-list statistics; a full slice makes the result an
 //   overflow whose bound covers both lists.
