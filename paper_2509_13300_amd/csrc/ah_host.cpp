@@ -1149,7 +1149,9 @@ ScanWs carve_scan(Carver& c, uint32_t n, uint64_t cap, uint64_t ccap) {
   w.sb.keys[1] = c.take<uint64_t>(cap ? cap : 1);
   w.sb.idx[0] = c.take<uint32_t>(cap ? cap : 1);
   w.sb.idx[1] = c.take<uint32_t>(cap ? cap : 1);
-  w.sb.hist = c.take<uint32_t>((uint64_t)ah::kSortDigits * ah::kSortGrid);
+  w.sb.hstride = ah::sort_hist_stride(cap);
+  for (int b = 0; b < 3; ++b)
+    w.sb.hist[b] = c.take<uint32_t>((uint64_t)ah::kSortDigits * w.sb.hstride);
   w.cstat = c.take<uint64_t>(4);
   w.slice_cnt = c.take<uint32_t>(kMaxScanGrid);
   w.slice_tot = c.take<uint32_t>(kMaxScanGrid);

@@ -62,8 +62,17 @@ hipError_t launch_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n_h
 struct SortBuffers {
   uint64_t* keys[2];
   uint32_t* idx[2];
-  uint32_t* hist;      // kSortDigits x kSortGrid digit counts (one row per digit)
+  uint32_t* hist[3];   // kSortDigits x hstride digit counts each (one row per digit)
+  uint32_t hstride;    // columns: the most chunks a sort of `capacity` records uses
 };
+// Column stride of the sort histograms for a capacity: the most chunks of
+// kSortChunkMin records (at most kSortGrid), a multiple of 4.
+constexpr uint32_t kSortChunkMin = 256;
+inline uint32_t sort_hist_stride(uint64_t capacity) {
+  const uint64_t g = (capacity + kSortChunkMin - 1) / kSortChunkMin;
+  const uint64_t c = g < (uint64_t)kSortGrid ? g : (uint64_t)kSortGrid;
+  return (uint32_t)((c + 3) / 4 * 4 > 0 ? (c + 3) / 4 * 4 : 4);
+}
 hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev,
                             KeyBits kb, const SortBuffers& sb, hipStream_t st);
 hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pairs, ah_hit* hits,

@@ -199,15 +199,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const T* __restrict__ in, 
 // ------------------------------------------------------------ radix sort --
 // LSD radix sort of the hit records by their canonical key, D = 8 or 9 bits
 // a pass (9 when that saves a pass).  Every pass splits the n records into
-// the same G <= kSortGrid contiguous chunks, one per workgroup: a histogram
-// kernel writes each chunk's digit counts, and the scatter kernel derives
-// its chunk's output offsets from all G histograms itself (no separate
-// prefix-scan launches).  The first histogram comes with the keys; the last
-// scatter writes the records.  The counts are stored digit-major
-// (hist[digit * kSortGrid + chunk]), so that the thread of a digit reads its
-// G counts with 16-byte loads, all in flight at once: the counts were written
-// by another kernel and miss the caches.
-constexpr u64 kSortChunkMin = kBlock;
+// the same G <= kSortGrid contiguous chunks, one per workgroup, and each
+// pass is one scatter kernel: it derives its chunk's output offsets from all
+// G chunk histograms of its digit itself (no prefix-scan launches) and,
+// while placing the items, counts their next digit per destination chunk
+// (no histogram launches).  The first histograms come with the keys; the
+// last scatter writes the records: passes + 1 launches in all.  The counts
+// are stored digit-major (hist[digit * hs + chunk], hs >= G a multiple of 4
+// from the capacity: SortBuffers::hstride), so that the
+// thread of a digit reads its G counts with 16-byte loads, all in flight at
+// once: the counts were written by another kernel and miss the caches.
 
 __device__ __forceinline__ u32 sort_chunks(u64 n, u64& chunk) {
   u64 c = (n + kSortGrid - 1) / kSortGrid;
@@ -218,21 +219,24 @@ __device__ __forceinline__ u32 sort_chunks(u64 n, u64& chunk) {
 
 // Digit counts of this chunk (h: 2^D LDS counters) into the digit-major table.
 template <int D>
-__device__ __forceinline__ void store_hist(const u32* h, u32* __restrict__ hist) {
-  for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x)
-    hist[(u64)d * kSortGrid + blockIdx.x] = h[d];
+__device__ __forceinline__ void store_hist(const u32* h, u32* __restrict__ hist, u32 hs) {
+  for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x) hist[(u64)d * hs + blockIdx.x] = h[d];
 }
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_keygen(const ah_hit* __restrict__ st,
                                                    const u64* __restrict__ n_dev, KeyBits kb,
                                                    u64* __restrict__ keys, u32* __restrict__ idx,
-                                                   u32* __restrict__ hist) {
+                                                   u32* __restrict__ hist, u32* __restrict__ hist_zero,
+                                                   u32 hs) {
   __shared__ u32 h[1u << D];
   const u64 n = *n_dev;
   u64 chunk;
   if (blockIdx.x >= sort_chunks(n, chunk)) return;
-  for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x) h[d] = 0;
+  for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x) {
+    h[d] = 0;
+    hist_zero[(u64)d * hs + blockIdx.x] = 0;  // pass 0 counts pass 1's digits there
+  }
   __syncthreads();
   const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   for (u64 i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
@@ -254,43 +258,22 @@ __global__ __launch_bounds__(kBlock) void k_keygen(const ah_hit* __restrict__ st
     }
   }
   __syncthreads();
-  store_hist<D>(h, hist);
-}
-
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_sort_hist(const u64* __restrict__ keys,
-                                                      const u64* __restrict__ n_dev, int shift,
-                                                      u32* __restrict__ hist) {
-  __shared__ u32 h[1u << D];
-  const u64 n = *n_dev;
-  u64 chunk;
-  if (blockIdx.x >= sort_chunks(n, chunk)) return;
-  for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x) h[d] = 0;
-  __syncthreads();
-  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
-  // four keys per thread in flight at once
-  for (u64 i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
-    u64 k[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const u64 i = i0 + (u64)q * blockDim.x;
-      k[q] = i < end ? keys[i] : 0;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (i0 + (u64)q * blockDim.x < end) atomicAdd(&h[(k[q] >> shift) & ((1u << D) - 1u)], 1u);
-  }
-  __syncthreads();
-  store_hist<D>(h, hist);
+  store_hist<D>(h, hist, hs);
 }
 
 // Stable scatter: items keep their order within a digit (chunk, then round,
 // then wave, then lane).  With `out` set (last pass) the records themselves
-// are written in sorted order instead of keys and indices.
+// are written in sorted order instead of keys and indices.  Otherwise each
+// item also counts its next digit into `hist_next`, in the column of the
+// chunk its new position falls in (the next pass's histograms, with no
+// histogram launch), and the workgroup zeroes its own column of
+// `hist_clear`, which the pass after next counts into (the previous pass
+// read it and has finished).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(
     const u64* __restrict__ kin, const u32* __restrict__ iin, u64* __restrict__ kout,
     u32* __restrict__ iout, const u64* __restrict__ n_dev, int shift, const u32* __restrict__ hist,
+    u32* __restrict__ hist_next, u32* __restrict__ hist_clear, u32 hs,
     const ah_hit* __restrict__ staged, ah_hit* __restrict__ out) {
   constexpr u32 NB = 1u << D, R = NB / kBlock;  // digits, digits per thread
   __shared__ u64 run[NB];
@@ -306,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
     u64 tot[R], before[R];
 #pragma unroll
     for (u32 e = 0; e < R; ++e) {
-      const uint4* row = (const uint4*)(hist + (u64)(R * threadIdx.x + e) * kSortGrid);
+      const uint4* row = (const uint4*)(hist + (u64)(R * threadIdx.x + e) * hs);
       tot[e] = 0;
       before[e] = 0;
 #pragma unroll 16
@@ -333,6 +316,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
       at += tot[e];
     }
   }
+  if (hist_clear)
+    for (u32 d = threadIdx.x; d < NB; d += blockDim.x) hist_clear[(u64)d * hs + blockIdx.x] = 0;
   const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   u64 pk[4];
@@ -389,6 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
       } else {
         kout[dst] = key;
         iout[dst] = id;
+        if (hist_next)
+          atomicAdd(&hist_next[(u64)((key >> (shift + D)) & (NB - 1u)) * hs + dst / chunk], 1u);
       }
     }
     __syncthreads();
@@ -1216,15 +1203,19 @@ template <int D>
 void sort_passes(const ah_hit* staged, ah_hit* out, const u64* n_dev, KeyBits kb,
                  const SortBuffers& sb, hipStream_t st) {
   const int bits = kb.total();
-  k_keygen<D><<<kSortGrid, kBlock, 0, st>>>(staged, n_dev, kb, (u64*)sb.keys[0], sb.idx[0], sb.hist);
+  const int passes = (bits + D - 1) / D;
+  // three histogram tables in rotation: pass p reads H[p % 3], counts pass
+  // p + 1's digits into H[(p + 1) % 3] and clears H[(p + 2) % 3]
+  k_keygen<D><<<kSortGrid, kBlock, 0, st>>>(staged, n_dev, kb, (u64*)sb.keys[0], sb.idx[0], sb.hist[0],
+                                            sb.hist[1], sb.hstride);
   int cur = 0;
-  for (int shift = 0; shift < bits; shift += D) {
-    if (shift > 0)
-      k_sort_hist<D><<<kSortGrid, kBlock, 0, st>>>((const u64*)sb.keys[cur], n_dev, shift, sb.hist);
-    const bool last = shift + D >= bits;
+  for (int p = 0; p < passes; ++p) {
+    const bool last = p + 1 == passes;
+    u32* next = last ? nullptr : sb.hist[(p + 1) % 3];
+    u32* clear = p + 2 < passes ? sb.hist[(p + 2) % 3] : nullptr;
     k_sort_scatter<D><<<kSortGrid, kBlock, 0, st>>>(
-        (const u64*)sb.keys[cur], sb.idx[cur], (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1], n_dev, shift,
-        sb.hist, staged, last ? out : nullptr);
+        (const u64*)sb.keys[cur], sb.idx[cur], (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1], n_dev, p * D,
+        sb.hist[p % 3], next, clear, sb.hstride, staged, last ? out : nullptr);
     cur ^= 1;
   }
 }
