@@ -1198,6 +1198,7 @@ ah::PairBuffers carve_pair(Carver& c, uint64_t cap) {
   b.cnt = c.take<uint32_t>(m);
   b.pre_f = c.take<uint32_t>(m);
   b.pre_r = c.take<uint32_t>(m);
+  b.rng = c.take<uint32_t>(8 * m);
   return b;
 }
 

@@ -91,6 +91,7 @@ struct PairBuffers {
   uint32_t* cnt;        // [cap] amplicons started by each leader + site
   uint32_t* pre_f;      // [cap] fwd-list minus sites before each hit (search hint)
   uint32_t* pre_r;      // [cap] rev-list
+  uint32_t* rng;        // [cap x 8] a leader's minus-site ranges (count -> write)
 };
 hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,

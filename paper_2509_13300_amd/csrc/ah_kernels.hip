@@ -557,7 +557,8 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
 // offsets from the previous kernel's per-chunk totals itself.
 //   mark:    kept minus sites of the fwd and rev primer per chunk;
 //   compact: the minus sites into two lists ordered like the hits;
-//   count:   amplicons started by each leader + site, and per chunk;
+//   count:   amplicons started by each leader + site (their minus-site
+//            ranges kept for the writer), and per chunk;
 //   write:   the amplicons at their offsets, and the result.
 constexpr u64 kPairChunkMin = kBlock;
 
@@ -756,7 +757,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_count(
     const PairTab* __restrict__ tabs, const u64* __restrict__ kf, const u32* __restrict__ pf,
     const u64* __restrict__ kr, const u32* __restrict__ pr, const u32* __restrict__ pre_f,
     const u32* __restrict__ pre_r, const u64* __restrict__ mtot, u32* __restrict__ cnt,
-    u64* __restrict__ cc) {
+    u64* __restrict__ cc, uint4* __restrict__ rng) {
   __shared__ u64 lds4[4];
   const u64 n = pair_n(nhits, hcap);
   u64 chunk;
@@ -774,6 +775,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_count(
       const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t, pre_f[i]);
       const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t, pre_r[i]);
       c += (rf.end - rf.beg) + (rr.end - rr.beg);
+      // the ranges, for the writer (list indices < cap < 2^32)
+      rng[2 * i + q] = make_uint4((u32)rf.beg, (u32)rf.end, (u32)rr.beg, (u32)rr.end);
     }
     cnt[i] = (u32)c;
     sum += c;
@@ -786,9 +789,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
     const ah_hit* __restrict__ hits, const ah_result* __restrict__ nhits, u64 hcap,
     const PairTab* __restrict__ tabs, const u64* __restrict__ kf, const u32* __restrict__ pf,
     const u32* __restrict__ xf, const u64* __restrict__ kr, const u32* __restrict__ pr,
-    const u32* __restrict__ xr, const u32* __restrict__ pre_f, const u32* __restrict__ pre_r,
-    const u64* __restrict__ mtot, const u32* __restrict__ cnt, const u64* __restrict__ cc,
-    ah_amplicon* __restrict__ amp, u64 cap, ah_result* __restrict__ res) {
+    const u32* __restrict__ xr, const uint4* __restrict__ rng, const u32* __restrict__ cnt,
+    const u64* __restrict__ cc, ah_amplicon* __restrict__ amp, u64 cap,
+    ah_result* __restrict__ res) {
   __shared__ u64 lds4[4];
   const u64 n = pair_n(nhits, hcap);
   u64 chunk;
@@ -802,7 +805,6 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
     res->status = total > cap ? AH_ERR_OVERFLOW : AH_OK;
     res->reserved = 0;
   }
-  const u64 mf = mtot[0], mr = mtot[1];
   const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   for (u64 rb = beg; rb < end; rb += blockDim.x) {
     const u64 i = rb + threadIdx.x;
@@ -823,10 +825,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
     int nl = 0;
     for (int q = 0; q < ng; ++q) {
       const PairTab t = tabs[a[q].pair];
-      const u64 key = ((u64)a[q].pair << 32) | a[q].genome;
       const u32 ap = a[q].strand_primer & 1u;
-      const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t, pre_f[i]);
-      const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t, pre_r[i]);
+      const uint4 g4 = rng[2 * i + q];  // the counting kernel's ranges
+      const Range rf{g4.x, g4.y}, rr{g4.z, g4.w};
       r[nl] = rf; lb[nl] = t.lf; P[nl] = pf; X[nl] = xf; plus_idx[nl] = (u32)(i + q);
       orient[nl] = ap ? (u32)AH_RF : (u32)AH_FF; ++nl;
       r[nl] = rr; lb[nl] = t.lr; P[nl] = pr; X[nl] = xr; plus_idx[nl] = (u32)(i + q);
@@ -1248,11 +1249,11 @@ hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_
   k_pair_count<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.mkey_f,
                                             pb.mpos_f, (const u64*)pb.mkey_r, pb.mpos_r,
                                             pb.pre_f, pb.pre_r, (const u64*)pb.mtot, pb.cnt,
-                                            (u64*)pb.cc);
+                                            (u64*)pb.cc, (uint4*)pb.rng);
   k_pair_write<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.mkey_f,
                                             pb.mpos_f, pb.midx_f, (const u64*)pb.mkey_r, pb.mpos_r,
-                                            pb.midx_r, pb.pre_f, pb.pre_r, (const u64*)pb.mtot,
-                                            pb.cnt, (const u64*)pb.cc, amp, cap, res);
+                                            pb.midx_r, (const uint4*)pb.rng, pb.cnt,
+                                            (const u64*)pb.cc, amp, cap, res);
   return hipGetLastError();
 }
 
