@@ -283,6 +283,29 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
   u64 chunk;
   const u32 G = sort_chunks(n, chunk);
   if (blockIdx.x >= G) return;
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  u64 pk[4];
+  u32 pi[4];
+  ah_hit ph[4];
+  // the keys (and, in the last pass, the records) of four rounds are loaded
+  // together, one round's latency; the first four are in flight while the
+  // counts are read
+  auto load4 = [&](u64 base) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u64 j = base + (u64)q * blockDim.x + threadIdx.x;
+      pk[q] = j < end ? kin[j] : 0;
+      pi[q] = j < end ? iin[j] : 0u;
+    }
+    if (out) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const u64 j = base + (u64)q * blockDim.x + threadIdx.x;
+        if (j < end) ph[q] = staged[pi[q]];
+      }
+    }
+  };
+  load4(beg);
   // this chunk's first slot per digit: records of smaller digits, then those
   // of the same digit in earlier chunks (thread t owns digits R t .. R t + R - 1)
   {
@@ -318,30 +341,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
   }
   if (hist_clear)
     for (u32 d = threadIdx.x; d < NB; d += blockDim.x) hist_clear[(u64)d * hs + blockIdx.x] = 0;
-  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  u64 pk[4];
-  u32 pi[4];
-  ah_hit ph[4];
   for (u64 base = beg; base < end; base += blockDim.x) {
-    // the keys (and, in the last pass, the records) of four rounds are
-    // loaded together: one round's latency
     const int r = (int)(((base - beg) / blockDim.x) & 3u);
-    if (r == 0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const u64 j = base + (u64)q * blockDim.x + threadIdx.x;
-        pk[q] = j < end ? kin[j] : 0;
-        pi[q] = j < end ? iin[j] : 0u;
-      }
-      if (out) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const u64 j = base + (u64)q * blockDim.x + threadIdx.x;
-          if (j < end) ph[q] = staged[pi[q]];
-        }
-      }
-    }
+    if (r == 0 && base != beg) load4(base);
     for (int q = 0; q < 4; ++q)
       for (u32 d = threadIdx.x; d < NB; d += blockDim.x) wcnt[q][d] = 0;
     __syncthreads();
@@ -633,22 +636,31 @@ __global__ __launch_bounds__(kBlock) void k_pair_compact(
   u64 chunk;
   const u32 G = pair_chunks(n, chunk);
   if (blockIdx.x >= (G ? G : 1u)) return;  // workgroup 0 runs even for no hits
-  u64 tf, tr;
-  u64 bf = chunk_prefix(cf, G, blockIdx.x, lds4, &tf);
-  u64 br = chunk_prefix(cr, G, blockIdx.x, lds4, &tr);
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  // the first round's records and both lists' chunk counts, loaded together
+  ah_hit h{};
+  if (beg + threadIdx.x < end) h = hits[beg + threadIdx.x];
+  u64 bf = 0, tf = 0, br = 0, tr = 0;
+  for (u32 w = threadIdx.x; w < G; w += blockDim.x) {
+    const u64 vf = cf[w], vr = cr[w];
+    tf += vf;
+    tr += vr;
+    bf += w < blockIdx.x ? vf : 0u;
+    br += w < blockIdx.x ? vr : 0u;
+  }
+  bf = block_sum(bf, lds4);
+  br = block_sum(br, lds4);
+  tf = block_sum(tf, lds4);
+  tr = block_sum(tr, lds4);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     mtot[0] = tf;
     mtot[1] = tr;
   }
-  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   for (u64 base = beg; base < end; base += blockDim.x) {
     const u64 i = base + threadIdx.x;
-    ah_hit h{};
     u32 k = 0;
-    if (i < end) {
-      h = hits[i];
-      k = minus_kind(h, tabs);
-    }
+    if (base != beg) h = i < end ? hits[i] : ah_hit{};
+    if (i < end) k = minus_kind(h, tabs);
     u64 sf, sr;
     const u64 ef = block_exclusive_scan(k & 1u, lds4, sf);
     const u64 er = block_exclusive_scan(k >> 1, lds4, sr);
@@ -737,18 +749,24 @@ __device__ __forceinline__ bool same_site(const ah_hit& a, const ah_hit& b) {
 
 // A leader is the first kept + site of its (pair, genome, pos) group; it owns
 // every amplicon that starts there (the fwd and rev + sites of that pos).
-__device__ __forceinline__ int group_of(const ah_hit* hits, u64 n, u64 i, const PairTab* tabs,
+// Hit i and its neighbours (i itself stands in for a missing one), loaded
+// unconditionally so that the three loads are in flight together.
+struct Nbr {
+  ah_hit prev, cur, next;
+};
+
+__device__ __forceinline__ Nbr load_nbr(const ah_hit* hits, u64 n, u64 i) {
+  return Nbr{hits[i > 0 ? i - 1 : i], hits[i], hits[i + 1 < n ? i + 1 : i]};
+}
+
+// Sites of the group hit i leads: 0 (not a leader), 1 or 2 (a[0], a[1]).
+__device__ __forceinline__ int group_of(const Nbr& b, u64 n, u64 i, const PairTab* tabs,
                                         ah_hit& a0, ah_hit& a1) {
-  a0 = hits[i];
+  a0 = b.cur;
+  a1 = b.next;
   if (!plus_kept(a0, tabs)) return 0;
-  if (i > 0) {
-    const ah_hit p = hits[i - 1];
-    if (plus_kept(p, tabs) && same_site(p, a0)) return 0;
-  }
-  if (i + 1 < n) {
-    a1 = hits[i + 1];
-    if (plus_kept(a1, tabs) && same_site(a1, a0)) return 2;
-  }
+  if (i > 0 && plus_kept(b.prev, tabs) && same_site(b.prev, a0)) return 0;
+  if (i + 1 < n && plus_kept(a1, tabs) && same_site(a1, a0)) return 2;
   return 1;
 }
 
@@ -766,14 +784,15 @@ __global__ __launch_bounds__(kBlock) void k_pair_count(
   const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   u64 sum = 0;
   for (u64 i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const u32 hf = pre_f[i], hr = pre_r[i];  // in flight with the records
     ah_hit a[2];
-    const int ng = group_of(hits, n, i, tabs, a[0], a[1]);
+    const int ng = group_of(load_nbr(hits, n, i), n, i, tabs, a[0], a[1]);
     u64 c = 0;
     for (int q = 0; q < ng; ++q) {
       const PairTab t = tabs[a[q].pair];
       const u64 key = ((u64)a[q].pair << 32) | a[q].genome;
-      const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t, pre_f[i]);
-      const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t, pre_r[i]);
+      const Range rf = minus_range(kf, pf, mf, key, a[q].pos, t.lf, t, hf);
+      const Range rr = minus_range(kr, pr, mr, key, a[q].pos, t.lr, t, hr);
       c += (rf.end - rf.beg) + (rr.end - rr.beg);
       // the ranges, for the writer (list indices < cap < 2^32)
       rng[2 * i + q] = make_uint4((u32)rf.beg, (u32)rf.end, (u32)rr.beg, (u32)rr.end);
@@ -797,6 +816,23 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
   u64 chunk;
   const u32 G = pair_chunks(n, chunk);
   if (blockIdx.x >= (G ? G : 1u)) return;  // workgroup 0 writes the result even for no hits
+  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  // a round's counts, records and ranges; the first round's are in flight
+  // with the chunk counts
+  u32 ci = 0;
+  Nbr nb;
+  uint4 g2[2];
+  auto load = [&](u64 rb) {
+    const u64 i = rb + threadIdx.x;
+    ci = 0;
+    if (i < end) {
+      ci = cnt[i];
+      nb = load_nbr(hits, n, i);
+      g2[0] = rng[2 * i];
+      g2[1] = rng[2 * i + 1];
+    }
+  };
+  if (beg < end) load(beg);
   u64 total;
   u64 run = chunk_prefix(cc, G, blockIdx.x, lds4, &total);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -805,16 +841,15 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
     res->status = total > cap ? AH_ERR_OVERFLOW : AH_OK;
     res->reserved = 0;
   }
-  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
   for (u64 rb = beg; rb < end; rb += blockDim.x) {
     const u64 i = rb + threadIdx.x;
-    const u32 ci = i < end ? cnt[i] : 0u;
+    if (rb != beg) load(rb);
     u64 rt;
     const u64 base = run + block_exclusive_scan(ci, lds4, rt);
     run += rt;
     if (ci == 0) continue;
     ah_hit a[2];
-    const int ng = group_of(hits, n, i, tabs, a[0], a[1]);
+    const int ng = group_of(nb, n, i, tabs, a[0], a[1]);
     if (ng == 0) continue;
     if (base >= cap) continue;
     // up to four lists, each ordered by end: (a primer, b primer)
@@ -826,7 +861,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
     for (int q = 0; q < ng; ++q) {
       const PairTab t = tabs[a[q].pair];
       const u32 ap = a[q].strand_primer & 1u;
-      const uint4 g4 = rng[2 * i + q];  // the counting kernel's ranges
+      const uint4 g4 = g2[q];  // the counting kernel's ranges
       const Range rf{g4.x, g4.y}, rr{g4.z, g4.w};
       r[nl] = rf; lb[nl] = t.lf; P[nl] = pf; X[nl] = xf; plus_idx[nl] = (u32)(i + q);
       orient[nl] = ap ? (u32)AH_RF : (u32)AH_FF; ++nl;
