@@ -127,6 +127,21 @@ def test_scan_tm_pair_random(dev, seed):
     check_case(p, [pr], dev)
 
 
+@pytest.mark.parametrize("k,L,clamp", [(6, 24, 3), (10, 32, 0), (15, 32, 5), (15, 20, 0),
+                                         (12, 16, 2)])
+def test_large_k_up_to_the_maximum(dev, k, L, clamp):
+    """k up to AH_MAX_K and primers up to the 32-base maximum: weak or no
+    filter, dense sites at k close to L, Tm of sites that are mostly
+    mismatches (far below zero)."""
+    fwd = plan.random_primer(900 + k + L, 0, L, "RYN")
+    rev = plan.random_primer(900 + k + L, 1, L, "SW")
+    pr = plan.PairSpec(fwd, rev, k=k, clamp=clamp, min_len=2 * L, max_len=2 * L + 100)
+    p = plan.tiny(910 + k + L, n_genomes=4, len_lo=800, len_hi=3000, pair=pr, n_copies=(1, 2))
+    say("large k", k, L, clamp, fwd, rev, p.lengths.tolist())
+    gh, _ = check_case(p, [pr], dev, hit_cap=1 << 20, amp_cap=1 << 22)
+    assert gh.size > 0
+
+
 def test_low_complexity_dense_hits_and_all_orientations(dev):
     """A tiny alphabet makes hits dense: many records per tile, all four
     orientations, ties in amplicon ends."""
