@@ -21,6 +21,31 @@ Model (float64 throughout):
   [Na+] in mol/L, N the primer length, and the sodium equivalent of von
   Ahsen et al. (2001): Na + K + Tris/2 + 120 sqrt(Mg - dNTPs) mM (the Mg term
   is zero when Mg <= dNTPs).  Method 0: no correction.
+* The other methods correct the 1 M temperature Tm1 (no salt term in
+  Delta-S), with the same sodium equivalent [Na+] (mol/L) for 1-4 and 6:
+    1 Schildkraut & Lifson (1965): Tm1 + 16.6 log10[Na+]
+    2 Wetmur (1991):               Tm1 + 16.6 log10([Na+] / (1 + 0.7 [Na+]))
+    3 SantaLucia et al. (1996):    Tm1 + 12.5 log10[Na+]
+    4 SantaLucia (1998):           Tm1 + 11.7 log10[Na+]
+    6 Owczarzy et al. (2004), on 1/T in kelvin:
+        1/T = 1/T1 + (4.29 fGC - 3.95) 1e-5 ln[Na+] + 9.40e-6 ln^2[Na+]
+    7 Owczarzy et al. (2008), magnesium: with the monovalent ions
+      [Mon] = Na + K + Tris/2 and the free magnesium [Mg] left by 1:1 binding
+      to dNTPs (association constant 3e4 per M), R = sqrt[Mg] / [Mon]:
+      R < 0.22 (or no Mg): method 6 on [Mon];  otherwise
+        1/T = 1/T1 + a + b ln[Mg] + fGC (c + d ln[Mg])
+              + (e + f ln[Mg] + g ln^2[Mg]) / (2 (N - 1))
+      with a 3.92e-5, b -9.11e-6, c 6.26e-5, d 1.42e-5, e -4.82e-4,
+      f 5.25e-4, g 8.31e-5; for R < 6, a, d, g are scaled by
+      0.843 - 0.352 sqrt[Mon] ln[Mon],
+      1.279 - 4.03e-3 ln[Mon] - 8.03e-3 ln^2[Mon] and
+      0.486 - 0.258 ln[Mon] + 5.25e-3 ln^3[Mon].
+  fGC is the G+C fraction of the oligo over its N positions (R27); methods
+  6 and 7 therefore differ between oligos that pair the site alike, and the
+  maximum runs over the oligos themselves.  The constants of methods 1-4, 6
+  and 7 are the published ones as restated here: parity unpinned against
+  the publications (not available here); the tests pin the reductions
+  (1 M monovalent, no magnesium) and the oligo-level maximum.
 * C = (max(dnac1, dnac2) - min(dnac1, dnac2) / 2) * 1e-9 M otherwise.
 * Tm = 1000 Delta-H / (Delta-S + R ln C) - 273.15 with R = 1.987.
 
@@ -37,6 +62,8 @@ Readings:
       perfect duplex this is exactly the closed form above.  Parity against the
       paper's tool for mismatched duplexes: unpinned.
   R20 only the maximum is part of the result.
+  R27 for the salt methods that depend on G+C content (6, 7), fGC is the
+      G+C fraction of the oligo over all its positions, paired or not.
 Template base opposite oligo position j: the complement of the top-strand base
 at pos + j for a + site, the top-strand base at pos + L - 1 - j for a - site.
 """
@@ -94,15 +121,86 @@ def sodium_equivalent(p: TmParams) -> float:
     return p.Na + p.K + p.Tris / 2.0 + (120.0 * math.sqrt(mg) if mg > 0 else 0.0)
 
 
-def salt_entropy(p: TmParams, length: int) -> float:
-    if p.saltcorr == 0:
-        return 0.0
-    if p.saltcorr != 5:
-        raise ValueError("salt correction method must be 0 or 5")
-    na = sodium_equivalent(p)
-    if na <= 0:
+SALT_METHODS = (0, 1, 2, 3, 4, 5, 6, 7)
+
+
+def _check_method(p: TmParams) -> None:
+    if p.saltcorr not in SALT_METHODS:
+        raise ValueError("salt correction method must be one of 0-7")
+    if p.saltcorr in (1, 2, 3, 4, 5, 6) and not sodium_equivalent(p) > 0:
         raise ValueError("salt correction needs a positive sodium equivalent")
-    return 0.368 * (length - 1) * math.log(na / 1000.0)
+    if p.saltcorr == 7 and not (monovalent(p) > 0 or free_magnesium(p) > 0):
+        raise ValueError("salt correction 7 needs monovalent ions or free magnesium")
+
+
+def salt_entropy(p: TmParams, length: int) -> float:
+    """Method 5's entropy term (zero for every other method)."""
+    _check_method(p)
+    if p.saltcorr != 5:
+        return 0.0
+    return 0.368 * (length - 1) * math.log(sodium_equivalent(p) / 1000.0)
+
+
+def monovalent(p: TmParams) -> float:
+    """[Mon] of method 7, mM."""
+    return p.Na + p.K + p.Tris / 2.0
+
+
+def free_magnesium(p: TmParams) -> float:
+    """Mg not bound by dNTPs (1:1 complexes, association constant 3e4 / M), mM."""
+    mg, d = p.Mg * 1e-3, p.dNTPs * 1e-3
+    if mg <= 0:
+        return 0.0
+    if d <= 0:
+        return p.Mg
+    ka = 3e4
+    b = ka * (d - mg) + 1.0
+    return 1e3 * (-b + math.sqrt(b * b + 4.0 * ka * mg)) / (2.0 * ka)
+
+
+def salt_shift(p: TmParams) -> float:
+    """Methods 1-4: the shift of Tm in degrees (zero for the others)."""
+    _check_method(p)
+    if p.saltcorr not in (1, 2, 3, 4):
+        return 0.0
+    na = sodium_equivalent(p) / 1000.0
+    if p.saltcorr == 1:
+        return 16.6 * math.log10(na)
+    if p.saltcorr == 2:
+        return 16.6 * math.log10(na / (1.0 + 0.7 * na))
+    if p.saltcorr == 3:
+        return 12.5 * math.log10(na)
+    return 11.7 * math.log10(na)
+
+
+def reciprocal_terms(p: TmParams, length: int):
+    """Methods 6 and 7: (A, B) with 1/T = 1/T1 + A + B fGC; None otherwise."""
+    _check_method(p)
+    if p.saltcorr not in (6, 7):
+        return None
+
+    def owczarzy2004(na_molar):
+        ln = math.log(na_molar)
+        return -3.95e-5 * ln + 9.40e-6 * ln * ln, 4.29e-5 * ln
+
+    if p.saltcorr == 6:
+        return owczarzy2004(sodium_equivalent(p) / 1000.0)
+    mon = monovalent(p) / 1000.0
+    mg = free_magnesium(p) / 1000.0
+    if mg <= 0:
+        return owczarzy2004(mon)
+    ratio = math.sqrt(mg) / mon if mon > 0 else math.inf
+    if ratio < 0.22:
+        return owczarzy2004(mon)
+    a, b, c, d, e, f, g = 3.92e-5, -9.11e-6, 6.26e-5, 1.42e-5, -4.82e-4, 5.25e-4, 8.31e-5
+    if ratio < 6.0:
+        lm = math.log(mon)
+        a *= 0.843 - 0.352 * math.sqrt(mon) * lm
+        d *= 1.279 - 4.03e-3 * lm - 8.03e-3 * lm * lm
+        g *= 0.486 - 0.258 * lm + 5.25e-3 * lm ** 3
+    lg = math.log(mg)
+    A = a + b * lg + (e + f * lg + g * lg * lg) / (2.0 * (length - 1))
+    return A, c + d * lg
 
 
 def concentration(p: TmParams) -> float:
@@ -133,18 +231,32 @@ def duplex_terms(oligo: np.ndarray, paired: np.ndarray):
     return dh, ds
 
 
-def tm_from_terms(dh, ds, length: int, p: TmParams):
+def tm_from_terms(dh, ds, length: int, p: TmParams, gc=None):
+    """Tm in degrees; ``gc``: the oligos' G+C counts (methods 6 and 7)."""
     ds = np.asarray(ds, dtype=np.float64) + salt_entropy(p, length)
     if p.selfcomp:
         ds = ds + SYM_DS
-    return 1000.0 * np.asarray(dh, dtype=np.float64) / (ds + R_GAS * math.log(concentration(p))) - 273.15
+    t = 1000.0 * np.asarray(dh, dtype=np.float64) / (ds + R_GAS * math.log(concentration(p))) - 273.15
+    rt = reciprocal_terms(p, length)
+    if rt is not None:
+        if gc is None:
+            raise ValueError("salt methods 6 and 7 need the oligos' G+C counts")
+        f_gc = np.asarray(gc, dtype=np.float64) / length
+        t = 1.0 / (1.0 / (t + 273.15) + rt[0] + rt[1] * f_gc) - 273.15
+    return t + salt_shift(p)
+
+
+def gc_count(oligo: np.ndarray) -> np.ndarray:
+    """G+C bases of each oligo (rows of codes)."""
+    o = np.atleast_2d(oligo)
+    return ((o == 1) | (o == 2)).sum(axis=1)
 
 
 def tm_perfect(oligo: str, p: TmParams = TmParams()) -> float:
     """Tm of an ACGT oligo with its exact complement."""
     o = codes(oligo)
     dh, ds = duplex_terms(o, np.ones((1, o.size), bool))
-    return float(tm_from_terms(dh, ds, o.size, p)[0])
+    return float(tm_from_terms(dh, ds, o.size, p, gc_count(o))[0])
 
 
 def tm_duplex(oligo: str, template_opposite: str, p: TmParams = TmParams()) -> float:
@@ -155,7 +267,7 @@ def tm_duplex(oligo: str, template_opposite: str, p: TmParams = TmParams()) -> f
     t = codes(template_opposite)
     paired = (t < 4) & (o == (3 - t))
     dh, ds = duplex_terms(o, paired[None, :])
-    return float(tm_from_terms(dh, ds, o.size, p)[0])
+    return float(tm_from_terms(dh, ds, o.size, p, gc_count(o))[0])
 
 
 def _expansion_codes(primer: str) -> np.ndarray:
@@ -188,7 +300,7 @@ def site_tm(genome_codes: np.ndarray, pos: int, primer: str, strand: int, k: int
     if not ok.any():
         return float("nan")
     dh, ds = duplex_terms(olig[ok], paired[ok])
-    return float(tm_from_terms(dh, ds, L, p).max())
+    return float(tm_from_terms(dh, ds, L, p, gc_count(olig[ok])).max())
 
 
 def fill_tm(hits: np.ndarray, seqs, pairs, p: TmParams = TmParams()) -> np.ndarray:

@@ -135,8 +135,21 @@ def brute_site_tm(g, pos, primer, strand, k, clamp, p):
     return best
 
 
-@pytest.mark.parametrize("seed", range(10))
-def test_site_tm_is_the_maximum_over_compatible_oligos(seed):
+# the default conditions (method 5), every other salt method, and method 7 in
+# each of its regimes (R = sqrt[Mg] / [Mon]
+# in the middle, >= 6, < 0.22, with dNTPs, without monovalent ions)
+SALT_CASES = [dict()] + [dict(saltcorr=m) for m in (0, 1, 2, 3, 4, 6, 7)] + [
+    dict(saltcorr=7, Na=10.0, Mg=10.0), dict(saltcorr=7, Na=200.0, Mg=0.5),
+    dict(saltcorr=7, Na=50.0, Mg=3.0, dNTPs=0.8), dict(saltcorr=7, Na=0.0, Mg=2.0)]
+
+
+# ten seeds under the default conditions, three under every other salt case
+MAX_CASES = [(seed, 0) for seed in range(10)] + [
+    (seed, case) for case in range(1, len(SALT_CASES)) for seed in range(3)]
+
+
+@pytest.mark.parametrize("seed,case", MAX_CASES)
+def test_site_tm_is_the_maximum_over_compatible_oligos(seed, case):
     rs = np.random.RandomState(100 + seed)
     L = rs.randint(8, 16)
     primer = list("".join(rs.choice(list("ACGT"), size=L)))
@@ -150,9 +163,90 @@ def test_site_tm_is_the_maximum_over_compatible_oligos(seed):
     g = g[:100] + o + g[100 + L:200] + iupac.revcomp_plain(o) + g[200 + L:]
     c = scan.codes(g)
     h = scan.scan_sequence(g, primer, primer, k, clamp)
-    p = tm.TmParams()
+    p = tm.TmParams(**SALT_CASES[case])
     assert h.size >= 2
     for r in h:
         got = tm.site_tm(c, int(r["pos"]), primer, int(r["strand"]), k, clamp, p)
         want = brute_site_tm(g, int(r["pos"]), primer, int(r["strand"]), k, clamp, p)
         assert got == pytest.approx(want, abs=1e-9)
+
+
+OLIGOS = ["AGCTTGCAAGGCTTACCGTA", "GGGCCCGCGGCCGC", "ATATTAATTATAAATTA", "CAGTCAGTCAGT"]
+
+
+def test_salt_methods_reduce_to_the_one_molar_reference():
+    # 1 M monovalent ions and no magnesium is the reference state the methods
+    # correct from: methods 1, 3, 4, 5, 6 and 7 leave Tm unchanged there
+    for o in OLIGOS:
+        t0 = tm.tm_perfect(o, tm.TmParams(Na=1000.0, Mg=0.0, saltcorr=0))
+        for m in (1, 3, 4, 5, 6, 7):
+            t = tm.tm_perfect(o, tm.TmParams(Na=1000.0, Mg=0.0, saltcorr=m))
+            assert t == pytest.approx(t0, abs=1e-9), m
+        # Wetmur's form keeps a term at 1 M but tends to Schildkraut-Lifson
+        # at low salt
+        a = tm.tm_perfect(o, tm.TmParams(Na=1000.0, Mg=0.0, saltcorr=2))
+        assert abs(a - t0) > 1.0
+        lo1 = tm.tm_perfect(o, tm.TmParams(Na=1e-3, Mg=0.0, saltcorr=1))
+        lo2 = tm.tm_perfect(o, tm.TmParams(Na=1e-3, Mg=0.0, saltcorr=2))
+        assert abs(lo1 - lo2) < 1e-4
+
+
+def test_methods_1_to_4_shift_every_oligo_alike():
+    for m in (1, 2, 3, 4):
+        p = tm.TmParams(Na=30.0, K=5.0, Mg=1.0, saltcorr=m)
+        p0 = tm.TmParams(Na=30.0, K=5.0, Mg=1.0, saltcorr=0)
+        d = [tm.tm_perfect(o, p) - tm.tm_perfect(o, p0) for o in OLIGOS]
+        assert max(d) - min(d) < 1e-9 and d[0] < 0  # below 1 M: lower Tm
+
+
+def test_method_7_without_magnesium_is_method_6_on_the_monovalent_ions():
+    for kw in (dict(Na=50.0, K=10.0, Tris=20.0), dict(Na=150.0), dict(Na=5.0, K=1.0)):
+        for o in OLIGOS:
+            t7 = tm.tm_perfect(o, tm.TmParams(Mg=0.0, saltcorr=7, **kw))
+            t6 = tm.tm_perfect(o, tm.TmParams(Mg=0.0, saltcorr=6, **kw))
+            assert t7 == pytest.approx(t6, abs=1e-9)
+    # and at R < 0.22 the magnesium is ignored
+    o = OLIGOS[0]
+    a = tm.tm_perfect(o, tm.TmParams(Na=200.0, Mg=0.5, saltcorr=7))
+    b = tm.tm_perfect(o, tm.TmParams(Na=200.0, Mg=0.0, saltcorr=7))
+    assert a == pytest.approx(b, abs=1e-9)
+    c = tm.tm_perfect(o, tm.TmParams(Na=50.0, Mg=1.5, saltcorr=7))
+    d = tm.tm_perfect(o, tm.TmParams(Na=50.0, Mg=0.0, saltcorr=7))
+    assert abs(c - d) > 0.1
+
+
+def test_free_magnesium_satisfies_mass_action():
+    for mg, dn in [(1.5, 0.8), (3.0, 3.0), (2.0, 10.0), (0.5, 0.1), (10.0, 0.2)]:
+        x = tm.free_magnesium(tm.TmParams(Mg=mg, dNTPs=dn)) * 1e-3
+        M, D = mg * 1e-3, dn * 1e-3
+        bound = M - x
+        assert 0 < x <= M and D - bound >= 0
+        # 1:1 complexes: [MgdNTP] = Ka [Mg][dNTP], Ka = 3e4 per M
+        assert bound == pytest.approx(3e4 * x * (D - bound), rel=1e-9)
+    assert tm.free_magnesium(tm.TmParams(Mg=1.5, dNTPs=0.0)) == 1.5
+    assert tm.free_magnesium(tm.TmParams(Mg=0.0, dNTPs=0.8)) == 0.0
+
+
+def test_gc_dependent_methods_favour_gc_at_unpaired_positions():
+    # two oligos that pair the template alike and differ only at a mismatched
+    # position (G against A): equal under methods 0-5; under 6 and 7 below
+    # 1 M the G+C-richer duplex is the more stable
+    opp = "".join(iupac.BASE_COMP[b] for b in "AGCTTGCAAGGCTTACCGTA")
+    o_g = "AGCTTGCAAGGCTGACCGTA"
+    o_a = "AGCTTGCAAGGCTAACCGTA"
+    assert opp[13] == "A"  # opposite the T of the exact complement
+    for m in range(6):
+        p = tm.TmParams(saltcorr=m)
+        assert tm.tm_duplex(o_g, opp, p) == pytest.approx(tm.tm_duplex(o_a, opp, p), abs=1e-9)
+    for m in (6, 7):
+        p = tm.TmParams(saltcorr=m)
+        assert tm.tm_duplex(o_g, opp, p) > tm.tm_duplex(o_a, opp, p) + 1e-3
+
+
+def test_salt_method_arguments_are_checked():
+    with pytest.raises(ValueError):
+        tm.tm_perfect("ACGTACGT", tm.TmParams(saltcorr=8))
+    with pytest.raises(ValueError):
+        tm.tm_perfect("ACGTACGT", tm.TmParams(Na=0.0, Mg=0.0, saltcorr=6))
+    with pytest.raises(ValueError):
+        tm.tm_perfect("ACGTACGT", tm.TmParams(Na=0.0, Mg=0.0, saltcorr=7))
