@@ -198,18 +198,33 @@ size_t ah_scan_workspace_bytes(const ah_genomes* genomes, const ah_primer_pair* 
                                uint32_t n_pairs, uint64_t capacity);
 
 /* ---------------------------------------------------------------------------
- * Melting temperature (Section 2.1, "Melting temperature filtering").
+ * Melting temperature (Section 2.1, "Melting temperature filtering"; the
+ * paper exposes the ion concentrations and the salt-correction method).
  * Nearest-neighbour model: SantaLucia (1998) unified stacks, initiation per
- * duplex end, salt method 5 (entropy term 0.368 (N-1) ln[Na+], sodium
- * equivalent Na + K + Tris/2 + 120 sqrt(Mg - dNTPs) mM) or 0 (none), and
- * C = max(dnac1,dnac2) - min(dnac1,dnac2)/2 (dnac1 if selfcomp).  A stack
- * with a mismatched pair contributes nothing and initiation is taken at the
- * outermost paired positions.  Sums are FP32 with compensation; the salt and
- * logarithm terms are FP64.
+ * duplex end, C = max(dnac1,dnac2) - min(dnac1,dnac2)/2 (dnac1 if selfcomp).
+ * A stack with a mismatched pair contributes nothing and initiation is taken
+ * at the outermost paired positions.  Salt correction (saltcorr), with the
+ * sodium equivalent [Na+] = Na + K + Tris/2 + 120 sqrt(Mg - dNTPs) mM for
+ * methods 1-6:
+ *   0 none;
+ *   1 Schildkraut & Lifson (1965): Tm + 16.6 log10[Na+];
+ *   2 Wetmur (1991): Tm + 16.6 log10([Na+] / (1 + 0.7 [Na+]));
+ *   3 SantaLucia et al. (1996): Tm + 12.5 log10[Na+];
+ *   4 SantaLucia (1998): Tm + 11.7 log10[Na+];
+ *   5 SantaLucia (1998): Delta-S + 0.368 (N-1) ln[Na+]  (the default);
+ *   6 Owczarzy et al. (2004): 1/T + (4.29 fGC - 3.95) 1e-5 ln[Na+]
+ *     + 9.40e-6 ln^2[Na+];
+ *   7 Owczarzy et al. (2008), magnesium, on the monovalent ions
+ *     Na + K + Tris/2 and the Mg left free by dNTPs (1:1, Ka 3e4 per M).
+ * fGC is the oligo's G+C fraction, so under 6 and 7 the maximum runs over
+ * oligos that pair the site alike too (the best member at each unpaired
+ * degenerate position).  Concentrations in M inside the logarithms.  Sums
+ * are FP32 with compensation; the salt and logarithm terms are FP64.
  * ------------------------------------------------------------------------- */
 typedef struct ah_tm_params {
   double dnac1_nM, dnac2_nM, Na_mM, K_mM, Tris_mM, Mg_mM, dNTPs_mM;
-  int32_t saltcorr; /* 0 or 5 */
+  int32_t saltcorr; /* 0-7, see above; AH_ERR_INVALID_ARG otherwise or when the
+                       method's ion concentration is not positive */
   int32_t selfcomp; /* 1: symmetry correction -1.4 cal/(K mol) and C = dnac1 */
 } ah_tm_params;
 

@@ -1280,6 +1280,84 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   return AH_OK;
 }
 
+// Salt correction of the melting temperature, from the ion concentrations.
+// Method 5 is an entropy term; 1-4 shift Tm; 6 (Owczarzy 2004) and 7
+// (Owczarzy 2008, magnesium) add a + b fGC to 1/T, the terms derived here
+// (a = a0 + a_len / (2 (N - 1)) for a primer of N bases).  Methods 1-6 take
+// the sodium equivalent Na + K + Tris/2 + 120 sqrt(Mg - dNTPs) mM; method 7
+// the monovalent ions Na + K + Tris/2 and the magnesium left free by 1:1
+// binding to dNTPs (association constant 3e4 per M).
+struct SaltTerms {
+  bool ok = true;
+  const char* why = "";
+  double ln_na = 0.0;  // ln of the sodium equivalent in M (methods 1-6)
+  double shift = 0.0;  // methods 1-4, degrees
+  bool recip = false;  // methods 6, 7
+  double a0 = 0.0, a_len = 0.0, b = 0.0;
+};
+
+SaltTerms salt_terms(const ah_tm_params& p) {
+  SaltTerms r;
+  const int m = p.saltcorr;
+  if (m == 0) return r;
+  const double mg_excess = p.Mg_mM - p.dNTPs_mM;
+  const double na_eq =
+      p.Na_mM + p.K_mM + p.Tris_mM / 2.0 + (mg_excess > 0 ? 120.0 * std::sqrt(mg_excess) : 0.0);
+  // 1/T terms of Owczarzy et al. (2004) for a monovalent concentration in M
+  auto mono = [&r](double molar) {
+    const double ln = std::log(molar);
+    r.recip = true;
+    r.a0 = -3.95e-5 * ln + 9.40e-6 * ln * ln;
+    r.b = 4.29e-5 * ln;
+  };
+  if (m <= 6) {
+    if (!(na_eq > 0)) {
+      r.ok = false;
+      r.why = "needs a positive sodium equivalent";
+      return r;
+    }
+    const double na = na_eq / 1000.0;
+    r.ln_na = std::log(na);
+    const double l10 = std::log10(na);
+    if (m == 1) r.shift = 16.6 * l10;
+    if (m == 2) r.shift = 16.6 * std::log10(na / (1.0 + 0.7 * na));
+    if (m == 3) r.shift = 12.5 * l10;
+    if (m == 4) r.shift = 11.7 * l10;
+    if (m == 6) mono(na);
+    return r;
+  }
+  const double mon = (p.Na_mM + p.K_mM + p.Tris_mM / 2.0) / 1000.0;
+  double mg = p.Mg_mM > 0 ? p.Mg_mM / 1000.0 : 0.0;
+  const double dn = p.dNTPs_mM / 1000.0;
+  if (mg > 0 && dn > 0) {  // free Mg: Ka x^2 + (Ka (D - M) + 1) x - M = 0
+    const double ka = 3e4, q = ka * (dn - mg) + 1.0;
+    mg = (-q + std::sqrt(q * q + 4.0 * ka * mg)) / (2.0 * ka);
+  }
+  if (!(mon > 0) && !(mg > 0)) {
+    r.ok = false;
+    r.why = "needs monovalent ions or free magnesium";
+    return r;
+  }
+  if (!(mg > 0) || (mon > 0 && std::sqrt(mg) / mon < 0.22)) {
+    mono(mon);
+    return r;
+  }
+  double a = 3.92e-5, b = -9.11e-6, c = 6.26e-5, d = 1.42e-5, e = -4.82e-4, f = 5.25e-4,
+         g = 8.31e-5;
+  if (mon > 0 && std::sqrt(mg) / mon < 6.0) {
+    const double lm = std::log(mon);
+    a *= 0.843 - 0.352 * std::sqrt(mon) * lm;
+    d *= 1.279 - 4.03e-3 * lm - 8.03e-3 * lm * lm;
+    g *= 0.486 - 0.258 * lm + 5.25e-3 * lm * lm * lm;
+  }
+  const double lg = std::log(mg);
+  r.recip = true;
+  r.a0 = a + b * lg;
+  r.a_len = e + f * lg + g * lg * lg;
+  r.b = c + d * lg;
+  return r;
+}
+
 }  // namespace
 
 namespace ah {
@@ -1420,12 +1498,11 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
   PairSet ps;
   s = compile_pairs(pairs, n_pairs, ps);
   if (s) return s;
-  if (p->saltcorr != 0 && p->saltcorr != 5)
-    return fail(AH_ERR_INVALID_ARG, "salt correction method %d (supported: 0, 5)", p->saltcorr);
-  const double mg = p->Mg_mM - p->dNTPs_mM;
-  const double na_eq = p->Na_mM + p->K_mM + p->Tris_mM / 2.0 + (mg > 0 ? 120.0 * std::sqrt(mg) : 0.0);
-  if (p->saltcorr == 5 && !(na_eq > 0))
-    return fail(AH_ERR_INVALID_ARG, "salt correction needs a positive sodium equivalent");
+  if (p->saltcorr < 0 || p->saltcorr > 7)
+    return fail(AH_ERR_INVALID_ARG, "salt correction method %d (supported: 0-7)", p->saltcorr);
+  const SaltTerms salt_t = salt_terms(*p);
+  if (!salt_t.ok)
+    return fail(AH_ERR_INVALID_ARG, "salt correction %d: %s", p->saltcorr, salt_t.why);
   double C;
   if (p->selfcomp) {
     C = p->dnac1_nM * 1e-9;
@@ -1470,8 +1547,14 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
                     (unsigned long long)deg);
       t.deg = deg;
       t.decoy = (ps.flags[q] & AH_PAIR_DECOY) ? 1u : 0u;
-      const double salt = p->saltcorr == 5 ? 0.368 * (pr.L - 1) * std::log(na_eq / 1000.0) : 0.0;
+      const double salt = p->saltcorr == 5 ? 0.368 * (pr.L - 1) * salt_t.ln_na : 0.0;
       t.KL = salt + R * std::log(C) + (p->selfcomp ? -1.4 : 0.0);
+      t.tshift = salt_t.shift;
+      if (salt_t.recip) {
+        t.recip = 1;
+        t.rA = salt_t.a0 + salt_t.a_len / (2.0 * (pr.L - 1));
+        t.rB = salt_t.b;
+      }
       tabs[2 * q + primer] = t;
     }
   }

@@ -26,6 +26,9 @@ struct PrimerTab {
   uint64_t stackm;    // positions 0..L-2 (left base of each stack)
   uint64_t deg;       // oligos in the expansion
   double KL;          // FP64: salt entropy + R ln C (+ symmetry), cal/(K mol)
+  double tshift;      // salt methods 1-4: degrees added to Tm
+  double rA, rB;      // salt methods 6, 7: 1/T += rA + rB * (G+C count) / L
+  uint32_t recip;     // 1: apply rA, rB
   uint32_t L, k, nd;
   uint32_t decoy;     // 1: the site is the primer against the reversed genome
   uint8_t dpos[32];   // degenerate positions, 5'->3'

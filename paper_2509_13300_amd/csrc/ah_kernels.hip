@@ -491,7 +491,17 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
     // elsewhere (those positions mismatch for every oligo).  Other compatible
     // pairings come from turning at most k - mm in-set, non-clamp positions
     // into mismatches, which any other member of their set does.
-    u64 o = T->fixed, afree = 0;
+    //
+    // Salt methods 6 and 7 also depend on the oligo's G+C count, so oligos
+    // that pair alike differ: each pairing takes the best choice at its
+    // unpaired degenerate positions, a member other than the template's base
+    // (any member where that base is not in the set): G or C if one is
+    // allowed when G+C raises Tm (rB < 0), else G or C only if every allowed
+    // member is.  gp: G+C bits (bit 2j) of the representative, which is the
+    // oligo at paired positions; gu: of the best choice at unpaired ones.
+    const bool recip = T->recip != 0u;
+    const bool want_gc = T->rB < 0.0;
+    u64 o = T->fixed, afree = 0, degm = 0, gu_deg = 0;
     for (u32 d = 0; d < T->nd; ++d) {
       const u32 pos2 = 2u * T->dpos[d];
       const u32 t = (u32)(ow >> pos2) & 3u;
@@ -501,7 +511,23 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
       in_set &= ((nb >> pos2) & 1u) == 0u;
       o |= (u64)(in_set ? t : (mem & 3u)) << pos2;
       if (in_set && ((clampm >> pos2) & 1u) == 0u) afree |= 1ull << pos2;
+      if (recip) {
+        bool any_gc = false, all_gc = true;
+        for (u32 r = 0; r < T->nmem[d]; ++r) {
+          const u32 b = (mem >> (2u * r)) & 3u;
+          if (in_set && b == t) continue;
+          const bool gc = ((b ^ (b >> 1)) & 1u) != 0u;  // C = 1, G = 2
+          any_gc |= gc;
+          all_gc &= gc;
+        }
+        degm |= 1ull << pos2;
+        if (want_gc ? any_gc : all_gc) gu_deg |= 1ull << pos2;
+      }
     }
+    const u64 allpos = T->lanes;
+    const u64 gp = (o ^ (o >> 1)) & allpos;
+    const u64 gu = (gp & ~degm) | gu_deg;
+    const double rA = T->rA, rB = T->rB, invL = 1.0 / (double)L;
     const u64 x = o ^ ow;
     const u64 eq0 = ~(x | (x >> 1)) & lanes;  // paired positions of the representative
     const u32 mism0 = L - (u32)__popcll(eq0);
@@ -523,7 +549,12 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
         init_term((u32)(o >> hi) & 3u, sh, ch, ss, cs);
       }
       const float den = (float)((double)ss + (double)cs + KL);
-      const float tm = 1000.0f * (sh + ch) / den - 273.15f;
+      float tm = 1000.0f * (sh + ch) / den - 273.15f;
+      if (recip) {  // 1/T += rA + rB fGC, with this pairing's best G+C count
+        const u32 gc = (u32)__popcll(eq & gp) + (u32)__popcll(allpos & ~eq & gu);
+        const double inv = 1.0 / ((double)tm + 273.15) + rA + rB * (double)gc * invL;
+        tm = (float)(1.0 / inv - 273.15);
+      }
       best = (best == best && best >= tm) ? best : tm;
     };
     if (mism0 <= k && (eq0 & clampm) == clampm) {
@@ -549,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
         }
       }
     }
-    h.tm = best;
+    h.tm = best + (float)T->tshift;  // salt methods 1-4 (NaN stays NaN)
     hits[i] = h;
   }
 }

@@ -298,6 +298,47 @@ def test_tm_conditions_and_error_statistics(dev):
         assert float(err.max()) <= TM_TOL
 
 
+SALT_CASES = [dict()] + [dict(saltcorr=m) for m in (1, 2, 3, 4, 6, 7)] + [
+    dict(saltcorr=7, Na=10.0, Mg=10.0), dict(saltcorr=7, Na=200.0, Mg=0.5),
+    dict(saltcorr=7, Na=50.0, Mg=3.0, dNTPs=0.8), dict(saltcorr=7, Na=0.0, Mg=2.0),
+    dict(saltcorr=6, Na=2000.0, Mg=0.0)]
+
+
+@pytest.mark.parametrize("case", range(len(SALT_CASES)))
+def test_tm_salt_methods_match_the_oracle(dev, case):
+    """Every salt-correction method (method 7 in each of its regimes; method
+    6 above 1 M, where G+C lowers Tm) on a primer with many degenerate
+    positions, whose G+C-best oligo differs from pairing to pairing."""
+    from paper_2509_13300_amd import _lib as L
+    from paper_2509_13300_amd import path
+
+    kw = SALT_CASES[case]
+    tp = L.tm_params(**kw)
+    op = otm.TmParams(dnac1=tp.dnac1_nM, dnac2=tp.dnac2_nM, Na=tp.Na_mM, K=tp.K_mM,
+                      Tris=tp.Tris_mM, Mg=tp.Mg_mM, dNTPs=tp.dNTPs_mM, saltcorr=tp.saltcorr,
+                      selfcomp=bool(tp.selfcomp))
+    cases = [
+        (plan.PairSpec("AGRRTTYGATYHTDGYTYAG", "YCNTTCCYTYDYRGTACT", k=3, clamp=0,
+                       min_len=100, max_len=3000),
+         dict(seed=99, n_genomes=3, len_lo=20000, len_hi=60000, n_copies=(2, 4), span=2455)),
+        # 20,736 oligos, random sites with up to 4 mismatches at degenerate positions
+        (plan.PairSpec("ACGRYSWKMBDHVNAC", "GTSWRYNHCAGKMT", k=4, clamp=2, min_len=40,
+                       max_len=400),
+         dict(seed=123, n_genomes=3, len_lo=3000, len_hi=8000, n_copies=(1, 2))),
+    ]
+    for pr, pk in cases:
+        pk = dict(pk)
+        p = plan.tiny(pk.pop("seed"), pair=pr, **pk)
+        say("salt", kw, pr.fwd)
+        coll, buf = run_gpu(p, [pr], dev, tm=tp)
+        gh = path.hits_numpy(buf)
+        oh, _ = run_oracle(p, [pr], tmp=op)
+        assert hit_tuples_gpu(gh) == hit_tuples_oracle(oh) and gh.size > 0
+        err = np.abs(gh["tm"].astype(np.float64) - oh["tm"])
+        say("Tm", kw, "hits", gh.size, "max err", float(err.max()))
+        assert np.all(np.isfinite(gh["tm"])) and float(err.max()) <= TM_TOL
+
+
 def test_plain_workload_full_parity(dev):
     """The 5 Mbp plain workload, compared in full."""
     p = plan.plain()

@@ -159,3 +159,22 @@ def test_decoy_pair_scans_the_complement_primers():
         assert dec != L.ah_scan_program_source([(fwd, rev, k, clamp)])
     assert L.ah_validate_pairs([(fwd, rev, 2, 0, 2)]) == L.AH_ERR_INVALID_ARG
     assert L.ah_validate_pairs([(fwd, rev, 2, 0, L.AH_PAIR_DECOY)]) == L.AH_OK
+
+
+def test_tm_salt_method_arguments_are_checked_before_any_device_work():
+    """ah_tm rejects unknown salt methods and ion sets a method cannot use
+    (no genomes, no device memory: the checks come first)."""
+    import ctypes
+
+    g = L.ah_genomes(None, None, None, None, 0, 1)
+    pp = L.primer_pairs([("ACGTACGTAC", "GGCCAATTGG", 1, 0)])
+    nres = ctypes.create_string_buffer(32)  # never read on these paths
+    bad = [dict(saltcorr=8), dict(saltcorr=-1), dict(Na=0.0, Mg=0.0, saltcorr=6),
+           dict(Na=0.0, Mg=0.0, saltcorr=1), dict(Na=0.0, Mg=0.0, saltcorr=7),
+           dict(Na=0.0, Mg=1.0, dNTPs=2.0, saltcorr=5)]
+    for kw in bad:
+        tp = L.tm_params(**kw)
+        st = L.lib().ah_tm(ctypes.byref(g), pp, len(pp), ctypes.byref(tp), None,
+                           ctypes.addressof(nres), 0, None)
+        assert st == L.AH_ERR_INVALID_ARG, kw
+        assert "salt" in L.lib().ah_last_error().decode()
