@@ -1215,7 +1215,8 @@ ah_status check_genomes(const ah_genomes* g) {
 // order, the final d_res (required, count, status), n_sort and the
 // candidate-list statistics.
 ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, const ScanWs& w,
-                             ah_result* d_res, uint64_t capacity, hipStream_t st) {
+                             ah_result* d_res, uint64_t capacity, hipStream_t st,
+                             const ah::KeyBits* kb) {
   if (g->n == 0) {
     AH_HIP(ah::launch_result_init(d_res, st));
     AH_HIP(ah::launch_zero_u64(w.cstat, 4, st));
@@ -1258,8 +1259,23 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   uint64_t* slice_sites = w.slice_sites;
   const uint4* ccands = w.cands;
   const uint32_t* cslice_cnt = w.slice_cnt;
-  void* vargs[] = {&words,      &nmask,      &word_off,    &len,         &ccands,   &slice,
-                   &cslice_cnt, &cand_sites, &slice_sites, &group_sites, &slice_win};
+  // the sort's start (kb set): emit writes the keys and counts the first
+  // digit into hist[0]; verify clears hist[0] and hist[1] before
+  const int dbits = kb ? ah::sort_digit_bits(*kb) : 0;
+  uint64_t* sort_keys = kb ? (uint64_t*)w.sb.keys[0] : nullptr;
+  uint32_t* sort_idx = kb ? w.sb.idx[0] : nullptr;
+  uint32_t* hist_a = kb ? w.sb.hist[0] : nullptr;
+  uint32_t* hist_b = kb ? w.sb.hist[1] : nullptr;
+  uint64_t hist_words = kb ? ((uint64_t)1 << dbits) * w.sb.hstride : 0;
+  uint32_t sort_hs = w.sb.hstride;
+  uint32_t sort_dmask = kb ? (1u << dbits) - 1u : 0u;
+  uint32_t sort_gshift = kb ? (uint32_t)(kb->pb + 2) : 0u;
+  uint32_t sort_qshift = kb ? (uint32_t)(kb->gb + kb->pb + 2) : 0u;
+  uint32_t sort_grid = (uint32_t)ah::kSortGrid;
+  uint32_t sort_chunk_min = ah::kSortChunkMin;
+  void* vargs[] = {&words,      &nmask,      &word_off,    &len,         &ccands,    &slice,
+                   &cslice_cnt, &cand_sites, &slice_sites, &group_sites, &slice_win, &hist_a,
+                   &hist_b,     &hist_words};
   {
     ProfScope prof_verify("verify", st);
     AH_HIP(hipModuleLaunchKernel(fn.verify, grid, 1, 1, ah::kBlock, 1, 1, 0, st, vargs, nullptr));
@@ -1272,9 +1288,12 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
     const uint64_t* cgroup_sites = w.group_sites;
     uint64_t* n_out = w.n_sort;
     uint64_t* cstat = w.cstat;
-    void* eargs[] = {&words,       &nmask,        &word_off,     &len,  &ccands,     &slice,
-                     &cslice_cnt,  &cslice_tot,   &cslice_win,   &ccand_sites, &cslice_sites,
-                     &cgroup_sites, &out,         &cap,          &d_res, &n_out,     &cstat};
+    void* eargs[] = {&words,       &nmask,       &word_off,    &len,         &ccands,
+                     &slice,       &cslice_cnt,  &cslice_tot,  &cslice_win,  &ccand_sites,
+                     &cslice_sites, &cgroup_sites, &out,       &cap,         &d_res,
+                     &n_out,       &cstat,       &sort_keys,   &sort_idx,    &hist_a,
+                     &sort_hs,     &sort_dmask,  &sort_gshift, &sort_qshift, &sort_grid,
+                     &sort_chunk_min};
     AH_HIP(hipModuleLaunchKernel(fn.emit, grid, 1, 1, ah::kBlock, 1, 1, 0, st, eargs, nullptr));
   }
   return AH_OK;
@@ -1480,7 +1499,7 @@ ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint
   Carver c(d_work, work_bytes);
   ScanWs w = carve_scan(c, g->n, capacity, 0);
   // the result, the records to sort (n_sort) and the candidate statistics
-  s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st);
+  s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st, &kb);
   if (s) return s;
   ProfScope prof_sort("sort", st);
   AH_HIP(ah::launch_sort_hits(w.staging, d_hits, w.n_sort, kb, w.sb, st));
@@ -1781,7 +1800,7 @@ ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uin
     for (uint32_t r = 0; r <= reps; ++r) {  // the first run warms up
       AH_HIP(ah::launch_result_init(d_res, strm));
       AH_HIP(hipEventRecord(e0, strm));
-      s = launch_scan_kernel(fn, cand[i], g, w, d_res, capacity, strm);
+      s = launch_scan_kernel(fn, cand[i], g, w, d_res, capacity, strm, nullptr);
       if (s) return s;
       AH_HIP(hipEventRecord(e1, strm));
       AH_HIP(hipEventSynchronize(e1));

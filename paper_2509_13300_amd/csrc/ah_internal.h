@@ -78,6 +78,14 @@ inline uint32_t sort_hist_stride(uint64_t capacity) {
   const uint64_t c = g < (uint64_t)kSortGrid ? g : (uint64_t)kSortGrid;
   return (uint32_t)((c + 3) / 4 * 4 > 0 ? (c + 3) / 4 * 4 : 4);
 }
+// Bits per digit of the radix sort of keys of `kb` (9 when that saves a pass).
+inline int sort_digit_bits(const KeyBits& kb) {
+  const int bits = kb.total();
+  return (bits + 8) / 9 < (bits + 7) / 8 ? 9 : 8;
+}
+// The sort of the staged records.  The scan's emit pass has written their
+// keys and indices (keys[0], idx[0]) and counted the first digit into
+// hist[0]; its verify pass has cleared hist[0] and hist[1].
 hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev,
                             KeyBits kb, const SortBuffers& sb, hipStream_t st);
 hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pairs, ah_hit* hits,

@@ -203,8 +203,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const T* __restrict__ in, 
 // pass is one scatter kernel: it derives its chunk's output offsets from all
 // G chunk histograms of its digit itself (no prefix-scan launches) and,
 // while placing the items, counts their next digit per destination chunk
-// (no histogram launches).  The first histograms come with the keys; the
-// last scatter writes the records: passes + 1 launches in all.  The counts
+// (no histogram launches).  The keys and the first histograms come from the
+// scan's emit pass, which uses the same chunking; the last scatter writes
+// the records: one launch per pass.  The counts
 // are stored digit-major (hist[digit * hs + chunk], hs >= G a multiple of 4
 // from the capacity: SortBuffers::hstride), so that the
 // thread of a digit reads its G counts with 16-byte loads, all in flight at
@@ -221,44 +222,6 @@ __device__ __forceinline__ u32 sort_chunks(u64 n, u64& chunk) {
 template <int D>
 __device__ __forceinline__ void store_hist(const u32* h, u32* __restrict__ hist, u32 hs) {
   for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x) hist[(u64)d * hs + blockIdx.x] = h[d];
-}
-
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_keygen(const ah_hit* __restrict__ st,
-                                                   const u64* __restrict__ n_dev, KeyBits kb,
-                                                   u64* __restrict__ keys, u32* __restrict__ idx,
-                                                   u32* __restrict__ hist, u32* __restrict__ hist_zero,
-                                                   u32 hs) {
-  __shared__ u32 h[1u << D];
-  const u64 n = *n_dev;
-  u64 chunk;
-  if (blockIdx.x >= sort_chunks(n, chunk)) return;
-  for (u32 d = threadIdx.x; d < (1u << D); d += blockDim.x) {
-    h[d] = 0;
-    hist_zero[(u64)d * hs + blockIdx.x] = 0;  // pass 0 counts pass 1's digits there
-  }
-  __syncthreads();
-  const u64 beg = (u64)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
-  for (u64 i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
-    ah_hit x[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const u64 i = i0 + (u64)q * blockDim.x;
-      if (i < end) x[q] = st[i];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const u64 i = i0 + (u64)q * blockDim.x;
-      if (i >= end) continue;
-      const u64 key = ((u64)x[q].pair << (kb.gb + kb.pb + 2)) | ((u64)x[q].genome << (kb.pb + 2)) |
-                      ((u64)x[q].pos << 2) | (u64)(x[q].strand_primer & 3u);
-      keys[i] = key;
-      idx[i] = (u32)i;
-      atomicAdd(&h[key & ((1u << D) - 1u)], 1u);
-    }
-  }
-  __syncthreads();
-  store_hist<D>(h, hist, hs);
 }
 
 // Stable scatter: items keep their order within a digit (chunk, then round,
@@ -1272,9 +1235,8 @@ void sort_passes(const ah_hit* staged, ah_hit* out, const u64* n_dev, KeyBits kb
   const int bits = kb.total();
   const int passes = (bits + D - 1) / D;
   // three histogram tables in rotation: pass p reads H[p % 3], counts pass
-  // p + 1's digits into H[(p + 1) % 3] and clears H[(p + 2) % 3]
-  k_keygen<D><<<kSortGrid, kBlock, 0, st>>>(staged, n_dev, kb, (u64*)sb.keys[0], sb.idx[0], sb.hist[0],
-                                            sb.hist[1], sb.hstride);
+  // p + 1's digits into H[(p + 1) % 3] and clears H[(p + 2) % 3]; the keys
+  // and H[0] come from the scan's emit pass
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
     const bool last = p + 1 == passes;
@@ -1289,8 +1251,7 @@ void sort_passes(const ah_hit* staged, ah_hit* out, const u64* n_dev, KeyBits kb
 
 hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev, KeyBits kb,
                             const SortBuffers& sb, hipStream_t st) {
-  const int bits = kb.total();
-  if ((bits + 8) / 9 < (bits + 7) / 8)  // 9-bit digits save a pass
+  if (sort_digit_bits(kb) == 9)
     sort_passes<9>(staged, out, (const u64*)n_dev, kb, sb, st);
   else
     sort_passes<8>(staged, out, (const u64*)n_dev, kb, sb, st);

@@ -28,7 +28,7 @@
 //   sum of the earlier slices' sites (the sums of the earlier groups of 64
 //   slices, then of the earlier slices of its own group; no device atomics),
 //   and the candidates with sites are counted again, now writing the site
-//   records.  Workgroup 0
+//   records, their sort keys and the sort's first histograms.  Workgroup 0
 //   also writes the result (required = sites found, count = records written)
 //   and the candidate-list statistics; a full slice makes the result an
 //   overflow whose bound covers both lists.
@@ -88,6 +88,21 @@ struct AhCands {
   u32 slice;    // records per workgroup
 };
 
+// Sort keys of the emitted records: the emit pass starts the radix sort that
+// puts the records in canonical order.  key = pair << qshift | genome <<
+// gshift | pos << 2 | strand-primer; the sort's first digit (key & dmask) is
+// counted per chunk of `chunk` records of the emitted order into
+// hist[digit * hs + chunk index] (cleared by the verify pass).  keys == null:
+// no keys (a scan run on its own).
+struct AhSortOut {
+  u64* keys;  // [cap]
+  u32* idx;   // [cap] the record's own slot
+  u32* hist;
+  u64 chunk;
+  u32 hs, dmask, gshift, qshift;
+};
+__shared__ AhSortOut ah_so;
+
 // This workgroup's candidate count and the windows in them.
 __shared__ u32 ah_n_cand;
 __shared__ unsigned long long ah_n_lost;  // windows of the candidates a full slice dropped
@@ -124,6 +139,13 @@ __device__ __forceinline__ void ah_emit(const AhCtx& c, AhHitRec* out, u64 cap, 
       r.mm = (unsigned char)mm;
       r.tm = __int_as_float(0x7fc00000);
       out[slot] = r;
+      if (ah_so.keys) {
+        const u64 key = ((u64)pair << ah_so.qshift) | ((u64)c.g << ah_so.gshift) |
+                        ((u64)r.pos << 2) | (u64)(sp & 3u);
+        ah_so.keys[slot] = key;
+        ah_so.idx[slot] = (u32)slot;
+        atomicAdd(&ah_so.hist[(u64)(key & ah_so.dmask) * ah_so.hs + slot / ah_so.chunk], 1u);
+      }
     }
     ++slot;
   }
@@ -259,10 +281,18 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
     const u64* __restrict__ word_off, const u32* __restrict__ len,
     const uint4* __restrict__ cands, u32 slice, const u32* __restrict__ slice_count,
     u32* __restrict__ cand_sites, u64* __restrict__ slice_sites, u64* __restrict__ group_sites,
-    u64* __restrict__ slice_win) {
+    u64* __restrict__ slice_win, u32* __restrict__ hist_a, u32* __restrict__ hist_b,
+    u64 hist_words) {
   // Sites of each candidate of this workgroup's slice, their sum, and the
   // candidates' windows (added to those of the candidates a full slice
-  // dropped).
+  // dropped).  The grid also clears the sort's first two histogram tables
+  // (the emit pass counts into the first, the first sort pass into the
+  // second).
+  for (u64 e = (u64)blockIdx.x * AH_BLOCK + threadIdx.x; e < hist_words;
+       e += (u64)gridDim.x * AH_BLOCK) {
+    hist_a[e] = 0u;
+    hist_b[e] = 0u;
+  }
   __shared__ u64 s_sites, s_win;
   if (threadIdx.x == 0) {
     s_sites = 0;
@@ -321,7 +351,10 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
     const u32* __restrict__ slice_total, const u64* __restrict__ slice_win,
     const u32* __restrict__ cand_sites, const u64* __restrict__ slice_sites,
     const u64* __restrict__ group_sites, AhHitRec* __restrict__ out, u64 cap,
-    AhResult* __restrict__ res, u64* __restrict__ n_out, u64* __restrict__ cand_stat) {
+    AhResult* __restrict__ res, u64* __restrict__ n_out, u64* __restrict__ cand_stat,
+    u64* __restrict__ sort_keys, u32* __restrict__ sort_idx, u32* __restrict__ sort_hist,
+    u32 sort_hs, u32 sort_dmask, u32 sort_gshift, u32 sort_qshift, u32 sort_grid,
+    u32 sort_chunk_min) {
   __shared__ u64 tmp[AH_BLOCK / 64];
   const u32 G = gridDim.x;
   // this slice's first record: the sites of the earlier groups of slices,
@@ -338,6 +371,23 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
   u64 slot, found;
   ah_block_scan(mine_before, tmp, &slot);
   ah_block_scan(mine_all, tmp, &found);
+  if (threadIdx.x == 0) {
+    // the sort's partition of the min(found, cap) records: chunks of
+    // ceil(n / sort_grid) rounded up to whole workgroups, at least
+    // sort_chunk_min
+    const u64 nrec = found < cap ? found : cap;
+    u64 ch = (nrec + sort_grid - 1) / sort_grid;
+    ch = (ch + AH_BLOCK - 1) / AH_BLOCK * AH_BLOCK;
+    ah_so.keys = sort_keys;
+    ah_so.idx = sort_idx;
+    ah_so.hist = sort_hist;
+    ah_so.chunk = ch < sort_chunk_min ? sort_chunk_min : ch;
+    ah_so.hs = sort_hs;
+    ah_so.dmask = sort_dmask;
+    ah_so.gshift = sort_gshift;
+    ah_so.qshift = sort_qshift;
+  }
+  __syncthreads();
   if (blockIdx.x == 0) {
     // candidate-list statistics: candidates, their windows, full slices, most
     // of one workgroup
