@@ -241,6 +241,7 @@ def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 6
     print(f"batched: {len(pairs)} pairs compiled in {prep_s:.1f} s; autotuning", file=sys.stderr,
           flush=True)
     sample = min(200, coll.n)
+    os.environ["AH_VERBOSE"] = "1"  # the autotuner reports each candidate on stderr
     t0 = time.perf_counter()
     shape, tune_ms = L.ah_autotune_scan(path.subset_view(coll, sample), L.primer_pairs(pairs),
                                         buf.hits, buf.hit_cap, buf.hit_res, buf.scan_work, repeats=2)

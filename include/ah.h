@@ -298,7 +298,8 @@ typedef struct ah_scan_tuning {
  * times after a warm-up, timed with HIP events on `stream`), keep the fastest
  * for later calls with the same set on this device, and return it.  The output
  * buffers are used as scratch (results unspecified afterwards).  Synchronises
- * `stream`.  Errors: as ah_scan_primers. */
+ * `stream`.  With the environment variable AH_VERBOSE=1 it writes a line to
+ * stderr as each candidate is compiled and timed.  Errors: as ah_scan_primers. */
 ah_status ah_autotune_scan(const ah_genomes* genomes, const ah_primer_pair* pairs, uint32_t n_pairs,
                            ah_hit* d_hits, uint64_t capacity, ah_result* d_res, void* d_work,
                            size_t work_bytes, void* stream, uint32_t repeats,

@@ -6,6 +6,7 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdlib>
 #include <cmath>
@@ -1771,12 +1772,28 @@ ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uin
   std::vector<ah_status> st(cand.size(), AH_OK);
   std::vector<std::string> errs(cand.size());
   for (size_t i = 0; i < cand.size(); ++i) srcs[i] = gen_program(pats, g->nmask != nullptr, cand[i]);
+  // AH_VERBOSE=1: a line on stderr as each candidate is compiled and timed
+  const char* verbose_env = getenv("AH_VERBOSE");
+  const bool verbose = verbose_env && verbose_env[0] == '1';
+  const auto t_start = std::chrono::steady_clock::now();
+  auto since = [&t_start] {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  };
   {
+    std::atomic<int> done{0};
+    std::mutex print_mu;
     std::vector<std::thread> th;
     for (size_t i = 0; i < cand.size(); ++i)
       th.emplace_back([&, i] {
         st[i] = rtc_compile(srcs[i], codes[i]);
         if (st[i]) errs[i] = g_err;
+        const int k = ++done;
+        if (verbose) {
+          std::lock_guard<std::mutex> lk(print_mu);
+          fprintf(stderr, "ah_autotune_scan: shape %d x %d compiled (%d of %zu) at %.1f s\n",
+                  cand[i].u, cand[i].group, k, cand.size(), since());
+          fflush(stderr);
+        }
       });
     for (auto& t : th) t.join();
   }
@@ -1809,6 +1826,11 @@ ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uin
       if (r) total += ms;
     }
     const double avg = total / reps;
+    if (verbose) {
+      fprintf(stderr, "ah_autotune_scan: shape %d x %d: %.3f ms at %.1f s\n", cand[i].u,
+              cand[i].group, avg, since());
+      fflush(stderr);
+    }
     if (avg < best) {
       best = avg;
       besti = i;

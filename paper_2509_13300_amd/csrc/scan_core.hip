@@ -88,21 +88,6 @@ struct AhCands {
   u32 slice;    // records per workgroup
 };
 
-// Sort keys of the emitted records: the emit pass starts the radix sort that
-// puts the records in canonical order.  key = pair << qshift | genome <<
-// gshift | pos << 2 | strand-primer; the sort's first digit (key & dmask) is
-// counted per chunk of `chunk` records of the emitted order into
-// hist[digit * hs + chunk index] (cleared by the verify pass).  keys == null:
-// no keys (a scan run on its own).
-struct AhSortOut {
-  u64* keys;  // [cap]
-  u32* idx;   // [cap] the record's own slot
-  u32* hist;
-  u64 chunk;
-  u32 hs, dmask, gshift, qshift;
-};
-__shared__ AhSortOut ah_so;
-
 // This workgroup's candidate count and the windows in them.
 __shared__ u32 ah_n_cand;
 __shared__ unsigned long long ah_n_lost;  // windows of the candidates a full slice dropped
@@ -139,13 +124,6 @@ __device__ __forceinline__ void ah_emit(const AhCtx& c, AhHitRec* out, u64 cap, 
       r.mm = (unsigned char)mm;
       r.tm = __int_as_float(0x7fc00000);
       out[slot] = r;
-      if (ah_so.keys) {
-        const u64 key = ((u64)pair << ah_so.qshift) | ((u64)c.g << ah_so.gshift) |
-                        ((u64)r.pos << 2) | (u64)(sp & 3u);
-        ah_so.keys[slot] = key;
-        ah_so.idx[slot] = (u32)slot;
-        atomicAdd(&ah_so.hist[(u64)(key & ah_so.dmask) * ah_so.hs + slot / ah_so.chunk], 1u);
-      }
     }
     ++slot;
   }
@@ -371,23 +349,21 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
   u64 slot, found;
   ah_block_scan(mine_before, tmp, &slot);
   ah_block_scan(mine_all, tmp, &found);
-  if (threadIdx.x == 0) {
-    // the sort's partition of the min(found, cap) records: chunks of
-    // ceil(n / sort_grid) rounded up to whole workgroups, at least
-    // sort_chunk_min
+  // The emit pass starts the radix sort that puts the records in canonical
+  // order: for each record it writes, the key (pair << qshift | genome <<
+  // gshift | pos << 2 | strand-primer) and index, and counts the sort's first
+  // digit (key & dmask) per chunk of the written order into hist[digit * hs
+  // + chunk] (cleared by the verify pass).  The sort partitions the
+  // min(found, cap) records into chunks of ceil(n / sort_grid) rounded up to
+  // whole workgroups, at least sort_chunk_min.  sort_keys == null: no keys
+  // (a scan run on its own).
+  u64 chunk;
+  {
     const u64 nrec = found < cap ? found : cap;
     u64 ch = (nrec + sort_grid - 1) / sort_grid;
     ch = (ch + AH_BLOCK - 1) / AH_BLOCK * AH_BLOCK;
-    ah_so.keys = sort_keys;
-    ah_so.idx = sort_idx;
-    ah_so.hist = sort_hist;
-    ah_so.chunk = ch < sort_chunk_min ? sort_chunk_min : ch;
-    ah_so.hs = sort_hs;
-    ah_so.dmask = sort_dmask;
-    ah_so.gshift = sort_gshift;
-    ah_so.qshift = sort_qshift;
+    chunk = ch < sort_chunk_min ? sort_chunk_min : ch;
   }
-  __syncthreads();
   if (blockIdx.x == 0) {
     // candidate-list statistics: candidates, their windows, full slices, most
     // of one workgroup
@@ -443,6 +419,17 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
       const uint4 e = mine[i];
       const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
       ah_verify_one(c, c.gw + e.y, e.y, e.z, e.w, out, cap, slot + off, true);
+      if (sort_keys) {  // keys of the records just written (read back by their writer)
+        const u64 end = slot + off + f < cap ? slot + off + f : cap;
+        for (u64 q = slot + off; q < end; ++q) {
+          const AhHitRec h = out[q];
+          const u64 key = ((u64)h.pair << sort_qshift) | ((u64)h.genome << sort_gshift) |
+                          ((u64)h.pos << 2) | (u64)(h.strand_primer & 3u);
+          sort_keys[q] = key;
+          sort_idx[q] = (u32)q;
+          atomicAdd(&sort_hist[(u64)(key & sort_dmask) * sort_hs + q / chunk], 1u);
+        }
+      }
     }
     slot += rt;
   }
