@@ -754,8 +754,8 @@ def main():
                          "out (reference for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
-              "described, not run, in this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the genomes over "
+              "GPUs is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
     if args.form == "batched":
         r = gpu_batched(args.steps, args.warmup)
