@@ -127,3 +127,54 @@ def test_graph_replay_equals_eager(batch, dev):
         torch.cuda.synchronize()
         assert np.array_equal(path.hits_numpy(buf), eager_h), rep
         assert np.array_equal(path.amps_numpy(buf), eager_a), rep
+
+
+def test_full_size_batch_sampled_against_oracle(dev):
+    """The batched workload at full size (2,000 genomes, 8.39 Gbp, 64 pairs of
+    the law) in one call with the batched benchmark's capacities: the records
+    of sampled (pair, genome) cells equal the oracle's, for the pairs planted
+    in three genomes, two pairs with hundreds of random sites per genome and
+    two pairs with none there."""
+    import torch
+
+    from paper_2509_13300_amd import path
+
+    p = plan.batched(2000, n_pairs=64)
+    pairs = p.pairs
+    ascii, off = gpu.fill_cuda(p, dev)
+    coll, _ = path.pack(ascii, off, p.lengths)
+    del ascii
+    torch.cuda.empty_cache()
+    buf = path.alloc(coll, pairs, 1 << 25, 1 << 24, dev)
+    say("full batch", coll.n, "genomes", coll.total_bp, "bp", len(pairs), "pairs")
+    path.run(coll, pairs, buf)
+    torch.cuda.synchronize()
+    rh, ra = path.result(buf.hit_res), path.result(buf.amp_res)
+    assert rh["status"] == 0 and ra["status"] == 0, (rh, ra)
+    h, a = path.hits_numpy(buf), path.amps_numpy(buf)
+    say("full batch hits", h.size, "amplicons", a.size)
+    checked = 0
+    for g in (0, 1000, 1999):
+        planted = sorted(set(p.plant_template[p.plant_genome == g].tolist()))  # template t: pair t
+        assert planted
+        one = p.subset([g])
+        for q in planted + [0, 21, 40, 63]:
+            oh, oa = run_oracle(one, [pairs[q]])
+            cell = (h["pair"] == q) & (h["genome"] == g)
+            first = np.flatnonzero(cell)
+            sel = h[cell].copy()
+            sel["pair"] = 0
+            sel["genome"] = 0
+            assert hit_tuples_gpu(sel) == hit_tuples_oracle(oh), (g, q)
+            assert np.abs(sel["tm"].astype(np.float64) - oh["tm"]).max(initial=0.0) <= 0.01
+            acell = (a["pair"] == q) & (a["genome"] == g)
+            asel = a[acell].copy()
+            asel["pair"] = 0
+            asel["genome"] = 0
+            if first.size:
+                asel["plus_hit"] -= np.uint32(first[0])
+                asel["minus_hit"] -= np.uint32(first[0])
+            assert amp_tuples(asel) == amp_tuples(oa), (g, q)
+            checked += int(oh.size > 0)
+            say("genome", g, "pair", q, "hits", sel.size, "amplicons", asel.size, "match the oracle")
+    assert checked >= 9
