@@ -238,3 +238,62 @@ def test_errors_and_degenerate_jobs(world, dev):
         assert srv.wait(0.05) is None
     finally:
         srv.close()
+
+
+def test_full_size_collection_jobs_sampled_against_oracle(dev):
+    """The serving workload at full size: the 100,000-genome collection
+    (418.7 Gbp, 104.7 GB packed) resident in HBM, a server with the serving
+    benchmark's part and capacity settings, the first nine jobs of its Poisson
+    job list (one law pair over a log-uniform subset of 11-69,792 genomes
+    each) and a job of a planted pair over every 97th genome, submitted
+    together.  Every job finishes; in each, the records of its first and last
+    genome, of the genome with the most sites, and (planted job) of two
+    genomes carrying the target equal the oracle's."""
+    import torch
+
+    from paper_2509_13300_amd import path
+
+    p = plan.serving(100000)
+    coll = path.pack_resident(lambda ids: gpu.fill_cuda(p.subset(ids), dev), p.lengths, dev)
+    say("full serving collection", coll.n, "genomes", coll.total_bp, "bp")
+    jobs = [(p.pairs[pid], ids) for _, pid, ids in plan.jobs(13306, 9, 4.0, p.n, len(p.pairs))]
+    every = np.arange(0, p.n, 97)
+    jobs.append((p.pairs[0], every))  # template 0 belongs to pair 0
+    carriers = np.intersect1d(p.plant_genome[p.plant_template == 0], every)
+    assert carriers.size >= 2
+    cfg = dict(n_lanes=4, n_compilers=8, part_bases=1 << 32, max_part_hits=1 << 25,
+               capacity_scale=2.0, host_pool_bytes=8 << 30)
+    srv = path.Server(coll, 32 << 30, dev, **cfg)
+    try:
+        out = serve_all(srv, jobs)
+    finally:
+        srv.close()
+    del coll
+    torch.cuda.empty_cache()
+    cells = 0
+    for j, (pr, ids) in enumerate(jobs):
+        h, a, st = out[j]
+        say("job", j, "genomes", len(ids), "k", pr.k, "hits", h.size, "amplicons", a.size)
+        sample = {int(ids[0]), int(ids[-1])}
+        if h.size:  # where this job found the most sites (which genomes to check, not what)
+            g_all, cnt = np.unique(h["genome"], return_counts=True)
+            sample.add(int(g_all[np.argmax(cnt)]))
+        if j == len(jobs) - 1:
+            sample.update(int(g) for g in carriers[:2])
+        for g in sorted(sample):
+            oh, oa = run_oracle(p.subset([g]), [pr])
+            cell = h["genome"] == g
+            first = np.flatnonzero(cell)
+            sel = h[cell].copy()
+            sel["genome"] = 0
+            assert hit_tuples_gpu(sel) == hit_tuples_oracle(oh), (j, g)
+            assert np.abs(sel["tm"].astype(np.float64) - oh["tm"]).max(initial=0.0) <= 0.01
+            asel = a[a["genome"] == g].copy()
+            asel["genome"] = 0
+            if first.size:
+                asel["plus_hit"] -= np.uint32(first[0])
+                asel["minus_hit"] -= np.uint32(first[0])
+            assert amp_tuples(asel) == amp_tuples(oa), (j, g)
+            cells += int(oh.size > 0)
+    say("sampled genomes with sites", cells)
+    assert cells >= 8
