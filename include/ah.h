@@ -86,7 +86,9 @@ typedef struct ah_genomes {
 
 /* Host-side layout query.  Fills h_word_off[0..n] (may be NULL) for genomes of
  * lengths h_len[0..n-1] and returns the total number of words.  The words
- * buffer needs 8 bytes per word, the nmask buffer 4 bytes per word. */
+ * buffer needs 8 bytes per word, the nmask buffer 4 bytes per word.  A genome
+ * has at most 2^32 - 1 bases (positions and lengths are 32-bit): for a longer
+ * one it returns UINT64_MAX, writes nothing and sets ah_last_error. */
 uint64_t ah_pack_layout(const uint64_t* h_len, uint32_t n, uint64_t* h_word_off);
 
 /* FASTA text in host memory -> the records' sequence bytes (Section 2.1: the
@@ -111,11 +113,11 @@ ah_status ah_fasta_read(const char* text, uint64_t bytes, uint8_t* seq, uint64_t
 /* Pack ASCII genomes into the layout above.  Genome g is
  * d_ascii[d_ascii_off[g] .. d_ascii_off[g+1]); upper or lower case A/C/G/T are
  * bases, every other byte is a non-ACGT base.  d_word_off must hold the
- * offsets from ah_pack_layout.  Writes d_words, d_len, and, when not NULL,
- * d_nmask and d_non_acgt[g] (number of non-ACGT bytes of genome g).  If any
- * genome has non-ACGT bytes the scan needs d_nmask.
- * Errors: AH_ERR_INVALID_ARG (null required pointer, a genome longer than
- * 2^32 - 1 bases), AH_ERR_HIP. */
+ * offsets from ah_pack_layout (which refuses genomes longer than 2^32 - 1
+ * bases).  Writes d_words, d_len, and, when not NULL, d_nmask and
+ * d_non_acgt[g] (number of non-ACGT bytes of genome g).  If any genome has
+ * non-ACGT bytes the scan needs d_nmask.
+ * Errors: AH_ERR_INVALID_ARG (null required pointer), AH_ERR_HIP. */
 ah_status ah_pack_genomes(const uint8_t* d_ascii, const uint64_t* d_ascii_off, uint32_t n,
                           const uint64_t* d_word_off, uint32_t* d_words, uint32_t* d_len,
                           uint32_t* d_nmask, uint64_t* d_non_acgt, void* stream);

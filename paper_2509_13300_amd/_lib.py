@@ -281,7 +281,9 @@ def tm_params(dnac1=250.0, dnac2=0.0, Na=50.0, K=0.0, Tris=0.0, Mg=1.5, dNTPs=0.
 def ah_pack_layout(lengths) -> np.ndarray:
     lengths = np.ascontiguousarray(lengths, dtype=np.uint64)
     out = np.zeros(lengths.size + 1, dtype=np.uint64)
-    lib().ah_pack_layout(lengths.ctypes.data, lengths.size, out.ctypes.data)
+    total = lib().ah_pack_layout(lengths.ctypes.data, lengths.size, out.ctypes.data)
+    if total == 0xFFFFFFFFFFFFFFFF:
+        raise AhError(AH_ERR_INVALID_ARG, "ah_pack_layout", lib().ah_last_error().decode())
     return out
 
 

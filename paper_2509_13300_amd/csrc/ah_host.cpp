@@ -1443,6 +1443,14 @@ void ah_release_caches(void) {
 }
 
 uint64_t ah_pack_layout(const uint64_t* h_len, uint32_t n, uint64_t* h_word_off) {
+  g_err.clear();
+  if (h_len)
+    for (uint32_t g = 0; g < n; ++g)
+      if (h_len[g] > 0xffffffffull) {
+        fail(AH_ERR_INVALID_ARG, "genome %u has %llu bases; at most 2^32 - 1 are supported", g,
+             (unsigned long long)h_len[g]);
+        return UINT64_MAX;
+      }
   uint64_t off = 0;
   if (h_word_off) h_word_off[0] = 0;
   for (uint32_t g = 0; g < n; ++g) {

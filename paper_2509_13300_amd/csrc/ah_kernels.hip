@@ -1077,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) void k_fasta_write(
       *o++ = '\n';
       text[at + rl - 1u] = '\n';
     }
-    const int S = (int)((glen[A.genome] + 31u) >> 5);
+    const int S = (int)(((u64)glen[A.genome] + 31u) >> 5);  // len up to 2^32 - 1
     const uint2* w = words + word_off[A.genome];
     const u32* nm = nmask ? nmask + word_off[A.genome] : nullptr;
     const bool rc = A.orient == AH_RF;

@@ -135,7 +135,7 @@ __device__ __forceinline__ AhCtx ah_ctx(const uint2* words, const u32* nmask,
   AhCtx c;
   c.g = g;
   c.n = len[g];
-  c.S = (c.n + 31u) >> 5;
+  c.S = (u32)(((u64)c.n + 31u) >> 5);  // n may be up to 2^32 - 1
   c.tail = (int)((long long)c.n - 31ll * (long long)c.S);
   const u64 wbase = word_off[g];
   c.gw = words + wbase;

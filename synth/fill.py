@@ -63,6 +63,31 @@ def genome_bytes(plan: Plan, g: int) -> np.ndarray:
     return seq
 
 
+def genome_range_bytes(plan: Plan, g: int, lo: int, hi: int) -> np.ndarray:
+    """Bytes [lo, hi) of genome ``g``, equal to ``genome_bytes(plan, g)[lo:hi]``
+    without building the whole genome (for genomes of billions of bases)."""
+    plan.check()
+    n = int(plan.lengths[g])
+    lo, hi = max(0, int(lo)), min(n, int(hi))
+    key = rng.stream_key(plan.seed, rng.S_BASES | plan.source_id(g))
+    u = (rng.draws(key, np.arange(lo, hi, dtype=np.int64)) >> np.uint64(32)).astype(np.uint32)
+    th = plan.thresholds[g]
+    code = (u >= th[0]).astype(np.uint8) + (u >= th[1]) + (u >= th[2])
+    seq = _LUT[code]
+    for c in np.flatnonzero(plan.plant_genome == g):
+        p = int(plan.plant_pos[c])
+        t = mutated_copy(plan, int(c))
+        a, b = max(p, lo), min(p + t.size, hi)
+        if a < b:
+            seq[a - lo:b - lo] = t[a - p:b - p]
+    for r in np.flatnonzero(plan.nrun_genome == g):
+        p, ln = int(plan.nrun_pos[r]), int(plan.nrun_len[r])
+        a, b = max(p, lo), min(p + ln, hi)
+        if a < b:
+            seq[a - lo:b - lo] = ord("N")
+    return seq
+
+
 def collection_bytes(plan: Plan) -> np.ndarray:
     """All genomes concatenated (offsets from ``plan.offsets``)."""
     out = np.empty(plan.total_bp, dtype=np.uint8)

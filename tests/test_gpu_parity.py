@@ -5,6 +5,8 @@ import numpy as np
 import pytest
 
 from gpu_util import amp_tuples, hit_tuples_gpu, hit_tuples_oracle, run_gpu, run_oracle, say
+from oracle import pair as opair
+from oracle import scan as oscan
 from oracle import tm as otm
 from synth import fill, gpu, plan
 
@@ -140,6 +142,53 @@ def test_large_k_up_to_the_maximum(dev, k, L, clamp):
     say("large k", k, L, clamp, fwd, rev, p.lengths.tolist())
     gh, _ = check_case(p, [pr], dev, hit_cap=1 << 20, amp_cap=1 << 22)
     assert gh.size > 0
+
+
+def test_longest_genome_positions_near_the_top_of_the_range(dev):
+    """One genome of 2^32 - 1 bases, the longest a 32-bit position allows
+    (packed words, window starts and amplicon ends reach the top of their
+    range): in 2 Mbp ranges around 2^31, around each planted copy and at the
+    genome's end, the sites, their Tm and the amplicons inside the range
+    equal the oracle's on those bytes."""
+    L = (1 << 32) - 1
+    # about 2.7e-5 random sites per base: ~50 in each range, ~114,000 in all
+    pr = plan.PairSpec("CAGCMGCCGCGGTAA", "ACHVGGGTWTCTAAT", k=2, clamp=0, min_len=200,
+                       max_len=600)
+    p = plan.tiny(4242, n_genomes=1, len_lo=L, len_hi=L, pair=pr, n_copies=(4, 4), span=400)
+    coll, buf = run_gpu(p, [pr], dev, hit_cap=1 << 22, amp_cap=1 << 20)
+    from paper_2509_13300_amd import path
+
+    res = path.result(buf.hit_res)
+    assert res["status"] == 0, res
+    gh, ga = path.hits_numpy(buf), path.amps_numpy(buf)
+    say("longest genome", L, "hits", gh.size, "amplicons", ga.size)
+    half = 1_000_000
+    centres = [1 << 31] + [int(x) + 200 for x in p.plant_pos] + [L - half]
+    plen = np.array([len(pr.fwd), len(pr.rev)])
+    checked = 0
+    for c in centres:
+        lo, hi = max(0, c - half), min(L, c + half)
+        seq = fill.genome_range_bytes(p, 0, lo, hi)
+        oh = oscan.scan_collection([seq], [pr])
+        oh = otm.fill_tm(oh, [seq], [pr])
+        oa = opair.call_amplicons(oh, [pr])
+        inside = (gh["pos"] >= lo) & (gh["pos"].astype(np.int64) +
+                                       plen[gh["strand_primer"] & 1] <= hi)
+        sel = gh[inside].copy()
+        sel["pos"] -= np.uint32(lo)
+        assert hit_tuples_gpu(sel) == hit_tuples_oracle(oh), c
+        assert np.abs(sel["tm"].astype(np.float64) - oh["tm"]).max(initial=0.0) <= TM_TOL
+        ain = ga[(ga["start"] >= lo) & (ga["end"] <= hi)]
+        got = sorted((int(x["start"]) - lo, int(x["end"]) - lo, int(x["orient"])) for x in ain)
+        want = sorted((int(x["start"]), int(x["end"]), int(x["orient"])) for x in oa)
+        assert got == want, c
+        checked += int(sel.size > 0)
+        say("range", lo, hi, "hits", sel.size, "amplicons", len(got))
+    # the ranges held sites, and records reach the top of the position range
+    assert checked >= 4
+    assert int(p.plant_pos.max()) > (1 << 31)
+    assert int(gh["pos"].max()) > (1 << 32) - (1 << 26)
+    assert int(ga["end"].max()) > (1 << 32) - (1 << 28)
 
 
 def test_low_complexity_dense_hits_and_all_orientations(dev):

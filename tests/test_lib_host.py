@@ -178,3 +178,12 @@ def test_tm_salt_method_arguments_are_checked_before_any_device_work():
                            ctypes.addressof(nres), 0, None)
         assert st == L.AH_ERR_INVALID_ARG, kw
         assert "salt" in L.lib().ah_last_error().decode()
+
+
+def test_pack_layout_takes_genomes_up_to_two_to_the_32_bases():
+    top = (1 << 32) - 1  # positions and lengths are 32-bit
+    off = L.ah_pack_layout([top, 5])
+    words = (top + 31) // 32
+    assert int(off[1]) == (words + 31 + 1) // 2 * 2 and int(off[1]) % 2 == 0
+    with pytest.raises(L.AhError, match="2\\^32 - 1"):
+        L.ah_pack_layout([10, 1 << 32])
