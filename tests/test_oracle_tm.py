@@ -192,11 +192,29 @@ def test_salt_methods_reduce_to_the_one_molar_reference():
 
 
 def test_methods_1_to_4_shift_every_oligo_alike():
+    shifts = []
     for m in (1, 2, 3, 4):
         p = tm.TmParams(Na=30.0, K=5.0, Mg=1.0, saltcorr=m)
         p0 = tm.TmParams(Na=30.0, K=5.0, Mg=1.0, saltcorr=0)
         d = [tm.tm_perfect(o, p) - tm.tm_perfect(o, p0) for o in OLIGOS]
         assert max(d) - min(d) < 1e-9 and d[0] < 0  # below 1 M: lower Tm
+        shifts.append(d[0])
+    # four different published corrections
+    assert min(abs(a - b) for i, a in enumerate(shifts) for b in shifts[i + 1:]) > 0.1
+
+
+def test_owczarzy_corrections_add_to_the_reciprocal_kelvin_temperature():
+    # methods 6 and 7 add a + b fGC to 1/T (T in kelvin): the same amount for
+    # duplexes of equal length and G+C whatever their 1 M stability
+    o1, o2 = "AGCTTGCAAGGCTTACCGTA", "ATGCGTCAAGCATGTCAGCA"
+    assert len(o1) == len(o2) and tm.gc_count(tm.codes(o1))[0] == tm.gc_count(tm.codes(o2))[0]
+    p1 = tm.TmParams(Na=1000.0, Mg=0.0, saltcorr=0)
+    assert abs(tm.tm_perfect(o1, p1) - tm.tm_perfect(o2, p1)) > 1.0
+    for kw in (dict(saltcorr=6), dict(saltcorr=7), dict(saltcorr=7, Na=10.0, Mg=10.0)):
+        d = [1.0 / (tm.tm_perfect(o, tm.TmParams(**kw)) + 273.15) -
+             1.0 / (tm.tm_perfect(o, tm.TmParams(Na=1000.0, Mg=0.0, saltcorr=0, dnac1=250.0))
+                    + 273.15) for o in (o1, o2)]
+        assert abs(d[0] - d[1]) < 1e-12 and abs(d[0]) > 1e-6, kw
 
 
 def test_method_7_without_magnesium_is_method_6_on_the_monovalent_ions():
@@ -210,9 +228,11 @@ def test_method_7_without_magnesium_is_method_6_on_the_monovalent_ions():
     a = tm.tm_perfect(o, tm.TmParams(Na=200.0, Mg=0.5, saltcorr=7))
     b = tm.tm_perfect(o, tm.TmParams(Na=200.0, Mg=0.0, saltcorr=7))
     assert a == pytest.approx(b, abs=1e-9)
-    c = tm.tm_perfect(o, tm.TmParams(Na=50.0, Mg=1.5, saltcorr=7))
-    d = tm.tm_perfect(o, tm.TmParams(Na=50.0, Mg=0.0, saltcorr=7))
-    assert abs(c - d) > 0.1
+    # from sqrt[Mg] / [Mon] = 0.22 on, the magnesium counts (0.32 and 0.77 here)
+    for na, mg in ((100.0, 1.0), (50.0, 1.5)):
+        c = tm.tm_perfect(o, tm.TmParams(Na=na, Mg=mg, saltcorr=7))
+        d = tm.tm_perfect(o, tm.TmParams(Na=na, Mg=0.0, saltcorr=7))
+        assert abs(c - d) > 0.1, (na, mg)
 
 
 def test_free_magnesium_satisfies_mass_action():
