@@ -240,6 +240,23 @@ ah_status ah_tm(const ah_genomes* genomes, const ah_primer_pair* pairs, uint32_t
                 const ah_tm_params* params, ah_hit* d_hits, const ah_result* d_nhits,
                 uint64_t capacity, void* stream);
 
+/* Melting temperature of one duplex, on the host in double precision (Section
+ * 2.1, "Melting temperature filtering": the nearest-neighbour Tm of an oligo
+ * against the template at a binding site).  oligo: A/C/G/T (case-insensitive),
+ * 5'->3', 2..AH_TM_DUPLEX_MAX_LEN bases.  opposite: the template bases written
+ * opposite each oligo base (same length, template read 3'->5'); position j
+ * pairs iff opposite[j] is the complement of oligo[j] (any other byte, N
+ * included, pairs with nothing).  Same model, conditions and salt methods as
+ * ah_tm (fGC of methods 6 and 7: the oligo's G+C fraction), all in double
+ * precision; a duplex in which no pair forms has zero enthalpy: -273.15.
+ * Writes *tm_c in degrees Celsius.  Borrowed host strings; no device work.
+ * Errors: AH_ERR_INVALID_ARG (null argument, lengths differ, bad salt method
+ * or concentrations), AH_ERR_INVALID_PRIMER (oligo byte not A/C/G/T),
+ * AH_ERR_LIMIT (length outside 2..AH_TM_DUPLEX_MAX_LEN). */
+enum { AH_TM_DUPLEX_MAX_LEN = 4096 };
+ah_status ah_tm_duplex(const char* oligo, const char* opposite, const ah_tm_params* params,
+                       double* tm_c);
+
 /* ---------------------------------------------------------------------------
  * Amplicon calling (Section 2.1, "Amplicon calling" and "Amplicon analysis").
  * ------------------------------------------------------------------------- */

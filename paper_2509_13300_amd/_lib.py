@@ -126,6 +126,7 @@ EXPORTS = (
     "ah_server_wait", "ah_server_part", "ah_server_release", "ah_server_stats_get",
     "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats", "ah_scan_candidate_capacity",
     "ah_fasta_workspace_bytes", "ah_amplicon_fasta", "ah_fasta_count", "ah_fasta_read",
+    "ah_tm_duplex",
 )
 
 _lib = None
@@ -151,6 +152,9 @@ def lib() -> ctypes.CDLL:
     L.ah_scan_workspace_bytes.restype = sz
     L.ah_tm.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, P(ah_tm_params), vp, vp, u64, vp]
     L.ah_tm.restype = st
+    L.ah_tm_duplex.argtypes = [ctypes.c_char_p, ctypes.c_char_p, P(ah_tm_params),
+                               P(ctypes.c_double)]
+    L.ah_tm_duplex.restype = st
     L.ah_pair_amplicons.argtypes = [vp, vp, u64, P(ah_primer_pair), P(ah_window), u32, vp, u64, vp,
                                     vp, sz, vp]
     L.ah_pair_amplicons.restype = st
@@ -320,6 +324,13 @@ def ah_tm(genomes: ah_genomes, pairs, params: ah_tm_params, hits, nhits, capacit
     pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
     _check(lib().ah_tm(ctypes.byref(genomes), pp, len(pp), ctypes.byref(params), _ptr(hits),
                        _ptr(nhits), int(capacity), _stream(stream)), "ah_tm")
+
+
+def ah_tm_duplex(oligo: str, opposite: str, params: ah_tm_params) -> float:
+    out = ctypes.c_double()
+    _check(lib().ah_tm_duplex(oligo.encode(), opposite.encode(), ctypes.byref(params),
+                              ctypes.byref(out)), "ah_tm_duplex")
+    return out.value
 
 
 def ah_pair_workspace_bytes(hit_capacity: int, n_pairs: int) -> int:

@@ -1378,6 +1378,35 @@ SaltTerms salt_terms(const ah_tm_params& p) {
   return r;
 }
 
+// Total strand concentration in M entering R ln C: dnac1 for a
+// self-complementary duplex, else max - min / 2 of the two strands.
+double strand_conc(const ah_tm_params& p) {
+  if (p.selfcomp) return p.dnac1_nM * 1e-9;
+  const double hi = p.dnac1_nM > p.dnac2_nM ? p.dnac1_nM : p.dnac2_nM;
+  const double lo = p.dnac1_nM > p.dnac2_nM ? p.dnac2_nM : p.dnac1_nM;
+  return (hi - lo / 2.0) * 1e-9;
+}
+
+// SantaLucia (1998) unified nearest-neighbour stacks in double precision for
+// the host-side duplex helper, indexed by (5' base * 4 + 3' base) of the
+// stack read on the oligo strand (A0 C1 G2 T3): Delta-H in kcal/mol and
+// Delta-S in cal/(K mol).  A stack and the one read on the other strand
+// (e.g. AC and GT) share their values.
+const double kNnH[16] = {-7.9, -8.4, -7.8, -7.2, -8.5, -8.0, -10.6, -7.8,
+                         -8.2, -9.8, -8.0, -8.4, -7.2, -8.2, -8.5, -7.9};
+const double kNnS[16] = {-22.2, -22.4, -21.0, -20.4, -22.7, -19.9, -27.2, -21.0,
+                         -22.2, -24.4, -19.9, -22.4, -21.3, -22.2, -22.7, -22.2};
+
+int base_code(char ch) {
+  switch (ch) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': return 3;
+    default: return -1;
+  }
+}
+
 }  // namespace
 
 namespace ah {
@@ -1531,14 +1560,7 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
   const SaltTerms salt_t = salt_terms(*p);
   if (!salt_t.ok)
     return fail(AH_ERR_INVALID_ARG, "salt correction %d: %s", p->saltcorr, salt_t.why);
-  double C;
-  if (p->selfcomp) {
-    C = p->dnac1_nM * 1e-9;
-  } else {
-    const double hi = p->dnac1_nM > p->dnac2_nM ? p->dnac1_nM : p->dnac2_nM;
-    const double lo = p->dnac1_nM > p->dnac2_nM ? p->dnac2_nM : p->dnac1_nM;
-    C = (hi - lo / 2.0) * 1e-9;
-  }
+  const double C = strand_conc(*p);
   if (!(C > 0)) return fail(AH_ERR_INVALID_ARG, "strand concentration must be positive");
   const double R = 1.987;
   std::vector<ah::PrimerTab> tabs(2 * (size_t)n_pairs);
@@ -1592,6 +1614,67 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
   ProfScope prof_tm("tm", (hipStream_t)stream);
   AH_HIP(ah::launch_tm(*g, (const ah::PrimerTab*)dt, n_pairs, d_hits, d_nhits, capacity,
                        cu_count() * 4, (hipStream_t)stream));
+  return AH_OK;
+}
+
+ah_status ah_tm_duplex(const char* oligo, const char* opposite, const ah_tm_params* p,
+                       double* tm_c) {
+  g_err.clear();
+  if (!oligo || !opposite || !p || !tm_c)
+    return fail(AH_ERR_INVALID_ARG, "ah_tm_duplex: oligo, opposite, params and tm_c are required");
+  const size_t n = strlen(oligo);
+  if (strlen(opposite) != n)
+    return fail(AH_ERR_INVALID_ARG, "ah_tm_duplex: oligo (%zu) and opposite (%zu) differ in length",
+                n, strlen(opposite));
+  if (n < 2 || n > AH_TM_DUPLEX_MAX_LEN)
+    return fail(AH_ERR_LIMIT, "ah_tm_duplex: length %zu outside 2..%d", n, AH_TM_DUPLEX_MAX_LEN);
+  if (p->saltcorr < 0 || p->saltcorr > 7)
+    return fail(AH_ERR_INVALID_ARG, "salt correction method %d (supported: 0-7)", p->saltcorr);
+  const SaltTerms salt_t = salt_terms(*p);
+  if (!salt_t.ok)
+    return fail(AH_ERR_INVALID_ARG, "salt correction %d: %s", p->saltcorr, salt_t.why);
+  const double C = strand_conc(*p);
+  if (!(C > 0)) return fail(AH_ERR_INVALID_ARG, "strand concentration must be positive");
+  std::vector<int> o(n);
+  std::vector<char> paired(n);
+  int gc = 0;
+  for (size_t j = 0; j < n; ++j) {
+    o[j] = base_code(oligo[j]);
+    if (o[j] < 0)
+      return fail(AH_ERR_INVALID_PRIMER, "ah_tm_duplex: oligo byte %zu ('%c') is not A/C/G/T", j,
+                  oligo[j]);
+    const int t = base_code(opposite[j]);
+    paired[j] = t >= 0 && t == 3 - o[j];  // opposite base is the complement
+    gc += o[j] == 1 || o[j] == 2;
+  }
+  // Stacks whose two pairs both form, then one initiation term per duplex
+  // end at the outermost formed pairs (none if no pair forms).
+  double dh = 0.0, ds = 0.0;
+  int lo = -1, hi = -1;
+  for (size_t j = 0; j < n; ++j) {
+    if (!paired[j]) continue;
+    if (lo < 0) lo = (int)j;
+    hi = (int)j;
+    if (j + 1 < n && paired[j + 1]) {
+      dh += kNnH[o[j] * 4 + o[j + 1]];
+      ds += kNnS[o[j] * 4 + o[j + 1]];
+    }
+  }
+  if (lo >= 0) {
+    for (int end : {lo, hi}) {
+      const bool g_or_c = o[end] == 1 || o[end] == 2;
+      dh += g_or_c ? 0.1 : 2.3;
+      ds += g_or_c ? -2.8 : 4.1;
+    }
+  }
+  if (p->saltcorr == 5) ds += 0.368 * (double)(n - 1) * salt_t.ln_na;
+  if (p->selfcomp) ds += -1.4;
+  double tm = 1000.0 * dh / (ds + 1.987 * std::log(C)) - 273.15;
+  if (salt_t.recip) {
+    const double rA = salt_t.a0 + salt_t.a_len / (2.0 * (double)(n - 1));
+    tm = 1.0 / (1.0 / (tm + 273.15) + rA + salt_t.b * (double)gc / (double)n) - 273.15;
+  }
+  *tm_c = tm + salt_t.shift;
   return AH_OK;
 }
 

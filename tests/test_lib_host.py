@@ -187,3 +187,83 @@ def test_pack_layout_takes_genomes_up_to_two_to_the_32_bases():
     assert int(off[1]) == (words + 31 + 1) // 2 * 2 and int(off[1]) % 2 == 0
     with pytest.raises(L.AhError, match="2\\^32 - 1"):
         L.ah_pack_layout([10, 1 << 32])
+
+
+def _golden_rows(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    with open(path) as f:
+        return [ln.rstrip("\n").split("\t") for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+_SALT_CONDITIONS = [
+    dict(saltcorr=0), dict(saltcorr=1), dict(saltcorr=2), dict(saltcorr=3), dict(saltcorr=4),
+    dict(saltcorr=5), dict(saltcorr=6), dict(saltcorr=7),
+    dict(saltcorr=7, Na=20.0, K=30.0, Tris=10.0, Mg=3.0, dNTPs=0.8),
+    dict(saltcorr=5, dnac1=500.0, dnac2=200.0, K=5.0, Tris=2.0, dNTPs=2.0),
+    dict(saltcorr=6, Na=1000.0, Mg=0.0),
+]
+
+
+def test_tm_duplex_matches_the_golden_perfect_duplexes():
+    from oracle import tm as otm
+    for oligo, selfcomp, _dh, _ds, _salt, tm_c in _golden_rows("nn_perfect_duplex.tsv"):
+        opp = "".join("TGCA"["ACGT".index(b)] for b in oligo)
+        got = L.ah_tm_duplex(oligo, opp, L.tm_params(selfcomp=selfcomp == "1"))
+        assert abs(got - float(tm_c)) < 5e-5, (oligo, got, tm_c)
+        want = otm.tm_duplex(oligo, opp, otm.TmParams(selfcomp=selfcomp == "1"))
+        assert abs(got - want) < 1e-9
+
+
+def test_tm_duplex_mismatch_rows_follow_the_hand_derived_sums():
+    # Tm from the golden (Delta-H, Delta-S) tenths under the default
+    # conditions, written out here from the published closed form
+    import math
+    for oligo, opp, dh_t, ds_t in _golden_rows("nn_mismatch_mm0.tsv"):
+        na = (50.0 + 120.0 * math.sqrt(1.5)) / 1000.0
+        ds = int(ds_t) / 10.0 + 0.368 * (len(oligo) - 1) * math.log(na)
+        want = 1000.0 * (int(dh_t) / 10.0) / (ds + 1.987 * math.log(250e-9)) - 273.15
+        got = L.ah_tm_duplex(oligo, opp, L.tm_params())
+        assert abs(got - want) < 1e-9, (oligo, opp, got, want)
+
+
+@pytest.mark.parametrize("cond", range(len(_SALT_CONDITIONS)))
+def test_tm_duplex_matches_the_oracle_on_random_duplexes(cond):
+    from oracle import tm as otm
+    kw = _SALT_CONDITIONS[cond]
+    rng = np.random.default_rng(1000 + cond)
+    params = L.tm_params(**kw)
+    op = otm.TmParams(**{k: v for k, v in kw.items()})
+    comp = {"A": "T", "C": "G", "G": "C", "T": "A"}
+    worst = 0.0
+    for trial in range(300):
+        n = int(rng.integers(2, 41))
+        oligo = "".join(rng.choice(list("ACGT"), n))
+        opp = [comp[b] for b in oligo]
+        for j in rng.choice(n, int(rng.integers(0, min(n, 6) + 1)), replace=False):
+            opp[j] = str(rng.choice(list("ACGTN")))  # a mismatch, an N or the same pair
+        opp = "".join(opp)
+        if trial % 7 == 0:
+            oligo = oligo.lower()
+        got = L.ah_tm_duplex(oligo, opp, params)
+        want = otm.tm_duplex(oligo.upper(), opp, op)
+        worst = max(worst, abs(got - want))
+    assert worst <= 1e-9, worst
+
+
+def test_tm_duplex_checks_its_arguments():
+    p = L.tm_params()
+    with pytest.raises(L.AhError) as e:
+        L.ah_tm_duplex("ACGT", "TGC", p)
+    assert e.value.status == L.AH_ERR_INVALID_ARG
+    with pytest.raises(L.AhError) as e:
+        L.ah_tm_duplex("ACNT", "TGCA", p)
+    assert e.value.status == L.AH_ERR_INVALID_PRIMER
+    with pytest.raises(L.AhError) as e:
+        L.ah_tm_duplex("A", "T", p)
+    assert e.value.status == L.AH_ERR_LIMIT
+    with pytest.raises(L.AhError) as e:
+        L.ah_tm_duplex("ACGT", "TGCA", L.tm_params(saltcorr=8))
+    assert e.value.status == L.AH_ERR_INVALID_ARG
+    with pytest.raises(L.AhError) as e:
+        L.ah_tm_duplex("ACGT", "TGCA", L.tm_params(Na=0.0, Mg=0.0))
+    assert e.value.status == L.AH_ERR_INVALID_ARG
