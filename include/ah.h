@@ -234,8 +234,15 @@ typedef struct ah_tm_params {
  * ah_scan_primers with the same genomes and pairs), set tm to the maximum
  * melting temperature over the oligos of the site's primer that have at most
  * k mismatches against the site and none in the clamp.  `capacity` is the
- * size of d_hits.  Errors: AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER,
- * AH_ERR_LIMIT, AH_ERR_HIP. */
+ * size of d_hits.  Oligos that pair a site at the same positions have the
+ * same nearest-neighbour sums, so a site costs one evaluation per set of
+ * paired positions: at most sum_{e <= min(k, nd)} C(nd, e) for a primer with
+ * nd degenerate positions outside the clamp.  A primer above
+ * AH_TM_MAX_PAIRINGS of them, or of degeneracy above 2^20, is refused with
+ * AH_ERR_LIMIT before any device work (the paper's web server caps
+ * degeneracy at 10,000, Section 2.2, which stays below both).  Errors:
+ * AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT, AH_ERR_HIP. */
+enum { AH_TM_MAX_PAIRINGS = 65536 };
 ah_status ah_tm(const ah_genomes* genomes, const ah_primer_pair* pairs, uint32_t n_pairs,
                 const ah_tm_params* params, ah_hit* d_hits, const ah_result* d_nhits,
                 uint64_t capacity, void* stream);
@@ -533,8 +540,9 @@ typedef struct ah_server_stats {
 ah_status ah_server_create(const ah_genomes* resident, const uint32_t* h_len,
                            const ah_server_config* cfg, void* d_pool, size_t pool_bytes,
                            ah_server** server);
-/* Queue a job; returns at once with its id.  Errors: AH_ERR_INVALID_ARG (bad
- * genome list or window), AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT. */
+/* Queue a job; returns at once with its id.  The pair and the Tm parameters
+ * are checked as ah_tm checks them.  Errors: AH_ERR_INVALID_ARG (bad genome
+ * list, window or Tm parameters), AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT. */
 ah_status ah_server_submit(ah_server* server, const ah_job* job, uint64_t* job_id);
 /* Wait up to timeout_s for the next finished job (in order of completion);
  * AH_ERR_AGAIN if none finished in time. */

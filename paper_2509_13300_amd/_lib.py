@@ -126,7 +126,7 @@ EXPORTS = (
     "ah_server_wait", "ah_server_part", "ah_server_release", "ah_server_stats_get",
     "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats", "ah_scan_candidate_capacity",
     "ah_fasta_workspace_bytes", "ah_amplicon_fasta", "ah_fasta_count", "ah_fasta_read",
-    "ah_tm_duplex",
+    "ah_tm_duplex", "ah_validate_tm",
 )
 
 _lib = None
@@ -179,6 +179,8 @@ def lib() -> ctypes.CDLL:
     L.ah_jit_stats.restype = None
     L.ah_validate_pairs.argtypes = [P(ah_primer_pair), u32]
     L.ah_validate_pairs.restype = st
+    L.ah_validate_tm.argtypes = [P(ah_primer_pair), u32, P(ah_tm_params)]
+    L.ah_validate_tm.restype = st
     L.ah_scan_program_source.argtypes = [P(ah_primer_pair), u32, ctypes.c_int, ctypes.c_char_p, sz]
     L.ah_scan_program_source.restype = sz
     L.ah_scan_program_compile.argtypes = [P(ah_primer_pair), u32, ctypes.c_int, P(ctypes.c_size_t)]
@@ -387,6 +389,11 @@ def ah_amplicon_fasta(genomes: ah_genomes, hits, amps, namp, amp_capacity: int, 
 def ah_validate_pairs(pairs) -> int:
     pp = primer_pairs(pairs)
     return int(lib().ah_validate_pairs(pp, len(pp)))
+
+
+def ah_validate_tm(pairs, params: ah_tm_params) -> int:
+    pp = primer_pairs(pairs)
+    return int(lib().ah_validate_tm(pp, len(pp), ctypes.byref(params)))
 
 
 def ah_last_error() -> str:

@@ -1407,9 +1407,62 @@ int base_code(char ch) {
   }
 }
 
+// Pairings the Tm kernel evaluates per site at most for a primer: the
+// representative oligo and every way of turning at most k of the degenerate
+// non-clamp positions into mismatches (every position in its set is the
+// worst case), sum over e <= min(k, nd) of C(nd, e).
+uint64_t worst_tm_pairings(const Primer& pr, uint32_t k, uint32_t clamp) {
+  uint32_t nd = 0;
+  for (int j = 0; j < pr.L; ++j)
+    if (set_size(pr.mask[j]) > 1 && j < pr.L - (int)clamp) ++nd;
+  uint64_t sum = 0, c = 1;  // c = C(nd, e)
+  for (uint32_t e = 0; e <= std::min(k, nd); ++e) {
+    sum += c;
+    c = c * (nd - e) / (e + 1);
+  }
+  return sum;
+}
+
+// Everything ah_tm checks before any device work: the pairs, the salt
+// method and its ion concentrations, a positive strand concentration, the
+// degeneracy limit and the bound on the pairings per site.
+ah_status check_tm_request(const ah_primer_pair* pairs, uint32_t n_pairs, const ah_tm_params* p,
+                           PairSet& ps) {
+  ah_status s = compile_pairs(pairs, n_pairs, ps);
+  if (s) return s;
+  if (!p) return fail(AH_ERR_INVALID_ARG, "Tm parameters are required");
+  if (p->saltcorr < 0 || p->saltcorr > 7)
+    return fail(AH_ERR_INVALID_ARG, "salt correction method %d (supported: 0-7)", p->saltcorr);
+  const SaltTerms salt_t = salt_terms(*p);
+  if (!salt_t.ok)
+    return fail(AH_ERR_INVALID_ARG, "salt correction %d: %s", p->saltcorr, salt_t.why);
+  if (!(strand_conc(*p) > 0)) return fail(AH_ERR_INVALID_ARG, "strand concentration must be positive");
+  for (uint32_t q = 0; q < n_pairs; ++q)
+    for (int primer = 0; primer < 2; ++primer) {
+      const Primer& pr = primer ? ps.rev[q] : ps.fwd[q];
+      uint64_t deg = 1;
+      for (int j = 0; j < pr.L; ++j) deg *= (uint64_t)set_size(pr.mask[j]);
+      if (deg > (1ull << 20))
+        return fail(AH_ERR_LIMIT, "pair %u: primer degeneracy %llu exceeds 2^20 for Tm", q,
+                    (unsigned long long)deg);
+      const uint64_t w = worst_tm_pairings(pr, ps.k[q], ps.clamp[q]);
+      if (w > (uint64_t)AH_TM_MAX_PAIRINGS)
+        return fail(AH_ERR_LIMIT,
+                    "pair %u: up to %llu pairings per site for Tm (at most %d: lower k or the "
+                    "degenerate positions outside the clamp)",
+                    q, (unsigned long long)w, (int)AH_TM_MAX_PAIRINGS);
+    }
+  return AH_OK;
+}
+
 }  // namespace
 
 namespace ah {
+ah_status check_tm(const ah_primer_pair* pairs, uint32_t n_pairs, const ah_tm_params* p) {
+  PairSet ps;
+  return check_tm_request(pairs, n_pairs, p, ps);
+}
+
 size_t scan_workspace_for(uint32_t n, uint64_t window_words, const ah_primer_pair* pairs,
                           uint32_t n_pairs, uint64_t capacity) {
   uint64_t ccap = min_cands(capacity);
@@ -1553,15 +1606,10 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
   if (!p || !d_nhits) return fail(AH_ERR_INVALID_ARG, "ah_tm: params and d_nhits are required");
   if (capacity > 0 && !d_hits) return fail(AH_ERR_INVALID_ARG, "d_hits is NULL");
   PairSet ps;
-  s = compile_pairs(pairs, n_pairs, ps);
+  s = check_tm_request(pairs, n_pairs, p, ps);
   if (s) return s;
-  if (p->saltcorr < 0 || p->saltcorr > 7)
-    return fail(AH_ERR_INVALID_ARG, "salt correction method %d (supported: 0-7)", p->saltcorr);
   const SaltTerms salt_t = salt_terms(*p);
-  if (!salt_t.ok)
-    return fail(AH_ERR_INVALID_ARG, "salt correction %d: %s", p->saltcorr, salt_t.why);
   const double C = strand_conc(*p);
-  if (!(C > 0)) return fail(AH_ERR_INVALID_ARG, "strand concentration must be positive");
   const double R = 1.987;
   std::vector<ah::PrimerTab> tabs(2 * (size_t)n_pairs);
   for (uint32_t q = 0; q < n_pairs; ++q) {
@@ -1592,9 +1640,6 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
         }
       }
       for (uint32_t j = 0; j < ps.clamp[q]; ++j) t.clampm |= 1ull << (2 * (pr.L - 1 - (int)j));
-      if (deg > (1ull << 20))
-        return fail(AH_ERR_LIMIT, "pair %u: primer degeneracy %llu exceeds 2^20 for Tm", q,
-                    (unsigned long long)deg);
       t.deg = deg;
       t.decoy = (ps.flags[q] & AH_PAIR_DECOY) ? 1u : 0u;
       const double salt = p->saltcorr == 5 ? 0.368 * (pr.L - 1) * salt_t.ln_na : 0.0;
@@ -1849,13 +1894,21 @@ ah_status ah_autotune_scan(const ah_genomes* g, const ah_primer_pair* pairs, uin
   if (!d_work || work_bytes < need)
     return fail(AH_ERR_WORKSPACE, "scan workspace: %zu bytes given, %zu needed", work_bytes, need);
   const std::vector<Pattern> pats = patterns_of(ps);
-  // candidates: tile words per lane x patterns per group (a single group when
-  // the set is small)
+  // candidates: the default shape first (kept unless another one is
+  // faster), then tile words per lane x patterns per group (a single group
+  // when the set is small)
   std::vector<Tuning> cand;
-  for (int u : {9, 15})
+  auto add = [&](Tuning t) {
+    t.group = std::min(t.group, (int)pats.size());
+    for (const Tuning& c : cand)
+      if (c.u == t.u && c.group == t.group) return;
+    cand.push_back(t);
+  };
+  add(default_tuning());
+  for (int u : {9, 15, 19, 21})
     for (int grp : {4, 8, 16}) {
       if (grp > (int)pats.size() && grp != 4) continue;
-      cand.push_back(Tuning{u, std::min(grp, (int)pats.size())});
+      add(Tuning{u, grp});
     }
   // compile every candidate concurrently (host threads), then time each
   std::vector<std::string> srcs(cand.size());
@@ -1992,6 +2045,12 @@ uint64_t ah_scan_candidate_capacity(size_t base_offset, size_t work_bytes, uint3
                                     uint64_t capacity) {
   Carver c((void*)(uintptr_t)(base_offset & 255u), work_bytes);
   return carve_scan(c, n_genomes, capacity, 0).ccap;
+}
+
+ah_status ah_validate_tm(const ah_primer_pair* pairs, uint32_t n_pairs, const ah_tm_params* p) {
+  g_err.clear();
+  PairSet ps;
+  return check_tm_request(pairs, n_pairs, p, ps);
 }
 
 ah_status ah_validate_pairs(const ah_primer_pair* pairs, uint32_t n_pairs) {

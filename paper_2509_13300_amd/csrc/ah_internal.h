@@ -145,6 +145,9 @@ hipError_t launch_tile_prefix_small(const uint32_t* len, uint32_t n, uint32_t ti
 size_t scan_workspace_for(uint32_t n, uint64_t window_words, const ah_primer_pair* pairs,
                           uint32_t n_pairs, uint64_t capacity);
 
+// Validation of a Tm request exactly as ah_tm does it, with no device work.
+ah_status check_tm(const ah_primer_pair* pairs, uint32_t n_pairs, const ah_tm_params* p);
+
 // Error reporting shared by the host sources: records the message returned by
 // ah_last_error() on this thread and returns s.
 ah_status set_error(ah_status s, const char* fmt, ...);

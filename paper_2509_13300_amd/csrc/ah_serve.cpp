@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -194,6 +195,10 @@ struct ah_server {
   std::deque<uint64_t> finished_q; // finished, not yet returned by wait
   ah_server_stats stats{};
   std::vector<std::thread> threads;
+  // Failure injection for tests (AH_SERVER_FAIL_PART=n at creation): the
+  // n-th part run (0-based, any lane) fails right after its first launch.
+  int64_t inject_fail = -1;
+  std::atomic<uint64_t> part_runs{0};
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -289,6 +294,14 @@ struct ah_server {
         srv->cv_lane.notify_all();
       }
     } extra{this};
+    // Whatever way this returns, nothing it queued on `st` is still running
+    // when the pool block (released by the caller) or the extra block
+    // (released by `extra`, destroyed after this) can be handed to another
+    // lane.  On the success paths the stream has already been synchronised.
+    struct SyncOnExit {
+      hipStream_t st;
+      ~SyncOnExit() { (void)hipStreamSynchronize(st); }
+    } sync_on_exit{st};
     uint64_t acap = p.acap;
     auto take_extra = [&](uint64_t cap) -> bool {
       std::lock_guard<std::mutex> lk(mu);
@@ -305,6 +318,8 @@ struct ah_server {
     };
     AH_HIP(hipMemcpyAsync(ids, j.ids.data() + p.g0, (size_t)n * 4, hipMemcpyHostToDevice, st));
     AH_HIP(ah::launch_gather_view(ids, n, res.word_off, res.len, off, len_v, st));
+    if (inject_fail >= 0 && part_runs.fetch_add(1) == (uint64_t)inject_fail)
+      return ah::set_error(AH_ERR_HIP, "injected failure after the first launch of a part");
     ah_genomes view = res;
     view.word_off = off;
     view.len = len_v;
@@ -531,6 +546,7 @@ ah_status ah_server_create(const ah_genomes* resident, const uint32_t* h_len,
   s->pool = Pool((pool_bytes - lost) & ~255ull);
   s->t0 = std::chrono::steady_clock::now();
   s->stats.pool_bytes = s->pool.bytes();
+  if (const char* e = getenv("AH_SERVER_FAIL_PART")) s->inject_fail = atoll(e);
   if (cfg->host_pool_bytes) {
     void* a = nullptr;
     AH_HIP(hipHostMalloc(&a, cfg->host_pool_bytes, hipHostMallocDefault));
@@ -548,7 +564,7 @@ ah_status ah_server_create(const ah_genomes* resident, const uint32_t* h_len,
 ah_status ah_server_submit(ah_server* srv, const ah_job* job, uint64_t* job_id) {
   ah::clear_error();
   if (!srv || !job) return ah::set_error(AH_ERR_INVALID_ARG, "server and job are required");
-  ah_status st = ah_validate_pairs(&job->pair, 1);
+  ah_status st = ah::check_tm(&job->pair, 1, &job->tm);
   if (st) return st;
   if (job->window.min_len > job->window.max_len)
     return ah::set_error(AH_ERR_INVALID_ARG, "window: min_len > max_len");

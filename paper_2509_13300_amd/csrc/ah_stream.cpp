@@ -150,7 +150,7 @@ ah_status ah_stream_query(const ah_host_genomes* hg, const ah_stream_config* cfg
   if (hit_capacity >= (1ull << 32)) return ah::set_error(AH_ERR_LIMIT, "hit capacity must be < 2^32");
   if (n_copy_streams > 0 && !copy_streams)
     return ah::set_error(AH_ERR_INVALID_ARG, "copy_streams is NULL");
-  s = ah_validate_pairs(pairs, n_pairs);
+  s = ah::check_tm(pairs, n_pairs, tm);
   if (s) return s;
   // the minimum layout; the scan workspace comes last and takes whatever the
   // caller gave beyond it (a longer candidate list)

@@ -297,3 +297,31 @@ def test_full_size_collection_jobs_sampled_against_oracle(dev):
             cells += int(oh.size > 0)
     say("sampled genomes with sites", cells)
     assert cells >= 8
+
+
+def test_a_part_that_fails_after_its_first_launch_frees_its_memory(world, dev, monkeypatch):
+    """A part run that fails after queueing device work (forced from the
+    host right after its first launch) ends its job with the error, returns
+    its pool block only once its stream is idle, and leaves the server able
+    to run the same job correctly."""
+    from paper_2509_13300_amd import path
+
+    p, c, pool = world
+    ids = np.array([1, 2, 5, 9, 30, 31, 60])
+    monkeypatch.setenv("AH_SERVER_FAIL_PART", "0")
+    srv = path.Server(c, 256 << 20, dev, n_lanes=1, part_bases=200_000)
+    monkeypatch.delenv("AH_SERVER_FAIL_PART")
+    try:
+        job = srv.submit(pool[0], ids)
+        st = srv.wait(60.0)
+        assert st is not None and st["job"] == job
+        assert st["status"] != 0
+        srv.release(job)
+        assert srv.stats()["pool_in_use"] == 0
+        got = serve_all(srv, [(pool[0], ids)])[0]
+        h0, a0 = direct(c, ids, pool[0], dev)
+        assert np.array_equal(got[0], h0) and np.array_equal(got[1], a0)
+        assert srv.stats()["pool_in_use"] == 0
+        say("failed part freed its block; rerun equal to the direct path:", h0.size, "hits")
+    finally:
+        srv.close()

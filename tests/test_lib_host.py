@@ -267,3 +267,49 @@ def test_tm_duplex_checks_its_arguments():
     with pytest.raises(L.AhError) as e:
         L.ah_tm_duplex("ACGT", "TGCA", L.tm_params(Na=0.0, Mg=0.0))
     assert e.value.status == L.AH_ERR_INVALID_ARG
+
+
+def _distinct_pairings_brute_force(primer: str, k: int, clamp: int) -> int:
+    """Distinct sets of paired positions over the compatible oligos of a
+    site whose template base lies in every position's set (the worst case):
+    every oligo of the expansion, paired where it carries the template base."""
+    import itertools
+    from oracle import iupac
+    sets = [iupac.members(c) for c in primer]
+    site = [s[0] for s in sets]  # template base in every set
+    L_ = len(primer)
+    seen = set()
+    for oligo in itertools.product(*sets):
+        paired = tuple(o == t for o, t in zip(oligo, site))
+        if L_ - sum(paired) <= k and all(paired[L_ - clamp:]):
+            seen.add(paired)
+    return len(seen)
+
+
+@pytest.mark.parametrize("primer,k,clamp", [
+    ("ACGRYTACGNACSW", 2, 0), ("ACGRYTACGNACSW", 3, 2), ("RYKMSWACGT", 10, 0),
+    ("NNNNACGTAC", 1, 0), ("ACGTACGTAR", 2, 1), ("ACGTACGTAC", 3, 0),
+])
+def test_tm_pairing_bound_counts_the_distinct_pairings(primer, k, clamp):
+    """The bound ah_tm enforces is the number of distinct paired-position
+    sets, counted here by brute force over the oligo expansion."""
+    import math
+    nd = sum(1 for j, c in enumerate(primer) if c not in "ACGT" and j < len(primer) - clamp)
+    formula = sum(math.comb(nd, e) for e in range(min(k, nd) + 1))
+    assert _distinct_pairings_brute_force(primer, k, clamp) == formula
+
+
+def test_tm_requests_above_the_pairing_bound_are_refused():
+    tp = L.tm_params()
+    fwd20 = "RYKMSWRYKMSWRYKMSWRY"  # 20 two-fold codes: degeneracy 2^20
+    rev = "ACGTACGTACGTACGTACGT"
+    # sum_{e <= 6} C(20, e) = 60,460 pairings: accepted; e <= 7: 137,980
+    assert L.ah_validate_tm([(fwd20, rev, 6, 0)], tp) == L.AH_OK
+    assert L.ah_validate_tm([(fwd20, rev, 7, 0)], tp) == L.AH_ERR_LIMIT
+    assert "pairings" in L.ah_last_error()
+    # a clamp over degenerate positions removes them from the count
+    assert L.ah_validate_tm([(fwd20, rev, 7, 4)], tp) == L.AH_OK
+    # degeneracy above 2^20 is refused whatever k is
+    assert L.ah_validate_tm([("N" * 11, rev, 0, 0)], tp) == L.AH_ERR_LIMIT
+    assert L.ah_validate_tm([("ACGTACGTAC", rev, 2, 0)], L.tm_params(saltcorr=9)) == \
+        L.AH_ERR_INVALID_ARG
