@@ -62,13 +62,30 @@ def _oracle_one(args):
     p, _ = workload(name)
     pr = p.pairs[0]
     h = oscan.scan_sequence(seq, pr.fwd, pr.rev, pr.k, pr.clamp)
-    h["genome"] = 0
+    h["genome"] = 0  # the index of seq in the list fill_tm gets
     h = otm.fill_tm(h, [seq], [pr])
+    h["genome"] = g
     a = opair.call_amplicons(h, [pr])
-    return int(h.size), int(a.size)
+    return g, h, a
+
+
+def host_cores():
+    """(cores this process may run on, os.cpu_count())."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    return aff, os.cpu_count() or 1
 
 
 def cpu_baseline(name: str, n_genomes: int, target_bp: float):
+    """The oracle as it stands on the first genomes of the workload: on the
+    host's cores (at most 16, one GPU's share of a shared host), and on one
+    core.  Returns the figures and the oracle's records of the sample."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
     p, _ = workload(name)
     ids, bp = [], 0
     for g in range(n_genomes):
@@ -76,26 +93,78 @@ def cpu_baseline(name: str, n_genomes: int, target_bp: float):
         bp += int(p.lengths[g])
         if bp >= target_bp:
             break
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    workers = max(1, min(16, cores, len(ids)))
+    aff, ncpu = host_cores()
+    workers = max(1, min(16, aff, len(ids)))
     ctx = mp.get_context("spawn")
-    with ctx.Pool(workers) as pool:
-        seqs = pool.map(_gen, [(name, g) for g in ids])
+    with cf.ProcessPoolExecutor(workers, mp_context=ctx) as ex:
+        seqs = list(ex.map(_gen, [(name, g) for g in ids]))
         t0 = time.perf_counter()
-        out = pool.map(_oracle_one, [(name, g, s) for g, s in zip(ids, seqs)])
+        out = list(ex.map(_oracle_one, [(name, g, s) for g, s in zip(ids, seqs)]))
         dt = time.perf_counter() - t0
+    # one core: the same oracle in this process on the first genomes, about
+    # a quarter of the sample
+    t0 = time.perf_counter()
+    one_bp, n_one = 0, 0
+    for g, s in zip(ids, seqs):
+        _oracle_one((name, g, s))
+        one_bp += int(p.lengths[g])
+        n_one += 1
+        if one_bp >= bp / 4:
+            break
+    dt1 = time.perf_counter() - t0
+    del seqs
+    hits = np.concatenate([o[1] for o in out])
+    amps, at = [], 0
+    for o in out:
+        a = o[2].copy()
+        a["plus_hit"] += at
+        a["minus_hit"] += at
+        at += o[1].size
+        amps.append(a)
+    amps = np.concatenate(amps)
     return {
         "value": bp / dt / 1e9,
         "unit": "Gbp/s",
         "cores": workers,
         "kind": "oracle",
         "sample": (f"first {len(ids)} genomes of the same collection ({bp / 1e6:.1f} Mbp), "
-                   f"oracle scan + Tm + pairing, one process per genome; {dt:.2f} s wall"),
-        "hits": sum(o[0] for o in out),
-    }
+                   f"oracle scan + Tm + pairing, one genome per task on {workers} worker "
+                   f"processes; {dt:.2f} s wall"),
+        "host_cores": {"affinity": aff, "os_cpu_count": ncpu, "workers": workers,
+                       "note": "workers capped at 16, one GPU's share of the host"},
+        "single_core": {"value": one_bp / dt1 / 1e9, "unit": "Gbp/s",
+                        "sample": f"first {n_one} genomes ({one_bp / 1e6:.1f} Mbp) in one "
+                                  f"process; {dt1:.2f} s"},
+        "hits": int(hits.size),
+    }, ids, hits, amps
+
+
+def oracle_agreement(gh, ga, ids, oh, oa) -> dict:
+    """The GPU records of the sample genomes (the first ones, so a prefix of
+    the canonical output) against the oracle's: every site, every amplicon
+    with its hit indices, and the Tm error."""
+    import numpy as np
+
+    n = len(ids)
+    assert list(ids) == list(range(n))
+    hsel = gh[gh["genome"] < n]
+    asel = ga[ga["genome"] < n]
+    got = [(int(x["genome"]), int(x["pos"]), int(x["strand_primer"]) >> 1,
+            int(x["strand_primer"]) & 1, int(x["mm"])) for x in hsel]
+    want = [(int(x["genome"]), int(x["pos"]), int(x["strand"]), int(x["primer"]), int(x["mm"]))
+            for x in oh]
+    ga_t = [(int(x["genome"]), int(x["start"]), int(x["end"]), int(x["orient"]),
+             int(x["plus_hit"]), int(x["minus_hit"])) for x in asel]
+    oa_t = [(int(x["genome"]), int(x["start"]), int(x["end"]), int(x["orient"]),
+             int(x["plus_hit"]), int(x["minus_hit"])) for x in oa]
+    equal = got == want and ga_t == oa_t
+    err = (np.abs(hsel["tm"].astype(np.float64) - oh["tm"]) if got == want
+           else np.array([np.inf]))
+    return {"oracle_equal": bool(equal),
+            "tm_error": {"max": float(err.max(initial=0.0)),
+                         "mean": float(err.mean()) if err.size else 0.0, "n": int(err.size),
+                         "unit": "C", "tolerance": 0.01},
+            "genomes": n, "sites": len(want), "amplicons": len(oa_t)}
 
 
 # ------------------------------------------------------------------ GPU --
@@ -169,6 +238,7 @@ def gpu_run(name: str, steps: int, warmup: int):
     ms_graph = (time.perf_counter() - t0) * 1e3 / steps
     assert path.result(buf.hit_res)["count"] == res_h["count"]
     hits = path.hits_numpy(buf)
+    amps = path.amps_numpy(buf)
     cands = L.ah_scan_candidate_stats(buf.scan_work, coll.n, buf.hit_cap)
     tm_ok = bool(np.all(np.isfinite(hits["tm"]))) if hits.size else True
     ms_step = dt * 1e3 / steps
@@ -194,7 +264,7 @@ def gpu_run(name: str, steps: int, warmup: int):
                          "valu_insts_per_dispatch": valu}},
         "pair": {"fwd": pr.fwd, "rev": pr.rev, "k": pr.k, "clamp": pr.clamp,
                  "window": [pr.min_len, pr.max_len]},
-        "genomes": coll.n,
+        "genomes": coll.n, "hits_np": hits, "amps_np": amps,
     }
 
 
@@ -748,7 +818,7 @@ def main():
     ap.add_argument("--jobs", type=int, default=120, help="serve: number of jobs")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: arrivals per second")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-target-mbp", type=float, default=64.0)
+    ap.add_argument("--cpu-target-mbp", type=float, default=128.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, launch one elementwise copy kernel of 1 GiB in / 1 GiB "
                          "out (reference for scaling rocprofv3 byte counters)")
@@ -872,10 +942,15 @@ def main():
         return
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, 1000, args.cpu_target_mbp * 1e6)
-        print(f"cpu baseline: {cpu['value']:.4f} Gbp/s on {cpu['cores']} cores", file=sys.stderr,
-              flush=True)
+        cpu, cpu_ids, cpu_hits, cpu_amps = cpu_baseline(args.workload, 1000,
+                                                        args.cpu_target_mbp * 1e6)
+        print(f"cpu baseline: {cpu['value']:.4f} Gbp/s on {cpu['cores']} cores, "
+              f"{cpu['single_core']['value']:.4f} on one", file=sys.stderr, flush=True)
     r = gpu_run(args.workload, args.steps, args.warmup)
+    agree = None
+    if cpu is not None:
+        agree = oracle_agreement(r["hits_np"], r["amps_np"], cpu_ids, cpu_hits, cpu_amps)
+        print(f"oracle agreement on the baseline's genomes: {agree}", file=sys.stderr, flush=True)
     print(f"gpu: {r['value']:.1f} Gbp/s, {r['ms_per_step']:.3f} ms/step, kernels {r['kernel_ms']}",
           file=sys.stderr, flush=True)
     line = {
@@ -898,6 +973,10 @@ def main():
             "graph_replay": r["graph_replay"],
             "ingest_pack": r["pack"], "jit": r["jit"],
             "tm_dtype": "f32 (compensated sums, f64 salt/log terms)",
+            "oracle_equal": None if agree is None else agree["oracle_equal"],
+            "tm_error": None if agree is None else agree["tm_error"],
+            "oracle_check": None if agree is None else {
+                k: agree[k] for k in ("genomes", "sites", "amplicons")},
         },
         "roofline": r["roofline"],
         "cpu_baseline": cpu,

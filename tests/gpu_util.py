@@ -88,3 +88,76 @@ def random_rate(pr):
             d[0] *= m
         tot += 2 * d[: pr.k + 1].sum()
     return tot
+
+
+# ---- the oracle over a whole collection, one genome per task, in worker
+# processes (the plain single-pair path; the genome bytes are regenerated in
+# each worker from the plan's seeds).
+_POOL_PLAN = None
+
+
+def _pool_init(p):
+    global _POOL_PLAN
+    _POOL_PLAN = p
+
+
+def _oracle_genome(args):
+    g, pr = args
+    seq = fill.genome_bytes(_POOL_PLAN, g)
+    h = oscan.scan_sequence(seq, pr.fwd, pr.rev, pr.k, pr.clamp)
+    h["genome"] = 0
+    h = otm.fill_tm(h, [seq], [pr])
+    a = opair.call_amplicons(h, [pr])
+    return g, h, a
+
+
+def oracle_pool_workers() -> int:
+    import os
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return max(1, min(16, cores))  # at most 16: one GPU's share of host cores
+
+
+def run_oracle_pool(p, pr, ids=None, label="oracle"):
+    """Hits (with Tm) and amplicons of pair ``pr`` over genomes ``ids`` of
+    plan ``p`` (all by default), in canonical order with genome ids of the
+    plan and hit indices into the returned hits."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import time
+
+    ids = list(range(p.n)) if ids is None else [int(g) for g in ids]
+    # longest first, so the pool does not end on one long genome
+    order = sorted(ids, key=lambda g: -int(p.lengths[g]))
+    workers = oracle_pool_workers()
+    res = {}
+    t0 = time.perf_counter()
+    # an executor (not multiprocessing.Pool): a worker that dies raises
+    # BrokenProcessPool here instead of leaving the caller waiting
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"),
+                                initializer=_pool_init, initargs=(p,)) as ex:
+        futs = [ex.submit(_oracle_genome, (g, pr)) for g in order]
+        for i, f in enumerate(cf.as_completed(futs)):
+            g, h, a = f.result()
+            res[g] = (h, a)
+            if (i + 1) % 100 == 0 or i + 1 == len(order):
+                say(f"{label}: {i + 1}/{len(order)} genomes on {workers} processes, "
+                    f"{time.perf_counter() - t0:.1f} s")
+    hs, amps, at = [], [], 0
+    for g in ids:
+        h, a = res[g]
+        h = h.copy()
+        a = a.copy()
+        h["genome"] = g
+        a["genome"] = g
+        a["plus_hit"] += at
+        a["minus_hit"] += at
+        at += h.size
+        hs.append(h)
+        amps.append(a)
+    h = np.concatenate(hs) if hs else np.zeros(0, oscan.HIT_DTYPE)
+    a = np.concatenate(amps) if amps else np.zeros(0, opair.AMP_DTYPE)
+    return h, a
