@@ -23,6 +23,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "genome Gbp/s scanned per primer pair at k mismatches; batched vs plain; p99 latency"
+BATCHED_DESC = ("batched: 2,000 genomes (log-normal lengths clipped 0.5-12 Mbp) x 64 law pairs "
+                "(L 15-30, degeneracy 2^0-2^10, k 0-3, windows 100-6000), one hipGraph replay per "
+                "step, against the 64 pairs as sequential plain queries")
+SERVE_DESC = ("serve: 100,000 genomes (log-normal lengths, median 4 Mbp, clipped 1-12 Mbp) resident "
+              "in HBM, Poisson arrivals, each job one law pair (1,024-pair pool: L 15-30, degeneracy "
+              "2^0-2^10, k 0-3) over a log-uniform subset of 10-100,000 genomes")
 HBM_PEAK_GBS = 8000.0
 SCAN_BYTES_PER_BP = 0.25  # 2-bit packed genome read once per query
 # int32 VALU lane-ops/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
@@ -285,9 +291,12 @@ def alu_roofline(pairs, bp: int, scan_ms: float, scan_bytes: float) -> dict:
             "algorithmic_ops": ops, "hbm_achieved_gbs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS}
 
 
-def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 64):
+def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 64,
+                shape=None):
     """Batched form: n_pairs primer pairs in one pass (hipGraph replay of the
-    whole scan -> Tm -> pairing sequence) against the same pairs one by one."""
+    whole scan -> Tm -> pairing sequence) against the same pairs one by one.
+    ``shape`` (words per lane, patterns per group) pins the batched kernel's
+    shape instead of autotuning it on a 200-genome sample."""
     import numpy as np
     import torch
 
@@ -305,18 +314,24 @@ def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 6
     torch.cuda.empty_cache()
     bp = coll.total_bp
     buf = path.alloc(coll, pairs, 1 << 25, 1 << 24, dev)
+    sample = min(200, coll.n)
+    tune_s = 0.0
+    if shape is not None:
+        L.ah_set_scan_tuning(pairs, shape)
     t0 = time.perf_counter()
     L.ah_scan_prepare(pairs)
     prep_s = time.perf_counter() - t0
-    print(f"batched: {len(pairs)} pairs compiled in {prep_s:.1f} s; autotuning", file=sys.stderr,
-          flush=True)
-    sample = min(200, coll.n)
-    os.environ["AH_VERBOSE"] = "1"  # the autotuner reports each candidate on stderr
-    t0 = time.perf_counter()
-    shape, tune_ms = L.ah_autotune_scan(path.subset_view(coll, sample), L.primer_pairs(pairs),
-                                        buf.hits, buf.hit_cap, buf.hit_res, buf.scan_work, repeats=2)
-    tune_s = time.perf_counter() - t0
-    print(f"batched: autotuned in {tune_s:.1f} s: {shape}", file=sys.stderr, flush=True)
+    print(f"batched: {len(pairs)} pairs compiled in {prep_s:.1f} s", file=sys.stderr, flush=True)
+    if shape is None:
+        os.environ["AH_VERBOSE"] = "1"  # the autotuner reports each candidate on stderr
+        t0 = time.perf_counter()
+        shape, tune_ms = L.ah_autotune_scan(path.subset_view(coll, sample), L.primer_pairs(pairs),
+                                            buf.hits, buf.hit_cap, buf.hit_res, buf.scan_work,
+                                            repeats=2)
+        tune_s = time.perf_counter() - t0
+        os.environ.pop("AH_VERBOSE", None)
+        print(f"batched: autotuned in {tune_s:.1f} s: {shape}", file=sys.stderr, flush=True)
+    shape = L.ah_get_scan_tuning(pairs)
     for _ in range(max(1, warmup)):
         path.run(coll, pairs, buf)
     torch.cuda.synchronize()
@@ -368,8 +383,11 @@ def gpu_batched(steps: int, warmup: int, n_genomes: int = 2000, n_pairs: int = 6
         "speedup_vs_sequential": ms_seq / ms_batched,
         "hits": rh["count"], "amplicons": ra["count"], "kernel_ms": kern,
         "tuning": {"words_per_lane": shape[0], "patterns_per_group": shape[1],
-                   "sample_genomes": sample, "autotune_s": tune_s, "compile_s": prep_s,
-                   "sequential_compile_s": prep_seq_s},
+                   "autotuned": tune_s > 0, "sample_genomes": sample if tune_s > 0 else 0,
+                   "autotune_s": tune_s, "compile_s": prep_s,
+                   "sequential_compile_s": prep_seq_s,
+                   "sequential_words_per_lane": sorted({L.ah_get_scan_tuning([q])[0]
+                                                        for q in pairs})},
         "roofline": alu_roofline(pairs, bp, kern["scan"], scan_bytes),
     }
 
@@ -727,10 +745,28 @@ def _lat_summary(sts):
             "queue_p99_ms": float(np.percentile(wait, 99))}
 
 
-def gpu_serve(n_jobs: int = 120, rate: float = 4.0, n_genomes: int = 100000,
-              pool_gb: float = 64.0, n_lanes: int = 4):
-    """Serving form: the 100,000-genome collection resident in HBM, Poisson
-    job arrivals (one law pair over a log-uniform genome subset each)."""
+def _pass_summary(sts, span, rate=None) -> dict:
+    bases = sum(st["bases"] for st in sts)
+    out = {"jobs": len(sts), "makespan_s": span, "jobs_per_s": len(sts) / span,
+           "gbps": bases / span / 1e9, "latency": _lat_summary(sts),
+           "hits": int(sum(st["hits"] for st in sts)),
+           "amplicons": int(sum(st["amplicons"] for st in sts))}
+    if rate is not None:
+        out["offered_jobs_per_s"] = rate
+    return out
+
+
+def gpu_serve(n_genomes: int = 100000, n_jobs: int = 2000, sat_jobs: int = 240,
+              main_frac: float = 0.7, sweep=(0.25, 0.5, 0.9), sweep_jobs: int = 500,
+              cold_jobs: int = 200, pool_gb: float = 48.0, host_gb: int = 48, n_lanes: int = 4):
+    """Serving form: the 100,000-genome collection resident in HBM; each job
+    is one law pair over a log-uniform genome subset.  Protocol: saturation
+    = jobs/s of a burst of the first ``sat_jobs`` jobs; then ``n_jobs``
+    Poisson arrivals at ``main_frac`` x saturation, a sweep over the other
+    fractions (the first ``sweep_jobs`` jobs each), all with every pair's
+    kernel compiled beforehand (warm); then ``cold_jobs`` Poisson jobs at the
+    main rate with every cached kernel dropped first, so that each new pair is
+    compiled on the request path (cold)."""
     import numpy as np
     import torch
 
@@ -746,58 +782,67 @@ def gpu_serve(n_jobs: int = 120, rate: float = 4.0, n_genomes: int = 100000,
     print(f"serve: resident {coll.total_bp / 1e9:.1f} Gbp, "
           f"{coll.words.numel() * 4 / 1e9:.1f} GB packed, built in {build_s:.1f} s",
           file=sys.stderr, flush=True)
-    jobs = plan.jobs(13306, n_jobs, rate, p.n, len(p.pairs))
-    used = sorted({pid for _, pid, _ in jobs})
+    n_all = max(n_jobs, sat_jobs, sweep_jobs if sweep else 0, cold_jobs)
+    base = plan.jobs(13306, n_all, 1.0, p.n, len(p.pairs))  # arrivals of a unit-rate process
+
+    def at_rate(jobs, rate):  # the same Poisson process run at `rate` jobs/s
+        return [(ta / rate, pid, ids) for ta, pid, ids in jobs]
+
+    warm_ids = sorted({pid for _, pid, _ in
+                       base[:max(n_jobs, sat_jobs, sweep_jobs if sweep else 0, 8)]})
     t0 = time.perf_counter()
-    L.prepare_many([[p.pairs[i]] for i in used])
+    L.prepare_many([[p.pairs[i]] for i in warm_ids])
     compile_s = time.perf_counter() - t0
-    print(f"serve: {len(used)} pair kernels compiled in {compile_s:.1f} s", file=sys.stderr,
+    print(f"serve: {len(warm_ids)} pair kernels compiled in {compile_s:.1f} s", file=sys.stderr,
           flush=True)
-    cfg = dict(n_lanes=n_lanes, n_compilers=8, part_bases=1 << 32, max_part_hits=1 << 25,
-               capacity_scale=2.0, host_pool_bytes=64 << 30)
-    t0 = time.perf_counter()
+    cfg = dict(n_lanes=n_lanes, n_compilers=16, part_bases=1 << 32, max_part_hits=1 << 25,
+               capacity_scale=2.0, host_pool_bytes=host_gb << 30)
+    out = {"genomes": n_genomes, "total_bp": coll.total_bp, "build_s": build_s,
+           "warm_compile_s": compile_s, "warm_distinct_pairs": len(warm_ids), "config": cfg,
+           "pool_gb": pool_gb}
     srv = path.Server(coll, int(pool_gb * (1 << 30)), dev, **cfg)
-    create_s = time.perf_counter() - t0
     try:
-        _serve_pass(srv, p, jobs[:8], "burst")  # warm-up: tables, staging buffers
-        print("serve: warm-up done", file=sys.stderr, flush=True)
-        sts, span = _serve_pass(srv, p, jobs, "poisson")
+        _serve_pass(srv, p, base[:8], "burst")  # warm-up: tables, staging buffers
+        sts, span = _serve_pass(srv, p, base[:sat_jobs], "burst")
+        sat = len(sts) / span
+        out["saturation"] = _pass_summary(sts, span)
+        print(f"serve: saturation {sat:.1f} jobs/s ({sat_jobs} jobs in a burst)",
+              file=sys.stderr, flush=True)
+        rate = main_frac * sat
+        sts, span = _serve_pass(srv, p, at_rate(base[:n_jobs], rate), "poisson")
+        out["main"] = dict(_pass_summary(sts, span, rate), fraction_of_saturation=main_frac)
+        print(f"serve: {n_jobs} jobs at {rate:.1f}/s: p50 {out['main']['latency']['p50_ms']:.1f} "
+              f"ms, p99 {out['main']['latency']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        out["sweep"] = []
+        for f in sweep:
+            sts, span = _serve_pass(srv, p, at_rate(base[:sweep_jobs], f * sat), "poisson")
+            out["sweep"].append(dict(_pass_summary(sts, span, f * sat), fraction_of_saturation=f))
+            print(f"serve: sweep {f}: p50 {out['sweep'][-1]['latency']['p50_ms']:.1f} ms, p99 "
+                  f"{out['sweep'][-1]['latency']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
         stats = srv.stats()
-        print(f"serve: poisson {n_jobs} jobs in {span:.2f} s", file=sys.stderr, flush=True)
-        bsts, bspan = _serve_pass(srv, p, jobs, "burst")
-        print(f"serve: burst in {bspan:.2f} s", file=sys.stderr, flush=True)
     finally:
         srv.close()
-    one = path.Server(coll, int(pool_gb * (1 << 30)), dev, **dict(cfg, n_lanes=1))
-    try:
-        ssts, sspan = _serve_pass(one, p, jobs, "serial")
-        print(f"serve: serial in {sspan:.2f} s", file=sys.stderr, flush=True)
-    finally:
-        one.close()
-    for a, b, c in zip(sorted(sts, key=lambda s: s["job"]), sorted(bsts, key=lambda s: s["job"]),
-                       sorted(ssts, key=lambda s: s["job"])):
-        assert a["hits"] == b["hits"] == c["hits"] and a["amplicons"] == b["amplicons"] == c["amplicons"]
-    bases = sum(st["bases"] for st in sts)
-    return {
-        "genomes": n_genomes, "total_bp": coll.total_bp, "jobs": n_jobs, "rate_per_s": rate,
-        "value": bases / span / 1e9, "ms_per_step": span * 1e3 / n_jobs,
-        "jobs_per_s": n_jobs / span, "bases": bases,
-        "latency": _lat_summary(sts),
-        "burst": {"gbps": bases / bspan / 1e9, "jobs_per_s": n_jobs / bspan,
-                  "latency": _lat_summary(bsts)},
-        "serial_one_lane": {"gbps": bases / sspan / 1e9, "jobs_per_s": n_jobs / sspan,
-                            "latency": _lat_summary(ssts)},
-        "hits": int(sum(st["hits"] for st in sts)),
-        "amplicons": int(sum(st["amplicons"] for st in sts)),
-        "retries": int(sum(st["retries"] for st in sts)),
-        "server": {k: stats[k] for k in ("parts_run", "retries", "pool_bytes", "pool_high_water",
-                                          "admission_waits", "lane_busy_s", "host_pool_bytes",
-                                          "host_pool_high_water", "host_fallbacks", "gpu_s",
-                                          "copy_s")},
-        "config": cfg, "pool_gb": pool_gb, "build_s": build_s, "compile_s": compile_s,
-        "server_create_s": create_s,
-        "distinct_pairs": len(used),
-    }
+    out["server"] = {k: stats[k] for k in ("parts_run", "retries", "pool_bytes", "pool_high_water",
+                                           "admission_waits", "lane_busy_s", "host_pool_bytes",
+                                           "host_pool_high_water", "host_fallbacks", "gpu_s",
+                                           "copy_s")}
+    if cold_jobs:
+        L.lib().ah_release_caches()  # every pair's kernel is compiled again, on request
+        srv = path.Server(coll, int(pool_gb * (1 << 30)), dev, **cfg)
+        try:
+            rate = main_frac * sat
+            sts, span = _serve_pass(srv, p, at_rate(base[:cold_jobs], rate), "poisson")
+            out["cold"] = dict(_pass_summary(sts, span, rate), fraction_of_saturation=main_frac,
+                               distinct_pairs=len({pid for _, pid, _ in base[:cold_jobs]}),
+                               ready_p50_ms=float(np.percentile(
+                                   [(st["t_ready"] - st["t_submit"]) * 1e3 for st in sts], 50)))
+            print(f"serve: cold {cold_jobs} jobs: p50 {out['cold']['latency']['p50_ms']:.1f} ms, "
+                  f"p99 {out['cold']['latency']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        finally:
+            srv.close()
+    m = out["main"]
+    out.update(value=m["gbps"], jobs_per_s=m["jobs_per_s"], ms_per_step=m["makespan_s"] * 1e3 / m["jobs"])
+    return out
 
 
 def main():
@@ -815,8 +860,10 @@ def main():
                          "(genomes reversed) in one pass; fasta: amplicon FASTA records, "
                          "sequence hashes and amplitypes; ingest: FASTA text read, copied and "
                          "packed")
-    ap.add_argument("--jobs", type=int, default=120, help="serve: number of jobs")
-    ap.add_argument("--rate", type=float, default=4.0, help="serve: arrivals per second")
+    ap.add_argument("--jobs", type=int, default=2000,
+                    help="serve: Poisson jobs at 0.7 x the measured saturation")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="the headline query only: no batched and serving sub-objects")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-mbp", type=float, default=128.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -836,9 +883,7 @@ def main():
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
             "data": "synthetic",
-            "config": {"workload": "batched: 2,000 genomes (log-normal lengths clipped 0.5-12 "
-                                   "Mbp) x 64 law pairs (L 15-30, degeneracy 2^0-2^10, k 0-3, "
-                                   "windows 100-6000), one hipGraph replay per step",
+            "config": {"workload": BATCHED_DESC,
                        "form": "batched", "genomes": r["genomes"], "total_bp": r["bp"],
                        "pairs": r["pairs"], "distinct_gbps": r["distinct_gbps"],
                        "sequential": r["sequential"],
@@ -898,26 +943,16 @@ def main():
             "roofline": r["roofline_scan"], "cpu_baseline": None}))
         return
     if args.form == "serve":
-        r = gpu_serve(args.jobs, args.rate)
-        print(f"serve: {r['value']:.1f} Gbp/s, {r['jobs_per_s']:.1f} jobs/s, p50 "
-              f"{r['latency']['p50_ms']:.1f} ms, p99 {r['latency']['p99_ms']:.1f} ms; burst "
-              f"{r['burst']['gbps']:.1f} Gbp/s; serial {r['serial_one_lane']['gbps']:.1f} Gbp/s",
-              file=sys.stderr, flush=True)
+        r = gpu_serve(n_jobs=args.jobs)
+        print(f"serve: {r['value']:.1f} Gbp/s, {r['jobs_per_s']:.1f} jobs/s at "
+              f"{r['main']['fraction_of_saturation']} x saturation", file=sys.stderr, flush=True)
         print(json.dumps({
             "metric": METRIC, "value": r["value"], "unit": "Gbp/s", "n_gpus": 1,
-            "steps": r["jobs"], "warmup": 8, "ms_per_step": r["ms_per_step"],
+            "steps": r["main"]["jobs"], "warmup": 8, "ms_per_step": r["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
             "data": "synthetic",
-            "config": {"workload": "serve: 100,000 genomes (log-normal lengths, median 4 Mbp, "
-                                   "clipped 1-12 Mbp) resident in HBM, Poisson arrivals, each job "
-                                   "one law pair (1,024-pair pool: L 15-30, degeneracy 2^0-2^10, "
-                                   "k 0-3) over a log-uniform subset of 10-100,000 genomes",
-                       "form": "serve", **{k: r[k] for k in (
-                           "genomes", "total_bp", "jobs", "rate_per_s", "jobs_per_s", "bases",
-                           "latency", "burst", "serial_one_lane", "hits", "amplicons", "retries",
-                           "server", "config", "pool_gb", "build_s", "compile_s",
-                           "server_create_s",
-                           "distinct_pairs")}},
+            "config": {"workload": SERVE_DESC, "form": "serve",
+                       **{k: v for k, v in r.items() if k not in ("value", "ms_per_step")}},
             "roofline": None, "cpu_baseline": None}))
         return
     if args.form == "stream":
@@ -951,6 +986,35 @@ def main():
     if cpu is not None:
         agree = oracle_agreement(r["hits_np"], r["amps_np"], cpu_ids, cpu_hits, cpu_amps)
         print(f"oracle agreement on the baseline's genomes: {agree}", file=sys.stderr, flush=True)
+    del r["hits_np"], r["amps_np"]
+    forms = {}
+    if not args.no_forms and args.workload == "collection":
+        import torch
+
+        torch.cuda.empty_cache()
+        # batched vs plain: the 64-pair workload in one pass against the same
+        # pairs one by one (shape pinned: autotuning takes minutes)
+        b = gpu_batched(max(3, args.steps // 4), 1, shape=(9, 8))
+        forms["batched"] = {
+            "workload": BATCHED_DESC, "genomes": b["genomes"], "total_bp": b["bp"],
+            "pairs": b["pairs"], "per_pair_gbps": b["value"], "distinct_gbps": b["distinct_gbps"],
+            "ms_per_step": b["ms_per_step"], "sequential": b["sequential"],
+            "speedup_vs_sequential": b["speedup_vs_sequential"], "hits": b["hits"],
+            "amplicons": b["amplicons"], "tuning": b["tuning"],
+            "roofline": {k: b["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac",
+                                                       "hbm_frac")}}
+        print(f"batched: {b['value']:.1f} Gbp/s per pair, {b['speedup_vs_sequential']:.2f}x vs "
+              f"sequential", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        # serving: a short run of the protocol (the full one: --form serve)
+        sv = gpu_serve(n_jobs=240, sat_jobs=120, sweep=(), cold_jobs=40, host_gb=16)
+        forms["serve"] = {"workload": SERVE_DESC + "; 120-job burst for saturation, 240 Poisson "
+                                                   "jobs at 0.7 x saturation (warm), 40 with "
+                                                   "every kernel compiled on request (cold)",
+                          **{k: sv[k] for k in ("saturation", "main", "cold", "warm_compile_s",
+                                                "warm_distinct_pairs", "build_s")}}
+        print(f"serve: warm p99 {sv['main']['latency']['p99_ms']:.1f} ms, cold p99 "
+              f"{sv['cold']['latency']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
     print(f"gpu: {r['value']:.1f} Gbp/s, {r['ms_per_step']:.3f} ms/step, kernels {r['kernel_ms']}",
           file=sys.stderr, flush=True)
     line = {
@@ -977,6 +1041,7 @@ def main():
             "tm_error": None if agree is None else agree["tm_error"],
             "oracle_check": None if agree is None else {
                 k: agree[k] for k in ("genomes", "sites", "amplicons")},
+            **forms,
         },
         "roofline": r["roofline"],
         "cpu_baseline": cpu,

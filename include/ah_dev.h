@@ -61,6 +61,42 @@ ah_status ah_scan_candidate_stats(const void* d_work, size_t work_bytes, uint32_
 uint64_t ah_scan_candidate_capacity(size_t base_offset, size_t work_bytes, uint32_t n_genomes,
                                     uint64_t capacity);
 
+/* Host-only simulation of the serving scheduler (ah_server_*): the lanes'
+ * own admission, round-robin and retry decisions, driven by simulated part
+ * runs on a simulated clock instead of device work.  Job i (the jobs need
+ * not be sorted) arrives at jobs[i].arrival with the parts
+ * parts[first_part .. first_part + n_parts) in that order; part q holds
+ * parts[q].bytes of the pool while it runs for parts[q].seconds, and its
+ * first parts[q].overflows runs report an output overflow (the part then runs
+ * again, as the server reruns a part with exact counts).  n_lanes lanes
+ * (1..16) share a pool of pool_bytes.  events[e] (up to max_events; the
+ * number of part runs in *n_events) lists every run in start order; done[i]
+ * gives job i's status (AH_OK, AH_ERR_LIMIT for a part larger than the pool),
+ * times (t_submit, t_start, t_done), parts and reruns.  Errors:
+ * AH_ERR_INVALID_ARG, AH_ERR_OVERFLOW (more runs than max_events; the
+ * statuses are still complete). */
+typedef struct ah_sched_part {
+  uint64_t bytes;
+  double seconds;
+  uint32_t overflows;
+  uint32_t reserved;
+} ah_sched_part;
+typedef struct ah_sched_job {
+  double arrival;
+  uint32_t first_part;
+  uint32_t n_parts;
+} ah_sched_job;
+typedef struct ah_sched_event {
+  double t_start, t_end;
+  uint32_t lane, job, part, run; /* run: 0 for a part's first run */
+  uint64_t block, bytes;         /* its pool block (offset) and size */
+  uint64_t pool_in_use;          /* pool bytes in use once it was admitted */
+} ah_sched_event;
+ah_status ah_sched_simulate(const ah_sched_job* jobs, uint32_t n_jobs, const ah_sched_part* parts,
+                            uint32_t n_parts, uint32_t n_lanes, uint64_t pool_bytes,
+                            ah_sched_event* events, uint64_t max_events, uint64_t* n_events,
+                            ah_job_status* done);
+
 #ifdef __cplusplus
 }
 #endif

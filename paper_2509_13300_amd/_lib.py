@@ -92,6 +92,23 @@ class ah_job(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class ah_sched_part(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_uint64), ("seconds", ctypes.c_double),
+                ("overflows", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ah_sched_job(ctypes.Structure):
+    _fields_ = [("arrival", ctypes.c_double), ("first_part", ctypes.c_uint32),
+                ("n_parts", ctypes.c_uint32)]
+
+
+class ah_sched_event(ctypes.Structure):
+    _fields_ = [("t_start", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("lane", ctypes.c_uint32), ("job", ctypes.c_uint32), ("part", ctypes.c_uint32),
+                ("run", ctypes.c_uint32), ("block", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
+                ("pool_in_use", ctypes.c_uint64)]
+
+
 class ah_job_status(ctypes.Structure):
     _fields_ = [("job", ctypes.c_uint64), ("status", ctypes.c_int32), ("n_parts", ctypes.c_uint32),
                 ("hits", ctypes.c_uint64), ("amplicons", ctypes.c_uint64),
@@ -126,7 +143,7 @@ EXPORTS = (
     "ah_server_wait", "ah_server_part", "ah_server_release", "ah_server_stats_get",
     "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats", "ah_scan_candidate_capacity",
     "ah_fasta_workspace_bytes", "ah_amplicon_fasta", "ah_fasta_count", "ah_fasta_read",
-    "ah_tm_duplex", "ah_validate_tm",
+    "ah_tm_duplex", "ah_validate_tm", "ah_sched_simulate",
 )
 
 _lib = None
@@ -181,6 +198,9 @@ def lib() -> ctypes.CDLL:
     L.ah_validate_pairs.restype = st
     L.ah_validate_tm.argtypes = [P(ah_primer_pair), u32, P(ah_tm_params)]
     L.ah_validate_tm.restype = st
+    L.ah_sched_simulate.argtypes = [P(ah_sched_job), u32, P(ah_sched_part), u32, u32, u64,
+                                    P(ah_sched_event), u64, P(ctypes.c_uint64), P(ah_job_status)]
+    L.ah_sched_simulate.restype = st
     L.ah_scan_program_source.argtypes = [P(ah_primer_pair), u32, ctypes.c_int, ctypes.c_char_p, sz]
     L.ah_scan_program_source.restype = sz
     L.ah_scan_program_compile.argtypes = [P(ah_primer_pair), u32, ctypes.c_int, P(ctypes.c_size_t)]
@@ -394,6 +414,28 @@ def ah_validate_pairs(pairs) -> int:
 def ah_validate_tm(pairs, params: ah_tm_params) -> int:
     pp = primer_pairs(pairs)
     return int(lib().ah_validate_tm(pp, len(pp), ctypes.byref(params)))
+
+
+def ah_sched_simulate(jobs, n_lanes: int, pool_bytes: int, max_events: int = 1 << 16):
+    """jobs: [(arrival_s, [(bytes, seconds, overflows), ...]), ...].  Returns
+    (events as dicts in start order, per-job status dicts)."""
+    parts = [q for _, ps in jobs for q in ps]
+    pa = (ah_sched_part * max(len(parts), 1))()
+    for i, (b, sec, ov) in enumerate(parts):
+        pa[i] = ah_sched_part(int(b), float(sec), int(ov), 0)
+    ja = (ah_sched_job * max(len(jobs), 1))()
+    at = 0
+    for i, (arr, ps) in enumerate(jobs):
+        ja[i] = ah_sched_job(float(arr), at, len(ps))
+        at += len(ps)
+    ev = (ah_sched_event * max_events)()
+    n = ctypes.c_uint64()
+    done = (ah_job_status * max(len(jobs), 1))()
+    _check(lib().ah_sched_simulate(ja, len(jobs), pa, len(parts), int(n_lanes), int(pool_bytes),
+                                   ev, max_events, ctypes.byref(n), done), "ah_sched_simulate")
+    evs = [{f: getattr(ev[i], f) for f, _ in ah_sched_event._fields_} for i in range(n.value)]
+    sts = [{f: getattr(done[i], f) for f, _ in ah_job_status._fields_} for i in range(len(jobs))]
+    return evs, sts
 
 
 def ah_last_error() -> str:

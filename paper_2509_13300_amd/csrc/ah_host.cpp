@@ -738,14 +738,126 @@ std::string gen_exact(size_t i, const Pattern& p, bool has_n) {
   return s;
 }
 
+// Candidate appends of a group's patterns a .. b - 1 (their filter outputs
+// c0, c1, ... relative to a), one record per quad of patterns: in tile mode
+// only from lanes with a candidate in the quad; in wave mode every lane calls
+// (the slot comes from a ballot over the wave).
+std::string quad_appends(size_t a, size_t b, bool wave) {
+  std::string s;
+  char buf[512];
+  for (size_t q = a; q < b; q += 4) {
+    std::string m[4];
+    for (int r = 0; r < 4; ++r)
+      m[r] = q + r < b ? "c" + std::to_string(q + r - a) : std::string("0u");
+    if (wave) {
+      snprintf(buf, sizeof buf, "      cnt = ah_wcand(c, k, t, %zuu, %s, %s, %s, %s, cnt, s);\n", q,
+               m[0].c_str(), m[1].c_str(), m[2].c_str(), m[3].c_str());
+    } else {
+      snprintf(buf, sizeof buf,
+               "      if (%s | %s | %s | %s) ah_cand(c, k, t, %zuu, %s, %s, %s, %s);\n",
+               m[0].c_str(), m[1].c_str(), m[2].c_str(), m[3].c_str(), q, m[0].c_str(),
+               m[1].c_str(), m[2].c_str(), m[3].c_str());
+    }
+    s += buf;
+  }
+  return s;
+}
+
+// Wave mode (see the scan core): per group, lane `lane` of the wave converts
+// its AH_U own words of the staged wave tile, the last group then issues the
+// copy of the wave's next tile, and every step takes the planes of the one
+// word past its own range that it newly needs from the next lane (the next
+// lane's own word of the same index: ds_bpermute).  The ring arrays hold the
+// own words at [0, AH_U) and those halo words after them, so the filters read
+// position j of window word u at index u + j as in tile mode.
+std::string gen_wave_groups(const std::vector<Pattern>& pats, size_t G) {
+  const size_t ngroups = (pats.size() + G - 1) / G;
+  std::string s;
+  char buf[2048];
+  for (size_t gi = 0; gi < ngroups; ++gi) {
+    const size_t a = gi * G, b = std::min(pats.size(), a + G);
+    int lg = 0;
+    for (size_t i = a; i < b; ++i) lg = std::max(lg, pats[i].L);
+    const bool last = gi + 1 == ngroups;
+    snprintf(buf, sizeof buf,
+             "__device__ %s u32 ah_wgroup_%zu(ah_lds_uint2* tw, u32 t0, const AhCtx& c, "
+             "const AhCands& k, u32 lane, uint4* my, const AhNext& nx, u32 cnt, u32 s) {\n"
+             "  const u32 base = lane * (u32)AH_U;\n"
+             "  u32 pa[AH_U + %d], pc[AH_U + %d], pg[AH_U + %d], pt[AH_U + %d];\n"
+             "  u32 ph[AH_U + %d], pl[AH_U + %d], px[AH_U + %d];\n"
+             "#pragma unroll\n"
+             "  for (int w = 0; w < AH_U; ++w)\n"
+             "    ah_planes(tw[base + (u32)w], pa[w], pc[w], pg[w], pt[w], ph[w], pl[w], px[w]);\n"
+             "%s"
+             "  const int src = (int)(((lane + 1u) & 63u) << 2);\n"
+             "  constexpr int kHalo = %d;  // the group's longest primer - 1\n"
+             "  // the planes of halo word hw, from the next lane's own word hw\n"
+             "  auto halo = [&](int hw) {\n"
+             "    pa[AH_U + hw] = __builtin_amdgcn_ds_bpermute(src, (int)pa[hw]);\n"
+             "    pc[AH_U + hw] = __builtin_amdgcn_ds_bpermute(src, (int)pc[hw]);\n"
+             "    pg[AH_U + hw] = __builtin_amdgcn_ds_bpermute(src, (int)pg[hw]);\n"
+             "    pt[AH_U + hw] = __builtin_amdgcn_ds_bpermute(src, (int)pt[hw]);\n"
+             "    ph[AH_U + hw] = __builtin_amdgcn_ds_bpermute(src, (int)ph[hw]);\n"
+             "    pl[AH_U + hw] = __builtin_amdgcn_ds_bpermute(src, (int)pl[hw]);\n"
+             "    px[AH_U + hw] = __builtin_amdgcn_ds_bpermute(src, (int)px[hw]);\n"
+             "  };\n"
+             "  // halo word u + kHalo - AH_U is first read at step u; it is fetched a\n"
+             "  // step earlier, so that the exchange is done when the step starts\n"
+             "  if (kHalo - AH_U >= 0) halo(kHalo - AH_U);\n"
+             "#pragma unroll\n"
+             "  for (int u = 0; u < AH_U; ++u) {\n"
+             "    if (u + 1 < AH_U && u + 1 + kHalo - AH_U >= 0) halo(u + 1 + kHalo - AH_U);\n"
+             "    const u32 t = lane < 63u ? t0 + base + (u32)u : 0xffffffffu;  // lane 63: no windows\n",
+             ngroups > 1 ? "__noinline__" : "__forceinline__", gi, lg - 1, lg - 1, lg - 1, lg - 1,
+             lg - 1, lg - 1, lg - 1,
+             last ? "  // every lane holds its planes: the slice is free for the next tile\n"
+                    "  __builtin_amdgcn_s_waitcnt(AH_WAIT_LGKMCNT0);\n"
+                    "  if (nx.valid) ah_wstage(nx.c, nx.t0, my, lane);\n"
+                  : "",
+             lg - 1);
+    s += buf;
+    std::string any;
+    for (size_t i = a; i < b; ++i) {
+      snprintf(buf, sizeof buf,
+               "    const u32 c%zu = ah_pf_%zu(pa + u, pc + u, pg + u, pt + u, ph + u, pl + u, px + u);\n",
+               i - a, i);
+      s += buf;
+      any += (i > a ? " | c" : "c") + std::to_string(i - a);
+    }
+    // a wave-wide vote, so that every lane takes the branch and keeps the same
+    // candidate count (the count is uniform over the wave)
+    s += "    if (__any((" + any + ") != 0u)) {\n";
+    s += quad_appends(a, b, true);
+    s += "    }\n  }\n  return cnt;\n}\n";
+  }
+  s += "__device__ u32 ah_wgroups(ah_lds_uint2* tw, u32 t0, const AhCtx& c, const AhCands& k, "
+       "u32 lane, uint4* my, const AhNext& nx, u32 cnt, u32 s) {\n";
+  for (size_t gi = 0; gi < ngroups; ++gi)
+    s += "  cnt = ah_wgroup_" + std::to_string(gi) + "(tw, t0, c, k, lane, my, nx, cnt, s);\n";
+  s += "  return cnt;\n}\n";
+  return s;
+}
+
+// Wave mode applies when every halo word lies in the next lane's own words
+// (AH_U >= longest primer - 1) and is not switched off (AH_SCAN_WAVE=0).
+bool wave_mode(const std::vector<Pattern>& pats, Tuning tn) {
+  const char* e = getenv("AH_SCAN_WAVE");
+  if (e && e[0] == '0') return false;
+  int lmax = 0;
+  for (const Pattern& p : pats) lmax = p.L > lmax ? p.L : lmax;
+  return tn.u >= lmax - 1;
+}
+
 std::string gen_program_uncached(const std::vector<Pattern>& pats, bool has_n, Tuning tn) {
   int lmax = 0;
   for (const Pattern& p : pats) lmax = p.L > lmax ? p.L : lmax;
   const bool allow = filter_enabled();
+  const bool wave = wave_mode(pats, tn);
   std::string s;
   char buf[2048];
-  snprintf(buf, sizeof buf, "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n", tn.u,
-           lmax - 1, has_n ? 1 : 0);
+  snprintf(buf, sizeof buf,
+           "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n#define AH_WAVE %d\n", tn.u,
+           lmax - 1, has_n ? 1 : 0, wave ? 1 : 0);
   std::string head = buf;
   for (size_t i = 0; i < pats.size(); ++i) {
     s += gen_filter(i, pats[i], plan_filter(pats[i], allow));
@@ -755,7 +867,7 @@ std::string gen_program_uncached(const std::vector<Pattern>& pats, bool has_n, T
   // each lane converts the words of its AH_U window words once and runs
   // every filter of the group on each window word
   const size_t G = (size_t)tn.group;
-  const size_t ngroups = (pats.size() + G - 1) / G;
+  const size_t ngroups = wave ? 0 : (pats.size() + G - 1) / G;
   for (size_t gi = 0; gi < ngroups; ++gi) {
     const size_t a = gi * G, b = std::min(pats.size(), a + G);
     int lg = 0;
@@ -791,15 +903,16 @@ std::string gen_program_uncached(const std::vector<Pattern>& pats, bool has_n, T
       any += (i > a ? " | c" : "c") + std::to_string(i - a);
     }
     s += "    if (" + any + ") {\n";
-    for (size_t i = a; i < b; ++i) {
-      snprintf(buf, sizeof buf, "      if (c%zu) ah_cand(c, k, t, %zuu, c%zu);\n", i - a, i, i - a);
-      s += buf;
-    }
+    s += quad_appends(a, b, false);
     s += "    }\n  }\n}\n";
   }
-  s += "__device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c, const AhCands& k) {\n";
-  for (size_t gi = 0; gi < ngroups; ++gi) s += "  ah_group_" + std::to_string(gi) + "(tw, t0, c, k);\n";
-  s += "}\n";
+  if (wave) {
+    s += gen_wave_groups(pats, G);
+  } else {
+    s += "__device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c, const AhCands& k) {\n";
+    for (size_t gi = 0; gi < ngroups; ++gi) s += "  ah_group_" + std::to_string(gi) + "(tw, t0, c, k);\n";
+    s += "}\n";
+  }
   // verification: the candidate's words from HBM, then the pattern's count
   snprintf(buf, sizeof buf,
            "template <class W>\n"
@@ -835,8 +948,9 @@ std::string gen_program(const std::vector<Pattern>& pats, bool has_n, Tuning tn)
     key.append((const char*)&q, sizeof q);
   }
   char buf[160];
-  snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%.17g|%d|%d", has_n ? 1 : 0, tn.u, tn.group,
-           filter_enabled() ? 1 : 0, cand_weight(), forced_need(), code_planes() ? 1 : 0);
+  snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%.17g|%d|%d|%d", has_n ? 1 : 0, tn.u, tn.group,
+           filter_enabled() ? 1 : 0, cand_weight(), forced_need(), code_planes() ? 1 : 0,
+           wave_mode(pats, tn) ? 1 : 0);
   key += buf;
   {
     std::lock_guard<std::mutex> lk(mu);
@@ -856,6 +970,7 @@ struct ScanFns {
   hipFunction_t scan = nullptr;    // filter: appends candidates
   hipFunction_t verify = nullptr;  // exact count of the candidates: sites per candidate
   hipFunction_t emit = nullptr;    // the site records, the result and the statistics
+  bool wave = false;               // wave mode: wave tiles of 63 x U words, 4 per workgroup
 };
 
 struct JitEntry {
@@ -915,6 +1030,7 @@ ah_status load_scan_kernel(int dev, const std::string& src, const std::vector<ch
   AH_HIP(hipModuleGetFunction(&e.fn.scan, e.mod, "ah_scan_kernel"));
   AH_HIP(hipModuleGetFunction(&e.fn.verify, e.mod, "ah_verify_kernel"));
   AH_HIP(hipModuleGetFunction(&e.fn.emit, e.mod, "ah_emit_kernel"));
+  e.fn.wave = src.find("#define AH_WAVE 1\n") != std::string::npos;
   g_jit[key] = e;
   fn = e.fn;
   return AH_OK;
@@ -1097,7 +1213,8 @@ struct Carver {
 struct ScanWs {
   uint64_t *counts, *tile_prefix, *scan_tmp, *n_sort;
   ah_hit* staging;
-  uint4* cands;           // filter output: {genome, window word, pattern, window mask}
+  uint4* cands;           // filter output: 2 uint4 per record ({genome, window word, first
+                          // pattern of the quad, 0}, the quad's window masks)
   uint32_t* slice_cnt;    // [kMaxScanGrid] candidates kept per workgroup
   uint32_t* slice_tot;    // [kMaxScanGrid] candidates found per workgroup
   uint64_t* slice_win;    // [kMaxScanGrid] windows in them
@@ -1111,6 +1228,8 @@ struct ScanWs {
 
 // Workgroups of the scan's filter at most (each owns a slice of the list).
 constexpr uint32_t kMaxScanGrid = 4096;
+// LDS bytes per compute unit on gfx950 (160 KiB).
+constexpr uint64_t kLdsPerCu = 160ull * 1024;
 
 // Candidate records the workspace must hold at least: the hit capacity (a
 // candidate holds one or more windows; every window of a site is in one), and
@@ -1164,14 +1283,14 @@ ScanWs carve_scan(Carver& c, uint32_t n, uint64_t cap, uint64_t ccap) {
   // spare bytes, so that the rest of a workspace of that size holds at least
   // ccap records, whatever the alignment of the workspace (one 256-byte
   // alignment pad between the two arrays, one for the base).
-  constexpr uint64_t kPerCand = sizeof(uint4) + sizeof(uint32_t);
+  constexpr uint64_t kPerCand = 2 * sizeof(uint4) + sizeof(uint32_t);
   const bool rest = ccap == 0;
   if (rest) {
     const uintptr_t at = (c.cur + 255) & ~(uintptr_t)255;
     ccap = c.end > at + 256 ? (uint64_t)(c.end - at - 256) / kPerCand : 0;
   }
   w.ccap = ccap;
-  w.cands = c.take<uint4>(ccap);
+  w.cands = c.take<uint4>(2 * ccap);
   w.cand_sites = c.take<uint32_t>(ccap);
   if (!rest) c.cur += 512;
   return w;
@@ -1224,7 +1343,9 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
     AH_HIP(ah::launch_zero_u64(w.n_sort, 1, st));
     return AH_OK;
   }
-  const uint32_t tile = (uint32_t)(ah::kBlock * tn.u);
+  // window words per tile: a workgroup's in tile mode, a wave's (63 lanes
+  // with windows) in wave mode
+  const uint32_t tile = fn.wave ? (uint32_t)(63 * tn.u) : (uint32_t)(ah::kBlock * tn.u);
   if (g->n <= ah::kSmallPrefix) {  // one launch, result reset included
     AH_HIP(ah::launch_tile_prefix_small(g->len, g->n, tile, w.tile_prefix, d_res, st));
   } else {
@@ -1236,8 +1357,16 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   // inputs get long slices); each workgroup owns ccap / grid records
   const uint64_t words_ub = ((uint64_t)g->max_len + 31) / 32;
   const uint64_t tiles_ub = (uint64_t)g->n * ((words_ub + tile - 1) / tile);
+  // wave mode: as many workgroups as are resident at once (LDS bound: four
+  // wave slices of 32 U + 1 16-byte pairs each), so that every wave keeps
+  // its slice busy until the tiles run out; at most one tile per wave
+  const uint64_t wave_res = fn.wave ? std::max<uint64_t>(1, kLdsPerCu / (4ull * (32 * tn.u + 1) * 16)) : 8;
+  const uint64_t want = fn.wave ? (tiles_ub + 3) / 4 : tiles_ub;
   const unsigned grid = (unsigned)std::max<uint64_t>(
-      1, std::min<uint64_t>({(uint64_t)cu_count() * 8u, tiles_ub, kMaxScanGrid}));
+      1, std::min<uint64_t>({(uint64_t)cu_count() * wave_res, want,
+                             fn.wave ? kMaxScanGrid / 4 : kMaxScanGrid}));
+  // candidate slices: one per workgroup, one per wave in wave mode
+  const unsigned n_slices = fn.wave ? grid * 4u : grid;
   const void* words = g->words;
   const uint32_t* nmask = g->nmask;
   const uint64_t* word_off = g->word_off;
@@ -1245,7 +1374,7 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   const uint64_t* tp = w.tile_prefix;
   uint32_t n = g->n;
   uint4* cands = w.cands;
-  uint32_t slice = (uint32_t)std::min<uint64_t>(w.ccap / grid, 0xffffffffu);
+  uint32_t slice = (uint32_t)std::min<uint64_t>(w.ccap / n_slices, 0xffffffffu);
   uint32_t* slice_cnt = w.slice_cnt;
   uint32_t* slice_tot = w.slice_tot;
   uint64_t* slice_win = w.slice_win;

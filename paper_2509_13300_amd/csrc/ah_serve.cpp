@@ -15,11 +15,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -200,7 +202,9 @@ struct ah_server {
   int64_t inject_fail = -1;
   std::atomic<uint64_t> part_runs{0};
 
+  double sim_now = -1.0;  // the simulated clock of ah_sched_simulate (>= 0 there)
   double now() const {
+    if (sim_now >= 0.0) return sim_now;
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
 
@@ -401,6 +405,105 @@ struct ah_server {
     return AH_OK;
   }
 
+  // ---- scheduling: the decisions the lanes take with mu held.  They touch
+  // only the jobs, the round robin, the pool and the statistics, so the
+  // host-only simulation (ah_sched_simulate) drives the same code with
+  // simulated part runs.
+
+  // The next part to run: the job at the front of the round robin, once its
+  // buffers (size_of(job, part) bytes) fit in the pool.  Returns true with
+  // the part taken (its block allocated, the round robin advanced), false
+  // when nothing is runnable or the front part's buffers do not fit yet.
+  template <class SizeFn>
+  bool take_next(SizeFn size_of, Job*& j, uint32_t& pi, uint64_t& blk, uint64_t& bytes) {
+    while (!active.empty()) {
+      Job* cand = jobs.at(active.front()).get();
+      if (!cand->has_work()) {  // failed meanwhile, or nothing left to start
+        cand->queued = false;
+        active.pop_front();
+        if (cand->in_flight == 0 &&
+            (cand->status != AH_OK || cand->done_parts == cand->parts.size()))
+          finish(*cand);
+        continue;
+      }
+      const uint32_t cpi = cand->redo.empty() ? (uint32_t)cand->next : cand->redo.front();
+      const uint64_t need = size_of(*cand, cpi);
+      if (need > pool.bytes()) {
+        cand->status = ah::set_error(AH_ERR_LIMIT, "a part needs %llu bytes > pool %llu",
+                                     (unsigned long long)need, (unsigned long long)pool.bytes());
+        continue;  // dropped on the next pass
+      }
+      if (!pool.alloc(need, &blk)) {
+        stats.admission_waits++;
+        return false;  // a finished part frees pool memory
+      }
+      j = cand;
+      pi = cpi;
+      bytes = need;
+      active.pop_front();
+      if (!j->redo.empty() && j->redo.front() == pi) j->redo.pop_front();
+      else j->next++;
+      j->in_flight++;
+      if (j->t_start < 0) j->t_start = now();
+      if (j->has_work()) active.push_back(j->id);
+      else j->queued = false;
+      stats.parts_run++;
+      return true;
+    }
+    return false;
+  }
+
+  // After part pi of job j ran with status s and results hr[0..1]: its block
+  // returns to the pool, an overflow sends the part back with the exact
+  // counts, and the job finishes once none of its parts is left.
+  void settle(Job& jr, uint32_t pi, uint64_t blk, uint64_t bytes, ah_status s,
+              const ah_result* hr) {
+    Job* j = &jr;
+    Part& p = j->parts[pi];
+    pool.release(blk, bytes);
+    j->in_flight--;
+    if (s != AH_OK) {
+      if (j->status == AH_OK) j->status = s;
+    } else if (hr[0].status != AH_OK || hr[1].status != AH_OK) {
+      // the exact counts are known now: run the part again with them
+      if (hr[0].required >= 0xffffffffull) {
+        if (j->status == AH_OK)
+          j->status = ah::set_error(AH_ERR_LIMIT, "a part of job %llu has %llu sites",
+                                    (unsigned long long)j->id,
+                                    (unsigned long long)hr[0].required);
+      } else if (hr[0].required <= p.hcap && hr[1].required <= p.acap) {
+        // a rerun with the same buffers would overflow again
+        if (j->status == AH_OK)
+          j->status = ah::set_error(AH_ERR_LIMIT,
+                                    "a part of job %llu overflows buffers sized for its "
+                                    "counts (%llu sites, %llu amplicons)",
+                                    (unsigned long long)j->id,
+                                    (unsigned long long)hr[0].required,
+                                    (unsigned long long)hr[1].required);
+      } else {
+        p.hcap = std::max<uint64_t>(p.hcap, hr[0].required);
+        p.acap = std::max<uint64_t>(p.acap, hr[1].required);
+        j->redo.push_back(pi);
+        j->retries++;
+        stats.retries++;
+        if (!j->queued) {
+          j->queued = true;
+          active.push_back(j->id);
+        }
+      }
+    } else {
+      p.done = true;
+      j->done_parts++;
+      j->hits += p.n_hits;
+      j->amps += p.n_amps;
+    }
+    if (j->in_flight == 0 && (j->status != AH_OK || j->done_parts == j->parts.size())) {
+      if (j->status != AH_OK)
+        for (Part& q : j->parts) drop_records(q);  // a failed job returns no records
+      finish(*j);
+    }
+  }
+
   void lane_loop() {
     (void)hipSetDevice(dev);
     hipStream_t st = nullptr;
@@ -409,53 +512,15 @@ struct ah_server {
     const hipError_t ce = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     std::unique_lock<std::mutex> lk(mu);
     if (ce != hipSuccess) return;
+    auto size_of = [](const Job& j, uint32_t pi) { return part_sizes(j.parts[pi], &j.pair).total; };
     for (;;) {
-      // the next part: the job at the front of the round robin, once its
-      // buffers fit in the pool
       Job* j = nullptr;
       uint32_t pi = 0;
-      uint64_t blk = 0;
-      PartSizes z{};
-      while (!stop) {
-        if (active.empty()) {
-          cv_lane.wait(lk);
-          continue;
-        }
-        Job* cand = jobs.at(active.front()).get();
-        if (!cand->has_work()) {  // failed meanwhile, or nothing left to start
-          cand->queued = false;
-          active.pop_front();
-          if (cand->in_flight == 0 &&
-              (cand->status != AH_OK || cand->done_parts == cand->parts.size()))
-            finish(*cand);
-          continue;
-        }
-        const uint32_t cpi = cand->redo.empty() ? (uint32_t)cand->next : cand->redo.front();
-        z = part_sizes(cand->parts[cpi], &cand->pair);
-        if (z.total > pool.bytes()) {
-          cand->status = ah::set_error(AH_ERR_LIMIT, "a part needs %llu bytes > pool %llu",
-                                       (unsigned long long)z.total,
-                                       (unsigned long long)pool.bytes());
-          continue;  // dropped on the next pass
-        }
-        if (pool.alloc(z.total, &blk)) {
-          j = cand;
-          pi = cpi;
-          break;
-        }
-        stats.admission_waits++;
-        cv_lane.wait(lk);  // a finished part frees pool memory
-      }
+      uint64_t blk = 0, bytes = 0;
+      while (!stop && !take_next(size_of, j, pi, blk, bytes)) cv_lane.wait(lk);
       if (stop) break;
-      active.pop_front();
-      if (!j->redo.empty() && j->redo.front() == pi) j->redo.pop_front();
-      else j->next++;
-      j->in_flight++;
-      if (j->t_start < 0) j->t_start = now();
-      if (j->has_work()) active.push_back(j->id);
-      else j->queued = false;
       Part& p = j->parts[pi];
-      stats.parts_run++;
+      const PartSizes z = part_sizes(p, &j->pair);
       lk.unlock();
 
       const double t_run = now();
@@ -468,48 +533,7 @@ struct ah_server {
       stats.lane_busy_s += now() - t_run;
       stats.gpu_s += t_gpu;
       stats.copy_s += t_copy;
-      pool.release(blk, z.total);
-      j->in_flight--;
-      if (s != AH_OK) {
-        if (j->status == AH_OK) j->status = s;
-      } else if (hr[0].status != AH_OK || hr[1].status != AH_OK) {
-        // the exact counts are known now: run the part again with them
-        if (hr[0].required >= 0xffffffffull) {
-          if (j->status == AH_OK)
-            j->status = ah::set_error(AH_ERR_LIMIT, "a part of job %llu has %llu sites",
-                                      (unsigned long long)j->id,
-                                      (unsigned long long)hr[0].required);
-        } else if (hr[0].required <= p.hcap && hr[1].required <= p.acap) {
-          // a rerun with the same buffers would overflow again
-          if (j->status == AH_OK)
-            j->status = ah::set_error(AH_ERR_LIMIT,
-                                      "a part of job %llu overflows buffers sized for its "
-                                      "counts (%llu sites, %llu amplicons)",
-                                      (unsigned long long)j->id,
-                                      (unsigned long long)hr[0].required,
-                                      (unsigned long long)hr[1].required);
-        } else {
-          p.hcap = std::max<uint64_t>(p.hcap, hr[0].required);
-          p.acap = std::max<uint64_t>(p.acap, hr[1].required);
-          j->redo.push_back(pi);
-          j->retries++;
-          stats.retries++;
-          if (!j->queued) {
-            j->queued = true;
-            active.push_back(j->id);
-          }
-        }
-      } else {
-        p.done = true;
-        j->done_parts++;
-        j->hits += p.n_hits;
-        j->amps += p.n_amps;
-      }
-      if (j->in_flight == 0 && (j->status != AH_OK || j->done_parts == j->parts.size())) {
-        if (j->status != AH_OK)
-          for (Part& q : j->parts) drop_records(q);  // a failed job returns no records
-        finish(*j);
-      }
+      settle(*j, pi, blk, bytes, s, hr);
       cv_lane.notify_all();
     }
     lk.unlock();
@@ -737,6 +761,132 @@ void ah_server_destroy(ah_server* srv) {
   for (std::thread& t : srv->threads) t.join();
   if (srv->arena) (void)hipHostFree(srv->arena);
   delete srv;
+}
+
+ah_status ah_sched_simulate(const ah_sched_job* jobs, uint32_t n_jobs, const ah_sched_part* parts,
+                            uint32_t n_parts, uint32_t n_lanes, uint64_t pool_bytes,
+                            ah_sched_event* events, uint64_t max_events, uint64_t* n_events,
+                            ah_job_status* done) {
+  ah::clear_error();
+  if ((n_jobs && !jobs) || (n_parts && !parts) || !n_events || (n_jobs && !done) ||
+      (max_events && !events))
+    return ah::set_error(AH_ERR_INVALID_ARG, "ah_sched_simulate: null argument");
+  if (n_lanes < 1 || n_lanes > 16)
+    return ah::set_error(AH_ERR_INVALID_ARG, "n_lanes must be 1..16");
+  std::vector<uint32_t> order(n_jobs);
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    if ((uint64_t)jobs[i].first_part + jobs[i].n_parts > n_parts || !(jobs[i].arrival >= 0.0))
+      return ah::set_error(AH_ERR_INVALID_ARG, "job %u: parts out of range or bad arrival", i);
+    order[i] = i;
+  }
+  for (uint32_t q = 0; q < n_parts; ++q)
+    if (!(parts[q].seconds >= 0.0))
+      return ah::set_error(AH_ERR_INVALID_ARG, "part %u: bad run time", q);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint32_t a, uint32_t b) { return jobs[a].arrival < jobs[b].arrival; });
+  ah_server srv;  // no device, no threads: only the scheduling state
+  srv.pool = Pool(pool_bytes & ~255ull);
+  srv.stats.pool_bytes = srv.pool.bytes();
+  srv.sim_now = 0.0;
+  std::vector<uint32_t> overflows_left(n_parts);
+  for (uint32_t q = 0; q < n_parts; ++q) overflows_left[q] = parts[q].overflows;
+  struct Lane {
+    bool busy = false;
+    double until = 0.0;
+    Job* j = nullptr;
+    uint32_t pi = 0, spec = 0;
+    uint64_t blk = 0, bytes = 0;
+  };
+  std::vector<Lane> lanes(n_lanes);
+  std::vector<uint32_t> runs(n_parts, 0);
+  auto spec_of = [&](const Job& j, uint32_t pi) { return jobs[j.id - 1].first_part + pi; };
+  auto size_of = [&](const Job& j, uint32_t pi) { return parts[spec_of(j, pi)].bytes; };
+  uint64_t ne = 0;
+  size_t next_arrival = 0;
+  std::unique_lock<std::mutex> lk(srv.mu);  // the decisions expect it held
+  for (;;) {
+    double t = std::numeric_limits<double>::infinity();
+    if (next_arrival < order.size()) t = jobs[order[next_arrival]].arrival;
+    for (const Lane& l : lanes)
+      if (l.busy) t = std::min(t, l.until);
+    if (t == std::numeric_limits<double>::infinity()) break;
+    srv.sim_now = t;
+    for (Lane& l : lanes) {  // part runs that end now
+      if (!l.busy || l.until > t) continue;
+      ah_result hr[2] = {};
+      Part& p = l.j->parts[l.pi];
+      if (overflows_left[l.spec] > 0) {  // the run reports more sites than it had room for
+        overflows_left[l.spec]--;
+        hr[0].status = AH_ERR_OVERFLOW;
+        hr[0].required = p.hcap + 1;
+      }
+      srv.settle(*l.j, l.pi, l.blk, l.bytes, AH_OK, hr);
+      l.busy = false;
+    }
+    while (next_arrival < order.size() && jobs[order[next_arrival]].arrival <= t) {
+      const uint32_t i = order[next_arrival++];
+      auto j = std::make_unique<Job>();
+      j->id = (uint64_t)i + 1;
+      j->t_submit = j->t_ready = t;
+      for (uint32_t q = 0; q < jobs[i].n_parts; ++q) {
+        Part p;
+        p.hcap = 1;  // an overflow asks for one more
+        p.acap = 1;
+        j->parts.push_back(p);
+      }
+      Job* jp = j.get();
+      srv.jobs[jp->id] = std::move(j);
+      srv.stats.jobs_submitted++;
+      if (jp->has_work()) {
+        jp->queued = true;
+        srv.active.push_back(jp->id);
+      } else {
+        jp->t_start = t;
+        srv.finish(*jp);
+      }
+    }
+    for (uint32_t li = 0; li < n_lanes; ++li) {  // idle lanes take the next parts
+      Lane& l = lanes[li];
+      if (l.busy) continue;
+      if (!srv.take_next(size_of, l.j, l.pi, l.blk, l.bytes)) break;
+      l.spec = spec_of(*l.j, l.pi);
+      l.busy = true;
+      l.until = t + parts[l.spec].seconds;
+      if (ne < max_events) {
+        ah_sched_event& e = events[ne];
+        e.t_start = t;
+        e.t_end = l.until;
+        e.lane = li;
+        e.job = (uint32_t)(l.j->id - 1);
+        e.part = l.pi;
+        e.run = runs[l.spec];
+        e.block = l.blk;
+        e.bytes = l.bytes;
+        e.pool_in_use = srv.pool.in_use();
+      }
+      ++ne;
+      runs[l.spec]++;
+    }
+  }
+  *n_events = ne;
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    ah_job_status& d = done[i];
+    memset(&d, 0, sizeof d);
+    auto it = srv.jobs.find((uint64_t)i + 1);
+    if (it == srv.jobs.end()) continue;
+    const Job& j = *it->second;
+    d.job = i;
+    d.status = j.finished ? j.status : AH_ERR_AGAIN;
+    d.n_parts = (uint32_t)j.parts.size();
+    d.t_submit = j.t_submit;
+    d.t_ready = j.t_ready;
+    d.t_start = j.t_start;
+    d.t_done = j.t_done;
+    d.retries = j.retries;
+  }
+  return ne > max_events ? ah::set_error(AH_ERR_OVERFLOW, "%llu events > %llu given",
+                                         (unsigned long long)ne, (unsigned long long)max_events)
+                         : AH_OK;
 }
 
 }  // extern "C"

@@ -36,7 +36,7 @@
 // Macros supplied by the generated program: AH_U (window words per lane, odd
 // so that the lanes' LDS reads fall in distinct banks), AH_HALO (longest
 // primer - 1), AH_HAS_N (1 if the collection has non-ACGT bases, whose
-// positions mismatch every primer position).
+// positions mismatch every primer position), AH_WAVE (1: wave mode, below).
 
 typedef unsigned int u32;
 typedef unsigned long long u64;
@@ -50,6 +50,41 @@ typedef unsigned long long u64;
 // own: atomics to one line serialise.
 #define AH_SLICE_GROUP 64
 #define AH_GROUP_STRIDE 32
+// Candidate slices per workgroup of the filter: one per wave in wave mode.
+// The verify and emit passes run one workgroup per filter workgroup and
+// read its slices in order as one list.
+#if AH_WAVE
+#define AH_SPW (AH_BLOCK / 64)
+#else
+#define AH_SPW 1
+#endif
+
+// Counts of the AH_SPW slices of workgroup b, and their total.
+struct AhSlices {
+  u32 n[AH_SPW];
+  u32 total;
+};
+__device__ __forceinline__ AhSlices ah_slices(const u32* __restrict__ slice_count, u32 b) {
+  AhSlices r;
+  r.total = 0;
+#pragma unroll
+  for (int q = 0; q < AH_SPW; ++q) {
+    r.n[q] = slice_count[b * AH_SPW + q];
+    r.total += r.n[q];
+  }
+  return r;
+}
+// Index into the candidate list of the i-th candidate of workgroup b's slices.
+__device__ __forceinline__ u64 ah_slice_at(const AhSlices& sl, u32 b, u32 slice, u32 i) {
+  u32 q = 0;
+#pragma unroll
+  for (int k = 0; k + 1 < AH_SPW; ++k)
+    if (q == (u32)k && i >= sl.n[k]) {  // past slice k (constant indices only)
+      i -= sl.n[k];
+      q = (u32)k + 1u;
+    }
+  return (u64)(b * AH_SPW + q) * slice + i;
+}
 
 // Must match ah_result in ah.h.
 struct AhResult {
@@ -80,12 +115,15 @@ struct AhCtx {
                     // every segment iff t + L <= tail
 };
 
-// Candidate list: one record per (window word, pattern) with at least one
-// window that passed the filter; workgroup b owns records [b * slice, (b + 1)
-// * slice).
+// Candidate list: one 32-byte record per (window word, quad of patterns p0 ..
+// p0 + 3) where the filter of at least one of the four passed a window: two
+// uint4, {genome, window word, p0, 0} and the four patterns' window masks
+// (0 for patterns past the set's last).  Slice s owns records [s * slice,
+// (s + 1) * slice).
 struct AhCands {
-  uint4* out;   // {genome, window word, pattern, window mask}
-  u32 slice;    // records per workgroup
+  uint4* out;   // 2 uint4 per record
+  u32 slice;    // records per workgroup (per wave in wave mode)
+  u64* win;     // wave mode: windows of the candidates a full slice dropped, per slice
 };
 
 // This workgroup's candidate count and the windows in them.
@@ -156,14 +194,42 @@ __device__ __forceinline__ u32 ah_tile_genome(const u64* __restrict__ tile_prefi
   return lo;
 }
 
-__device__ __forceinline__ void ah_cand(const AhCtx& c, const AhCands& k, u32 t, u32 pattern,
-                                        u32 cand) {
+__device__ __forceinline__ void ah_cand(const AhCtx& c, const AhCands& k, u32 t, u32 p0, u32 m0,
+                                        u32 m1, u32 m2, u32 m3) {
   if (t >= c.S) return;  // lanes past the genome's last window word
   const u32 slot = atomicAdd(&ah_n_cand, 1u);
-  if (slot < k.slice)
-    k.out[(u64)blockIdx.x * k.slice + slot] = make_uint4(c.g, t, pattern, cand);
-  else
-    atomicAdd(&ah_n_lost, (unsigned long long)__popc(cand));
+  if (slot < k.slice) {
+    uint4* o = k.out + 2 * ((u64)blockIdx.x * k.slice + slot);
+    o[0] = make_uint4(c.g, t, p0, 0u);
+    o[1] = make_uint4(m0, m1, m2, m3);
+  } else {
+    atomicAdd(&ah_n_lost, (unsigned long long)(__popc(m0) + __popc(m1) + __popc(m2) + __popc(m3)));
+  }
+}
+
+// Wave mode: append the lanes' candidates of the quad of patterns p0 .. p0 +
+// 3 to slice s, owned by this wave alone; cnt (wave-uniform: every lane
+// calls this) counts the records offered so far, kept or not, and the new
+// count is returned.  Slots come from a ballot over the wave, so nothing on
+// this path touches LDS (an LDS access here would also wait for the wave's
+// copy of its next tile to land).
+__device__ __forceinline__ u32 ah_wcand(const AhCtx& c, const AhCands& k, u32 t, u32 p0, u32 m0,
+                                        u32 m1, u32 m2, u32 m3, u32 cnt, u32 s) {
+  const bool ok = (m0 | m1 | m2 | m3) != 0u && t < c.S;  // t >= S: past the genome, or lane 63
+  const u64 m = __ballot(ok);
+  if (ok) {
+    const u32 slot = cnt + __builtin_amdgcn_mbcnt_hi((u32)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((u32)m, 0u));
+    if (slot < k.slice) {
+      uint4* o = k.out + 2 * ((u64)s * k.slice + slot);
+      o[0] = make_uint4(c.g, t, p0, 0u);
+      o[1] = make_uint4(m0, m1, m2, m3);
+    } else {
+      atomicAdd(&k.win[s],
+                (unsigned long long)(__popc(m0) + __popc(m1) + __popc(m2) + __popc(m3)));
+    }
+  }
+  return cnt + (u32)__popcll(m);
 }
 
 // Bit planes of a packed word: bit b of the one-hot planes a/c/g/t is set iff
@@ -220,6 +286,126 @@ __device__ __forceinline__ void ah_stage(const AhCtx& c, u32 t0, uint4* tw) {
   }
 }
 
+#if AH_WAVE
+// ---- wave mode (AH_WAVE = 1): every wave of the workgroup scans wave tiles
+// of its own, with no workgroup barrier.  A wave tile is 63 x AH_U window
+// words: lane i < 63 filters the AH_U words [i AH_U, (i + 1) AH_U) of it and
+// lane 63 only holds the words after the tile.  The wave stages 64 x AH_U
+// words (plus one when the tile starts at an odd word, to keep 16-byte copies
+// aligned) in its own LDS slice; each lane converts its own words to one-hot
+// planes once, and reads the planes of the words past its range (at most
+// AH_U, since AH_U >= the longest primer - 1) from the next lane's registers
+// with ds_bpermute, which moves data between the lanes of a wave without
+// using the vector ALU.  Once every lane holds its planes, the LDS slice is
+// free: the copy of the wave's next tile is issued then and lands while the
+// steps run from registers.
+#define AH_WTILE (63u * (u32)AH_U)
+#define AH_WSTAGE_PAIRS (32 * AH_U + 1)
+#define AH_WSTAGE_ROUNDS ((AH_WSTAGE_PAIRS + 63) / 64)
+
+// s_waitcnt immediates (gfx9 family: vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8; a field at its maximum does not wait)
+#define AH_WAIT_VMCNT0 0x0F70
+#define AH_WAIT_LGKMCNT0 0xC07F
+
+// Copy wave tile words [t0 & ~1, (t0 & ~1) + 2 AH_WSTAGE_PAIRS) of genome c into
+// this wave's LDS slice, 16 bytes per lane and instruction (the hardware puts
+// lane i at base + 16 i); indices past the genome's allocation are clamped
+// (only lanes whose windows lie past the genome read them).
+__device__ __forceinline__ void ah_wstage(const AhCtx& c, u32 t0, uint4* my, u32 lane) {
+  const u32 last_pair = ((c.S + 31u + 1u) >> 1) - 1u;
+  const uint4* gp = (const uint4*)c.gw + (t0 >> 1);
+  const u32 room = last_pair - (t0 >> 1);
+#pragma unroll
+  for (int k = 0; k < AH_WSTAGE_ROUNDS; ++k) {
+    const u32 i = lane + 64u * (u32)k;
+    if (i < AH_WSTAGE_PAIRS)
+      __builtin_amdgcn_global_load_lds((ah_global_void*)(gp + min(i, room)),
+                                       (ah_lds_void*)(my + 64u * (u32)k), 16, 0, 0);
+  }
+}
+
+// The next stage of a wave: genome context and first window word of the
+// wave's next tile (valid = 0 when the wave has none).
+struct AhNext {
+  AhCtx c;
+  u32 t0;
+  u32 valid;
+};
+
+// Generated: every group of patterns in turn converts this lane's words of
+// the staged wave tile and filters them, appending candidates to slice s
+// (cnt of them so far; returns the new count); the last group issues the copy
+// of the next tile (`nx`) into `my` once its words are in registers.
+__device__ u32 ah_wgroups(ah_lds_uint2* tw, u32 t0, const AhCtx& c, const AhCands& k, u32 lane,
+                          uint4* my, const AhNext& nx, u32 cnt, u32 s);
+
+// Wave tile of round r for wave `wv` of workgroup b: with a grid that is a
+// multiple of the 8 XCDs (workgroups are placed on them round robin), the
+// waves of one XCD take consecutive tiles, so the words a tile shares with the
+// next (the last lane's) are read from the same L2.
+__device__ __forceinline__ u64 ah_wtile(u64 r, u32 b, u32 wv) {
+  const u64 V = (u64)gridDim.x * 4u;
+  if ((gridDim.x & 7u) == 0u) {
+    const u32 vx = (gridDim.x >> 3) * 4u;
+    return r * V + (u64)(b & 7u) * vx + (u64)(b >> 3) * 4u + wv;
+  }
+  return r * V + (u64)b * 4u + wv;
+}
+
+extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
+    const uint2* __restrict__ words, const u32* __restrict__ nmask,
+    const u64* __restrict__ word_off, const u32* __restrict__ len,
+    const u64* __restrict__ tile_prefix, u32 n_genomes, uint4* __restrict__ cand_out,
+    u32 slice, u32* __restrict__ slice_count, u32* __restrict__ slice_total,
+    u64* __restrict__ slice_win, u64* __restrict__ group_sites) {
+  // Each wave owns candidate slice s = 4 b + wave (slice records each) and
+  // reports it as a workgroup does in tile mode; the verify and emit passes
+  // read the four slices of a workgroup as one list.
+  __shared__ uint4 tiles[AH_BLOCK / 64][AH_WSTAGE_PAIRS];
+  const u64 n_tiles = tile_prefix[n_genomes];
+  const AhCands k{cand_out, slice, slice_win};
+  const u32 wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const u32 lane = threadIdx.x & 63u;
+  const u32 s = blockIdx.x * (AH_BLOCK / 64) + wv;
+  uint4* my = tiles[wv];
+  if (lane == 0) {
+    slice_win[s] = 0;  // windows of dropped candidates, added by ah_wcand
+    if (wv == 0 && blockIdx.x % AH_SLICE_GROUP == 0)  // summed by the verify pass
+      group_sites[(blockIdx.x / AH_SLICE_GROUP) * AH_GROUP_STRIDE] = 0;
+  }
+  __builtin_amdgcn_s_waitcnt(AH_WAIT_VMCNT0);  // the zero is in place before any atomic on it
+  u32 cnt = 0;
+  u32 lo = 0;
+  u64 r = 0;
+  u64 T = ah_wtile(r, blockIdx.x, wv);
+  AhNext cur;
+  cur.valid = T < n_tiles ? 1u : 0u;
+  if (cur.valid) {
+    const u32 g = ah_tile_genome(tile_prefix, n_genomes, T, lo);
+    cur.c = ah_ctx(words, nmask, word_off, len, g);
+    cur.t0 = (u32)(T - tile_prefix[g]) * AH_WTILE;
+    ah_wstage(cur.c, cur.t0, my, lane);
+  }
+  while (cur.valid) {
+    AhNext nx;
+    const u64 Tn = ah_wtile(++r, blockIdx.x, wv);
+    nx.valid = Tn < n_tiles ? 1u : 0u;
+    if (nx.valid) {
+      const u32 g = ah_tile_genome(tile_prefix, n_genomes, Tn, lo);
+      nx.c = ah_ctx(words, nmask, word_off, len, g);
+      nx.t0 = (u32)(Tn - tile_prefix[g]) * AH_WTILE;
+    }
+    __builtin_amdgcn_s_waitcnt(AH_WAIT_VMCNT0);  // this wave's copies have landed
+    cnt = ah_wgroups((ah_lds_uint2*)my + (cur.t0 & 1u), cur.t0, cur.c, k, lane, my, nx, cnt, s);
+    cur = nx;
+  }
+  if (lane == 0) {  // every wave reports its slice, with or without tiles
+    slice_count[s] = min(cnt, slice);
+    slice_total[s] = cnt;
+  }
+}
+#else
 extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     const uint2* __restrict__ words, const u32* __restrict__ nmask,
     const u64* __restrict__ word_off, const u32* __restrict__ len,
@@ -228,7 +414,7 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     u64* __restrict__ slice_win, u64* __restrict__ group_sites) {
   __shared__ uint4 tile[AH_STAGE_PAIRS];
   const u64 n_tiles = tile_prefix[n_genomes];
-  const AhCands k{cand_out, slice};
+  const AhCands k{cand_out, slice, nullptr};
   if (threadIdx.x == 0) {
     ah_n_cand = 0;
     ah_n_lost = 0;
@@ -253,6 +439,7 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     slice_win[blockIdx.x] = ah_n_lost;  // the verify kernel adds the kept ones
   }
 }
+#endif
 
 extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
     const uint2* __restrict__ words, const u32* __restrict__ nmask,
@@ -277,17 +464,22 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
     s_win = 0;
   }
   __syncthreads();
-  const u32 n = slice_count[blockIdx.x];
-  const uint4* mine = cands + (u64)blockIdx.x * slice;
-  u32* sites = cand_sites + (u64)blockIdx.x * slice;
+  const AhSlices sl = ah_slices(slice_count, blockIdx.x);
   u64 my_sites = 0, my_win = 0;
-  for (u32 i = threadIdx.x; i < n; i += AH_BLOCK) {
-    const uint4 e = mine[i];
+  for (u32 i = threadIdx.x; i < sl.total; i += AH_BLOCK) {
+    const u64 at = ah_slice_at(sl, blockIdx.x, slice, i);
+    const uint4 e = cands[2 * at], mk = cands[2 * at + 1];
     const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
-    const u32 found = ah_verify_one(c, c.gw + e.y, e.y, e.z, e.w, nullptr, 0, 0, false);
-    sites[i] = found;
+    const u32 m[4] = {mk.x, mk.y, mk.z, mk.w};
+    u32 found = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (m[q]) {
+        found += ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], nullptr, 0, 0, false);
+        my_win += (u64)__popc(m[q]);
+      }
+    cand_sites[at] = found;
     my_sites += found;
-    my_win += (u64)__popc(e.w);
   }
   if (my_sites) atomicAdd(&s_sites, my_sites);
   atomicAdd(&s_win, my_win);
@@ -295,7 +487,7 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
   if (threadIdx.x == 0) {
     slice_sites[blockIdx.x] = s_sites;
     if (s_sites) atomicAdd(&group_sites[(blockIdx.x / AH_SLICE_GROUP) * AH_GROUP_STRIDE], s_sites);
-    slice_win[blockIdx.x] += s_win;
+    slice_win[blockIdx.x * AH_SPW] += s_win;  // the statistics sum over every slice
   }
 }
 
@@ -366,9 +558,10 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
   }
   if (blockIdx.x == 0) {
     // candidate-list statistics: candidates, their windows, full slices, most
-    // of one workgroup
+    // of one slice
+    const u32 GS = G * AH_SPW;  // slices
     u64 c = 0, wn = 0, full = 0, mx = 0;
-    for (u32 w = threadIdx.x; w < G; w += AH_BLOCK) {
+    for (u32 w = threadIdx.x; w < GS; w += AH_BLOCK) {
       const u64 t = slice_total[w];
       c += t;
       wn += slice_win[w];
@@ -397,8 +590,8 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
       cand_stat[1] = sw;
       cand_stat[2] = sf;
       cand_stat[3] = mx;
-      if (sf > 0) {  // dropped candidates: sites <= windows, list >= G x most
-        const u64 list = (u64)G * mx;
+      if (sf > 0) {  // dropped candidates: sites <= windows, list >= slices x most
+        const u64 list = (u64)GS * mx;
         const u64 bound = sw > list ? sw : list;
         if (bound > res->required) res->required = bound;
         res->status = AH_RES_OVERFLOW;
@@ -406,19 +599,23 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
     }
     __syncthreads();  // thread 0 has read tmp before the loop below reuses it
   }
-  // the slice's candidates with sites, in order, written from `slot` on
-  const u32 n = slice_count[blockIdx.x];
-  const uint4* mine = cands + (u64)blockIdx.x * slice;
-  const u32* sites = cand_sites + (u64)blockIdx.x * slice;
+  // the slices' candidates with sites, in order, written from `slot` on
+  const AhSlices sl = ah_slices(slice_count, blockIdx.x);
+  const u32 n = sl.total;
   for (u32 r = 0; r < n; r += AH_BLOCK) {
     const u32 i = r + threadIdx.x;
-    const u32 f = i < n ? sites[i] : 0u;
+    const u64 at = i < n ? ah_slice_at(sl, blockIdx.x, slice, i) : 0ull;
+    const u32 f = i < n ? cand_sites[at] : 0u;
     u64 rt;
     const u64 off = ah_block_scan(f, tmp, &rt);
     if (f) {
-      const uint4 e = mine[i];
+      const uint4 e = cands[2 * at], mk = cands[2 * at + 1];
       const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
-      ah_verify_one(c, c.gw + e.y, e.y, e.z, e.w, out, cap, slot + off, true);
+      const u32 m[4] = {mk.x, mk.y, mk.z, mk.w};
+      u64 q_slot = slot + off;  // the quad's patterns in order
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (m[q]) q_slot += ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], out, cap, q_slot, true);
       if (sort_keys) {  // keys of the records just written (read back by their writer)
         const u64 end = slot + off + f < cap ? slot + off + f : cap;
         for (u64 q = slot + off; q < end; ++q) {

@@ -163,15 +163,16 @@ def test_tight_pool_admission_changes_nothing(world, dev):
         ref = serve_all(srv, jobs)
     finally:
         srv.close()
-    # 2.5 MiB admits two parts (~1.2 MiB each) at a time on four lanes
-    srv = path.Server(c, 5 << 19, dev, n_lanes=4, part_bases=400_000)
+    # 5 MiB admits two parts (~2.4 MiB each, most of it the candidate list of
+    # at least 2^16 records) at a time on four lanes
+    srv = path.Server(c, 5 << 20, dev, n_lanes=4, part_bases=400_000)
     try:
         got = serve_all(srv, jobs)
         st = srv.stats()
     finally:
         srv.close()
     say("tight stats", st)
-    assert st["admission_waits"] > 0 and st["pool_high_water"] <= 5 << 19
+    assert st["admission_waits"] > 0 and st["pool_high_water"] <= 5 << 20
     for i in range(len(jobs)):
         assert np.array_equal(got[i][0], ref[i][0]) and np.array_equal(got[i][1], ref[i][1]), i
 
