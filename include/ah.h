@@ -192,6 +192,28 @@ typedef struct ah_result {
 ah_status ah_scan_primers(const ah_genomes* genomes, const ah_primer_pair* pairs,
                           uint32_t n_pairs, ah_hit* d_hits, uint64_t capacity,
                           ah_result* d_res, void* d_work, size_t work_bytes, void* stream);
+/* ah_scan_primers for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid allocation):
+ * the same sites in the same order, with the workspace taken from a scratch
+ * array of AH_SCAN_SCRATCH_BYTES bytes that the library holds on each device
+ * (part of its code object, so it is reserved on a device with the library's
+ * kernels and kept until the process ends).  The call allocates nothing: the
+ * primer set's kernels must already be compiled and loaded on the current
+ * device (by ah_scan_prepare, or an earlier ah_scan_primers call with the same
+ * set and shape), else AH_ERR_INVALID_ARG; profiling events (ah_profile_*) are
+ * not recorded for it.  Its candidate list is the part of the array that the
+ * fixed parts for n genomes and `capacity` sites leave; AH_ERR_WORKSPACE if
+ * those parts do not fit with at least max(capacity, 2^16) candidates.
+ * Every call on a device uses that device's one array, and nothing in it has
+ * to start at any value: calls that overlap in time on one device (different
+ * streams, or host threads) race and give unspecified results; enqueue them
+ * on one stream or synchronise between them.  Errors: those of
+ * ah_scan_primers, AH_ERR_WORKSPACE as above. */
+enum { AH_SCAN_SCRATCH_BYTES = 64 << 20 };
+ah_status ah_scan_primers_noalloc(const ah_genomes* genomes, const ah_primer_pair* pairs,
+                                  uint32_t n_pairs, ah_hit* d_hits, uint64_t capacity,
+                                  ah_result* d_res, void* stream);
+
 /* Recommended workspace: the fixed parts for `capacity` sites plus a
  * candidate list of twice the records that the filters of `pairs` are
  * expected to pass on random bases, over at most n x ceil(max_len / 32)

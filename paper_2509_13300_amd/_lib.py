@@ -143,7 +143,7 @@ EXPORTS = (
     "ah_server_wait", "ah_server_part", "ah_server_release", "ah_server_stats_get",
     "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats", "ah_scan_candidate_capacity",
     "ah_fasta_workspace_bytes", "ah_amplicon_fasta", "ah_fasta_count", "ah_fasta_read",
-    "ah_tm_duplex", "ah_validate_tm", "ah_sched_simulate",
+    "ah_tm_duplex", "ah_validate_tm", "ah_scan_primers_noalloc", "ah_sched_simulate",
 )
 
 _lib = None
@@ -165,6 +165,8 @@ def lib() -> ctypes.CDLL:
     L.ah_pack_genomes.restype = st
     L.ah_scan_primers.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, vp, u64, vp, vp, sz, vp]
     L.ah_scan_primers.restype = st
+    L.ah_scan_primers_noalloc.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, vp, u64, vp, vp]
+    L.ah_scan_primers_noalloc.restype = st
     L.ah_scan_workspace_bytes.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, u64]
     L.ah_scan_workspace_bytes.restype = sz
     L.ah_tm.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, P(ah_tm_params), vp, vp, u64, vp]
@@ -339,6 +341,13 @@ def ah_scan_primers(genomes: ah_genomes, pairs, hits, capacity: int, res, work, 
     _check(lib().ah_scan_primers(ctypes.byref(genomes), pp, len(pp), _ptr(hits), int(capacity),
                                  _ptr(res), _ptr(work), 0 if work is None else work.numel(),
                                  _stream(stream)), "ah_scan_primers")
+
+
+def ah_scan_primers_noalloc(genomes: ah_genomes, pairs, hits, capacity: int, res, stream=None):
+    pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
+    _check(lib().ah_scan_primers_noalloc(ctypes.byref(genomes), pp, len(pp), _ptr(hits),
+                                         int(capacity), _ptr(res), _stream(stream)),
+           "ah_scan_primers_noalloc")
 
 
 def ah_tm(genomes: ah_genomes, pairs, params: ah_tm_params, hits, nhits, capacity: int,

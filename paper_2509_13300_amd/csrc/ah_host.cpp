@@ -1075,6 +1075,30 @@ ah_status scan_kernels_for(const ah_primer_pair* pairs, uint32_t n_pairs, const 
   return AH_OK;
 }
 
+// The kernels of a primer set when they are already loaded on the current
+// device (nothing is compiled or loaded).
+bool find_scan_kernels(const ah_primer_pair* pairs, uint32_t n_pairs, const PairSet& ps,
+                       bool has_n, Tuning tn, ScanFns& fn) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  const auto key = std::make_pair(dev, fns_key(set_key(pairs, n_pairs), has_n, tn));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_fns.find(key);
+    if (it != g_fns.end()) {
+      fn = it->second;
+      return true;
+    }
+  }
+  const std::string src = gen_program(patterns_of(ps), has_n, tn);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_jit.find(std::make_pair(dev, src));
+  if (it == g_jit.end()) return false;
+  fn = it->second.fn;
+  g_fns[key] = fn;
+  return true;
+}
+
 ah_status get_scan_kernel(const std::string& src, ScanFns& fn) {
   int dev = 0;
   AH_HIP(hipGetDevice(&dev));
@@ -1171,11 +1195,15 @@ hipEvent_t take_event() {
 }
 
 // Brackets one or more launches on `st` with events when profiling is on.
+// Set while a call that must not create HIP objects runs on this thread.
+thread_local bool t_prof_off = false;
+
 struct ProfScope {
   const char* name;
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
+    if (t_prof_off) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return;
     a = take_event();
@@ -1722,6 +1750,48 @@ ah_status ah_scan_primers(const ah_genomes* g, const ah_primer_pair* pairs, uint
   s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st, &kb);
   if (s) return s;
   ProfScope prof_sort("sort", st);
+  AH_HIP(ah::launch_sort_hits(w.staging, d_hits, w.n_sort, kb, w.sb, st));
+  return AH_OK;
+}
+
+ah_status ah_scan_primers_noalloc(const ah_genomes* g, const ah_primer_pair* pairs,
+                                  uint32_t n_pairs, ah_hit* d_hits, uint64_t capacity,
+                                  ah_result* d_res, void* stream) {
+  g_err.clear();
+  ah_status s = check_genomes(g);
+  if (s) return s;
+  if (!d_res) return fail(AH_ERR_INVALID_ARG, "d_res is NULL");
+  if (capacity > 0 && !d_hits) return fail(AH_ERR_INVALID_ARG, "d_hits is NULL");
+  if (capacity >= (1ull << 32)) return fail(AH_ERR_LIMIT, "hit capacity must be < 2^32");
+  PairSet ps;
+  s = compile_pairs(pairs, n_pairs, ps);
+  if (s) return s;
+  ah::KeyBits kb{bits_for(n_pairs - 1), bits_for(g->n ? g->n - 1 : 0), bits_for(g->max_len)};
+  if (kb.total() > 64) return fail(AH_ERR_LIMIT, "sort key needs %d > 64 bits", kb.total());
+  const size_t need = scan_ws_bytes(g->n, capacity, min_cands(capacity));
+  if (need > (size_t)AH_SCAN_SCRATCH_BYTES)
+    return fail(AH_ERR_WORKSPACE,
+                "ah_scan_primers_noalloc: %u genomes and capacity %llu need %zu bytes of "
+                "workspace; the scratch array holds %d",
+                g->n, (unsigned long long)capacity, need, (int)AH_SCAN_SCRATCH_BYTES);
+  const Tuning tn = tuning_for(pairs, n_pairs);
+  ScanFns fn;
+  if (!find_scan_kernels(pairs, n_pairs, ps, g->nmask != nullptr, tn, fn))
+    return fail(AH_ERR_INVALID_ARG,
+                "ah_scan_primers_noalloc: this primer set's kernels are not loaded on the current "
+                "device (ah_scan_prepare compiles and loads them)");
+  void* scratch = nullptr;
+  AH_HIP(ah::scan_scratch(&scratch));
+  struct NoProf {  // no profiling events: creating them is not allowed here
+    bool was;
+    NoProf() : was(t_prof_off) { t_prof_off = true; }
+    ~NoProf() { t_prof_off = was; }
+  } no_prof;
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(scratch, (size_t)AH_SCAN_SCRATCH_BYTES);
+  ScanWs w = carve_scan(c, g->n, capacity, 0);
+  s = launch_scan_kernel(fn, tn, g, w, d_res, capacity, st, &kb);
+  if (s) return s;
   AH_HIP(ah::launch_sort_hits(w.staging, d_hits, w.n_sort, kb, w.sb, st));
   return AH_OK;
 }

@@ -145,6 +145,11 @@ hipError_t launch_tile_prefix_small(const uint32_t* len, uint32_t n, uint32_t ti
 size_t scan_workspace_for(uint32_t n, uint64_t window_words, const ah_primer_pair* pairs,
                           uint32_t n_pairs, uint64_t capacity);
 
+// Device address of the current device's scratch array
+// (AH_SCAN_SCRATCH_BYTES bytes, the workspace of ah_scan_primers_noalloc),
+// looked up on the first call on each device.
+hipError_t scan_scratch(void** ptr);
+
 // Validation of a Tm request exactly as ah_tm does it, with no device work.
 ah_status check_tm(const ah_primer_pair* pairs, uint32_t n_pairs, const ah_tm_params* p);
 

@@ -4,6 +4,8 @@
 // run time (scan_core.hip).
 #include <math.h>
 
+#include <mutex>
+
 #include "ah_internal.h"
 
 namespace ah {
@@ -1188,6 +1190,37 @@ __global__ __launch_bounds__(kBlock) void k_remap(ah_hit* __restrict__ hits,
 // Runs after the result is finalised, so `count` stays the number of records
 // written; only `required` and `status` change.
 }  // namespace
+
+// --------------------------------------------------- scan scratch array --
+// Workspace of ah_scan_primers_noalloc: one array per device, part of the
+// library's code object (so it exists as soon as the library's kernels are
+// loaded on a device and lives until the process ends).  Host code never uses
+// the array's name as an address: scan_scratch() looks the device address up
+// once per device, with that device current, and hands out that address.
+static __device__ __align__(256) unsigned char scratch[AH_SCAN_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kScratchDevices] = {};
+}  // namespace
+
+hipError_t scan_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[dev] = p;
+  }
+  *ptr = g_scratch[dev];
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------- launchers ----
 hipError_t launch_pack(const uint8_t* ascii, const uint64_t* ascii_off, uint32_t n,
