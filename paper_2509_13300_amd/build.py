@@ -72,6 +72,11 @@ def build(verbose: bool = False) -> str:
         lang = ["-x", "hip"] if name.endswith(".hip") else []
         _run([HIPCC, *COMMON, *DEVFLAGS, *lang, "-c", src, "-o", obj])
         objs.append(obj)
+    # the compile helper: scan programs compile in processes of their own
+    helper = os.path.join(HERE, "ah_jitc")
+    _run([HIPCC, "-O2", "-std=c++17", os.path.join(CSRC, "ah_jitc.cpp"), "-o", helper + ".tmp",
+          "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
+    os.replace(helper + ".tmp", helper)
     lib = os.path.join(HERE, "libah.so")
     tmp = lib + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs,

@@ -5,8 +5,14 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <dlfcn.h>
+#include <spawn.h>
+#include <sys/wait.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <atomic>
+#include <cerrno>
 #include <chrono>
 #include <cstdlib>
 #include <cmath>
@@ -987,13 +993,95 @@ std::map<int, int> g_cus;
 
 std::mutex g_stats_mu;
 
+// The compile helper (ah_jitc) installed beside this library, or "" if
+// there is none.  hipRTC compiles one program at a time per process, so
+// concurrent compiles (several primer sets prepared at once, the serving
+// form's compile threads, the autotuner's shapes) only overlap when each runs
+// in a process of its own.
+const std::string& jit_helper() {
+  static const std::string path = [] {
+    Dl_info info;
+    if (!dladdr((const void*)&ah_status_str, &info) || !info.dli_fname) return std::string();
+    std::string p = info.dli_fname;
+    const size_t slash = p.rfind('/');
+    p = (slash == std::string::npos ? std::string(".") : p.substr(0, slash)) + "/ah_jitc";
+    return access(p.c_str(), X_OK) == 0 ? p : std::string();
+  }();
+  return path;
+}
+
+const char* const kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17"};
+
+// Compile in a child process running the helper: the source and the code
+// object travel through two temporary files.
+ah_status rtc_compile_child(const std::string& helper, const std::string& src,
+                            std::vector<char>& code) {
+  const char* tmp = getenv("TMPDIR");
+  std::string dir = tmp && tmp[0] ? tmp : "/tmp";
+  std::string in = dir + "/ah_jit_XXXXXX", out = dir + "/ah_jit_XXXXXX";
+  const int fi = mkstemp(&in[0]);
+  if (fi < 0) return fail(AH_ERR_JIT, "cannot create a temporary file in %s", dir.c_str());
+  const int fo = mkstemp(&out[0]);
+  if (fo < 0) {
+    close(fi);
+    unlink(in.c_str());
+    return fail(AH_ERR_JIT, "cannot create a temporary file in %s", dir.c_str());
+  }
+  close(fo);
+  struct Cleanup {
+    std::string a, b;
+    ~Cleanup() {
+      unlink(a.c_str());
+      unlink(b.c_str());
+    }
+  } cleanup{in, out};
+  size_t done = 0;
+  while (done < src.size()) {
+    const ssize_t w = write(fi, src.data() + done, src.size() - done);
+    if (w <= 0) {
+      close(fi);
+      return fail(AH_ERR_JIT, "cannot write the scan program to %s", in.c_str());
+    }
+    done += (size_t)w;
+  }
+  close(fi);
+  std::vector<char*> argv = {const_cast<char*>(helper.c_str()), &in[0], &out[0]};
+  for (const char* o : kRtcOpts) argv.push_back(const_cast<char*>(o));
+  argv.push_back(nullptr);
+  pid_t pid = 0;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (posix_spawn(&pid, helper.c_str(), nullptr, nullptr, argv.data(), environ) != 0)
+    return fail(AH_ERR_JIT, "cannot start %s", helper.c_str());
+  int wst = 0;
+  while (waitpid(pid, &wst, 0) < 0)
+    if (errno != EINTR) return fail(AH_ERR_JIT, "waiting for %s failed", helper.c_str());
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  std::vector<char> data;
+  if (FILE* f = fopen(out.c_str(), "rb")) {
+    char buf[1 << 16];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0) data.insert(data.end(), buf, buf + n);
+    fclose(f);
+  }
+  if (!WIFEXITED(wst) || WEXITSTATUS(wst) != 0) {
+    data.push_back('\0');
+    return fail(AH_ERR_JIT, "%.400s", data.size() > 1 ? data.data() : "the compile helper failed");
+  }
+  code.swap(data);
+  std::lock_guard<std::mutex> lk(g_stats_mu);
+  g_jit_n += 1;
+  g_jit_ms += ms;
+  return AH_OK;
+}
+
 ah_status rtc_compile(const std::string& src, std::vector<char>& code) {
+  if (!jit_helper().empty()) return rtc_compile_child(jit_helper(), src, code);
   hiprtcProgram prog;
   if (hiprtcCreateProgram(&prog, src.c_str(), "ah_scan.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
     return fail(AH_ERR_JIT, "hiprtcCreateProgram failed");
-  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17"};
   const auto t0 = std::chrono::steady_clock::now();
-  const hiprtcResult r = hiprtcCompileProgram(prog, 3, opts);
+  const hiprtcResult r = hiprtcCompileProgram(prog, 3, const_cast<const char**>(kRtcOpts));
   const double ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (r != HIPRTC_SUCCESS) {
