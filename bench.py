@@ -235,13 +235,15 @@ def gpu_run(name: str, steps: int, warmup: int):
             valu = d.get("sq_insts_valu_per_dispatch")
     # the same pass captured once into a hipGraph and replayed
     graph = path.capture(coll, [pr], buf)
-    graph.replay()
+    for _ in range(max(1, warmup)):
+        graph.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         graph.replay()
     torch.cuda.synchronize()
     ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+    # the records compared with the oracle below are those of the last replay
     assert path.result(buf.hit_res)["count"] == res_h["count"]
     hits = path.hits_numpy(buf)
     amps = path.amps_numpy(buf)
@@ -761,7 +763,7 @@ def _pass_summary(sts, span, rate=None) -> dict:
 
 def gpu_serve(n_genomes: int = 100000, n_jobs: int = 2000, sat_jobs: int = 240,
               main_frac: float = 0.7, sweep=(0.25, 0.5, 0.9), sweep_jobs: int = 500,
-              cold_jobs: int = 200, pool_gb: float = 48.0, host_gb: int = 48, n_lanes: int = 4):
+              cold_jobs: int = 200, pool_gb: float = 48.0, host_gb: int = 64, n_lanes: int = 4):
     """Serving form: the 100,000-genome collection resident in HBM; each job
     is one law pair over a log-uniform genome subset.  Protocol: saturation
     = jobs/s of a burst of the first ``sat_jobs`` jobs; then ``n_jobs``
@@ -1010,7 +1012,7 @@ def main():
               f"sequential", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         # serving: a short run of the protocol (the full one: --form serve)
-        sv = gpu_serve(n_jobs=240, sat_jobs=120, sweep=(), cold_jobs=40, host_gb=16)
+        sv = gpu_serve(n_jobs=240, sat_jobs=120, sweep=(), cold_jobs=40, host_gb=64)
         forms["serve"] = {"workload": SERVE_DESC + "; 120-job burst for saturation, 240 Poisson "
                                                    "jobs at 0.7 x saturation (warm), 40 with "
                                                    "every kernel compiled on request (cold)",
@@ -1018,16 +1020,18 @@ def main():
                                                 "warm_distinct_pairs", "build_s")}}
         print(f"serve: warm p99 {sv['main']['latency']['p99_ms']:.1f} ms, cold p99 "
               f"{sv['cold']['latency']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
-    print(f"gpu: {r['value']:.1f} Gbp/s, {r['ms_per_step']:.3f} ms/step, kernels {r['kernel_ms']}",
-          file=sys.stderr, flush=True)
+    g = r["graph_replay"]
+    print(f"gpu: {g['gbps']:.1f} Gbp/s, {g['ms_per_step']:.3f} ms/step replayed from a hipGraph "
+          f"({r['value']:.1f} Gbp/s, {r['ms_per_step']:.3f} ms launched call by call), kernels "
+          f"{r['kernel_ms']}", file=sys.stderr, flush=True)
     line = {
         "metric": METRIC,
-        "value": r["value"],
+        "value": g["gbps"],
         "unit": "Gbp/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["ms_per_step"],
+        "ms_per_step": g["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -1037,7 +1041,9 @@ def main():
             "workload": r["desc"], "genomes": r["genomes"], "total_bp": r["bp"],
             "pair": r["pair"], "form": "plain", "hits": r["hits"], "amplicons": r["amplicons"],
             "kernel_ms": r["kernel_ms"], "scan_candidates": r["scan_candidates"],
-            "graph_replay": r["graph_replay"],
+            "launch": "one hipGraph replay per step of the whole path (scan, sort, Tm, pairing), "
+                      "captured once; the same K steps launched call by call under 'eager'",
+            "eager": {"ms_per_step": r["ms_per_step"], "gbps": r["value"]},
             "ingest_pack": r["pack"], "jit": r["jit"],
             "tm_dtype": "f32 (compensated sums, f64 salt/log terms)",
             "oracle_equal": None if agree is None else agree["oracle_equal"],

@@ -322,6 +322,23 @@ ah_status ah_pair_amplicons(const ah_hit* d_hits, const ah_result* d_nhits, uint
                             ah_result* d_res, void* d_work, size_t work_bytes, void* stream);
 size_t ah_pair_workspace_bytes(uint64_t hit_capacity, uint32_t n_pairs);
 
+/* The whole query in one call: ah_scan_primers, ah_tm and ah_pair_amplicons
+ * of `pairs` (with `windows` and Tm parameters `tm`) in that order on
+ * `stream`, with the same outputs byte for byte (sites in d_hits and
+ * *d_hit_res, Tm included; amplicons in d_amp and *d_amp_res) and the same
+ * workspaces (ah_scan_workspace_bytes for hit_capacity, and
+ * ah_pair_workspace_bytes).  Knowing the whole query lets the library fold
+ * steps together: the melting temperature of each site is computed by extra
+ * workgroups of the canonical sort's first pass (on the records before they
+ * move), and the pairing's per-chunk counts of kept minus sites are taken by
+ * the sort's last pass as the records reach their places, which saves two
+ * launches.  Errors: those of the three calls. */
+ah_status ah_query(const ah_genomes* genomes, const ah_primer_pair* pairs, const ah_window* windows,
+                   uint32_t n_pairs, const ah_tm_params* tm, ah_hit* d_hits, uint64_t hit_capacity,
+                   ah_result* d_hit_res, ah_amplicon* d_amp, uint64_t amp_capacity,
+                   ah_result* d_amp_res, void* d_scan_work, size_t scan_work_bytes,
+                   void* d_pair_work, size_t pair_work_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Batched form: many primer pairs in one pass over the genomes (the paper's
  * future work, Section 4: analysing several primer pairs simultaneously so that

@@ -144,6 +144,7 @@ EXPORTS = (
     "ah_server_now", "ah_server_destroy", "ah_scan_candidate_stats", "ah_scan_candidate_capacity",
     "ah_fasta_workspace_bytes", "ah_amplicon_fasta", "ah_fasta_count", "ah_fasta_read",
     "ah_tm_duplex", "ah_validate_tm", "ah_scan_primers_noalloc", "ah_sched_simulate",
+    "ah_query",
 )
 
 _lib = None
@@ -171,6 +172,9 @@ def lib() -> ctypes.CDLL:
     L.ah_scan_workspace_bytes.restype = sz
     L.ah_tm.argtypes = [P(ah_genomes), P(ah_primer_pair), u32, P(ah_tm_params), vp, vp, u64, vp]
     L.ah_tm.restype = st
+    L.ah_query.argtypes = [P(ah_genomes), P(ah_primer_pair), P(ah_window), u32, P(ah_tm_params),
+                           vp, u64, vp, vp, u64, vp, vp, sz, vp, sz, vp]
+    L.ah_query.restype = st
     L.ah_tm_duplex.argtypes = [ctypes.c_char_p, ctypes.c_char_p, P(ah_tm_params),
                                P(ctypes.c_double)]
     L.ah_tm_duplex.restype = st
@@ -348,6 +352,17 @@ def ah_scan_primers_noalloc(genomes: ah_genomes, pairs, hits, capacity: int, res
     _check(lib().ah_scan_primers_noalloc(ctypes.byref(genomes), pp, len(pp), _ptr(hits),
                                          int(capacity), _ptr(res), _stream(stream)),
            "ah_scan_primers_noalloc")
+
+
+def ah_query(genomes: ah_genomes, pairs, wins, params: ah_tm_params, hits, hit_capacity: int,
+             hit_res, amps, amp_capacity: int, amp_res, scan_work, pair_work, stream=None):
+    pp = pairs if isinstance(pairs, ctypes.Array) else primer_pairs(pairs)
+    _check(lib().ah_query(ctypes.byref(genomes), pp, wins, len(pp), ctypes.byref(params),
+                          _ptr(hits), int(hit_capacity), _ptr(hit_res), _ptr(amps),
+                          int(amp_capacity), _ptr(amp_res), _ptr(scan_work),
+                          0 if scan_work is None else scan_work.numel(), _ptr(pair_work),
+                          0 if pair_work is None else pair_work.numel(), _stream(stream)),
+           "ah_query")
 
 
 def ah_tm(genomes: ah_genomes, pairs, params: ah_tm_params, hits, nhits, capacity: int,

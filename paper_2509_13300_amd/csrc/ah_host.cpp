@@ -1700,6 +1700,75 @@ ah_status check_tm_request(const ah_primer_pair* pairs, uint32_t n_pairs, const 
   return AH_OK;
 }
 
+// The Tm kernel's per-primer tables of a validated request (check_tm_request),
+// uploaded once per content (get_table).
+ah_status tm_table(const PairSet& ps, uint32_t n_pairs, const ah_tm_params& pp, void** dt) {
+  const ah_tm_params* p = &pp;
+  const SaltTerms salt_t = salt_terms(*p);
+  const double C = strand_conc(*p);
+  const double R = 1.987;
+  std::vector<ah::PrimerTab> tabs(2 * (size_t)n_pairs);
+  for (uint32_t q = 0; q < n_pairs; ++q) {
+    for (int primer = 0; primer < 2; ++primer) {
+      const Primer& pr = primer ? ps.rev[q] : ps.fwd[q];
+      ah::PrimerTab t;
+      memset(&t, 0, sizeof t);
+      t.L = (uint32_t)pr.L;
+      t.k = ps.k[q];
+      uint64_t deg = 1;
+      for (int j = 0; j < pr.L; ++j) {
+        const uint8_t m = pr.mask[j];
+        const int cnt = __builtin_popcount(m);
+        t.lanes |= 1ull << (2 * j);
+        if (j < pr.L - 1) t.stackm |= 1ull << (2 * j);
+        if (cnt == 1) {
+          t.fixed |= (uint64_t)__builtin_ctz(m) << (2 * j);
+        } else {
+          uint8_t packed = 0;
+          int r = 0;
+          for (int b = 0; b < 4; ++b)
+            if (m >> b & 1) packed |= (uint8_t)(b << (2 * r++));
+          t.dpos[t.nd] = (uint8_t)j;
+          t.nmem[t.nd] = (uint8_t)cnt;
+          t.mem[t.nd] = packed;
+          t.nd++;
+          deg *= (uint64_t)cnt;
+        }
+      }
+      for (uint32_t j = 0; j < ps.clamp[q]; ++j) t.clampm |= 1ull << (2 * (pr.L - 1 - (int)j));
+      t.deg = deg;
+      t.decoy = (ps.flags[q] & AH_PAIR_DECOY) ? 1u : 0u;
+      const double salt = p->saltcorr == 5 ? 0.368 * (pr.L - 1) * salt_t.ln_na : 0.0;
+      t.KL = salt + R * std::log(C) + (p->selfcomp ? -1.4 : 0.0);
+      t.tshift = salt_t.shift;
+      if (salt_t.recip) {
+        t.recip = 1;
+        t.rA = salt_t.a0 + salt_t.a_len / (2.0 * (pr.L - 1));
+        t.rB = salt_t.b;
+      }
+      tabs[2 * q + primer] = t;
+    }
+  }
+  return get_table(tabs.data(), tabs.size() * sizeof(ah::PrimerTab), dt);
+}
+
+// The pairing kernels' per-pair table (primer lengths, window, Tm filter),
+// uploaded once per content.
+ah_status pair_table(const PairSet& ps, const ah_window* windows, uint32_t n_pairs, void** dt) {
+  std::vector<ah::PairTab> tabs(n_pairs);
+  for (uint32_t q = 0; q < n_pairs; ++q) {
+    if (windows[q].min_len > windows[q].max_len)
+      return fail(AH_ERR_INVALID_ARG, "pair %u: min_len > max_len", q);
+    tabs[q].lf = (uint32_t)ps.fwd[q].L;
+    tabs[q].lr = (uint32_t)ps.rev[q].L;
+    tabs[q].min_len = windows[q].min_len;
+    tabs[q].max_len = windows[q].max_len;
+    tabs[q].filter_tm = windows[q].filter_tm ? 1 : 0;
+    tabs[q].min_tm = windows[q].min_tm;
+  }
+  return get_table(tabs.data(), tabs.size() * sizeof(ah::PairTab), dt);
+}
+
 }  // namespace
 
 namespace ah {
@@ -1895,53 +1964,8 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
   PairSet ps;
   s = check_tm_request(pairs, n_pairs, p, ps);
   if (s) return s;
-  const SaltTerms salt_t = salt_terms(*p);
-  const double C = strand_conc(*p);
-  const double R = 1.987;
-  std::vector<ah::PrimerTab> tabs(2 * (size_t)n_pairs);
-  for (uint32_t q = 0; q < n_pairs; ++q) {
-    for (int primer = 0; primer < 2; ++primer) {
-      const Primer& pr = primer ? ps.rev[q] : ps.fwd[q];
-      ah::PrimerTab t;
-      memset(&t, 0, sizeof t);
-      t.L = (uint32_t)pr.L;
-      t.k = ps.k[q];
-      uint64_t deg = 1;
-      for (int j = 0; j < pr.L; ++j) {
-        const uint8_t m = pr.mask[j];
-        const int cnt = __builtin_popcount(m);
-        t.lanes |= 1ull << (2 * j);
-        if (j < pr.L - 1) t.stackm |= 1ull << (2 * j);
-        if (cnt == 1) {
-          t.fixed |= (uint64_t)__builtin_ctz(m) << (2 * j);
-        } else {
-          uint8_t packed = 0;
-          int r = 0;
-          for (int b = 0; b < 4; ++b)
-            if (m >> b & 1) packed |= (uint8_t)(b << (2 * r++));
-          t.dpos[t.nd] = (uint8_t)j;
-          t.nmem[t.nd] = (uint8_t)cnt;
-          t.mem[t.nd] = packed;
-          t.nd++;
-          deg *= (uint64_t)cnt;
-        }
-      }
-      for (uint32_t j = 0; j < ps.clamp[q]; ++j) t.clampm |= 1ull << (2 * (pr.L - 1 - (int)j));
-      t.deg = deg;
-      t.decoy = (ps.flags[q] & AH_PAIR_DECOY) ? 1u : 0u;
-      const double salt = p->saltcorr == 5 ? 0.368 * (pr.L - 1) * salt_t.ln_na : 0.0;
-      t.KL = salt + R * std::log(C) + (p->selfcomp ? -1.4 : 0.0);
-      t.tshift = salt_t.shift;
-      if (salt_t.recip) {
-        t.recip = 1;
-        t.rA = salt_t.a0 + salt_t.a_len / (2.0 * (pr.L - 1));
-        t.rB = salt_t.b;
-      }
-      tabs[2 * q + primer] = t;
-    }
-  }
   void* dt = nullptr;
-  s = get_table(tabs.data(), tabs.size() * sizeof(ah::PrimerTab), &dt);
+  s = tm_table(ps, n_pairs, *p, &dt);
   if (s) return s;
   ProfScope prof_tm("tm", (hipStream_t)stream);
   AH_HIP(ah::launch_tm(*g, (const ah::PrimerTab*)dt, n_pairs, d_hits, d_nhits, capacity,
@@ -2010,6 +2034,76 @@ ah_status ah_tm_duplex(const char* oligo, const char* opposite, const ah_tm_para
   return AH_OK;
 }
 
+ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_window* windows,
+                   uint32_t n_pairs, const ah_tm_params* tm, ah_hit* d_hits, uint64_t hit_capacity,
+                   ah_result* d_hit_res, ah_amplicon* d_amp, uint64_t amp_capacity,
+                   ah_result* d_amp_res, void* d_scan_work, size_t scan_work_bytes,
+                   void* d_pair_work, size_t pair_work_bytes, void* stream) {
+  g_err.clear();
+  ah_status s = check_genomes(g);
+  if (s) return s;
+  if (!d_hit_res || !d_amp_res || !windows || !tm)
+    return fail(AH_ERR_INVALID_ARG, "ah_query: results, windows and Tm parameters are required");
+  if (hit_capacity > 0 && !d_hits) return fail(AH_ERR_INVALID_ARG, "d_hits is NULL");
+  if (amp_capacity > 0 && !d_amp) return fail(AH_ERR_INVALID_ARG, "d_amp is NULL");
+  if (hit_capacity >= (1ull << 32)) return fail(AH_ERR_LIMIT, "hit capacity must be < 2^32");
+  PairSet ps;
+  s = check_tm_request(pairs, n_pairs, tm, ps);
+  if (s) return s;
+  for (uint32_t q = 0; q < n_pairs; ++q)
+    if (windows[q].min_len > windows[q].max_len)
+      return fail(AH_ERR_INVALID_ARG, "pair %u: min_len > max_len", q);
+  ah::KeyBits kb{bits_for(n_pairs - 1), bits_for(g->n ? g->n - 1 : 0), bits_for(g->max_len)};
+  if (kb.total() > 64) return fail(AH_ERR_LIMIT, "sort key needs %d > 64 bits", kb.total());
+  const size_t sneed = scan_ws_bytes(g->n, hit_capacity, min_cands(hit_capacity));
+  if (!d_scan_work || scan_work_bytes < sneed)
+    return fail(AH_ERR_WORKSPACE, "scan workspace: %zu bytes given, %zu needed", scan_work_bytes,
+                sneed);
+  const size_t pneed = ah_pair_workspace_bytes(hit_capacity, n_pairs);
+  if (!d_pair_work || pair_work_bytes < pneed)
+    return fail(AH_ERR_WORKSPACE, "pair workspace: %zu bytes given, %zu needed", pair_work_bytes,
+                pneed);
+  void* tm_tabs = nullptr;
+  s = tm_table(ps, n_pairs, *tm, &tm_tabs);
+  if (s) return s;
+  void* pair_tabs = nullptr;
+  s = pair_table(ps, windows, n_pairs, &pair_tabs);
+  if (s) return s;
+  const Tuning tn = tuning_for(pairs, n_pairs);
+  ScanFns fn;
+  s = scan_kernels_for(pairs, n_pairs, ps, g->nmask != nullptr, tn, fn);
+  if (s) return s;
+
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_scan_work, scan_work_bytes);
+  ScanWs w = carve_scan(c, g->n, hit_capacity, 0);
+  Carver cp(d_pair_work, pair_work_bytes);
+  ah::PairBuffers pb = carve_pair(cp, hit_capacity);
+  s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, &kb);
+  if (s) return s;
+  const auto* ttab = (const ah::PrimerTab*)tm_tabs;
+  const auto* ptab = (const ah::PairTab*)pair_tabs;
+  bool marked = false;
+  {
+    ProfScope prof_sort("sort", st);
+    if (ah::sort_fusable(kb)) {  // Tm and the pairing's first step inside the sort
+      AH_HIP(ah::launch_sort_tm_mark(w.staging, d_hits, w.n_sort, kb, w.sb, *g, ttab, n_pairs, ptab,
+                                     pb, cu_count() * 4, st));
+      marked = true;
+    } else {
+      AH_HIP(ah::launch_sort_hits(w.staging, d_hits, w.n_sort, kb, w.sb, st));
+    }
+  }
+  if (!marked) {
+    ProfScope prof_tm("tm", st);
+    AH_HIP(ah::launch_tm(*g, ttab, n_pairs, d_hits, d_hit_res, hit_capacity, cu_count() * 4, st));
+  }
+  ProfScope prof_pair("pair", st);
+  AH_HIP(ah::launch_pair(d_hits, d_hit_res, hit_capacity, ptab, d_amp, amp_capacity, d_amp_res, pb,
+                         st, marked));
+  return AH_OK;
+}
+
 size_t ah_pair_workspace_bytes(uint64_t hit_capacity, uint32_t n_pairs) {
   (void)n_pairs;
   Carver c(nullptr, 0);
@@ -2029,22 +2123,14 @@ ah_status ah_pair_amplicons(const ah_hit* d_hits, const ah_result* d_nhits, uint
   PairSet ps;
   ah_status s = compile_pairs(pairs, n_pairs, ps);
   if (s) return s;
-  std::vector<ah::PairTab> tabs(n_pairs);
-  for (uint32_t q = 0; q < n_pairs; ++q) {
+  for (uint32_t q = 0; q < n_pairs; ++q)
     if (windows[q].min_len > windows[q].max_len)
       return fail(AH_ERR_INVALID_ARG, "pair %u: min_len > max_len", q);
-    tabs[q].lf = (uint32_t)ps.fwd[q].L;
-    tabs[q].lr = (uint32_t)ps.rev[q].L;
-    tabs[q].min_len = windows[q].min_len;
-    tabs[q].max_len = windows[q].max_len;
-    tabs[q].filter_tm = windows[q].filter_tm ? 1 : 0;
-    tabs[q].min_tm = windows[q].min_tm;
-  }
   const size_t need = ah_pair_workspace_bytes(hit_capacity, n_pairs);
   if (!d_work || work_bytes < need)
     return fail(AH_ERR_WORKSPACE, "pair workspace: %zu bytes given, %zu needed", work_bytes, need);
   void* dt = nullptr;
-  s = get_table(tabs.data(), tabs.size() * sizeof(ah::PairTab), &dt);
+  s = pair_table(ps, windows, n_pairs, &dt);
   if (s) return s;
   Carver c(d_work, work_bytes);
   ah::PairBuffers pb = carve_pair(c, hit_capacity);

@@ -106,9 +106,20 @@ struct PairBuffers {
   uint32_t* pre_r;      // [cap] rev-list
   uint32_t* rng;        // [cap x 8] a leader's minus-site ranges (count -> write)
 };
+// marked: the per-chunk counts of kept minus sites are in place already (the
+// sort of ah_query took them), so the pairing starts with the compaction.
 hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
-                       const PairBuffers& pb, hipStream_t st);
+                       const PairBuffers& pb, hipStream_t st, bool marked = false);
+// The sort of ah_query: as launch_sort_hits, with the melting temperature of
+// the staged records computed in tm_blocks extra blocks of the first pass and
+// the pairing's per-chunk counts of kept minus sites (k_pair_mark) taken by
+// the last pass.  Needs at least two passes (sort_fusable).
+bool sort_fusable(const KeyBits& kb);
+hipError_t launch_sort_tm_mark(ah_hit* staged, ah_hit* out, const uint64_t* n_dev, KeyBits kb,
+                               const SortBuffers& sb, const ah_genomes& g, const PrimerTab* tm_tabs,
+                               uint32_t n_pairs, const PairTab* pair_tabs,
+                               const PairBuffers& pb, int tm_blocks, hipStream_t st);
 
 // Amplicon FASTA records, sequence hashes and amplitypes (see ah.h); rec_len
 // [acap], rec_at [acap] and cc [kPairGrid] are workspace; `waves` writers.

@@ -234,17 +234,23 @@ __device__ __forceinline__ void store_hist(const u32* h, u32* __restrict__ hist,
 // histogram launch), and the workgroup zeroes its own column of
 // `hist_clear`, which the pass after next counts into (the previous pass
 // read it and has finished).
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_sort_scatter(
+// No-op observer of the records the last pass writes.
+struct NoWritten {
+  __device__ void operator()(u64, const ah_hit&) const {}
+};
+
+// One pass of the sort by one block (chunk blockIdx.x); in the last pass
+// (out != null) written(dst, record) is called for every record written.
+template <int D, class Written>
+__device__ __forceinline__ void scatter_pass(
     const u64* __restrict__ kin, const u32* __restrict__ iin, u64* __restrict__ kout,
-    u32* __restrict__ iout, const u64* __restrict__ n_dev, int shift, const u32* __restrict__ hist,
+    u32* __restrict__ iout, u64 n, int shift, const u32* __restrict__ hist,
     u32* __restrict__ hist_next, u32* __restrict__ hist_clear, u32 hs,
-    const ah_hit* __restrict__ staged, ah_hit* __restrict__ out) {
+    const ah_hit* __restrict__ staged, ah_hit* __restrict__ out, const Written& written) {
   constexpr u32 NB = 1u << D, R = NB / kBlock;  // digits, digits per thread
   __shared__ u64 run[NB];
   __shared__ u32 wcnt[4][NB];
   __shared__ u64 lds4[4];
-  const u64 n = *n_dev;
   u64 chunk;
   const u32 G = sort_chunks(n, chunk);
   if (blockIdx.x >= G) return;
@@ -338,7 +344,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
       u64 dst = run[d] + rank;
       for (int q = 0; q < w; ++q) dst += wcnt[q][d];
       if (out) {
-        out[dst] = r == 0 ? ph[0] : r == 1 ? ph[1] : r == 2 ? ph[2] : ph[3];
+        const ah_hit rec = r == 0 ? ph[0] : r == 1 ? ph[1] : r == 2 ? ph[2] : ph[3];
+        out[dst] = rec;
+        written(dst, rec);
       } else {
         kout[dst] = key;
         iout[dst] = id;
@@ -351,6 +359,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
       run[e] += (u64)wcnt[0][e] + wcnt[1][e] + wcnt[2][e] + wcnt[3][e];
     __syncthreads();
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(
+    const u64* __restrict__ kin, const u32* __restrict__ iin, u64* __restrict__ kout,
+    u32* __restrict__ iout, const u64* __restrict__ n_dev, int shift, const u32* __restrict__ hist,
+    u32* __restrict__ hist_next, u32* __restrict__ hist_clear, u32 hs,
+    const ah_hit* __restrict__ staged, ah_hit* __restrict__ out) {
+  scatter_pass<D>(kin, iin, kout, iout, *n_dev, shift, hist, hist_next, hist_clear, hs, staged, out,
+                  NoWritten{});
 }
 
 // ------------------------------------------------ melting temperature ----
@@ -384,28 +402,29 @@ __device__ __forceinline__ void init_term(u32 base, float& sh, float& ch, float&
   two_sum(ss, cs, gc ? kInitGcS : kInitAtS);
 }
 
-__global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
-                                               const u32* __restrict__ nmask,
-                                               const u64* __restrict__ word_off,
-                                               const u32* __restrict__ len,
-                                               const PrimerTab* __restrict__ tabs,
-                                               ah_hit* __restrict__ hits,
-                                               const ah_result* __restrict__ nhits, u64 cap,
-                                               u32 n_genomes, u32 n_pairs) {
-  // the stack tables in LDS: lanes index them divergently, once per stack
-  __shared__ float s_dh[16], s_ds[16];
-  if (threadIdx.x < 16) {
-    s_dh[threadIdx.x] = c_nn_dh[threadIdx.x];
-    s_ds[threadIdx.x] = c_nn_ds[threadIdx.x];
-  }
-  __syncthreads();
-  const u64 cnt = nhits->count;
-  const u64 n = cnt < cap ? cnt : cap;
-  for (u64 i = global_tid(); i < n; i += grid_threads()) {
+// The genomes and primer tables a Tm evaluation reads.
+struct TmJob {
+  const uint2* words;
+  const u32* nmask;
+  const u64* word_off;
+  const u32* len;
+  const PrimerTab* tabs;
+  u32 n_genomes, n_pairs;
+};
+
+// Sets hits[i].tm; s_dh / s_ds: the stack tables in LDS.
+__device__ __forceinline__ void tm_one(const TmJob& J, ah_hit* __restrict__ hits, u64 i,
+                                       const float* s_dh, const float* s_ds) {
+  const uint2* __restrict__ words = J.words;
+  const u32* __restrict__ nmask = J.nmask;
+  const u64* __restrict__ word_off = J.word_off;
+  const u32* __restrict__ len = J.len;
+  const PrimerTab* __restrict__ tabs = J.tabs;
+  {
     ah_hit h = hits[i];
     // a record that does not name a genome and pair of this call (never
     // written by a scan of it) is left alone rather than followed
-    if (h.genome >= n_genomes || h.pair >= n_pairs) continue;
+    if (h.genome >= J.n_genomes || h.pair >= J.n_pairs) return;
     const PrimerTab* T = &tabs[(u32)h.pair * 2u + (h.strand_primer & 1u)];
     const u32 L = T->L;
     const u32 strand = (h.strand_primer >> 1) & 1u;
@@ -548,6 +567,25 @@ __global__ __launch_bounds__(kBlock) void k_tm(const uint2* __restrict__ words,
     h.tm = best + (float)T->tshift;  // salt methods 1-4 (NaN stays NaN)
     hits[i] = h;
   }
+}
+
+// Loads the stack tables into LDS (every thread of the block calls this).
+__device__ __forceinline__ void tm_tables(float* s_dh, float* s_ds) {
+  if (threadIdx.x < 16) {
+    s_dh[threadIdx.x] = c_nn_dh[threadIdx.x];
+    s_ds[threadIdx.x] = c_nn_ds[threadIdx.x];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_tm(TmJob J, ah_hit* __restrict__ hits,
+                                               const ah_result* __restrict__ nhits, u64 cap) {
+  // the stack tables in LDS: lanes index them divergently, once per stack
+  __shared__ float s_dh[16], s_ds[16];
+  tm_tables(s_dh, s_ds);
+  const u64 cnt = nhits->count;
+  const u64 n = cnt < cap ? cnt : cap;
+  for (u64 i = global_tid(); i < n; i += grid_threads()) tm_one(J, hits, i, s_dh, s_ds);
 }
 
 // ----------------------------------------------------------- pairing ----
@@ -1177,18 +1215,101 @@ __global__ __launch_bounds__(kBlock) void k_remap(ah_hit* __restrict__ hits,
     amp[i].genome = ids[amp[i].genome];
 }
 
-// ---- scan: candidate-list overflow -------------------------------------
-// stat: [0] candidates, [1] windows in them, [2] workgroups whose slice of the
-// list was full, [3] most candidates of one workgroup.  A full slice means
-// lost candidates: the result is an overflow, and `required` is raised to at
-// least the windows in all
-// candidates (an upper bound on the sites) and grid x the fullest workgroup's
-// candidates (which exceeds the capacity, since the slice was ccap / grid >=
-// capacity / grid).  A call with that capacity gets slices long enough for
-// every workgroup (the tiles map to workgroups the same way) and finds all
-// sites.
-// Runs after the result is finalised, so `count` stays the number of records
-// written; only `required` and `status` change.
+// ---- the query in one call (ah_query): the sort's passes also carry the
+// melting temperature and the first step of the pairing.
+//
+// First pass: blocks [0, kSortGrid) run the pass; blocks from kSortGrid on
+// compute the Tm of every staged record (the order is irrelevant to it, and
+// the last pass copies the records, Tm included, into place) and clear the
+// pairing's per-chunk counts.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sort_scatter_tm(
+    const u64* __restrict__ kin, const u32* __restrict__ iin, u64* __restrict__ kout,
+    u32* __restrict__ iout, const u64* __restrict__ n_dev, int shift, const u32* __restrict__ hist,
+    u32* __restrict__ hist_next, u32* __restrict__ hist_clear, u32 hs, TmJob J,
+    ah_hit* __restrict__ staged, u64* __restrict__ cf, u64* __restrict__ cr) {
+  if (blockIdx.x < (u32)kSortGrid) {
+    scatter_pass<D>(kin, iin, kout, iout, *n_dev, shift, hist, hist_next, hist_clear, hs, nullptr,
+                    nullptr, NoWritten{});
+    return;
+  }
+  __shared__ float s_dh[16], s_ds[16];
+  tm_tables(s_dh, s_ds);
+  const u64 n = *n_dev;
+  const u64 t = (u64)(blockIdx.x - kSortGrid) * kBlock + threadIdx.x;
+  const u64 stride = (u64)(gridDim.x - kSortGrid) * kBlock;
+  for (u64 c = t; c < (u64)kPairGrid; c += stride) {
+    cf[c] = 0;
+    cr[c] = 0;
+  }
+  for (u64 i = t; i < n; i += stride) tm_one(J, staged, i, s_dh, s_ds);
+}
+
+// Last pass: as a record reaches its place, the kept minus sites of the fwd
+// and rev primer are counted per chunk of the pairing (what k_pair_mark counts
+// from the sorted records), summed in LDS per block first.
+struct MarkWritten {
+  const PairTab* tabs;
+  u32* lf;  // LDS, [kPairGrid]
+  u32* lr;
+  u64 pchunk;
+  __device__ void operator()(u64 dst, const ah_hit& rec) const {
+    const u32 k = minus_kind(rec, tabs);
+    if (k) atomicAdd(&((k & 1u) ? lf : lr)[dst / pchunk], 1u);
+  }
+};
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sort_scatter_mark(
+    const u64* __restrict__ kin, const u32* __restrict__ iin, const u64* __restrict__ n_dev,
+    int shift, const u32* __restrict__ hist, u32 hs, const ah_hit* __restrict__ staged,
+    ah_hit* __restrict__ out, const PairTab* __restrict__ tabs, u64* __restrict__ cf,
+    u64* __restrict__ cr) {
+  __shared__ u32 lf[kPairGrid], lr[kPairGrid];
+  const u64 n = *n_dev;
+  u64 pchunk;
+  const u32 PG = pair_chunks(n, pchunk);
+  for (u32 c = threadIdx.x; c < PG; c += blockDim.x) {
+    lf[c] = 0;
+    lr[c] = 0;
+  }
+  __syncthreads();
+  scatter_pass<D>(kin, iin, nullptr, nullptr, n, shift, hist, nullptr, nullptr, hs, staged, out,
+                  MarkWritten{tabs, lf, lr, pchunk});
+  __syncthreads();
+  for (u32 c = threadIdx.x; c < PG; c += blockDim.x) {
+    if (lf[c]) atomicAdd(&cf[c], (u64)lf[c]);
+    if (lr[c]) atomicAdd(&cr[c], (u64)lr[c]);
+  }
+}
+
+template <int D>
+void sort_passes_fused(ah_hit* staged, ah_hit* out, const u64* n_dev, KeyBits kb,
+                       const SortBuffers& sb, const TmJob& J, const PairTab* ptabs, u64* cf,
+                       u64* cr, int tm_blocks, hipStream_t st) {
+  const int bits = kb.total();
+  const int passes = (bits + D - 1) / D;  // at least 2 (the caller checks)
+  int cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    const bool last = p + 1 == passes;
+    u32* next = last ? nullptr : sb.hist[(p + 1) % 3];
+    u32* clear = p + 2 < passes ? sb.hist[(p + 2) % 3] : nullptr;
+    if (p == 0) {
+      k_sort_scatter_tm<D><<<kSortGrid + tm_blocks, kBlock, 0, st>>>(
+          (const u64*)sb.keys[cur], sb.idx[cur], (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1], n_dev, 0,
+          sb.hist[0], next, clear, sb.hstride, J, staged, cf, cr);
+    } else if (last) {
+      k_sort_scatter_mark<D><<<kSortGrid, kBlock, 0, st>>>(
+          (const u64*)sb.keys[cur], sb.idx[cur], n_dev, p * D, sb.hist[p % 3], sb.hstride, staged,
+          out, ptabs, cf, cr);
+    } else {
+      k_sort_scatter<D><<<kSortGrid, kBlock, 0, st>>>(
+          (const u64*)sb.keys[cur], sb.idx[cur], (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1], n_dev,
+          p * D, sb.hist[p % 3], next, clear, sb.hstride, staged, nullptr);
+    }
+    cur ^= 1;
+  }
+}
 }  // namespace
 
 // --------------------------------------------------- scan scratch array --
@@ -1291,17 +1412,37 @@ hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n
   return hipGetLastError();
 }
 
+bool sort_fusable(const KeyBits& kb) {
+  const int d = sort_digit_bits(kb);
+  return (kb.total() + d - 1) / d >= 2;
+}
+
+hipError_t launch_sort_tm_mark(ah_hit* staged, ah_hit* out, const uint64_t* n_dev, KeyBits kb,
+                               const SortBuffers& sb, const ah_genomes& g, const PrimerTab* tm_tabs,
+                               uint32_t n_pairs, const PairTab* pair_tabs, const PairBuffers& pb,
+                               int tm_blocks, hipStream_t st) {
+  const TmJob J{(const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, tm_tabs, g.n, n_pairs};
+  if (sort_digit_bits(kb) == 9)
+    sort_passes_fused<9>(staged, out, (const u64*)n_dev, kb, sb, J, pair_tabs, (u64*)pb.cf,
+                         (u64*)pb.cr, tm_blocks, st);
+  else
+    sort_passes_fused<8>(staged, out, (const u64*)n_dev, kb, sb, J, pair_tabs, (u64*)pb.cf,
+                         (u64*)pb.cr, tm_blocks, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pairs, ah_hit* hits,
                      const ah_result* nhits, uint64_t cap, int grid, hipStream_t st) {
-  k_tm<<<grid, kBlock, 0, st>>>((const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, tabs,
-                                hits, nhits, cap, g.n, n_pairs);
+  const TmJob J{(const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, tabs, g.n, n_pairs};
+  k_tm<<<grid, kBlock, 0, st>>>(J, hits, nhits, cap);
   return hipGetLastError();
 }
 
 hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
-                       const PairBuffers& pb, hipStream_t st) {
-  k_pair_mark<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (u64*)pb.cf, (u64*)pb.cr);
+                       const PairBuffers& pb, hipStream_t st, bool marked) {
+  if (!marked)
+    k_pair_mark<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (u64*)pb.cf, (u64*)pb.cr);
   k_pair_compact<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.cf,
                                               (const u64*)pb.cr, (u64*)pb.mkey_f, pb.mpos_f,
                                               pb.midx_f, (u64*)pb.mkey_r, pb.mpos_r, pb.midx_r,

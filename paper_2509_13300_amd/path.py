@@ -106,10 +106,16 @@ def alloc(coll: PackedCollection, pairs, hit_cap: int, amp_cap: int, device) -> 
 
 def run(coll: PackedCollection, pairs: Sequence, buf: QueryBuffers, tm: Optional[L.ah_tm_params] = None,
         filter_tm: bool = False, min_tm: float = 50.0, stream=None, do_tm: bool = True,
-        do_pair: bool = True):
-    """Enqueue scan (+ Tm, + pairing) for ``pairs`` over the collection."""
+        do_pair: bool = True, fused: bool = True):
+    """Enqueue scan (+ Tm, + pairing) for ``pairs`` over the collection: the
+    whole query in one ah_query call (``fused``), or the separate calls."""
     g = coll.view()
     pp = L.primer_pairs(pairs)
+    if fused and do_tm and do_pair:
+        L.ah_query(g, pp, L.windows(pairs, filter_tm, min_tm),
+                   tm if tm is not None else L.tm_params(), buf.hits, buf.hit_cap, buf.hit_res,
+                   buf.amps, buf.amp_cap, buf.amp_res, buf.scan_work, buf.pair_work, stream)
+        return
     L.ah_scan_primers(g, pp, buf.hits, buf.hit_cap, buf.hit_res, buf.scan_work, stream)
     if do_tm:
         L.ah_tm(g, pp, tm if tm is not None else L.tm_params(), buf.hits, buf.hit_res, buf.hit_cap,
@@ -172,7 +178,7 @@ def amps_numpy(buf: QueryBuffers) -> np.ndarray:
 
 
 def capture(coll: PackedCollection, pairs: Sequence, buf: QueryBuffers, tm=None, filter_tm=False,
-            min_tm: float = 50.0):
+            min_tm: float = 50.0, fused: bool = True):
     """Record one scan -> Tm -> pairing pass for ``pairs`` into a hipGraph
     (through torch.cuda.CUDAGraph).  Call ``run`` once with the same pairs
     first, so that the specialised kernel and per-set tables exist; the graph
@@ -181,7 +187,7 @@ def capture(coll: PackedCollection, pairs: Sequence, buf: QueryBuffers, tm=None,
 
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        run(coll, pairs, buf, tm=tm, filter_tm=filter_tm, min_tm=min_tm)
+        run(coll, pairs, buf, tm=tm, filter_tm=filter_tm, min_tm=min_tm, fused=fused)
     return g
 
 
