@@ -322,17 +322,25 @@ ah_status ah_pair_amplicons(const ah_hit* d_hits, const ah_result* d_nhits, uint
                             ah_result* d_res, void* d_work, size_t work_bytes, void* stream);
 size_t ah_pair_workspace_bytes(uint64_t hit_capacity, uint32_t n_pairs);
 
-/* The whole query in one call: ah_scan_primers, ah_tm and ah_pair_amplicons
- * of `pairs` (with `windows` and Tm parameters `tm`) in that order on
+/* The whole query in one call (Section 2.1: primer matching, melting
+ * temperature, amplicon calling): ah_scan_primers, ah_tm and
+ * ah_pair_amplicons of `pairs` (with `windows` and Tm parameters `tm`) on
  * `stream`, with the same outputs byte for byte (sites in d_hits and
  * *d_hit_res, Tm included; amplicons in d_amp and *d_amp_res) and the same
  * workspaces (ah_scan_workspace_bytes for hit_capacity, and
- * ah_pair_workspace_bytes).  Knowing the whole query lets the library fold
- * steps together: the melting temperature of each site is computed by extra
- * workgroups of the canonical sort's first pass (on the records before they
- * move), and the pairing's per-chunk counts of kept minus sites are taken by
- * the sort's last pass as the records reach their places, which saves two
- * launches.  Errors: those of the three calls. */
+ * ah_pair_workspace_bytes), except that the amplicons need every site: when
+ * the sites overflow, no amplicon is written and *d_amp_res is
+ * AH_ERR_OVERFLOW with count and required 0 (run again with the sites'
+ * `required` first).  Knowing the whole query lets the library fold steps
+ * together.  Up to 4,096 segments (n_pairs x genomes, each a pair on one
+ * genome), the scan puts the sites of each segment together and one
+ * workgroup per segment sorts them into canonical order (in LDS up to 2,048
+ * sites), computes their Tm and counts the amplicons each + site starts; a
+ * last launch writes the amplicons.  With more segments (or
+ * AH_QUERY_SEGMENTED=0 in the environment) the sites go through the radix
+ * sort, the Tm is computed by extra workgroups of its first pass and the
+ * pairing's per-chunk counts of kept minus sites are taken by its last.
+ * Errors: those of the three calls. */
 ah_status ah_query(const ah_genomes* genomes, const ah_primer_pair* pairs, const ah_window* windows,
                    uint32_t n_pairs, const ah_tm_params* tm, ah_hit* d_hits, uint64_t hit_capacity,
                    ah_result* d_hit_res, ah_amplicon* d_amp, uint64_t amp_capacity,

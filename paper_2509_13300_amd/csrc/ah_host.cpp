@@ -935,6 +935,12 @@ std::string gen_program_uncached(const std::vector<Pattern>& pats, bool has_n, T
     s += buf;
   }
   s += "    default: return 0u;\n  }\n}\n";
+  s += "__device__ u32 ah_pat_pair(u32 p) {\n  switch (p) {\n";
+  for (size_t i = 0; i < pats.size(); ++i) {
+    snprintf(buf, sizeof buf, "    case %zuu: return %uu;\n", i, pats[i].pair);
+    s += buf;
+  }
+  s += "    default: return 0u;\n  }\n}\n";
   return head + std::string(kScanCore) + s;
 }
 
@@ -976,6 +982,7 @@ struct ScanFns {
   hipFunction_t scan = nullptr;    // filter: appends candidates
   hipFunction_t verify = nullptr;  // exact count of the candidates: sites per candidate
   hipFunction_t emit = nullptr;    // the site records, the result and the statistics
+  hipFunction_t emit_seg = nullptr;  // the same, each segment (pair, genome) together
   bool wave = false;               // wave mode: wave tiles of 63 x U words, 4 per workgroup
 };
 
@@ -1118,6 +1125,7 @@ ah_status load_scan_kernel(int dev, const std::string& src, const std::vector<ch
   AH_HIP(hipModuleGetFunction(&e.fn.scan, e.mod, "ah_scan_kernel"));
   AH_HIP(hipModuleGetFunction(&e.fn.verify, e.mod, "ah_verify_kernel"));
   AH_HIP(hipModuleGetFunction(&e.fn.emit, e.mod, "ah_emit_kernel"));
+  AH_HIP(hipModuleGetFunction(&e.fn.emit_seg, e.mod, "ah_emit_seg_kernel"));
   e.fn.wave = src.find("#define AH_WAVE 1\n") != std::string::npos;
   g_jit[key] = e;
   fn = e.fn;
@@ -1446,13 +1454,38 @@ ah_status check_genomes(const ah_genomes* g) {
   return AH_OK;
 }
 
+// Segment buffers of ah_query, carved from the workspace's radix-sort
+// buffers, which its segmented tail does not use.  False when the segments
+// are more than kSegMax or do not fit there.
+bool carve_seg(const ScanWs& w, uint32_t n_genomes, uint64_t n_seg, ah::SegBuffers& sg) {
+  if (n_seg == 0 || n_seg > ah::kSegMax) return false;
+  const uintptr_t beg = (uintptr_t)w.sb.keys[0];
+  const uintptr_t end = (uintptr_t)w.sb.hist[2] +
+                        (uintptr_t)ah::kSortDigits * w.sb.hstride * sizeof(uint32_t);
+  Carver c((void*)beg, (size_t)(end - beg));
+  sg.cnt = c.take<uint32_t>(2 * n_seg);
+  sg.fill = sg.cnt + n_seg;
+  sg.off = c.take<uint64_t>(n_seg + 1);
+  sg.amp = c.take<uint64_t>(n_seg);
+  sg.n_seg = (uint32_t)n_seg;
+  sg.n_genomes = n_genomes;
+  return c.cur <= c.end;
+}
+
+// AH_QUERY_SEGMENTED=0 keeps ah_query on the radix-sort tail.
+bool seg_mode() {
+  const char* e = getenv("AH_QUERY_SEGMENTED");
+  return !(e && e[0] == '0');
+}
+
 // Reset of d_res, tile counts and prefix, then the filter, the exact count
 // and the emit pass, which writes the sites to the staging area in slice
 // order, the final d_res (required, count, status), n_sort and the
-// candidate-list statistics.
+// candidate-list statistics.  With seg set, the segmented emit instead puts
+// the sites of each segment (pair, genome) together (n_sort is not written).
 ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, const ScanWs& w,
                              ah_result* d_res, uint64_t capacity, hipStream_t st,
-                             const ah::KeyBits* kb) {
+                             const ah::KeyBits* kb, const ah::SegBuffers* seg = nullptr) {
   if (g->n == 0) {
     AH_HIP(ah::launch_result_init(d_res, st));
     AH_HIP(ah::launch_zero_u64(w.cstat, 4, st));
@@ -1462,9 +1495,11 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   // window words per tile: a workgroup's in tile mode, a wave's (63 lanes
   // with windows) in wave mode
   const uint32_t tile = fn.wave ? (uint32_t)(63 * tn.u) : (uint32_t)(ah::kBlock * tn.u);
-  if (g->n <= ah::kSmallPrefix) {  // one launch, result reset included
-    AH_HIP(ah::launch_tile_prefix_small(g->len, g->n, tile, w.tile_prefix, d_res, st));
+  if (g->n <= ah::kSmallPrefix) {  // one launch, result reset (and segment counters) included
+    AH_HIP(ah::launch_tile_prefix_small(g->len, g->n, tile, w.tile_prefix, d_res, st,
+                                        seg ? seg->cnt : nullptr, seg ? 2 * seg->n_seg : 0));
   } else {
+    if (seg) AH_HIP(ah::launch_zero_u64((uint64_t*)seg->cnt, seg->n_seg, st));
     AH_HIP(ah::launch_result_init(d_res, st));
     AH_HIP(ah::launch_tile_counts(g->len, g->n, tile, w.counts, st));
     AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
@@ -1519,12 +1554,33 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   uint32_t sort_qshift = kb ? (uint32_t)(kb->gb + kb->pb + 2) : 0u;
   uint32_t sort_grid = (uint32_t)ah::kSortGrid;
   uint32_t sort_chunk_min = ah::kSortChunkMin;
+  uint32_t* seg_cnt = seg ? seg->cnt : nullptr;
+  uint32_t seg_n = seg ? seg->n_genomes : 0;
   void* vargs[] = {&words,      &nmask,      &word_off,    &len,         &ccands,    &slice,
                    &cslice_cnt, &cand_sites, &slice_sites, &group_sites, &slice_win, &hist_a,
-                   &hist_b,     &hist_words};
+                   &hist_b,     &hist_words, &seg_cnt,     &seg_n};
   {
     ProfScope prof_verify("verify", st);
     AH_HIP(hipModuleLaunchKernel(fn.verify, grid, 1, 1, ah::kBlock, 1, 1, 0, st, vargs, nullptr));
+    if (seg) {
+      const uint32_t* cslice_tot = w.slice_tot;
+      const uint64_t* cslice_win = w.slice_win;
+      const uint32_t* ccand_sites = w.cand_sites;
+      const uint32_t* cseg_cnt = seg->cnt;
+      uint32_t n_seg = seg->n_seg;
+      uint64_t* seg_off = seg->off;
+      uint32_t* seg_fill = seg->fill;
+      ah_hit* out = w.staging;
+      uint64_t cap = capacity;
+      uint64_t* cstat = w.cstat;
+      void* sargs[] = {&words,      &nmask,       &word_off, &len,      &ccands,
+                       &slice,      &cslice_cnt,  &cslice_tot, &cslice_win, &ccand_sites,
+                       &cseg_cnt,   &n_seg,       &seg_n,    &seg_off,  &seg_fill,
+                       &out,        &cap,         &d_res,    &cstat};
+      AH_HIP(hipModuleLaunchKernel(fn.emit_seg, grid, 1, 1, ah::kBlock, 1, 1, 0, st, sargs,
+                                   nullptr));
+      return AH_OK;
+    }
     ah_hit* out = w.staging;
     uint64_t cap = capacity;
     const uint32_t* cslice_tot = w.slice_tot;
@@ -2079,10 +2135,26 @@ ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_wi
   ScanWs w = carve_scan(c, g->n, hit_capacity, 0);
   Carver cp(d_pair_work, pair_work_bytes);
   ah::PairBuffers pb = carve_pair(cp, hit_capacity);
-  s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, &kb);
-  if (s) return s;
   const auto* ttab = (const ah::PrimerTab*)tm_tabs;
   const auto* ptab = (const ah::PairTab*)pair_tabs;
+  ah::SegBuffers sg{};
+  if (g->n > 0 && seg_mode() &&
+      carve_seg(w, g->n, (uint64_t)n_pairs * g->n, sg)) {
+    // each segment (pair, genome) sorted, its Tm and amplicons, by one workgroup
+    s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, nullptr, &sg);
+    if (s) return s;
+    {
+      ProfScope prof_sort("sort", st);
+      AH_HIP(ah::launch_seg_tail(w.staging, d_hits, sg, d_hit_res, kb.pb + 2, *g, ttab, n_pairs,
+                                 ptab, pb, d_amp, amp_capacity, d_amp_res, 0, st));
+    }
+    ProfScope prof_pair("pair", st);
+    AH_HIP(ah::launch_seg_tail(w.staging, d_hits, sg, d_hit_res, kb.pb + 2, *g, ttab, n_pairs,
+                               ptab, pb, d_amp, amp_capacity, d_amp_res, 1, st));
+    return AH_OK;
+  }
+  s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, &kb);
+  if (s) return s;
   bool marked = false;
   {
     ProfScope prof_sort("sort", st);
@@ -2100,7 +2172,7 @@ ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_wi
   }
   ProfScope prof_pair("pair", st);
   AH_HIP(ah::launch_pair(d_hits, d_hit_res, hit_capacity, ptab, d_amp, amp_capacity, d_amp_res, pb,
-                         st, marked));
+                         st, marked, true));
   return AH_OK;
 }
 

@@ -108,9 +108,12 @@ struct PairBuffers {
 };
 // marked: the per-chunk counts of kept minus sites are in place already (the
 // sort of ah_query took them), so the pairing starts with the compaction.
+// need_all: when the sites' result is not AH_OK (some sites are missing),
+// write no amplicons and an overflow result with count and required 0.
 hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
-                       const PairBuffers& pb, hipStream_t st, bool marked = false);
+                       const PairBuffers& pb, hipStream_t st, bool marked = false,
+                       bool need_all = false);
 // The sort of ah_query: as launch_sort_hits, with the melting temperature of
 // the staged records computed in tm_blocks extra blocks of the first pass and
 // the pairing's per-chunk counts of kept minus sites (k_pair_mark) taken by
@@ -120,6 +123,29 @@ hipError_t launch_sort_tm_mark(ah_hit* staged, ah_hit* out, const uint64_t* n_de
                                const SortBuffers& sb, const ah_genomes& g, const PrimerTab* tm_tabs,
                                uint32_t n_pairs, const PairTab* pair_tabs,
                                const PairBuffers& pb, int tm_blocks, hipStream_t st);
+
+// The tail of ah_query over at most kSegMax segments (pair, genome), after
+// the scan's segmented emit has put each segment's sites at
+// off[s] .. off[s + 1] of the staging area in no particular order.  Part 0:
+// each segment sorted into canonical order by a workgroup of one wave (in LDS
+// up to kSegLds sites), the Tm of every site and the amplicons each leader +
+// site starts; part 1: the amplicons.  key_bits: bits of pos << 2 |
+// strand-primer.  When the sites overflowed, nothing is written but the
+// amplicon result, an overflow with count and required 0.
+constexpr uint32_t kSegMax = 4096;  // AH_SEG_MAX of the scan core
+constexpr uint32_t kSegLds = 1024;
+struct SegBuffers {
+  uint32_t* cnt;   // [n_seg] sites per segment, then
+  uint32_t* fill;  // [n_seg] places taken so far (both cleared before the filter)
+  uint64_t* off;   // [n_seg + 1] first site of each segment
+  uint64_t* amp;   // [n_seg] amplicons per segment
+  uint32_t n_seg, n_genomes;
+};
+hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
+                           const ah_result* hres, int key_bits, const ah_genomes& g,
+                           const PrimerTab* tm_tabs, uint32_t n_pairs, const PairTab* pair_tabs,
+                           const PairBuffers& pb, ah_amplicon* amp, uint64_t acap,
+                           ah_result* ares, int part, hipStream_t st);
 
 // Amplicon FASTA records, sequence hashes and amplitypes (see ah.h); rec_len
 // [acap], rec_at [acap] and cc [kPairGrid] are workspace; `waves` writers.
@@ -146,10 +172,12 @@ hipError_t launch_remap(ah_hit* hits, const ah_result* hres, ah_amplicon* amp, c
 // Scan: zero n u64 (graph-capturable, no memset node).
 hipError_t launch_zero_u64(uint64_t* p, uint32_t n, hipStream_t st);
 // Tile counts of n <= kSmallPrefix genomes, their exclusive prefix
-// (prefix[n] = total) and the reset of `res`, in one launch.
+// (prefix[n] = total), the reset of `res` and (zero set) the clearing of
+// zero[0 .. n_zero), in one launch.
 constexpr uint32_t kSmallPrefix = 4096;
 hipError_t launch_tile_prefix_small(const uint32_t* len, uint32_t n, uint32_t tile_words,
-                                    uint64_t* prefix, ah_result* res, hipStream_t st);
+                                    uint64_t* prefix, ah_result* res, hipStream_t st,
+                                    uint32_t* zero = nullptr, uint32_t n_zero = 0);
 
 // Recommended scan workspace for n genomes holding at most `window_words`
 // window words in total (pairs may be null: the minimum).

@@ -115,9 +115,11 @@ constexpr int kSmallBlock = 1024;
 __global__ __launch_bounds__(kSmallBlock) void k_tile_prefix_small(const u32* __restrict__ len, u32 n,
                                                                    u32 tile_words,
                                                                    u64* __restrict__ prefix,
-                                                                   ah_result* r) {
+                                                                   ah_result* r, u32* __restrict__ zero,
+                                                                   u32 n_zero) {
   __shared__ u64 wsum[kSmallBlock / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (u32 i = threadIdx.x; i < n_zero; i += kSmallBlock) zero[i] = 0u;
   if (threadIdx.x == 0) {
     r->count = 0;
     r->required = 0;
@@ -412,19 +414,16 @@ struct TmJob {
   u32 n_genomes, n_pairs;
 };
 
-// Sets hits[i].tm; s_dh / s_ds: the stack tables in LDS.
-__device__ __forceinline__ void tm_one(const TmJob& J, ah_hit* __restrict__ hits, u64 i,
-                                       const float* s_dh, const float* s_ds) {
+// The Tm of site record h (a genome and pair of this call); s_dh / s_ds:
+// the stack tables in LDS.
+__device__ __forceinline__ float tm_value(const TmJob& J, const ah_hit& h, const float* s_dh,
+                                          const float* s_ds) {
   const uint2* __restrict__ words = J.words;
   const u32* __restrict__ nmask = J.nmask;
   const u64* __restrict__ word_off = J.word_off;
   const u32* __restrict__ len = J.len;
   const PrimerTab* __restrict__ tabs = J.tabs;
   {
-    ah_hit h = hits[i];
-    // a record that does not name a genome and pair of this call (never
-    // written by a scan of it) is left alone rather than followed
-    if (h.genome >= J.n_genomes || h.pair >= J.n_pairs) return;
     const PrimerTab* T = &tabs[(u32)h.pair * 2u + (h.strand_primer & 1u)];
     const u32 L = T->L;
     const u32 strand = (h.strand_primer >> 1) & 1u;
@@ -564,9 +563,18 @@ __device__ __forceinline__ void tm_one(const TmJob& J, ah_hit* __restrict__ hits
         }
       }
     }
-    h.tm = best + (float)T->tshift;  // salt methods 1-4 (NaN stays NaN)
-    hits[i] = h;
+    return best + (float)T->tshift;  // salt methods 1-4 (NaN stays NaN)
   }
+}
+
+// Sets hits[i].tm.  A record that does not name a genome and pair of this
+// call (never written by a scan of it) is left alone rather than followed.
+__device__ __forceinline__ void tm_one(const TmJob& J, ah_hit* __restrict__ hits, u64 i,
+                                       const float* s_dh, const float* s_ds) {
+  ah_hit h = hits[i];
+  if (h.genome >= J.n_genomes || h.pair >= J.n_pairs) return;
+  h.tm = tm_value(J, h, s_dh, s_ds);
+  hits[i] = h;
 }
 
 // Loads the stack tables into LDS (every thread of the block calls this).
@@ -844,8 +852,17 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
     const u32* __restrict__ xf, const u64* __restrict__ kr, const u32* __restrict__ pr,
     const u32* __restrict__ xr, const uint4* __restrict__ rng, const u32* __restrict__ cnt,
     const u64* __restrict__ cc, ah_amplicon* __restrict__ amp, u64 cap,
-    ah_result* __restrict__ res) {
+    ah_result* __restrict__ res, int need_all) {
   __shared__ u64 lds4[4];
+  if (need_all && nhits->status != AH_OK) {  // some sites are missing: no amplicons
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      res->count = 0;
+      res->required = 0;
+      res->status = AH_ERR_OVERFLOW;
+      res->reserved = 0;
+    }
+    return;
+  }
   const u64 n = pair_n(nhits, hcap);
   u64 chunk;
   const u32 G = pair_chunks(n, chunk);
@@ -926,6 +943,388 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
       A.reserved = 0;
       amp[w++] = A;
       ++r[best].beg;
+    }
+  }
+}
+
+// ------------------------------------------------ segmented query tail ----
+// ah_query over at most kSegMax segments (pair, genome).  The scan's
+// segmented emit has put each segment's records together, in no particular
+// order, at seg_off[s] .. seg_off[s + 1] of the staging area.  k_seg_sort puts
+// each segment in canonical order (its keys pos << 2 | strand-primer are
+// distinct), computes every site's Tm and counts the amplicons each leader +
+// site starts (the leader, its minus ranges and the count as the pairing
+// kernels above define them, inside one segment); k_seg_pair writes them at
+// the prefix of the segments' counts.  A segment of at most kSegLds records
+// is sorted and searched in LDS; a longer one by its workgroup alone in
+// global memory: stable LSD radix passes between the staging area and the
+// output, an odd number of them so that the last lands in the output.
+struct SegArgs {
+  ah_hit* staged;          // the segments' records (the long path sorts through it)
+  ah_hit* out;             // the records in canonical order
+  const u32* seg_cnt;      // records of each segment
+  const u64* seg_off;      // first record of each segment
+  u32 n_seg, n_genomes;    // segment s = pair * n_genomes + genome
+  const ah_result* hres;   // the sites' result: nothing is done on an overflow
+  int key_bits;            // bits of pos << 2 | strand-primer
+  TmJob tj;
+  const PairTab* ptabs;
+  u32* pcf;                // long segments: kept fwd- / rev- minus sites up to
+  u32* pcr;                // each record (inclusive), by record index
+  u32* cnt;                // amplicons each record leads (0: not a leader)
+  uint4* rng;              // a leader's minus ranges, per + site of its group
+  u64* amp_seg;            // amplicons of each segment
+};
+
+__device__ __forceinline__ u64 seg_key(const ah_hit& h) {
+  return ((u64)h.pos << 2) | (u64)(h.strand_primer & 3u);
+}
+
+// strand-primer (bits 0-1: primer, strand) and kept (bit 2): a kept + site
+// has (kind & 6) == 4, a kept fwd-primer minus site is 6, a rev-primer one 7.
+__device__ __forceinline__ u32 seg_kind(const ah_hit& h, const PairTab& p) {
+  const bool k = !p.filter_tm || h.tm >= p.min_tm;  // NaN fails the filter
+  return (h.strand_primer & 3u) | (k ? 4u : 0u);
+}
+__device__ __forceinline__ bool plus_kind(u32 k) { return (k & 6u) == 4u; }
+
+// First index in [0, m) whose position is >= x.
+template <class PosF>
+__device__ __forceinline__ u32 seg_lower(const PosF& P, u32 m, u64 x) {
+  u32 lo = 0, hi = m;
+  while (lo < hi) {
+    const u32 mid = (lo + hi) >> 1;
+    if ((u64)P(mid) < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Records [x, y) of the minus sites whose amplicon with a + site at pos
+// (end = their pos + lb) has a length in [min_len, max_len].
+template <class PosF>
+__device__ __forceinline__ uint2 seg_range(const PosF& P, u32 m, u32 pos, u32 lb, const PairTab& t) {
+  const long long lo = (long long)pos + (long long)t.min_len - (long long)lb;
+  const long long hi = (long long)pos + (long long)t.max_len - (long long)lb;
+  if (hi < 0) return make_uint2(0u, 0u);
+  const u32 a = seg_lower(P, m, lo < 0 ? 0ull : (u64)lo);
+  const u32 b = seg_lower(P, m, (u64)hi + 1ull);
+  return make_uint2(a, b < a ? a : b);
+}
+
+// Wanted sites in [r.x, r.y) from inclusive counts pc.
+template <class C>
+__device__ __forceinline__ u32 seg_count(const C* pc, uint2 r) {
+  return (r.y ? (u32)pc[r.y - 1] : 0u) - (r.x ? (u32)pc[r.x - 1] : 0u);
+}
+
+// One wave per segment: the segment kernels run workgroups of one wave, so
+// that a segment of a few sites does not hold three idle waves (and their
+// registers), and every segment of the query is resident at once.
+constexpr u32 kSegBlock = 64;
+
+__device__ __forceinline__ u64 wave_incl_scan(u64 v) {
+  const u32 lane = threadIdx.x & 63u;
+  u64 x = v;
+#pragma unroll
+  for (u32 o = 1; o < 64; o <<= 1) {
+    const u64 y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ u64 wave_sum(u64 v) {
+#pragma unroll
+  for (u32 o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Leaders of the sorted segment at records base .. base + m: the amplicons
+// each starts (cnt) and its ranges (rng); returns the segment's total.
+template <class PosF, class KindF, class C>
+__device__ __forceinline__ u64 seg_leaders(const SegArgs& A, const PairTab& pt, u64 base, u32 m,
+                                           const PosF& P, const KindF& K, const C* pcf,
+                                           const C* pcr) {
+  u64 sum = 0;
+  for (u32 i = threadIdx.x; i < m; i += kSegBlock) {
+    u32 c = 0;
+    const u32 k = K(i), pos = P(i);
+    if (plus_kind(k) && !(i > 0 && plus_kind(K(i - 1)) && P(i - 1) == pos)) {
+      const u32 ng = (i + 1 < m && plus_kind(K(i + 1)) && P(i + 1) == pos) ? 2u : 1u;
+      // both + sites of a group share the position, hence the ranges
+      const uint2 rf = seg_range(P, m, pos, pt.lf, pt), rr = seg_range(P, m, pos, pt.lr, pt);
+      c = ng * (seg_count(pcf, rf) + seg_count(pcr, rr));
+      for (u32 q = 0; q < ng; ++q)
+        A.rng[2 * (base + i) + q] = make_uint4(rf.x, rf.y, rr.x, rr.y);
+    }
+    A.cnt[base + i] = c;
+    sum += c;
+  }
+  return wave_sum(sum);
+}
+
+// Bitonic sort of a[0 .. n2) (n2 a power of two) by the one-wave workgroup.
+__device__ __forceinline__ void lds_bitonic(u64* a, u32 n2) {
+  for (u32 k = 2; k <= n2; k <<= 1)
+    for (u32 j = k >> 1; j > 0; j >>= 1) {
+      for (u32 p = threadIdx.x; p < n2 / 2; p += kSegBlock) {
+        const u32 i = ((p & ~(j - 1u)) << 1) | (p & (j - 1u));  // bit j of i clear
+        const u32 l = i | j;
+        const u64 x = a[i], y = a[l];
+        if ((x > y) == ((i & k) == 0u)) {
+          a[i] = y;
+          a[l] = x;
+        }
+      }
+      __syncthreads();
+    }
+}
+
+constexpr u32 kSegIdxBits = 10;  // record index inside a sorted LDS key
+static_assert((1u << kSegIdxBits) == kSegLds, "LDS keys carry the record index");
+
+// Segment blockIdx.x: canonical order, Tm, leaders and amplicon counts.
+__global__ __launch_bounds__(kSegBlock) void k_seg_sort(SegArgs A) {
+  __shared__ u64 keys[kSegLds];  // also the long path's digit counters
+  __shared__ u32 spos[kSegLds];
+  __shared__ unsigned short pcf[kSegLds], pcr[kSegLds];
+  __shared__ unsigned char kind[kSegLds];
+  __shared__ float s_dh[16], s_ds[16];
+  tm_tables(s_dh, s_ds);
+  if (A.hres->status != AH_OK) return;
+  const u32 t = threadIdx.x, s = blockIdx.x;
+  const u32 m = A.seg_cnt[s];
+  if (m == 0) {
+    if (t == 0) A.amp_seg[s] = 0;
+    return;
+  }
+  const u64 base = A.seg_off[s];
+  const PairTab pt = A.ptabs[s / A.n_genomes];
+  const bool small = m <= kSegLds;
+  if (small) {
+    // keys with the record index below them, padded to a power of two
+    u32 n2 = 1;
+    while (n2 < m) n2 <<= 1;
+    for (u32 e = t; e < n2; e += kSegBlock)
+      keys[e] = e < m ? (seg_key(A.staged[base + e]) << kSegIdxBits) | e : ~0ull;
+    __syncthreads();
+    lds_bitonic(keys, n2);
+  } else {
+    // stable LSD passes, an odd number, staging <-> output
+    u32* hist = (u32*)keys;  // [256] digit counts, then first slots
+    const int bits = A.key_bits;
+    int np = (bits + 7) / 8;
+    if ((np & 1) == 0) ++np;
+    const int D = (bits + np - 1) / np;
+    const u32 mask = (1u << D) - 1u;
+    ah_hit* src = A.staged + base;
+    ah_hit* dst = A.out + base;
+    const u32 lane = t & 63u;
+    for (int p = 0; p < np; ++p) {
+      const int shift = p * D;
+#pragma unroll
+      for (u32 q = 0; q < 4; ++q) hist[q * 64 + t] = 0;
+      __syncthreads();
+      for (u32 i = t; i < m; i += kSegBlock)
+        atomicAdd(&hist[(u32)(seg_key(src[i]) >> shift) & mask], 1u);
+      __syncthreads();
+      {  // exclusive prefix of the 256 counts: lane t owns digits 4t .. 4t + 3
+        u32 c[4];
+        u64 own = 0;
+#pragma unroll
+        for (u32 q = 0; q < 4; ++q) {
+          c[q] = hist[4 * t + q];
+          own += c[q];
+        }
+        u64 at = wave_incl_scan(own) - own;
+#pragma unroll
+        for (u32 q = 0; q < 4; ++q) {
+          hist[4 * t + q] = (u32)at;
+          at += c[q];
+        }
+      }
+      __syncthreads();
+      for (u32 r0 = 0; r0 < m; r0 += kSegBlock) {
+        const u32 i = r0 + t;
+        const bool valid = i < m;
+        ah_hit h{};
+        u32 d = 0;
+        if (valid) {
+          h = src[i];
+          d = (u32)(seg_key(h) >> shift) & mask;
+        }
+        // this lane's rank among the lanes with the same digit
+        u64 peers = __ballot(valid);
+        for (int bit = 0; bit < D; ++bit) {
+          const bool on = (d >> bit) & 1u;
+          const u64 bal = __ballot(valid && on);
+          peers &= on ? bal : ~bal;
+        }
+        const u32 rank = (u32)__popcll(peers & ((1ull << lane) - 1ull));
+        if (valid) dst[hist[d] + rank] = h;
+        __syncthreads();
+        if (valid && rank == 0) hist[d] += (u32)__popcll(peers);
+        __syncthreads();
+      }
+      ah_hit* x = src;
+      src = dst;
+      dst = x;
+    }
+    // src == A.out + base: the passes are odd in number
+  }
+  // the Tm of every site, written with the record to its place
+  ah_hit* o = A.out + base;
+  for (u32 i = t; i < m; i += kSegBlock) {
+    ah_hit h = small ? A.staged[base + (u32)(keys[i] & (kSegLds - 1u))] : o[i];
+    h.tm = tm_value(A.tj, h, s_dh, s_ds);
+    o[i] = h;
+    if (small) {
+      spos[i] = h.pos;
+      kind[i] = (unsigned char)seg_kind(h, pt);
+    }
+  }
+  __syncthreads();
+  // kept fwd- (low half) and rev- (high half) minus sites up to each record
+  u64 carry = 0;
+  for (u32 r0 = 0; r0 < m; r0 += kSegBlock) {
+    const u32 i = r0 + t;
+    const u32 k = i < m ? (small ? (u32)kind[i] : seg_kind(o[i], pt)) : 0u;
+    const u64 v = (k == 6u ? 1ull : 0ull) | (k == 7u ? 1ull << 32 : 0ull);
+    const u64 incl = wave_incl_scan(v);
+    const u64 inc = carry + incl;
+    if (i < m) {
+      if (small) {
+        pcf[i] = (unsigned short)(inc & 0xffffffffull);
+        pcr[i] = (unsigned short)(inc >> 32);
+      } else {
+        A.pcf[base + i] = (u32)(inc & 0xffffffffull);
+        A.pcr[base + i] = (u32)(inc >> 32);
+      }
+    }
+    carry += __shfl(incl, 63, 64);
+  }
+  __syncthreads();
+  u64 sum;
+  if (small)
+    sum = seg_leaders(A, pt, base, m, [&](u32 i) { return spos[i]; },
+                      [&](u32 i) { return (u32)kind[i]; }, pcf, pcr);
+  else
+    sum = seg_leaders(A, pt, base, m, [&](u32 i) { return o[i].pos; },
+                      [&](u32 i) { return seg_kind(o[i], pt); }, A.pcf + base, A.pcr + base);
+  if (t == 0) A.amp_seg[s] = sum;
+}
+
+// Writes the amplicons leader i starts, from slot `at` on (below acap), in
+// (end, orient) order: up to four lists (each + site of the group with the
+// fwd- and the rev- sites of its ranges), each ordered by end.
+template <class PosF, class KindF>
+__device__ __forceinline__ void seg_write(const SegArgs& A, const PairTab& pt, const ah_hit* o,
+                                          u64 base, u32 i, u32 m, u64 at, u64 acap,
+                                          ah_amplicon* __restrict__ amp, const PosF& P,
+                                          const KindF& K) {
+  const u32 pos = P(i);
+  const u32 ng = (i + 1 < m && plus_kind(K(i + 1)) && P(i + 1) == pos) ? 2u : 1u;
+  u32 cur[4], hi[4], want[4], lb[4], orient[4], plus[4];
+  int nl = 0;
+  for (u32 q = 0; q < ng; ++q) {
+    const uint4 g = A.rng[2 * (base + i) + q];
+    const u32 ap = K(i + q) & 1u;  // the + site's primer
+    cur[nl] = g.x; hi[nl] = g.y; want[nl] = 6u; lb[nl] = pt.lf; plus[nl] = i + q;
+    orient[nl] = ap ? (u32)AH_RF : (u32)AH_FF;
+    ++nl;
+    cur[nl] = g.z; hi[nl] = g.w; want[nl] = 7u; lb[nl] = pt.lr; plus[nl] = i + q;
+    orient[nl] = ap ? (u32)AH_RR : (u32)AH_FR;
+    ++nl;
+  }
+  for (int q = 0; q < nl; ++q)
+    while (cur[q] < hi[q] && K(cur[q]) != want[q]) ++cur[q];
+  const ah_hit lead = o[i];
+  u64 w = at;
+  while (w < acap) {
+    int best = -1;
+    u64 bend = 0;
+    for (int q = 0; q < nl; ++q) {
+      if (cur[q] >= hi[q]) continue;
+      const u64 e = (u64)P(cur[q]) + lb[q];
+      if (best < 0 || e < bend || (e == bend && orient[q] < orient[best])) {
+        best = q;
+        bend = e;
+      }
+    }
+    if (best < 0) break;
+    ah_amplicon a;
+    a.genome = lead.genome;
+    a.start = pos;
+    a.end = (u32)bend;
+    a.plus_hit = (u32)(base + plus[best]);
+    a.minus_hit = (u32)(base + cur[best]);
+    a.pair = lead.pair;
+    a.orient = (uint8_t)orient[best];
+    a.reserved = 0;
+    amp[w++] = a;
+    ++cur[best];
+    while (cur[best] < hi[best] && K(cur[best]) != want[best]) ++cur[best];
+  }
+}
+
+// Segment blockIdx.x: its amplicons, after those of the earlier segments.
+__global__ __launch_bounds__(kSegBlock) void k_seg_pair(SegArgs A, ah_amplicon* __restrict__ amp,
+                                                        u64 acap, ah_result* __restrict__ ares) {
+  __shared__ u32 spos[kSegLds];
+  __shared__ unsigned char kind[kSegLds];
+  const u32 t = threadIdx.x, s = blockIdx.x;
+  if (A.hres->status != AH_OK) {  // the sites overflowed: the pairing needs all of them
+    if (s == 0 && t == 0) {
+      ares->count = 0;
+      ares->required = 0;
+      ares->status = AH_ERR_OVERFLOW;
+      ares->reserved = 0;
+    }
+    return;
+  }
+  // the amplicons of the earlier segments, and of all
+  u64 before = 0, total = 0;
+  for (u32 q = t; q < A.n_seg; q += kSegBlock) {
+    const u64 v = A.amp_seg[q];
+    total += v;
+    before += q < s ? v : 0ull;
+  }
+  before = wave_sum(before);
+  total = wave_sum(total);
+  if (s == 0 && t == 0) {
+    ares->required = total;
+    ares->count = total < acap ? total : acap;
+    ares->status = total > acap ? AH_ERR_OVERFLOW : AH_OK;
+    ares->reserved = 0;
+  }
+  if (A.amp_seg[s] == 0 || before >= acap) return;
+  const u32 m = A.seg_cnt[s];
+  const u64 base = A.seg_off[s];
+  const PairTab pt = A.ptabs[s / A.n_genomes];
+  const ah_hit* o = A.out + base;
+  const bool small = m <= kSegLds;
+  if (small) {
+    for (u32 i = t; i < m; i += kSegBlock) {
+      const ah_hit h = o[i];
+      spos[i] = h.pos;
+      kind[i] = (unsigned char)seg_kind(h, pt);
+    }
+    __syncthreads();
+  }
+  u64 at0 = before;
+  for (u32 r0 = 0; r0 < m; r0 += kSegBlock) {
+    const u32 i = r0 + t;
+    const u32 c = i < m ? A.cnt[base + i] : 0u;
+    const u64 incl = wave_incl_scan(c);
+    const u64 at = at0 + incl - c;
+    at0 += __shfl(incl, 63, 64);
+    if (c && at < acap) {
+      if (small)
+        seg_write(A, pt, o, base, i, m, at, acap, amp, [&](u32 j) { return spos[j]; },
+                  [&](u32 j) { return (u32)kind[j]; });
+      else
+        seg_write(A, pt, o, base, i, m, at, acap, amp, [&](u32 j) { return o[j].pos; },
+                  [&](u32 j) { return seg_kind(o[j], pt); });
     }
   }
 }
@@ -1362,8 +1761,10 @@ hipError_t launch_result_init(ah_result* res, hipStream_t st) {
 }
 
 hipError_t launch_tile_prefix_small(const uint32_t* len, uint32_t n, uint32_t tile_words,
-                                    uint64_t* prefix, ah_result* res, hipStream_t st) {
-  k_tile_prefix_small<<<1, kSmallBlock, 0, st>>>(len, n, tile_words, (u64*)prefix, res);
+                                    uint64_t* prefix, ah_result* res, hipStream_t st,
+                                    uint32_t* zero, uint32_t n_zero) {
+  k_tile_prefix_small<<<1, kSmallBlock, 0, st>>>(len, n, tile_words, (u64*)prefix, res, zero,
+                                                 zero ? n_zero : 0u);
   return hipGetLastError();
 }
 
@@ -1431,6 +1832,33 @@ hipError_t launch_sort_tm_mark(ah_hit* staged, ah_hit* out, const uint64_t* n_de
   return hipGetLastError();
 }
 
+hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
+                           const ah_result* hres, int key_bits, const ah_genomes& g,
+                           const PrimerTab* tm_tabs, uint32_t n_pairs, const PairTab* pair_tabs,
+                           const PairBuffers& pb, ah_amplicon* amp, uint64_t acap,
+                           ah_result* ares, int part, hipStream_t st) {
+  SegArgs A;
+  A.staged = staged;
+  A.out = out;
+  A.seg_cnt = sg.cnt;
+  A.seg_off = (const u64*)sg.off;
+  A.n_seg = sg.n_seg;
+  A.n_genomes = sg.n_genomes;
+  A.hres = hres;
+  A.key_bits = key_bits;
+  A.tj = TmJob{(const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, tm_tabs, g.n, n_pairs};
+  A.ptabs = pair_tabs;
+  A.pcf = pb.pre_f;
+  A.pcr = pb.pre_r;
+  A.cnt = pb.cnt;
+  A.rng = (uint4*)pb.rng;
+  A.amp_seg = (u64*)sg.amp;
+  const u32 grid = sg.n_seg > 0 ? sg.n_seg : 1u;
+  if (part == 0) k_seg_sort<<<grid, kSegBlock, 0, st>>>(A);
+  else k_seg_pair<<<grid, kSegBlock, 0, st>>>(A, amp, acap, ares);
+  return hipGetLastError();
+}
+
 hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pairs, ah_hit* hits,
                      const ah_result* nhits, uint64_t cap, int grid, hipStream_t st) {
   const TmJob J{(const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, tabs, g.n, n_pairs};
@@ -1440,7 +1868,7 @@ hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pair
 
 hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_cap,
                        const PairTab* tabs, ah_amplicon* amp, uint64_t cap, ah_result* res,
-                       const PairBuffers& pb, hipStream_t st, bool marked) {
+                       const PairBuffers& pb, hipStream_t st, bool marked, bool need_all) {
   if (!marked)
     k_pair_mark<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (u64*)pb.cf, (u64*)pb.cr);
   k_pair_compact<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.cf,
@@ -1454,7 +1882,7 @@ hipError_t launch_pair(const ah_hit* hits, const ah_result* nhits, uint64_t hit_
   k_pair_write<<<kPairGrid, kBlock, 0, st>>>(hits, nhits, hit_cap, tabs, (const u64*)pb.mkey_f,
                                             pb.mpos_f, pb.midx_f, (const u64*)pb.mkey_r, pb.mpos_r,
                                             pb.midx_r, (const uint4*)pb.rng, pb.cnt,
-                                            (const u64*)pb.cc, amp, cap, res);
+                                            (const u64*)pb.cc, amp, cap, res, need_all ? 1 : 0);
   return hipGetLastError();
 }
 

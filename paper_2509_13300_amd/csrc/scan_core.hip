@@ -258,6 +258,8 @@ __device__ void ah_groups(ah_lds_uint2* tw, u32 t0, const AhCtx& c, const AhCand
 template <class W>
 __device__ u32 ah_verify_one(const AhCtx& c, W w, u32 t, u32 p, u32 cand, AhHitRec* out, u64 cap,
                              u64 slot, bool emit);
+// Generated: the primer pair of pattern p.
+__device__ u32 ah_pat_pair(u32 p);
 
 // Words staged per tile: the tile's window words plus the halo, in 16-byte
 // pairs (every genome starts 16-byte aligned).
@@ -447,12 +449,13 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
     const uint4* __restrict__ cands, u32 slice, const u32* __restrict__ slice_count,
     u32* __restrict__ cand_sites, u64* __restrict__ slice_sites, u64* __restrict__ group_sites,
     u64* __restrict__ slice_win, u32* __restrict__ hist_a, u32* __restrict__ hist_b,
-    u64 hist_words) {
+    u64 hist_words, u32* __restrict__ seg_cnt, u32 seg_n) {
   // Sites of each candidate of this workgroup's slice, their sum, and the
   // candidates' windows (added to those of the candidates a full slice
   // dropped).  The grid also clears the sort's first two histogram tables
   // (the emit pass counts into the first, the first sort pass into the
-  // second).
+  // second).  With seg_cnt set, the sites are also counted per segment
+  // (pair, genome) at seg_cnt[pair * seg_n + genome].
   for (u64 e = (u64)blockIdx.x * AH_BLOCK + threadIdx.x; e < hist_words;
        e += (u64)gridDim.x * AH_BLOCK) {
     hist_a[e] = 0u;
@@ -475,7 +478,9 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (m[q]) {
-        found += ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], nullptr, 0, 0, false);
+        const u32 f = ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], nullptr, 0, 0, false);
+        if (seg_cnt && f) atomicAdd(&seg_cnt[ah_pat_pair(e.z + (u32)q) * seg_n + e.x], f);
+        found += f;
         my_win += (u64)__popc(m[q]);
       }
     cand_sites[at] = found;
@@ -629,6 +634,125 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
       }
     }
     slot += rt;
+  }
+}
+
+// Segmented emit (the whole query in one call): the records go straight to
+// their segment (pair, genome), whose first slot is the sum of the sites of
+// the earlier segments (seg_cnt from the verify pass, at most AH_SEG_MAX
+// segments), at a place inside it taken with a device atomic on
+// seg_fill[segment] (cleared before the filter).  The order inside a segment
+// is left to the segment sort that follows.  Workgroup 0 also writes the
+// segments' first slots (seg_off, n_seg + 1 entries), the result and the
+// candidate-list statistics, as the slice-order emit does.  Nothing is
+// written when the sites overflow the capacity.
+#define AH_SEG_MAX 4096
+extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_seg_kernel(
+    const uint2* __restrict__ words, const u32* __restrict__ nmask,
+    const u64* __restrict__ word_off, const u32* __restrict__ len,
+    const uint4* __restrict__ cands, u32 slice, const u32* __restrict__ slice_count,
+    const u32* __restrict__ slice_total, const u64* __restrict__ slice_win,
+    const u32* __restrict__ cand_sites, const u32* __restrict__ seg_cnt, u32 n_seg, u32 seg_n,
+    u64* __restrict__ seg_off, u32* __restrict__ seg_fill, AhHitRec* __restrict__ out, u64 cap,
+    AhResult* __restrict__ res, u64* __restrict__ cand_stat) {
+  __shared__ u64 s_off[AH_SEG_MAX + 1];
+  __shared__ u64 tmp[AH_BLOCK / 64];
+  // the segments' first slots: thread i sums a run of `per` segments
+  const u32 per = (n_seg + AH_BLOCK - 1) / AH_BLOCK;
+  const u32 s0 = threadIdx.x * per;
+  u32 v[AH_SEG_MAX / AH_BLOCK];
+  u64 mine = 0;
+#pragma unroll
+  for (u32 q = 0; q < AH_SEG_MAX / AH_BLOCK; ++q) {
+    v[q] = q < per && s0 + q < n_seg ? seg_cnt[s0 + q] : 0u;
+    mine += v[q];
+  }
+  u64 found;
+  u64 run = ah_block_scan(mine, tmp, &found);
+#pragma unroll
+  for (u32 q = 0; q < AH_SEG_MAX / AH_BLOCK; ++q)
+    if (q < per && s0 + q < n_seg) {
+      s_off[s0 + q] = run;
+      run += v[q];
+    }
+  if (threadIdx.x == 0) s_off[n_seg] = found;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (u32 q = threadIdx.x; q <= n_seg; q += AH_BLOCK) seg_off[q] = s_off[q];
+    // candidate-list statistics: candidates, their windows, full slices,
+    // most of one slice
+    const u32 GS = gridDim.x * AH_SPW;
+    u64 c = 0, wn = 0, full = 0, mx = 0;
+    for (u32 w = threadIdx.x; w < GS; w += AH_BLOCK) {
+      const u64 t = slice_total[w];
+      c += t;
+      wn += slice_win[w];
+      full += t > slice_count[w] ? 1ull : 0ull;
+      mx = t > mx ? t : mx;
+    }
+    u64 sc, sw, sf;
+    ah_block_scan(c, tmp, &sc);
+    ah_block_scan(wn, tmp, &sw);
+    ah_block_scan(full, tmp, &sf);
+    for (u32 o = 32; o > 0; o >>= 1) {
+      const u64 y = __shfl_xor(mx, o, 64);
+      mx = y > mx ? y : mx;
+    }
+    if ((threadIdx.x & 63u) == 0) tmp[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (u32 q = 0; q < AH_BLOCK / 64; ++q) mx = tmp[q] > mx ? tmp[q] : mx;
+      res->count = found < cap ? found : cap;
+      res->required = found;
+      res->status = found > cap ? AH_RES_OVERFLOW : 0;
+      cand_stat[0] = sc;
+      cand_stat[1] = sw;
+      cand_stat[2] = sf;
+      cand_stat[3] = mx;
+      if (sf > 0) {  // dropped candidates: sites <= windows, list >= slices x most
+        const u64 list = (u64)GS * mx;
+        const u64 bound = sw > list ? sw : list;
+        if (bound > res->required) res->required = bound;
+        res->status = AH_RES_OVERFLOW;
+      }
+    }
+  }
+  if (found > cap) return;
+  const AhSlices sl = ah_slices(slice_count, blockIdx.x);
+  for (u32 i = threadIdx.x; i < sl.total; i += AH_BLOCK) {
+    const u64 at = ah_slice_at(sl, blockIdx.x, slice, i);
+    const u32 f = cand_sites[at];
+    if (!f) continue;
+    const uint4 e = cands[2 * at], mk = cands[2 * at + 1];
+    const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
+    const u32 m[4] = {mk.x, mk.y, mk.z, mk.w};
+    // one reservation when the quad's patterns with windows share a pair
+    u32 pq = 0xffffffffu;
+    bool one = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (m[q]) {
+        const u32 pp = ah_pat_pair(e.z + (u32)q);
+        one &= pq == 0xffffffffu || pq == pp;
+        pq = pp;
+      }
+    if (one) {
+      const u32 sg = pq * seg_n + e.x;
+      u64 slot = s_off[sg] + atomicAdd(&seg_fill[sg], f);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (m[q]) slot += ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], out, cap, slot, true);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (m[q]) {
+          const u32 fq = ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], nullptr, 0, 0, false);
+          if (!fq) continue;
+          const u32 sg = ah_pat_pair(e.z + (u32)q) * seg_n + e.x;
+          const u64 slot = s_off[sg] + atomicAdd(&seg_fill[sg], fq);
+          ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], out, cap, slot, true);
+        }
+    }
   }
 }
 

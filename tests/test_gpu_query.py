@@ -1,6 +1,9 @@
-"""ah_query (scan, Tm and pairing in one call, with the Tm computed inside
-the sort's first pass and the pairing's chunk counts inside its last) gives
-the same bytes as the three separate calls."""
+"""ah_query (scan, Tm and pairing in one call) gives the same bytes as the
+three separate calls, on both of its tails: per segment (pair, genome) --
+sorted in LDS, or through global memory for a segment longer than LDS holds
+-- and, past the segment limit or when asked (AH_QUERY_SEGMENTED=0), the
+radix sort with the Tm computed inside its first pass and the pairing's
+chunk counts inside its last."""
 import numpy as np
 import pytest
 
@@ -72,14 +75,22 @@ def test_query_with_a_one_pass_sort(dev):
     assert fus == sep
 
 
-def test_query_overflow_reports_like_the_three_calls(dev):
+@pytest.mark.parametrize("segmented", ["1", "0"])
+def test_query_overflow_reports_like_the_three_calls(dev, monkeypatch, segmented):
+    """The sites' result as the scan's; the pairing, which needs every site,
+    reports an overflow with nothing counted until the sites fit."""
+    monkeypatch.setenv("AH_QUERY_SEGMENTED", segmented)
     pr = plan.PairSpec("ACGTACGTAC", "GGCCAATTGG", k=3, clamp=0, min_len=20, max_len=2000)
     p = plan.tiny(9301, n_genomes=4, len_lo=20000, len_hi=40000, pair=pr)
     sep, fus = _both(p, [pr], dev, hit_cap=64, amp_cap=64)
     assert sep[0]["status"] == -4
-    assert fus[0] == sep[0] and fus[1]["status"] == sep[1]["status"]
-    sep, fus = _both(p, [pr], dev, hit_cap=sep[0]["required"], amp_cap=1 << 18)
-    assert sep[0]["status"] == 0 and fus == sep
+    assert fus[0] == sep[0]
+    assert (fus[1]["status"], fus[1]["count"], fus[1]["required"]) == (-4, 0, 0)
+    sep, fus = _both(p, [pr], dev, hit_cap=sep[0]["required"], amp_cap=64)
+    assert sep[0]["status"] == 0 and sep[1]["status"] == -4
+    assert fus == sep
+    sep, fus = _both(p, [pr], dev, hit_cap=sep[0]["required"], amp_cap=sep[1]["required"])
+    assert sep[0]["status"] == 0 and sep[1]["status"] == 0 and fus == sep
 
 
 def test_query_on_the_collection_workload(dev):
@@ -87,3 +98,46 @@ def test_query_on_the_collection_workload(dev):
     sep, fus = _both(p, p.pairs, dev, hit_cap=1 << 20, amp_cap=1 << 20)
     say("collection-60", sep[0], sep[1])
     assert sep[0]["status"] == 0 and fus == sep
+
+
+def test_query_segments_longer_than_lds(dev):
+    """A short primer at k = 3 on genomes of ~300 kbp: thousands of sites per
+    (pair, genome), past the 2,048 the segment sort keeps in LDS, so those
+    segments are sorted and paired through global memory."""
+    pr = plan.PairSpec("ACGTACGTAC", "GGCCAATTGG", k=3, clamp=0, min_len=20, max_len=3000)
+    p = plan.tiny(9302, n_genomes=3, len_lo=250000, len_hi=350000, pair=pr)
+    sep, fus = _both(p, [pr], dev, hit_cap=1 << 16, amp_cap=1 << 21)
+    per_genome = np.bincount(np.frombuffer(sep[2], dtype=np.uint32).reshape(-1, 4)[:, 0],
+                             minlength=p.n)
+    say("long segments: sites per genome", per_genome.tolist(), "amplicons", sep[1]["count"])
+    assert per_genome.max() > 2048 and sep[1]["status"] == 0
+    assert fus == sep
+
+
+def test_query_filters_tm_on_long_segments(dev):
+    pr = plan.PairSpec("ACGTRCGTAC", "GGCCAATYGG", k=3, clamp=1, min_len=20, max_len=3000)
+    p = plan.tiny(9303, n_genomes=2, len_lo=250000, len_hi=300000, pair=pr)
+    sep, fus = _both(p, [pr], dev, hit_cap=1 << 16, amp_cap=1 << 21, filter_tm=True, min_tm=30.0)
+    assert sep[0]["status"] == 0 and sep[1]["status"] == 0
+    assert fus == sep
+
+
+@pytest.mark.parametrize("n_genomes", [1024, 1025])
+def test_query_at_the_segment_limit(dev, n_genomes):
+    """Four pairs over 1,024 genomes are 4,096 segments, the most the
+    segmented tail takes; 1,025 genomes go to the radix-sort tail."""
+    p = plan.tiny(9304, n_genomes=n_genomes, len_lo=200, len_hi=3000, n_copies=(0, 2))
+    pairs = [p.pairs[0]] + plan.law_pairs(9305, 3)
+    sep, fus = _both(p, pairs, dev, hit_cap=1 << 18, amp_cap=1 << 18)
+    say("segment limit", n_genomes, "sites", sep[0]["count"], "amplicons", sep[1]["count"])
+    assert sep[0]["status"] == 0 and sep[1]["status"] == 0 and sep[0]["count"] > 0
+    assert fus == sep
+
+
+def test_query_radix_tail_when_asked(dev, monkeypatch):
+    monkeypatch.setenv("AH_QUERY_SEGMENTED", "0")
+    p = plan.tiny(9306, n_genomes=12, len_lo=2000, len_hi=80000, n_copies=(1, 3), nruns=2)
+    pairs = [p.pairs[0]] + plan.law_pairs(9307, 2)
+    sep, fus = _both(p, pairs, dev)
+    assert sep[0]["status"] == 0 and sep[1]["status"] == 0 and sep[0]["count"] > 0
+    assert fus == sep
