@@ -861,9 +861,16 @@ std::string gen_program_uncached(const std::vector<Pattern>& pats, bool has_n, T
   const bool wave = wave_mode(pats, tn);
   std::string s;
   char buf[2048];
+  // every quad of patterns (4 from the start of each group) within one pair
+  bool uniform = true;
+  for (size_t a = 0; a < pats.size(); a += (size_t)tn.group)
+    for (size_t q = a; q < std::min(pats.size(), a + (size_t)tn.group); q += 4)
+      for (size_t r = q + 1; r < std::min({pats.size(), a + (size_t)tn.group, q + 4}); ++r)
+        uniform &= pats[r].pair == pats[q].pair;
   snprintf(buf, sizeof buf,
-           "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n#define AH_WAVE %d\n", tn.u,
-           lmax - 1, has_n ? 1 : 0, wave ? 1 : 0);
+           "#define AH_U %d\n#define AH_HALO %d\n#define AH_HAS_N %d\n#define AH_WAVE %d\n"
+           "#define AH_QUAD_ONE_PAIR %d\n",
+           tn.u, lmax - 1, has_n ? 1 : 0, wave ? 1 : 0, uniform ? 1 : 0);
   std::string head = buf;
   for (size_t i = 0; i < pats.size(); ++i) {
     s += gen_filter(i, pats[i], plan_filter(pats[i], allow));

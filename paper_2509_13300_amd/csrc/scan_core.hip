@@ -36,7 +36,9 @@
 // Macros supplied by the generated program: AH_U (window words per lane, odd
 // so that the lanes' LDS reads fall in distinct banks), AH_HALO (longest
 // primer - 1), AH_HAS_N (1 if the collection has non-ACGT bases, whose
-// positions mismatch every primer position), AH_WAVE (1: wave mode, below).
+// positions mismatch every primer position), AH_WAVE (1: wave mode, below),
+// AH_QUAD_ONE_PAIR (1: the four patterns of every candidate record belong to
+// one primer pair).
 
 typedef unsigned int u32;
 typedef unsigned long long u64;
@@ -455,7 +457,10 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
   // dropped).  The grid also clears the sort's first two histogram tables
   // (the emit pass counts into the first, the first sort pass into the
   // second).  With seg_cnt set, the sites are also counted per segment
-  // (pair, genome) at seg_cnt[pair * seg_n + genome].
+  // (pair, genome) at seg_cnt[pair * seg_n + genome]; when every record's
+  // patterns share a pair, one device atomic per candidate reserves its
+  // sites' places in the segment, and cand_sites keeps the first place + 1
+  // (0: no sites) for the segmented emit instead of the count.
   for (u64 e = (u64)blockIdx.x * AH_BLOCK + threadIdx.x; e < hist_words;
        e += (u64)gridDim.x * AH_BLOCK) {
     hist_a[e] = 0u;
@@ -479,11 +484,15 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
     for (int q = 0; q < 4; ++q)
       if (m[q]) {
         const u32 f = ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], nullptr, 0, 0, false);
-        if (seg_cnt && f) atomicAdd(&seg_cnt[ah_pat_pair(e.z + (u32)q) * seg_n + e.x], f);
+        if (!AH_QUAD_ONE_PAIR && seg_cnt && f)
+          atomicAdd(&seg_cnt[ah_pat_pair(e.z + (u32)q) * seg_n + e.x], f);
         found += f;
         my_win += (u64)__popc(m[q]);
       }
-    cand_sites[at] = found;
+    if (AH_QUAD_ONE_PAIR && seg_cnt)
+      cand_sites[at] = found ? atomicAdd(&seg_cnt[ah_pat_pair(e.z) * seg_n + e.x], found) + 1u : 0u;
+    else
+      cand_sites[at] = found;
     my_sites += found;
   }
   if (my_sites) atomicAdd(&s_sites, my_sites);
@@ -640,7 +649,8 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
 // Segmented emit (the whole query in one call): the records go straight to
 // their segment (pair, genome), whose first slot is the sum of the sites of
 // the earlier segments (seg_cnt from the verify pass, at most AH_SEG_MAX
-// segments), at a place inside it taken with a device atomic on
+// segments), at the place inside it that the verify pass reserved
+// (AH_QUAD_ONE_PAIR) or one taken here with a device atomic on
 // seg_fill[segment] (cleared before the filter).  The order inside a segment
 // is left to the segment sort that follows.  Workgroup 0 also writes the
 // segments' first slots (seg_off, n_seg + 1 entries), the result and the
@@ -657,6 +667,17 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_seg_kernel(
     AhResult* __restrict__ res, u64* __restrict__ cand_stat) {
   __shared__ u64 s_off[AH_SEG_MAX + 1];
   __shared__ u64 tmp[AH_BLOCK / 64];
+  // this thread's first candidate, in flight while the slots are summed
+  const AhSlices sl = ah_slices(slice_count, blockIdx.x);
+  u64 at0 = 0;
+  u32 f0 = 0;
+  uint4 e0 = make_uint4(0u, 0u, 0u, 0u), mk0 = e0;
+  if (threadIdx.x < sl.total) {
+    at0 = ah_slice_at(sl, blockIdx.x, slice, threadIdx.x);
+    f0 = cand_sites[at0];
+    e0 = cands[2 * at0];
+    mk0 = cands[2 * at0 + 1];
+  }
   // the segments' first slots: thread i sums a run of `per` segments
   const u32 per = (n_seg + AH_BLOCK - 1) / AH_BLOCK;
   const u32 s0 = threadIdx.x * per;
@@ -718,14 +739,28 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_seg_kernel(
     }
   }
   if (found > cap) return;
-  const AhSlices sl = ah_slices(slice_count, blockIdx.x);
   for (u32 i = threadIdx.x; i < sl.total; i += AH_BLOCK) {
-    const u64 at = ah_slice_at(sl, blockIdx.x, slice, i);
-    const u32 f = cand_sites[at];
+    u64 at = at0;
+    u32 f = f0;
+    uint4 e = e0, mk = mk0;
+    if (i != threadIdx.x) {
+      at = ah_slice_at(sl, blockIdx.x, slice, i);
+      f = cand_sites[at];
+      e = cands[2 * at];
+      mk = cands[2 * at + 1];
+    }
     if (!f) continue;
-    const uint4 e = cands[2 * at], mk = cands[2 * at + 1];
     const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
     const u32 m[4] = {mk.x, mk.y, mk.z, mk.w};
+#if AH_QUAD_ONE_PAIR
+    {  // f - 1: the first place the verify pass reserved in the segment
+      u64 slot = s_off[ah_pat_pair(e.z) * seg_n + e.x] + (f - 1u);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (m[q]) slot += ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], out, cap, slot, true);
+      continue;
+    }
+#endif
     // one reservation when the quad's patterns with windows share a pair
     u32 pq = 0xffffffffu;
     bool one = true;

@@ -141,3 +141,16 @@ def test_query_radix_tail_when_asked(dev, monkeypatch):
     sep, fus = _both(p, pairs, dev)
     assert sep[0]["status"] == 0 and sep[1]["status"] == 0 and sep[0]["count"] > 0
     assert fus == sep
+
+
+@pytest.mark.parametrize("group", ["3", "6"])
+def test_query_with_records_across_pairs(dev, monkeypatch, group):
+    """Pattern groups of 3 or 6 put patterns of two pairs in one candidate
+    record: the segmented emit then takes each pattern's places itself
+    instead of the verify pass reserving them per record."""
+    monkeypatch.setenv("AH_SCAN_GROUP", group)
+    p = plan.tiny(9308, n_genomes=12, len_lo=2000, len_hi=80000, n_copies=(1, 3), nruns=2)
+    pairs = [p.pairs[0]] + plan.law_pairs(9309, 3)
+    sep, fus = _both(p, pairs, dev)
+    assert sep[0]["status"] == 0 and sep[1]["status"] == 0 and sep[0]["count"] > 0
+    assert fus == sep
