@@ -334,9 +334,10 @@ size_t ah_pair_workspace_bytes(uint64_t hit_capacity, uint32_t n_pairs);
  * `required` first).  Knowing the whole query lets the library fold steps
  * together.  Up to 4,096 segments (n_pairs x genomes, each a pair on one
  * genome), the scan puts the sites of each segment together and one
- * workgroup per segment sorts them into canonical order (in LDS up to 2,048
- * sites), computes their Tm and counts the amplicons each + site starts; a
- * last launch writes the amplicons.  With more segments (or
+ * workgroup per segment sorts them into canonical order (in LDS up to 1,024
+ * sites), computes their Tm, counts the amplicons each + site starts, takes
+ * its first amplicon slot from the counts of the earlier segments and
+ * writes its amplicons, in one launch.  With more segments (or
  * AH_QUERY_SEGMENTED=0 in the environment) the sites go through the radix
  * sort, the Tm is computed by extra workgroups of its first pass and the
  * pairing's per-chunk counts of kept minus sites are taken by its last.

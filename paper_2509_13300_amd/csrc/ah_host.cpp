@@ -1470,10 +1470,10 @@ bool carve_seg(const ScanWs& w, uint32_t n_genomes, uint64_t n_seg, ah::SegBuffe
   const uintptr_t end = (uintptr_t)w.sb.hist[2] +
                         (uintptr_t)ah::kSortDigits * w.sb.hstride * sizeof(uint32_t);
   Carver c((void*)beg, (size_t)(end - beg));
-  sg.cnt = c.take<uint32_t>(2 * n_seg);
+  sg.cnt = c.take<uint32_t>(4 * n_seg);  // counts, fill counters, look-back words
   sg.fill = sg.cnt + n_seg;
+  sg.lb = (uint64_t*)(sg.cnt + 2 * n_seg);
   sg.off = c.take<uint64_t>(n_seg + 1);
-  sg.amp = c.take<uint64_t>(n_seg);
   sg.n_seg = (uint32_t)n_seg;
   sg.n_genomes = n_genomes;
   return c.cur <= c.end;
@@ -1504,9 +1504,9 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   const uint32_t tile = fn.wave ? (uint32_t)(63 * tn.u) : (uint32_t)(ah::kBlock * tn.u);
   if (g->n <= ah::kSmallPrefix) {  // one launch, result reset (and segment counters) included
     AH_HIP(ah::launch_tile_prefix_small(g->len, g->n, tile, w.tile_prefix, d_res, st,
-                                        seg ? seg->cnt : nullptr, seg ? 2 * seg->n_seg : 0));
+                                        seg ? seg->cnt : nullptr, seg ? 4 * seg->n_seg : 0));
   } else {
-    if (seg) AH_HIP(ah::launch_zero_u64((uint64_t*)seg->cnt, seg->n_seg, st));
+    if (seg) AH_HIP(ah::launch_zero_u64((uint64_t*)seg->cnt, 2 * seg->n_seg, st));
     AH_HIP(ah::launch_result_init(d_res, st));
     AH_HIP(ah::launch_tile_counts(g->len, g->n, tile, w.counts, st));
     AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
@@ -2150,14 +2150,9 @@ ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_wi
     // each segment (pair, genome) sorted, its Tm and amplicons, by one workgroup
     s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, nullptr, &sg);
     if (s) return s;
-    {
-      ProfScope prof_sort("sort", st);
-      AH_HIP(ah::launch_seg_tail(w.staging, d_hits, sg, d_hit_res, kb.pb + 2, *g, ttab, n_pairs,
-                                 ptab, pb, d_amp, amp_capacity, d_amp_res, 0, st));
-    }
-    ProfScope prof_pair("pair", st);
+    ProfScope prof_sort("sort", st);
     AH_HIP(ah::launch_seg_tail(w.staging, d_hits, sg, d_hit_res, kb.pb + 2, *g, ttab, n_pairs,
-                               ptab, pb, d_amp, amp_capacity, d_amp_res, 1, st));
+                               ptab, pb, d_amp, amp_capacity, d_amp_res, st));
     return AH_OK;
   }
   s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, &kb);

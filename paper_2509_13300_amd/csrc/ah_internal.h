@@ -126,26 +126,28 @@ hipError_t launch_sort_tm_mark(ah_hit* staged, ah_hit* out, const uint64_t* n_de
 
 // The tail of ah_query over at most kSegMax segments (pair, genome), after
 // the scan's segmented emit has put each segment's sites at
-// off[s] .. off[s + 1] of the staging area in no particular order.  Part 0:
-// each segment sorted into canonical order by a workgroup of one wave (in LDS
-// up to kSegLds sites), the Tm of every site and the amplicons each leader +
-// site starts; part 1: the amplicons.  key_bits: bits of pos << 2 |
-// strand-primer.  When the sites overflowed, nothing is written but the
-// amplicon result, an overflow with count and required 0.
+// off[s] .. off[s + 1] of the staging area in no particular order: one
+// launch, a workgroup of one wave per segment, sorts the segment into
+// canonical order (in LDS up to kSegLds sites), computes the Tm of every
+// site, counts the amplicons each leader + site starts, takes the amplicons
+// of the earlier segments by a look-back over lb, and writes its own.
+// key_bits: bits of pos << 2 | strand-primer.  When the sites overflowed,
+// nothing is written but the amplicon result, an overflow with count and
+// required 0.
 constexpr uint32_t kSegMax = 4096;  // AH_SEG_MAX of the scan core
 constexpr uint32_t kSegLds = 1024;
 struct SegBuffers {
   uint32_t* cnt;   // [n_seg] sites per segment, then
-  uint32_t* fill;  // [n_seg] places taken so far (both cleared before the filter)
+  uint32_t* fill;  // [n_seg] places taken so far, then
+  uint64_t* lb;    // [n_seg] look-back words (the three cleared together before the filter)
   uint64_t* off;   // [n_seg + 1] first site of each segment
-  uint64_t* amp;   // [n_seg] amplicons per segment
   uint32_t n_seg, n_genomes;
 };
 hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
                            const ah_result* hres, int key_bits, const ah_genomes& g,
                            const PrimerTab* tm_tabs, uint32_t n_pairs, const PairTab* pair_tabs,
                            const PairBuffers& pb, ah_amplicon* amp, uint64_t acap,
-                           ah_result* ares, int part, hipStream_t st);
+                           ah_result* ares, hipStream_t st);
 
 // Amplicon FASTA records, sequence hashes and amplitypes (see ah.h); rec_len
 // [acap], rec_at [acap] and cc [kPairGrid] are workspace; `waves` writers.

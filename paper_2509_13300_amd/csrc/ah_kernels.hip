@@ -416,20 +416,18 @@ struct TmJob {
 
 // The Tm of site record h (a genome and pair of this call); s_dh / s_ds:
 // the stack tables in LDS.
-__device__ __forceinline__ float tm_value(const TmJob& J, const ah_hit& h, const float* s_dh,
-                                          const float* s_ds) {
+// S: the segment words of the site's genome, wbase: its first word.
+__device__ __forceinline__ float tm_value_at(const TmJob& J, const ah_hit& h, u64 S, u64 wbase,
+                                             const float* s_dh, const float* s_ds) {
   const uint2* __restrict__ words = J.words;
   const u32* __restrict__ nmask = J.nmask;
-  const u64* __restrict__ word_off = J.word_off;
-  const u32* __restrict__ len = J.len;
   const PrimerTab* __restrict__ tabs = J.tabs;
   {
     const PrimerTab* T = &tabs[(u32)h.pair * 2u + (h.strand_primer & 1u)];
     const u32 L = T->L;
     const u32 strand = (h.strand_primer >> 1) & 1u;
-    const u64 S = ((u64)len[h.genome] + 31) >> 5;
     const u32 b = (u32)(h.pos / S);
-    const u64 w0 = word_off[h.genome] + (h.pos - (u64)b * S);
+    const u64 w0 = wbase + (h.pos - (u64)b * S);
     // ow: the base an oligo must carry at each primer position to pair with
     // the template (2 bits per position, primer 5'->3'); nb: positions
     // opposite a non-ACGT template base, which pair with nothing.  The
@@ -565,6 +563,11 @@ __device__ __forceinline__ float tm_value(const TmJob& J, const ah_hit& h, const
     }
     return best + (float)T->tshift;  // salt methods 1-4 (NaN stays NaN)
   }
+}
+
+__device__ __forceinline__ float tm_value(const TmJob& J, const ah_hit& h, const float* s_dh,
+                                          const float* s_ds) {
+  return tm_value_at(J, h, ((u64)J.len[h.genome] + 31) >> 5, J.word_off[h.genome], s_dh, s_ds);
 }
 
 // Sets hits[i].tm.  A record that does not name a genome and pair of this
@@ -950,15 +953,17 @@ __global__ __launch_bounds__(kBlock) void k_pair_write(
 // ------------------------------------------------ segmented query tail ----
 // ah_query over at most kSegMax segments (pair, genome).  The scan's
 // segmented emit has put each segment's records together, in no particular
-// order, at seg_off[s] .. seg_off[s + 1] of the staging area.  k_seg_sort puts
-// each segment in canonical order (its keys pos << 2 | strand-primer are
-// distinct), computes every site's Tm and counts the amplicons each leader +
-// site starts (the leader, its minus ranges and the count as the pairing
-// kernels above define them, inside one segment); k_seg_pair writes them at
-// the prefix of the segments' counts.  A segment of at most kSegLds records
-// is sorted and searched in LDS; a longer one by its workgroup alone in
-// global memory: stable LSD radix passes between the staging area and the
-// output, an odd number of them so that the last lands in the output.
+// order, at seg_off[s] .. seg_off[s + 1] of the staging area.  k_seg_tail, one
+// one-wave workgroup per segment, puts the segment in canonical order (its
+// keys pos << 2 | strand-primer are distinct), computes every site's Tm,
+// counts the amplicons each leader + site starts (the leader, its minus
+// ranges and the count as the pairing kernels above define them, inside one
+// segment), takes the amplicons of the earlier segments by a decoupled
+// look-back over the segments' published counts, and writes its amplicons
+// there.  A segment of at most kSegLds records is sorted and searched in LDS
+// (at most 64 in registers); a longer one by its workgroup alone in global
+// memory: stable LSD radix passes between the staging area and the output,
+// an odd number of them so that the last lands in the output.
 struct SegArgs {
   ah_hit* staged;          // the segments' records (the long path sorts through it)
   ah_hit* out;             // the records in canonical order
@@ -973,7 +978,10 @@ struct SegArgs {
   u32* pcr;                // each record (inclusive), by record index
   u32* cnt;                // amplicons each record leads (0: not a leader)
   uint4* rng;              // a leader's minus ranges, per + site of its group
-  u64* amp_seg;            // amplicons of each segment
+  u64* lb;                 // look-back words, one per segment (cleared before the scan)
+  ah_amplicon* amp;
+  u64 acap;
+  ah_result* ares;
 };
 
 __device__ __forceinline__ u64 seg_key(const ah_hit& h) {
@@ -1063,6 +1071,60 @@ __device__ __forceinline__ u64 seg_leaders(const SegArgs& A, const PairTab& pt, 
   return wave_sum(sum);
 }
 
+// Look-back words: (state << 62) | value, state 1: the segment's own
+// amplicons, 2: those of it and every earlier segment; kLbErr marks a
+// prefix that a wait gave up on.
+constexpr u64 kLbAgg = 1ull << 62, kLbIncl = 2ull << 62, kLbErr = 1ull << 61;
+constexpr u64 kLbVal = (1ull << 61) - 1ull;
+constexpr u32 kLbPolls = 1u << 20;  // polls of one window before a wait gives up
+
+__device__ __forceinline__ u64 lb_load(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Amplicons of segments 0 .. s - 1, with kLbErr set when a wait gave up
+// (every lane returns the same).  Segment s publishes its own count `agg`
+// first, then reads the words of the 64 segments before the ones it has
+// summed at once, back to the nearest inclusive word, and publishes its
+// inclusive count.  A workgroup waits only on lower segments, whose
+// workgroups were dispatched before it.
+__device__ __forceinline__ u64 seg_lookback(u64* lb, u32 s, u64 agg) {
+  const u32 lane = threadIdx.x & 63u;
+  if (s == 0) {
+    if (lane == 0) lb_store(&lb[0], kLbIncl | agg);
+    return 0;
+  }
+  if (lane == 0) lb_store(&lb[s], kLbAgg | agg);
+  u64 acc = 0, err = 0;
+  long long j = (long long)s - 1;
+  u32 polls = 0;
+  for (;;) {
+    const long long idx = j - (long long)lane;
+    const u64 w = idx >= 0 ? lb_load(&lb[idx]) : kLbIncl;
+    const u64 incl = __ballot((w >> 62) == 2u);
+    const u32 first = incl ? (u32)__ffsll((long long)incl) - 1u : 64u;  // lane 0 reads j
+    const u64 need = first >= 63u ? ~0ull : (2ull << first) - 1ull;
+    const u64 ready = __ballot((w >> 62) != 0u);
+    if ((ready & need) != need) {  // a word the sum needs is not published yet
+      if (++polls > kLbPolls) {
+        err = kLbErr;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    acc += wave_sum(lane <= first ? (w & kLbVal) : 0ull);
+    if (__ballot(lane <= first && (w & kLbErr) != 0ull)) err = kLbErr;
+    if (first < 64u) break;
+    j -= 64;
+  }
+  if (lane == 0) lb_store(&lb[s], kLbIncl | err | ((acc + agg) & kLbVal));
+  return acc | err;
+}
+
 // Bitonic sort of a[0 .. n2) (n2 a power of two) by the one-wave workgroup.
 __device__ __forceinline__ void lds_bitonic(u64* a, u32 n2) {
   for (u32 k = 2; k <= n2; k <<= 1)
@@ -1083,25 +1145,132 @@ __device__ __forceinline__ void lds_bitonic(u64* a, u32 n2) {
 constexpr u32 kSegIdxBits = 10;  // record index inside a sorted LDS key
 static_assert((1u << kSegIdxBits) == kSegLds, "LDS keys carry the record index");
 
-// Segment blockIdx.x: canonical order, Tm, leaders and amplicon counts.
-__global__ __launch_bounds__(kSegBlock) void k_seg_sort(SegArgs A) {
+// Writes the amplicons leader i starts, from slot `at` on (below acap), in
+// (end, orient) order: up to four lists (each + site of the group with the
+// fwd- and the rev- sites of its ranges), each ordered by end.
+template <class PosF, class KindF>
+__device__ __forceinline__ void seg_write(const SegArgs& A, const PairTab& pt, const ah_hit* o,
+                                          u64 base, u32 i, u32 m, u64 at, u64 acap,
+                                          ah_amplicon* __restrict__ amp, const PosF& P,
+                                          const KindF& K) {
+  const u32 pos = P(i);
+  const u32 ng = (i + 1 < m && plus_kind(K(i + 1)) && P(i + 1) == pos) ? 2u : 1u;
+  u32 cur[4], hi[4], want[4], lb[4], orient[4], plus[4];
+  int nl = 0;
+  for (u32 q = 0; q < ng; ++q) {
+    const uint4 g = A.rng[2 * (base + i) + q];
+    const u32 ap = K(i + q) & 1u;  // the + site's primer
+    cur[nl] = g.x; hi[nl] = g.y; want[nl] = 6u; lb[nl] = pt.lf; plus[nl] = i + q;
+    orient[nl] = ap ? (u32)AH_RF : (u32)AH_FF;
+    ++nl;
+    cur[nl] = g.z; hi[nl] = g.w; want[nl] = 7u; lb[nl] = pt.lr; plus[nl] = i + q;
+    orient[nl] = ap ? (u32)AH_RR : (u32)AH_FR;
+    ++nl;
+  }
+  for (int q = 0; q < nl; ++q)
+    while (cur[q] < hi[q] && K(cur[q]) != want[q]) ++cur[q];
+  const ah_hit lead = o[i];
+  u64 w = at;
+  while (w < acap) {
+    int best = -1;
+    u64 bend = 0;
+    for (int q = 0; q < nl; ++q) {
+      if (cur[q] >= hi[q]) continue;
+      const u64 e = (u64)P(cur[q]) + lb[q];
+      if (best < 0 || e < bend || (e == bend && orient[q] < orient[best])) {
+        best = q;
+        bend = e;
+      }
+    }
+    if (best < 0) break;
+    ah_amplicon a;
+    a.genome = lead.genome;
+    a.start = pos;
+    a.end = (u32)bend;
+    a.plus_hit = (u32)(base + plus[best]);
+    a.minus_hit = (u32)(base + cur[best]);
+    a.pair = lead.pair;
+    a.orient = (uint8_t)orient[best];
+    a.reserved = 0;
+    amp[w++] = a;
+    ++cur[best];
+    while (cur[best] < hi[best] && K(cur[best]) != want[best]) ++cur[best];
+  }
+}
+
+// The amplicon result from the query's total (kLbErr: a look-back wait gave
+// up, reported as AH_ERR_HIP), written by the last segment's workgroup.
+__device__ __forceinline__ void seg_result(const SegArgs& A, u64 total) {
+  const u64 n = total & kLbVal;
+  A.ares->required = n;
+  A.ares->count = n < A.acap ? n : A.acap;
+  A.ares->status = (total & kLbErr) ? AH_ERR_HIP : (n > A.acap ? AH_ERR_OVERFLOW : AH_OK);
+  A.ares->reserved = 0;
+}
+
+// Segment blockIdx.x: canonical order, Tm, leaders, amplicons.
+__global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   __shared__ u64 keys[kSegLds];  // also the long path's digit counters
   __shared__ u32 spos[kSegLds];
   __shared__ unsigned short pcf[kSegLds], pcr[kSegLds];
   __shared__ unsigned char kind[kSegLds];
   __shared__ float s_dh[16], s_ds[16];
-  tm_tables(s_dh, s_ds);
-  if (A.hres->status != AH_OK) return;
   const u32 t = threadIdx.x, s = blockIdx.x;
+  // the segment's constants, loaded together: its sites, first slot, pair
+  // table and genome (every site of segment s is on genome s mod n)
+  const int status = A.hres->status;
   const u32 m = A.seg_cnt[s];
-  if (m == 0) {
-    if (t == 0) A.amp_seg[s] = 0;
-    return;
-  }
   const u64 base = A.seg_off[s];
   const PairTab pt = A.ptabs[s / A.n_genomes];
-  const bool small = m <= kSegLds;
-  if (small) {
+  const u32 g = s % A.n_genomes;
+  const u64 S = ((u64)A.tj.len[g] + 31) >> 5, wbase = A.tj.word_off[g];
+  tm_tables(s_dh, s_ds);
+  if (status != AH_OK) {  // the sites overflowed: the pairing needs all of them
+    if (s == 0 && t == 0) {
+      A.ares->count = 0;
+      A.ares->required = 0;
+      A.ares->status = AH_ERR_OVERFLOW;
+      A.ares->reserved = 0;
+    }
+    return;
+  }
+  if (m == 0) {
+    const u64 before = seg_lookback(A.lb, s, 0ull);
+    if (s + 1 == A.n_seg && t == 0) seg_result(A, before);
+    return;
+  }
+  const bool tiny = m <= kSegBlock, small = m <= kSegLds;
+  ah_hit* o = A.out + base;
+  if (tiny) {
+    // one site per lane: a bitonic network over the wave's registers, then
+    // each lane takes the record of its sorted place from the lane that
+    // loaded it
+    ah_hit h{};
+    u64 key = ~0ull;
+    if (t < m) {
+      h = A.staged[base + t];
+      key = (seg_key(h) << 6) | t;
+    }
+    for (u32 k = 2; k <= kSegBlock; k <<= 1)
+      for (u32 j = k >> 1; j > 0; j >>= 1) {
+        const u64 y = __shfl_xor(key, j, 64);
+        const bool keep_min = ((t & j) == 0u) == ((t & k) == 0u);
+        key = keep_min ? (y < key ? y : key) : (y > key ? y : key);
+      }
+    u32 hv[4];
+    __builtin_memcpy(hv, &h, sizeof hv);
+    const int from = (int)(key & 63u);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hv[q] = __shfl(hv[q], from, 64);
+    if (t < m) {
+      ah_hit r;
+      __builtin_memcpy(&r, hv, sizeof r);
+      r.tm = tm_value_at(A.tj, r, S, wbase, s_dh, s_ds);
+      o[t] = r;
+      spos[t] = r.pos;
+      kind[t] = (unsigned char)seg_kind(r, pt);
+    }
+  } else if (small) {
     // keys with the record index below them, padded to a power of two
     u32 n2 = 1;
     while (n2 < m) n2 <<= 1;
@@ -1173,16 +1342,16 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_sort(SegArgs A) {
     // src == A.out + base: the passes are odd in number
   }
   // the Tm of every site, written with the record to its place
-  ah_hit* o = A.out + base;
-  for (u32 i = t; i < m; i += kSegBlock) {
-    ah_hit h = small ? A.staged[base + (u32)(keys[i] & (kSegLds - 1u))] : o[i];
-    h.tm = tm_value(A.tj, h, s_dh, s_ds);
-    o[i] = h;
-    if (small) {
-      spos[i] = h.pos;
-      kind[i] = (unsigned char)seg_kind(h, pt);
+  if (!tiny)
+    for (u32 i = t; i < m; i += kSegBlock) {
+      ah_hit h = small ? A.staged[base + (u32)(keys[i] & (kSegLds - 1u))] : o[i];
+      h.tm = tm_value_at(A.tj, h, S, wbase, s_dh, s_ds);
+      o[i] = h;
+      if (small) {
+        spos[i] = h.pos;
+        kind[i] = (unsigned char)seg_kind(h, pt);
+      }
     }
-  }
   __syncthreads();
   // kept fwd- (low half) and rev- (high half) minus sites up to each record
   u64 carry = 0;
@@ -1211,106 +1380,10 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_sort(SegArgs A) {
   else
     sum = seg_leaders(A, pt, base, m, [&](u32 i) { return o[i].pos; },
                       [&](u32 i) { return seg_kind(o[i], pt); }, A.pcf + base, A.pcr + base);
-  if (t == 0) A.amp_seg[s] = sum;
-}
-
-// Writes the amplicons leader i starts, from slot `at` on (below acap), in
-// (end, orient) order: up to four lists (each + site of the group with the
-// fwd- and the rev- sites of its ranges), each ordered by end.
-template <class PosF, class KindF>
-__device__ __forceinline__ void seg_write(const SegArgs& A, const PairTab& pt, const ah_hit* o,
-                                          u64 base, u32 i, u32 m, u64 at, u64 acap,
-                                          ah_amplicon* __restrict__ amp, const PosF& P,
-                                          const KindF& K) {
-  const u32 pos = P(i);
-  const u32 ng = (i + 1 < m && plus_kind(K(i + 1)) && P(i + 1) == pos) ? 2u : 1u;
-  u32 cur[4], hi[4], want[4], lb[4], orient[4], plus[4];
-  int nl = 0;
-  for (u32 q = 0; q < ng; ++q) {
-    const uint4 g = A.rng[2 * (base + i) + q];
-    const u32 ap = K(i + q) & 1u;  // the + site's primer
-    cur[nl] = g.x; hi[nl] = g.y; want[nl] = 6u; lb[nl] = pt.lf; plus[nl] = i + q;
-    orient[nl] = ap ? (u32)AH_RF : (u32)AH_FF;
-    ++nl;
-    cur[nl] = g.z; hi[nl] = g.w; want[nl] = 7u; lb[nl] = pt.lr; plus[nl] = i + q;
-    orient[nl] = ap ? (u32)AH_RR : (u32)AH_FR;
-    ++nl;
-  }
-  for (int q = 0; q < nl; ++q)
-    while (cur[q] < hi[q] && K(cur[q]) != want[q]) ++cur[q];
-  const ah_hit lead = o[i];
-  u64 w = at;
-  while (w < acap) {
-    int best = -1;
-    u64 bend = 0;
-    for (int q = 0; q < nl; ++q) {
-      if (cur[q] >= hi[q]) continue;
-      const u64 e = (u64)P(cur[q]) + lb[q];
-      if (best < 0 || e < bend || (e == bend && orient[q] < orient[best])) {
-        best = q;
-        bend = e;
-      }
-    }
-    if (best < 0) break;
-    ah_amplicon a;
-    a.genome = lead.genome;
-    a.start = pos;
-    a.end = (u32)bend;
-    a.plus_hit = (u32)(base + plus[best]);
-    a.minus_hit = (u32)(base + cur[best]);
-    a.pair = lead.pair;
-    a.orient = (uint8_t)orient[best];
-    a.reserved = 0;
-    amp[w++] = a;
-    ++cur[best];
-    while (cur[best] < hi[best] && K(cur[best]) != want[best]) ++cur[best];
-  }
-}
-
-// Segment blockIdx.x: its amplicons, after those of the earlier segments.
-__global__ __launch_bounds__(kSegBlock) void k_seg_pair(SegArgs A, ah_amplicon* __restrict__ amp,
-                                                        u64 acap, ah_result* __restrict__ ares) {
-  __shared__ u32 spos[kSegLds];
-  __shared__ unsigned char kind[kSegLds];
-  const u32 t = threadIdx.x, s = blockIdx.x;
-  if (A.hres->status != AH_OK) {  // the sites overflowed: the pairing needs all of them
-    if (s == 0 && t == 0) {
-      ares->count = 0;
-      ares->required = 0;
-      ares->status = AH_ERR_OVERFLOW;
-      ares->reserved = 0;
-    }
-    return;
-  }
-  // the amplicons of the earlier segments, and of all
-  u64 before = 0, total = 0;
-  for (u32 q = t; q < A.n_seg; q += kSegBlock) {
-    const u64 v = A.amp_seg[q];
-    total += v;
-    before += q < s ? v : 0ull;
-  }
-  before = wave_sum(before);
-  total = wave_sum(total);
-  if (s == 0 && t == 0) {
-    ares->required = total;
-    ares->count = total < acap ? total : acap;
-    ares->status = total > acap ? AH_ERR_OVERFLOW : AH_OK;
-    ares->reserved = 0;
-  }
-  if (A.amp_seg[s] == 0 || before >= acap) return;
-  const u32 m = A.seg_cnt[s];
-  const u64 base = A.seg_off[s];
-  const PairTab pt = A.ptabs[s / A.n_genomes];
-  const ah_hit* o = A.out + base;
-  const bool small = m <= kSegLds;
-  if (small) {
-    for (u32 i = t; i < m; i += kSegBlock) {
-      const ah_hit h = o[i];
-      spos[i] = h.pos;
-      kind[i] = (unsigned char)seg_kind(h, pt);
-    }
-    __syncthreads();
-  }
+  const u64 before = seg_lookback(A.lb, s, sum);
+  if (s + 1 == A.n_seg && t == 0) seg_result(A, (before & kLbErr) | ((before & kLbVal) + sum));
+  if ((before & kLbErr) || sum == 0 || before >= A.acap) return;
+  __syncthreads();  // this wave's counts and ranges are in place
   u64 at0 = before;
   for (u32 r0 = 0; r0 < m; r0 += kSegBlock) {
     const u32 i = r0 + t;
@@ -1318,12 +1391,12 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_pair(SegArgs A, ah_amplicon* 
     const u64 incl = wave_incl_scan(c);
     const u64 at = at0 + incl - c;
     at0 += __shfl(incl, 63, 64);
-    if (c && at < acap) {
+    if (c && at < A.acap) {
       if (small)
-        seg_write(A, pt, o, base, i, m, at, acap, amp, [&](u32 j) { return spos[j]; },
+        seg_write(A, pt, o, base, i, m, at, A.acap, A.amp, [&](u32 j) { return spos[j]; },
                   [&](u32 j) { return (u32)kind[j]; });
       else
-        seg_write(A, pt, o, base, i, m, at, acap, amp, [&](u32 j) { return o[j].pos; },
+        seg_write(A, pt, o, base, i, m, at, A.acap, A.amp, [&](u32 j) { return o[j].pos; },
                   [&](u32 j) { return seg_kind(o[j], pt); });
     }
   }
@@ -1836,7 +1909,7 @@ hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
                            const ah_result* hres, int key_bits, const ah_genomes& g,
                            const PrimerTab* tm_tabs, uint32_t n_pairs, const PairTab* pair_tabs,
                            const PairBuffers& pb, ah_amplicon* amp, uint64_t acap,
-                           ah_result* ares, int part, hipStream_t st) {
+                           ah_result* ares, hipStream_t st) {
   SegArgs A;
   A.staged = staged;
   A.out = out;
@@ -1852,10 +1925,11 @@ hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
   A.pcr = pb.pre_r;
   A.cnt = pb.cnt;
   A.rng = (uint4*)pb.rng;
-  A.amp_seg = (u64*)sg.amp;
-  const u32 grid = sg.n_seg > 0 ? sg.n_seg : 1u;
-  if (part == 0) k_seg_sort<<<grid, kSegBlock, 0, st>>>(A);
-  else k_seg_pair<<<grid, kSegBlock, 0, st>>>(A, amp, acap, ares);
+  A.lb = (u64*)sg.lb;
+  A.amp = amp;
+  A.acap = acap;
+  A.ares = ares;
+  k_seg_tail<<<sg.n_seg > 0 ? sg.n_seg : 1u, kSegBlock, 0, st>>>(A);
   return hipGetLastError();
 }
 
