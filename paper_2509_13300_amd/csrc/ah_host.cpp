@@ -1502,15 +1502,6 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   // window words per tile: a workgroup's in tile mode, a wave's (63 lanes
   // with windows) in wave mode
   const uint32_t tile = fn.wave ? (uint32_t)(63 * tn.u) : (uint32_t)(ah::kBlock * tn.u);
-  if (g->n <= ah::kSmallPrefix) {  // one launch, result reset (and segment counters) included
-    AH_HIP(ah::launch_tile_prefix_small(g->len, g->n, tile, w.tile_prefix, d_res, st,
-                                        seg ? seg->cnt : nullptr, seg ? 4 * seg->n_seg : 0));
-  } else {
-    if (seg) AH_HIP(ah::launch_zero_u64((uint64_t*)seg->cnt, 2 * seg->n_seg, st));
-    AH_HIP(ah::launch_result_init(d_res, st));
-    AH_HIP(ah::launch_tile_counts(g->len, g->n, tile, w.counts, st));
-    AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
-  }
   // persistent grid, no larger than an upper bound on the tiles (so that small
   // inputs get long slices); each workgroup owns ccap / grid records
   const uint64_t words_ub = ((uint64_t)g->max_len + 31) / 32;
@@ -1523,6 +1514,20 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   const unsigned grid = (unsigned)std::max<uint64_t>(
       1, std::min<uint64_t>({(uint64_t)cu_count() * wave_res, want,
                              fn.wave ? kMaxScanGrid / 4 : kMaxScanGrid}));
+  // the sums of the groups of 64 slices, cleared before the filter (in wave
+  // mode its waves add to them as they finish)
+  const uint32_t group_words = (grid + 63) / 64 * 32;
+  if (g->n <= ah::kSmallPrefix) {  // one launch, result reset and clearing included
+    AH_HIP(ah::launch_tile_prefix_small(g->len, g->n, tile, w.tile_prefix, d_res, st,
+                                        seg ? seg->cnt : nullptr, seg ? 4 * seg->n_seg : 0,
+                                        w.group_sites, group_words));
+  } else {
+    if (seg) AH_HIP(ah::launch_zero_u64((uint64_t*)seg->cnt, 2 * seg->n_seg, st));
+    AH_HIP(ah::launch_zero_u64(w.group_sites, group_words, st));
+    AH_HIP(ah::launch_result_init(d_res, st));
+    AH_HIP(ah::launch_tile_counts(g->len, g->n, tile, w.counts, st));
+    AH_HIP(ah::launch_exclusive_scan(w.counts, w.tile_prefix, g->n, nullptr, w.scan_tmp, st));
+  }
   // candidate slices: one per workgroup, one per wave in wave mode
   const unsigned n_slices = fn.wave ? grid * 4u : grid;
   const void* words = g->words;
@@ -1537,18 +1542,11 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   uint32_t* slice_tot = w.slice_tot;
   uint64_t* slice_win = w.slice_win;
   uint64_t* group_sites = w.group_sites;
-  void* args[] = {&words, &nmask,     &word_off,  &len,       &tp,        &n,
-                  &cands, &slice,     &slice_cnt, &slice_tot, &slice_win, &group_sites};
-  {
-    ProfScope prof_scan("scan", st);
-    AH_HIP(hipModuleLaunchKernel(fn.scan, grid, 1, 1, ah::kBlock, 1, 1, 0, st, args, nullptr));
-  }
   uint32_t* cand_sites = w.cand_sites;
   uint64_t* slice_sites = w.slice_sites;
-  const uint4* ccands = w.cands;
-  const uint32_t* cslice_cnt = w.slice_cnt;
   // the sort's start (kb set): emit writes the keys and counts the first
-  // digit into hist[0]; verify clears hist[0] and hist[1] before
+  // digit into hist[0]; the exact count (in the filter in wave mode) clears
+  // hist[0] and hist[1] before
   const int dbits = kb ? ah::sort_digit_bits(*kb) : 0;
   uint64_t* sort_keys = kb ? (uint64_t*)w.sb.keys[0] : nullptr;
   uint32_t* sort_idx = kb ? w.sb.idx[0] : nullptr;
@@ -1563,12 +1561,23 @@ ah_status launch_scan_kernel(const ScanFns& fn, Tuning tn, const ah_genomes* g, 
   uint32_t sort_chunk_min = ah::kSortChunkMin;
   uint32_t* seg_cnt = seg ? seg->cnt : nullptr;
   uint32_t seg_n = seg ? seg->n_genomes : 0;
+  void* args[] = {&words,      &nmask,      &word_off,   &len,         &tp,
+                  &n,          &cands,      &slice,      &slice_cnt,   &slice_tot,
+                  &slice_win,  &group_sites, &cand_sites, &slice_sites, &hist_a,
+                  &hist_b,     &hist_words, &seg_cnt,    &seg_n};
+  {
+    ProfScope prof_scan("scan", st);
+    AH_HIP(hipModuleLaunchKernel(fn.scan, grid, 1, 1, ah::kBlock, 1, 1, 0, st, args, nullptr));
+  }
+  const uint4* ccands = w.cands;
+  const uint32_t* cslice_cnt = w.slice_cnt;
   void* vargs[] = {&words,      &nmask,      &word_off,    &len,         &ccands,    &slice,
                    &cslice_cnt, &cand_sites, &slice_sites, &group_sites, &slice_win, &hist_a,
                    &hist_b,     &hist_words, &seg_cnt,     &seg_n};
   {
     ProfScope prof_verify("verify", st);
-    AH_HIP(hipModuleLaunchKernel(fn.verify, grid, 1, 1, ah::kBlock, 1, 1, 0, st, vargs, nullptr));
+    if (!fn.wave)  // wave mode: each wave of the filter counted its own candidates
+      AH_HIP(hipModuleLaunchKernel(fn.verify, grid, 1, 1, ah::kBlock, 1, 1, 0, st, vargs, nullptr));
     if (seg) {
       const uint32_t* cslice_tot = w.slice_tot;
       const uint64_t* cslice_win = w.slice_win;

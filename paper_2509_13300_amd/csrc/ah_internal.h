@@ -174,12 +174,13 @@ hipError_t launch_remap(ah_hit* hits, const ah_result* hres, ah_amplicon* amp, c
 // Scan: zero n u64 (graph-capturable, no memset node).
 hipError_t launch_zero_u64(uint64_t* p, uint32_t n, hipStream_t st);
 // Tile counts of n <= kSmallPrefix genomes, their exclusive prefix
-// (prefix[n] = total), the reset of `res` and (zero set) the clearing of
-// zero[0 .. n_zero), in one launch.
+// (prefix[n] = total), the reset of `res` and the clearing of
+// zero[0 .. n_zero) and zero64[0 .. n_zero64) (each when set), in one launch.
 constexpr uint32_t kSmallPrefix = 4096;
 hipError_t launch_tile_prefix_small(const uint32_t* len, uint32_t n, uint32_t tile_words,
                                     uint64_t* prefix, ah_result* res, hipStream_t st,
-                                    uint32_t* zero = nullptr, uint32_t n_zero = 0);
+                                    uint32_t* zero = nullptr, uint32_t n_zero = 0,
+                                    uint64_t* zero64 = nullptr, uint32_t n_zero64 = 0);
 
 // Recommended scan workspace for n genomes holding at most `window_words`
 // window words in total (pairs may be null: the minimum).

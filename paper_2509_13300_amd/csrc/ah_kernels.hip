@@ -116,10 +116,12 @@ __global__ __launch_bounds__(kSmallBlock) void k_tile_prefix_small(const u32* __
                                                                    u32 tile_words,
                                                                    u64* __restrict__ prefix,
                                                                    ah_result* r, u32* __restrict__ zero,
-                                                                   u32 n_zero) {
+                                                                   u32 n_zero, u64* __restrict__ zero64,
+                                                                   u32 n_zero64) {
   __shared__ u64 wsum[kSmallBlock / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (u32 i = threadIdx.x; i < n_zero; i += kSmallBlock) zero[i] = 0u;
+  for (u32 i = threadIdx.x; i < n_zero64; i += kSmallBlock) zero64[i] = 0ull;
   if (threadIdx.x == 0) {
     r->count = 0;
     r->required = 0;
@@ -1835,9 +1837,11 @@ hipError_t launch_result_init(ah_result* res, hipStream_t st) {
 
 hipError_t launch_tile_prefix_small(const uint32_t* len, uint32_t n, uint32_t tile_words,
                                     uint64_t* prefix, ah_result* res, hipStream_t st,
-                                    uint32_t* zero, uint32_t n_zero) {
+                                    uint32_t* zero, uint32_t n_zero, uint64_t* zero64,
+                                    uint32_t n_zero64) {
   k_tile_prefix_small<<<1, kSmallBlock, 0, st>>>(len, n, tile_words, (u64*)prefix, res, zero,
-                                                 zero ? n_zero : 0u);
+                                                 zero ? n_zero : 0u, (u64*)zero64,
+                                                 zero64 ? n_zero64 : 0u);
   return hipGetLastError();
 }
 

@@ -21,9 +21,11 @@
 //   path, where same-address device atomics would serialise).
 // * ah_verify_kernel: one workgroup per slice; the exact count (every
 //   position, the non-ACGT mask, the clamp, window starts inside the genome)
-//   of every candidate, stored per candidate and summed per slice.  Kept
-//   apart from the filter so that its registers do not lower the filter's
-//   occupancy.
+//   of every candidate, stored per candidate and summed per slice.  In wave
+//   mode each wave of the filter does this for its own slice after its last
+//   tile instead (the filter's occupancy is set by its LDS there, and the
+//   count's registers stay below that bound), and this kernel is not
+//   launched.
 // * ah_emit_kernel: one workgroup per slice; the slice's output offset is the
 //   sum of the earlier slices' sites (the sums of the earlier groups of 64
 //   slices, then of the earlier slices of its own group; no device atomics),
@@ -263,6 +265,41 @@ __device__ u32 ah_verify_one(const AhCtx& c, W w, u32 t, u32 p, u32 cand, AhHitR
 // Generated: the primer pair of pattern p.
 __device__ u32 ah_pat_pair(u32 p);
 
+// Exact count of candidate record `at` (the windows of its four patterns):
+// its sites go to cand_sites[at] and the running sums; with seg_cnt set they
+// are also counted per segment (pair, genome) at seg_cnt[pair * seg_n +
+// genome], and when every record's patterns share a pair (AH_QUAD_ONE_PAIR)
+// one device atomic per candidate reserves its sites' places in the segment:
+// cand_sites[at] then keeps the first place + 1 (0: no sites) for the
+// segmented emit instead of the count.
+__device__ __forceinline__ void ah_verify_cand(const uint2* __restrict__ words,
+                                               const u32* __restrict__ nmask,
+                                               const u64* __restrict__ word_off,
+                                               const u32* __restrict__ len,
+                                               const uint4* __restrict__ cands, u64 at,
+                                               u32* __restrict__ cand_sites,
+                                               u32* __restrict__ seg_cnt, u32 seg_n,
+                                               u64& my_sites, u64& my_win) {
+  const uint4 e = cands[2 * at], mk = cands[2 * at + 1];
+  const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
+  const u32 m[4] = {mk.x, mk.y, mk.z, mk.w};
+  u32 found = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (m[q]) {
+      const u32 f = ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], nullptr, 0, 0, false);
+      if (!AH_QUAD_ONE_PAIR && seg_cnt && f)
+        atomicAdd(&seg_cnt[ah_pat_pair(e.z + (u32)q) * seg_n + e.x], f);
+      found += f;
+      my_win += (u64)__popc(m[q]);
+    }
+  if (AH_QUAD_ONE_PAIR && seg_cnt)
+    cand_sites[at] = found ? atomicAdd(&seg_cnt[ah_pat_pair(e.z) * seg_n + e.x], found) + 1u : 0u;
+  else
+    cand_sites[at] = found;
+  my_sites += found;
+}
+
 // Words staged per tile: the tile's window words plus the halo, in 16-byte
 // pairs (every genome starts 16-byte aligned).
 #define AH_STAGE_PAIRS ((AH_TILE + AH_HALO + 1) / 2)
@@ -362,22 +399,29 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     const u64* __restrict__ word_off, const u32* __restrict__ len,
     const u64* __restrict__ tile_prefix, u32 n_genomes, uint4* __restrict__ cand_out,
     u32 slice, u32* __restrict__ slice_count, u32* __restrict__ slice_total,
-    u64* __restrict__ slice_win, u64* __restrict__ group_sites) {
-  // Each wave owns candidate slice s = 4 b + wave (slice records each) and
-  // reports it as a workgroup does in tile mode; the verify and emit passes
-  // read the four slices of a workgroup as one list.
+    u64* __restrict__ slice_win, u64* __restrict__ group_sites, u32* __restrict__ cand_sites,
+    u64* __restrict__ slice_sites, u32* __restrict__ hist_a, u32* __restrict__ hist_b,
+    u64 hist_words, u32* __restrict__ seg_cnt, u32 seg_n) {
+  // Each wave owns candidate slice s = 4 b + wave (slice records each).  After
+  // its last tile the wave also counts the sites of its own candidates exactly
+  // (what ah_verify_kernel does in tile mode), while the other waves still
+  // filter; the emit pass reads the four slices of a workgroup as one list.
+  // The grid clears the sort's first two histogram tables (the emit pass
+  // counts into the first, the first sort pass into the second); the group
+  // sums were cleared before this launch.
   __shared__ uint4 tiles[AH_BLOCK / 64][AH_WSTAGE_PAIRS];
+  for (u64 e = (u64)blockIdx.x * AH_BLOCK + threadIdx.x; e < hist_words;
+       e += (u64)gridDim.x * AH_BLOCK) {
+    hist_a[e] = 0u;
+    hist_b[e] = 0u;
+  }
   const u64 n_tiles = tile_prefix[n_genomes];
   const AhCands k{cand_out, slice, slice_win};
   const u32 wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const u32 lane = threadIdx.x & 63u;
   const u32 s = blockIdx.x * (AH_BLOCK / 64) + wv;
   uint4* my = tiles[wv];
-  if (lane == 0) {
-    slice_win[s] = 0;  // windows of dropped candidates, added by ah_wcand
-    if (wv == 0 && blockIdx.x % AH_SLICE_GROUP == 0)  // summed by the verify pass
-      group_sites[(blockIdx.x / AH_SLICE_GROUP) * AH_GROUP_STRIDE] = 0;
-  }
+  if (lane == 0) slice_win[s] = 0;  // windows of dropped candidates, added by ah_wcand
   __builtin_amdgcn_s_waitcnt(AH_WAIT_VMCNT0);  // the zero is in place before any atomic on it
   u32 cnt = 0;
   u32 lo = 0;
@@ -404,9 +448,24 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     cnt = ah_wgroups((ah_lds_uint2*)my + (cur.t0 & 1u), cur.t0, cur.c, k, lane, my, nx, cnt, s);
     cur = nx;
   }
+  // the exact count of this wave's candidates (records written by its own
+  // lanes: the fence orders their stores before the loads)
+  __threadfence_block();
+  const u32 nk = min(cnt, slice);
+  u64 my_sites = 0, my_win = 0;
+  for (u32 i = lane; i < nk; i += 64u)
+    ah_verify_cand(words, nmask, word_off, len, cand_out, (u64)s * slice + i, cand_sites, seg_cnt,
+                   seg_n, my_sites, my_win);
+  for (u32 o = 32; o > 0; o >>= 1) {
+    my_sites += __shfl_xor(my_sites, o, 64);
+    my_win += __shfl_xor(my_win, o, 64);
+  }
   if (lane == 0) {  // every wave reports its slice, with or without tiles
-    slice_count[s] = min(cnt, slice);
+    slice_count[s] = nk;
     slice_total[s] = cnt;
+    slice_sites[s] = my_sites;
+    if (my_sites) atomicAdd(&group_sites[(blockIdx.x / AH_SLICE_GROUP) * AH_GROUP_STRIDE], my_sites);
+    atomicAdd(&slice_win[s], my_win);
   }
 }
 #else
@@ -415,7 +474,9 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     const u64* __restrict__ word_off, const u32* __restrict__ len,
     const u64* __restrict__ tile_prefix, u32 n_genomes, uint4* __restrict__ cand_out,
     u32 slice, u32* __restrict__ slice_count, u32* __restrict__ slice_total,
-    u64* __restrict__ slice_win, u64* __restrict__ group_sites) {
+    u64* __restrict__ slice_win, u64* __restrict__ group_sites, u32* __restrict__ cand_sites,
+    u64* __restrict__ slice_sites, u32* __restrict__ hist_a, u32* __restrict__ hist_b,
+    u64 hist_words, u32* __restrict__ seg_cnt, u32 seg_n) {
   __shared__ uint4 tile[AH_STAGE_PAIRS];
   const u64 n_tiles = tile_prefix[n_genomes];
   const AhCands k{cand_out, slice, nullptr};
@@ -423,8 +484,6 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     ah_n_cand = 0;
     ah_n_lost = 0;
   }
-  if (blockIdx.x % AH_SLICE_GROUP == 0 && threadIdx.x == 0)
-    group_sites[(blockIdx.x / AH_SLICE_GROUP) * AH_GROUP_STRIDE] = 0;  // summed by the verify pass
   __syncthreads();
   u32 lo = 0;
   for (u64 T = blockIdx.x; T < n_tiles; T += gridDim.x) {
@@ -474,27 +533,9 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
   __syncthreads();
   const AhSlices sl = ah_slices(slice_count, blockIdx.x);
   u64 my_sites = 0, my_win = 0;
-  for (u32 i = threadIdx.x; i < sl.total; i += AH_BLOCK) {
-    const u64 at = ah_slice_at(sl, blockIdx.x, slice, i);
-    const uint4 e = cands[2 * at], mk = cands[2 * at + 1];
-    const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
-    const u32 m[4] = {mk.x, mk.y, mk.z, mk.w};
-    u32 found = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (m[q]) {
-        const u32 f = ah_verify_one(c, c.gw + e.y, e.y, e.z + (u32)q, m[q], nullptr, 0, 0, false);
-        if (!AH_QUAD_ONE_PAIR && seg_cnt && f)
-          atomicAdd(&seg_cnt[ah_pat_pair(e.z + (u32)q) * seg_n + e.x], f);
-        found += f;
-        my_win += (u64)__popc(m[q]);
-      }
-    if (AH_QUAD_ONE_PAIR && seg_cnt)
-      cand_sites[at] = found ? atomicAdd(&seg_cnt[ah_pat_pair(e.z) * seg_n + e.x], found) + 1u : 0u;
-    else
-      cand_sites[at] = found;
-    my_sites += found;
-  }
+  for (u32 i = threadIdx.x; i < sl.total; i += AH_BLOCK)
+    ah_verify_cand(words, nmask, word_off, len, cands, ah_slice_at(sl, blockIdx.x, slice, i),
+                   cand_sites, seg_cnt, seg_n, my_sites, my_win);
   if (my_sites) atomicAdd(&s_sites, my_sites);
   atomicAdd(&s_win, my_win);
   __syncthreads();
@@ -550,8 +591,8 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
     mine_all += v;
     mine_before += q < my ? v : 0ull;
   }
-  for (u32 w = my * AH_SLICE_GROUP + threadIdx.x; w < blockIdx.x; w += AH_BLOCK)
-    mine_before += slice_sites[w];
+  for (u32 w = my * AH_SLICE_GROUP * AH_SPW + threadIdx.x; w < blockIdx.x * AH_SPW; w += AH_BLOCK)
+    mine_before += slice_sites[w];  // sites per slice (AH_SPW slices per workgroup)
   u64 slot, found;
   ah_block_scan(mine_before, tmp, &slot);
   ah_block_scan(mine_all, tmp, &found);
