@@ -263,6 +263,8 @@ def gpu_run(name: str, steps: int, warmup: int):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "ah_scan_kernel", "algorithmic_bytes": scan_bytes,
+                     "kernel_work": "filter over the packed genome, then each wave's exact "
+                                    "count of its own candidates",
                      # the filter's VALU issue rate: the profiled instruction count of
                      # this exact program (64 lanes each) over the live kernel time
                      "valu_issue": None if valu is None else {
