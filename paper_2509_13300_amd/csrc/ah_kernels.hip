@@ -418,17 +418,19 @@ struct TmJob {
 
 // The Tm of site record h (a genome and pair of this call); s_dh / s_ds:
 // the stack tables in LDS.
-// S: the segment words of the site's genome, wbase: its first word.
+// S: the segment words of the site's genome, wbase: its first word; T2: the
+// two primer tables (fwd, rev) of the site's pair (global memory, or a copy
+// in LDS).
 __device__ __forceinline__ float tm_value_at(const TmJob& J, const ah_hit& h, u64 S, u64 wbase,
-                                             const float* s_dh, const float* s_ds) {
+                                             const float* s_dh, const float* s_ds,
+                                             const PrimerTab* T2) {
   const uint2* __restrict__ words = J.words;
   const u32* __restrict__ nmask = J.nmask;
-  const PrimerTab* __restrict__ tabs = J.tabs;
   {
-    const PrimerTab* T = &tabs[(u32)h.pair * 2u + (h.strand_primer & 1u)];
+    const PrimerTab* T = &T2[h.strand_primer & 1u];
     const u32 L = T->L;
     const u32 strand = (h.strand_primer >> 1) & 1u;
-    const u32 b = (u32)(h.pos / S);
+    const u32 b = h.pos / (u32)S;  // S <= 2^27: 32-bit division
     const u64 w0 = wbase + (h.pos - (u64)b * S);
     // ow: the base an oligo must carry at each primer position to pair with
     // the template (2 bits per position, primer 5'->3'); nb: positions
@@ -515,15 +517,25 @@ __device__ __forceinline__ float tm_value_at(const TmJob& J, const ah_hit& h, u6
     const u64 eq0 = ~(x | (x >> 1)) & lanes;  // paired positions of the representative
     const u32 mism0 = L - (u32)__popcll(eq0);
     float best = __int_as_float(0x7fc00000);  // NaN: no compatible oligo
+    // The representative's stacks are summed once.  Another pairing turns
+    // positions of it into mismatches, which only removes the stacks on
+    // either side of each: its sums are the representative's minus those
+    // (compensated sums throughout).
+    const u64 st0 = eq0 & (eq0 >> 2) & stackm;
+    float sh0 = 0.f, ch0 = 0.f, ss0 = 0.f, cs0 = 0.f;
+    for (u64 st = st0; st; st &= st - 1) {
+      const u32 j2 = (u32)__ffsll((long long)st) - 1u;
+      const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
+      two_sum(sh0, ch0, s_dh[ix]);
+      two_sum(ss0, cs0, s_ds[ix]);
+    }
     auto consider = [&](u64 eq) {
-      float sh = 0.f, ch = 0.f, ss = 0.f, cs = 0.f;
-      u64 st = eq & (eq >> 2) & stackm;
-      while (st) {
+      float sh = sh0, ch = ch0, ss = ss0, cs = cs0;
+      for (u64 st = st0 & ~(eq & (eq >> 2)); st; st &= st - 1) {  // the stacks eq breaks
         const u32 j2 = (u32)__ffsll((long long)st) - 1u;
-        st &= st - 1;
         const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
-        two_sum(sh, ch, s_dh[ix]);
-        two_sum(ss, cs, s_ds[ix]);
+        two_sum(sh, ch, -s_dh[ix]);
+        two_sum(ss, cs, -s_ds[ix]);
       }
       if (eq) {
         const u32 lo = (u32)__ffsll((long long)eq) - 1u;
@@ -559,7 +571,7 @@ __device__ __forceinline__ float tm_value_at(const TmJob& J, const ah_hit& h, u6
           const u64 low = comb & (0ull - comb);
           const u64 r = comb + low;
           if (r == 0) break;
-          comb = (((r ^ comb) >> 2) / low) | r;
+          comb = (((r ^ comb) >> 2) >> (__ffsll((long long)low) - 1)) | r;  // low: a power of two
         }
       }
     }
@@ -569,7 +581,8 @@ __device__ __forceinline__ float tm_value_at(const TmJob& J, const ah_hit& h, u6
 
 __device__ __forceinline__ float tm_value(const TmJob& J, const ah_hit& h, const float* s_dh,
                                           const float* s_ds) {
-  return tm_value_at(J, h, ((u64)J.len[h.genome] + 31) >> 5, J.word_off[h.genome], s_dh, s_ds);
+  return tm_value_at(J, h, ((u64)J.len[h.genome] + 31) >> 5, J.word_off[h.genome], s_dh, s_ds,
+                     &J.tabs[(u32)h.pair * 2u]);
 }
 
 // Sets hits[i].tm.  A record that does not name a genome and pair of this
@@ -979,7 +992,7 @@ struct SegArgs {
   u32* pcf;                // long segments: kept fwd- / rev- minus sites up to
   u32* pcr;                // each record (inclusive), by record index
   u32* cnt;                // amplicons each record leads (0: not a leader)
-  uint4* rng;              // a leader's minus ranges, per + site of its group
+  uint4* rng;              // a leader's minus ranges, one per record
   u64* lb;                 // look-back words, one per segment (cleared before the scan)
   ah_amplicon* amp;
   u64 acap;
@@ -1050,24 +1063,30 @@ __device__ __forceinline__ u64 wave_sum(u64 v) {
 }
 
 // Leaders of the sorted segment at records base .. base + m: the amplicons
-// each starts (cnt) and its ranges (rng); returns the segment's total.
+// each starts (cnt) and its minus ranges (rng: fwd-primer x, y and
+// rev-primer z, w, the same for both + sites of a group, which share the
+// position); returns the segment's total.  The last record a lane handled
+// leaves its count and ranges in c_last / r_last (for a segment of at most
+// one record per lane, this lane's own).
 template <class PosF, class KindF, class C>
 __device__ __forceinline__ u64 seg_leaders(const SegArgs& A, const PairTab& pt, u64 base, u32 m,
                                            const PosF& P, const KindF& K, const C* pcf,
-                                           const C* pcr) {
+                                           const C* pcr, u32& c_last, uint4& r_last) {
   u64 sum = 0;
+  c_last = 0;
+  r_last = make_uint4(0u, 0u, 0u, 0u);
   for (u32 i = threadIdx.x; i < m; i += kSegBlock) {
     u32 c = 0;
     const u32 k = K(i), pos = P(i);
     if (plus_kind(k) && !(i > 0 && plus_kind(K(i - 1)) && P(i - 1) == pos)) {
       const u32 ng = (i + 1 < m && plus_kind(K(i + 1)) && P(i + 1) == pos) ? 2u : 1u;
-      // both + sites of a group share the position, hence the ranges
       const uint2 rf = seg_range(P, m, pos, pt.lf, pt), rr = seg_range(P, m, pos, pt.lr, pt);
       c = ng * (seg_count(pcf, rf) + seg_count(pcr, rr));
-      for (u32 q = 0; q < ng; ++q)
-        A.rng[2 * (base + i) + q] = make_uint4(rf.x, rf.y, rr.x, rr.y);
+      r_last = make_uint4(rf.x, rf.y, rr.x, rr.y);
+      A.rng[base + i] = r_last;
     }
     A.cnt[base + i] = c;
+    c_last = c;
     sum += c;
   }
   return wave_sum(sum);
@@ -1154,13 +1173,12 @@ template <class PosF, class KindF>
 __device__ __forceinline__ void seg_write(const SegArgs& A, const PairTab& pt, const ah_hit* o,
                                           u64 base, u32 i, u32 m, u64 at, u64 acap,
                                           ah_amplicon* __restrict__ amp, const PosF& P,
-                                          const KindF& K) {
+                                          const KindF& K, uint4 g) {
   const u32 pos = P(i);
   const u32 ng = (i + 1 < m && plus_kind(K(i + 1)) && P(i + 1) == pos) ? 2u : 1u;
   u32 cur[4], hi[4], want[4], lb[4], orient[4], plus[4];
   int nl = 0;
   for (u32 q = 0; q < ng; ++q) {
-    const uint4 g = A.rng[2 * (base + i) + q];
     const u32 ap = K(i + q) & 1u;  // the + site's primer
     cur[nl] = g.x; hi[nl] = g.y; want[nl] = 6u; lb[nl] = pt.lf; plus[nl] = i + q;
     orient[nl] = ap ? (u32)AH_RF : (u32)AH_FF;
@@ -1217,16 +1235,20 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   __shared__ unsigned short pcf[kSegLds], pcr[kSegLds];
   __shared__ unsigned char kind[kSegLds];
   __shared__ float s_dh[16], s_ds[16];
+  __shared__ PrimerTab s_tab[2];  // the pair's primer tables, read throughout the Tm
   const u32 t = threadIdx.x, s = blockIdx.x;
   // the segment's constants, loaded together: its sites, first slot, pair
-  // table and genome (every site of segment s is on genome s mod n)
+  // tables and genome (every site of segment s is on genome s mod n)
   const int status = A.hres->status;
   const u32 m = A.seg_cnt[s];
   const u64 base = A.seg_off[s];
-  const PairTab pt = A.ptabs[s / A.n_genomes];
-  const u32 g = s % A.n_genomes;
+  const u32 pair = s / A.n_genomes, g = s % A.n_genomes;
+  const PairTab pt = A.ptabs[pair];
   const u64 S = ((u64)A.tj.len[g] + 31) >> 5, wbase = A.tj.word_off[g];
-  tm_tables(s_dh, s_ds);
+  static_assert(sizeof(PrimerTab) % 4 == 0, "primer tables copy as words");
+  for (u32 i = t; i < 2 * sizeof(PrimerTab) / 4; i += kSegBlock)
+    ((u32*)s_tab)[i] = ((const u32*)(A.tj.tabs + 2 * pair))[i];
+  tm_tables(s_dh, s_ds);  // its barrier also covers the copy
   if (status != AH_OK) {  // the sites overflowed: the pairing needs all of them
     if (s == 0 && t == 0) {
       A.ares->count = 0;
@@ -1267,7 +1289,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
     if (t < m) {
       ah_hit r;
       __builtin_memcpy(&r, hv, sizeof r);
-      r.tm = tm_value_at(A.tj, r, S, wbase, s_dh, s_ds);
+      r.tm = tm_value_at(A.tj, r, S, wbase, s_dh, s_ds, s_tab);
       o[t] = r;
       spos[t] = r.pos;
       kind[t] = (unsigned char)seg_kind(r, pt);
@@ -1347,7 +1369,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   if (!tiny)
     for (u32 i = t; i < m; i += kSegBlock) {
       ah_hit h = small ? A.staged[base + (u32)(keys[i] & (kSegLds - 1u))] : o[i];
-      h.tm = tm_value_at(A.tj, h, S, wbase, s_dh, s_ds);
+      h.tm = tm_value_at(A.tj, h, S, wbase, s_dh, s_ds, s_tab);
       o[i] = h;
       if (small) {
         spos[i] = h.pos;
@@ -1376,12 +1398,15 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   }
   __syncthreads();
   u64 sum;
+  u32 c_own;
+  uint4 r_own;
   if (small)
     sum = seg_leaders(A, pt, base, m, [&](u32 i) { return spos[i]; },
-                      [&](u32 i) { return (u32)kind[i]; }, pcf, pcr);
+                      [&](u32 i) { return (u32)kind[i]; }, pcf, pcr, c_own, r_own);
   else
     sum = seg_leaders(A, pt, base, m, [&](u32 i) { return o[i].pos; },
-                      [&](u32 i) { return seg_kind(o[i], pt); }, A.pcf + base, A.pcr + base);
+                      [&](u32 i) { return seg_kind(o[i], pt); }, A.pcf + base, A.pcr + base,
+                      c_own, r_own);
   const u64 before = seg_lookback(A.lb, s, sum);
   if (s + 1 == A.n_seg && t == 0) seg_result(A, (before & kLbErr) | ((before & kLbVal) + sum));
   if ((before & kLbErr) || sum == 0 || before >= A.acap) return;
@@ -1389,17 +1414,19 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   u64 at0 = before;
   for (u32 r0 = 0; r0 < m; r0 += kSegBlock) {
     const u32 i = r0 + t;
-    const u32 c = i < m ? A.cnt[base + i] : 0u;
+    // one record per lane: the count and ranges are still in this lane's registers
+    const u32 c = tiny ? c_own : (i < m ? A.cnt[base + i] : 0u);
     const u64 incl = wave_incl_scan(c);
     const u64 at = at0 + incl - c;
     at0 += __shfl(incl, 63, 64);
     if (c && at < A.acap) {
+      const uint4 g = tiny ? r_own : A.rng[base + i];
       if (small)
         seg_write(A, pt, o, base, i, m, at, A.acap, A.amp, [&](u32 j) { return spos[j]; },
-                  [&](u32 j) { return (u32)kind[j]; });
+                  [&](u32 j) { return (u32)kind[j]; }, g);
       else
         seg_write(A, pt, o, base, i, m, at, A.acap, A.amp, [&](u32 j) { return o[j].pos; },
-                  [&](u32 j) { return seg_kind(o[j], pt); });
+                  [&](u32 j) { return seg_kind(o[j], pt); }, g);
     }
   }
 }
