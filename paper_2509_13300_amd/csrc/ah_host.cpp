@@ -831,8 +831,22 @@ std::string gen_wave_groups(const std::vector<Pattern>& pats, size_t G) {
       any += (i > a ? " | c" : "c") + std::to_string(i - a);
     }
     // a wave-wide vote, so that every lane takes the branch and keeps the same
-    // candidate count (the count is uniform over the wave)
-    s += "    if (__any((" + any + ") != 0u)) {\n";
+    // candidate count (the count is uniform over the wave).  With an even
+    // number of patterns the last filter's result is compared with the OR of
+    // the others as one 64-bit pair (v_cmp_ne_u64 into a lane mask, the
+    // branch on that mask is scalar): one OR fewer per window word than a
+    // 32-bit compare of the OR of all of them.
+    const size_t gn = b - a;
+    if (gn >= 2 && gn % 2 == 0) {
+      std::string rest;
+      for (size_t i = 0; i + 1 < gn; ++i) rest += (i ? " | c" : "c") + std::to_string(i);
+      s += "    u64 any_c;\n"
+           "    asm volatile(\"v_cmp_ne_u64_e64 %0, 0, %1\" : \"=s\"(any_c) : \"v\"((u64)(" + rest +
+           ") | ((u64)c" + std::to_string(gn - 1) + " << 32)));\n";
+      s += "    if (any_c != 0ull) {\n";
+    } else {
+      s += "    if (__any((" + any + ") != 0u)) {\n";
+    }
     s += quad_appends(a, b, true);
     s += "    }\n  }\n  return cnt;\n}\n";
   }
