@@ -337,10 +337,13 @@ size_t ah_pair_workspace_bytes(uint64_t hit_capacity, uint32_t n_pairs);
  * workgroup per segment sorts them into canonical order (in LDS up to 1,024
  * sites), computes their Tm, counts the amplicons each + site starts, takes
  * its first amplicon slot from the counts of the earlier segments and
- * writes its amplicons, in one launch.  With more segments (or
- * AH_QUERY_SEGMENTED=0 in the environment) the sites go through the radix
- * sort, the Tm is computed by extra workgroups of its first pass and the
- * pairing's per-chunk counts of kept minus sites are taken by its last.
+ * writes its amplicons, in one launch.  With more segments, when a pair is
+ * expected to give more than 512 sites on the longest genome (random bases,
+ * both primers and strands: one workgroup per segment would take too long),
+ * or with AH_QUERY_SEGMENTED=0 in the environment (=1 forces the segmented
+ * tail), the sites go through the radix sort instead, the Tm is computed by
+ * extra workgroups of its first pass and the pairing's per-chunk counts of
+ * kept minus sites are taken by its last.
  * Errors: those of the three calls. */
 ah_status ah_query(const ah_genomes* genomes, const ah_primer_pair* pairs, const ah_window* windows,
                    uint32_t n_pairs, const ah_tm_params* tm, ah_hit* d_hits, uint64_t hit_capacity,

@@ -1493,10 +1493,23 @@ bool carve_seg(const ScanWs& w, uint32_t n_genomes, uint64_t n_seg, ah::SegBuffe
   return c.cur <= c.end;
 }
 
-// AH_QUERY_SEGMENTED=0 keeps ah_query on the radix-sort tail.
-bool seg_mode() {
+// The segmented tail gives each (pair, genome) segment one wave, which takes
+// the segment's sites 64 at a time: past a few hundred sites per segment the
+// radix tail, which spreads every site over the whole device, is faster.  The
+// expected random sites of a pair's segment on the longest genome (both
+// primers, both strands) decide, against kSegExpected; AH_QUERY_SEGMENTED=1
+// or 0 forces one tail (the segmented one still only up to kSegMax segments).
+constexpr double kSegExpected = 512.0;
+bool seg_mode(const ah_primer_pair* pairs, uint32_t n_pairs, uint32_t max_len) {
   const char* e = getenv("AH_QUERY_SEGMENTED");
-  return !(e && e[0] == '0');
+  if (e && e[0] == '0') return false;
+  if (e && e[0] == '1') return true;
+  for (uint32_t q = 0; q < n_pairs; ++q) {
+    const double rate = 2.0 * (ah::site_probability(pairs[q].fwd, pairs[q].k, pairs[q].clamp) +
+                               ah::site_probability(pairs[q].rev, pairs[q].k, pairs[q].clamp));
+    if (rate * (double)max_len > kSegExpected) return false;
+  }
+  return true;
 }
 
 // Reset of d_res, tile counts and prefix, then the filter, the exact count
@@ -1858,6 +1871,35 @@ ah_status pair_table(const PairSet& ps, const ah_window* windows, uint32_t n_pai
 }  // namespace
 
 namespace ah {
+// Members of an IUPAC code (0 for anything else; primers are validated first).
+static int code_size(char c) {
+  switch (c | 0x20) {
+    case 'a': case 'c': case 'g': case 't': return 1;
+    case 'r': case 'y': case 's': case 'w': case 'k': case 'm': return 2;
+    case 'b': case 'd': case 'h': case 'v': return 3;
+    case 'n': return 4;
+    default: return 0;
+  }
+}
+
+// A Poisson-binomial over the non-clamp positions (each mismatches with
+// chance 1 - |set| / 4), times the clamp's chance to match.
+double site_probability(const std::string& primer, uint32_t k, uint32_t clamp) {
+  const int L = (int)primer.size();
+  const int free_len = L - (int)std::min<uint32_t>(clamp, (uint32_t)L);
+  std::vector<double> d(L + 2, 0.0);
+  d[0] = 1.0;
+  for (int j = 0; j < free_len; ++j) {
+    const double p = code_size(primer[j]) / 4.0;
+    for (int m = j + 1; m >= 1; --m) d[m] = d[m] * p + d[m - 1] * (1.0 - p);
+    d[0] *= p;
+  }
+  double pk = 0.0;
+  for (int m = 0; m <= (int)k && m <= L; ++m) pk += d[m];
+  for (int j = free_len; j < L; ++j) pk *= code_size(primer[j]) / 4.0;
+  return pk;
+}
+
 ah_status check_tm(const ah_primer_pair* pairs, uint32_t n_pairs, const ah_tm_params* p) {
   PairSet ps;
   return check_tm_request(pairs, n_pairs, p, ps);
@@ -2168,7 +2210,7 @@ ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_wi
   const auto* ttab = (const ah::PrimerTab*)tm_tabs;
   const auto* ptab = (const ah::PairTab*)pair_tabs;
   ah::SegBuffers sg{};
-  if (g->n > 0 && seg_mode() &&
+  if (g->n > 0 && seg_mode(pairs, n_pairs, g->max_len) &&
       carve_seg(w, g->n, (uint64_t)n_pairs * g->n, sg)) {
     // each segment (pair, genome) sorted, its Tm and amplicons, by one workgroup
     s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, nullptr, &sg);

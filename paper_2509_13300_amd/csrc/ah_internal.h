@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "ah.h"
 
 namespace ah {
@@ -191,6 +193,11 @@ size_t scan_workspace_for(uint32_t n, uint64_t window_words, const ah_primer_pai
 // (AH_SCAN_SCRATCH_BYTES bytes, the workspace of ah_scan_primers_noalloc),
 // looked up on the first call on each device.
 hipError_t scan_scratch(void** ptr);
+
+// Chance that a window of independent uniform bases is a site of `primer` on
+// one strand (clamp positions match, at most k others mismatch): the serving
+// form sizes buffers from it, and ah_query picks its tail.
+double site_probability(const std::string& primer, uint32_t k, uint32_t clamp);
 
 // Validation of a Tm request exactly as ah_tm does it, with no device work.
 ah_status check_tm(const ah_primer_pair* pairs, uint32_t n_pairs, const ah_tm_params* p);

@@ -46,36 +46,6 @@ namespace {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-// Members of an IUPAC code (0 for anything else; primers are validated first).
-int code_size(char c) {
-  switch (c | 0x20) {
-    case 'a': case 'c': case 'g': case 't': return 1;
-    case 'r': case 'y': case 's': case 'w': case 'k': case 'm': return 2;
-    case 'b': case 'd': case 'h': case 'v': return 3;
-    case 'n': return 4;
-    default: return 0;
-  }
-}
-
-// Chance that a window of independent uniform bases is a site of `primer` on
-// one strand: the clamp positions match and at most k others mismatch.  Used
-// only to size buffers; a part that overflows is run again with exact counts.
-double site_probability(const std::string& primer, uint32_t k, uint32_t clamp) {
-  const int L = (int)primer.size();
-  const int free_len = L - (int)std::min<uint32_t>(clamp, (uint32_t)L);
-  std::vector<double> d(L + 2, 0.0);
-  d[0] = 1.0;
-  for (int j = 0; j < free_len; ++j) {
-    const double p = code_size(primer[j]) / 4.0;
-    for (int m = j + 1; m >= 1; --m) d[m] = d[m] * p + d[m - 1] * (1.0 - p);
-    d[0] *= p;
-  }
-  double pk = 0.0;
-  for (int m = 0; m <= (int)k && m <= L; ++m) pk += d[m];
-  for (int j = free_len; j < L; ++j) pk *= code_size(primer[j]) / 4.0;
-  return pk;
-}
-
 // First-fit allocator over the caller's pool (offsets; 256-byte granules).
 class Pool {
  public:
@@ -614,8 +584,8 @@ ah_status ah_server_submit(ah_server* srv, const ah_job* job, uint64_t* job_id) 
   // parts: whole genomes, at most part_bases bases and about max_part_hits
   // expected sites each
   const auto& cfg = srv->cfg;
-  const double rate = 2.0 * (site_probability(j->fwd, j->pair.k, j->pair.clamp) +
-                             site_probability(j->rev, j->pair.k, j->pair.clamp));
+  const double rate = 2.0 * (ah::site_probability(j->fwd, j->pair.k, j->pair.clamp) +
+                             ah::site_probability(j->rev, j->pair.k, j->pair.clamp));
   const double scale = cfg.capacity_scale;
   double cut = (double)cfg.part_bases;
   if (rate * scale > 0) cut = std::min(cut, (double)cfg.max_part_hits / (rate * scale));

@@ -1,9 +1,10 @@
 """ah_query (scan, Tm and pairing in one call) gives the same bytes as the
 three separate calls, on both of its tails: per segment (pair, genome) --
-sorted in LDS, or through global memory for a segment longer than LDS holds
--- and, past the segment limit or when asked (AH_QUERY_SEGMENTED=0), the
-radix sort with the Tm computed inside its first pass and the pairing's
-chunk counts inside its last."""
+sorted in registers, in LDS, or through global memory for a segment longer
+than LDS holds -- and, past the segment limit, for pairs expected to give
+long segments, or when asked (AH_QUERY_SEGMENTED=0), the radix sort with the
+Tm computed inside its first pass and the pairing's chunk counts inside its
+last."""
 import numpy as np
 import pytest
 
@@ -100,10 +101,16 @@ def test_query_on_the_collection_workload(dev):
     assert sep[0]["status"] == 0 and fus == sep
 
 
-def test_query_segments_longer_than_lds(dev):
+@pytest.mark.parametrize("segmented", ["1", None])
+def test_query_segments_longer_than_lds(dev, monkeypatch, segmented):
     """A short primer at k = 3 on genomes of ~300 kbp: thousands of sites per
-    (pair, genome), past the 2,048 the segment sort keeps in LDS, so those
-    segments are sorted and paired through global memory."""
+    (pair, genome), past the 1,024 the segment sort keeps in LDS, so those
+    segments are sorted and paired through global memory (forced: left to
+    itself, ah_query expects segments this long and takes the radix tail)."""
+    if segmented is None:
+        monkeypatch.delenv("AH_QUERY_SEGMENTED", raising=False)
+    else:
+        monkeypatch.setenv("AH_QUERY_SEGMENTED", segmented)
     pr = plan.PairSpec("ACGTACGTAC", "GGCCAATTGG", k=3, clamp=0, min_len=20, max_len=3000)
     p = plan.tiny(9302, n_genomes=3, len_lo=250000, len_hi=350000, pair=pr)
     sep, fus = _both(p, [pr], dev, hit_cap=1 << 16, amp_cap=1 << 21)
@@ -114,7 +121,8 @@ def test_query_segments_longer_than_lds(dev):
     assert fus == sep
 
 
-def test_query_filters_tm_on_long_segments(dev):
+def test_query_filters_tm_on_long_segments(dev, monkeypatch):
+    monkeypatch.setenv("AH_QUERY_SEGMENTED", "1")
     pr = plan.PairSpec("ACGTRCGTAC", "GGCCAATYGG", k=3, clamp=1, min_len=20, max_len=3000)
     p = plan.tiny(9303, n_genomes=2, len_lo=250000, len_hi=300000, pair=pr)
     sep, fus = _both(p, [pr], dev, hit_cap=1 << 16, amp_cap=1 << 21, filter_tm=True, min_tm=30.0)
