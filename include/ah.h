@@ -259,11 +259,19 @@ typedef struct ah_tm_params {
  * size of d_hits.  Oligos that pair a site at the same positions have the
  * same nearest-neighbour sums, so a site costs one evaluation per set of
  * paired positions: at most sum_{e <= min(k, nd)} C(nd, e) for a primer with
- * nd degenerate positions outside the clamp.  A primer above
- * AH_TM_MAX_PAIRINGS of them, or of degeneracy above 2^20, is refused with
- * AH_ERR_LIMIT before any device work (the paper's web server caps
- * degeneracy at 10,000, Section 2.2, which stays below both).  Errors:
- * AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT, AH_ERR_HIP. */
+ * nd degenerate positions outside the clamp, whatever its degeneracy.  Up to
+ * AH_TM_MAX_PAIRINGS of them are enumerated.  Above that, under salt methods
+ * 0-5 (where Tm rises with Delta-H / (Delta-S + R ln C + salt entropy)), the
+ * best set is found exactly by Dinkelbach's iteration for a maximum ratio,
+ * each step a pass over the positions with the mismatches spent as state: a
+ * few passes of L x (k + 1) x 4 states per site.  It needs R ln C plus the
+ * salt entropy below -8.2 cal/(K mol), so that no set of pairs can make the
+ * denominator non-negative.  Methods 6 and 7 also depend on the oligo's G+C
+ * count and stay at the enumeration bound.  A request outside these limits
+ * is refused with AH_ERR_LIMIT before any device work (the paper's web
+ * server caps degeneracy at 10,000, Section 2.2; its command-line tool has
+ * no cap).  Errors: AH_ERR_INVALID_ARG, AH_ERR_INVALID_PRIMER, AH_ERR_LIMIT,
+ * AH_ERR_HIP. */
 enum { AH_TM_MAX_PAIRINGS = 65536 };
 ah_status ah_tm(const ah_genomes* genomes, const ah_primer_pair* pairs, uint32_t n_pairs,
                 const ah_tm_params* params, ah_hit* d_hits, const ah_result* d_nhits,

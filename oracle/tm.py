@@ -64,12 +64,17 @@ Readings:
   R20 only the maximum is part of the result.
   R27 for the salt methods that depend on G+C content (6, 7), fGC is the
       G+C fraction of the oligo over all its positions, paired or not.
+  R21 every compatible oligo is evaluated, however many there are; for
+      methods 0-5 ``site_tm_by_pairing`` takes the same maximum over the sets
+      of paired positions, which stays feasible where the oligos are too
+      many to list (pinned to ``site_tm`` and to brute force).
 Template base opposite oligo position j: the complement of the top-strand base
 at pos + j for a + site, the top-strand base at pos + L - 1 - j for a - site.
 """
 from __future__ import annotations
 
 import dataclasses
+import itertools
 import math
 
 import numpy as np
@@ -316,3 +321,54 @@ def fill_tm(hits: np.ndarray, seqs, pairs, p: TmParams = TmParams()) -> np.ndarr
         h["tm"][r] = site_tm(cache[g], int(h["pos"][r]), primer, int(h["strand"][r]),
                              pr.k, pr.clamp, p)
     return h
+
+
+def site_tm_by_pairing(genome_codes: np.ndarray, pos: int, primer: str, strand: int, k: int,
+                       clamp: int, p: TmParams = TmParams(), chunk: int = 1 << 16) -> float:
+    """``site_tm`` for salt methods 0-5, taken over sets of paired positions
+    instead of oligos, for primers whose expansion is too large to list.
+
+    Under R9 a stack or an initiation term involves paired positions only,
+    and a paired position carries the base the template fixes there; methods
+    0-5 add nothing that depends on the other positions.  So every compatible
+    oligo that pairs the site at the same set of positions has the same Tm,
+    and the maximum over oligos is the maximum over those sets.  A set is
+    formed by some compatible oligo iff it holds every position whose primer
+    code admits the template's base and has no other member, holds no
+    position whose code excludes it (or faces a non-ACGT base), covers the
+    clamp, and leaves at most k positions unpaired."""
+    _check_method(p)
+    if p.saltcorr in (6, 7):
+        raise ValueError("methods 6 and 7 depend on the oligo's G+C count, not only its pairing")
+    primer = iupac.normalise(primer)
+    L = len(primer)
+    w = np.asarray(genome_codes[pos:pos + L], dtype=np.int64)
+    if strand == 0:
+        need = w  # the oligo base that pairs with the template at each position
+    else:
+        r = w[::-1]
+        need = np.where(r < 4, 3 - r, 9)
+    sets = [["ACGT".index(b) for b in iupac.members(ch)] for ch in primer]
+    can = np.array([need[j] < 4 and int(need[j]) in sets[j] for j in range(L)])
+    c = min(clamp, L)
+    if not can[L - c:].all():
+        return float("nan")
+    budget = k - int((~can).sum())
+    if budget < 0:
+        return float("nan")
+    optional = np.array([j for j in range(L) if can[j] and len(sets[j]) > 1 and j < L - c],
+                        dtype=np.int64)
+    oligo = np.array([int(need[j]) if can[j] else sets[j][0] for j in range(L)], dtype=np.int64)
+    best = -math.inf
+    for e in range(min(budget, optional.size) + 1):
+        # every e-subset of the optional positions, unpaired
+        subsets = list(itertools.combinations(range(optional.size), e))
+        combos = np.array(subsets, dtype=np.int64).reshape(len(subsets), e)
+        for lo in range(0, combos.shape[0], chunk):
+            part = combos[lo:lo + chunk]
+            paired = np.tile(can, (part.shape[0], 1))
+            if e:
+                paired[np.arange(part.shape[0])[:, None], optional[part]] = False
+            dh, ds = duplex_terms(np.broadcast_to(oligo, paired.shape), paired)
+            best = max(best, float(tm_from_terms(dh, ds, L, p).max()))
+    return best

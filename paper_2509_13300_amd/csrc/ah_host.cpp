@@ -1767,9 +1767,36 @@ uint64_t worst_tm_pairings(const Primer& pr, uint32_t k, uint32_t clamp) {
   return sum;
 }
 
+// Constant part of the Tm denominator for a primer of L bases, cal/(K mol):
+// method 5's salt entropy, R ln C and the symmetry term.
+double tm_denominator_const(const ah_tm_params& p, const SaltTerms& salt_t, int L) {
+  const double salt = p.saltcorr == 5 ? 0.368 * (L - 1) * salt_t.ln_na : 0.0;
+  return salt + 1.987 * std::log(strand_conc(p)) + (p.selfcomp ? -1.4 : 0.0);
+}
+
+// The largest Delta-S a set of paired positions can have: two A.T
+// initiations and no stack (every stack's Delta-S is negative).
+constexpr double kMaxPairingDs = 8.2;
+
+// AH_TM_EXACT=1 sends every primer the exact route can take there (salt
+// methods 0-5), not only those above the enumeration bound.
+bool tm_exact_forced() {
+  const char* e = std::getenv("AH_TM_EXACT");
+  return e && e[0] == '1';
+}
+
+// Whether the Tm kernels take a primer's best pairing by the exact ratio
+// iteration rather than by enumerating its pairings.
+bool tm_exact_route(const Primer& pr, uint32_t k, uint32_t clamp, const SaltTerms& salt_t) {
+  if (salt_t.recip) return false;
+  return worst_tm_pairings(pr, k, clamp) > (uint64_t)AH_TM_MAX_PAIRINGS || tm_exact_forced();
+}
+
 // Everything ah_tm checks before any device work: the pairs, the salt
-// method and its ion concentrations, a positive strand concentration, the
-// degeneracy limit and the bound on the pairings per site.
+// method and its ion concentrations, a positive strand concentration, and
+// for a primer above the enumeration bound what the exact route needs: a
+// salt method whose Tm depends on the pairing alone (not 6 or 7) and a
+// denominator that stays negative for every pairing.
 ah_status check_tm_request(const ah_primer_pair* pairs, uint32_t n_pairs, const ah_tm_params* p,
                            PairSet& ps) {
   ah_status s = compile_pairs(pairs, n_pairs, ps);
@@ -1784,28 +1811,31 @@ ah_status check_tm_request(const ah_primer_pair* pairs, uint32_t n_pairs, const 
   for (uint32_t q = 0; q < n_pairs; ++q)
     for (int primer = 0; primer < 2; ++primer) {
       const Primer& pr = primer ? ps.rev[q] : ps.fwd[q];
-      uint64_t deg = 1;
-      for (int j = 0; j < pr.L; ++j) deg *= (uint64_t)set_size(pr.mask[j]);
-      if (deg > (1ull << 20))
-        return fail(AH_ERR_LIMIT, "pair %u: primer degeneracy %llu exceeds 2^20 for Tm", q,
-                    (unsigned long long)deg);
       const uint64_t w = worst_tm_pairings(pr, ps.k[q], ps.clamp[q]);
-      if (w > (uint64_t)AH_TM_MAX_PAIRINGS)
+      if (w <= (uint64_t)AH_TM_MAX_PAIRINGS) continue;
+      if (salt_t.recip)
         return fail(AH_ERR_LIMIT,
-                    "pair %u: up to %llu pairings per site for Tm (at most %d: lower k or the "
-                    "degenerate positions outside the clamp)",
-                    q, (unsigned long long)w, (int)AH_TM_MAX_PAIRINGS);
+                    "pair %u: up to %llu pairings per site for Tm (at most %d under salt method %d, "
+                    "whose Tm also depends on the oligo's G+C count: lower k, or the degenerate "
+                    "positions outside the clamp, or use a method of 0-5)",
+                    q, (unsigned long long)w, (int)AH_TM_MAX_PAIRINGS, p->saltcorr);
+      if (!(tm_denominator_const(*p, salt_t, pr.L) + kMaxPairingDs < 0.0))
+        return fail(AH_ERR_LIMIT,
+                    "pair %u: up to %llu pairings per site for Tm, whose exact route needs "
+                    "R ln C + salt entropy < -%.1f cal/(K mol) (a lower strand concentration)",
+                    q, (unsigned long long)w, kMaxPairingDs);
     }
   return AH_OK;
 }
 
 // The Tm kernel's per-primer tables of a validated request (check_tm_request),
-// uploaded once per content (get_table).
-ah_status tm_table(const PairSet& ps, uint32_t n_pairs, const ah_tm_params& pp, void** dt) {
+// uploaded once per content (get_table); *exact: some primer takes the exact
+// route (the kernels' variant that carries it).
+ah_status tm_table(const PairSet& ps, uint32_t n_pairs, const ah_tm_params& pp, void** dt,
+                   bool* exact) {
   const ah_tm_params* p = &pp;
   const SaltTerms salt_t = salt_terms(*p);
-  const double C = strand_conc(*p);
-  const double R = 1.987;
+  bool any_exact = false;
   std::vector<ah::PrimerTab> tabs(2 * (size_t)n_pairs);
   for (uint32_t q = 0; q < n_pairs; ++q) {
     for (int primer = 0; primer < 2; ++primer) {
@@ -1831,14 +1861,15 @@ ah_status tm_table(const PairSet& ps, uint32_t n_pairs, const ah_tm_params& pp, 
           t.nmem[t.nd] = (uint8_t)cnt;
           t.mem[t.nd] = packed;
           t.nd++;
-          deg *= (uint64_t)cnt;
+          deg = deg > (~0ull >> 2) ? ~0ull : deg * (uint64_t)cnt;  // saturates
         }
       }
       for (uint32_t j = 0; j < ps.clamp[q]; ++j) t.clampm |= 1ull << (2 * (pr.L - 1 - (int)j));
       t.deg = deg;
       t.decoy = (ps.flags[q] & AH_PAIR_DECOY) ? 1u : 0u;
-      const double salt = p->saltcorr == 5 ? 0.368 * (pr.L - 1) * salt_t.ln_na : 0.0;
-      t.KL = salt + R * std::log(C) + (p->selfcomp ? -1.4 : 0.0);
+      t.KL = tm_denominator_const(*p, salt_t, pr.L);
+      t.dp = tm_exact_route(pr, ps.k[q], ps.clamp[q], salt_t) ? 1u : 0u;
+      any_exact |= t.dp != 0u;
       t.tshift = salt_t.shift;
       if (salt_t.recip) {
         t.recip = 1;
@@ -1848,6 +1879,7 @@ ah_status tm_table(const PairSet& ps, uint32_t n_pairs, const ah_tm_params& pp, 
       tabs[2 * q + primer] = t;
     }
   }
+  *exact = any_exact;
   return get_table(tabs.data(), tabs.size() * sizeof(ah::PrimerTab), dt);
 }
 
@@ -2093,11 +2125,12 @@ ah_status ah_tm(const ah_genomes* g, const ah_primer_pair* pairs, uint32_t n_pai
   s = check_tm_request(pairs, n_pairs, p, ps);
   if (s) return s;
   void* dt = nullptr;
-  s = tm_table(ps, n_pairs, *p, &dt);
+  bool exact = false;
+  s = tm_table(ps, n_pairs, *p, &dt, &exact);
   if (s) return s;
   ProfScope prof_tm("tm", (hipStream_t)stream);
   AH_HIP(ah::launch_tm(*g, (const ah::PrimerTab*)dt, n_pairs, d_hits, d_nhits, capacity,
-                       cu_count() * 4, (hipStream_t)stream));
+                       cu_count() * 4, exact, (hipStream_t)stream));
   return AH_OK;
 }
 
@@ -2192,7 +2225,8 @@ ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_wi
     return fail(AH_ERR_WORKSPACE, "pair workspace: %zu bytes given, %zu needed", pair_work_bytes,
                 pneed);
   void* tm_tabs = nullptr;
-  s = tm_table(ps, n_pairs, *tm, &tm_tabs);
+  bool exact = false;
+  s = tm_table(ps, n_pairs, *tm, &tm_tabs, &exact);
   if (s) return s;
   void* pair_tabs = nullptr;
   s = pair_table(ps, windows, n_pairs, &pair_tabs);
@@ -2217,7 +2251,7 @@ ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_wi
     if (s) return s;
     ProfScope prof_sort("sort", st);
     AH_HIP(ah::launch_seg_tail(w.staging, d_hits, sg, d_hit_res, kb.pb + 2, *g, ttab, n_pairs,
-                               ptab, pb, d_amp, amp_capacity, d_amp_res, st));
+                               ptab, pb, d_amp, amp_capacity, d_amp_res, exact, st));
     return AH_OK;
   }
   s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, &kb);
@@ -2227,7 +2261,7 @@ ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_wi
     ProfScope prof_sort("sort", st);
     if (ah::sort_fusable(kb)) {  // Tm and the pairing's first step inside the sort
       AH_HIP(ah::launch_sort_tm_mark(w.staging, d_hits, w.n_sort, kb, w.sb, *g, ttab, n_pairs, ptab,
-                                     pb, cu_count() * 4, st));
+                                     pb, cu_count() * 4, exact, st));
       marked = true;
     } else {
       AH_HIP(ah::launch_sort_hits(w.staging, d_hits, w.n_sort, kb, w.sb, st));
@@ -2235,7 +2269,8 @@ ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_wi
   }
   if (!marked) {
     ProfScope prof_tm("tm", st);
-    AH_HIP(ah::launch_tm(*g, ttab, n_pairs, d_hits, d_hit_res, hit_capacity, cu_count() * 4, st));
+    AH_HIP(ah::launch_tm(*g, ttab, n_pairs, d_hits, d_hit_res, hit_capacity, cu_count() * 4, exact,
+                         st));
   }
   ProfScope prof_pair("pair", st);
   AH_HIP(ah::launch_pair(d_hits, d_hit_res, hit_capacity, ptab, d_amp, amp_capacity, d_amp_res, pb,

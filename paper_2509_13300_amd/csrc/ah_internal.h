@@ -33,6 +33,7 @@ struct PrimerTab {
   uint32_t recip;     // 1: apply rA, rB
   uint32_t L, k, nd;
   uint32_t decoy;     // 1: the site is the primer against the reversed genome
+  uint32_t dp;        // 1: exact best pairing (ratio iteration), not enumeration
   uint8_t dpos[32];   // degenerate positions, 5'->3'
   uint8_t nmem[32];   // number of members of each degenerate position
   uint8_t mem[32];    // members, 2 bits each, in A<C<G<T order
@@ -90,8 +91,9 @@ inline int sort_digit_bits(const KeyBits& kb) {
 // hist[0]; its verify pass has cleared hist[0] and hist[1].
 hipError_t launch_sort_hits(const ah_hit* staged, ah_hit* out, const uint64_t* n_dev,
                             KeyBits kb, const SortBuffers& sb, hipStream_t st);
+// exact: some primer table has dp set (the kernels' exact-route variant).
 hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pairs, ah_hit* hits,
-                     const ah_result* nhits, uint64_t cap, int grid, hipStream_t st);
+                     const ah_result* nhits, uint64_t cap, int grid, bool exact, hipStream_t st);
 struct PairBuffers {
   uint64_t* cf;         // [kPairGrid] kept fwd-primer minus sites per chunk
   uint64_t* cr;         // [kPairGrid] rev-primer
@@ -124,7 +126,7 @@ bool sort_fusable(const KeyBits& kb);
 hipError_t launch_sort_tm_mark(ah_hit* staged, ah_hit* out, const uint64_t* n_dev, KeyBits kb,
                                const SortBuffers& sb, const ah_genomes& g, const PrimerTab* tm_tabs,
                                uint32_t n_pairs, const PairTab* pair_tabs,
-                               const PairBuffers& pb, int tm_blocks, hipStream_t st);
+                               const PairBuffers& pb, int tm_blocks, bool exact, hipStream_t st);
 
 // The tail of ah_query over at most kSegMax segments (pair, genome), after
 // the scan's segmented emit has put each segment's sites at
@@ -149,7 +151,7 @@ hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
                            const ah_result* hres, int key_bits, const ah_genomes& g,
                            const PrimerTab* tm_tabs, uint32_t n_pairs, const PairTab* pair_tabs,
                            const PairBuffers& pb, ah_amplicon* amp, uint64_t acap,
-                           ah_result* ares, hipStream_t st);
+                           ah_result* ares, bool exact, hipStream_t st);
 
 // Amplicon FASTA records, sequence hashes and amplitypes (see ah.h); rec_len
 // [acap], rec_at [acap] and cc [kPairGrid] are workspace; `waves` writers.

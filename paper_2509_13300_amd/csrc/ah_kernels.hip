@@ -416,11 +416,138 @@ struct TmJob {
   u32 n_genomes, n_pairs;
 };
 
+// ---- exact route for primers with too many pairings to enumerate ----------
+// Under salt methods 0-5 the Tm of a pairing (a set of paired positions)
+// rises with the ratio N / D of N = -Delta-H and D = -(Delta-S + KL), and D
+// is positive for every pairing (the host checks KL against the largest
+// Delta-S a pairing can have: two A.T initiations and no stack).  The best
+// pairing then follows from Dinkelbach's iteration for a maximum ratio: with
+// lambda the best ratio found so far, one max-sum pass over the positions
+// finds the pairing that maximises N - lambda D, and it becomes the best
+// while its ratio is higher.  The ratio rises at every step over a finite
+// set, and a pass that finds nothing higher proves lambda the maximum.
+//
+// The pass runs over the primer's positions 5'->3' with a state per number
+// e of in-set positions turned into mismatches so far (e <= budget), times
+// four: S0 nothing paired yet; S1 this position paired, more pairs may
+// follow; S2 a gap after a pair; S3 the last pair placed (its right
+// initiation counted), nothing pairs after it.  A stack counts when a pair
+// follows S1; the left initiation when a pair leaves S0.  Only positions of
+// eq0 (the representative's pairs) can pair, and those outside afree (clamp
+// or non-degenerate) must.  A term (h, s) weighs -h + lambda s; the constant
+// lambda KL is left out.  Each state keeps its pairing as a position mask.
+constexpr int kDpE = AH_MAX_K + 1;
+
+// Delta-H / (Delta-S + KL) of pairing eq (bit 2j: position j paired) of
+// oligo o, in double precision; equal to N / D above.
+__device__ double pairing_ratio(u64 eq, u64 o, double KL, const float* s_dh, const float* s_ds) {
+  double h = 0.0, s = 0.0;
+  for (u64 st = eq & (eq >> 2); st; st &= st - 1) {
+    const u32 j2 = (u32)__ffsll((long long)st) - 1u;
+    const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
+    h += (double)s_dh[ix];
+    s += (double)s_ds[ix];
+  }
+  if (eq) {
+    const u32 ends[2] = {(u32)__ffsll((long long)eq) - 1u, 63u - (u32)__clzll((long long)eq)};
+    for (u32 i = 0; i < 2; ++i) {
+      const u32 b = (u32)(o >> ends[i]) & 3u;
+      const bool gc = b == 1u || b == 2u;
+      h += (double)(gc ? kInitGcH : kInitAtH);
+      s += (double)(gc ? kInitGcS : kInitAtS);
+    }
+  }
+  return h / (s + KL);
+}
+
+// The pairing of highest Tm among eq0 with at most `budget` positions of
+// afree unpaired (bit 2j: position j paired); o: the representative oligo.
+// Not inlined: the enumeration route's kernels keep their own registers.
+__device__ __noinline__ u64 tm_dp_pairing(u64 o, u64 eq0, u64 afree, u32 budget, u32 L, double KL,
+                                          const float* s_dh, const float* s_ds) {
+  const double kNeg = -__builtin_inf();
+  double v[4][kDpE];
+  u32 m[4][kDpE];
+  u64 best = eq0;
+  double rbest = pairing_ratio(eq0, o, KL, s_dh, s_ds);
+  budget = min(budget, (u32)(kDpE - 1));
+  for (int it = 0; it < 64; ++it) {
+    const double lam = rbest;
+    for (u32 e = 0; e <= budget; ++e)
+      for (u32 q = 0; q < 4; ++q) {
+        v[q][e] = kNeg;
+        m[q][e] = 0u;
+      }
+    v[0][0] = 0.0;
+    for (u32 j = 0; j < L; ++j) {
+      const u32 j2 = 2u * j;
+      const bool can_pair = ((eq0 >> j2) & 1u) != 0u;
+      const bool is_free = ((afree >> j2) & 1u) != 0u;
+      const u32 b = (u32)(o >> j2) & 3u;
+      const bool gc = b == 1u || b == 2u;
+      const double wi = -(double)(gc ? kInitGcH : kInitAtH) + lam * (double)(gc ? kInitGcS : kInitAtS);
+      double ws = kNeg;
+      if (j > 0u && can_pair && ((eq0 >> (j2 - 2u)) & 1u) != 0u) {
+        const u32 ix = (((u32)(o >> (j2 - 2u)) & 3u) << 2) | b;
+        ws = -(double)s_dh[ix] + lam * (double)s_ds[ix];
+      }
+      const u32 bit = 1u << j;
+      // descending e: an unpaired free position reads e - 1 before it is
+      // rewritten, every other transition reads e itself
+      for (int e = (int)budget; e >= 0; --e) {
+        double n[4] = {kNeg, kNeg, kNeg, kNeg};
+        u32 q[4] = {0u, 0u, 0u, 0u};
+        if (can_pair) {
+          double p = v[0][e] + wi;
+          u32 pm = m[0][e];
+          if (v[1][e] + ws > p) { p = v[1][e] + ws; pm = m[1][e]; }
+          if (v[2][e] > p) { p = v[2][e]; pm = m[2][e]; }
+          n[1] = p;
+          q[1] = pm | bit;
+          n[3] = p + wi;
+          q[3] = pm | bit;
+        }
+        if (!can_pair || is_free) {
+          const int eu = can_pair ? e - 1 : e;
+          if (eu >= 0) {
+            n[0] = v[0][eu];
+            q[0] = m[0][eu];
+            n[2] = v[1][eu];
+            q[2] = m[1][eu];
+            if (v[2][eu] > n[2]) { n[2] = v[2][eu]; q[2] = m[2][eu]; }
+            if (v[3][eu] > n[3]) { n[3] = v[3][eu]; q[3] = m[3][eu]; }
+          }
+        }
+        for (u32 s = 0; s < 4; ++s) {
+          v[s][e] = n[s];
+          m[s][e] = q[s];
+        }
+      }
+    }
+    double fb = kNeg;
+    u32 fm = 0u;
+    for (u32 e = 0; e <= budget; ++e) {
+      if (v[0][e] > fb) { fb = v[0][e]; fm = 0u; }
+      if (v[3][e] > fb) { fb = v[3][e]; fm = m[3][e]; }
+    }
+    u64 eq = 0;
+    for (u32 j = 0; j < L; ++j) eq |= (u64)((fm >> j) & 1u) << (2u * j);
+    const double r = pairing_ratio(eq, o, KL, s_dh, s_ds);
+    if (!(r > rbest)) break;
+    rbest = r;
+    best = eq;
+  }
+  return best;
+}
+
 // The Tm of site record h (a genome and pair of this call); s_dh / s_ds:
 // the stack tables in LDS.
 // S: the segment words of the site's genome, wbase: its first word; T2: the
 // two primer tables (fwd, rev) of the site's pair (global memory, or a copy
-// in LDS).
+// in LDS).  kExact: instantiated with the exact route (tm_dp_pairing) for
+// calls whose primers need it; the enumeration-only instantiation carries
+// none of its private memory.
+template <bool kExact>
 __device__ __forceinline__ float tm_value_at(const TmJob& J, const ah_hit& h, u64 S, u64 wbase,
                                              const float* s_dh, const float* s_ds,
                                              const PrimerTab* T2) {
@@ -556,7 +683,10 @@ __device__ __forceinline__ float tm_value_at(const TmJob& J, const ah_hit& h, u6
       consider(eq0);
       const u32 nfree = (u32)__popcll(afree);
       const u32 budget = min(k - mism0, nfree);
-      for (u32 e = 1; e <= budget; ++e) {
+      const bool exact = kExact && T->dp != 0u;
+      if (exact && budget)  // too many pairings to enumerate: the exact route
+        consider(tm_dp_pairing(o, eq0, afree, budget, L, KL, s_dh, s_ds));
+      for (u32 e = 1; e <= (exact ? 0u : budget); ++e) {
         // every e-subset of the free positions (Gosper's next combination
         // over nfree bits, deposited onto the position mask)
         u64 comb = (1ull << e) - 1ull;
@@ -579,19 +709,21 @@ __device__ __forceinline__ float tm_value_at(const TmJob& J, const ah_hit& h, u6
   }
 }
 
+template <bool kExact>
 __device__ __forceinline__ float tm_value(const TmJob& J, const ah_hit& h, const float* s_dh,
                                           const float* s_ds) {
-  return tm_value_at(J, h, ((u64)J.len[h.genome] + 31) >> 5, J.word_off[h.genome], s_dh, s_ds,
+  return tm_value_at<kExact>(J, h, ((u64)J.len[h.genome] + 31) >> 5, J.word_off[h.genome], s_dh, s_ds,
                      &J.tabs[(u32)h.pair * 2u]);
 }
 
 // Sets hits[i].tm.  A record that does not name a genome and pair of this
 // call (never written by a scan of it) is left alone rather than followed.
+template <bool kExact>
 __device__ __forceinline__ void tm_one(const TmJob& J, ah_hit* __restrict__ hits, u64 i,
                                        const float* s_dh, const float* s_ds) {
   ah_hit h = hits[i];
   if (h.genome >= J.n_genomes || h.pair >= J.n_pairs) return;
-  h.tm = tm_value(J, h, s_dh, s_ds);
+  h.tm = tm_value<kExact>(J, h, s_dh, s_ds);
   hits[i] = h;
 }
 
@@ -604,6 +736,7 @@ __device__ __forceinline__ void tm_tables(float* s_dh, float* s_ds) {
   __syncthreads();
 }
 
+template <bool kExact>
 __global__ __launch_bounds__(kBlock) void k_tm(TmJob J, ah_hit* __restrict__ hits,
                                                const ah_result* __restrict__ nhits, u64 cap) {
   // the stack tables in LDS: lanes index them divergently, once per stack
@@ -611,7 +744,7 @@ __global__ __launch_bounds__(kBlock) void k_tm(TmJob J, ah_hit* __restrict__ hit
   tm_tables(s_dh, s_ds);
   const u64 cnt = nhits->count;
   const u64 n = cnt < cap ? cnt : cap;
-  for (u64 i = global_tid(); i < n; i += grid_threads()) tm_one(J, hits, i, s_dh, s_ds);
+  for (u64 i = global_tid(); i < n; i += grid_threads()) tm_one<kExact>(J, hits, i, s_dh, s_ds);
 }
 
 // ----------------------------------------------------------- pairing ----
@@ -1229,6 +1362,7 @@ __device__ __forceinline__ void seg_result(const SegArgs& A, u64 total) {
 }
 
 // Segment blockIdx.x: canonical order, Tm, leaders, amplicons.
+template <bool kExact>
 __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   __shared__ u64 keys[kSegLds];  // also the long path's digit counters
   __shared__ u32 spos[kSegLds];
@@ -1289,7 +1423,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
     if (t < m) {
       ah_hit r;
       __builtin_memcpy(&r, hv, sizeof r);
-      r.tm = tm_value_at(A.tj, r, S, wbase, s_dh, s_ds, s_tab);
+      r.tm = tm_value_at<kExact>(A.tj, r, S, wbase, s_dh, s_ds, s_tab);
       o[t] = r;
       spos[t] = r.pos;
       kind[t] = (unsigned char)seg_kind(r, pt);
@@ -1369,7 +1503,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   if (!tiny)
     for (u32 i = t; i < m; i += kSegBlock) {
       ah_hit h = small ? A.staged[base + (u32)(keys[i] & (kSegLds - 1u))] : o[i];
-      h.tm = tm_value_at(A.tj, h, S, wbase, s_dh, s_ds, s_tab);
+      h.tm = tm_value_at<kExact>(A.tj, h, S, wbase, s_dh, s_ds, s_tab);
       o[i] = h;
       if (small) {
         spos[i] = h.pos;
@@ -1723,7 +1857,7 @@ __global__ __launch_bounds__(kBlock) void k_remap(ah_hit* __restrict__ hits,
 // compute the Tm of every staged record (the order is irrelevant to it, and
 // the last pass copies the records, Tm included, into place) and clear the
 // pairing's per-chunk counts.
-template <int D>
+template <int D, bool kExact>
 __global__ __launch_bounds__(kBlock) void k_sort_scatter_tm(
     const u64* __restrict__ kin, const u32* __restrict__ iin, u64* __restrict__ kout,
     u32* __restrict__ iout, const u64* __restrict__ n_dev, int shift, const u32* __restrict__ hist,
@@ -1743,7 +1877,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter_tm(
     cf[c] = 0;
     cr[c] = 0;
   }
-  for (u64 i = t; i < n; i += stride) tm_one(J, staged, i, s_dh, s_ds);
+  for (u64 i = t; i < n; i += stride) tm_one<kExact>(J, staged, i, s_dh, s_ds);
 }
 
 // Last pass: as a record reaches its place, the kept minus sites of the fwd
@@ -1784,7 +1918,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter_mark(
   }
 }
 
-template <int D>
+template <int D, bool kExact>
 void sort_passes_fused(ah_hit* staged, ah_hit* out, const u64* n_dev, KeyBits kb,
                        const SortBuffers& sb, const TmJob& J, const PairTab* ptabs, u64* cf,
                        u64* cr, int tm_blocks, hipStream_t st) {
@@ -1796,7 +1930,7 @@ void sort_passes_fused(ah_hit* staged, ah_hit* out, const u64* n_dev, KeyBits kb
     u32* next = last ? nullptr : sb.hist[(p + 1) % 3];
     u32* clear = p + 2 < passes ? sb.hist[(p + 2) % 3] : nullptr;
     if (p == 0) {
-      k_sort_scatter_tm<D><<<kSortGrid + tm_blocks, kBlock, 0, st>>>(
+      k_sort_scatter_tm<D, kExact><<<kSortGrid + tm_blocks, kBlock, 0, st>>>(
           (const u64*)sb.keys[cur], sb.idx[cur], (u64*)sb.keys[cur ^ 1], sb.idx[cur ^ 1], n_dev, 0,
           sb.hist[0], next, clear, sb.hstride, J, staged, cf, cr);
     } else if (last) {
@@ -1925,14 +2059,19 @@ bool sort_fusable(const KeyBits& kb) {
 hipError_t launch_sort_tm_mark(ah_hit* staged, ah_hit* out, const uint64_t* n_dev, KeyBits kb,
                                const SortBuffers& sb, const ah_genomes& g, const PrimerTab* tm_tabs,
                                uint32_t n_pairs, const PairTab* pair_tabs, const PairBuffers& pb,
-                               int tm_blocks, hipStream_t st) {
+                               int tm_blocks, bool exact, hipStream_t st) {
   const TmJob J{(const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, tm_tabs, g.n, n_pairs};
+  auto run = [&](auto d, auto x) {
+    sort_passes_fused<decltype(d)::value, decltype(x)::value>(
+        staged, out, (const u64*)n_dev, kb, sb, J, pair_tabs, (u64*)pb.cf, (u64*)pb.cr, tm_blocks,
+        st);
+  };
+  using I8 = std::integral_constant<int, 8>;
+  using I9 = std::integral_constant<int, 9>;
   if (sort_digit_bits(kb) == 9)
-    sort_passes_fused<9>(staged, out, (const u64*)n_dev, kb, sb, J, pair_tabs, (u64*)pb.cf,
-                         (u64*)pb.cr, tm_blocks, st);
+    exact ? run(I9{}, std::true_type{}) : run(I9{}, std::false_type{});
   else
-    sort_passes_fused<8>(staged, out, (const u64*)n_dev, kb, sb, J, pair_tabs, (u64*)pb.cf,
-                         (u64*)pb.cr, tm_blocks, st);
+    exact ? run(I8{}, std::true_type{}) : run(I8{}, std::false_type{});
   return hipGetLastError();
 }
 
@@ -1940,7 +2079,7 @@ hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
                            const ah_result* hres, int key_bits, const ah_genomes& g,
                            const PrimerTab* tm_tabs, uint32_t n_pairs, const PairTab* pair_tabs,
                            const PairBuffers& pb, ah_amplicon* amp, uint64_t acap,
-                           ah_result* ares, hipStream_t st) {
+                           ah_result* ares, bool exact, hipStream_t st) {
   SegArgs A;
   A.staged = staged;
   A.out = out;
@@ -1960,14 +2099,21 @@ hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
   A.amp = amp;
   A.acap = acap;
   A.ares = ares;
-  k_seg_tail<<<sg.n_seg > 0 ? sg.n_seg : 1u, kSegBlock, 0, st>>>(A);
+  const u32 grid = sg.n_seg > 0 ? sg.n_seg : 1u;
+  if (exact)
+    k_seg_tail<true><<<grid, kSegBlock, 0, st>>>(A);
+  else
+    k_seg_tail<false><<<grid, kSegBlock, 0, st>>>(A);
   return hipGetLastError();
 }
 
 hipError_t launch_tm(const ah_genomes& g, const PrimerTab* tabs, uint32_t n_pairs, ah_hit* hits,
-                     const ah_result* nhits, uint64_t cap, int grid, hipStream_t st) {
+                     const ah_result* nhits, uint64_t cap, int grid, bool exact, hipStream_t st) {
   const TmJob J{(const uint2*)g.words, g.nmask, (const u64*)g.word_off, g.len, tabs, g.n, n_pairs};
-  k_tm<<<grid, kBlock, 0, st>>>(J, hits, nhits, cap);
+  if (exact)
+    k_tm<true><<<grid, kBlock, 0, st>>>(J, hits, nhits, cap);
+  else
+    k_tm<false><<<grid, kBlock, 0, st>>>(J, hits, nhits, cap);
   return hipGetLastError();
 }
 

@@ -1,0 +1,205 @@
+"""GPU parity of the exact Tm route, which finds a site's best set of paired
+positions by a ratio iteration instead of enumerating the sets (salt methods
+0-5).  Forced at ordinary sizes, it must agree with the enumeration and the
+oligo-level oracle.  Above the enumeration bound it must agree with the
+oracle's maximum over sets of paired positions."""
+import numpy as np
+import pytest
+
+from gpu_util import amp_tuples, hit_tuples_gpu, hit_tuples_oracle, run_gpu, run_oracle, say
+from oracle import iupac
+from oracle import pair as opair
+from oracle import scan as oscan
+from oracle import tm as otm
+from synth import plan
+
+pytestmark = pytest.mark.gpu
+
+TM_TOL = 0.01
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch.device("cuda:0")
+
+
+def _oracle_params(tp):
+    return otm.TmParams(dnac1=tp.dnac1_nM, dnac2=tp.dnac2_nM, Na=tp.Na_mM, K=tp.K_mM,
+                        Tris=tp.Tris_mM, Mg=tp.Mg_mM, dNTPs=tp.dNTPs_mM, saltcorr=tp.saltcorr,
+                        selfcomp=bool(tp.selfcomp))
+
+
+CONDITIONS = [dict(), dict(Na=100.0, Mg=0.0, dnac1=500.0, dnac2=100.0), dict(saltcorr=0),
+              dict(K=20.0, Tris=10.0, dNTPs=0.8, selfcomp=True)] + [
+    dict(saltcorr=m) for m in (1, 2, 3, 4)]
+
+CASES = [
+    (plan.PairSpec("AGRRTTYGATYHTDGYTYAG", "YCNTTCCYTYDYRGTACT", k=3, clamp=0, min_len=100,
+                   max_len=3000),
+     dict(seed=99, n_genomes=3, len_lo=20000, len_hi=60000, n_copies=(2, 4), span=2455), False),
+    (plan.PairSpec("ACGRYSWKMBDHVNAC", "GTSWRYNHCAGKMT", k=4, clamp=2, min_len=40, max_len=400),
+     dict(seed=123, n_genomes=3, len_lo=3000, len_hi=8000, n_copies=(1, 2)), False),
+    # G+C-rich primers with two-fold A/T codes inside A/T pockets: the weak
+    # stacks around them lower the duplex's ratio, so at every site the best
+    # pairing leaves some of them unpaired (elsewhere it is the representative)
+    (plan.PairSpec("GCGGCCGCTWTGCGGCCGCGATWAGGCGCC", "GGCGCCGCAWTGCCGGCGCTAWAGCGGCCG", k=3,
+                   clamp=0, min_len=60, max_len=1500),
+     dict(seed=321, n_genomes=4, len_lo=5000, len_hi=20000, n_copies=(2, 4)), True),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_forced_exact_route_equals_the_enumeration_and_the_oracle(dev, monkeypatch, case):
+    from paper_2509_13300_amd import _lib as L
+    from paper_2509_13300_amd import path
+
+    pr, pk, want_nontrivial = CASES[case]
+    pk = dict(pk)
+    p = plan.tiny(pk.pop("seed"), pair=pr, **pk)
+    nontrivial = 0
+    for kw in CONDITIONS:
+        tp = L.tm_params(**kw)
+        monkeypatch.delenv("AH_TM_EXACT", raising=False)
+        _, buf = run_gpu(p, [pr], dev, tm=tp)
+        enum = path.hits_numpy(buf)
+        monkeypatch.setenv("AH_TM_EXACT", "1")
+        _, buf = run_gpu(p, [pr], dev, tm=tp)
+        exact = path.hits_numpy(buf)
+        monkeypatch.delenv("AH_TM_EXACT", raising=False)
+        oh, _ = run_oracle(p, [pr], tmp=_oracle_params(tp))
+        assert hit_tuples_gpu(exact) == hit_tuples_oracle(oh) == hit_tuples_gpu(enum)
+        assert exact.size > 0 and np.all(np.isfinite(exact["tm"]))
+        d_enum = np.abs(exact["tm"].astype(np.float64) - enum["tm"])
+        err = np.abs(exact["tm"].astype(np.float64) - oh["tm"])
+        # sites whose best pairing leaves in-set positions unpaired: above the
+        # Tm of the oligos that pair wherever they can (k cut to the site's mm)
+        seqs = {}
+        for r in oh:
+            g = int(r["genome"])
+            if g not in seqs:
+                from synth import fill
+
+                seqs[g] = oscan.codes(fill.genome_bytes(p, g))
+            prim = pr.fwd if r["primer"] == 0 else pr.rev
+            rep = otm.site_tm(seqs[g], int(r["pos"]), prim, int(r["strand"]), int(r["mm"]),
+                              pr.clamp, _oracle_params(tp))
+            nontrivial += bool(r["tm"] > rep + 1e-6)
+        say("exact", kw, "hits", exact.size, "max |exact - enum|", float(d_enum.max()),
+            "bit-equal", int((d_enum == 0).sum()), "max err", float(err.max()))
+        assert float(d_enum.max()) <= 1e-4
+        assert float(err.max()) <= TM_TOL
+    say("sites whose best pairing is not the representative:", nontrivial)
+    assert nontrivial > 0 or not want_nontrivial
+
+
+def _host_collection(seqs, dev):
+    import torch
+
+    from paper_2509_13300_amd import path
+
+    lens = np.array([len(s) for s in seqs], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    buf = np.frombuffer(b"".join(s.encode() for s in seqs), dtype=np.uint8)
+    ascii = torch.from_numpy(buf.copy()).to(dev)
+    coll, _ = path.pack(ascii, torch.from_numpy(off).to(dev), lens, with_nmask=True)
+    return coll
+
+
+def _member(rs, prim):
+    """A random oligo of primer prim (uniform member per position)."""
+    return "".join(rs.choice(list(iupac.members(c))) for c in prim)
+
+
+def _mutate(rs, prim, o, m):
+    """Oligo o of primer prim with m positions moved outside their sets."""
+    o = list(o)
+    for j in rs.choice(len(o), size=m, replace=False):
+        out = [b for b in "ACGT" if not (iupac.mask(prim[j]) >> "ACGT".index(b)) & 1]
+        o[j] = rs.choice(out) if out else "N"
+    return "".join(o)
+
+
+# 20 two-fold codes in 32: sum_{e <= 7} C(20, e) = 137,980 pairings per site
+# and sum_{e <= 9} = 431,910, above the 65,536 the enumeration takes; 18 in
+# 30 at k = 7: 63,004, enumerated (one pair, two routes)
+ABOVE = [
+    ("SRTRGGGWMCRKRGKYTCAMGSYSMKYWCAYW", "GYSGMRKMYGCRGTKCSSWWRYGAGKGWGM", 7, 0, dict()),
+    ("SRTRGGGWMCRKRGKYTCAMGSYSMKYWCAYW", "GYSGMRKMYGCRGTKCSSWWRYGAGKGWGM", 9, 2,
+     dict(saltcorr=0)),
+    ("SRTRGGGWMCRKRGKYTCAMGSYSMKYWCAYW", "GYSGMRKMYGCRGTKCSSWWRYGAGKGWGM", 7, 0,
+     dict(saltcorr=3, Na=120.0, Mg=0.0)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(ABOVE)))
+def test_exact_route_above_the_enumeration_bound(dev, case):
+    """Primers with more pairings per site than the enumeration takes, on
+    planted sites with 0..k mismatches (some facing an N) and amplicons,
+    against the oracle's maximum over sets of paired positions."""
+    from paper_2509_13300_amd import _lib as L
+    from paper_2509_13300_amd import path
+
+    fwd, rev, k, clamp, kw = ABOVE[case]
+    assert sum(c not in "ACGT" for c in fwd) == 20 and sum(c not in "ACGT" for c in rev) == 18
+    pr = plan.PairSpec(fwd, rev, k=k, clamp=clamp, min_len=40, max_len=2000)
+    tp = L.tm_params(**kw)
+    assert L.ah_validate_tm([(fwd, rev, k, clamp)], tp) == L.AH_OK
+    rs = np.random.RandomState(4000 + case)
+    seqs = []
+    for g in range(2):
+        n = 60000
+        s = list(rs.choice(list("ACGT"), size=n))
+        for q in range(24):
+            m = [0, 0, 1, k // 2, k][q % 5] if q % 7 else 1
+            f = _mutate(rs, fwd, _member(rs, fwd), m)
+            r = _mutate(rs, rev, _member(rs, rev), q % (k + 1))
+            site = f + "".join(rs.choice(list("ACGT"), size=300)) + iupac.revcomp_plain(r)
+            if q % 11 == 3:
+                site = site[:5] + "N" + site[6:]
+            at = q * (n // 24) + int(rs.randint(0, n // 24 - len(site)))
+            s[at:at + len(site)] = list(site)
+        seqs.append("".join(s))
+    coll = _host_collection(seqs, dev)
+    buf = path.alloc(coll, [pr], 1 << 16, 1 << 16, dev)
+    path.run(coll, [pr], buf, tm=tp)
+    import torch
+
+    torch.cuda.synchronize()
+    assert path.result(buf.hit_res)["status"] == 0
+    gh = path.hits_numpy(buf)
+    ga = path.amps_numpy(buf)
+    op = _oracle_params(tp)
+    hs = []
+    cache = {}
+    nontrivial = 0
+    for g, s in enumerate(seqs):
+        h = oscan.scan_sequence(s, fwd, rev, k, clamp)
+        h["genome"] = g
+        c = oscan.codes(s)
+        for i in range(h.size):
+            pos, strand, primer = int(h["pos"][i]), int(h["strand"][i]), int(h["primer"][i])
+            prim = fwd if primer == 0 else rev
+            key = (s[pos:pos + len(prim)], strand, primer)
+            if key not in cache:
+                # the maximum, and the Tm of the oligos that pair wherever
+                # they can (k cut to the site's own mismatches)
+                cache[key] = (otm.site_tm_by_pairing(c, pos, prim, strand, k, clamp, op),
+                              otm.site_tm_by_pairing(c, pos, prim, strand, int(h["mm"][i]),
+                                                     clamp, op))
+            h["tm"][i] = cache[key][0]
+            nontrivial += bool(cache[key][0] > cache[key][1] + 1e-6)
+        hs.append(h)
+    oh = oscan.sort_hits(np.concatenate(hs))
+    oa = opair.call_amplicons(oh, [pr], False, 50.0)
+    assert hit_tuples_gpu(gh) == hit_tuples_oracle(oh)
+    assert gh.size >= 80
+    err = np.abs(gh["tm"].astype(np.float64) - oh["tm"])
+    say("above bound", case, "hits", gh.size, "distinct sites", len(cache), "max err",
+        float(err.max()), "mean err", float(err.mean()), "best pairing not the representative",
+        nontrivial)
+    assert nontrivial >= 10
+    assert np.all(np.isfinite(gh["tm"])) and float(err.max()) <= TM_TOL
+    assert amp_tuples(ga) == amp_tuples(oa) and ga.size >= 20

@@ -299,17 +299,30 @@ def test_tm_pairing_bound_counts_the_distinct_pairings(primer, k, clamp):
     assert _distinct_pairings_brute_force(primer, k, clamp) == formula
 
 
-def test_tm_requests_above_the_pairing_bound_are_refused():
+def test_tm_requests_above_the_pairing_bound_take_the_exact_route_or_are_refused():
     tp = L.tm_params()
     fwd20 = "RYKMSWRYKMSWRYKMSWRY"  # 20 two-fold codes: degeneracy 2^20
     rev = "ACGTACGTACGTACGTACGT"
-    # sum_{e <= 6} C(20, e) = 60,460 pairings: accepted; e <= 7: 137,980
+    # sum_{e <= 6} C(20, e) = 60,460 pairings: enumerated; e <= 7: 137,980,
+    # above the bound: the exact route under methods 0-5
     assert L.ah_validate_tm([(fwd20, rev, 6, 0)], tp) == L.AH_OK
-    assert L.ah_validate_tm([(fwd20, rev, 7, 0)], tp) == L.AH_ERR_LIMIT
-    assert "pairings" in L.ah_last_error()
+    for m in (0, 1, 2, 3, 4, 5):
+        assert L.ah_validate_tm([(fwd20, rev, 7, 0)], L.tm_params(saltcorr=m)) == L.AH_OK
+    # methods 6 and 7 depend on the G+C count as well: refused above the bound
+    for m in (6, 7):
+        assert L.ah_validate_tm([(fwd20, rev, 6, 0)], L.tm_params(saltcorr=m)) == L.AH_OK
+        assert L.ah_validate_tm([(fwd20, rev, 7, 0)], L.tm_params(saltcorr=m)) == L.AH_ERR_LIMIT
+        assert "pairings" in L.ah_last_error() and "G+C" in L.ah_last_error()
     # a clamp over degenerate positions removes them from the count
-    assert L.ah_validate_tm([(fwd20, rev, 7, 4)], tp) == L.AH_OK
-    # degeneracy above 2^20 is refused whatever k is
-    assert L.ah_validate_tm([("N" * 11, rev, 0, 0)], tp) == L.AH_ERR_LIMIT
+    assert L.ah_validate_tm([(fwd20, rev, 7, 4)], L.tm_params(saltcorr=6)) == L.AH_OK
+    # the exact route needs every pairing's denominator negative: R ln C
+    # + salt entropy below -8.2 (two A.T initiations); C = 0.1 M is above
+    hot = L.tm_params(saltcorr=0, dnac1=1e8)
+    assert L.ah_validate_tm([(fwd20, rev, 6, 0)], hot) == L.AH_OK
+    assert L.ah_validate_tm([(fwd20, rev, 7, 0)], hot) == L.AH_ERR_LIMIT
+    assert "exact route" in L.ah_last_error()
+    # degeneracy alone is no limit: 4^11 oligos, one pairing per site at k = 0
+    assert L.ah_validate_tm([("N" * 11, rev, 0, 0)], tp) == L.AH_OK
+    assert L.ah_validate_tm([("N" * 32, rev, 15, 0)], tp) == L.AH_OK
     assert L.ah_validate_tm([("ACGTACGTAC", rev, 2, 0)], L.tm_params(saltcorr=9)) == \
         L.AH_ERR_INVALID_ARG

@@ -270,3 +270,64 @@ def test_salt_method_arguments_are_checked():
         tm.tm_perfect("ACGTACGT", tm.TmParams(Na=0.0, Mg=0.0, saltcorr=6))
     with pytest.raises(ValueError):
         tm.tm_perfect("ACGTACGT", tm.TmParams(Na=0.0, Mg=0.0, saltcorr=7))
+
+
+# salt methods whose Tm depends on the pairing alone (all but 6 and 7)
+PAIRING_CASES = [c for c in SALT_CASES if c.get("saltcorr", 5) not in (6, 7)]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_site_tm_by_pairing_equals_the_oligo_maximum(seed):
+    """The maximum over sets of paired positions equals the maximum over the
+    oligos themselves (site_tm, pinned on brute force above) at every
+    position and strand of a genome with planted sites and non-ACGT bases,
+    for primers with many degenerate positions, k up to 6 and a clamp."""
+    rs = np.random.RandomState(700 + seed)
+    L = rs.randint(8, 15)
+    primer = list(rs.choice(list("ACGT"), size=L))
+    for j in rs.choice(L, size=rs.randint(3, 7), replace=False):
+        primer[j] = rs.choice(list("RYSWKMBDHVN"))
+    primer = "".join(primer)
+    k = int(rs.randint(0, 7))
+    clamp = int(rs.randint(0, 3))
+    g = list("".join(rs.choice(list("ACGT"), size=300)))
+    o = iupac.expand(primer)[rs.randint(iupac.degeneracy(primer))]
+    g[40:40 + L] = o
+    g[150:150 + L] = iupac.revcomp_plain(o)
+    g[230:230 + L] = iupac.revcomp_plain(o)
+    g[230 + rs.randint(L)] = "N"
+    g = "".join(g)
+    c = scan.codes(g)
+    p = tm.TmParams(**PAIRING_CASES[seed % len(PAIRING_CASES)])
+    finite = 0
+    for pos in range(0, len(g) - L + 1):
+        for strand in (0, 1):
+            got = tm.site_tm_by_pairing(c, pos, primer, strand, k, clamp, p)
+            want = tm.site_tm(c, pos, primer, strand, k, clamp, p)
+            if math.isnan(want):
+                assert math.isnan(got)
+            else:
+                finite += 1
+                assert got == pytest.approx(want, abs=1e-9)
+    assert finite >= 2
+
+
+def test_site_tm_by_pairing_small_cases_against_brute_force():
+    g = "TTGACGTAGCCATGNAGCTAGGCATTACGGATCCAT"
+    c = scan.codes(g)
+    for primer, k, clamp in (("ACGTAGCCATG", 3, 1), ("RCGYAGSCWTG", 4, 0), ("NNGTAGCCAKG", 5, 2)):
+        for case in PAIRING_CASES[:4]:
+            p = tm.TmParams(**case)
+            for pos in range(len(g) - len(primer) + 1):
+                for strand in (0, 1):
+                    got = tm.site_tm_by_pairing(c, pos, primer, strand, k, clamp, p)
+                    want = brute_site_tm(g, pos, primer, strand, k, clamp, p)
+                    assert (math.isnan(got) and math.isnan(want)) or \
+                        got == pytest.approx(want, abs=1e-9)
+
+
+def test_site_tm_by_pairing_refuses_the_gc_dependent_methods():
+    c = scan.codes("ACGTACGTAC")
+    for m in (6, 7):
+        with pytest.raises(ValueError):
+            tm.site_tm_by_pairing(c, 0, "ACGTACGTAC", 0, 1, 0, tm.TmParams(saltcorr=m))
