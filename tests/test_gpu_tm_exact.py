@@ -135,10 +135,12 @@ ABOVE = [
 
 
 @pytest.mark.parametrize("case", range(len(ABOVE)))
-def test_exact_route_above_the_enumeration_bound(dev, case):
+def test_exact_route_above_the_enumeration_bound(dev, monkeypatch, case):
     """Primers with more pairings per site than the enumeration takes, on
     planted sites with 0..k mismatches (some facing an N) and amplicons,
-    against the oracle's maximum over sets of paired positions."""
+    against the oracle's maximum over sets of paired positions; the same
+    records from the radix tail of ah_query and from the separate calls
+    (ah_scan_primers, ah_tm, ah_pair_amplicons)."""
     from paper_2509_13300_amd import _lib as L
     from paper_2509_13300_amd import path
 
@@ -203,3 +205,17 @@ def test_exact_route_above_the_enumeration_bound(dev, case):
     assert nontrivial >= 10
     assert np.all(np.isfinite(gh["tm"])) and float(err.max()) <= TM_TOL
     assert amp_tuples(ga) == amp_tuples(oa) and ga.size >= 20
+    for label, segmented, fused in (("radix tail", "0", True), ("separate calls", None, False)):
+        if segmented is None:
+            monkeypatch.delenv("AH_QUERY_SEGMENTED", raising=False)
+        else:
+            monkeypatch.setenv("AH_QUERY_SEGMENTED", segmented)
+        buf2 = path.alloc(coll, [pr], 1 << 16, 1 << 16, dev)
+        path.run(coll, [pr], buf2, tm=tp, fused=fused)
+        torch.cuda.synchronize()
+        gh2 = path.hits_numpy(buf2)
+        say(label, "hits", gh2.size)
+        assert hit_tuples_gpu(gh2) == hit_tuples_gpu(gh)
+        assert np.array_equal(gh2["tm"].view(np.uint32), gh["tm"].view(np.uint32))
+        assert amp_tuples(path.amps_numpy(buf2)) == amp_tuples(ga)
+    monkeypatch.delenv("AH_QUERY_SEGMENTED", raising=False)
