@@ -1785,10 +1785,18 @@ bool tm_exact_forced() {
   return e && e[0] == '1';
 }
 
+// Whether the route applies: a Tm that depends on the pairing alone and a
+// negative denominator for every pairing.
+bool tm_exact_applies(const ah_tm_params& p, const SaltTerms& salt_t, int L) {
+  return !salt_t.recip && tm_denominator_const(p, salt_t, L) + kMaxPairingDs < 0.0;
+}
+
 // Whether the Tm kernels take a primer's best pairing by the exact ratio
-// iteration rather than by enumerating its pairings.
-bool tm_exact_route(const Primer& pr, uint32_t k, uint32_t clamp, const SaltTerms& salt_t) {
-  if (salt_t.recip) return false;
+// iteration rather than by enumerating its pairings (a request above the
+// bound where it does not apply is refused by check_tm_request).
+bool tm_exact_route(const Primer& pr, uint32_t k, uint32_t clamp, const ah_tm_params& p,
+                    const SaltTerms& salt_t) {
+  if (!tm_exact_applies(p, salt_t, pr.L)) return false;
   return worst_tm_pairings(pr, k, clamp) > (uint64_t)AH_TM_MAX_PAIRINGS || tm_exact_forced();
 }
 
@@ -1868,7 +1876,7 @@ ah_status tm_table(const PairSet& ps, uint32_t n_pairs, const ah_tm_params& pp, 
       t.deg = deg;
       t.decoy = (ps.flags[q] & AH_PAIR_DECOY) ? 1u : 0u;
       t.KL = tm_denominator_const(*p, salt_t, pr.L);
-      t.dp = tm_exact_route(pr, ps.k[q], ps.clamp[q], salt_t) ? 1u : 0u;
+      t.dp = tm_exact_route(pr, ps.k[q], ps.clamp[q], *p, salt_t) ? 1u : 0u;
       any_exact |= t.dp != 0u;
       t.tshift = salt_t.shift;
       if (salt_t.recip) {
