@@ -540,191 +540,380 @@ __device__ __noinline__ u64 tm_dp_pairing(u64 o, u64 eq0, u64 afree, u32 budget,
   return best;
 }
 
-// The Tm of site record h (a genome and pair of this call); s_dh / s_ds:
-// the stack tables in LDS.
-// S: the segment words of the site's genome, wbase: its first word; T2: the
-// two primer tables (fwd, rev) of the site's pair (global memory, or a copy
-// in LDS).  kExact: instantiated with the exact route (tm_dp_pairing) for
-// calls whose primers need it; the enumeration-only instantiation carries
-// none of its private memory.
-template <bool kExact>
-__device__ __forceinline__ float tm_value_at(const TmJob& J, const ah_hit& h, u64 S, u64 wbase,
-                                             const float* s_dh, const float* s_ds,
-                                             const PrimerTab* T2) {
+__device__ __forceinline__ u64 wave_incl_scan(u64 v) {
+  const u32 lane = threadIdx.x & 63u;
+  u64 x = v;
+#pragma unroll
+  for (u32 o = 1; o < 64; o <<= 1) {
+    const u64 y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ u64 wave_sum(u64 v) {
+#pragma unroll
+  for (u32 o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// A site's representative pairing and the sums every other pairing of it
+// starts from.  Under the model only paired positions enter Delta-H, Delta-S
+// and the initiation terms, so every oligo with the same set of paired
+// positions has the same Tm.  Representative oligo: the template's base at
+// each degenerate position whose set holds it ("in-set"), any member
+// elsewhere (those positions mismatch for every oligo).  Other compatible
+// pairings come from turning at most k - mm in-set, non-clamp positions into
+// mismatches, which any other member of their set does.
+//
+// Salt methods 6 and 7 also depend on the oligo's G+C count, so oligos that
+// pair alike differ: each pairing takes the best choice at its unpaired
+// degenerate positions, a member other than the template's base (any member
+// where that base is not in the set): G or C if one is allowed when G+C
+// raises Tm (rB < 0), else G or C only if every allowed member is.  gp: G+C
+// bits (bit 2j) of the representative, which is the oligo at paired
+// positions; gu: of the best choice at unpaired ones.
+struct TmRep {
+  u64 o;       // representative oligo, 2 bits per position
+  u64 eq0;     // its paired positions (bit 2j)
+  u64 afree;   // in-set, non-clamp positions a pairing may unpair
+  u64 st0;     // its stacks (bit 2j: positions j, j + 1 paired)
+  u64 gp, gu;  // G+C bits (salt methods 6 and 7)
+  float sh0, ch0, ss0, cs0;  // its stack sums, compensated
+  u32 budget;  // positions of afree a pairing may unpair
+  u32 nfree;   // positions in afree
+  bool ok;     // some oligo of the primer is compatible with the site
+};
+
+// Site record h (a genome and pair of this call); T: its primer's table;
+// S: the segment words of the site's genome, wbase: its first word; s_dh /
+// s_ds: the stack tables in LDS.
+__device__ __forceinline__ TmRep tm_rep(const TmJob& J, const ah_hit& h, u64 S, u64 wbase,
+                                        const float* s_dh, const float* s_ds,
+                                        const PrimerTab* T) {
   const uint2* __restrict__ words = J.words;
   const u32* __restrict__ nmask = J.nmask;
-  {
-    const PrimerTab* T = &T2[h.strand_primer & 1u];
-    const u32 L = T->L;
-    const u32 strand = (h.strand_primer >> 1) & 1u;
-    const u32 b = h.pos / (u32)S;  // S <= 2^27: 32-bit division
-    const u64 w0 = wbase + (h.pos - (u64)b * S);
-    // ow: the base an oligo must carry at each primer position to pair with
-    // the template (2 bits per position, primer 5'->3'); nb: positions
-    // opposite a non-ACGT template base, which pair with nothing.  The
-    // oligo's position runs against the window on the - strand; it carries
-    // the complement of the window's base on the - strand of a site, and on
-    // the + strand of a decoy site (the decoy's + pattern is the primer's
-    // complement: the primer against the reversed genome's - strand).
-    const u32 cflip = strand ^ T->decoy;
-    // All 32 words a primer can span are loaded at once, unconditionally:
-    // the window word is t < S and every genome carries 31 halo words, so
-    // words t .. t + 31 lie inside its allocation (and its mask's).
-    uint2 wv[32];
+  TmRep r;
+  const u32 L = T->L;
+  const u32 strand = (h.strand_primer >> 1) & 1u;
+  const u32 b = h.pos / (u32)S;  // S <= 2^27: 32-bit division
+  const u64 w0 = wbase + (h.pos - (u64)b * S);
+  // ow: the base an oligo must carry at each primer position to pair with
+  // the template (2 bits per position, primer 5'->3'); nb: positions
+  // opposite a non-ACGT template base, which pair with nothing.  The
+  // oligo's position runs against the window on the - strand; it carries
+  // the complement of the window's base on the - strand of a site, and on
+  // the + strand of a decoy site (the decoy's + pattern is the primer's
+  // complement: the primer against the reversed genome's - strand).
+  const u32 cflip = strand ^ T->decoy;
+  // All 32 words a primer can span are loaded at once, unconditionally:
+  // the window word is t < S and every genome carries 31 halo words, so
+  // words t .. t + 31 lie inside its allocation (and its mask's).
+  uint2 wv[32];
 #pragma unroll
-    for (u32 j = 0; j < 32; ++j) wv[j] = words[w0 + j];
-    u64 ow = 0;
+  for (u32 j = 0; j < 32; ++j) wv[j] = words[w0 + j];
+  u64 ow = 0;
+#pragma unroll
+  for (u32 j = 0; j < 32; ++j) {
+    const u32 c = (((wv[j].x >> b) & 1u) << 1) | ((wv[j].y >> b) & 1u);
+    const u32 jj = strand ? L - 1u - j : j;
+    if (j < L) ow |= (u64)(cflip ? 3u - c : c) << (2u * jj);
+  }
+  u64 nb = 0;
+  if (nmask) {
+    u32 nmv[32];
+#pragma unroll
+    for (u32 j = 0; j < 32; ++j) nmv[j] = nmask[w0 + j];
 #pragma unroll
     for (u32 j = 0; j < 32; ++j) {
-      const u32 c = (((wv[j].x >> b) & 1u) << 1) | ((wv[j].y >> b) & 1u);
       const u32 jj = strand ? L - 1u - j : j;
-      if (j < L) ow |= (u64)(cflip ? 3u - c : c) << (2u * jj);
+      if (j < L) nb |= (u64)((nmv[j] >> b) & 1u) << (2u * jj);
     }
-    u64 nb = 0;
-    if (nmask) {
-      u32 nmv[32];
-#pragma unroll
-      for (u32 j = 0; j < 32; ++j) nmv[j] = nmask[w0 + j];
-#pragma unroll
-      for (u32 j = 0; j < 32; ++j) {
-        const u32 jj = strand ? L - 1u - j : j;
-        if (j < L) nb |= (u64)((nmv[j] >> b) & 1u) << (2u * jj);
-      }
-    }
-    const u64 lanes = T->lanes & ~nb;
-    const u64 clampm = T->clampm;
-    const u64 stackm = T->stackm;
-    const u32 k = T->k;
-    const double KL = T->KL;
-    // Under the model only paired positions enter Delta-H, Delta-S and the
-    // initiation terms, so every oligo with the same set of paired positions
-    // has the same Tm.  Representative oligo: the template's base at each
-    // degenerate position whose set holds it ("in-set"), any member
-    // elsewhere (those positions mismatch for every oligo).  Other compatible
-    // pairings come from turning at most k - mm in-set, non-clamp positions
-    // into mismatches, which any other member of their set does.
-    //
-    // Salt methods 6 and 7 also depend on the oligo's G+C count, so oligos
-    // that pair alike differ: each pairing takes the best choice at its
-    // unpaired degenerate positions, a member other than the template's base
-    // (any member where that base is not in the set): G or C if one is
-    // allowed when G+C raises Tm (rB < 0), else G or C only if every allowed
-    // member is.  gp: G+C bits (bit 2j) of the representative, which is the
-    // oligo at paired positions; gu: of the best choice at unpaired ones.
-    const bool recip = T->recip != 0u;
-    const bool want_gc = T->rB < 0.0;
-    u64 o = T->fixed, afree = 0, degm = 0, gu_deg = 0;
-    for (u32 d = 0; d < T->nd; ++d) {
-      const u32 pos2 = 2u * T->dpos[d];
-      const u32 t = (u32)(ow >> pos2) & 3u;
-      const u32 mem = T->mem[d];
-      bool in_set = false;
-      for (u32 r = 0; r < T->nmem[d]; ++r) in_set |= ((mem >> (2u * r)) & 3u) == t;
-      in_set &= ((nb >> pos2) & 1u) == 0u;
-      o |= (u64)(in_set ? t : (mem & 3u)) << pos2;
-      if (in_set && ((clampm >> pos2) & 1u) == 0u) afree |= 1ull << pos2;
-      if (recip) {
-        bool any_gc = false, all_gc = true;
-        for (u32 r = 0; r < T->nmem[d]; ++r) {
-          const u32 b = (mem >> (2u * r)) & 3u;
-          if (in_set && b == t) continue;
-          const bool gc = ((b ^ (b >> 1)) & 1u) != 0u;  // C = 1, G = 2
-          any_gc |= gc;
-          all_gc &= gc;
-        }
-        degm |= 1ull << pos2;
-        if (want_gc ? any_gc : all_gc) gu_deg |= 1ull << pos2;
-      }
-    }
-    const u64 allpos = T->lanes;
-    const u64 gp = (o ^ (o >> 1)) & allpos;
-    const u64 gu = (gp & ~degm) | gu_deg;
-    const double rA = T->rA, rB = T->rB, invL = 1.0 / (double)L;
-    const u64 x = o ^ ow;
-    const u64 eq0 = ~(x | (x >> 1)) & lanes;  // paired positions of the representative
-    const u32 mism0 = L - (u32)__popcll(eq0);
-    float best = __int_as_float(0x7fc00000);  // NaN: no compatible oligo
-    // The representative's stacks are summed once.  Another pairing turns
-    // positions of it into mismatches, which only removes the stacks on
-    // either side of each: its sums are the representative's minus those
-    // (compensated sums throughout).
-    const u64 st0 = eq0 & (eq0 >> 2) & stackm;
-    float sh0 = 0.f, ch0 = 0.f, ss0 = 0.f, cs0 = 0.f;
-    for (u64 st = st0; st; st &= st - 1) {
-      const u32 j2 = (u32)__ffsll((long long)st) - 1u;
-      const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
-      two_sum(sh0, ch0, s_dh[ix]);
-      two_sum(ss0, cs0, s_ds[ix]);
-    }
-    auto consider = [&](u64 eq) {
-      float sh = sh0, ch = ch0, ss = ss0, cs = cs0;
-      for (u64 st = st0 & ~(eq & (eq >> 2)); st; st &= st - 1) {  // the stacks eq breaks
-        const u32 j2 = (u32)__ffsll((long long)st) - 1u;
-        const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
-        two_sum(sh, ch, -s_dh[ix]);
-        two_sum(ss, cs, -s_ds[ix]);
-      }
-      if (eq) {
-        const u32 lo = (u32)__ffsll((long long)eq) - 1u;
-        const u32 hi = 63u - (u32)__clzll((long long)eq);
-        init_term((u32)(o >> lo) & 3u, sh, ch, ss, cs);
-        init_term((u32)(o >> hi) & 3u, sh, ch, ss, cs);
-      }
-      const float den = (float)((double)ss + (double)cs + KL);
-      float tm = 1000.0f * (sh + ch) / den - 273.15f;
-      if (recip) {  // 1/T += rA + rB fGC, with this pairing's best G+C count
-        const u32 gc = (u32)__popcll(eq & gp) + (u32)__popcll(allpos & ~eq & gu);
-        const double inv = 1.0 / ((double)tm + 273.15) + rA + rB * (double)gc * invL;
-        tm = (float)(1.0 / inv - 273.15);
-      }
-      best = (best == best && best >= tm) ? best : tm;
-    };
-    if (mism0 <= k && (eq0 & clampm) == clampm) {
-      consider(eq0);
-      const u32 nfree = (u32)__popcll(afree);
-      const u32 budget = min(k - mism0, nfree);
-      const bool exact = kExact && T->dp != 0u;
-      if (exact && budget)  // too many pairings to enumerate: the exact route
-        consider(tm_dp_pairing(o, eq0, afree, budget, L, KL, s_dh, s_ds));
-      for (u32 e = 1; e <= (exact ? 0u : budget); ++e) {
-        // every e-subset of the free positions (Gosper's next combination
-        // over nfree bits, deposited onto the position mask)
-        u64 comb = (1ull << e) - 1ull;
-        while (comb < (1ull << nfree)) {  // nfree <= 32
-          u64 sub = 0, m = afree, c = comb;
-          while (c) {
-            if (c & 1ull) sub |= m & (0ull - m);
-            m &= m - 1ull;
-            c >>= 1;
-          }
-          consider(eq0 & ~sub);
-          const u64 low = comb & (0ull - comb);
-          const u64 r = comb + low;
-          if (r == 0) break;
-          comb = (((r ^ comb) >> 2) >> (__ffsll((long long)low) - 1)) | r;  // low: a power of two
-        }
-      }
-    }
-    return best + (float)T->tshift;  // salt methods 1-4 (NaN stays NaN)
   }
+  const u64 lanes = T->lanes & ~nb;
+  const u64 clampm = T->clampm;
+  const u64 stackm = T->stackm;
+  const u32 k = T->k;
+  const bool recip = T->recip != 0u;
+  const bool want_gc = T->rB < 0.0;
+  u64 o = T->fixed, afree = 0, degm = 0, gu_deg = 0;
+  for (u32 d = 0; d < T->nd; ++d) {
+    const u32 pos2 = 2u * T->dpos[d];
+    const u32 t = (u32)(ow >> pos2) & 3u;
+    const u32 mem = T->mem[d];
+    bool in_set = false;
+    for (u32 q = 0; q < T->nmem[d]; ++q) in_set |= ((mem >> (2u * q)) & 3u) == t;
+    in_set &= ((nb >> pos2) & 1u) == 0u;
+    o |= (u64)(in_set ? t : (mem & 3u)) << pos2;
+    if (in_set && ((clampm >> pos2) & 1u) == 0u) afree |= 1ull << pos2;
+    if (recip) {
+      bool any_gc = false, all_gc = true;
+      for (u32 q = 0; q < T->nmem[d]; ++q) {
+        const u32 m = (mem >> (2u * q)) & 3u;
+        if (in_set && m == t) continue;
+        const bool gc = ((m ^ (m >> 1)) & 1u) != 0u;  // C = 1, G = 2
+        any_gc |= gc;
+        all_gc &= gc;
+      }
+      degm |= 1ull << pos2;
+      if (want_gc ? any_gc : all_gc) gu_deg |= 1ull << pos2;
+    }
+  }
+  const u64 allpos = T->lanes;
+  r.o = o;
+  r.afree = afree;
+  r.gp = (o ^ (o >> 1)) & allpos;
+  r.gu = (r.gp & ~degm) | gu_deg;
+  const u64 x = o ^ ow;
+  r.eq0 = ~(x | (x >> 1)) & lanes;  // paired positions of the representative
+  const u32 mism0 = L - (u32)__popcll(r.eq0);
+  // The representative's stacks are summed once.  Another pairing turns
+  // positions of it into mismatches, which only removes the stacks on
+  // either side of each: its sums are the representative's minus those
+  // (compensated sums throughout).
+  r.st0 = r.eq0 & (r.eq0 >> 2) & stackm;
+  float sh0 = 0.f, ch0 = 0.f, ss0 = 0.f, cs0 = 0.f;
+  for (u64 st = r.st0; st; st &= st - 1) {
+    const u32 j2 = (u32)__ffsll((long long)st) - 1u;
+    const u32 ix = (u32)(((o >> j2) & 3u) << 2) | (u32)((o >> (j2 + 2u)) & 3u);
+    two_sum(sh0, ch0, s_dh[ix]);
+    two_sum(ss0, cs0, s_ds[ix]);
+  }
+  r.sh0 = sh0;
+  r.ch0 = ch0;
+  r.ss0 = ss0;
+  r.cs0 = cs0;
+  r.ok = mism0 <= k && (r.eq0 & clampm) == clampm;
+  r.nfree = (u32)__popcll(afree);
+  r.budget = r.ok ? min(k - mism0, r.nfree) : 0u;
+  return r;
 }
 
-template <bool kExact>
-__device__ __forceinline__ float tm_value(const TmJob& J, const ah_hit& h, const float* s_dh,
-                                          const float* s_ds) {
-  return tm_value_at<kExact>(J, h, ((u64)J.len[h.genome] + 31) >> 5, J.word_off[h.genome], s_dh, s_ds,
-                     &J.tabs[(u32)h.pair * 2u]);
+// The Tm of pairing eq (a subset of r.eq0) of site r, in degrees before the
+// shift of salt methods 1-4.
+__device__ __forceinline__ float tm_pairing(const TmRep& r, const PrimerTab* T, u64 eq,
+                                            const float* s_dh, const float* s_ds) {
+  float sh = r.sh0, ch = r.ch0, ss = r.ss0, cs = r.cs0;
+  for (u64 st = r.st0 & ~(eq & (eq >> 2)); st; st &= st - 1) {  // the stacks eq breaks
+    const u32 j2 = (u32)__ffsll((long long)st) - 1u;
+    const u32 ix = (u32)(((r.o >> j2) & 3u) << 2) | (u32)((r.o >> (j2 + 2u)) & 3u);
+    two_sum(sh, ch, -s_dh[ix]);
+    two_sum(ss, cs, -s_ds[ix]);
+  }
+  if (eq) {
+    const u32 lo = (u32)__ffsll((long long)eq) - 1u;
+    const u32 hi = 63u - (u32)__clzll((long long)eq);
+    init_term((u32)(r.o >> lo) & 3u, sh, ch, ss, cs);
+    init_term((u32)(r.o >> hi) & 3u, sh, ch, ss, cs);
+  }
+  const float den = (float)((double)ss + (double)cs + T->KL);
+  float tm = 1000.0f * (sh + ch) / den - 273.15f;
+  if (T->recip) {  // 1/T += rA + rB fGC, with this pairing's best G+C count
+    const u64 allpos = T->lanes;
+    const u32 gc = (u32)__popcll(eq & r.gp) + (u32)__popcll(allpos & ~eq & r.gu);
+    const double inv = 1.0 / ((double)tm + 273.15) + T->rA + T->rB * (double)gc / (double)T->L;
+    tm = (float)(1.0 / inv - 273.15);
+  }
+  return tm;
 }
 
-// Sets hits[i].tm.  A record that does not name a genome and pair of this
-// call (never written by a scan of it) is left alone rather than followed.
+// C(n, r) for n <= 32.  Each partial product is a binomial below 2^30 and
+// each step's product below 2^35, so double precision carries them exactly
+// (and a correctly rounded division of an exact multiple is exact), without
+// the 64-bit integer division the device does in software.
+__device__ __forceinline__ u64 binom(u32 n, u32 r) {
+  if (r > n) return 0;
+  double c = 1.0;
+  for (u32 i = 1; i <= r; ++i) c = c * (double)(n - r + i) / (double)i;
+  return (u64)c;
+}
+
+// Extra pairings of a site with nfree positions to choose from and budget
+// of them to unpair: every nonempty subset of at most budget positions.
+__device__ __forceinline__ u64 extra_pairings(u32 nfree, u32 budget) {
+  u64 p = 0;
+  for (u32 e = 1; e <= budget; ++e) p += binom(nfree, e);
+  return p;
+}
+
+// The q-th of those subsets, as positions of afree (bit 2j), q <
+// extra_pairings(nfree, budget): subsets by size 1, 2, ..., each size in
+// colexicographic order (the combinatorial number system).
+__device__ __forceinline__ u64 unrank_pairing(u64 q, u64 afree, u32 nfree, u32 budget) {
+  u32 e = 1;
+  for (; e < budget; ++e) {
+    const u64 c = binom(nfree, e);
+    if (q < c) break;
+    q -= c;
+  }
+  u32 sel = 0, n = nfree;
+  for (u32 i = e; i >= 1; --i) {
+    u32 c = n - 1u;  // the largest c < n with C(c, i) <= q (C(i - 1, i) = 0)
+    u64 bc = binom(c, i);
+    while (bc > q) bc = binom(--c, i);
+    sel |= 1u << c;
+    q -= bc;
+    n = c;
+  }
+  u64 sub = 0, m = afree;  // the sel-th positions of afree
+  for (u32 j = 0; m; ++j, m &= m - 1ull)
+    if ((sel >> j) & 1u) sub |= m & (0ull - m);
+  return sub;
+}
+
+__device__ __forceinline__ u64 shfl64(u64 v, int src) {
+  const u32 lo = (u32)__shfl((int)(u32)v, src, 64), hi = (u32)__shfl((int)(u32)(v >> 32), src, 64);
+  return ((u64)hi << 32) | lo;
+}
+__device__ __forceinline__ float shflf(float v, int src) { return __shfl(v, src, 64); }
+
+// A float as an int that orders like it (for LDS atomic max; NaN never
+// stored).
+__device__ __forceinline__ int tm_key(float v) {
+  const int b = __float_as_int(v);
+  return b >= 0 ? b : b ^ 0x7fffffff;
+}
+__device__ __forceinline__ float tm_unkey(int k) {
+  return __int_as_float(k >= 0 ? k : k ^ 0x7fffffff);
+}
+
+// The Tm of each lane's site record h (valid: the lane has one; every lane
+// of the wave calls this together).  T2: the lane's pair's two primer
+// tables; s_best: 64 ints of LDS for this wave.  The representative pairing
+// is evaluated by its own lane.  The other pairings of all the wave's sites
+// are then dealt out over the 64 lanes in turn (a site with many pairings no
+// longer holds the wave while the others idle): lane l takes pairings l,
+// l + 64, ... of the wave's list, finds the site each belongs to and its
+// subset, and its Tm goes to the site's slot by an atomic max.  A wave whose
+// sites have at most kTmLaneMax extra pairings each keeps them in their own
+// lanes (a round of the dealing costs more than a few pairings).  Primers
+// that take the exact route (kExact and the table's dp) find their best
+// pairing by tm_dp_pairing in their own lane instead.
+constexpr u64 kTmLaneMax = 4;
 template <bool kExact>
-__device__ __forceinline__ void tm_one(const TmJob& J, ah_hit* __restrict__ hits, u64 i,
-                                       const float* s_dh, const float* s_ds) {
-  ah_hit h = hits[i];
-  if (h.genome >= J.n_genomes || h.pair >= J.n_pairs) return;
-  h.tm = tm_value<kExact>(J, h, s_dh, s_ds);
-  hits[i] = h;
+__device__ __forceinline__ float tm_wave(const TmJob& J, const ah_hit& h, bool valid, u64 S,
+                                         u64 wbase, const float* s_dh, const float* s_ds,
+                                         const PrimerTab* T2, int* s_best) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const PrimerTab* T = &T2[h.strand_primer & 1u];
+  TmRep r{};
+  float best = __int_as_float(0x7fc00000);  // NaN: no compatible oligo
+  u64 own = 0;                                // this site's extra pairings
+  constexpr int kNoTm = (int)0x80000000;      // below every tm_key
+  if (valid) {
+    r = tm_rep(J, h, S, wbase, s_dh, s_ds, T);
+    if (r.ok) {
+      best = tm_pairing(r, T, r.eq0, s_dh, s_ds);
+      if (kExact && T->dp != 0u) {
+        if (r.budget) {  // too many pairings to enumerate: the exact route
+          const float v = tm_pairing(
+              r, T, tm_dp_pairing(r.o, r.eq0, r.afree, r.budget, T->L, T->KL, s_dh, s_ds), s_dh,
+              s_ds);
+          best = best >= v ? best : v;
+        }
+      } else {
+        own = extra_pairings(r.nfree, r.budget);
+      }
+    }
+  }
+  u64 most = own;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const u64 y = ((u64)(u32)__shfl_xor((int)(u32)(most >> 32), o, 64) << 32) |
+                  (u32)__shfl_xor((int)(u32)most, o, 64);
+    most = y > most ? y : most;
+  }
+  if (most <= kTmLaneMax) {
+    // every e-subset of the free positions, e <= budget (Gosper's next
+    // combination over nfree bits, deposited onto the position mask)
+    for (u32 e = 1; own && e <= r.budget; ++e) {
+      u64 comb = (1ull << e) - 1ull;
+      while (comb < (1ull << r.nfree)) {  // nfree <= 32
+        u64 sub = 0, m = r.afree, c = comb;
+        while (c) {
+          if (c & 1ull) sub |= m & (0ull - m);
+          m &= m - 1ull;
+          c >>= 1;
+        }
+        const float v = tm_pairing(r, T, r.eq0 & ~sub, s_dh, s_ds);
+        best = (best == best && best >= v) ? best : v;
+        const u64 low = comb & (0ull - comb);
+        const u64 nx = comb + low;
+        if (nx == 0) break;
+        comb = (((nx ^ comb) >> 2) >> (__ffsll((long long)low) - 1)) | nx;  // low: a power of two
+      }
+    }
+    return valid ? best + (float)T->tshift : best;  // salt methods 1-4 (NaN stays NaN)
+  }
+  const u64 incl = wave_incl_scan(own);
+  const u64 total = shfl64(incl, 63);
+  {
+    s_best[lane] = kNoTm;
+    for (u64 g0 = 0; g0 < total; g0 += 64) {
+      const u64 g = g0 + (u64)lane;
+      // the site of pairing g: the first lane whose inclusive count exceeds g
+      int site = 0;
+      for (int step = 32; step > 0; step >>= 1) {
+        const u64 v = shfl64(incl, site + step - 1);
+        if (v <= g) site += step;
+      }
+      site = site < 63 ? site : 63;
+      TmRep q;
+      q.o = shfl64(r.o, site);
+      q.eq0 = shfl64(r.eq0, site);
+      q.afree = shfl64(r.afree, site);
+      q.st0 = shfl64(r.st0, site);
+      q.gp = shfl64(r.gp, site);
+      q.gu = shfl64(r.gu, site);
+      q.sh0 = shflf(r.sh0, site);
+      q.ch0 = shflf(r.ch0, site);
+      q.ss0 = shflf(r.ss0, site);
+      q.cs0 = shflf(r.cs0, site);
+      q.nfree = (u32)__shfl((int)r.nfree, site, 64);
+      q.budget = (u32)__shfl((int)r.budget, site, 64);
+      const PrimerTab* Tq = (const PrimerTab*)shfl64((u64)(uintptr_t)T, site);
+      const u64 first = shfl64(incl - own, site);
+      if (g < total) {
+        const u64 sub = unrank_pairing(g - first, q.afree, q.nfree, q.budget);
+        const float v = tm_pairing(q, Tq, q.eq0 & ~sub, s_dh, s_ds);
+        if (v == v) atomicMax(&s_best[site], tm_key(v));
+      }
+    }
+    const int kb = s_best[lane];
+    if (own && kb != kNoTm) {
+      const float v = tm_unkey(kb);
+      best = (best == best && best >= v) ? best : v;
+    }
+  }
+  return valid ? best + (float)T->tshift : best;  // salt methods 1-4 (NaN stays NaN)
+}
+
+// Whether record h names a genome and pair of this call (a record never
+// written by a scan of it is left alone rather than followed).
+__device__ __forceinline__ bool tm_record_ok(const TmJob& J, const ah_hit& h) {
+  return h.genome < J.n_genomes && h.pair < J.n_pairs;
+}
+
+// Sets the tm of records i = i0 + lane of hits (i < n), for the whole wave
+// at once (i0: the wave's first index, the same in every lane).
+template <bool kExact>
+__device__ __forceinline__ void tm_records(const TmJob& J, ah_hit* __restrict__ hits, u64 i0,
+                                           u64 n, const float* s_dh, const float* s_ds,
+                                           int* s_best) {
+  const u64 i = i0 + (threadIdx.x & 63u);
+  ah_hit h{};
+  bool valid = false;
+  if (i < n) {
+    h = hits[i];
+    valid = tm_record_ok(J, h);
+  }
+  const u32 g = valid ? h.genome : 0u, pair = valid ? (u32)h.pair : 0u;
+  const u64 S = valid ? ((u64)J.len[g] + 31) >> 5 : 1u, wbase = valid ? J.word_off[g] : 0u;
+  const float v = tm_wave<kExact>(J, h, valid, S, wbase, s_dh, s_ds, &J.tabs[pair * 2u], s_best);
+  if (valid) {
+    h.tm = v;
+    hits[i] = h;
+  }
 }
 
 // Loads the stack tables into LDS (every thread of the block calls this).
@@ -741,10 +930,13 @@ __global__ __launch_bounds__(kBlock) void k_tm(TmJob J, ah_hit* __restrict__ hit
                                                const ah_result* __restrict__ nhits, u64 cap) {
   // the stack tables in LDS: lanes index them divergently, once per stack
   __shared__ float s_dh[16], s_ds[16];
+  __shared__ int s_best[kBlock];  // per wave: the best pairing of each lane's site
   tm_tables(s_dh, s_ds);
   const u64 cnt = nhits->count;
   const u64 n = cnt < cap ? cnt : cap;
-  for (u64 i = global_tid(); i < n; i += grid_threads()) tm_one<kExact>(J, hits, i, s_dh, s_ds);
+  // a wave takes 64 consecutive records at a time (the stride is whole waves)
+  for (u64 i0 = global_tid() - (threadIdx.x & 63u); i0 < n; i0 += grid_threads())
+    tm_records<kExact>(J, hits, i0, n, s_dh, s_ds, s_best + (threadIdx.x & ~63u));
 }
 
 // ----------------------------------------------------------- pairing ----
@@ -1178,22 +1370,6 @@ __device__ __forceinline__ u32 seg_count(const C* pc, uint2 r) {
 // registers), and every segment of the query is resident at once.
 constexpr u32 kSegBlock = 64;
 
-__device__ __forceinline__ u64 wave_incl_scan(u64 v) {
-  const u32 lane = threadIdx.x & 63u;
-  u64 x = v;
-#pragma unroll
-  for (u32 o = 1; o < 64; o <<= 1) {
-    const u64 y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  return x;
-}
-
-__device__ __forceinline__ u64 wave_sum(u64 v) {
-#pragma unroll
-  for (u32 o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // Leaders of the sorted segment at records base .. base + m: the amplicons
 // each starts (cnt) and its minus ranges (rng: fwd-primer x, y and
@@ -1370,6 +1546,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   __shared__ unsigned char kind[kSegLds];
   __shared__ float s_dh[16], s_ds[16];
   __shared__ PrimerTab s_tab[2];  // the pair's primer tables, read throughout the Tm
+  __shared__ int s_best[kSegBlock];  // the best pairing of each lane's site
   const u32 t = threadIdx.x, s = blockIdx.x;
   // the segment's constants, loaded together: its sites, first slot, pair
   // tables and genome (every site of segment s is on genome s mod n)
@@ -1420,10 +1597,11 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
     const int from = (int)(key & 63u);
 #pragma unroll
     for (int q = 0; q < 4; ++q) hv[q] = __shfl(hv[q], from, 64);
+    ah_hit r;
+    __builtin_memcpy(&r, hv, sizeof r);
+    const float tmv = tm_wave<kExact>(A.tj, r, t < m, S, wbase, s_dh, s_ds, s_tab, s_best);
     if (t < m) {
-      ah_hit r;
-      __builtin_memcpy(&r, hv, sizeof r);
-      r.tm = tm_value_at<kExact>(A.tj, r, S, wbase, s_dh, s_ds, s_tab);
+      r.tm = tmv;
       o[t] = r;
       spos[t] = r.pos;
       kind[t] = (unsigned char)seg_kind(r, pt);
@@ -1501,13 +1679,18 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   }
   // the Tm of every site, written with the record to its place
   if (!tiny)
-    for (u32 i = t; i < m; i += kSegBlock) {
-      ah_hit h = small ? A.staged[base + (u32)(keys[i] & (kSegLds - 1u))] : o[i];
-      h.tm = tm_value_at<kExact>(A.tj, h, S, wbase, s_dh, s_ds, s_tab);
-      o[i] = h;
-      if (small) {
-        spos[i] = h.pos;
-        kind[i] = (unsigned char)seg_kind(h, pt);
+    for (u32 r0 = 0; r0 < m; r0 += kSegBlock) {  // the whole wave, 64 records at a time
+      const u32 i = r0 + t;
+      ah_hit h{};
+      if (i < m) h = small ? A.staged[base + (u32)(keys[i] & (kSegLds - 1u))] : o[i];
+      const float tmv = tm_wave<kExact>(A.tj, h, i < m, S, wbase, s_dh, s_ds, s_tab, s_best);
+      if (i < m) {
+        h.tm = tmv;
+        o[i] = h;
+        if (small) {
+          spos[i] = h.pos;
+          kind[i] = (unsigned char)seg_kind(h, pt);
+        }
       }
     }
   __syncthreads();
@@ -1869,6 +2052,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter_tm(
     return;
   }
   __shared__ float s_dh[16], s_ds[16];
+  __shared__ int s_best[kBlock];  // per wave: the best pairing of each lane's site
   tm_tables(s_dh, s_ds);
   const u64 n = *n_dev;
   const u64 t = (u64)(blockIdx.x - kSortGrid) * kBlock + threadIdx.x;
@@ -1877,7 +2061,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter_tm(
     cf[c] = 0;
     cr[c] = 0;
   }
-  for (u64 i = t; i < n; i += stride) tm_one<kExact>(J, staged, i, s_dh, s_ds);
+  for (u64 i0 = t - (threadIdx.x & 63u); i0 < n; i0 += stride)
+    tm_records<kExact>(J, staged, i0, n, s_dh, s_ds, s_best + (threadIdx.x & ~63u));
 }
 
 // Last pass: as a record reaches its place, the kept minus sites of the fwd
