@@ -3,7 +3,8 @@
 // This file is compiled at run time (hipRTC) once per primer set, with a
 // generated pattern program appended after it; the build compiles a few such
 // specialisations to check that it builds.  A pattern is one primer of a pair
-// on one strand.  Three kernels:
+// on one strand.  The kernels: the filter, the exact count where the filter
+// does not take it, and one of two emit passes:
 //
 // * ah_scan_kernel, the filter.  Packed layout (see ah.h): bit b of word t of a
 //   genome holds the base at b*S + t, so the window starting at b*S + t reads
@@ -18,14 +19,15 @@
 //   mismatches (pigeonhole blocks, or the exact count for patterns where
 //   blocks do not pay); windows that pass are appended to the workgroup's own
 //   slice of a candidate list (counted in LDS: no global atomics on the hot
-//   path, where same-address device atomics would serialise).
-// * ah_verify_kernel: one workgroup per slice; the exact count (every
-//   position, the non-ACGT mask, the clamp, window starts inside the genome)
-//   of every candidate, stored per candidate and summed per slice.  In wave
-//   mode each wave of the filter does this for its own slice after its last
-//   tile instead (the filter's occupancy is set by its LDS there, and the
-//   count's registers stay below that bound), and this kernel is not
-//   launched.
+//   path, where same-address device atomics would serialise).  After its
+//   last tile each wave (wave mode) or workgroup (tile mode, AH_TILE_COUNT)
+//   takes the exact count (every position, the non-ACGT mask, the clamp,
+//   window starts inside the genome) of the candidates of its own slice,
+//   stored per candidate and summed per slice, while others still filter:
+//   the count waits on memory, the filter on the vector ALU.
+// * ah_verify_kernel: the same count as a launch of its own after the
+//   filter, one workgroup per slice, for tile-mode programs of many
+//   patterns (AH_TILE_COUNT 0).
 // * ah_emit_kernel: one workgroup per slice; the slice's output offset is the
 //   sum of the earlier slices' sites (the sums of the earlier groups of 64
 //   slices, then of the earlier slices of its own group; no device atomics),
@@ -34,13 +36,17 @@
 //   also writes the result (required = sites found, count = records written)
 //   and the candidate-list statistics; a full slice makes the result an
 //   overflow whose bound covers both lists.
+// * ah_emit_seg_kernel: the same records, written into their (pair, genome)
+//   segments at the places the exact count reserved, for the segmented tail
+//   of the whole query.
 //
 // Macros supplied by the generated program: AH_U (window words per lane, odd
 // so that the lanes' LDS reads fall in distinct banks), AH_HALO (longest
 // primer - 1), AH_HAS_N (1 if the collection has non-ACGT bases, whose
 // positions mismatch every primer position), AH_WAVE (1: wave mode, below),
 // AH_QUAD_ONE_PAIR (1: the four patterns of every candidate record belong to
-// one primer pair).
+// one primer pair), AH_TILE_COUNT (1: in tile mode the filter takes the exact
+// count).
 
 typedef unsigned int u32;
 typedef unsigned long long u64;
@@ -49,14 +55,14 @@ typedef unsigned long long u64;
 #define AH_BLOCK 256
 #endif
 #define AH_TILE (AH_BLOCK * AH_U)
-// Slices per group of the emit pass's offsets (group sums kept by the verify
-// pass; the filter zeroes them).  Each group's sum has a 256-byte line of its
+// Slices per group of the emit pass's offsets (group sums added by the exact
+// count, cleared before the filter).  Each group's sum has a 256-byte line of its
 // own: atomics to one line serialise.
 #define AH_SLICE_GROUP 64
 #define AH_GROUP_STRIDE 32
 // Candidate slices per workgroup of the filter: one per wave in wave mode.
-// The verify and emit passes run one workgroup per filter workgroup and
-// read its slices in order as one list.
+// The count and emit passes run one workgroup per filter workgroup and read
+// its slices in order as one list.
 #if AH_WAVE
 #define AH_SPW (AH_BLOCK / 64)
 #else
@@ -404,7 +410,7 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     u64 hist_words, u32* __restrict__ seg_cnt, u32 seg_n) {
   // Each wave owns candidate slice s = 4 b + wave (slice records each).  After
   // its last tile the wave also counts the sites of its own candidates exactly
-  // (what ah_verify_kernel does in tile mode), while the other waves still
+  // (as a workgroup does in tile mode), while the other waves still
   // filter; the emit pass reads the four slices of a workgroup as one list.
   // The grid clears the sort's first two histogram tables (the emit pass
   // counts into the first, the first sort pass into the second); the group
@@ -477,12 +483,32 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     u64* __restrict__ slice_win, u64* __restrict__ group_sites, u32* __restrict__ cand_sites,
     u64* __restrict__ slice_sites, u32* __restrict__ hist_a, u32* __restrict__ hist_b,
     u64 hist_words, u32* __restrict__ seg_cnt, u32 seg_n) {
+  // The workgroup's candidates go to its slice.  With AH_TILE_COUNT, after
+  // its last tile it counts their sites exactly, while other workgroups
+  // still filter, and the grid clears the sort's first two histogram tables
+  // (the emit pass counts into the first, the first sort pass into the
+  // second); the group sums were cleared before this launch.  Without it
+  // ah_verify_kernel does both after the filter: a program of many patterns
+  // keeps every workgroup filtering to the end, so nothing would overlap the
+  // count, which then runs at the filter's occupancy.
   __shared__ uint4 tile[AH_STAGE_PAIRS];
+#if AH_TILE_COUNT
+  __shared__ u64 s_sites, s_win;
+  for (u64 e = (u64)blockIdx.x * AH_BLOCK + threadIdx.x; e < hist_words;
+       e += (u64)gridDim.x * AH_BLOCK) {
+    hist_a[e] = 0u;
+    hist_b[e] = 0u;
+  }
+#endif
   const u64 n_tiles = tile_prefix[n_genomes];
   const AhCands k{cand_out, slice, nullptr};
   if (threadIdx.x == 0) {
     ah_n_cand = 0;
     ah_n_lost = 0;
+#if AH_TILE_COUNT
+    s_sites = 0;
+    s_win = 0;
+#endif
   }
   __syncthreads();
   u32 lo = 0;
@@ -496,11 +522,34 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_scan_kernel(
     ah_groups((ah_lds_uint2*)tile, t0, c, k);
     __syncthreads();                // nobody reads the tile any more
   }
+#if AH_TILE_COUNT
+  // the exact count of the workgroup's candidates (records written by its
+  // own threads: the fence and the barrier order their stores before the
+  // loads)
+  __threadfence_block();
+  __syncthreads();
+  const u32 nk = min(ah_n_cand, slice);
+  u64 my_sites = 0, my_win = 0;
+  for (u32 i = threadIdx.x; i < nk; i += AH_BLOCK)
+    ah_verify_cand(words, nmask, word_off, len, cand_out, (u64)blockIdx.x * slice + i, cand_sites,
+                   seg_cnt, seg_n, my_sites, my_win);
+  if (my_sites) atomicAdd(&s_sites, my_sites);
+  if (my_win) atomicAdd(&s_win, my_win);
+  __syncthreads();
+  if (threadIdx.x == 0) {  // every workgroup reports, with or without tiles
+    slice_count[blockIdx.x] = nk;
+    slice_total[blockIdx.x] = ah_n_cand;
+    slice_win[blockIdx.x] = ah_n_lost + s_win;  // dropped candidates' windows and the kept ones'
+    slice_sites[blockIdx.x] = s_sites;
+    if (s_sites) atomicAdd(&group_sites[(blockIdx.x / AH_SLICE_GROUP) * AH_GROUP_STRIDE], s_sites);
+  }
+#else
   if (threadIdx.x == 0) {  // every workgroup reports, with or without tiles
     slice_count[blockIdx.x] = min(ah_n_cand, slice);
     slice_total[blockIdx.x] = ah_n_cand;
-    slice_win[blockIdx.x] = ah_n_lost;  // the verify kernel adds the kept ones
+    slice_win[blockIdx.x] = ah_n_lost;  // ah_verify_kernel adds the kept ones
   }
+#endif
 }
 #endif
 
@@ -511,7 +560,8 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_verify_kernel(
     u32* __restrict__ cand_sites, u64* __restrict__ slice_sites, u64* __restrict__ group_sites,
     u64* __restrict__ slice_win, u32* __restrict__ hist_a, u32* __restrict__ hist_b,
     u64 hist_words, u32* __restrict__ seg_cnt, u32 seg_n) {
-  // Sites of each candidate of this workgroup's slice, their sum, and the
+  // Tile mode with AH_TILE_COUNT 0 (programs of many patterns): sites of each
+  // candidate of a workgroup's slice after the filter, their sum, and the
   // candidates' windows (added to those of the candidates a full slice
   // dropped).  The grid also clears the sort's first two histogram tables
   // (the emit pass counts into the first, the first sort pass into the
@@ -600,7 +650,7 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
   // order: for each record it writes, the key (pair << qshift | genome <<
   // gshift | pos << 2 | strand-primer) and index, and counts the sort's first
   // digit (key & dmask) per chunk of the written order into hist[digit * hs
-  // + chunk] (cleared by the verify pass).  The sort partitions the
+  // + chunk] (cleared by the filter or the count).  The sort partitions the
   // min(found, cap) records into chunks of ceil(n / sort_grid) rounded up to
   // whole workgroups, at least sort_chunk_min.  sort_keys == null: no keys
   // (a scan run on its own).
@@ -689,8 +739,8 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_kernel(
 
 // Segmented emit (the whole query in one call): the records go straight to
 // their segment (pair, genome), whose first slot is the sum of the sites of
-// the earlier segments (seg_cnt from the verify pass, at most AH_SEG_MAX
-// segments), at the place inside it that the verify pass reserved
+// the earlier segments (seg_cnt from the exact count, at most AH_SEG_MAX
+// segments), at the place inside it that the count reserved
 // (AH_QUAD_ONE_PAIR) or one taken here with a device atomic on
 // seg_fill[segment] (cleared before the filter).  The order inside a segment
 // is left to the segment sort that follows.  Workgroup 0 also writes the
@@ -794,7 +844,7 @@ extern "C" __global__ __launch_bounds__(AH_BLOCK) void ah_emit_seg_kernel(
     const AhCtx c = ah_ctx(words, nmask, word_off, len, e.x);
     const u32 m[4] = {mk.x, mk.y, mk.z, mk.w};
 #if AH_QUAD_ONE_PAIR
-    {  // f - 1: the first place the verify pass reserved in the segment
+    {  // f - 1: the first place the exact count reserved in the segment
       u64 slot = s_off[ah_pat_pair(e.z) * seg_n + e.x] + (f - 1u);
 #pragma unroll
       for (int q = 0; q < 4; ++q)

@@ -129,6 +129,29 @@ def test_scan_tm_pair_random(dev, seed):
     check_case(p, [pr], dev)
 
 
+@pytest.mark.parametrize("seed", [0, 3, 5, 9, 12])
+@pytest.mark.parametrize("segmented", ["1", "0"])
+def test_tile_mode_random_cases(dev, monkeypatch, seed, segmented):
+    """The filter in tile mode (a workgroup per tile, its exact count after
+    its last tile), asked for with AH_SCAN_WAVE=0, on random cases through
+    both tails of the query."""
+    monkeypatch.setenv("AH_SCAN_WAVE", "0")
+    monkeypatch.setenv("AH_QUERY_SEGMENTED", segmented)
+    rs = np.random.RandomState(seed)
+    codes = "RYSWKMBDHVN"
+    lf, lr = rs.randint(5, 33), rs.randint(5, 33)
+    fwd = plan.random_primer(500 + seed, 0, lf, "".join(rs.choice(list(codes), size=rs.randint(0, 5))))
+    rev = plan.random_primer(500 + seed, 1, lr, "".join(rs.choice(list(codes), size=rs.randint(0, 5))))
+    k = int(rs.randint(0, 4))
+    clamp = int(rs.choice([0, 0, 1, 3, 5])) if min(lf, lr) >= 5 else 0
+    pr = plan.PairSpec(fwd, rev, k=k, clamp=clamp, min_len=lf + lr + 5, max_len=lf + lr + 900)
+    p = plan.tiny(600 + seed, n_genomes=int(rs.randint(1, 6)), len_lo=1, len_hi=60000, pair=pr,
+                  n_copies=(1, 4), nruns=int(rs.choice([0, 0, 5])),
+                  gc_lo=0.3, gc_hi=0.7)
+    say("tile mode", seed, segmented, fwd, rev, k, clamp, p.lengths.tolist())
+    check_case(p, [pr], dev)
+
+
 @pytest.mark.parametrize("k,L,clamp", [(6, 24, 3), (10, 32, 0), (15, 32, 5), (15, 20, 0),
                                          (12, 16, 2)])
 def test_large_k_up_to_the_maximum(dev, k, L, clamp):
