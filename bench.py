@@ -1003,8 +1003,9 @@ def main():
 
         torch.cuda.empty_cache()
         # batched vs plain: the 64-pair workload in one pass against the same
-        # pairs one by one (shape pinned: autotuning takes minutes)
-        b = gpu_batched(max(3, args.steps // 4), 1, shape=(9, 8))
+        # pairs one by one (shape pinned to the autotuner's usual choice:
+        # autotuning takes minutes)
+        b = gpu_batched(max(3, args.steps // 4), 1, shape=(15, 16))
         forms["batched"] = {
             "workload": BATCHED_DESC, "genomes": b["genomes"], "total_bp": b["bp"],
             "pairs": b["pairs"], "per_pair_gbps": b["value"], "distinct_gbps": b["distinct_gbps"],
