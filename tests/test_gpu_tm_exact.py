@@ -48,6 +48,11 @@ CASES = [
     (plan.PairSpec("GCGGCCGCTWTGCGGCCGCGATWAGGCGCC", "GGCGCCGCAWTGCCGGCGCTAWAGCGGCCG", k=3,
                    clamp=0, min_len=60, max_len=1500),
      dict(seed=321, n_genomes=4, len_lo=5000, len_hi=20000, n_copies=(2, 4)), True),
+    # four such codes per primer at k = 3: 14 extra pairings at a perfect site,
+    # more than a lane keeps, so the wave deals them out
+    (plan.PairSpec("GCCGCWATGCGGCTWAGCCGCWTAGCGCWT", "GCGGCWTGCCGCWAGCGGCWTGCGCWAGCG", k=3,
+                   clamp=0, min_len=60, max_len=1500),
+     dict(seed=654, n_genomes=4, len_lo=5000, len_hi=20000, n_copies=(2, 4)), True),
 ]
 
 
