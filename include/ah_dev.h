@@ -20,9 +20,10 @@ extern "C" {
 ah_status ah_validate_pairs(const ah_primer_pair* pairs, uint32_t n_pairs);
 
 /* Validate a Tm request exactly as ah_tm does (the pairs, the salt method
- * and its ion concentrations, the strand concentration, the degeneracy limit
- * and AH_TM_MAX_PAIRINGS); no device work.  Returns AH_OK or the error ah_tm
- * would return (message in ah_last_error()). */
+ * and its ion concentrations, the strand concentration, and for a primer
+ * above AH_TM_MAX_PAIRINGS what the exact route needs); no device work.
+ * Returns AH_OK or the error ah_tm would return (message in
+ * ah_last_error()). */
 ah_status ah_validate_tm(const ah_primer_pair* pairs, uint32_t n_pairs, const ah_tm_params* params);
 
 /* Source text of the specialised scan program for a primer set (has_nmask:
