@@ -224,3 +224,35 @@ def test_exact_route_above_the_enumeration_bound(dev, monkeypatch, case):
         assert np.array_equal(gh2["tm"].view(np.uint32), gh["tm"].view(np.uint32))
         assert amp_tuples(path.amps_numpy(buf2)) == amp_tuples(ga)
     monkeypatch.delenv("AH_QUERY_SEGMENTED", raising=False)
+
+
+def test_forced_exact_route_on_decoy_pairs(dev, monkeypatch):
+    """Decoy sites (the primer against the reversed genome, whose template
+    complement rule flips per strand) through the exact route: the same Tm as
+    the enumeration, bit for bit, and the oracle's run on the reversed
+    genomes."""
+    import dataclasses
+
+    from paper_2509_13300_amd import path
+
+    rich = plan.PairSpec("ACGTRYACGTAC", "TTGCANNGCA", k=3, clamp=0, min_len=20, max_len=400)
+    p = plan.tiny(502, n_genomes=6, len_lo=300, len_hi=60000, n_copies=(0, 2))
+    pairs = [rich, dataclasses.replace(rich, decoy=True),
+             dataclasses.replace(rich, decoy=True, k=2, clamp=3)]
+    monkeypatch.delenv("AH_TM_EXACT", raising=False)
+    _, buf = run_gpu(p, pairs, dev, hit_cap=1 << 20, amp_cap=1 << 20)
+    enum = path.hits_numpy(buf)
+    monkeypatch.setenv("AH_TM_EXACT", "1")
+    _, buf = run_gpu(p, pairs, dev, hit_cap=1 << 20, amp_cap=1 << 20)
+    exact = path.hits_numpy(buf)
+    monkeypatch.delenv("AH_TM_EXACT", raising=False)
+    oh, _ = run_oracle(p, pairs)
+    assert hit_tuples_gpu(exact) == hit_tuples_oracle(oh) == hit_tuples_gpu(enum)
+    dec = exact["pair"] > 0
+    assert dec.sum() > 100
+    fin = np.isfinite(oh["tm"])
+    assert np.array_equal(np.isfinite(exact["tm"]), fin)
+    assert np.array_equal(exact["tm"][fin].view(np.uint32), enum["tm"][fin].view(np.uint32))
+    err = np.abs(exact["tm"][fin].astype(np.float64) - oh["tm"][fin])
+    say("decoy exact", "hits", exact.size, "decoy", int(dec.sum()), "max err", float(err.max()))
+    assert float(err.max()) <= TM_TOL
