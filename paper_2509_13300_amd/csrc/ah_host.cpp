@@ -2268,8 +2268,8 @@ ah_status ah_query(const ah_genomes* g, const ah_primer_pair* pairs, const ah_wi
     s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, nullptr, &sg);
     if (s) return s;
     ProfScope prof_sort("sort", st);
-    AH_HIP(ah::launch_seg_tail(w.staging, d_hits, sg, d_hit_res, kb.pb + 2, *g, ttab, n_pairs,
-                               ptab, pb, d_amp, amp_capacity, d_amp_res, exact, st));
+    AH_HIP(ah::launch_seg_tail(w.staging, d_hits, hit_capacity, sg, d_hit_res, kb.pb + 2, *g, ttab,
+                               n_pairs, ptab, pb, d_amp, amp_capacity, d_amp_res, exact, st));
     return AH_OK;
   }
   s = launch_scan_kernel(fn, tn, g, w, d_hit_res, hit_capacity, st, &kb);

@@ -135,9 +135,11 @@ hipError_t launch_sort_tm_mark(ah_hit* staged, ah_hit* out, const uint64_t* n_de
 // canonical order (in LDS up to kSegLds sites), computes the Tm of every
 // site, counts the amplicons each leader + site starts, takes the amplicons
 // of the earlier segments by a look-back over lb, and writes its own.
-// key_bits: bits of pos << 2 | strand-primer.  When the sites overflowed,
-// nothing is written but the amplicon result, an overflow with count and
-// required 0.
+// key_bits: bits of pos << 2 | strand-primer; hcap: the capacity of out.
+// When the sites overflowed, the amplicon result is an overflow with count
+// and required 0 and no amplicon is written; the sites found still go to
+// out in canonical order with their Tm when they fit in hcap (a full
+// candidate list), as the separate calls write them.
 constexpr uint32_t kSegMax = 4096;  // AH_SEG_MAX of the scan core
 constexpr uint32_t kSegLds = 1024;
 struct SegBuffers {
@@ -147,7 +149,7 @@ struct SegBuffers {
   uint64_t* off;   // [n_seg + 1] first site of each segment
   uint32_t n_seg, n_genomes;
 };
-hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
+hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, uint64_t hcap, const SegBuffers& sg,
                            const ah_result* hres, int key_bits, const ah_genomes& g,
                            const PrimerTab* tm_tabs, uint32_t n_pairs, const PairTab* pair_tabs,
                            const PairBuffers& pb, ah_amplicon* amp, uint64_t acap,

@@ -1322,6 +1322,7 @@ struct SegArgs {
   ah_amplicon* amp;
   u64 acap;
   ah_result* ares;
+  u64 hcap;                // capacity of out (the sites)
 };
 
 __device__ __forceinline__ u64 seg_key(const ah_hit& h) {
@@ -1560,14 +1561,18 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
   for (u32 i = t; i < 2 * sizeof(PrimerTab) / 4; i += kSegBlock)
     ((u32*)s_tab)[i] = ((const u32*)(A.tj.tabs + 2 * pair))[i];
   tm_tables(s_dh, s_ds);  // its barrier also covers the copy
-  if (status != AH_OK) {  // the sites overflowed: the pairing needs all of them
+  const bool sites_ok = status == AH_OK;
+  if (!sites_ok) {  // the sites overflowed: the pairing needs all of them
     if (s == 0 && t == 0) {
       A.ares->count = 0;
       A.ares->required = 0;
       A.ares->status = AH_ERR_OVERFLOW;
       A.ares->reserved = 0;
     }
-    return;
+    // The sites found still go out in canonical order with their Tm, as the
+    // separate calls write them, when they fit (a full candidate list left
+    // them incomplete); past the capacity none were staged.
+    if (m == 0 || A.seg_off[A.n_seg] > A.hcap) return;
   }
   if (m == 0) {
     const u64 before = seg_lookback(A.lb, s, 0ull);
@@ -1694,6 +1699,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_tail(SegArgs A) {
       }
     }
   __syncthreads();
+  if (!sites_ok) return;  // the sites are in place; no pairing
   // kept fwd- (low half) and rev- (high half) minus sites up to each record
   u64 carry = 0;
   for (u32 r0 = 0; r0 < m; r0 += kSegBlock) {
@@ -2260,7 +2266,7 @@ hipError_t launch_sort_tm_mark(ah_hit* staged, ah_hit* out, const uint64_t* n_de
   return hipGetLastError();
 }
 
-hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
+hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, uint64_t hcap, const SegBuffers& sg,
                            const ah_result* hres, int key_bits, const ah_genomes& g,
                            const PrimerTab* tm_tabs, uint32_t n_pairs, const PairTab* pair_tabs,
                            const PairBuffers& pb, ah_amplicon* amp, uint64_t acap,
@@ -2283,6 +2289,7 @@ hipError_t launch_seg_tail(ah_hit* staged, ah_hit* out, const SegBuffers& sg,
   A.lb = (u64*)sg.lb;
   A.amp = amp;
   A.acap = acap;
+  A.hcap = hcap;
   A.ares = ares;
   const u32 grid = sg.n_seg > 0 ? sg.n_seg : 1u;
   if (exact)

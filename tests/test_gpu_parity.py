@@ -256,15 +256,18 @@ def test_overflow_reports_required_and_retry_is_identical(dev):
     assert np.array_equal(path.amps_numpy(again), famp)
 
 
-def test_candidate_list_overflow_reports_bound_and_retry_is_identical(dev):
+@pytest.mark.parametrize("wave", ["1", "0"])
+def test_candidate_list_overflow_reports_bound_and_retry_is_identical(dev, monkeypatch, wave):
     """The filter's candidate list split over its workgroups: with the minimum
     workspace, a dense pair fills some workgroup's share; the call reports
     overflow with a bound, and a call with that capacity gives the full
-    result."""
+    result.  In wave mode and in tile mode (AH_SCAN_WAVE=0), where each
+    workgroup counts its own full slice."""
     import torch
 
     from paper_2509_13300_amd import path
 
+    monkeypatch.setenv("AH_SCAN_WAVE", wave)
     pr = plan.PairSpec("AAAAAAAC", "AAAAAAAG", k=2, clamp=0, min_len=8, max_len=20)
     p = plan.tiny(79, n_genomes=1, len_lo=2_000_000, len_hi=2_000_001, pair=pr, n_copies=(0, 0),
                   gc_lo=0.0, gc_hi=0.1)
@@ -289,7 +292,8 @@ def test_candidate_list_overflow_reports_bound_and_retry_is_identical(dev):
     assert np.array_equal(path.amps_numpy(again), famp)
 
 
-def test_full_candidate_slices_with_few_sites(dev, monkeypatch):
+@pytest.mark.parametrize("wave", ["1", "0"])
+def test_full_candidate_slices_with_few_sites(dev, monkeypatch, wave):
     """A weak filter (forced: one clean block of four) on a specific primer:
     many candidates fill the workgroups' shares of a minimum list while the
     real sites stay far below the capacity.  The result reports overflow
@@ -302,6 +306,7 @@ def test_full_candidate_slices_with_few_sites(dev, monkeypatch):
     from paper_2509_13300_amd import path
 
     monkeypatch.setenv("AH_SCAN_FORCE_NEED", "1")
+    monkeypatch.setenv("AH_SCAN_WAVE", wave)  # "0": tile mode, the workgroups count
     pr = plan.PairSpec("ACGTTGCAAGCTTCGAAC", "GGATCCTTGAGCAATGCC", k=3, clamp=0, min_len=20,
                        max_len=4000)
     src = L.ah_scan_program_source([pr])
@@ -325,6 +330,12 @@ def test_full_candidate_slices_with_few_sites(dev, monkeypatch):
     got = path.hits_numpy(small)  # the sites the filled slices still held
     assert got.size == r["count"] <= full.size
     assert np.all(np.isfinite(got["tm"])) and np.all(got["genome"] == 0)
+    # the whole query writes them as the separate calls do, byte for byte
+    sep = path.alloc(coll, 1, 1 << 16, 1 << 16, dev)
+    path.run(coll, [pr], sep, fused=False)
+    torch.cuda.synchronize()
+    assert path.result(sep.hit_res) == r
+    assert np.array_equal(path.hits_numpy(sep), got)
     again = path.alloc(coll, 1, r["required"], 1 << 16, dev)
     path.run(coll, [pr], again)
     torch.cuda.synchronize()
