@@ -87,7 +87,10 @@ class QueryBuffers:
 
 def alloc(coll: PackedCollection, pairs, hit_cap: int, amp_cap: int, device) -> QueryBuffers:
     """Buffers for queries of `pairs` (a pair list, sizing the scan's candidate
-    list for their filters; or a pair count, for the minimum)."""
+    list for their filters; or a pair count, for the minimum).  The site and
+    amplicon buffers start filled with the byte 0xA5, so that a record a
+    result counts but no kernel wrote shows up as such (genome 0xA5A5A5A5)
+    instead of as whatever the memory held before."""
     import torch
 
     g = coll.view()
@@ -95,10 +98,10 @@ def alloc(coll: PackedCollection, pairs, hit_cap: int, amp_cap: int, device) -> 
     sw = L.ah_scan_workspace_bytes(g, pairs, hit_cap)
     pw = L.ah_pair_workspace_bytes(hit_cap, n_pairs)
     return QueryBuffers(
-        hits=torch.empty(max(hit_cap, 1) * 16, dtype=torch.uint8, device=device),
+        hits=torch.full((max(hit_cap, 1) * 16,), 0xA5, dtype=torch.uint8, device=device),
         hit_res=torch.zeros(24, dtype=torch.uint8, device=device),
         scan_work=torch.empty(sw, dtype=torch.uint8, device=device),
-        amps=torch.empty(max(amp_cap, 1) * 24, dtype=torch.uint8, device=device),
+        amps=torch.full((max(amp_cap, 1) * 24,), 0xA5, dtype=torch.uint8, device=device),
         amp_res=torch.zeros(24, dtype=torch.uint8, device=device),
         pair_work=torch.empty(pw, dtype=torch.uint8, device=device),
         hit_cap=hit_cap, amp_cap=amp_cap)
