@@ -111,6 +111,34 @@ def test_prefilter_can_be_switched_off(monkeypatch):
     assert re.search(r"pattern 0: .*prefilter: [23] of [45] blocks", src)
 
 
+def test_tile_mode_count_inside_the_filter_only_for_small_programs(monkeypatch):
+    """Wave mode (primers up to U + 1 bases) counts in the filter anyway; in
+    tile mode the filter takes the exact count for up to 16 patterns (4
+    pairs) and leaves it to a launch of its own for more."""
+    def macro(src, name):
+        return int(re.search(r"#define %s (\d+)" % name, src).group(1))
+
+    short = ("ACGTACGTACGTAC", "GGTTCCAAGGTTC", 2, 0)
+    long_ = ("GCCGCWATGCGGCTWAGCCGCWTAGCGCWT", "GCGGCWTGCCGCWAGCGGCWTGCGCWAGCG", 3, 0)
+    src = L.ah_scan_program_source([short])
+    assert (macro(src, "AH_WAVE"), macro(src, "AH_TILE_COUNT")) == (1, 0)
+    src = L.ah_scan_program_source([long_])
+    assert (macro(src, "AH_WAVE"), macro(src, "AH_TILE_COUNT")) == (0, 1)
+    src = L.ah_scan_program_source([long_] * 4)
+    assert (macro(src, "AH_WAVE"), macro(src, "AH_TILE_COUNT")) == (0, 1)
+    src = L.ah_scan_program_source([long_] * 5)
+    assert (macro(src, "AH_WAVE"), macro(src, "AH_TILE_COUNT")) == (0, 0)
+    monkeypatch.setenv("AH_SCAN_WAVE", "0")
+    src = L.ah_scan_program_source([short])
+    assert (macro(src, "AH_WAVE"), macro(src, "AH_TILE_COUNT")) == (0, 1)
+
+
+@pytest.mark.parametrize("n_pairs", [1, 5])
+def test_tile_mode_programs_compile_with_and_without_the_count(n_pairs):
+    long_ = ("GCCGCWATGCGGCTWAGCCGCWTAGCGCWT", "GCGGCWTGCCGCWAGCGGCWTGCGCWAGCG", 3, 0)
+    assert L.ah_scan_program_compile([long_] * n_pairs, has_nmask=n_pairs > 1) > 1000
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_generated_programs_compile_for_gfx950(seed):
     rs = np.random.RandomState(seed)
